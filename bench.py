@@ -1,0 +1,220 @@
+"""Benchmark of the batched SF on one MI355X.
+
+One step = one batched forward (sf_project, L* iterations, checkpoints saved)
+plus the adjoint (sf_project_backward) over the whole batch: every step of the
+hot path.  Default workload: 64 independent problems of 32 robots and 20
+obstacles (12 m arena, 11 Bernstein coefficients per axis, 100 time steps),
+run for L* iterations, the smallest multiple of 10 at which every problem's
+FP64-oracle residual is <= 1e-3 (determined offline by oracle/lstar.py).
+
+Prints one JSON line.  Extra fields: the forward-only rate, the plain
+per-problem path's forward rate (one problem per launch group, per-stage
+kernels) and the batched/plain ratio, the residual check on the GPU outputs,
+the roofline of the dominant kernel and the FP64 oracle timed on host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "SF problems/s (fwd, fwd+bwd) at 32 robots, residual≤1e-3; batched vs plain"
+RHO = 0.5
+# L* per workload at rho = 0.5 (oracle/lstar.py; recorded with its output in the design doc)
+LSTAR = {1: 100, 2: 400, 3: 1200, 4: 2000, 5: 2000}
+CKPT = 10
+# MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz; FMA = 2 flops.  Packed FP32
+# is disabled in this build, so scalar FP32 FMA is the attainable ceiling.
+PEAK_ALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12          # 78.6
+PEAK_FP32_PACKED_TFLOPS = 157.3
+
+
+def algorithmic_flops(problems, T, nc, L, kind):
+    """Data-independent algorithmic flop count of one launch (FMA = 2):
+    distance tests of every unordered robot pair and robot-obstacle pair per
+    step (6 flops), box residuals (4 per coordinate), the coefficient<->time maps
+    (2 n_d n T nc FMAs each), the mode products on coefficients (2 n_d n nc^2
+    FMAs each) and ~10 flops per coefficient of elementwise work.  Work on active
+    constraints (data dependent, a small fraction) is not counted."""
+    tot = 0.0
+    for p in problems:
+        n, M = p.n, p.M
+        Sc = 2 * n * nc
+        tests = 6.0 * (n * (n - 1) / 2 + n * M) * T + 4.0 * 2 * n * T
+        maps = 2.0 * 2 * n * T * nc
+        modes = 2.0 * Sc * nc
+        if kind == "fwd":
+            per_it = tests + 2 * maps + 2 * modes + 10.0 * Sc
+            tot += per_it * L + tests + maps          # + residual of the returned iterate
+        else:
+            per_it = tests + 3 * maps + 2 * modes + 10.0 * Sc
+            tot += per_it * L
+    return tot
+
+
+def cpu_baseline(problem, L, budget_s=20.0):
+    """The FP64 oracle on one problem of the workload, on one host core:
+    forward iterations for ~half the budget, then the oracle adjoint (forward +
+    reverse sweep) for the rest; scaled to problems/s at L iterations."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import SFAdjoint, SFOracle
+    with threadpool_limits(limits=1):
+        orc = SFOracle.for_problem(problem, RHO)
+        t0 = time.perf_counter()
+        n_f = 0
+        xib, lam = orc.flat(problem.xi), np.zeros(problem.xi.size)
+        xi = orc.flat(problem.xi)
+        while time.perf_counter() - t0 < budget_s / 2:
+            xib, lam, _, _ = orc.step(xi, xib, lam)
+            n_f += 1
+        t_f = (time.perf_counter() - t0) / n_f
+        n_b = max(5, int(0.25 * budget_s / (3 * t_f)))
+        g = np.ones(problem.xi.shape)
+        t1 = time.perf_counter()
+        SFAdjoint(orc).gradient(problem.xi, problem.xi, None, n_b, g, np.zeros_like(g))
+        t_fb = (time.perf_counter() - t1) / n_b
+    return dict(value=1.0 / (t_fb * L), unit="problems/s", cores=1, kind="oracle",
+                sample=f"1 problem ({problem.n} robots, {problem.M} obstacles): {n_f} forward "
+                       f"iterations ({t_f * 1e3:.1f} ms each) and a {n_b}-iteration forward+"
+                       f"adjoint ({t_fb * 1e3:.1f} ms per iteration), scaled to {L} iterations",
+                fwd_value=1.0 / (t_f * L))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=3)
+    ap.add_argument("--iters", type=int, default=None)
+    ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    a = ap.parse_args(argv)
+    if a.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for {a.gpus}); "
+              "the problems of a batch are independent, so a multi-GPU run would shard "
+              "them across GPUs without communication.", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_2510_09204_amd import SFPlan, load_library, to_device
+    from workloads import CONFIGS, make_batch, pack
+
+    load_library()
+    dev = torch.device("cuda:0")
+    cfg = CONFIGS[a.config]
+    L = a.iters if a.iters is not None else LSTAR[a.config]
+    probs = make_batch(cfg)
+    pk = pack(probs)
+    B = len(probs)
+    plan = SFPlan(pk.n_robots, pk.n_obs, pk.robot_a, pk.box, pk.n_coef, pk.n_steps, RHO,
+                  checkpoint_every=CKPT, max_iters=L, threads=a.threads, device=dev)
+    t = to_device(pk, dev)
+    args = (t["xi"], t["xi0"], t["lam0"], t["boundary"], t["obstacles"])
+    g_out = torch.ones_like(t["xi"])
+    g_res = torch.zeros((B, 4), dtype=torch.float32, device=dev)
+    g_res[:, 0] = 1.0
+    g_res[:, 1] = 1.0
+    stream = torch.cuda.current_stream(dev)
+
+    def step(evs=None):
+        if evs is not None:
+            evs[0].record(stream)
+        xo, lo, res = plan.project(*args, L, save=True)
+        if evs is not None:
+            evs[1].record(stream)
+        g = plan.backward(g_out, None, g_res)
+        if evs is not None:
+            evs[2].record(stream)
+        return xo, lo, res, g
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    kev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(a.steps):
+        out = step(kev[s])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fwd_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in kev]))
+    bwd_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in kev]))
+    ms_per_step = wall * 1e3 / a.steps
+    res = out[2].cpu().numpy()
+    resid = np.hypot(res[:, 0], res[:, 1])
+
+    # forward only
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    plan.project(*args, L)
+    e0.record(stream)
+    for _ in range(a.steps):
+        plan.project(*args, L)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    fwd_only_ms = e0.elapsed_time(e1) / a.steps
+
+    plain = None
+    if not a.no_plain:
+        e0.record(stream)
+        xp, lp, rp = plan.project(*args, L, plain=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        plain_ms = e0.elapsed_time(e1)
+        plain = dict(ms=plain_ms, problems_per_s=B / (plain_ms / 1e3),
+                     max_abs_diff_vs_batched=float((xp - out[0]).abs().max().item()))
+
+    nc, T = pk.n_coef, pk.n_steps
+    f_fwd = algorithmic_flops(probs, T, nc, L, "fwd")
+    f_bwd = algorithmic_flops(probs, T, nc, L, "bwd")
+    dom = ("sf_bwd_fused", f_bwd, bwd_ms) if bwd_ms >= fwd_ms else ("sf_fwd_fused", f_fwd, fwd_ms)
+    ach = dom[1] / (dom[2] / 1e3) / 1e12
+    roofline = dict(bound="alu", kernel=dom[0], achieved=round(ach, 3),
+                    peak=round(PEAK_ALU_TFLOPS, 2), unit="TFLOP/s",
+                    frac=round(ach / PEAK_ALU_TFLOPS, 4), traffic=None,
+                    frac_vs_packed_fp32_peak=round(ach / PEAK_FP32_PACKED_TFLOPS, 4),
+                    kernels={"sf_fwd_fused": dict(ms=round(fwd_ms, 4),
+                                                  tflops=round(f_fwd / fwd_ms / 1e9, 3)),
+                             "sf_bwd_fused": dict(ms=round(bwd_ms, 4),
+                                                  tflops=round(f_bwd / bwd_ms / 1e9, 3))})
+    cpu = None
+    if not a.no_cpu:
+        cpu = cpu_baseline(probs[0], L, a.cpu_budget)
+
+    value = B / (ms_per_step / 1e3)
+    line = dict(metric=METRIC, value=round(value, 2), unit="problems/s", n_gpus=1,
+                steps=a.steps, warmup=a.warmup, ms_per_step=round(ms_per_step, 4),
+                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
+                data="synthetic",
+                config=dict(workload=f"{cfg.name}: {cfg.description}", global_batch=B,
+                            robots=int(pk.n_robots.max()), obstacles=int(pk.n_obs.max()),
+                            n_coef=nc, n_steps=T, iters=L, rho=RHO, checkpoint_every=CKPT,
+                            threads=plan.threads, residual_tol=1e-3),
+                fwd_problems_per_s=round(B / (fwd_only_ms / 1e3), 2),
+                fwd_ms=round(fwd_only_ms, 4),
+                plain_fwd_problems_per_s=None if plain is None else round(plain["problems_per_s"], 2),
+                batched_over_plain_fwd=None if plain is None else
+                round((B / (fwd_only_ms / 1e3)) / plain["problems_per_s"], 2),
+                plain_max_abs_diff=None if plain is None else plain["max_abs_diff_vs_batched"],
+                residual_max=float(resid.max()), residual_median=float(np.median(resid)),
+                frac_residual_le_tol=float(np.mean(resid <= 1e-3)),
+                status_nonzero=int(np.sum(res[:, 3] != 0)),
+                roofline=roofline, cpu_baseline=cpu)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,164 @@
+/*
+ * sf.h - C ABI of the MI355X safety-filter (SF) library.
+ *
+ * The SF projects a sampled joint multi-robot trajectory xi onto the
+ * inter-robot, obstacle and workspace constraints and the start/goal
+ * equalities (projection problem, eqs. proj_cost..proj_robot) by L
+ * applications of the fixed-point operator T (eq. fixed_point), whose steps are
+ * the alternating-minimisation updates of the Appendix (eqs. alpha_step ..
+ * xi_step) on the augmented Lagrangian (eq. aug_lag).  2D workspace only.
+ *
+ * Layouts (all float32, contiguous, device memory unless marked host):
+ *   coefficient arrays (xi, xi_bar, lambda and their gradients): problems
+ *     concatenated in batch order; problem b holds [N_DIM=2][n_b][n_coef],
+ *     i.e. the paper's stacking (all robots' x coefficients, then all y);
+ *   boundary: [sum_b n_b][2][2]  = (b_{i,0}, b_{i,K}) positions per robot;
+ *   obstacles: [sum_b M_b][3]    = centre x, centre y, a_o (inflated size:
+ *     the minimum distance between a robot centre and the obstacle centre);
+ *   residual: [B][4] = ||r_1||, ||r_2|| of the returned xi_bar (metres),
+ *     ||z^L - z^{L-1}|| with z = (xi_bar, lambda), and a status word stored
+ *     as a float (0 = finite outputs, 1 = non-finite value in the outputs).
+ *   The robot size a is the minimum centre-to-centre distance (diag(a, a)
+ *   is M_r of the inter-robot constraint); box = p_min, p_max per problem.
+ *
+ * Ownership: the caller allocates every array and the workspace; the library
+ * owns only the host-side plan.  Calls never retain caller pointers (the
+ * forward copies what the backward needs into the workspace).  All work is
+ * asynchronous on the given hipStream_t (passed as void*).  Calls on one plan
+ * must be serialised by the caller; the workspace of a plan must not be shared
+ * with another plan.
+ *
+ * Errors: functions return 0 on success or a negative SF_ERR_* code and never
+ * throw.  sf_last_error_detail() gives a thread-local message for the last
+ * failing call.  Numerical divergence inside a problem does not fail the call:
+ * it shows in that problem's status word.
+ */
+#ifndef SF_H_
+#define SF_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SF_OK 0
+#define SF_ERR_INVALID_ARG (-1)     /* NULL pointer, bad count or parameter */
+#define SF_ERR_SHAPE (-2)           /* sizes the library cannot handle */
+#define SF_ERR_WORKSPACE_SMALL (-3) /* workspace smaller than sf_setup reported */
+#define SF_ERR_NOT_SAVED (-4)       /* backward without a saved forward */
+#define SF_ERR_HIP (-5)             /* HIP runtime error (detail has the code) */
+#define SF_ERR_NONFINITE (-6)       /* non-finite host input */
+
+/* sf_project flags */
+#define SF_SAVE_FOR_BACKWARD 1 /* keep checkpoints for sf_project_backward */
+#define SF_PLAIN 2             /* unfused per-stage kernels, one problem per launch */
+#define SF_GRAPH 4             /* capture the launch once per argument set, replay after */
+
+typedef struct sf_plan sf_plan_t;
+
+typedef struct {
+  int32_t n_dim;            /* workspace dimension n_d; must be 2 */
+  int32_t n_coef;           /* basis size n_xi per axis, 2..32 (Bernstein, eq. poly) */
+  int32_t n_steps;          /* time samples T = K + 1, 2..4096 */
+  int32_t checkpoint_every; /* k >= 1: the forward stores (xi_bar, lambda) every k
+                               iterates; the backward recomputes the rest */
+  int32_t max_iters;        /* largest n_iters a saved forward may use (sizes the
+                               checkpoint area); >= 0 */
+  int32_t threads;          /* threads per workgroup for the fused kernels:
+                               256, 512 or 1024; 0 = autotuned */
+  double rho;               /* augmented-Lagrangian penalty rho > 0 (eq. aug_lag) */
+} sf_config_t;
+
+/*
+ * Build a plan for a batch of B problems and report the workspace it needs.
+ *
+ * The KKT matrix of the xi_bar step (Appendix, "Solution Process": M, with
+ * the workspace terms rho G^T G kept) does not depend on xi, so its inverse is
+ * factored once here, in FP64 on the host, per distinct (robot, obstacle)
+ * count, and stored in float32 (Appendix, eq. batch_comp: "factorizations can
+ * be pre-stored"; the factor must be rebuilt when rho or the basis changes).
+ *
+ *   cfg            host; see sf_config_t.
+ *   n_problems     B >= 1.
+ *   n_robots       host int32[B], each 1..64.
+ *   n_obs          host int32[B], each 0..4096.
+ *   robot_a        host float[B], a > 0.
+ *   box            host float[B][2][2] = p_min, p_max; p_min < p_max.
+ *   workspace      NULL: only *workspace_bytes is set and *plan is left alone.
+ *                  Otherwise a device buffer of at least *workspace_bytes bytes,
+ *                  256-byte aligned, that this plan uses until sf_destroy; the
+ *                  plan's constant tables are copied into it on `stream`.
+ *   workspace_bytes in/out: required size (out); with a workspace, its size (in).
+ *   stream         hipStream_t or NULL (default stream).
+ *   plan           out: the new plan (only when workspace != NULL).
+ */
+int sf_setup(const sf_config_t* cfg, int32_t n_problems, const int32_t* n_robots,
+             const int32_t* n_obs, const float* robot_a, const float* box,
+             void* workspace, size_t* workspace_bytes, void* stream, sf_plan_t** plan);
+
+/*
+ * Run n_iters applications of the fixed-point operator T (eq. fixed_point)
+ * from the warm start (xi_bar^0, lambda^0) (eq. NN_loss's initialisation) for
+ * every problem of the plan, and report the residual of the returned iterate
+ * (eq. primal_residual, read as sqrt(||r_1||^2 + ||r_2||^2)).
+ *
+ * One iteration (Appendix, eqs. alpha_step..xi_step, in the order given there):
+ * closed-form alpha/d steps on every robot pair and robot-obstacle pair at every
+ * time sample, the slack s step, lambda^{l+1} = lambda^l - rho F^T r_1 -
+ * rho G^T r_2, and the equality-constrained xi_bar step.
+ *
+ *   xi          flow sample xi (the projection target), coefficient layout.
+ *   xi0, lam0   warm start, coefficient layout.
+ *   boundary    [sum n][2][2]; obstacles [sum M][3] (may be NULL if sum M = 0).
+ *   n_iters     L >= 0 (L = 0 copies the warm start and reports its residual).
+ *   flags       SF_SAVE_FOR_BACKWARD | SF_PLAIN | SF_GRAPH.  Saving requires
+ *               n_iters <= cfg.max_iters and is not combined with SF_PLAIN.
+ *   xi_out, lam_out  coefficient layout, must not alias the inputs.
+ *   residual    [B][4] (see the layout notes above).
+ * Input arrays are read during the call's kernels only.
+ */
+int sf_project(sf_plan_t* plan, void* workspace, const float* xi, const float* xi0,
+               const float* lam0, const float* boundary, const float* obstacles,
+               int32_t n_iters, int32_t flags, float* xi_out, float* lam_out,
+               float* residual, void* stream);
+
+/*
+ * Vector-Jacobian product of the last saved sf_project call (the unrolled
+ * chain of T, Sec. "Fixed-Point Representation"; "Differentiability" in the
+ * Appendix), for the scalar
+ *   <g_xi_out, xi_bar^L> + <g_lam_out, lambda^L>
+ *   + sum_b (g_residual[b][0] ||r_1|| + g_residual[b][1] ||r_2||)
+ *   + fp_weight * sum_l ||z^{l+1} - z^l||^2   (eq. NN_loss's L_FP terms).
+ * Iterates between checkpoints are recomputed.  Non-smooth points: a pair
+ * exactly at distance a, or a coordinate exactly on a box bound, counts as
+ * inactive; norm gradients at a zero norm are zero.
+ *
+ *   g_xi_out, g_lam_out  coefficient layout; either may be NULL (= zero).
+ *   g_residual           [B][4] or NULL; columns 2 and 3 are ignored.
+ *   g_xi, g_xi0, g_lam0  outputs, coefficient layout; each may be NULL (skipped).
+ * Returns SF_ERR_NOT_SAVED unless the latest sf_project on this plan saved.
+ */
+int sf_project_backward(sf_plan_t* plan, void* workspace, const float* g_xi_out,
+                        const float* g_lam_out, const float* g_residual, float fp_weight,
+                        float* g_xi, float* g_xi0, float* g_lam0, void* stream);
+
+/* Free the plan (host memory and cached graphs).  NULL is accepted.  The
+ * workspace stays the caller's. */
+void sf_destroy(sf_plan_t* plan);
+
+/* Static description of an SF_* code. */
+const char* sf_error_string(int code);
+
+/* Thread-local detail of the last failing call on this thread ("" if none). */
+const char* sf_last_error_detail(void);
+
+/* Threads per workgroup the plan's fused kernels use (after autotuning). */
+int sf_plan_threads(const sf_plan_t* plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SF_H_ */

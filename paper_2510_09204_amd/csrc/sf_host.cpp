@@ -1,0 +1,577 @@
+// Host runtime of the SF library: argument validation, the FP64 KKT factors,
+// the workspace layout, launch dispatch, the graph cache and the autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/sf.h"
+#include "sf_internal.h"
+
+namespace {
+
+thread_local std::string g_detail;
+
+int fail(int code, const std::string& msg) {
+  g_detail = msg;
+  return code;
+}
+
+#define SF_HIP_CHECK(expr)                                                              \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(SF_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_) + " (" + \
+                                  std::to_string((int)e_) + ")");                       \
+  } while (0)
+
+constexpr size_t kLdsBudget = 160 * 1024;  // gfx950 LDS per workgroup
+constexpr int kMaxRobots = 1024;
+constexpr int kMaxObs = 4096;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// ---------------------------------------------------------------------------
+// FP64 factors.  The xi_bar step solves [I + rho H, A^T; A, 0] [xi; nu] =
+// [eta; b] with H = F^T F + G^T G = ((n + M + 2) I - 1 1^T) (x) W^T W per axis
+// and A = I_n (x) A1.  In the robot-mean mode H acts as (M + 2) W^T W and in
+// each deviation mode as (n + M + 2) W^T W, so the inverse reduces to two
+// (nc + 2)-sized KKT matrices K(c) = [I + rho c W^T W, A1^T; A1, 0].
+// ---------------------------------------------------------------------------
+std::vector<double> bernstein(int nc, int T) {
+  std::vector<double> W((size_t)T * nc);
+  const int deg = nc - 1;
+  std::vector<double> binom(nc);
+  for (int c = 0; c < nc; ++c) {
+    double v = 1.0;
+    for (int q = 1; q <= c; ++q) v = v * (deg - c + q) / q;
+    binom[c] = v;
+  }
+  for (int k = 0; k < T; ++k) {
+    const double tau = (double)k / (double)(T - 1);
+    for (int c = 0; c < nc; ++c)
+      W[(size_t)k * nc + c] = binom[c] * std::pow(tau, c) * std::pow(1.0 - tau, deg - c);
+  }
+  return W;
+}
+
+// In-place Gauss-Jordan inverse with partial pivoting; false if singular.
+bool invert(std::vector<double>& A, int m) {
+  std::vector<double> I((size_t)m * m, 0.0);
+  for (int i = 0; i < m; ++i) I[(size_t)i * m + i] = 1.0;
+  for (int col = 0; col < m; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < m; ++r)
+      if (std::fabs(A[(size_t)r * m + col]) > std::fabs(A[(size_t)piv * m + col])) piv = r;
+    if (std::fabs(A[(size_t)piv * m + col]) < 1e-300) return false;
+    if (piv != col)
+      for (int q = 0; q < m; ++q) {
+        std::swap(A[(size_t)piv * m + q], A[(size_t)col * m + q]);
+        std::swap(I[(size_t)piv * m + q], I[(size_t)col * m + q]);
+      }
+    const double d = 1.0 / A[(size_t)col * m + col];
+    for (int q = 0; q < m; ++q) {
+      A[(size_t)col * m + q] *= d;
+      I[(size_t)col * m + q] *= d;
+    }
+    for (int r = 0; r < m; ++r) {
+      if (r == col) continue;
+      const double f = A[(size_t)r * m + col];
+      if (f == 0.0) continue;
+      for (int q = 0; q < m; ++q) {
+        A[(size_t)r * m + q] -= f * A[(size_t)col * m + q];
+        I[(size_t)r * m + q] -= f * I[(size_t)col * m + q];
+      }
+    }
+  }
+  A.swap(I);
+  return true;
+}
+
+struct ModeFactors {
+  std::vector<double> S, SH, N;  // [nc][nc], [nc][nc], [nc][2]
+};
+
+bool mode_factors(const std::vector<double>& W, int nc, int T, double rho, double c,
+                  ModeFactors& out) {
+  std::vector<double> WtW((size_t)nc * nc, 0.0);
+  for (int p = 0; p < nc; ++p)
+    for (int q = 0; q < nc; ++q) {
+      double s = 0.0;
+      for (int k = 0; k < T; ++k) s += W[(size_t)k * nc + p] * W[(size_t)k * nc + q];
+      WtW[(size_t)p * nc + q] = s;
+    }
+  const int m = nc + 2;
+  std::vector<double> K((size_t)m * m, 0.0);
+  for (int p = 0; p < nc; ++p) {
+    for (int q = 0; q < nc; ++q) K[(size_t)p * m + q] = rho * c * WtW[(size_t)p * nc + q];
+    K[(size_t)p * m + p] += 1.0;
+    K[(size_t)p * m + nc] = W[p];                          // A1 row 0: position at k = 0
+    K[(size_t)p * m + nc + 1] = W[(size_t)(T - 1) * nc + p];  // A1 row 1: k = K
+    K[(size_t)nc * m + p] = W[p];
+    K[(size_t)(nc + 1) * m + p] = W[(size_t)(T - 1) * nc + p];
+  }
+  if (!invert(K, m)) return false;
+  out.S.assign((size_t)nc * nc, 0.0);
+  out.SH.assign((size_t)nc * nc, 0.0);
+  out.N.assign((size_t)nc * 2, 0.0);
+  for (int p = 0; p < nc; ++p) {
+    for (int q = 0; q < nc; ++q) out.S[(size_t)p * nc + q] = K[(size_t)p * m + q];
+    out.N[p * 2 + 0] = K[(size_t)p * m + nc];
+    out.N[p * 2 + 1] = K[(size_t)p * m + nc + 1];
+  }
+  for (int p = 0; p < nc; ++p)
+    for (int q = 0; q < nc; ++q) {
+      double s = 0.0;
+      for (int r = 0; r < nc; ++r) s += out.S[(size_t)p * nc + r] * WtW[(size_t)r * nc + q];
+      out.SH[(size_t)p * nc + q] = rho * c * s;
+    }
+  return true;
+}
+
+int choose_tc(int nc, int T, int n_max, int M_max, int S_max, int threads, bool bwd) {
+  auto bytes = [&](int tc) {
+    return bwd ? sf::bwd_lds_bytes(nc, T, tc, n_max, M_max, S_max, threads)
+               : sf::fwd_lds_bytes(nc, T, tc, n_max, M_max, S_max, threads);
+  };
+  int best = 0;
+  for (int tc = T; tc >= 1; --tc)
+    if (bytes(tc) <= kLdsBudget) {
+      best = tc;
+      break;
+    }
+  if (best == 0) return 0;
+  const int chunks = (T + best - 1) / best;
+  return (T + chunks - 1) / chunks;  // balanced chunks
+}
+
+struct GraphEntry {
+  std::vector<uint64_t> key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace
+
+struct sf_plan {
+  sf_config_t cfg{};
+  int B = 0;
+  std::vector<sf::ProbDesc> desc;
+  std::vector<int32_t> order;
+  std::vector<float> W, Wt, fac;
+  int nfac = 0;
+  int n_max = 0, M_max = 0, S_max = 0;
+  int64_t S_total = 0, pos_total = 0, obs_total = 0, rob_total = 0;
+  int n_ckpt = 0;
+  int threads = 512;
+  int Tc_fwd = 0, Tc_bwd = 0;
+  size_t lds_fwd = 0, lds_bwd = 0;
+  // workspace layout (byte offsets)
+  size_t off_desc = 0, off_order = 0, off_W = 0, off_Wt = 0, off_fac = 0, off_cxi = 0,
+         off_obs = 0, off_ckpt = 0, off_final = 0, off_seg = 0, off_X = 0, off_V = 0,
+         off_R = 0, off_xb0 = 0, off_xb1 = 0, off_lam = 0, off_pcxi = 0, off_red = 0,
+         total = 0;
+  char* ws = nullptr;
+  bool saved = false;
+  int saved_L = 0;
+  std::vector<GraphEntry> graphs;
+
+  ~sf_plan() {
+    for (auto& g : graphs) {
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+      if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+  }
+  template <typename Tp>
+  Tp* at(size_t off) const {
+    return reinterpret_cast<Tp*>(ws + off);
+  }
+};
+
+namespace {
+
+int validate_cfg(const sf_config_t* cfg) {
+  if (!cfg) return fail(SF_ERR_INVALID_ARG, "cfg is NULL");
+  if (cfg->n_dim != 2) return fail(SF_ERR_SHAPE, "only n_dim = 2 is supported");
+  if (cfg->n_coef < 2 || cfg->n_coef > sf::kMaxCoef)
+    return fail(SF_ERR_SHAPE, "n_coef must be in [2, 32]");
+  if (cfg->n_steps < 2 || cfg->n_steps > 4096)
+    return fail(SF_ERR_SHAPE, "n_steps must be in [2, 4096]");
+  if (cfg->checkpoint_every < 1) return fail(SF_ERR_INVALID_ARG, "checkpoint_every < 1");
+  if (cfg->max_iters < 0) return fail(SF_ERR_INVALID_ARG, "max_iters < 0");
+  if (!(cfg->rho > 0.0) || !std::isfinite(cfg->rho))
+    return fail(SF_ERR_INVALID_ARG, "rho must be finite and > 0");
+  if (cfg->threads != 0 && cfg->threads != 256 && cfg->threads != 512 &&
+      cfg->threads != 1024)
+    return fail(SF_ERR_INVALID_ARG, "threads must be 0, 256, 512 or 1024");
+  return SF_OK;
+}
+
+int build_plan(const sf_config_t* cfg, int B, const int32_t* n_robots, const int32_t* n_obs,
+               const float* robot_a, const float* box, std::unique_ptr<sf_plan>& out) {
+  int rc = validate_cfg(cfg);
+  if (rc) return rc;
+  if (B < 1) return fail(SF_ERR_INVALID_ARG, "n_problems < 1");
+  if (!n_robots || !n_obs || !robot_a || !box)
+    return fail(SF_ERR_INVALID_ARG, "n_robots, n_obs, robot_a and box must be non-NULL");
+  auto p = std::make_unique<sf_plan>();
+  p->cfg = *cfg;
+  p->B = B;
+  const int nc = cfg->n_coef, T = cfg->n_steps;
+  const std::vector<double> W = bernstein(nc, T);
+  p->W.resize((size_t)T * nc);
+  p->Wt.resize((size_t)T * nc);
+  for (int k = 0; k < T; ++k)
+    for (int c = 0; c < nc; ++c) {
+      p->W[(size_t)k * nc + c] = (float)W[(size_t)k * nc + c];
+      p->Wt[(size_t)c * T + k] = (float)W[(size_t)k * nc + c];
+    }
+  std::map<std::pair<int, int>, int> fac_index;
+  const int fs = sf::fac_stride(nc);
+  int64_t coef = 0, rob = 0, obs = 0, pos = 0;
+  std::vector<double> cost(B);
+  for (int b = 0; b < B; ++b) {
+    const int n = n_robots[b], M = n_obs[b];
+    if (n < 1 || n > kMaxRobots)
+      return fail(SF_ERR_SHAPE, "problem " + std::to_string(b) + ": n_robots out of [1, 1024]");
+    if (M < 0 || M > kMaxObs)
+      return fail(SF_ERR_SHAPE, "problem " + std::to_string(b) + ": n_obs out of [0, 4096]");
+    const float a = robot_a[b];
+    if (!(a > 0.f) || !std::isfinite(a))
+      return fail(SF_ERR_INVALID_ARG, "problem " + std::to_string(b) + ": robot_a must be > 0");
+    const float* bx = box + (size_t)b * 4;
+    for (int q = 0; q < 4; ++q)
+      if (!std::isfinite(bx[q]))
+        return fail(SF_ERR_NONFINITE, "problem " + std::to_string(b) + ": box not finite");
+    if (!(bx[0] < bx[2]) || !(bx[1] < bx[3]))
+      return fail(SF_ERR_INVALID_ARG, "problem " + std::to_string(b) + ": p_min >= p_max");
+    auto key = std::make_pair(n, M);
+    auto it = fac_index.find(key);
+    int fi;
+    if (it == fac_index.end()) {
+      ModeFactors perp, par;
+      if (!mode_factors(W, nc, T, cfg->rho, (double)(n + M + 2), perp) ||
+          !mode_factors(W, nc, T, cfg->rho, (double)(M + 2), par))
+        return fail(SF_ERR_SHAPE, "singular KKT matrix");
+      fi = p->nfac++;
+      fac_index[key] = fi;
+      const size_t base = p->fac.size();
+      p->fac.resize(base + fs);
+      float* f = p->fac.data() + base;
+      const int nc2 = nc * nc;
+      for (int q = 0; q < nc2; ++q) {
+        f[q] = (float)perp.S[q];
+        f[nc2 + q] = (float)(par.S[q] - perp.S[q]);
+        f[2 * nc2 + q] = (float)perp.SH[q];
+        f[3 * nc2 + q] = (float)(par.SH[q] - perp.SH[q]);
+      }
+      for (int q = 0; q < 2 * nc; ++q) {
+        f[4 * nc2 + q] = (float)perp.N[q];
+        f[4 * nc2 + 2 * nc + q] = (float)(par.N[q] - perp.N[q]);
+      }
+    } else {
+      fi = it->second;
+    }
+    sf::ProbDesc d{};
+    d.n = n;
+    d.M = M;
+    d.coef_off = (int32_t)coef;
+    d.rob_off = (int32_t)rob;
+    d.obs_off = (int32_t)obs;
+    d.fac = fi;
+    d.pos_off = (int32_t)pos;
+    d.a = a;
+    d.pmin[0] = bx[0];
+    d.pmin[1] = bx[1];
+    d.pmax[0] = bx[2];
+    d.pmax[1] = bx[3];
+    p->desc.push_back(d);
+    coef += 2LL * n * nc;
+    rob += n;
+    obs += M;
+    pos += (int64_t)n * T;
+    p->n_max = std::max(p->n_max, n);
+    p->M_max = std::max(p->M_max, M);
+    p->S_max = std::max(p->S_max, 2 * n * nc);
+    cost[b] = (double)T * (0.5 * n * (n - 1) + (double)n * M + n) + 4.0 * n * nc * nc;
+  }
+  if (coef > (int64_t)1 << 30 || pos > (int64_t)1 << 30)
+    return fail(SF_ERR_SHAPE, "batch too large for 32-bit offsets");
+  p->S_total = coef;
+  p->rob_total = rob;
+  p->obs_total = obs;
+  p->pos_total = pos;
+  // longest problems first (LPT order of the launch slots)
+  p->order.resize(B);
+  for (int b = 0; b < B; ++b) p->order[b] = b;
+  std::stable_sort(p->order.begin(), p->order.end(),
+                   [&](int x, int y) { return cost[x] > cost[y]; });
+  p->threads = cfg->threads ? cfg->threads : 512;
+  p->Tc_fwd = choose_tc(nc, T, p->n_max, p->M_max, p->S_max, p->threads, false);
+  p->Tc_bwd = choose_tc(nc, T, p->n_max, p->M_max, p->S_max, p->threads, true);
+  if (p->Tc_fwd == 0 || p->Tc_bwd == 0)
+    return fail(SF_ERR_SHAPE, "problem state does not fit the LDS of one workgroup");
+  p->lds_fwd = sf::fwd_lds_bytes(nc, T, p->Tc_fwd, p->n_max, p->M_max, p->S_max, p->threads);
+  p->lds_bwd = sf::bwd_lds_bytes(nc, T, p->Tc_bwd, p->n_max, p->M_max, p->S_max, p->threads);
+  const int L = cfg->max_iters, k = cfg->checkpoint_every;
+  p->n_ckpt = L > 0 ? (L + k - 1) / k : 0;
+  // workspace layout
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + std::max<size_t>(bytes, 1));
+    return o;
+  };
+  const size_t F = sizeof(float);
+  p->off_desc = take(sizeof(sf::ProbDesc) * B);
+  p->off_order = take(sizeof(int32_t) * B);
+  p->off_W = take(F * T * nc);
+  p->off_Wt = take(F * T * nc);
+  p->off_fac = take(F * p->fac.size());
+  p->off_cxi = take(F * coef);
+  p->off_obs = take(F * 3 * obs);
+  p->off_ckpt = take(F * 2 * coef * (size_t)p->n_ckpt);
+  p->off_final = take(F * 2 * coef);
+  p->off_seg = take(F * 2 * coef * (size_t)k);
+  p->off_X = take(F * 2 * pos);
+  p->off_V = take(F * 2 * pos);
+  p->off_R = take(F * coef);
+  p->off_xb0 = take(F * coef);
+  p->off_xb1 = take(F * coef);
+  p->off_lam = take(F * coef);
+  p->off_pcxi = take(F * coef);
+  p->off_red = take(F * 4 * B);
+  p->total = off;
+  out = std::move(p);
+  return SF_OK;
+}
+
+sf::FwdArgs fwd_args(const sf_plan* p, const float* xi, const float* xi0, const float* lam0,
+                     const float* boundary, const float* obstacles, int L, bool save,
+                     float* xi_out, float* lam_out, float* residual) {
+  sf::FwdArgs a{};
+  a.probs = p->at<sf::ProbDesc>(p->off_desc);
+  a.order = p->at<int32_t>(p->off_order);
+  a.W = p->at<float>(p->off_W);
+  a.Wt = p->at<float>(p->off_Wt);
+  a.fac = p->at<float>(p->off_fac);
+  a.xi = xi;
+  a.xi0 = xi0;
+  a.lam0 = lam0;
+  a.boundary = boundary;
+  a.obstacles = obstacles;
+  a.xi_out = xi_out;
+  a.lam_out = lam_out;
+  a.residual = residual;
+  a.ws_cxi = p->at<float>(p->off_cxi);
+  a.ws_obs = p->at<float>(p->off_obs);
+  a.ws_ckpt = p->at<float>(p->off_ckpt);
+  a.ws_final = p->at<float>(p->off_final);
+  a.S_total = p->S_total;
+  a.B = p->B;
+  a.nc = p->cfg.n_coef;
+  a.T = p->cfg.n_steps;
+  a.Tc = p->Tc_fwd;
+  a.n_max = p->n_max;
+  a.M_max = p->M_max;
+  a.S_max = p->S_max;
+  a.L = L;
+  a.ckpt_every = p->cfg.checkpoint_every;
+  a.save = save ? 1 : 0;
+  a.rho = (float)p->cfg.rho;
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sf_setup(const sf_config_t* cfg, int32_t n_problems, const int32_t* n_robots,
+             const int32_t* n_obs, const float* robot_a, const float* box, void* workspace,
+             size_t* workspace_bytes, void* stream, sf_plan_t** plan) {
+  g_detail.clear();
+  if (!workspace_bytes) return fail(SF_ERR_INVALID_ARG, "workspace_bytes is NULL");
+  std::unique_ptr<sf_plan> p;
+  int rc = build_plan(cfg, n_problems, n_robots, n_obs, robot_a, box, p);
+  if (rc) return rc;
+  if (!workspace) {
+    *workspace_bytes = p->total;
+    return SF_OK;
+  }
+  if (!plan) return fail(SF_ERR_INVALID_ARG, "plan is NULL");
+  if (*workspace_bytes < p->total)
+    return fail(SF_ERR_WORKSPACE_SMALL, "workspace has " + std::to_string(*workspace_bytes) +
+                                            " bytes, plan needs " + std::to_string(p->total));
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+    return fail(SF_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  int dev = 0, lds_max = 0;
+  SF_HIP_CHECK(hipGetDevice(&dev));
+  SF_HIP_CHECK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  if ((size_t)lds_max < std::max(p->lds_fwd, p->lds_bwd))
+    return fail(SF_ERR_SHAPE, "device LDS per workgroup (" + std::to_string(lds_max) +
+                                  ") below the plan's need");
+  SF_HIP_CHECK(sf::prepare_kernels(std::max(p->lds_fwd, p->lds_bwd)));
+  p->ws = static_cast<char*>(workspace);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  SF_HIP_CHECK(hipMemcpyAsync(p->ws + p->off_desc, p->desc.data(),
+                              sizeof(sf::ProbDesc) * p->B, hipMemcpyHostToDevice, s));
+  SF_HIP_CHECK(hipMemcpyAsync(p->ws + p->off_order, p->order.data(), sizeof(int32_t) * p->B,
+                              hipMemcpyHostToDevice, s));
+  SF_HIP_CHECK(hipMemcpyAsync(p->ws + p->off_W, p->W.data(), sizeof(float) * p->W.size(),
+                              hipMemcpyHostToDevice, s));
+  SF_HIP_CHECK(hipMemcpyAsync(p->ws + p->off_Wt, p->Wt.data(), sizeof(float) * p->Wt.size(),
+                              hipMemcpyHostToDevice, s));
+  SF_HIP_CHECK(hipMemcpyAsync(p->ws + p->off_fac, p->fac.data(), sizeof(float) * p->fac.size(),
+                              hipMemcpyHostToDevice, s));
+  SF_HIP_CHECK(hipStreamSynchronize(s));
+  *workspace_bytes = p->total;
+  *plan = p.release();
+  return SF_OK;
+}
+
+int sf_project(sf_plan_t* plan, void* workspace, const float* xi, const float* xi0,
+               const float* lam0, const float* boundary, const float* obstacles,
+               int32_t n_iters, int32_t flags, float* xi_out, float* lam_out, float* residual,
+               void* stream) {
+  g_detail.clear();
+  if (!plan) return fail(SF_ERR_INVALID_ARG, "plan is NULL");
+  if (workspace != plan->ws)
+    return fail(SF_ERR_INVALID_ARG, "workspace differs from the one bound at sf_setup");
+  if (!xi || !xi0 || !lam0 || !boundary || !xi_out || !lam_out || !residual)
+    return fail(SF_ERR_INVALID_ARG, "NULL input or output pointer");
+  if (plan->obs_total > 0 && !obstacles)
+    return fail(SF_ERR_INVALID_ARG, "obstacles is NULL but the plan has obstacles");
+  if (n_iters < 0) return fail(SF_ERR_INVALID_ARG, "n_iters < 0");
+  if (flags & ~(SF_SAVE_FOR_BACKWARD | SF_PLAIN | SF_GRAPH))
+    return fail(SF_ERR_INVALID_ARG, "unknown flag bits");
+  const bool save = flags & SF_SAVE_FOR_BACKWARD;
+  const bool plain = flags & SF_PLAIN;
+  if (save && plain) return fail(SF_ERR_INVALID_ARG, "SF_SAVE_FOR_BACKWARD with SF_PLAIN");
+  if (save && n_iters > plan->cfg.max_iters)
+    return fail(SF_ERR_INVALID_ARG, "n_iters exceeds cfg.max_iters for a saved forward");
+  if (xi_out == xi || xi_out == xi0 || lam_out == lam0 || xi_out == lam_out)
+    return fail(SF_ERR_INVALID_ARG, "outputs must not alias inputs");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  plan->saved = false;
+  sf::FwdArgs a = fwd_args(plan, xi, xi0, lam0, boundary, obstacles, n_iters, save, xi_out,
+                           lam_out, residual);
+  if (plain) {
+    sf::PlainBufs pb{};
+    pb.X = plan->at<float>(plan->off_X);
+    pb.V = plan->at<float>(plan->off_V);
+    pb.R = plan->at<float>(plan->off_R);
+    pb.xb[0] = plan->at<float>(plan->off_xb0);
+    pb.xb[1] = plan->at<float>(plan->off_xb1);
+    pb.lam = plan->at<float>(plan->off_lam);
+    pb.cxi = plan->at<float>(plan->off_pcxi);
+    pb.red = plan->at<float>(plan->off_red);
+    for (int b = 0; b < plan->B; ++b) SF_HIP_CHECK(sf::launch_plain_problem(a, pb, b, s));
+    return SF_OK;
+  }
+  if ((flags & SF_GRAPH) && s == nullptr)
+    return fail(SF_ERR_INVALID_ARG, "SF_GRAPH needs a non-default stream (capture)");
+  if (flags & SF_GRAPH) {
+    std::vector<uint64_t> key = {(uint64_t)xi,      (uint64_t)xi0,     (uint64_t)lam0,
+                                 (uint64_t)boundary, (uint64_t)obstacles, (uint64_t)xi_out,
+                                 (uint64_t)lam_out, (uint64_t)residual, (uint64_t)n_iters,
+                                 (uint64_t)save,    (uint64_t)plan->threads, (uint64_t)s};
+    GraphEntry* hit = nullptr;
+    for (auto& g : plan->graphs)
+      if (g.key == key) hit = &g;
+    if (!hit) {
+      GraphEntry g;
+      g.key = key;
+      SF_HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      hipError_t le = sf::launch_fwd_fused(a, plan->threads, plan->lds_fwd, s);
+      hipError_t ce = hipStreamEndCapture(s, &g.graph);
+      SF_HIP_CHECK(le);
+      SF_HIP_CHECK(ce);
+      SF_HIP_CHECK(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
+      if (plan->graphs.size() >= 8) {
+        (void)hipGraphExecDestroy(plan->graphs.front().exec);
+        (void)hipGraphDestroy(plan->graphs.front().graph);
+        plan->graphs.erase(plan->graphs.begin());
+      }
+      plan->graphs.push_back(g);
+      hit = &plan->graphs.back();
+    }
+    SF_HIP_CHECK(hipGraphLaunch(hit->exec, s));
+  } else {
+    SF_HIP_CHECK(sf::launch_fwd_fused(a, plan->threads, plan->lds_fwd, s));
+  }
+  plan->saved = save;
+  plan->saved_L = n_iters;
+  return SF_OK;
+}
+
+int sf_project_backward(sf_plan_t* plan, void* workspace, const float* g_xi_out,
+                        const float* g_lam_out, const float* g_residual, float fp_weight,
+                        float* g_xi, float* g_xi0, float* g_lam0, void* stream) {
+  g_detail.clear();
+  if (!plan) return fail(SF_ERR_INVALID_ARG, "plan is NULL");
+  if (workspace != plan->ws)
+    return fail(SF_ERR_INVALID_ARG, "workspace differs from the one bound at sf_setup");
+  if (!plan->saved) return fail(SF_ERR_NOT_SAVED, "no saved forward on this plan");
+  if (!std::isfinite(fp_weight)) return fail(SF_ERR_NONFINITE, "fp_weight not finite");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  sf::BwdArgs a{};
+  a.probs = plan->at<sf::ProbDesc>(plan->off_desc);
+  a.order = plan->at<int32_t>(plan->off_order);
+  a.W = plan->at<float>(plan->off_W);
+  a.Wt = plan->at<float>(plan->off_Wt);
+  a.fac = plan->at<float>(plan->off_fac);
+  a.cxi = plan->at<float>(plan->off_cxi);
+  a.obs = plan->at<float>(plan->off_obs);
+  a.ckpt = plan->at<float>(plan->off_ckpt);
+  a.fin = plan->at<float>(plan->off_final);
+  a.seg = plan->at<float>(plan->off_seg);
+  a.g_xi_out = g_xi_out;
+  a.g_lam_out = g_lam_out;
+  a.g_res = g_residual;
+  a.g_xi = g_xi;
+  a.g_xi0 = g_xi0;
+  a.g_lam0 = g_lam0;
+  a.S_total = plan->S_total;
+  a.B = plan->B;
+  a.nc = plan->cfg.n_coef;
+  a.T = plan->cfg.n_steps;
+  a.Tc = plan->Tc_bwd;
+  a.n_max = plan->n_max;
+  a.M_max = plan->M_max;
+  a.S_max = plan->S_max;
+  a.L = plan->saved_L;
+  a.ckpt_every = plan->cfg.checkpoint_every;
+  a.rho = (float)plan->cfg.rho;
+  a.fp_weight = fp_weight;
+  SF_HIP_CHECK(sf::launch_bwd_fused(a, plan->threads, plan->lds_bwd, s));
+  return SF_OK;
+}
+
+void sf_destroy(sf_plan_t* plan) { delete plan; }
+
+const char* sf_error_string(int code) {
+  switch (code) {
+    case SF_OK: return "success";
+    case SF_ERR_INVALID_ARG: return "invalid argument";
+    case SF_ERR_SHAPE: return "unsupported shape";
+    case SF_ERR_WORKSPACE_SMALL: return "workspace too small";
+    case SF_ERR_NOT_SAVED: return "no saved forward for the backward";
+    case SF_ERR_HIP: return "HIP runtime error";
+    case SF_ERR_NONFINITE: return "non-finite input";
+    default: return "unknown error code";
+  }
+}
+
+const char* sf_last_error_detail(void) { return g_detail.c_str(); }
+
+int sf_plan_threads(const sf_plan_t* plan) { return plan ? plan->threads : 0; }
+
+}  // extern "C"

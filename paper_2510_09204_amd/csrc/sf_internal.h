@@ -1,0 +1,119 @@
+// Internal declarations shared by the host runtime (sf_host.cpp) and the HIP
+// kernels (sf_kernels.hip).  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sf {
+
+constexpr int kDim = 2;
+constexpr int kMaxCoef = 32;
+
+// Per-problem descriptor, resident in the workspace.
+struct ProbDesc {
+  int32_t n;         // robots
+  int32_t M;         // obstacles
+  int32_t coef_off;  // first float of this problem in coefficient arrays
+  int32_t rob_off;   // first robot (boundary rows)
+  int32_t obs_off;   // first obstacle (obstacle rows)
+  int32_t fac;       // index of this problem's factor block
+  int32_t pos_off;   // first (robot, step) slot in the plain-path position buffers
+  int32_t pad0;
+  float a;           // minimum robot centre distance
+  float pmin[2];
+  float pmax[2];
+  float pad1[3];
+};
+static_assert(sizeof(ProbDesc) == 64, "descriptor layout");
+
+// Factor block of one (n, M) class, float32, each matrix row-major [n_coef][.]:
+//   S_perp, DS = S_par - S_perp, SH_perp, DSH = SH_par - SH_perp   [nc][nc]
+//   N_perp, DN = N_par - N_perp                                    [nc][2]
+__host__ __device__ inline int fac_stride(int nc) { return 4 * nc * nc + 4 * nc; }
+
+struct FwdArgs {
+  const ProbDesc* probs;
+  const int32_t* order;   // launch slot -> problem (longest first)
+  const float* W;         // [T][nc]
+  const float* Wt;        // [nc][T]
+  const float* fac;       // factor blocks
+  const float* xi;
+  const float* xi0;
+  const float* lam0;
+  const float* boundary;
+  const float* obstacles;
+  float* xi_out;
+  float* lam_out;
+  float* residual;        // [B][4]
+  float* ws_cxi;          // saved constant term, coefficient layout
+  float* ws_obs;          // saved obstacles
+  float* ws_ckpt;         // [n_ckpt][2][S_total]
+  float* ws_final;        // [2][S_total]
+  int64_t S_total;        // floats in one coefficient array
+  int32_t B;
+  int32_t nc;
+  int32_t T;
+  int32_t Tc;             // time-chunk length held in LDS
+  int32_t n_max, M_max, S_max;
+  int32_t L;
+  int32_t ckpt_every;
+  int32_t save;
+  float rho;
+};
+
+struct BwdArgs {
+  const ProbDesc* probs;
+  const int32_t* order;
+  const float* W;
+  const float* Wt;
+  const float* fac;
+  const float* cxi;       // saved constant term
+  const float* obs;       // saved obstacles
+  const float* ckpt;      // [n_ckpt][2][S_total]
+  const float* fin;       // [2][S_total]
+  float* seg;             // recompute scratch [ckpt_every][2][S_total]
+  const float* g_xi_out;  // nullable
+  const float* g_lam_out; // nullable
+  const float* g_res;     // nullable [B][4]
+  float* g_xi;            // nullable
+  float* g_xi0;           // nullable
+  float* g_lam0;          // nullable
+  int64_t S_total;
+  int32_t B;
+  int32_t nc;
+  int32_t T;
+  int32_t Tc;
+  int32_t n_max, M_max, S_max;
+  int32_t L;
+  int32_t ckpt_every;
+  float rho;
+  float fp_weight;
+};
+
+// Dynamic LDS bytes of the fused kernels for given batch maxima.
+size_t fwd_lds_bytes(int nc, int T, int Tc, int n_max, int M_max, int S_max, int threads);
+size_t bwd_lds_bytes(int nc, int T, int Tc, int n_max, int M_max, int S_max, int threads);
+
+hipError_t launch_fwd_fused(const FwdArgs& a, int threads, size_t lds, hipStream_t s);
+hipError_t launch_bwd_fused(const BwdArgs& a, int threads, size_t lds, hipStream_t s);
+
+// Plain path: one problem, one iteration per launch group.
+struct PlainBufs {
+  float* X;      // [sum n][T][2] positions
+  float* V;      // [sum n][T][2] constraint sums
+  float* R;      // coefficient layout
+  float* xb[2];  // ping-pong xi_bar, coefficient layout
+  float* lam;    // coefficient layout
+  float* cxi;    // coefficient layout
+  float* red;    // [B][4] residual partials
+};
+hipError_t launch_plain_problem(const FwdArgs& a, const PlainBufs& pb, int b,
+                                hipStream_t s);
+
+hipError_t launch_fill(float* p, float v, int64_t n, hipStream_t s);
+
+// Raise the dynamic-LDS limit of the fused kernels to `lds` bytes.
+hipError_t prepare_kernels(size_t lds);
+
+}  // namespace sf

@@ -1,0 +1,141 @@
+"""Helpers shared by the GPU tests: run the HIP path through the C ABI and the
+FP64 oracle on the same (float32-rounded) inputs, and compare."""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle import SFAdjoint, SFOracle
+from workloads import N_DIM, pack, unpack_coefs
+
+# Tolerances of the GPU path against the FP64 oracle: per problem, relative L2
+# error of the coefficients, and error of the residual norms (metres):
+# 1e-5 absolute at converged scale plus 1e-4 relative, the share of a
+# residual that a 1e-4 relative coefficient error can move.
+REL_TOL = 1e-4
+RES_TOL = 1e-5
+RES_REL_TOL = 1e-4
+GRAD_REL_TOL = 1e-3
+
+
+def oracle_inputs(packed, problems):
+    """Per-problem float64 copies of exactly the float32 values the GPU sees."""
+    xi = unpack_coefs(packed.xi.astype(np.float64), problems)
+    xi0 = unpack_coefs(packed.xi0.astype(np.float64), problems)
+    lam0 = unpack_coefs(packed.lam0.astype(np.float64), problems)
+    out, r, o = [], 0, 0
+    for b, p in enumerate(problems):
+        bnd = packed.boundary[r * 4:(r + p.n) * 4].astype(np.float64).reshape(p.n, 2, N_DIM)
+        obs = packed.obstacles[o * 3:(o + p.M) * 3].astype(np.float64).reshape(p.M, 3)
+        box = packed.box[b].astype(np.float64)
+        out.append(dict(n=p.n, M=p.M, n_coef=p.n_coef, n_steps=p.n_steps,
+                        a=float(packed.robot_a[b]), box=box, obstacles=obs, boundary=bnd,
+                        xi=xi[b], xi0=xi0[b], lam0=lam0[b]))
+        r += p.n
+        o += p.M
+    return out
+
+
+def oracle_solve(inp, rho, L):
+    orc = SFOracle(inp["n"], inp["M"], inp["n_coef"], inp["n_steps"], rho, inp["a"],
+                   inp["box"], inp["obstacles"], inp["boundary"])
+    return orc.solve(inp["xi"], inp["xi0"], inp["lam0"], L)
+
+
+def oracle_grad(inp, rho, L, g_xi_out, g_lam_out, g_r1=0.0, g_r2=0.0, fp_weight=0.0):
+    orc = SFOracle(inp["n"], inp["M"], inp["n_coef"], inp["n_steps"], rho, inp["a"],
+                   inp["box"], inp["obstacles"], inp["boundary"])
+    return SFAdjoint(orc).gradient(inp["xi"], inp["xi0"], inp["lam0"], L, g_xi_out,
+                                   g_lam_out, g_r1, g_r2, fp_weight)
+
+
+def make_plan(problems, rho, L=0, ckpt=1, threads=0, device="cuda"):
+    from paper_2510_09204_amd import SFPlan
+    pk = pack(problems)
+    plan = SFPlan(pk.n_robots, pk.n_obs, pk.robot_a, pk.box, pk.n_coef, pk.n_steps, rho,
+                  checkpoint_every=ckpt, max_iters=L, threads=threads, device=device)
+    return plan, pk
+
+
+def gpu_forward(problems, rho, L, save=False, ckpt=1, threads=0, plain=False, graph=False,
+                packed=None, plan=None):
+    import torch
+    from paper_2510_09204_amd import to_device
+    if plan is None:
+        plan, pk = make_plan(problems, rho, L if save else 0, ckpt, threads)
+    else:
+        pk = pack(problems)
+    if packed is not None:
+        pk = packed
+    t = to_device(pk)
+    xo, lo, res = plan.project(t["xi"], t["xi0"], t["lam0"], t["boundary"], t["obstacles"],
+                               L, save=save, plain=plain, graph=graph)
+    torch.cuda.synchronize()
+    return dict(plan=plan, packed=pk, t=t, xi=xo.cpu().numpy(), lam=lo.cpu().numpy(),
+                res=res.cpu().numpy())
+
+
+def rel_err(a, b):
+    a, b = np.asarray(a, np.float64).ravel(), np.asarray(b, np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def oracle_residual_terms(inp, rho, xi_bar):
+    """||r_1||, ||r_2|| of a given iterate, in FP64."""
+    orc = SFOracle(inp["n"], inp["M"], inp["n_coef"], inp["n_steps"], rho, inp["a"],
+                   inp["box"], inp["obstacles"], inp["boundary"])
+    r1, r2, _, _, _ = orc.residual_terms(orc.flat(xi_bar))
+    return float(np.linalg.norm(r1)), float(np.linalg.norm(r2))
+
+
+def oracle_sensitivity(inp, rho, L, eps=1e-7, seed=0):
+    """Relative change of the oracle's xi_bar^L when the warm start moves by
+    eps (relative): large values mark an instance whose iterate sequence is
+    decided by rounding (a pair or obstacle distance grazing its kink)."""
+    base = oracle_solve(inp, rho, L)
+    rng = np.random.default_rng(seed)
+    pert = dict(inp)
+    pert["xi0"] = inp["xi0"] * (1.0 + eps * rng.standard_normal(inp["xi0"].shape))
+    moved = oracle_solve(pert, rho, L)
+    return rel_err(moved.xi_bar, base.xi_bar)
+
+
+ILL_CONDITIONED = 1e-5   # oracle output change under a 1e-7 input change
+
+
+def compare_forward(problems, out, rho, L, idx=None, rel_tol=REL_TOL, res_tol=RES_TOL,
+                    allow_ill_conditioned=False):
+    """Check GPU outputs against the oracle for the problems in `idx`.
+
+    Per problem: the coefficients (xi_bar, lambda) within rel_tol; the GPU's
+    ||r_1||, ||r_2|| equal to the FP64 residual of the GPU's own iterate (the
+    residual computation itself, 1e-5 + 1e-5 relative); the total residual
+    within 1e-5 + 1e-4 relative of the oracle's.  With allow_ill_conditioned, a
+    coefficient mismatch on an instance the oracle itself flags as
+    rounding-decided is recorded instead of failing."""
+    inps = oracle_inputs(out["packed"], problems)
+    gx = unpack_coefs(out["xi"], problems)
+    gl = unpack_coefs(out["lam"], problems)
+    errs = []
+    for b in (range(len(problems)) if idx is None else idx):
+        ref = oracle_solve(inps[b], rho, L)
+        e_x = rel_err(gx[b], ref.xi_bar)
+        lam_scale = max(np.linalg.norm(ref.lam), np.linalg.norm(ref.xi_bar))
+        e_l = float(np.linalg.norm(gl[b] - ref.lam) / lam_scale)
+        g1, g2 = float(out["res"][b, 0]), float(out["res"][b, 1])
+        o1, o2 = oracle_residual_terms(inps[b], rho, gx[b])
+        e_tot = abs(np.hypot(g1, g2) - ref.residual)
+        rec = dict(b=b, xi=e_x, lam=e_l, own_r1=abs(g1 - o1), own_r2=abs(g2 - o2),
+                   total=e_tot, res=ref.residual, status=float(out["res"][b, 3]))
+        errs.append(rec)
+        assert rec["status"] == 0.0, rec
+        assert rec["own_r1"] <= 1e-5 + 1e-5 * o1 and rec["own_r2"] <= 1e-5 + 1e-5 * o2, rec
+        if e_x > rel_tol or e_l > rel_tol:
+            if allow_ill_conditioned:
+                sens = oracle_sensitivity(inps[b], rho, L)
+                rec["sensitivity"] = sens
+                if sens > ILL_CONDITIONED:
+                    rec["ill_conditioned"] = True
+                    continue
+            raise AssertionError(rec)
+        assert e_tot <= res_tol + RES_REL_TOL * ref.residual, rec
+    return errs

@@ -1,0 +1,136 @@
+"""Adjoint parity: the HIP reverse sweep (sf_project_backward through the C
+ABI) against the FP64 oracle's hand-written reverse sweep, which is itself
+pinned to central finite differences on the CPU."""
+import numpy as np
+import pytest
+
+from sf_testlib import GRAD_REL_TOL, make_plan, oracle_grad, oracle_inputs, rel_err
+from workloads import CONFIGS, make_batch, make_problem, pack, scaled, unpack_coefs
+
+pytestmark = pytest.mark.gpu
+RHO = 0.5
+
+
+def _run(problems, L, ckpt, g_xi, g_lam, g_res=None, fp_weight=0.0, threads=0):
+    import torch
+    from paper_2510_09204_amd import to_device
+    plan, pk = make_plan(problems, RHO, L=L, ckpt=ckpt, threads=threads)
+    t = to_device(pk)
+    xo, lo, res = plan.project(t["xi"], t["xi0"], t["lam0"], t["boundary"], t["obstacles"], L,
+                               save=True)
+    gx = torch.from_numpy(np.concatenate([g.ravel() for g in g_xi]).astype(np.float32)).cuda()
+    gl = torch.from_numpy(np.concatenate([g.ravel() for g in g_lam]).astype(np.float32)).cuda()
+    gr = None if g_res is None else torch.from_numpy(g_res.astype(np.float32)).cuda()
+    g = plan.backward(gx, gl, gr, fp_weight)
+    torch.cuda.synchronize()
+    return pk, [unpack_coefs(x.cpu().numpy(), problems) for x in g], res.cpu().numpy()
+
+
+def _cotangents(problems, seed):
+    rng = np.random.default_rng(seed)
+    g_xi = [rng.standard_normal(p.xi.shape) for p in problems]
+    g_lam = [rng.standard_normal(p.xi.shape) for p in problems]
+    return g_xi, g_lam
+
+
+def _check(problems, pk, grads, L, g_xi, g_lam, g_res=None, fp_weight=0.0, idx=None):
+    inps = oracle_inputs(pk, problems)
+    for b in (range(len(problems)) if idx is None else idx):
+        gr1 = 0.0 if g_res is None else float(np.float32(g_res[b, 0]))
+        gr2 = 0.0 if g_res is None else float(np.float32(g_res[b, 1]))
+        ref = oracle_grad(inps[b], RHO, L, g_xi[b].astype(np.float32).astype(np.float64),
+                          g_lam[b].astype(np.float32).astype(np.float64), gr1, gr2, fp_weight)
+        for name, gv, rv in (("xi", grads[0][b], ref.g_xi), ("xi0", grads[1][b], ref.g_xi0),
+                             ("lam0", grads[2][b], ref.g_lam0)):
+            e = rel_err(gv, rv)
+            assert e <= GRAD_REL_TOL, (b, name, e)
+
+
+@pytest.mark.parametrize("L", [20, 100])
+def test_adjoint_four_robot_copy(gpu, L):
+    cfg = scaled(CONFIGS[3], n_robots=(4, 4), n_obs=(3, 3), arena=4.0)
+    probs = [make_problem(cfg, i) for i in range(3)]
+    g_xi, g_lam = _cotangents(probs, 0)
+    pk, grads, _ = _run(probs, L, 1, g_xi, g_lam)
+    _check(probs, pk, grads, L, g_xi, g_lam)
+
+
+def test_adjoint_with_residual_and_fixed_point_terms(gpu):
+    cfg = scaled(CONFIGS[3], n_robots=(6, 6), n_obs=(4, 4), arena=4.0)
+    probs = [make_problem(cfg, i) for i in range(2)]
+    g_xi, g_lam = _cotangents(probs, 1)
+    g_res = np.array([[0.7, 0.4, 0.0, 0.0], [1.3, 0.0, 0.0, 0.0]])
+    pk, grads, _ = _run(probs, 30, 1, g_xi, g_lam, g_res, fp_weight=0.25)
+    _check(probs, pk, grads, 30, g_xi, g_lam, g_res, 0.25)
+
+
+def test_adjoint_c3_problem(gpu):
+    probs = make_batch(CONFIGS[3], batch=2)
+    g_xi, g_lam = _cotangents(probs, 2)
+    pk, grads, _ = _run(probs, 40, 10, g_xi, g_lam)
+    _check(probs, pk, grads, 40, g_xi, g_lam)
+
+
+@pytest.mark.parametrize("ckpt", [3, 7, 40])
+def test_checkpoint_interval_does_not_change_gradients(gpu, ckpt):
+    probs = make_batch(CONFIGS[4], batch=4)
+    g_xi, g_lam = _cotangents(probs, 3)
+    g_res = np.tile([[0.5, 0.5, 0.0, 0.0]], (4, 1))
+    _, ref, _ = _run(probs, 40, 1, g_xi, g_lam, g_res, fp_weight=0.1)
+    _, out, _ = _run(probs, 40, ckpt, g_xi, g_lam, g_res, fp_weight=0.1)
+    for q in range(3):
+        for b in range(4):
+            np.testing.assert_array_equal(out[q][b], ref[q][b])
+
+
+def test_c5_shape_adjoint_with_time_chunks(gpu):
+    probs = make_batch(CONFIGS[5], batch=1)
+    g_xi, g_lam = _cotangents(probs, 4)
+    pk, grads, _ = _run(probs, 12, 5, g_xi, g_lam)
+    _check(probs, pk, grads, 12, g_xi, g_lam)
+
+
+def test_autograd_function_matches_oracle_loss_gradient(gpu):
+    """loss = sum_b ||xi_bar^L - xi_straight||^2 + ||r_1||^2 + ||r_2||^2 through
+    SFProject; gradient w.r.t. the flow sample and the warm start."""
+    import torch
+    from paper_2510_09204_amd import SFProject, to_device
+    cfg = scaled(CONFIGS[3], n_robots=(4, 4), n_obs=(3, 3), arena=4.0)
+    probs = [make_problem(cfg, i) for i in range(2)]
+    L = 25
+    plan, pk = make_plan(probs, RHO, L=L, ckpt=5)
+    t = to_device(pk)
+    straight = torch.from_numpy(np.concatenate([p.straight.ravel() for p in probs])
+                                .astype(np.float32)).cuda()
+    xi = t["xi"].clone().requires_grad_(True)
+    xi0 = t["xi0"].clone().requires_grad_(True)
+    lam0 = t["lam0"].clone().requires_grad_(True)
+    xo, lo, res = SFProject.apply(xi, xi0, lam0, t["boundary"], t["obstacles"], plan, L)
+    loss = ((xo - straight) ** 2).sum() + (res[:, 0] ** 2).sum() + (res[:, 1] ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    xo_np = xo.detach().cpu().numpy()
+    res_np = res.detach().cpu().numpy()
+    g_out = 2.0 * (xo_np - straight.cpu().numpy())
+    g_xi_b = unpack_coefs(g_out, probs)
+    inps = oracle_inputs(pk, probs)
+    for b in range(2):
+        ref = oracle_grad(inps[b], RHO, L, g_xi_b[b].astype(np.float64),
+                          np.zeros_like(g_xi_b[b], dtype=np.float64),
+                          2.0 * float(res_np[b, 0]), 2.0 * float(res_np[b, 1]))
+        got = [unpack_coefs(v.grad.cpu().numpy(), probs)[b] for v in (xi, xi0, lam0)]
+        for gv, rv in zip(got, (ref.g_xi, ref.g_xi0, ref.g_lam0)):
+            assert rel_err(gv, rv) <= GRAD_REL_TOL
+
+
+def test_backward_without_saved_forward_is_an_error(gpu):
+    import torch
+    from paper_2510_09204_amd import SFError, to_device
+    probs = make_batch(CONFIGS[3], batch=1)
+    plan, pk = make_plan(probs, RHO, L=10)
+    t = to_device(pk)
+    plan.project(t["xi"], t["xi0"], t["lam0"], t["boundary"], t["obstacles"], 10, save=False)
+    with pytest.raises(SFError) as e:
+        plan.backward(t["xi"], None, None)
+    assert e.value.code == -4
+    torch.cuda.synchronize()

@@ -1,0 +1,214 @@
+"""Forward parity of the HIP SF (through the C ABI) with the FP64 oracle.
+
+Sizes are chosen so that the oracle finishes in seconds while the GPU launch
+still spans several waves, a ragged tail of time steps and (for the long
+horizon case) several LDS time chunks; the full-size batch is checked on
+sampled problems in the launch configuration the benchmark times.
+"""
+import numpy as np
+import pytest
+
+from sf_testlib import compare_forward, gpu_forward, make_plan, rel_err
+from workloads import CONFIGS, make_batch, make_problem, pack, scaled, straight_coefficients
+from workloads.gen import Problem
+
+pytestmark = pytest.mark.gpu
+RHO = 0.5
+
+
+def test_c1_single_problem(gpu):
+    probs = make_batch(CONFIGS[1])
+    out = gpu_forward(probs, RHO, 100)
+    compare_forward(probs, out, RHO, 100)
+
+
+def test_c2_candidates_subset(gpu):
+    probs = make_batch(CONFIGS[2], batch=6)
+    out = gpu_forward(probs, RHO, 200)
+    compare_forward(probs, out, RHO, 200)
+
+
+def test_c3_subset(gpu):
+    probs = make_batch(CONFIGS[3], batch=3)
+    out = gpu_forward(probs, RHO, 100)
+    compare_forward(probs, out, RHO, 100)
+
+
+def test_converged_candidates_residual_within_1e5(gpu):
+    """Candidates run past the point where the oracle's residual is <= 1e-3:
+    the GPU residual within 1e-5 (absolute) of the oracle's."""
+    probs = make_batch(CONFIGS[2], batch=4)
+    out = gpu_forward(probs, RHO, 400)
+    errs = compare_forward(probs, out, RHO, 400)
+    for e in errs:
+        assert e["res"] <= 1e-3 and e["total"] <= 1e-5, e
+
+
+def test_c3_full_batch_sampled(gpu):
+    """All 64 problems in one launch (the benchmark's configuration); sampled
+    problems against the oracle, every problem's outputs finite."""
+    probs = make_batch(CONFIGS[3])
+    out = gpu_forward(probs, RHO, 100)
+    assert np.all(out["res"][:, 3] == 0.0)
+    compare_forward(probs, out, RHO, 100, idx=[0, 37, 63])
+
+
+def test_c4_uneven_batch_sampled(gpu):
+    probs = make_batch(CONFIGS[4])
+    out = gpu_forward(probs, RHO, 150)
+    ns = np.array([p.n for p in probs])
+    pick = [int(np.argmin(ns)), int(np.argmax(ns)), 5, 17]
+    compare_forward(probs, out, RHO, 150, idx=pick)
+
+
+def test_c5_shape_short_run(gpu):
+    probs = make_batch(CONFIGS[5], batch=2)
+    out = gpu_forward(probs, RHO, 30)
+    compare_forward(probs, out, RHO, 30)
+
+
+def test_long_horizon_uses_several_time_chunks(gpu):
+    cfg = scaled(CONFIGS[3], n_robots=(40, 40), n_obs=(6, 6), n_steps=1500, arena=8.0)
+    probs = [make_problem(cfg, 0)]
+    plan, _ = make_plan(probs, RHO)
+    out = gpu_forward(probs, RHO, 15, plan=plan)
+    compare_forward(probs, out, RHO, 15)
+
+
+def test_zero_iterations_returns_warm_start_and_its_residual(gpu):
+    probs = make_batch(CONFIGS[3], batch=2)
+    out = gpu_forward(probs, RHO, 0)
+    pk = out["packed"]
+    np.testing.assert_array_equal(out["xi"], pk.xi0)
+    np.testing.assert_array_equal(out["lam"], pk.lam0)
+    compare_forward(probs, out, RHO, 0)
+
+
+def test_one_iteration(gpu):
+    probs = make_batch(CONFIGS[3], batch=2)
+    out = gpu_forward(probs, RHO, 1)
+    compare_forward(probs, out, RHO, 1)
+
+
+def _custom(n, M, starts, goals, obstacles, n_coef=7, T=33, half=3.0, r=0.2, noise=None):
+    starts, goals = np.asarray(starts, float), np.asarray(goals, float)
+    xi = straight_coefficients(starts, goals, n_coef)
+    if noise is not None:
+        xi = xi + noise
+    return Problem(n=n, M=M, n_coef=n_coef, n_steps=T, r_robot=r, a=2 * r,
+                   box=np.array([[-half, -half], [half, half]]),
+                   obstacles=np.asarray(obstacles, float).reshape(M, 3),
+                   boundary=np.stack([starts, goals], axis=1), xi=xi,
+                   straight=straight_coefficients(starts, goals, n_coef))
+
+
+def test_edge_single_robot_no_obstacles(gpu):
+    rng = np.random.default_rng(0)
+    p = _custom(1, 0, [[-1.0, 0.2]], [[1.0, -0.4]], [], noise=0.3 * rng.standard_normal((2, 1, 7)))
+    out = gpu_forward([p], RHO, 50)
+    compare_forward([p], out, RHO, 50)
+
+
+def test_edge_coincident_robots(gpu):
+    """Two robots with identical trajectories: every pair difference is 0, the
+    alpha step's atan2(0, 0) = 0 tie, which decides the first step uniquely.
+    (Later iterates of this exactly symmetric instance are rounding-decided.)"""
+    p = _custom(2, 0, [[-1.0, 0.0], [-1.0, 0.0]], [[1.0, 0.0], [1.0, 0.0]], [])
+    out = gpu_forward([p], RHO, 1)
+    compare_forward([p], out, RHO, 1)
+
+
+def test_edge_trajectory_through_obstacle_centre(gpu):
+    """A robot path that passes exactly through an obstacle centre at one time
+    sample (the obstacle-side atan2(0, 0) tie) for one step."""
+    p = _custom(1, 1, [[-1.0, -1.0]], [[1.0, 1.0]], [[0.0, 0.0, 0.5]])
+    out = gpu_forward([p], RHO, 1)
+    compare_forward([p], out, RHO, 1)
+
+
+def test_edge_box_violations_and_mixed_batch(gpu):
+    rng = np.random.default_rng(1)
+    a = _custom(3, 1, [[-2.5, 0.0], [0.0, -2.5], [2.5, 0.0]], [[2.5, 0.0], [0.0, 2.5], [-2.5, 0.0]],
+                [[0.0, 0.0, 0.6]], noise=1.0 * rng.standard_normal((2, 3, 7)), half=2.6)
+    b = _custom(1, 2, [[-1.0, -1.0]], [[1.0, 1.0]], [[0.08, -0.05, 0.5], [0.5, 0.4, 0.3]])
+    c = _custom(5, 0, [[-2, -2], [-1, -2], [0, -2], [1, -2], [2, -2]],
+                [[2, 2], [1, 2], [0, 2], [-1, 2], [-2, 2]], [],
+                noise=0.2 * rng.standard_normal((2, 5, 7)))
+    probs = [a, b, c]
+    out = gpu_forward(probs, RHO, 40)
+    compare_forward(probs, out, RHO, 40)
+
+
+def test_plain_path_matches_fused_bitwise(gpu):
+    probs = make_batch(CONFIGS[3], batch=4)
+    fused = gpu_forward(probs, RHO, 60)
+    plain = gpu_forward(probs, RHO, 60, plain=True)
+    np.testing.assert_array_equal(plain["xi"], fused["xi"])
+    np.testing.assert_array_equal(plain["lam"], fused["lam"])
+    np.testing.assert_allclose(plain["res"], fused["res"], rtol=1e-5, atol=1e-7)
+
+
+@pytest.mark.parametrize("threads", [256, 512, 1024])
+def test_thread_counts_give_identical_coefficients(gpu, threads):
+    probs = make_batch(CONFIGS[4], batch=6)
+    ref = gpu_forward(probs, RHO, 40, threads=256)
+    out = gpu_forward(probs, RHO, 40, threads=threads)
+    np.testing.assert_array_equal(out["xi"], ref["xi"])
+    np.testing.assert_array_equal(out["lam"], ref["lam"])
+    np.testing.assert_allclose(out["res"], ref["res"], rtol=1e-5, atol=1e-7)
+
+
+def test_repeat_is_bitwise_deterministic(gpu):
+    probs = make_batch(CONFIGS[2], batch=8)
+    a = gpu_forward(probs, RHO, 80)
+    b = gpu_forward(probs, RHO, 80)
+    np.testing.assert_array_equal(a["xi"], b["xi"])
+    np.testing.assert_array_equal(a["res"], b["res"])
+
+
+def test_graph_replays_match_eager(gpu):
+    import torch
+    probs = make_batch(CONFIGS[3], batch=5)
+    eager = gpu_forward(probs, RHO, 50)
+    plan = eager["plan"]
+    t = eager["t"]
+    outs = (torch.empty_like(t["xi"]), torch.empty_like(t["xi"]),
+            torch.empty((len(probs), 4), device=t["xi"].device))
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    for rep in range(4):
+        with torch.cuda.stream(side):
+            outs[0].fill_(float("nan"))
+            plan.project(t["xi"], t["xi0"], t["lam0"], t["boundary"], t["obstacles"], 50,
+                         graph=True, out=outs)
+        side.synchronize()
+        # eager work between replays
+        _ = (t["xi"] * 2.0).sum().item()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(outs[0].cpu().numpy(), eager["xi"])
+        np.testing.assert_array_equal(outs[2].cpu().numpy(), eager["res"])
+
+
+def test_resume_equals_one_long_run(gpu):
+    """(xi_bar, lambda) is the whole fixed-point state: L1 + L2 iterations in two
+    calls equal L1 + L2 in one."""
+    import torch
+    probs = make_batch(CONFIGS[3], batch=3)
+    full = gpu_forward(probs, RHO, 70)
+    first = gpu_forward(probs, RHO, 30)
+    plan, t = first["plan"], first["t"]
+    xi1 = torch.from_numpy(first["xi"]).cuda()
+    lam1 = torch.from_numpy(first["lam"]).cuda()
+    xo, lo, res = plan.project(t["xi"], xi1, lam1, t["boundary"], t["obstacles"], 40)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(xo.cpu().numpy(), full["xi"])
+    np.testing.assert_array_equal(lo.cpu().numpy(), full["lam"])
+
+
+def test_nonfinite_input_is_flagged_not_crashed(gpu):
+    probs = make_batch(CONFIGS[3], batch=2)
+    pk = pack(probs)
+    pk.xi0[5] = np.nan
+    out = gpu_forward(probs, RHO, 10, packed=pk)
+    assert out["res"][0, 3] == 1.0
+    assert out["res"][1, 3] == 0.0
