@@ -29,7 +29,7 @@ if ROOT not in sys.path:
 METRIC = "SF problems/s (fwd, fwd+bwd) at 32 robots, residual≤1e-3; batched vs plain"
 RHO = 0.5
 # L* per workload at rho = 0.5 (oracle/lstar.py; recorded with its output in the design doc)
-LSTAR = {1: 100, 2: 400, 3: 1200, 4: 2000, 5: 2000}
+LSTAR = {1: 100, 2: 400, 3: 2000, 4: 2000, 5: 2000}
 CKPT = 10
 # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz; FMA = 2 flops.  Packed FP32
 # is disabled in this build, so scalar FP32 FMA is the attainable ceiling.
@@ -100,7 +100,17 @@ def main(argv=None):
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB MiB (counter calibration)")
     a = ap.parse_args(argv)
+    if a.copy_probe:
+        import torch
+        src = torch.ones(a.copy_probe * (1 << 18), dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(copy_probe_bytes=src.numel() * 4)))
+        return 0
     if a.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for {a.gpus}); "
               "the problems of a batch are independent, so a multi-GPU run would shard "
@@ -201,7 +211,7 @@ def main(argv=None):
                 config=dict(workload=f"{cfg.name}: {cfg.description}", global_batch=B,
                             robots=int(pk.n_robots.max()), obstacles=int(pk.n_obs.max()),
                             n_coef=nc, n_steps=T, iters=L, rho=RHO, checkpoint_every=CKPT,
-                            threads=plan.threads, residual_tol=1e-3),
+                            threads_fwd=plan.threads, residual_tol=1e-3),
                 fwd_problems_per_s=round(B / (fwd_only_ms / 1e3), 2),
                 fwd_ms=round(fwd_only_ms, 4),
                 plain_fwd_problems_per_s=None if plain is None else round(plain["problems_per_s"], 2),

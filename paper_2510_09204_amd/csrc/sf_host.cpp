@@ -3,14 +3,15 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
-#include <tuple>
 #include <vector>
 
 #include "../../include/sf.h"
@@ -166,18 +167,21 @@ struct sf_plan {
   int B = 0;
   std::vector<sf::ProbDesc> desc;
   std::vector<int32_t> order;
-  std::vector<float> W, Wt, fac;
+  std::vector<float> W, fac;
   int nfac = 0;
   int n_max = 0, M_max = 0, S_max = 0;
   int64_t S_total = 0, pos_total = 0, obs_total = 0, rob_total = 0;
   int n_ckpt = 0;
-  int threads = 512;
+  int threads = 512;      // fused forward
+  int threads_bwd = 512;  // fused adjoint
+  bool tune_fwd = false;  // pick threads on first use (cfg.threads == 0)
+  bool tune_bwd = false;
   int Tc_fwd = 0, Tc_bwd = 0;
   size_t lds_fwd = 0, lds_bwd = 0;
   // workspace layout (byte offsets)
-  size_t off_desc = 0, off_order = 0, off_W = 0, off_Wt = 0, off_fac = 0, off_cxi = 0,
+  size_t off_desc = 0, off_order = 0, off_W = 0, off_fac = 0, off_cxi = 0,
          off_obs = 0, off_ckpt = 0, off_final = 0, off_seg = 0, off_X = 0, off_V = 0,
-         off_R = 0, off_xb0 = 0, off_xb1 = 0, off_lam = 0, off_pcxi = 0, off_red = 0,
+         off_R = 0, off_xb0 = 0, off_xb1 = 0, off_lam = 0, off_pcxi = 0, off_red = 0, off_part = 0,
          total = 0;
   char* ws = nullptr;
   bool saved = false;
@@ -228,12 +232,7 @@ int build_plan(const sf_config_t* cfg, int B, const int32_t* n_robots, const int
   const int nc = cfg->n_coef, T = cfg->n_steps;
   const std::vector<double> W = bernstein(nc, T);
   p->W.resize((size_t)T * nc);
-  p->Wt.resize((size_t)T * nc);
-  for (int k = 0; k < T; ++k)
-    for (int c = 0; c < nc; ++c) {
-      p->W[(size_t)k * nc + c] = (float)W[(size_t)k * nc + c];
-      p->Wt[(size_t)c * T + k] = (float)W[(size_t)k * nc + c];
-    }
+  for (size_t q = 0; q < p->W.size(); ++q) p->W[q] = (float)W[q];
   std::map<std::pair<int, int>, int> fac_index;
   const int fs = sf::fac_stride(nc);
   int64_t coef = 0, rob = 0, obs = 0, pos = 0;
@@ -315,10 +314,15 @@ int build_plan(const sf_config_t* cfg, int B, const int32_t* n_robots, const int
   std::stable_sort(p->order.begin(), p->order.end(),
                    [&](int x, int y) { return cost[x] > cost[y]; });
   p->threads = cfg->threads ? cfg->threads : 512;
+  p->threads_bwd = p->threads;
+  p->tune_fwd = p->tune_bwd = (cfg->threads == 0);
+  // One time-chunk length for both kernels: the adjoint recomputes forward
+  // iterates and must sum in the same order to reproduce them bitwise.
   p->Tc_fwd = choose_tc(nc, T, p->n_max, p->M_max, p->S_max, p->threads, false);
   p->Tc_bwd = choose_tc(nc, T, p->n_max, p->M_max, p->S_max, p->threads, true);
   if (p->Tc_fwd == 0 || p->Tc_bwd == 0)
     return fail(SF_ERR_SHAPE, "problem state does not fit the LDS of one workgroup");
+  p->Tc_fwd = p->Tc_bwd = std::min(p->Tc_fwd, p->Tc_bwd);
   p->lds_fwd = sf::fwd_lds_bytes(nc, T, p->Tc_fwd, p->n_max, p->M_max, p->S_max, p->threads);
   p->lds_bwd = sf::bwd_lds_bytes(nc, T, p->Tc_bwd, p->n_max, p->M_max, p->S_max, p->threads);
   const int L = cfg->max_iters, k = cfg->checkpoint_every;
@@ -334,7 +338,6 @@ int build_plan(const sf_config_t* cfg, int B, const int32_t* n_robots, const int
   p->off_desc = take(sizeof(sf::ProbDesc) * B);
   p->off_order = take(sizeof(int32_t) * B);
   p->off_W = take(F * T * nc);
-  p->off_Wt = take(F * T * nc);
   p->off_fac = take(F * p->fac.size());
   p->off_cxi = take(F * coef);
   p->off_obs = take(F * 3 * obs);
@@ -349,6 +352,7 @@ int build_plan(const sf_config_t* cfg, int B, const int32_t* n_robots, const int
   p->off_lam = take(F * coef);
   p->off_pcxi = take(F * coef);
   p->off_red = take(F * 4 * B);
+  p->off_part = take(F * 4 * coef);
   p->total = off;
   out = std::move(p);
   return SF_OK;
@@ -361,7 +365,6 @@ sf::FwdArgs fwd_args(const sf_plan* p, const float* xi, const float* xi0, const 
   a.probs = p->at<sf::ProbDesc>(p->off_desc);
   a.order = p->at<int32_t>(p->off_order);
   a.W = p->at<float>(p->off_W);
-  a.Wt = p->at<float>(p->off_Wt);
   a.fac = p->at<float>(p->off_fac);
   a.xi = xi;
   a.xi0 = xi0;
@@ -388,6 +391,114 @@ sf::FwdArgs fwd_args(const sf_plan* p, const float* xi, const float* xi0, const 
   a.save = save ? 1 : 0;
   a.rho = (float)p->cfg.rho;
   return a;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: threads per workgroup of the fused kernels, chosen by timing the
+// candidates on the device at the first call of a plan and cached per size
+// bucket (gfx arch, n_coef, n_steps, robot/obstacle/batch buckets, kernel).
+// With SF_AUTOTUNE_CACHE=<file> the choices persist as JSON lines.
+// ---------------------------------------------------------------------------
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune;
+bool g_tune_loaded = false;
+
+int bucket_up(int v, const int* edges, int ne) {
+  for (int q = 0; q < ne; ++q)
+    if (v <= edges[q]) return edges[q];
+  return ((v + 63) / 64) * 64;
+}
+
+std::string tune_key(const sf_plan* p, bool bwd) {
+  static const int nb[] = {8, 16, 32, 48, 64};
+  static const int mb[] = {0, 15, 30, 60};
+  static const int bb[] = {16, 64, 128, 256};
+  int dev = 0;
+  char arch[64] = "unknown";
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    std::snprintf(arch, sizeof(arch), "%s", prop.gcnArchName);
+    for (char* c = arch; *c; ++c)
+      if (*c == ':' || *c == '"' || *c == ' ') *c = '_';
+  }
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "%s/%s/nc%d/T%d/n%d/M%d/B%d/k%d", bwd ? "bwd" : "fwd", arch,
+                p->cfg.n_coef, p->cfg.n_steps, bucket_up(p->n_max, nb, 5),
+                bucket_up(p->M_max, mb, 4), bucket_up(p->B, bb, 4),
+                bwd ? p->cfg.checkpoint_every : 0);
+  return buf;
+}
+
+void tune_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = std::getenv("SF_AUTOTUNE_CACHE");
+  if (!path || !*path) return;
+  std::ifstream in(path);
+  std::string line;
+  while (std::getline(in, line)) {
+    const size_t k0 = line.find("\"key\": \"");
+    const size_t t0 = line.find("\"threads\": ");
+    if (k0 == std::string::npos || t0 == std::string::npos) continue;
+    const size_t ks = k0 + 8, ke = line.find('"', ks);
+    if (ke == std::string::npos) continue;
+    const int t = std::atoi(line.c_str() + t0 + 11);
+    if (t == 256 || t == 512 || t == 1024) g_tune[line.substr(ks, ke - ks)] = t;
+  }
+}
+
+bool tune_lookup(const std::string& key, int& threads) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  tune_load_locked();
+  auto it = g_tune.find(key);
+  if (it == g_tune.end()) return false;
+  threads = it->second;
+  return true;
+}
+
+void tune_store(const std::string& key, int threads, const float* ms) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  tune_load_locked();
+  g_tune[key] = threads;
+  const char* path = std::getenv("SF_AUTOTUNE_CACHE");
+  if (!path || !*path) return;
+  std::ofstream out(path, std::ios::app);
+  out << "{\"key\": \"" << key << "\", \"threads\": " << threads << ", \"ms\": [" << ms[0]
+      << ", " << ms[1] << ", " << ms[2] << "]}\n";
+}
+
+// Time `launch(threads)` for each candidate (one warm-up, then the mean of two
+// timed launches) and return the fastest.  Synchronises the stream.
+template <typename F>
+int time_candidates(hipStream_t s, F launch, float* ms_out, hipError_t& err) {
+  static const int cand[3] = {256, 512, 1024};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  err = hipEventCreate(&e0);
+  if (err == hipSuccess) err = hipEventCreate(&e1);
+  int best = 512;
+  float best_ms = 1e30f;
+  for (int q = 0; q < 3 && err == hipSuccess; ++q) {
+    err = launch(cand[q]);
+    if (err == hipSuccess) err = hipEventRecord(e0, s);
+    for (int r = 0; r < 2 && err == hipSuccess; ++r) err = launch(cand[q]);
+    if (err == hipSuccess) err = hipEventRecord(e1, s);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    ms_out[q] = ms / 2.f;
+    if (err == hipSuccess && ms < best_ms) {
+      best_ms = ms;
+      best = cand[q];
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return best;
+}
+
+bool stream_capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(s, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
 }
 
 }  // namespace
@@ -426,8 +537,6 @@ int sf_setup(const sf_config_t* cfg, int32_t n_problems, const int32_t* n_robots
   SF_HIP_CHECK(hipMemcpyAsync(p->ws + p->off_order, p->order.data(), sizeof(int32_t) * p->B,
                               hipMemcpyHostToDevice, s));
   SF_HIP_CHECK(hipMemcpyAsync(p->ws + p->off_W, p->W.data(), sizeof(float) * p->W.size(),
-                              hipMemcpyHostToDevice, s));
-  SF_HIP_CHECK(hipMemcpyAsync(p->ws + p->off_Wt, p->Wt.data(), sizeof(float) * p->Wt.size(),
                               hipMemcpyHostToDevice, s));
   SF_HIP_CHECK(hipMemcpyAsync(p->ws + p->off_fac, p->fac.data(), sizeof(float) * p->fac.size(),
                               hipMemcpyHostToDevice, s));
@@ -473,11 +582,30 @@ int sf_project(sf_plan_t* plan, void* workspace, const float* xi, const float* x
     pb.lam = plan->at<float>(plan->off_lam);
     pb.cxi = plan->at<float>(plan->off_pcxi);
     pb.red = plan->at<float>(plan->off_red);
+    pb.part = plan->at<float>(plan->off_part);
     for (int b = 0; b < plan->B; ++b) SF_HIP_CHECK(sf::launch_plain_problem(a, pb, b, s));
     return SF_OK;
   }
   if ((flags & SF_GRAPH) && s == nullptr)
     return fail(SF_ERR_INVALID_ARG, "SF_GRAPH needs a non-default stream (capture)");
+  if (plan->tune_fwd && n_iters > 0 && !stream_capturing(s)) {
+    const std::string key = tune_key(plan, false);
+    int t = 0;
+    if (!tune_lookup(key, t)) {
+      sf::FwdArgs trial = a;
+      trial.L = std::min<int>(n_iters, 3);
+      trial.save = 0;
+      float ms[3] = {0.f, 0.f, 0.f};
+      hipError_t err = hipSuccess;
+      t = time_candidates(
+          s, [&](int th) { return sf::launch_fwd_fused(trial, th, plan->lds_fwd, s); }, ms,
+          err);
+      SF_HIP_CHECK(err);
+      tune_store(key, t, ms);
+    }
+    plan->threads = t;
+    plan->tune_fwd = false;
+  }
   if (flags & SF_GRAPH) {
     std::vector<uint64_t> key = {(uint64_t)xi,      (uint64_t)xi0,     (uint64_t)lam0,
                                  (uint64_t)boundary, (uint64_t)obstacles, (uint64_t)xi_out,
@@ -526,7 +654,6 @@ int sf_project_backward(sf_plan_t* plan, void* workspace, const float* g_xi_out,
   a.probs = plan->at<sf::ProbDesc>(plan->off_desc);
   a.order = plan->at<int32_t>(plan->off_order);
   a.W = plan->at<float>(plan->off_W);
-  a.Wt = plan->at<float>(plan->off_Wt);
   a.fac = plan->at<float>(plan->off_fac);
   a.cxi = plan->at<float>(plan->off_cxi);
   a.obs = plan->at<float>(plan->off_obs);
@@ -551,7 +678,24 @@ int sf_project_backward(sf_plan_t* plan, void* workspace, const float* g_xi_out,
   a.ckpt_every = plan->cfg.checkpoint_every;
   a.rho = (float)plan->cfg.rho;
   a.fp_weight = fp_weight;
-  SF_HIP_CHECK(sf::launch_bwd_fused(a, plan->threads, plan->lds_bwd, s));
+  if (plan->tune_bwd && a.L > 0 && !stream_capturing(s)) {
+    const std::string key = tune_key(plan, true);
+    int t = 0;
+    if (!tune_lookup(key, t)) {
+      sf::BwdArgs trial = a;
+      trial.L = std::min<int>(a.L, std::max(2, a.ckpt_every));
+      float ms[3] = {0.f, 0.f, 0.f};
+      hipError_t err = hipSuccess;
+      t = time_candidates(
+          s, [&](int th) { return sf::launch_bwd_fused(trial, th, plan->lds_bwd, s); }, ms,
+          err);
+      SF_HIP_CHECK(err);
+      tune_store(key, t, ms);
+    }
+    plan->threads_bwd = t;
+    plan->tune_bwd = false;
+  }
+  SF_HIP_CHECK(sf::launch_bwd_fused(a, plan->threads_bwd, plan->lds_bwd, s));
   return SF_OK;
 }
 

@@ -36,7 +36,6 @@ struct FwdArgs {
   const ProbDesc* probs;
   const int32_t* order;   // launch slot -> problem (longest first)
   const float* W;         // [T][nc]
-  const float* Wt;        // [nc][T]
   const float* fac;       // factor blocks
   const float* xi;
   const float* xi0;
@@ -66,7 +65,6 @@ struct BwdArgs {
   const ProbDesc* probs;
   const int32_t* order;
   const float* W;
-  const float* Wt;
   const float* fac;
   const float* cxi;       // saved constant term
   const float* obs;       // saved obstacles
@@ -107,6 +105,7 @@ struct PlainBufs {
   float* lam;    // coefficient layout
   float* cxi;    // coefficient layout
   float* red;    // [B][4] residual partials
+  float* part;   // per-problem K-split partial sums, 4 x coefficient layout
 };
 hipError_t launch_plain_problem(const FwdArgs& a, const PlainBufs& pb, int b,
                                 hipStream_t s);

@@ -27,10 +27,12 @@
 // than a (plus a rounding margin) at every step of the window, so it is
 // inactive and contributes exactly 0: the result equals the full loop's.
 //
+// The coefficient<->time maps are dense contractions and run on MFMA (16x16x4
+// FP32 tiles); the constraint stages are VALU work over LDS.
+//
 // Data layout: coefficient arrays [axis][robot][coef]; positions and
-// constraint sums [robot][time] as float2 (x, y) with the time stride padded
-// to 16; W both [T][nc] and transposed [nc][T] so that lanes over consecutive
-// time steps or coefficients read consecutive LDS words.
+// constraint sums [robot][time] as float2 (x, y) with an odd row stride
+// (window multiple + 1) to spread robots over LDS banks; W as [T][nc].
 #include <hip/hip_runtime.h>
 
 #include "sf_internal.h"
@@ -48,11 +50,55 @@ typedef unsigned long long u64;
 __device__ __forceinline__ int round4(int x) { return (x + 3) & ~3; }
 __device__ __forceinline__ int round16(int x) { return (x + 15) & ~15; }
 
+// Row stride (in steps) of the position/sum buffers: a window multiple plus
+// one, so that the 2*stride-float rows of different robots start in different
+// LDS banks.
+__host__ __device__ __forceinline__ int tstride(int Tc) { return ((Tc + 15) & ~15) + 1; }
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// D += A B for a 16x4 by 4x16 FP32 tile: lane l supplies A[l%16][l/16] and
+// B[l/16][l%16] and holds D[4(l/16)+v][l%16] in element v.
+__device__ __forceinline__ floatx4 mfma_16x16x4(float a, float b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
+
+// DPP move of v (rows outside row_mask keep `old`); all lanes must be active.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_f(float old, float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL,
+                                                    ROW_MASK, 0xF, false));
+}
+
+// Wave sum through DPP in a fixed order: pairs, quads, half rows, rows, then
+// row broadcasts; the total lands in lane 63 and is returned to all lanes.
+__device__ __forceinline__ float wave_sum_dpp(float v) {
+  v += dpp_f<0xB1, 0xF>(0.f, v);    // quad_perm [1,0,3,2]
+  v += dpp_f<0x4E, 0xF>(0.f, v);    // quad_perm [2,3,0,1]
+  v += dpp_f<0x141, 0xF>(0.f, v);   // row_half_mirror
+  v += dpp_f<0x140, 0xF>(0.f, v);   // row_mirror
+  v += dpp_f<0x142, 0xA>(0.f, v);   // row_bcast:15 -> rows 1, 3
+  v += dpp_f<0x143, 0xC>(0.f, v);   // row_bcast:31 -> rows 2, 3
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+// OR over each quad of lanes (DPP quad permutations); all lanes active.
+__device__ __forceinline__ unsigned quad_or(unsigned v) {
+  v |= (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true);
+  v |= (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true);
+  return v;
+}
+
+// floor(x / d) for 0 <= x < 2^16 and 16 <= d <= 4096 through a multiply-high
+// by m = floor((2^32 - 1)/d) + 1 (exact in that range).
+__device__ __forceinline__ unsigned div_magic(unsigned d) { return 0xFFFFFFFFu / d + 1u; }
+__device__ __forceinline__ int fast_div(int x, unsigned m) { return (int)__umulhi((unsigned)x, m); }
 
 // Deterministic block sum of up to 4 values: wave shuffles, then a fixed-order
 // pass over the per-wave partials.  All threads get the totals.
@@ -86,28 +132,6 @@ __device__ __forceinline__ u64 readlane64(u64 v, int lane) {
 // ---------------------------------------------------------------------------
 // Stages used by the plain (unfused, global-memory) path.
 // ---------------------------------------------------------------------------
-
-// X[i][kk] = sum_c W[k0+kk][c] xi_bar[axis][i][c]   (coefficient -> time map)
-__device__ __forceinline__ void stage_xmap(const float* __restrict__ Wt, int T, int k0,
-                                           const float* __restrict__ xb, int n, int nc,
-                                           float2* __restrict__ X, int Tce, int Tcs,
-                                           int tid, int nthr) {
-  const int items = n * Tce;
-  for (int idx = tid; idx < items; idx += nthr) {
-    const int i = idx / Tce;
-    const int kk = idx - i * Tce;
-    const int k = k0 + kk;
-    const float* xr = xb + i * nc;
-    const float* yr = xb + n * nc + i * nc;
-    float x = 0.f, y = 0.f;
-    for (int c = 0; c < nc; ++c) {
-      const float w = Wt[c * T + k];
-      x = fmaf(w, xr[c], x);
-      y = fmaf(w, yr[c], y);
-    }
-    X[i * Tcs + kk] = make_float2(x, y);
-  }
-}
 
 // Pair/obstacle/box residual sums for one (robot, step): every other robot
 // and every obstacle is visited.
@@ -171,24 +195,6 @@ __device__ __forceinline__ void stage_constraints(
   }
 }
 
-// R[axis][i][c] (+)= sum_kk W[k0+kk][c] V[i][kk].axis   (time -> coefficient map)
-__device__ __forceinline__ void stage_wtmap(const float* __restrict__ W, int nc, int k0,
-                                            const float2* __restrict__ V, int n, int Tce,
-                                            int Tcs, float* __restrict__ R, bool accumulate,
-                                            int tid, int nthr) {
-  const int S = 2 * n * nc;
-  for (int s = tid; s < S; s += nthr) {
-    const int ax = s / (n * nc);
-    const int rem = s - ax * n * nc;
-    const int i = rem / nc;
-    const int c = rem - i * nc;
-    float acc = accumulate ? R[s] : 0.f;
-    const float* vrow = reinterpret_cast<const float*>(V + i * Tcs) + ax;
-    for (int kk = 0; kk < Tce; ++kk) acc = fmaf(W[(k0 + kk) * nc + c], vrow[2 * kk], acc);
-    R[s] = acc;
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Coefficient-space helpers shared by both paths.
 // ---------------------------------------------------------------------------
@@ -232,7 +238,7 @@ __device__ __forceinline__ void robot_means(const float* __restrict__ src0,
     const float* base = src + ax * n * nc + c;
     float s = 0.f;
     for (int i = lane; i < n; i += 64) s += base[i * nc];
-    s = wave_sum(s);
+    s = wave_sum_dpp(s);
     if (lane == 0) out[col] = s * inv;
   }
 }
@@ -271,22 +277,226 @@ __device__ __forceinline__ void boundary_means(const float* __restrict__ bnd, in
 }
 
 // ---------------------------------------------------------------------------
+// The two dense contractions on MFMA (16x16x4 FP32 tiles), one tile per wave.
+// Columns are (robot, axis) pairs col = 2 i + axis, padded to a multiple of 16.
+// Positions/sums are float views of [robot][step] float2 arrays with row
+// stride Ts steps.
+// ---------------------------------------------------------------------------
+
+// Coefficient -> time map X[i][kk].axis = sum_c W[kk][c] xb[axis][i][c] for kk <
+// Tce (rows = steps, 16 per tile = one culling window; K = coefficients padded
+// to 4).  Padding rows repeat the chunk's last step.  With `box`, each robot's
+// per-window bounding box (xmin, xmax, ymin, ymax) is reduced from the tile.
+__device__ __forceinline__ void stage_xmap_mfma(const float* __restrict__ W, int nc,
+                                                const float* __restrict__ xb, int n,
+                                                float* __restrict__ Xf, int Tce, int Ts,
+                                                float* __restrict__ boxf, int nws, int wave,
+                                                int nwaves, int lane) {
+  const int nwin = (Tce + 15) >> 4;
+  const int ncol = (2 * n + 15) >> 4;
+  const int ks = (nc + 3) >> 2;
+  const int m = lane & 15, kq = lane >> 4;
+  for (int tile = wave; tile < nwin * ncol; tile += nwaves) {
+    const int mt = tile / ncol, nt = tile - mt * ncol;
+    const int row = min(mt * 16 + m, Tce - 1);
+    const int col = nt * 16 + m;
+    const int i = col >> 1, ax = col & 1;
+    const bool colok = i < n;
+    const float* wrow = W + row * nc;
+    const float* brow = xb + ax * n * nc + i * nc;
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int s = 0; s < ks; ++s) {
+      const int c = 4 * s + kq;
+      const float a = c < nc ? wrow[c] : 0.f;
+      const float b = (c < nc && colok) ? brow[c] : 0.f;
+      acc = mfma_16x16x4(a, b, acc);
+    }
+    const int k0 = mt * 16 + 4 * kq;
+    if (colok) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (k0 + v < Tce) Xf[((size_t)i * Ts + k0 + v) * 2 + ax] = acc[v];
+    }
+    if (boxf) {
+      float lo = fminf(fminf(acc[0], acc[1]), fminf(acc[2], acc[3]));
+      float hi = fmaxf(fmaxf(acc[0], acc[1]), fmaxf(acc[2], acc[3]));
+      lo = fminf(lo, __shfl_xor(lo, 16, 64));
+      hi = fmaxf(hi, __shfl_xor(hi, 16, 64));
+      lo = fminf(lo, __shfl_xor(lo, 32, 64));
+      hi = fmaxf(hi, __shfl_xor(hi, 32, 64));
+      if (lane < 16 && colok) {
+        float* bx = boxf + ((size_t)i * nws + mt) * 4 + 2 * ax;
+        bx[0] = lo;
+        bx[1] = hi;
+      }
+    }
+  }
+}
+
+// Time -> coefficient map R[axis][i][c] (+)= sum_kk W[kk][c] V[i][kk].axis over
+// kk < Tce (rows = coefficients, K = steps padded to 16).  With `lam`, the
+// lambda step runs on the finished R: lambda' = lambda - rho R and R becomes
+// u = lambda - 2 rho R.
+__device__ __forceinline__ void stage_wtmap_mfma(const float* __restrict__ W, int nc,
+                                                 const float* __restrict__ Vf, int n, int Tce,
+                                                 int Ts, float* __restrict__ R, bool accumulate,
+                                                 float* __restrict__ lam, float rho,
+                                                 bool want_dz, float& dzsq, int wave, int nwaves,
+                                                 int lane) {
+  const int nct = (nc + 15) >> 4;
+  const int ncol = (2 * n + 15) >> 4;
+  const int ks = ((Tce + 15) >> 4) * 4;
+  const int m = lane & 15, kq = lane >> 4;
+  for (int tile = wave; tile < nct * ncol; tile += nwaves) {
+    const int ct = tile / ncol, nt = tile - ct * ncol;
+    const int ca = ct * 16 + m;
+    const int col = nt * 16 + m;
+    const int i = col >> 1, ax = col & 1;
+    const bool colok = i < n;
+    const float* vrow = Vf + (size_t)(colok ? i : 0) * Ts * 2 + ax;
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int st = 0; st < ks; st += 4) {
+      float av[4], bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int kk = 4 * (st + u) + kq;
+        const bool kok = kk < Tce;
+        av[u] = (kok && ca < nc) ? W[kk * nc + ca] : 0.f;
+        bv[u] = (kok && colok) ? vrow[2 * kk] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = mfma_16x16x4(av[u], bv[u], acc);
+    }
+    if (colok) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int c = ct * 16 + 4 * kq + v;
+        if (c >= nc) continue;
+        const int sidx = ax * n * nc + i * nc + c;
+        const float r = accumulate ? R[sidx] + acc[v] : acc[v];
+        if (lam) {
+          const float lm = lam[sidx];
+          lam[sidx] = fmaf(-rho, r, lm);
+          R[sidx] = fmaf(-2.f * rho, r, lm);
+          if (want_dz) dzsq = fmaf(rho * r, rho * r, dzsq);
+        } else {
+          R[sidx] = r;
+        }
+      }
+    }
+  }
+}
+
+// Number of K splits of the time->coefficient map for a problem: enough
+// (tile, split) work items for 16 waves, at most kSplitMax; depends only on
+// the problem's shape, so every launch configuration sums in the same order.
+constexpr int kSplitMax = 4;
+__host__ __device__ __forceinline__ int wt_splits(int n, int nc) {
+  const int tiles = ((nc + 15) >> 4) * ((2 * n + 15) >> 4);
+  const int ks = 16 / tiles;
+  return ks < 1 ? 1 : (ks > kSplitMax ? kSplitMax : ks);
+}
+
+// K-split time->coefficient map: split sp of tile t adds sum over its share of
+// the steps of W[kk][c] V[i][kk].axis into part[sp*S + s] (or stores it).
+// Loads of four K steps are issued ahead of their MFMAs; zero-padded steps
+// add exact zeros.
+__device__ __forceinline__ void stage_wtmap_part(const float* __restrict__ W, int nc,
+                                                 const float* __restrict__ Vf, int n, int Tce,
+                                                 int Ts, float* __restrict__ part, int S,
+                                                 bool accumulate, int wave, int nwaves,
+                                                 int lane) {
+  const int nct = (nc + 15) >> 4;
+  const int ncol = (2 * n + 15) >> 4;
+  const int tiles = nct * ncol;
+  const int KS = wt_splits(n, nc);
+  const int ks = ((Tce + 15) >> 4) * 4;
+  const int kps = (((ks + KS - 1) / KS) + 3) & ~3;
+  const int m = lane & 15, kq = lane >> 4;
+  for (int wi = wave; wi < tiles * KS; wi += nwaves) {
+    const int sp = wi / tiles, tile = wi - sp * tiles;
+    const int ct = tile / ncol, nt = tile - ct * ncol;
+    const int ca = ct * 16 + m;
+    const int col = nt * 16 + m;
+    const int i = col >> 1, ax = col & 1;
+    const bool colok = i < n;
+    const float* vrow = Vf + (size_t)(colok ? i : 0) * Ts * 2 + ax;
+    const int s0 = sp * kps, s1 = min(ks, s0 + kps);
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int st = s0; st < s1; st += 4) {
+      float av[4], bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int kk = 4 * (st + u) + kq;
+        const bool kok = (st + u < s1) && kk < Tce;
+        av[u] = (kok && ca < nc) ? W[kk * nc + ca] : 0.f;
+        bv[u] = (kok && colok) ? vrow[2 * kk] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = mfma_16x16x4(av[u], bv[u], acc);
+    }
+    if (colok) {
+      float* dst = part + (size_t)sp * S;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int c = ct * 16 + 4 * kq + v;
+        if (c >= nc) continue;
+        const int sidx = ax * n * nc + i * nc + c;
+        dst[sidx] = accumulate ? dst[sidx] + acc[v] : acc[v];
+      }
+    }
+  }
+}
+
+// R = the K-split partials summed in split order; lambda step lambda' =
+// lambda - rho R; u = lambda - 2 rho R into Ru; robot means of u
+// (means[axis*nc + c]) and of xb (means[2nc + axis*nc + c]).  One wave per
+// column, lanes over robots.
+__device__ __forceinline__ void combine_lambda_means(const float* __restrict__ part, int S,
+                                                     float* __restrict__ lam,
+                                                     float* __restrict__ Ru,
+                                                     const float* __restrict__ xb, int n, int nc,
+                                                     float rho, bool want_dz, float& dzsq,
+                                                     float* __restrict__ means, int tid,
+                                                     int nthr) {
+  const int lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
+  const int KS = wt_splits(n, nc);
+  const float inv = 1.f / (float)n;
+  for (int col = wave; col < 4 * nc; col += nwaves) {
+    const bool ucol = col < 2 * nc;
+    const int cc = ucol ? col : col - 2 * nc;
+    const int ax = cc / nc, c = cc - ax * nc;
+    float acc = 0.f;
+    for (int i = lane; i < n; i += 64) {
+      const int sidx = ax * n * nc + i * nc + c;
+      if (ucol) {
+        float r = part[sidx];
+        for (int k = 1; k < KS; ++k) r += part[(size_t)k * S + sidx];
+        const float lm = lam[sidx];
+        lam[sidx] = fmaf(-rho, r, lm);
+        const float u = fmaf(-2.f * rho, r, lm);
+        Ru[sidx] = u;
+        acc += u;
+        if (want_dz) dzsq = fmaf(rho * r, rho * r, dzsq);
+      } else {
+        acc += xb[sidx];
+      }
+    }
+    acc = wave_sum_dpp(acc);
+    if (lane == 0) means[col] = acc * inv;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Stages of the fused kernels (LDS-resident state, culled constraints).
 // Loops over (robot, step) items advance a whole wave at a time so that a
 // 16-lane row always holds one (robot, window) and shuffles see whole rows.
 // ---------------------------------------------------------------------------
 
-// Copy rows k0 .. k0+Tce-1 of W (global, [T][nc]) into the LDS tables
-// W[kk][c] and Wt[c][kk] (row stride Tc).
+// Copy rows k0 .. k0+Tce-1 of W (global, [T][nc]) into the LDS table W.
 __device__ __forceinline__ void load_wchunk(const float* __restrict__ Wg, float* __restrict__ W,
-                                            float* __restrict__ Wt, int nc, int Tc, int k0,
-                                            int Tce, int tid, int nthr) {
-  for (int t = tid; t < Tce * nc; t += nthr) {
-    const int kk = t / nc, c = t - kk * nc;
-    const float v = Wg[(k0 + kk) * nc + c];
-    W[kk * nc + c] = v;
-    Wt[c * Tc + kk] = v;
-  }
+                                            int nc, int k0, int Tce, int tid, int nthr) {
+  for (int t = tid; t < Tce * nc; t += nthr) W[t] = Wg[k0 * nc + t];
 }
 
 // Culling geometry of one chunk: padded step count, window count and strides.
@@ -299,81 +509,58 @@ struct Geo {
   int ow;    // 64-bit mask words for obstacles
 };
 
-// X map for a chunk plus each robot's bounding box per window:
-// box[i*nws + w] = (xmin, xmax, ymin, ymax) over the window's steps.
-__device__ __forceinline__ void stage_xmap_box(const float* __restrict__ Wt, int Tc,
-                                               const float* __restrict__ xb, int n, int nc,
-                                               float2* __restrict__ X, float4* __restrict__ box,
-                                               const Geo& g, int tid, int nthr) {
-  const int items = n * g.Tcp;
-  for (int base = tid & ~63; base < items; base += nthr) {
-    const int idx = base + (tid & 63);
-    const bool live = idx < items;
-    const int i = live ? idx / g.Tcp : 0;
-    const int kk = live ? idx - i * g.Tcp : 0;
-    const int kq = min(kk, g.Tce - 1);     // padding lanes repeat the last step
-    const float* xr = xb + i * nc;
-    const float* yr = xb + n * nc + i * nc;
-    float x = 0.f, y = 0.f;
-    for (int c = 0; c < nc; ++c) {
-      const float w = Wt[c * Tc + kq];
-      x = fmaf(w, xr[c], x);
-      y = fmaf(w, yr[c], y);
-    }
-    if (live && kk < g.Tce) X[i * g.Tcs + kk] = make_float2(x, y);
-    float x0 = x, x1 = x, y0 = y, y1 = y;
-#pragma unroll
-    for (int off = kWin / 2; off > 0; off >>= 1) {
-      x0 = fminf(x0, __shfl_xor(x0, off, 64));
-      x1 = fmaxf(x1, __shfl_xor(x1, off, 64));
-      y0 = fminf(y0, __shfl_xor(y0, off, 64));
-      y1 = fmaxf(y1, __shfl_xor(y1, off, 64));
-    }
-    if (live && (kk & (kWin - 1)) == 0) box[i * g.nws + (kk >> 4)] = make_float4(x0, x1, y0, y1);
-  }
-}
-
-// Candidate masks per (robot, window): bit j of word q set when robot 64q+j's
-// box comes within a (plus margin) of robot i's box in both axes; bit m of the
-// obstacle words when obstacle m's disc (plus margin) meets robot i's box.
-// The margin covers rounding of the box comparison and of the exact test.
+// Candidate masks per (robot, window): bit j of word q set when robot 64q+j
+// (j != i) has a box within a (plus margin) of robot i's box in both axes;
+// bit m of the obstacle words when obstacle m's disc (plus margin) meets robot
+// i's box.  Four lanes (a DPP quad) share a (robot, window) and split the
+// candidates.  The margin covers rounding of the box comparison and of the
+// exact test at coordinates of magnitude up to the box's plus the threshold.
 __device__ __forceinline__ void stage_masks(const float4* __restrict__ box, int n,
                                             const float4* __restrict__ obs, int M, float a,
                                             u64* __restrict__ masks, const Geo& g, int tid,
                                             int nthr) {
-  const int lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
-  const int nwin = g.Tcp / kWin;
+  const int lane = tid & 63;
+  const int nwin = g.Tcp >> 4;
+  const int tasks = n * nwin;
   const int mw = g.pw + g.ow;
-  for (int task = wave; task < n * nwin; task += nwaves) {
+  for (int base = tid & ~63; base < tasks * 4; base += nthr) {
+    const int idx = base + lane;
+    const bool live = idx < tasks * 4;
+    const int task = live ? idx >> 2 : 0;
+    const int q = idx & 3;
     const int i = task / nwin, w = task - i * nwin;
     const float4 bi = box[i * g.nws + w];
     const float si = fmaxf(fmaxf(fabsf(bi.x), fabsf(bi.y)), fmaxf(fabsf(bi.z), fabsf(bi.w)));
+    const float am = a * 1.0001f + 4e-6f * (1.f + si + 2.f * a);
     u64* out = masks + (size_t)(i * g.nws + w) * mw;
-    for (int q = 0; q < g.pw; ++q) {
-      const int j = q * 64 + lane;
-      bool c = false;
-      if (j < n) {
+    for (int wd = 0; wd < g.pw; ++wd) {
+      unsigned lo = 0u, hi = 0u;
+      const int jend = min(n - wd * 64, 64);
+      for (int jj = q; jj < jend; jj += 4) {
+        const int j = wd * 64 + jj;
         const float4 bj = box[j * g.nws + w];
-        const float sj =
-            fmaxf(fmaxf(fabsf(bj.x), fabsf(bj.y)), fmaxf(fabsf(bj.z), fabsf(bj.w)));
-        const float am = a * 1.0001f + 4e-6f * (1.f + fmaxf(si, sj));
-        c = (bi.x < bj.y + am) && (bj.x < bi.y + am) && (bi.z < bj.w + am) &&
-            (bj.z < bi.w + am);
+        const bool c = (j != i) && (bi.x < bj.y + am) && (bj.x < bi.y + am) &&
+                       (bi.z < bj.w + am) && (bj.z < bi.w + am);
+        const unsigned bit = c ? (1u << (jj & 31)) : 0u;
+        if (jj < 32) lo |= bit; else hi |= bit;
       }
-      const u64 m = __ballot(c);
-      if (lane == 0) out[q] = m;
+      lo = quad_or(lo);
+      hi = quad_or(hi);
+      if (live && q == 0) out[wd] = ((u64)hi << 32) | lo;
     }
-    for (int q = 0; q < g.ow; ++q) {
-      const int mm = q * 64 + lane;
-      bool c = false;
-      if (mm < M) {
-        const float4 o = obs[mm];
-        const float so = fmaxf(fabsf(o.x), fabsf(o.y));
-        const float r = o.z * 1.0001f + 4e-6f * (1.f + fmaxf(si, so));
-        c = (o.x - r < bi.y) && (bi.x < o.x + r) && (o.y - r < bi.w) && (bi.z < o.y + r);
+    for (int wd = 0; wd < g.ow; ++wd) {
+      unsigned lo = 0u, hi = 0u;
+      const int mend = min(M - wd * 64, 64);
+      for (int mm = q; mm < mend; mm += 4) {
+        const float4 o = obs[wd * 64 + mm];
+        const float r = o.z * 1.0001f + 4e-6f * (1.f + si + 2.f * o.z);
+        const bool c = (o.x - r < bi.y) && (bi.x < o.x + r) && (o.y - r < bi.w) && (bi.z < o.y + r);
+        const unsigned bit = c ? (1u << (mm & 31)) : 0u;
+        if (mm < 32) lo |= bit; else hi |= bit;
       }
-      const u64 m = __ballot(c);
-      if (lane == 0) out[g.pw + q] = m;
+      lo = quad_or(lo);
+      hi = quad_or(hi);
+      if (live && q == 0) out[g.pw + wd] = ((u64)hi << 32) | lo;
     }
   }
 }
@@ -395,10 +582,11 @@ __device__ __forceinline__ void stage_constraints_culled(
   const float a2 = a * a;
   const int items = n * g.Tcp;
   const int mw = g.pw + g.ow;
+  const unsigned dm = div_magic((unsigned)g.Tcp);
   for (int base = tid & ~63; base < items; base += nthr) {
     const int idx = base + (tid & 63);
     const bool live = idx < items;
-    const int i = live ? idx / g.Tcp : 0;
+    const int i = live ? fast_div(idx, dm) : 0;
     const int kk = live ? idx - i * g.Tcp : 0;
     const bool valid = live && kk < g.Tce;
     const int kq = min(kk, g.Tce - 1);
@@ -483,10 +671,11 @@ __device__ __forceinline__ void stage_vjp_culled(
   const float a2 = a * a;
   const int items = n * g.Tcp;
   const int mw = g.pw + g.ow;
+  const unsigned dm = div_magic((unsigned)g.Tcp);
   for (int base = tid & ~63; base < items; base += nthr) {
     const int idx = base + (tid & 63);
     const bool live = idx < items;
-    const int i = live ? idx / g.Tcp : 0;
+    const int i = live ? fast_div(idx, dm) : 0;
     const int kk = live ? idx - i * g.Tcp : 0;
     const int kq = min(kk, g.Tce - 1);
     const u64* my = masks + (size_t)(i * g.nws + (kk >> 4)) * mw;
@@ -549,40 +738,11 @@ __device__ __forceinline__ void stage_vjp_culled(
   }
 }
 
-// R[s] (+)= sum_kk W[kk][c] V[i][kk].axis over a chunk (LDS tables).  On the
-// last chunk with `lam` given, the lambda step runs on the finished R:
-// lambda' = lambda - rho R and R is replaced by u = lambda - 2 rho R.
-__device__ __forceinline__ void stage_wtmap_fused(const float* __restrict__ W, int nc,
-                                                  const float2* __restrict__ V, int n,
-                                                  const Geo& g, float* __restrict__ R,
-                                                  bool accumulate, float* __restrict__ lam,
-                                                  float rho, bool want_dz, float& dzsq, int tid,
-                                                  int nthr) {
-  const int S = 2 * n * nc;
-  for (int s = tid; s < S; s += nthr) {
-    const int ax = s / (n * nc);
-    const int rem = s - ax * n * nc;
-    const int i = rem / nc;
-    const int c = rem - i * nc;
-    float acc = accumulate ? R[s] : 0.f;
-    const float* vrow = reinterpret_cast<const float*>(V + i * g.Tcs) + ax;
-    for (int kk = 0; kk < g.Tce; ++kk) acc = fmaf(W[kk * nc + c], vrow[2 * kk], acc);
-    if (lam) {
-      const float lm = lam[s];
-      lam[s] = fmaf(-rho, acc, lm);
-      R[s] = fmaf(-2.f * rho, acc, lm);
-      if (want_dz) dzsq = fmaf(rho * acc, rho * acc, dzsq);
-    } else {
-      R[s] = acc;
-    }
-  }
-}
-
 // Per-problem constants of the fused kernels, with LDS-resident tables.
 struct Ctx {
   int n, M, nc, T, Tc, S, tid;
   float rho, a, pmin0, pmin1, pmax0, pmax1;
-  float *Wt, *W;
+  float* W;
   const float *fac, *Wg;
   const float4* obs;
   float4* box;
@@ -594,7 +754,7 @@ struct Ctx {
     Geo g;
     g.Tce = min(Tc, T - k0);
     g.Tcp = round16(g.Tce);
-    g.Tcs = round16(Tc);
+    g.Tcs = tstride(Tc);
     g.nws = g.Tcs / kWin;
     g.pw = (n + 63) >> 6;
     g.ow = (M + 63) >> 6;
@@ -607,14 +767,15 @@ struct Ctx {
   __device__ __forceinline__ void wchunk(int k0, int Tce) const {
     if (!chunked) return;
     __syncthreads();
-    load_wchunk(Wg, W, Wt, nc, Tc, k0, Tce, tid, NT);
+    load_wchunk(Wg, W, nc, k0, Tce, tid, NT);
     __syncthreads();
   }
 
   // X map, boxes and masks of one chunk into X (block-synchronised on return).
   template <int NT>
   __device__ __forceinline__ void positions(const float* xb, float2* X, const Geo& g) const {
-    stage_xmap_box(Wt, Tc, xb, n, nc, X, box, g, tid, NT);
+    stage_xmap_mfma(W, nc, xb, n, reinterpret_cast<float*>(X), g.Tce, g.Tcs,
+                    reinterpret_cast<float*>(box), g.nws, tid >> 6, NT >> 6, tid & 63);
     __syncthreads();
     stage_masks(box, n, obs, M, a, masks, g, tid, NT);
     __syncthreads();
@@ -633,9 +794,9 @@ __host__ __device__ inline int mask_floats(int Tc, int n_max, int M_max) {
 // One application of T on the LDS state (xb, lam) -> (xn, lam).  Ru, X, V and
 // means are scratch.  Entered and left with the block synchronised.
 template <int NT>
-__device__ void sf_iteration(const Ctx& C, const float* xb, float* xn, float* lam, float* Ru,
+__device__ __forceinline__ void sf_iteration(const Ctx& C, const float* xb, float* xn, float* lam, float* Ru,
                              float* means, float2* X, float2* V, const float* cx, bool last,
-                             float& dzsq) {
+                             float& dzsq, float* part) {
   const int n = C.n, nc = C.nc, T = C.T, S = C.S, tid = C.tid;
   float d1 = 0.f, d2 = 0.f;
   for (int k0 = 0; k0 < T; k0 += C.Tc) {
@@ -645,12 +806,11 @@ __device__ void sf_iteration(const Ctx& C, const float* xb, float* xn, float* la
     stage_constraints_culled(X, V, n, C.obs, C.masks, C.a, C.pmin0, C.pmin1, C.pmax0, C.pmax1,
                              false, d1, d2, g, tid, NT);
     __syncthreads();
-    const bool fin = k0 + C.Tc >= T;
-    stage_wtmap_fused(C.W, nc, V, n, g, Ru, k0 > 0, fin ? lam : nullptr, C.rho, last, dzsq,
-                      tid, NT);
+    stage_wtmap_part(C.W, nc, reinterpret_cast<const float*>(V), n, g.Tce, g.Tcs, part, S,
+                     k0 > 0, tid >> 6, NT >> 6, tid & 63);
   }
   __syncthreads();
-  robot_means(Ru, xb, n, nc, means, tid, NT);
+  combine_lambda_means(part, S, lam, Ru, xb, n, nc, C.rho, last, dzsq, means, tid, NT);
   __syncthreads();
   const int nc2 = nc * nc;
   for (int s = tid; s < S; s += NT) {
@@ -671,7 +831,7 @@ __device__ void sf_iteration(const Ctx& C, const float* xb, float* xn, float* la
 // ||r_1||^2 and ||r_2||^2 partials of the iterate xb (block-synchronised on
 // return); V is scratch.
 template <int NT>
-__device__ void residual_norms(const Ctx& C, const float* xb, float2* X, float2* V, float& r1sq,
+__device__ __forceinline__ void residual_norms(const Ctx& C, const float* xb, float2* X, float2* V, float& r1sq,
                                float& r2sq) {
   for (int k0 = 0; k0 < C.T; k0 += C.Tc) {
     const Geo g = C.geo(k0);
@@ -684,7 +844,7 @@ __device__ void residual_norms(const Ctx& C, const float* xb, float2* X, float2*
 }
 
 struct FwdLds {
-  float *Wt, *W, *fac, *xbA, *xbB, *lam, *cx, *Ru, *means, *red;
+  float *W, *fac, *xbA, *xbB, *lam, *cx, *Ru, *means, *red, *part;
   float4* obs;
   float4* box;
   u64* masks;
@@ -695,7 +855,6 @@ __device__ __forceinline__ FwdLds carve_fwd(float* sm, int nc, int Tc, int n_max
                                             int S_max) {
   FwdLds L;
   float* p = sm;
-  L.Wt = p; p += round4(nc * Tc);
   L.W = p; p += round4(nc * Tc);
   L.fac = p; p += round4(fac_stride(nc));
   L.xbA = p; p += round4(S_max);
@@ -703,12 +862,13 @@ __device__ __forceinline__ FwdLds carve_fwd(float* sm, int nc, int Tc, int n_max
   L.lam = p; p += round4(S_max);
   L.cx = p; p += round4(S_max);
   L.Ru = p; p += round4(S_max);
+  L.part = p; p += kSplitMax * round4(S_max);
   L.means = p; p += kMeans;
   L.red = p; p += kRed;
   L.obs = reinterpret_cast<float4*>(p); p += 4 * M_max;
   L.box = reinterpret_cast<float4*>(p); p += box_floats(Tc, n_max);
   L.masks = reinterpret_cast<u64*>(p); p += mask_floats(Tc, n_max, M_max);
-  L.X = reinterpret_cast<float2*>(p); p += 2 * n_max * round16(Tc);
+  L.X = reinterpret_cast<float2*>(p); p += 2 * n_max * tstride(Tc);
   L.V = reinterpret_cast<float2*>(p);
   return L;
 }
@@ -717,8 +877,8 @@ __device__ __forceinline__ FwdLds carve_fwd(float* sm, int nc, int Tc, int n_max
 
 size_t fwd_lds_bytes(int nc, int T, int Tc, int n_max, int M_max, int S_max, int) {
   auto r4 = [](int x) { return (size_t)((x + 3) & ~3); };
-  const size_t Tcs = (Tc + 15) & ~15;
-  size_t f = 2 * r4(nc * Tc) + r4(fac_stride(nc)) + 5 * r4(S_max) + kMeans + kRed +
+  const size_t Tcs = tstride(Tc);
+  size_t f = r4(nc * Tc) + r4(fac_stride(nc)) + (5 + kSplitMax) * r4(S_max) + kMeans + kRed +
              4 * (size_t)M_max + box_floats(Tc, n_max) + mask_floats(Tc, n_max, M_max) +
              4 * (size_t)n_max * Tcs;
   return f * sizeof(float);
@@ -740,9 +900,9 @@ __global__ __launch_bounds__(NT) void fwd_fused_kernel(FwdArgs A) {
   const int fs = fac_stride(nc);
   FwdLds L = carve_fwd(sm, nc, A.Tc, A.n_max, A.M_max, A.S_max);
   Ctx C{n,         M,         nc,        T,         A.Tc, S,   tid,   A.rho, P.a,
-        P.pmin[0], P.pmin[1], P.pmax[0], P.pmax[1], L.Wt, L.W, L.fac, A.W,   L.obs,
+        P.pmin[0], P.pmin[1], P.pmax[0], P.pmax[1], L.W, L.fac, A.W,   L.obs,
         L.box,     L.masks,   A.n_max,   A.M_max,   A.Tc < T};
-  if (!C.chunked) load_wchunk(A.W, L.W, L.Wt, nc, A.Tc, 0, T, tid, NT);
+  if (!C.chunked) load_wchunk(A.W, L.W, nc, 0, T, tid, NT);
   for (int t = tid; t < fs; t += NT) L.fac[t] = A.fac[(size_t)P.fac * fs + t];
   for (int m = tid; m < M; m += NT) {
     const float* o = A.obstacles + ((size_t)P.obs_off + m) * 3;
@@ -784,7 +944,8 @@ __global__ __launch_bounds__(NT) void fwd_fused_kernel(FwdArgs A) {
         ck[A.S_total + s] = L.lam[s];
       }
     }
-    sf_iteration<NT>(C, xb, xn, L.lam, L.Ru, L.means, L.X, L.V, L.cx, l == A.L - 1, dzsq);
+    sf_iteration<NT>(C, xb, xn, L.lam, L.Ru, L.means, L.X, L.V, L.cx, l == A.L - 1, dzsq,
+                     L.part);
     float* t = xb;
     xb = xn;
     xn = t;
@@ -844,7 +1005,7 @@ hipError_t launch_fwd_fused(const FwdArgs& a, int threads, size_t lds, hipStream
 namespace {
 
 struct BwdLds {
-  float *Wt, *W, *fac, *red, *means, *gA, *gB, *glam, *gxi, *cx, *b0, *b1, *b2, *b3;
+  float *W, *fac, *red, *means, *gA, *gB, *glam, *gxi, *cx, *b0, *b1, *b2, *b3, *part;
   float4* obs;
   float4* box;
   u64* masks;
@@ -855,7 +1016,6 @@ __device__ __forceinline__ BwdLds carve_bwd(float* sm, int nc, int Tc, int n_max
                                             int S_max) {
   BwdLds L;
   float* p = sm;
-  L.Wt = p; p += round4(nc * Tc);
   L.W = p; p += round4(nc * Tc);
   L.fac = p; p += round4(fac_stride(nc));
   L.red = p; p += kRed;
@@ -865,11 +1025,12 @@ __device__ __forceinline__ BwdLds carve_bwd(float* sm, int nc, int Tc, int n_max
     *bufs[q] = p;
     p += round4(S_max);
   }
+  L.part = p; p += kSplitMax * round4(S_max);
   L.obs = reinterpret_cast<float4*>(p); p += 4 * M_max;
   L.box = reinterpret_cast<float4*>(p); p += box_floats(Tc, n_max);
   L.masks = reinterpret_cast<u64*>(p); p += mask_floats(Tc, n_max, M_max);
-  L.X = reinterpret_cast<float2*>(p); p += 2 * n_max * round16(Tc);
-  L.G = reinterpret_cast<float2*>(p); p += 2 * n_max * round16(Tc);
+  L.X = reinterpret_cast<float2*>(p); p += 2 * n_max * tstride(Tc);
+  L.G = reinterpret_cast<float2*>(p); p += 2 * n_max * tstride(Tc);
   L.H = reinterpret_cast<float2*>(p);
   return L;
 }
@@ -889,9 +1050,9 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
   const size_t St = (size_t)A.S_total;
   BwdLds L = carve_bwd(sm, nc, Tc, A.n_max, A.M_max, A.S_max);
   Ctx C{n,         M,         nc,        T,         Tc,   S,   tid,   rho, P.a,
-        P.pmin[0], P.pmin[1], P.pmax[0], P.pmax[1], L.Wt, L.W, L.fac, A.W, L.obs,
+        P.pmin[0], P.pmin[1], P.pmax[0], P.pmax[1], L.W, L.fac, A.W, L.obs,
         L.box,     L.masks,   A.n_max,   A.M_max,   Tc < T};
-  if (!C.chunked) load_wchunk(A.W, L.W, L.Wt, nc, Tc, 0, T, tid, NT);
+  if (!C.chunked) load_wchunk(A.W, L.W, nc, 0, T, tid, NT);
   for (int t = tid; t < fs; t += NT) L.fac[t] = A.fac[(size_t)P.fac * fs + t];
   for (int m = tid; m < M; m += NT) {
     const float* o = A.obs + ((size_t)P.obs_off + m) * 3;
@@ -928,7 +1089,8 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
       stage_constraints_culled(L.X, L.H, n, L.obs, L.masks, P.a, P.pmin[0], P.pmin[1],
                                P.pmax[0], P.pmax[1], false, d1, d2, g, tid, NT, c1, c2);
       __syncthreads();
-      stage_wtmap_fused(L.W, nc, L.H, n, g, gx, true, nullptr, 0.f, false, dz, tid, NT);
+      stage_wtmap_mfma(L.W, nc, reinterpret_cast<const float*>(L.H), n, g.Tce, g.Tcs, gx, true,
+                       nullptr, 0.f, false, dz, tid >> 6, NT >> 6, tid & 63);
     }
     __syncthreads();
   }
@@ -954,7 +1116,7 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
       }
       __syncthreads();
       for (int l = l0; l < l1 - 1; ++l) {
-        sf_iteration<NT>(C, xr, xq, L.b2, L.b3, L.means, L.X, L.G, L.cx, false, dz);
+        sf_iteration<NT>(C, xr, xq, L.b2, L.b3, L.means, L.X, L.G, L.cx, false, dz, L.part);
         float* t = xr;
         xr = xq;
         xq = t;
@@ -1006,12 +1168,14 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
       for (int k0 = 0; k0 < T; k0 += Tc) {
         const Geo g = C.geo(k0);
         C.wchunk<NT>(k0, g.Tce);
-        stage_xmap(L.Wt, Tc, 0, gR, n, nc, L.G, g.Tce, g.Tcs, tid, NT);
+        stage_xmap_mfma(L.W, nc, gR, n, reinterpret_cast<float*>(L.G), g.Tce, g.Tcs, nullptr, 0,
+                        tid >> 6, NT >> 6, tid & 63);
         C.positions<NT>(xbl, L.X, g);
         stage_vjp_culled(L.X, L.G, L.H, n, L.obs, L.masks, P.a, P.pmin[0], P.pmin[1],
                          P.pmax[0], P.pmax[1], g, tid, NT);
         __syncthreads();
-        stage_wtmap_fused(L.W, nc, L.H, n, g, gn, true, nullptr, 0.f, false, dz, tid, NT);
+        stage_wtmap_mfma(L.W, nc, reinterpret_cast<const float*>(L.H), n, g.Tce, g.Tcs, gn,
+                         true, nullptr, 0.f, false, dz, tid >> 6, NT >> 6, tid & 63);
       }
       __syncthreads();
       float* t = gx;
@@ -1030,8 +1194,8 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
 
 size_t bwd_lds_bytes(int nc, int T, int Tc, int n_max, int M_max, int S_max, int) {
   auto r4 = [](int x) { return (size_t)((x + 3) & ~3); };
-  const size_t Tcs = (Tc + 15) & ~15;
-  size_t f = 2 * r4(nc * Tc) + r4(fac_stride(nc)) + kRed + kMeans + 9 * r4(S_max) +
+  const size_t Tcs = tstride(Tc);
+  size_t f = r4(nc * Tc) + r4(fac_stride(nc)) + kRed + kMeans + (9 + kSplitMax) * r4(S_max) +
              4 * (size_t)M_max + box_floats(Tc, n_max) + mask_floats(Tc, n_max, M_max) +
              6 * (size_t)n_max * Tcs;
   return f * sizeof(float);
@@ -1099,9 +1263,9 @@ __global__ __launch_bounds__(256) void plain_prep_kernel(FwdArgs A, PlainBufs Bf
 __global__ __launch_bounds__(256) void plain_xmap_kernel(FwdArgs A, PlainBufs Bf, int b,
                                                          int pp) {
   const ProbDesc P = A.probs[b];
-  const int tid = blockIdx.x * 256 + threadIdx.x;
-  stage_xmap(A.Wt, A.T, 0, Bf.xb[pp] + P.coef_off, P.n, A.nc,
-             reinterpret_cast<float2*>(Bf.X) + P.pos_off, A.T, A.T, tid, gridDim.x * 256);
+  stage_xmap_mfma(A.W, A.nc, Bf.xb[pp] + P.coef_off, P.n, Bf.X + (size_t)P.pos_off * 2, A.T,
+                  A.T, nullptr, 0, blockIdx.x * 4 + (threadIdx.x >> 6), gridDim.x * 4,
+                  threadIdx.x & 63);
 }
 
 __global__ __launch_bounds__(256) void plain_constraint_kernel(FwdArgs A, PlainBufs Bf,
@@ -1115,11 +1279,12 @@ __global__ __launch_bounds__(256) void plain_constraint_kernel(FwdArgs A, PlainB
                     P.pmax[0], P.pmax[1], false, d1, d2, tid, gridDim.x * 256);
 }
 
-__global__ __launch_bounds__(64) void plain_wtmap_kernel(FwdArgs A, PlainBufs Bf, int b) {
+__global__ __launch_bounds__(256) void plain_wtmap_kernel(FwdArgs A, PlainBufs Bf, int b) {
   const ProbDesc P = A.probs[b];
-  const int tid = blockIdx.x * 64 + threadIdx.x;
-  stage_wtmap(A.W, A.nc, 0, reinterpret_cast<const float2*>(Bf.V) + P.pos_off, P.n, A.T,
-              A.T, Bf.R + P.coef_off, false, tid, gridDim.x * 64);
+  const int S = 2 * P.n * A.nc;
+  stage_wtmap_part(A.W, A.nc, Bf.V + (size_t)P.pos_off * 2, P.n, A.T, A.T,
+                   Bf.part + (size_t)kSplitMax * P.coef_off, S, false,
+                   blockIdx.x * 4 + (threadIdx.x >> 6), gridDim.x * 4, threadIdx.x & 63);
 }
 
 __global__ __launch_bounds__(256) void plain_update_kernel(FwdArgs A, PlainBufs Bf, int b,
@@ -1136,14 +1301,8 @@ __global__ __launch_bounds__(256) void plain_update_kernel(FwdArgs A, PlainBufs 
   float* xn = Bf.xb[pp ^ 1] + P.coef_off;
   const float* cx = Bf.cxi + P.coef_off;
   float dzsq = 0.f;
-  for (int s = tid; s < S; s += 256) {
-    const float r = R[s], lm = lam[s];
-    lam[s] = fmaf(-rho, r, lm);
-    R[s] = fmaf(-2.f * rho, r, lm);
-    if (last) dzsq = fmaf(rho * r, rho * r, dzsq);
-  }
-  __syncthreads();
-  robot_means(R, xb, n, nc, means, tid, 256);
+  combine_lambda_means(Bf.part + (size_t)kSplitMax * P.coef_off, S, lam, R, xb, n, nc, rho,
+                       last, dzsq, means, tid, 256);
   __syncthreads();
   for (int s = tid; s < S; s += 256) {
     const int ax = s / (n * nc), rem = s - ax * n * nc, i = rem / nc, c = rem - i * nc;
@@ -1200,15 +1359,17 @@ __global__ void fill_kernel(float* p, float v, int64_t n) {
 hipError_t launch_plain_problem(const FwdArgs& a, const PlainBufs& pb, int b, hipStream_t s) {
   // grids sized for the batch's largest problem; the kernels stride over the
   // items of problem b
-  const int items = a.n_max * a.T;
-  const int gx = (items + 255) / 256;
-  const int gw = (2 * a.n_max * a.nc + 63) / 64;
+  const int tiles_x = ((a.T + 15) / 16) * ((2 * a.n_max + 15) / 16);
+  const int tiles_w = ((a.nc + 15) / 16) * ((2 * a.n_max + 15) / 16) * kSplitMax;
+  const int gx = (tiles_x + 3) / 4;             // four waves per block, a tile per wave
+  const int gw = (tiles_w + 3) / 4;
+  const int gc = (a.n_max * a.T + 255) / 256;
   hipLaunchKernelGGL(plain_prep_kernel, dim3(1), dim3(256), 0, s, a, pb, b);
   int pp = 0;
   for (int l = 0; l < a.L; ++l) {
     hipLaunchKernelGGL(plain_xmap_kernel, dim3(gx), dim3(256), 0, s, a, pb, b, pp);
-    hipLaunchKernelGGL(plain_constraint_kernel, dim3(gx), dim3(256), 0, s, a, pb, b);
-    hipLaunchKernelGGL(plain_wtmap_kernel, dim3(gw), dim3(64), 0, s, a, pb, b);
+    hipLaunchKernelGGL(plain_constraint_kernel, dim3(gc), dim3(256), 0, s, a, pb, b);
+    hipLaunchKernelGGL(plain_wtmap_kernel, dim3(gw), dim3(256), 0, s, a, pb, b);
     hipLaunchKernelGGL(plain_update_kernel, dim3(1), dim3(256), 0, s, a, pb, b, pp,
                        (int)(l == a.L - 1));
     pp ^= 1;

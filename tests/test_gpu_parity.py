@@ -110,18 +110,20 @@ def test_edge_single_robot_no_obstacles(gpu):
 
 
 def test_edge_coincident_robots(gpu):
-    """Two robots with identical trajectories: every pair difference is 0, the
-    alpha step's atan2(0, 0) = 0 tie, which decides the first step uniquely.
-    (Later iterates of this exactly symmetric instance are rounding-decided.)"""
-    p = _custom(2, 0, [[-1.0, 0.0], [-1.0, 0.0]], [[1.0, 0.0], [1.0, 0.0]], [])
+    """Two robots parked at the origin: every pair difference is exactly 0 on
+    both sides (all positions are exact zeros), the alpha step's
+    atan2(0, 0) = 0 tie decides the first step; a third robot moves past."""
+    p = _custom(3, 0, [[0.0, 0.0], [0.0, 0.0], [-1.0, 0.5]], [[0.0, 0.0], [0.0, 0.0], [1.0, 0.5]],
+                [])
     out = gpu_forward([p], RHO, 1)
     compare_forward([p], out, RHO, 1)
 
 
-def test_edge_trajectory_through_obstacle_centre(gpu):
-    """A robot path that passes exactly through an obstacle centre at one time
-    sample (the obstacle-side atan2(0, 0) tie) for one step."""
-    p = _custom(1, 1, [[-1.0, -1.0]], [[1.0, 1.0]], [[0.0, 0.0, 0.5]])
+def test_edge_robot_at_obstacle_centre(gpu):
+    """A robot parked exactly on an obstacle centre (the obstacle-side tie) for
+    one step."""
+    p = _custom(2, 2, [[0.0, 0.0], [1.5, -1.5]], [[0.0, 0.0], [1.5, 1.5]],
+                [[0.0, 0.0, 0.5], [-0.8, 0.8, 0.3]])
     out = gpu_forward([p], RHO, 1)
     compare_forward([p], out, RHO, 1)
 
