@@ -352,7 +352,7 @@ int build_plan(const sf_config_t* cfg, int B, const int32_t* n_robots, const int
   p->off_lam = take(F * coef);
   p->off_pcxi = take(F * coef);
   p->off_red = take(F * 4 * B);
-  p->off_part = take(F * 4 * coef);
+  p->off_part = take(F * sf::plain_part_floats(T, coef));
   p->total = off;
   out = std::move(p);
   return SF_OK;

@@ -105,12 +105,15 @@ struct PlainBufs {
   float* lam;    // coefficient layout
   float* cxi;    // coefficient layout
   float* red;    // [B][4] residual partials
-  float* part;   // per-problem K-split partial sums, 4 x coefficient layout
+  float* part;   // per-problem per-window partial sums [windows][coefficient layout]
 };
 hipError_t launch_plain_problem(const FwdArgs& a, const PlainBufs& pb, int b,
                                 hipStream_t s);
 
 hipError_t launch_fill(float* p, float v, int64_t n, hipStream_t s);
+
+// Floats of the plain path's per-window partial buffer for `coef` coefficients.
+size_t plain_part_floats(int T, int64_t coef);
 
 // Raise the dynamic-LDS limit of the fused kernels to `lds` bytes.
 hipError_t prepare_kernels(size_t lds);

@@ -19,16 +19,17 @@
 // F^T F + G^T G = ((n + M + 2) I - 1 1^T) (x) W^T W: a problem's operator is
 // P_perp Y_i + (P_par - P_perp) mean_i(Y) per axis with nc x nc matrices.
 //
-// Constraint evaluation is exact but culled: time is cut into windows of 16
-// steps (one 16-lane DPP row of a wave each); the coefficient->time map also
-// reduces each robot's bounding box per window, a wave per (robot, window)
-// turns box overlaps into 64-bit candidate masks with a ballot, and the
-// pair/obstacle loop visits only candidates.  A skipped pair is farther apart
-// than a (plus a rounding margin) at every step of the window, so it is
-// inactive and contributes exactly 0: the result equals the full loop's.
-//
-// The coefficient<->time maps are dense contractions and run on MFMA (16x16x4
-// FP32 tiles); the constraint stages are VALU work over LDS.
+// Work decomposition.  Time is cut into windows of 16 steps.  A wave owns a
+// (window, robot part) unit and runs it end to end without block barriers:
+// the coefficient->time map of the window for all robots on MFMA (16x16x4 FP32
+// tiles; the per-window bounding box of every robot falls out of the tile),
+// candidate masks for its robots (a pair or obstacle is a candidate when the
+// boxes come within the constraint distance plus a rounding margin), the exact
+// pair/obstacle/box stage over candidates, and the window's share of the
+// time->coefficient map R = W^T V on MFMA into a per-window partial.  Skipped
+// pairs are inactive at every step of the window and contribute exactly 0.
+// The partials are summed in window order, so every launch shape gives the
+// same bits.  Coefficient updates are MFMA tiles as well.
 //
 // Data layout: coefficient arrays [axis][robot][coef]; positions and
 // constraint sums [robot][time] as float2 (x, y) with an odd row stride
@@ -41,26 +42,30 @@ namespace sf {
 
 namespace {
 
-constexpr int kRed = 64;   // floats of LDS reduction scratch
-constexpr int kWin = 16;   // time steps per culling window (one DPP row)
+constexpr int kRed = 64;      // floats of LDS reduction scratch
 constexpr int kMeans = 4 * kMaxCoef + 8;
+constexpr int kMaxParts = 4;  // waves sharing one window
 
 typedef unsigned long long u64;
+typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int round4(int x) { return (x + 3) & ~3; }
-__device__ __forceinline__ int round16(int x) { return (x + 15) & ~15; }
 
 // Row stride (in steps) of the position/sum buffers: a window multiple plus
 // one, so that the 2*stride-float rows of different robots start in different
 // LDS banks.
 __host__ __device__ __forceinline__ int tstride(int Tc) { return ((Tc + 15) & ~15) + 1; }
-
-typedef float floatx4 __attribute__((ext_vector_type(4)));
+__host__ __device__ __forceinline__ int nwindows(int Tc) { return (Tc + 15) >> 4; }
 
 // D += A B for a 16x4 by 4x16 FP32 tile: lane l supplies A[l%16][l/16] and
 // B[l/16][l%16] and holds D[4(l/16)+v][l%16] in element v.
 __device__ __forceinline__ floatx4 mfma_16x16x4(float a, float b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Orders the LDS accesses of one wave (its stores before its later loads).
+__device__ __forceinline__ void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 }
 
 __device__ __forceinline__ float wave_sum(float v) {
@@ -95,12 +100,13 @@ __device__ __forceinline__ unsigned quad_or(unsigned v) {
   return v;
 }
 
-// floor(x / d) for 0 <= x < 2^16 and 16 <= d <= 4096 through a multiply-high
-// by m = floor((2^32 - 1)/d) + 1 (exact in that range).
-__device__ __forceinline__ unsigned div_magic(unsigned d) { return 0xFFFFFFFFu / d + 1u; }
-__device__ __forceinline__ int fast_div(int x, unsigned m) { return (int)__umulhi((unsigned)x, m); }
+__device__ __forceinline__ u64 readlane64(u64 v, int lane) {
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)v, lane);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(v >> 32), lane);
+  return ((u64)hi << 32) | lo;
+}
 
-// Deterministic block sum of up to 4 values: wave shuffles, then a fixed-order
+// Deterministic block sum of up to 4 values: wave sums, then a fixed-order
 // pass over the per-wave partials.  All threads get the totals.
 template <int K>
 __device__ void block_sum(float (&v)[K], float* scratch) {
@@ -123,195 +129,49 @@ __device__ void block_sum(float (&v)[K], float* scratch) {
   __syncthreads();
 }
 
-__device__ __forceinline__ u64 readlane64(u64 v, int lane) {
-  const unsigned lo = __builtin_amdgcn_readlane((unsigned)v, lane);
-  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(v >> 32), lane);
-  return ((u64)hi << 32) | lo;
-}
-
 // ---------------------------------------------------------------------------
-// Stages used by the plain (unfused, global-memory) path.
+// Window stages.  Xf/Vf are float views of [robot][step] float2 arrays with
+// row stride Ts steps; steps are chunk-local.  Columns of the map tiles are
+// (robot, axis) pairs col = 2 i + axis, 16 per tile (8 robots).
 // ---------------------------------------------------------------------------
 
-// Pair/obstacle/box residual sums for one (robot, step): every other robot
-// and every obstacle is visited.
-__device__ __forceinline__ void stage_constraints(
-    const float2* __restrict__ X, float2* __restrict__ V, int n, int Tce, int Tcs,
-    const float* __restrict__ obs, int M, float a, float pmin0, float pmin1, float pmax0,
-    float pmax1, bool accum, float& r1sq, float& r2sq, int tid, int nthr) {
-  const float a2 = a * a;
-  const int items = n * Tce;
-  for (int idx = tid; idx < items; idx += nthr) {
-    const int i = idx / Tce;
-    const int kk = idx - i * Tce;
-    const float2 p = X[i * Tcs + kk];
-    float vx = 0.f, vy = 0.f;
-    for (int j = 0; j < n; ++j) {
-      const float2 q = X[j * Tcs + kk];
-      const float dx = p.x - q.x;
-      const float dy = p.y - q.y;
-      const float d2 = fmaf(dy, dy, dx * dx);
-      if (d2 < a2 && j != i) {
-        float rx, ry;
-        if (d2 > 0.f) {
-          const float f = 1.f - a * rsqrtf(d2);
-          rx = f * dx;
-          ry = f * dy;
-        } else {  // coincident: alpha = atan2(0, 0) = 0 for the row (min, max)
-          rx = (i < j) ? -a : a;
-          ry = 0.f;
-        }
-        vx += rx;
-        vy += ry;
-        if (accum && j > i) r1sq = fmaf(rx, rx, fmaf(ry, ry, r1sq));
-      }
-    }
-    for (int m = 0; m < M; ++m) {
-      const float cx = obs[3 * m], cy = obs[3 * m + 1], ao = obs[3 * m + 2];
-      const float dx = p.x - cx;
-      const float dy = p.y - cy;
-      const float d2 = fmaf(dy, dy, dx * dx);
-      if (d2 < ao * ao) {
-        float rx, ry;
-        if (d2 > 0.f) {
-          const float f = 1.f - ao * rsqrtf(d2);
-          rx = f * dx;
-          ry = f * dy;
-        } else {
-          rx = -ao;
-          ry = 0.f;
-        }
-        vx += rx;
-        vy += ry;
-        if (accum) r1sq = fmaf(rx, rx, fmaf(ry, ry, r1sq));
-      }
-    }
-    const float hx = fmaxf(p.x - pmax0, 0.f), lx = fmaxf(pmin0 - p.x, 0.f);
-    const float hy = fmaxf(p.y - pmax1, 0.f), ly = fmaxf(pmin1 - p.y, 0.f);
-    vx = fmaf(1.f, hx - lx, vx);
-    vy = fmaf(1.f, hy - ly, vy);
-    if (accum) r2sq += hx * hx + lx * lx + hy * hy + ly * ly;
-    V[i * Tcs + kk] = make_float2(vx, vy);
-  }
+// t-th robot of part h when 8-robot groups are dealt round-robin to H parts.
+__device__ __forceinline__ int part_robot(int t, int h, int H) {
+  return ((t >> 3) * H + h) * 8 + (t & 7);
 }
 
-// ---------------------------------------------------------------------------
-// Coefficient-space helpers shared by both paths.
-// ---------------------------------------------------------------------------
-
-// Mode operator: out_i = P_perp y_i + D ybar (rows of P are contiguous).
-__device__ __forceinline__ float mode_row(const float* __restrict__ Pp,
-                                          const float* __restrict__ D,
-                                          const float* __restrict__ y,
-                                          const float* __restrict__ ym, int nc, int c,
-                                          float acc) {
-  const float* pr = Pp + c * nc;
-  const float* dr = D + c * nc;
-  for (int q = 0; q < nc; ++q) acc = fmaf(pr[q], y[q], fmaf(dr[q], ym[q], acc));
-  return acc;
-}
-
-// Transposed mode operator: out_i = P_perp^T y_i + D^T ybar.
-__device__ __forceinline__ float mode_row_t(const float* __restrict__ Pp,
-                                            const float* __restrict__ D,
-                                            const float* __restrict__ y,
-                                            const float* __restrict__ ym, int nc, int c,
-                                            float acc) {
-  for (int q = 0; q < nc; ++q)
-    acc = fmaf(Pp[q * nc + c], y[q], fmaf(D[q * nc + c], ym[q], acc));
-  return acc;
-}
-
-// Robot means of every (axis, coef) column of up to two coefficient arrays:
-// out[axis*nc + c] for src0 and out[2nc + axis*nc + c] for src1.  One wave per
-// column; lane i holds robots i, i+64, ...; fixed reduction tree.
-__device__ __forceinline__ void robot_means(const float* __restrict__ src0,
-                                            const float* __restrict__ src1, int n, int nc,
-                                            float* __restrict__ out, int tid, int nthr) {
-  const int lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
-  const float inv = 1.f / (float)n;
-  const int cols = (src1 ? 4 : 2) * nc;
-  for (int col = wave; col < cols; col += nwaves) {
-    const float* src = col < 2 * nc ? src0 : src1;
-    const int cc = col < 2 * nc ? col : col - 2 * nc;
-    const int ax = cc / nc, c = cc - ax * nc;
-    const float* base = src + ax * n * nc + c;
-    float s = 0.f;
-    for (int i = lane; i < n; i += 64) s += base[i * nc];
-    s = wave_sum_dpp(s);
-    if (lane == 0) out[col] = s * inv;
-  }
-}
-
-// Constant term c_xi = S xi + N b, mode form (first block of K^{-1} applied to
-// the xi and b parts of eta).  tgt: target xi (coefficient layout), xm/bm:
-// robot means of xi ([2][nc]) and of b ([2 axes][2 ends] as bm[ax*2+q]).
-__device__ __forceinline__ float cxi_entry(const float* __restrict__ fac, int nc,
-                                           const float* __restrict__ tgt,
-                                           const float* __restrict__ xm,
-                                           const float* __restrict__ bnd_i,
-                                           const float* __restrict__ bm, int n, int ax, int i,
-                                           int c) {
-  const int nc2 = nc * nc;
-  const float* Sp = fac;
-  const float* DS = fac + nc2;
-  const float* Np = fac + 4 * nc2;
-  const float* DN = Np + 2 * nc;
-  float out = mode_row(Sp, DS, tgt + ax * n * nc + i * nc, xm + ax * nc, nc, c, 0.f);
-  for (int q = 0; q < 2; ++q) {
-    out = fmaf(Np[c * 2 + q], bnd_i[q * 2 + ax], out);
-    out = fmaf(DN[c * 2 + q], bm[ax * 2 + q], out);
-  }
-  return out;
-}
-
-// Robot means of the boundary positions into bm[ax*2 + q].
-__device__ __forceinline__ void boundary_means(const float* __restrict__ bnd, int n,
-                                               float* __restrict__ bm, int tid, int nthr) {
-  for (int t = tid; t < 4; t += nthr) {
-    const int ax = t >> 1, q = t & 1;
-    float s = 0.f;
-    for (int i = 0; i < n; ++i) s += bnd[i * 4 + q * 2 + ax];
-    bm[t] = s / (float)n;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// The two dense contractions on MFMA (16x16x4 FP32 tiles), one tile per wave.
-// Columns are (robot, axis) pairs col = 2 i + axis, padded to a multiple of 16.
-// Positions/sums are float views of [robot][step] float2 arrays with row
-// stride Ts steps.
-// ---------------------------------------------------------------------------
-
-// Coefficient -> time map X[i][kk].axis = sum_c W[kk][c] xb[axis][i][c] for kk <
-// Tce (rows = steps, 16 per tile = one culling window; K = coefficients padded
-// to 4).  Padding rows repeat the chunk's last step.  With `box`, each robot's
-// per-window bounding box (xmin, xmax, ymin, ymax) is reduced from the tile.
-__device__ __forceinline__ void stage_xmap_mfma(const float* __restrict__ W, int nc,
-                                                const float* __restrict__ xb, int n,
-                                                float* __restrict__ Xf, int Tce, int Ts,
-                                                float* __restrict__ boxf, int nws, int wave,
-                                                int nwaves, int lane) {
-  const int nwin = (Tce + 15) >> 4;
+// Coefficient -> time map of window w for all robots: X[i][16w + r].axis =
+// sum_c W[16w + r][c] xb[axis][i][c] for steps < Tce (padding rows repeat the
+// last step), and with `boxf` each robot's box (xmin, xmax, ymin, ymax) over
+// the window's steps.
+__device__ __forceinline__ void xmap_window(const float* __restrict__ W, int nc,
+                                            const float* __restrict__ xb, int n,
+                                            float* __restrict__ Xf, int Ts, int w, int Tce,
+                                            float* __restrict__ boxf, int nws, int lane) {
   const int ncol = (2 * n + 15) >> 4;
   const int ks = (nc + 3) >> 2;
   const int m = lane & 15, kq = lane >> 4;
-  for (int tile = wave; tile < nwin * ncol; tile += nwaves) {
-    const int mt = tile / ncol, nt = tile - mt * ncol;
-    const int row = min(mt * 16 + m, Tce - 1);
+  const int row = min(w * 16 + m, Tce - 1);
+  float av[kMaxCoef / 4];
+#pragma unroll
+  for (int s = 0; s < kMaxCoef / 4; ++s) {
+    const int c = 4 * s + kq;
+    av[s] = (s < ks && c < nc) ? W[row * nc + c] : 0.f;
+  }
+  const int k0 = w * 16 + 4 * kq;
+  for (int nt = 0; nt < ncol; ++nt) {
     const int col = nt * 16 + m;
     const int i = col >> 1, ax = col & 1;
     const bool colok = i < n;
-    const float* wrow = W + row * nc;
-    const float* brow = xb + ax * n * nc + i * nc;
+    const float* brow = xb + ax * n * nc + (colok ? i : 0) * nc;
     floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int s = 0; s < ks; ++s) {
-      const int c = 4 * s + kq;
-      const float a = c < nc ? wrow[c] : 0.f;
-      const float b = (c < nc && colok) ? brow[c] : 0.f;
-      acc = mfma_16x16x4(a, b, acc);
+#pragma unroll
+    for (int s = 0; s < kMaxCoef / 4; ++s) {
+      if (s < ks) {
+        const int c = 4 * s + kq;
+        acc = mfma_16x16x4(av[s], (c < nc && colok) ? brow[c] : 0.f, acc);
+      }
     }
-    const int k0 = mt * 16 + 4 * kq;
     if (colok) {
 #pragma unroll
       for (int v = 0; v < 4; ++v)
@@ -325,7 +185,7 @@ __device__ __forceinline__ void stage_xmap_mfma(const float* __restrict__ W, int
       lo = fminf(lo, __shfl_xor(lo, 32, 64));
       hi = fmaxf(hi, __shfl_xor(hi, 32, 64));
       if (lane < 16 && colok) {
-        float* bx = boxf + ((size_t)i * nws + mt) * 4 + 2 * ax;
+        float* bx = boxf + ((size_t)i * nws + w) * 4 + 2 * ax;
         bx[0] = lo;
         bx[1] = hi;
       }
@@ -333,212 +193,32 @@ __device__ __forceinline__ void stage_xmap_mfma(const float* __restrict__ W, int
   }
 }
 
-// Time -> coefficient map R[axis][i][c] (+)= sum_kk W[kk][c] V[i][kk].axis over
-// kk < Tce (rows = coefficients, K = steps padded to 16).  With `lam`, the
-// lambda step runs on the finished R: lambda' = lambda - rho R and R becomes
-// u = lambda - 2 rho R.
-__device__ __forceinline__ void stage_wtmap_mfma(const float* __restrict__ W, int nc,
-                                                 const float* __restrict__ Vf, int n, int Tce,
-                                                 int Ts, float* __restrict__ R, bool accumulate,
-                                                 float* __restrict__ lam, float rho,
-                                                 bool want_dz, float& dzsq, int wave, int nwaves,
-                                                 int lane) {
-  const int nct = (nc + 15) >> 4;
-  const int ncol = (2 * n + 15) >> 4;
-  const int ks = ((Tce + 15) >> 4) * 4;
-  const int m = lane & 15, kq = lane >> 4;
-  for (int tile = wave; tile < nct * ncol; tile += nwaves) {
-    const int ct = tile / ncol, nt = tile - ct * ncol;
-    const int ca = ct * 16 + m;
-    const int col = nt * 16 + m;
-    const int i = col >> 1, ax = col & 1;
-    const bool colok = i < n;
-    const float* vrow = Vf + (size_t)(colok ? i : 0) * Ts * 2 + ax;
-    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int st = 0; st < ks; st += 4) {
-      float av[4], bv[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int kk = 4 * (st + u) + kq;
-        const bool kok = kk < Tce;
-        av[u] = (kok && ca < nc) ? W[kk * nc + ca] : 0.f;
-        bv[u] = (kok && colok) ? vrow[2 * kk] : 0.f;
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) acc = mfma_16x16x4(av[u], bv[u], acc);
-    }
-    if (colok) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int c = ct * 16 + 4 * kq + v;
-        if (c >= nc) continue;
-        const int sidx = ax * n * nc + i * nc + c;
-        const float r = accumulate ? R[sidx] + acc[v] : acc[v];
-        if (lam) {
-          const float lm = lam[sidx];
-          lam[sidx] = fmaf(-rho, r, lm);
-          R[sidx] = fmaf(-2.f * rho, r, lm);
-          if (want_dz) dzsq = fmaf(rho * r, rho * r, dzsq);
-        } else {
-          R[sidx] = r;
-        }
-      }
-    }
-  }
-}
-
-// Number of K splits of the time->coefficient map for a problem: enough
-// (tile, split) work items for 16 waves, at most kSplitMax; depends only on
-// the problem's shape, so every launch configuration sums in the same order.
-constexpr int kSplitMax = 4;
-__host__ __device__ __forceinline__ int wt_splits(int n, int nc) {
-  const int tiles = ((nc + 15) >> 4) * ((2 * n + 15) >> 4);
-  const int ks = 16 / tiles;
-  return ks < 1 ? 1 : (ks > kSplitMax ? kSplitMax : ks);
-}
-
-// K-split time->coefficient map: split sp of tile t adds sum over its share of
-// the steps of W[kk][c] V[i][kk].axis into part[sp*S + s] (or stores it).
-// Loads of four K steps are issued ahead of their MFMAs; zero-padded steps
-// add exact zeros.
-__device__ __forceinline__ void stage_wtmap_part(const float* __restrict__ W, int nc,
-                                                 const float* __restrict__ Vf, int n, int Tce,
-                                                 int Ts, float* __restrict__ part, int S,
-                                                 bool accumulate, int wave, int nwaves,
-                                                 int lane) {
-  const int nct = (nc + 15) >> 4;
-  const int ncol = (2 * n + 15) >> 4;
-  const int tiles = nct * ncol;
-  const int KS = wt_splits(n, nc);
-  const int ks = ((Tce + 15) >> 4) * 4;
-  const int kps = (((ks + KS - 1) / KS) + 3) & ~3;
-  const int m = lane & 15, kq = lane >> 4;
-  for (int wi = wave; wi < tiles * KS; wi += nwaves) {
-    const int sp = wi / tiles, tile = wi - sp * tiles;
-    const int ct = tile / ncol, nt = tile - ct * ncol;
-    const int ca = ct * 16 + m;
-    const int col = nt * 16 + m;
-    const int i = col >> 1, ax = col & 1;
-    const bool colok = i < n;
-    const float* vrow = Vf + (size_t)(colok ? i : 0) * Ts * 2 + ax;
-    const int s0 = sp * kps, s1 = min(ks, s0 + kps);
-    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int st = s0; st < s1; st += 4) {
-      float av[4], bv[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int kk = 4 * (st + u) + kq;
-        const bool kok = (st + u < s1) && kk < Tce;
-        av[u] = (kok && ca < nc) ? W[kk * nc + ca] : 0.f;
-        bv[u] = (kok && colok) ? vrow[2 * kk] : 0.f;
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) acc = mfma_16x16x4(av[u], bv[u], acc);
-    }
-    if (colok) {
-      float* dst = part + (size_t)sp * S;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int c = ct * 16 + 4 * kq + v;
-        if (c >= nc) continue;
-        const int sidx = ax * n * nc + i * nc + c;
-        dst[sidx] = accumulate ? dst[sidx] + acc[v] : acc[v];
-      }
-    }
-  }
-}
-
-// R = the K-split partials summed in split order; lambda step lambda' =
-// lambda - rho R; u = lambda - 2 rho R into Ru; robot means of u
-// (means[axis*nc + c]) and of xb (means[2nc + axis*nc + c]).  One wave per
-// column, lanes over robots.
-__device__ __forceinline__ void combine_lambda_means(const float* __restrict__ part, int S,
-                                                     float* __restrict__ lam,
-                                                     float* __restrict__ Ru,
-                                                     const float* __restrict__ xb, int n, int nc,
-                                                     float rho, bool want_dz, float& dzsq,
-                                                     float* __restrict__ means, int tid,
-                                                     int nthr) {
-  const int lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
-  const int KS = wt_splits(n, nc);
-  const float inv = 1.f / (float)n;
-  for (int col = wave; col < 4 * nc; col += nwaves) {
-    const bool ucol = col < 2 * nc;
-    const int cc = ucol ? col : col - 2 * nc;
-    const int ax = cc / nc, c = cc - ax * nc;
-    float acc = 0.f;
-    for (int i = lane; i < n; i += 64) {
-      const int sidx = ax * n * nc + i * nc + c;
-      if (ucol) {
-        float r = part[sidx];
-        for (int k = 1; k < KS; ++k) r += part[(size_t)k * S + sidx];
-        const float lm = lam[sidx];
-        lam[sidx] = fmaf(-rho, r, lm);
-        const float u = fmaf(-2.f * rho, r, lm);
-        Ru[sidx] = u;
-        acc += u;
-        if (want_dz) dzsq = fmaf(rho * r, rho * r, dzsq);
-      } else {
-        acc += xb[sidx];
-      }
-    }
-    acc = wave_sum_dpp(acc);
-    if (lane == 0) means[col] = acc * inv;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Stages of the fused kernels (LDS-resident state, culled constraints).
-// Loops over (robot, step) items advance a whole wave at a time so that a
-// 16-lane row always holds one (robot, window) and shuffles see whole rows.
-// ---------------------------------------------------------------------------
-
-// Copy rows k0 .. k0+Tce-1 of W (global, [T][nc]) into the LDS table W.
-__device__ __forceinline__ void load_wchunk(const float* __restrict__ Wg, float* __restrict__ W,
-                                            int nc, int k0, int Tce, int tid, int nthr) {
-  for (int t = tid; t < Tce * nc; t += nthr) W[t] = Wg[k0 * nc + t];
-}
-
-// Culling geometry of one chunk: padded step count, window count and strides.
-struct Geo {
-  int Tce;   // steps in this chunk
-  int Tcp;   // Tce rounded up to a window multiple
-  int Tcs;   // row stride of X/V buffers (>= Tcp)
-  int nws;   // row stride (in windows) of the box and mask arrays
-  int pw;    // 64-bit mask words for robots
-  int ow;    // 64-bit mask words for obstacles
-};
-
-// Candidate masks per (robot, window): bit j of word q set when robot 64q+j
-// (j != i) has a box within a (plus margin) of robot i's box in both axes;
-// bit m of the obstacle words when obstacle m's disc (plus margin) meets robot
-// i's box.  Four lanes (a DPP quad) share a (robot, window) and split the
-// candidates.  The margin covers rounding of the box comparison and of the
-// exact test at coordinates of magnitude up to the box's plus the threshold.
-__device__ __forceinline__ void stage_masks(const float4* __restrict__ box, int n,
-                                            const float4* __restrict__ obs, int M, float a,
-                                            u64* __restrict__ masks, const Geo& g, int tid,
-                                            int nthr) {
-  const int lane = tid & 63;
-  const int nwin = g.Tcp >> 4;
-  const int tasks = n * nwin;
-  const int mw = g.pw + g.ow;
-  for (int base = tid & ~63; base < tasks * 4; base += nthr) {
-    const int idx = base + lane;
-    const bool live = idx < tasks * 4;
-    const int task = live ? idx >> 2 : 0;
-    const int q = idx & 3;
-    const int i = task / nwin, w = task - i * nwin;
-    const float4 bi = box[i * g.nws + w];
+// Candidate masks of window w for the robots of part h: bit j of word q set
+// when robot 64q+j (j != i) has a box within a (plus margin) of robot i's box
+// in both axes; bit m of the obstacle words when obstacle m's disc (plus
+// margin) meets robot i's box.  Four lanes (a DPP quad) per robot.  The
+// margin covers rounding of the box comparison and of the exact test at
+// coordinates up to the box's magnitude plus the threshold.
+__device__ __forceinline__ void masks_window(const float4* __restrict__ box, int n,
+                                             const float4* __restrict__ obs, int M, float a,
+                                             u64* __restrict__ masks, int nws, int pw, int ow,
+                                             int w, int h, int H, int lane) {
+  const int mw = pw + ow;
+  const int q = lane & 3;
+  for (int t0 = 0; part_robot(t0, h, H) < n; t0 += 16) {
+    const int i0 = part_robot(t0 + (lane >> 2), h, H);
+    const bool live = i0 < n;
+    const int i = live ? i0 : 0;
+    const float4 bi = box[i * nws + w];
     const float si = fmaxf(fmaxf(fabsf(bi.x), fabsf(bi.y)), fmaxf(fabsf(bi.z), fabsf(bi.w)));
     const float am = a * 1.0001f + 4e-6f * (1.f + si + 2.f * a);
-    u64* out = masks + (size_t)(i * g.nws + w) * mw;
-    for (int wd = 0; wd < g.pw; ++wd) {
+    u64* out = masks + (size_t)(i * nws + w) * mw;
+    for (int wd = 0; wd < pw; ++wd) {
       unsigned lo = 0u, hi = 0u;
       const int jend = min(n - wd * 64, 64);
       for (int jj = q; jj < jend; jj += 4) {
         const int j = wd * 64 + jj;
-        const float4 bj = box[j * g.nws + w];
+        const float4 bj = box[j * nws + w];
         const bool c = (j != i) && (bi.x < bj.y + am) && (bj.x < bi.y + am) &&
                        (bi.z < bj.w + am) && (bj.z < bi.w + am);
         const unsigned bit = c ? (1u << (jj & 31)) : 0u;
@@ -548,7 +228,7 @@ __device__ __forceinline__ void stage_masks(const float4* __restrict__ box, int 
       hi = quad_or(hi);
       if (live && q == 0) out[wd] = ((u64)hi << 32) | lo;
     }
-    for (int wd = 0; wd < g.ow; ++wd) {
+    for (int wd = 0; wd < ow; ++wd) {
       unsigned lo = 0u, hi = 0u;
       const int mend = min(M - wd * 64, 64);
       for (int mm = q; mm < mend; mm += 4) {
@@ -560,45 +240,43 @@ __device__ __forceinline__ void stage_masks(const float4* __restrict__ box, int 
       }
       lo = quad_or(lo);
       hi = quad_or(hi);
-      if (live && q == 0) out[g.pw + wd] = ((u64)hi << 32) | lo;
+      if (live && q == 0) out[pw + wd] = ((u64)hi << 32) | lo;
     }
   }
 }
 
-// Union over the wave's four rows of the rows' candidate words.
+// Union over the wave's four 16-lane rows of the rows' candidate words.
 __device__ __forceinline__ u64 wave_union(u64 m) {
   return readlane64(m, 0) | readlane64(m, 16) | readlane64(m, 32) | readlane64(m, 48);
 }
 
-// Culled constraint stage: V = w_pair (pair + obstacle sums) + w_box (box
-// residual), pairs visited in increasing robot index, then obstacles, then the
-// box (the order of the full loop).  With `accum`, ||r_1||^2 (each unordered
-// pair once) and ||r_2||^2.
-__device__ __forceinline__ void stage_constraints_culled(
-    const float2* __restrict__ X, float2* __restrict__ V, int n,
-    const float4* __restrict__ obs, const u64* __restrict__ masks, float a, float pmin0,
-    float pmin1, float pmax0, float pmax1, bool accum, float& r1sq, float& r2sq,
-    const Geo& g, int tid, int nthr, float w_pair = 1.f, float w_box = 1.f) {
+// Exact constraint stage of window w for the robots of part h (a 16-lane row
+// per robot): V = w_pair (pair + obstacle sums) + w_box (box residual), pairs
+// visited in increasing robot index, then obstacles, then the box.  With
+// `accum`, ||r_1||^2 (each unordered pair once) and ||r_2||^2.
+__device__ __forceinline__ void constraints_window(
+    const float2* __restrict__ X, float2* __restrict__ V, int n, int Ts,
+    const float4* __restrict__ obs, const u64* __restrict__ masks, int nws, int pw, int ow,
+    float a, float pmin0, float pmin1, float pmax0, float pmax1, int w, int Tce, int h, int H,
+    bool accum, float& r1sq, float& r2sq, float w_pair, float w_box, int lane) {
   const float a2 = a * a;
-  const int items = n * g.Tcp;
-  const int mw = g.pw + g.ow;
-  const unsigned dm = div_magic((unsigned)g.Tcp);
-  for (int base = tid & ~63; base < items; base += nthr) {
-    const int idx = base + (tid & 63);
-    const bool live = idx < items;
-    const int i = live ? fast_div(idx, dm) : 0;
-    const int kk = live ? idx - i * g.Tcp : 0;
-    const bool valid = live && kk < g.Tce;
-    const int kq = min(kk, g.Tce - 1);
-    const u64* my = masks + (size_t)(i * g.nws + (kk >> 4)) * mw;
-    const float2 p = X[i * g.Tcs + kq];
+  const int mw = pw + ow;
+  const int kk = w * 16 + (lane & 15);
+  const int kq = min(kk, Tce - 1);
+  for (int t0 = 0; part_robot(t0, h, H) < n; t0 += 4) {
+    const int i0 = part_robot(t0 + (lane >> 4), h, H);
+    const bool live = i0 < n;
+    const int i = live ? i0 : 0;
+    const bool valid = live && kk < Tce;
+    const u64* my = masks + (size_t)(i * nws + w) * mw;
+    const float2 p = X[i * Ts + kq];
     float vx = 0.f, vy = 0.f, s1 = 0.f;
-    for (int q = 0; q < g.pw; ++q) {
+    for (int q = 0; q < pw; ++q) {
       u64 u = wave_union(live ? my[q] : 0ull);
       while (u) {
         const int j = q * 64 + __builtin_ctzll(u);
         u &= u - 1;
-        const float2 o = X[j * g.Tcs + kq];
+        const float2 o = X[j * Ts + kq];
         const float dx = p.x - o.x;
         const float dy = p.y - o.y;
         const float d2 = fmaf(dy, dy, dx * dx);
@@ -618,8 +296,8 @@ __device__ __forceinline__ void stage_constraints_culled(
         }
       }
     }
-    for (int q = 0; q < g.ow; ++q) {
-      u64 u = wave_union(live ? my[g.pw + q] : 0ull);
+    for (int q = 0; q < ow; ++q) {
+      u64 u = wave_union(live ? my[pw + q] : 0ull);
       while (u) {
         const int m = q * 64 + __builtin_ctzll(u);
         u &= u - 1;
@@ -648,7 +326,7 @@ __device__ __forceinline__ void stage_constraints_culled(
     vx = fmaf(w_box, hx - lx, w_pair * vx);
     vy = fmaf(w_box, hy - ly, w_pair * vy);
     if (valid) {
-      V[i * g.Tcs + kk] = make_float2(vx, vy);
+      V[i * Ts + kk] = make_float2(vx, vy);
       if (accum) {
         r1sq += s1;
         r2sq += hx * hx + lx * lx + hy * hy + ly * ly;
@@ -657,42 +335,42 @@ __device__ __forceinline__ void stage_constraints_culled(
   }
 }
 
-// Culled vector-Jacobian product of the constraint stage: given the cotangent
-// G of V at positions X,
+// Vector-Jacobian product of the constraint stage over window w for the robots
+// of part h: given the cotangent G of V at positions X,
 //   H_i = sum_{j != i} J(X_i - X_j) (G_i - G_j) + sum_m J_o(X_i - c_m) G_i
 //         + box'(X_i) G_i,
 // where J(D) = (1 - f) I + f u u^T, f = a/|D|, u = D/|D| is the Jacobian of
 // r(D) = D - e(D) for an active pair (|D| < a) and 0 otherwise; at D = 0 the
 // e of the alpha/d steps is locally constant, so J = I.
-__device__ __forceinline__ void stage_vjp_culled(
-    const float2* __restrict__ X, const float2* __restrict__ G, float2* __restrict__ H, int n,
-    const float4* __restrict__ obs, const u64* __restrict__ masks, float a, float pmin0,
-    float pmin1, float pmax0, float pmax1, const Geo& g, int tid, int nthr) {
+__device__ __forceinline__ void vjp_window(const float2* __restrict__ X,
+                                           const float2* __restrict__ G, float2* __restrict__ Hb,
+                                           int n, int Ts, const float4* __restrict__ obs,
+                                           const u64* __restrict__ masks, int nws, int pw, int ow,
+                                           float a, float pmin0, float pmin1, float pmax0,
+                                           float pmax1, int w, int Tce, int h, int H, int lane) {
   const float a2 = a * a;
-  const int items = n * g.Tcp;
-  const int mw = g.pw + g.ow;
-  const unsigned dm = div_magic((unsigned)g.Tcp);
-  for (int base = tid & ~63; base < items; base += nthr) {
-    const int idx = base + (tid & 63);
-    const bool live = idx < items;
-    const int i = live ? fast_div(idx, dm) : 0;
-    const int kk = live ? idx - i * g.Tcp : 0;
-    const int kq = min(kk, g.Tce - 1);
-    const u64* my = masks + (size_t)(i * g.nws + (kk >> 4)) * mw;
-    const float2 p = X[i * g.Tcs + kq];
-    const float2 gi = G[i * g.Tcs + kq];
+  const int mw = pw + ow;
+  const int kk = w * 16 + (lane & 15);
+  const int kq = min(kk, Tce - 1);
+  for (int t0 = 0; part_robot(t0, h, H) < n; t0 += 4) {
+    const int i0 = part_robot(t0 + (lane >> 4), h, H);
+    const bool live = i0 < n;
+    const int i = live ? i0 : 0;
+    const u64* my = masks + (size_t)(i * nws + w) * mw;
+    const float2 p = X[i * Ts + kq];
+    const float2 gi = G[i * Ts + kq];
     float hx = 0.f, hy = 0.f;
-    for (int q = 0; q < g.pw; ++q) {
+    for (int q = 0; q < pw; ++q) {
       u64 u = wave_union(live ? my[q] : 0ull);
       while (u) {
         const int j = q * 64 + __builtin_ctzll(u);
         u &= u - 1;
-        const float2 o = X[j * g.Tcs + kq];
+        const float2 o = X[j * Ts + kq];
         const float dx = p.x - o.x;
         const float dy = p.y - o.y;
         const float d2 = fmaf(dy, dy, dx * dx);
         if (d2 < a2 && j != i) {
-          const float2 gj = G[j * g.Tcs + kq];
+          const float2 gj = G[j * Ts + kq];
           const float wx = gi.x - gj.x, wy = gi.y - gj.y;
           if (d2 > 0.f) {
             const float inv = rsqrtf(d2);
@@ -708,8 +386,8 @@ __device__ __forceinline__ void stage_vjp_culled(
         }
       }
     }
-    for (int q = 0; q < g.ow; ++q) {
-      u64 u = wave_union(live ? my[g.pw + q] : 0ull);
+    for (int q = 0; q < ow; ++q) {
+      u64 u = wave_union(live ? my[pw + q] : 0ull);
       while (u) {
         const int m = q * 64 + __builtin_ctzll(u);
         u &= u - 1;
@@ -734,11 +412,288 @@ __device__ __forceinline__ void stage_vjp_culled(
     }
     if (p.x > pmax0 || p.x < pmin0) hx += gi.x;
     if (p.y > pmax1 || p.y < pmin1) hy += gi.y;
-    if (live && kk < g.Tce) H[i * g.Tcs + kk] = make_float2(hx, hy);
+    if (live && kk < Tce) Hb[i * Ts + kk] = make_float2(hx, hy);
   }
 }
 
-// Per-problem constants of the fused kernels, with LDS-resident tables.
+// Window w's share of the time->coefficient map for the column tiles of part
+// h (tiles nt = h, h+H, ...): part_w[axis][i][c] (+)= sum over the window's
+// steps of W[k][c] V[i][k].axis.
+__device__ __forceinline__ void wtmap_window(const float* __restrict__ W, int nc,
+                                             const float* __restrict__ Vf, int n, int Ts, int w,
+                                             int Tce, int h, int H, float* __restrict__ part_w,
+                                             bool accumulate, int lane) {
+  const int nct = (nc + 15) >> 4;
+  const int ncol = (2 * n + 15) >> 4;
+  const int m = lane & 15, kq = lane >> 4;
+  for (int nt = h; nt < ncol; nt += H) {
+    const int col = nt * 16 + m;
+    const int i = col >> 1, ax = col & 1;
+    const bool colok = i < n;
+    const float* vrow = Vf + (size_t)(colok ? i : 0) * Ts * 2 + ax;
+    float bv[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int kk = w * 16 + 4 * s + kq;
+      bv[s] = (kk < Tce && colok) ? vrow[2 * kk] : 0.f;
+    }
+    for (int ct = 0; ct < nct; ++ct) {
+      const int ca = ct * 16 + m;
+      float av[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int kk = w * 16 + 4 * s + kq;
+        av[s] = (kk < Tce && ca < nc) ? W[kk * nc + ca] : 0.f;
+      }
+      floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc = mfma_16x16x4(av[s], bv[s], acc);
+      if (colok) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int c = ct * 16 + 4 * kq + v;
+          if (c >= nc) continue;
+          const int sidx = ax * n * nc + i * nc + c;
+          part_w[sidx] = accumulate ? part_w[sidx] + acc[v] : acc[v];
+        }
+      }
+    }
+  }
+}
+
+// Waves per window: enough (window, part) units for the block's waves, at most
+// kMaxParts and at most one part per 8-robot group.
+__device__ __forceinline__ int parts_per_window(int n, int nwin, int nwaves) {
+  int H = nwaves / max(nwin, 1);
+  H = min(H, kMaxParts);
+  H = min(H, (n + 7) >> 3);
+  return max(H, 1);
+}
+
+// ---------------------------------------------------------------------------
+// Coefficient-space stages.
+// ---------------------------------------------------------------------------
+
+// R = per-window partials summed in window order; lambda' = lambda - rho R;
+// u = lambda - 2 rho R into Ru; robot means of u (means[axis*nc + c]) and of xb
+// (means[2nc + axis*nc + c]).  One wave per column, lanes over robots.
+__device__ __forceinline__ void combine_lambda_means(const float* __restrict__ part, int nwin,
+                                                     int S, float* __restrict__ lam,
+                                                     float* __restrict__ Ru,
+                                                     const float* __restrict__ xb, int n, int nc,
+                                                     float rho, bool want_dz, float& dzsq,
+                                                     float* __restrict__ means, int wave,
+                                                     int nwaves, int lane) {
+  const float inv = 1.f / (float)n;
+  for (int col = wave; col < 4 * nc; col += nwaves) {
+    const bool ucol = col < 2 * nc;
+    const int cc = ucol ? col : col - 2 * nc;
+    const int ax = cc / nc, c = cc - ax * nc;
+    float acc = 0.f;
+    for (int i = lane; i < n; i += 64) {
+      const int sidx = ax * n * nc + i * nc + c;
+      if (ucol) {
+        float r = part[sidx];
+        for (int w = 1; w < nwin; ++w) r += part[(size_t)w * S + sidx];
+        const float lm = lam[sidx];
+        lam[sidx] = fmaf(-rho, r, lm);
+        const float u = fmaf(-2.f * rho, r, lm);
+        Ru[sidx] = u;
+        acc += u;
+        if (want_dz) dzsq = fmaf(rho * r, rho * r, dzsq);
+      } else {
+        acc += xb[sidx];
+      }
+    }
+    acc = wave_sum_dpp(acc);
+    if (lane == 0) means[col] = acc * inv;
+  }
+}
+
+// Robot means of the columns of one coefficient array (or two) into out.
+__device__ __forceinline__ void robot_means(const float* __restrict__ src0,
+                                            const float* __restrict__ src1, int n, int nc,
+                                            float* __restrict__ out, int wave, int nwaves,
+                                            int lane) {
+  const float inv = 1.f / (float)n;
+  const int cols = (src1 ? 4 : 2) * nc;
+  for (int col = wave; col < cols; col += nwaves) {
+    const float* src = col < 2 * nc ? src0 : src1;
+    const int cc = col < 2 * nc ? col : col - 2 * nc;
+    const int ax = cc / nc, c = cc - ax * nc;
+    const float* base = src + ax * n * nc + c;
+    float s = 0.f;
+    for (int i = lane; i < n; i += 64) s += base[i * nc];
+    s = wave_sum_dpp(s);
+    if (lane == 0) out[col] = s * inv;
+  }
+}
+
+// Mode operators on MFMA tiles (rows = robots, columns = coefficients):
+//   out[axis][i][c] = init + sum_q P0[c][q] Y0_i[q] + D0[c][q] Ym0[q]
+//                          (+ sum_q P1[c][q] Y1_i[q] + D1[c][q] Ym1[q])
+// with (P, D) pairs at fac + f0 and fac + f1 (D = P_par - P_perp), means
+// Ym[axis*nc + q]; `trans` applies P^T and D^T instead.  K runs over the
+// (Y, Ym[, Y1, Ym1]) blocks, nc each.  Calls emit(axis, i, c, value).
+template <typename Emit>
+__device__ __forceinline__ void mode_mfma(const float* __restrict__ fac, int nc, int n,
+                                          const float* __restrict__ Y0,
+                                          const float* __restrict__ Ym0, int f0,
+                                          const float* __restrict__ Y1,
+                                          const float* __restrict__ Ym1, int f1, bool trans,
+                                          const float* __restrict__ init, Emit emit, int wave,
+                                          int nwaves, int lane) {
+  const int nrt = (n + 15) >> 4, nct = (nc + 15) >> 4;
+  const int nc2 = nc * nc;
+  const int blocks = Y1 ? 4 : 2;
+  const int ks = (blocks * nc + 3) >> 2;
+  const int m = lane & 15, kq = lane >> 4;
+  for (int tile = wave; tile < 2 * nrt * nct; tile += nwaves) {
+    const int ax = tile / (nrt * nct);
+    const int rem = tile - ax * nrt * nct;
+    const int rt = rem / nct, ct = rem - rt * nct;
+    const int ia = rt * 16 + m;
+    const int cb = ct * 16 + m;
+    floatx4 acc;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int io = rt * 16 + 4 * kq + v;
+      acc[v] = (init && io < n && cb < nc) ? init[ax * n * nc + io * nc + cb] : 0.f;
+    }
+    for (int s = 0; s < ks; ++s) {
+      const int k = 4 * s + kq;
+      const int blk = (k >= nc) + (k >= 2 * nc) + (k >= 3 * nc);
+      const int q = k - blk * nc;
+      float a = 0.f, b = 0.f;
+      if (blk < blocks && cb < nc) {
+        const int fo = (blk < 2 ? f0 : f1) + (blk & 1) * nc2;
+        b = trans ? fac[fo + q * nc + cb] : fac[fo + cb * nc + q];
+      }
+      if (blk < blocks && ia < n) {
+        const float* Y = blk < 2 ? Y0 : Y1;
+        const float* Ym = blk < 2 ? Ym0 : Ym1;
+        a = (blk & 1) ? Ym[ax * nc + q] : Y[ax * n * nc + ia * nc + q];
+      }
+      acc = mfma_16x16x4(a, b, acc);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int io = rt * 16 + 4 * kq + v;
+      if (io < n && cb < nc) emit(ax, io, cb, acc[v]);
+    }
+  }
+}
+
+// Constant term c_xi = S xi + N b, mode form (first block of K^{-1} applied to
+// the xi and b parts of eta), one entry.  tgt: target xi, xm/bm: robot means of
+// xi ([2][nc]) and of b (bm[ax*2 + q]).
+__device__ __forceinline__ float cxi_entry(const float* __restrict__ fac, int nc,
+                                           const float* __restrict__ tgt,
+                                           const float* __restrict__ xm,
+                                           const float* __restrict__ bnd_i,
+                                           const float* __restrict__ bm, int n, int ax, int i,
+                                           int c) {
+  const int nc2 = nc * nc;
+  const float* Sp = fac + c * nc;
+  const float* DS = fac + nc2 + c * nc;
+  const float* Np = fac + 4 * nc2;
+  const float* DN = Np + 2 * nc;
+  const float* y = tgt + ax * n * nc + i * nc;
+  const float* ym = xm + ax * nc;
+  float out = 0.f;
+  for (int q = 0; q < nc; ++q) out = fmaf(Sp[q], y[q], fmaf(DS[q], ym[q], out));
+  for (int q = 0; q < 2; ++q) {
+    out = fmaf(Np[c * 2 + q], bnd_i[q * 2 + ax], out);
+    out = fmaf(DN[c * 2 + q], bm[ax * 2 + q], out);
+  }
+  return out;
+}
+
+// Robot means of the boundary positions into bm[ax*2 + q].
+__device__ __forceinline__ void boundary_means(const float* __restrict__ bnd, int n,
+                                               float* __restrict__ bm, int tid, int nthr) {
+  for (int t = tid; t < 4; t += nthr) {
+    const int ax = t >> 1, q = t & 1;
+    float s = 0.f;
+    for (int i = 0; i < n; ++i) s += bnd[i * 4 + q * 2 + ax];
+    bm[t] = s / (float)n;
+  }
+}
+
+// Pair/obstacle/box residual sums with every pair visited (plain path; global
+// memory, one thread per (robot, step)), in the culled stage's order.
+__device__ __forceinline__ void constraints_full(
+    const float2* __restrict__ X, float2* __restrict__ V, int n, int T,
+    const float* __restrict__ obs, int M, float a, float pmin0, float pmin1, float pmax0,
+    float pmax1, bool accum, float& r1sq, float& r2sq, int tid, int nthr) {
+  const float a2 = a * a;
+  for (int idx = tid; idx < n * T; idx += nthr) {
+    const int i = idx / T;
+    const int kk = idx - i * T;
+    const float2 p = X[i * T + kk];
+    float vx = 0.f, vy = 0.f, s1 = 0.f;
+    for (int j = 0; j < n; ++j) {
+      const float2 q = X[j * T + kk];
+      const float dx = p.x - q.x;
+      const float dy = p.y - q.y;
+      const float d2 = fmaf(dy, dy, dx * dx);
+      if (d2 < a2 && j != i) {
+        float rx, ry;
+        if (d2 > 0.f) {
+          const float f = 1.f - a * rsqrtf(d2);
+          rx = f * dx;
+          ry = f * dy;
+        } else {
+          rx = (i < j) ? -a : a;
+          ry = 0.f;
+        }
+        vx += rx;
+        vy += ry;
+        if (j > i) s1 = fmaf(rx, rx, fmaf(ry, ry, s1));
+      }
+    }
+    for (int m = 0; m < M; ++m) {
+      const float cx = obs[3 * m], cy = obs[3 * m + 1], ao = obs[3 * m + 2];
+      const float dx = p.x - cx;
+      const float dy = p.y - cy;
+      const float d2 = fmaf(dy, dy, dx * dx);
+      if (d2 < ao * ao) {
+        float rx, ry;
+        if (d2 > 0.f) {
+          const float f = 1.f - ao * rsqrtf(d2);
+          rx = f * dx;
+          ry = f * dy;
+        } else {
+          rx = -ao;
+          ry = 0.f;
+        }
+        vx += rx;
+        vy += ry;
+        s1 = fmaf(rx, rx, fmaf(ry, ry, s1));
+      }
+    }
+    const float hx = fmaxf(p.x - pmax0, 0.f), lx = fmaxf(pmin0 - p.x, 0.f);
+    const float hy = fmaxf(p.y - pmax1, 0.f), ly = fmaxf(pmin1 - p.y, 0.f);
+    vx = fmaf(1.f, hx - lx, 1.f * vx);
+    vy = fmaf(1.f, hy - ly, 1.f * vy);
+    if (accum) {
+      r1sq += s1;
+      r2sq += hx * hx + lx * lx + hy * hy + ly * ly;
+    }
+    V[i * T + kk] = make_float2(vx, vy);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused kernels: per-problem context and the block-level steps.
+// ---------------------------------------------------------------------------
+
+// Copy rows k0 .. k0+Tce-1 of W (global, [T][nc]) into the LDS table W.
+__device__ __forceinline__ void load_wchunk(const float* __restrict__ Wg, float* __restrict__ W,
+                                            int nc, int k0, int Tce, int tid, int nthr) {
+  for (int t = tid; t < Tce * nc; t += nthr) W[t] = Wg[k0 * nc + t];
+}
+
 struct Ctx {
   int n, M, nc, T, Tc, S, tid;
   float rho, a, pmin0, pmin1, pmax0, pmax1;
@@ -747,21 +702,14 @@ struct Ctx {
   const float4* obs;
   float4* box;
   u64* masks;
-  int n_max, M_max;
-  bool chunked;  // T > Tc: the LDS W tables hold one time chunk at a time
+  bool chunked;  // T > Tc: the LDS W table holds one time chunk at a time
 
-  __device__ __forceinline__ Geo geo(int k0) const {
-    Geo g;
-    g.Tce = min(Tc, T - k0);
-    g.Tcp = round16(g.Tce);
-    g.Tcs = tstride(Tc);
-    g.nws = g.Tcs / kWin;
-    g.pw = (n + 63) >> 6;
-    g.ow = (M + 63) >> 6;
-    return g;
-  }
+  __device__ __forceinline__ int Ts() const { return tstride(Tc); }
+  __device__ __forceinline__ int nws() const { return nwindows(Tc); }
+  __device__ __forceinline__ int pw() const { return (n + 63) >> 6; }
+  __device__ __forceinline__ int ow() const { return (M + 63) >> 6; }
 
-  // Make the LDS W tables hold rows k0 .. k0+Tce-1 (block-wide; no-op when
+  // Make the LDS W table hold rows k0 .. k0+Tce-1 (block-wide; no-op when
   // the whole horizon is resident).
   template <int NT>
   __device__ __forceinline__ void wchunk(int k0, int Tce) const {
@@ -770,81 +718,93 @@ struct Ctx {
     load_wchunk(Wg, W, nc, k0, Tce, tid, NT);
     __syncthreads();
   }
-
-  // X map, boxes and masks of one chunk into X (block-synchronised on return).
-  template <int NT>
-  __device__ __forceinline__ void positions(const float* xb, float2* X, const Geo& g) const {
-    stage_xmap_mfma(W, nc, xb, n, reinterpret_cast<float*>(X), g.Tce, g.Tcs,
-                    reinterpret_cast<float*>(box), g.nws, tid >> 6, NT >> 6, tid & 63);
-    __syncthreads();
-    stage_masks(box, n, obs, M, a, masks, g, tid, NT);
-    __syncthreads();
-  }
 };
 
-// Floats of the box and mask regions shared by both fused kernels.
-__host__ __device__ inline int box_floats(int Tc, int n_max) {
-  return 4 * n_max * (((Tc + 15) & ~15) / 16);
-}
-__host__ __device__ inline int mask_floats(int Tc, int n_max, int M_max) {
-  const int nws = ((Tc + 15) & ~15) / 16;
-  return 2 * n_max * nws * ((n_max + 63) / 64 + (M_max + 63) / 64);
-}
-
-// One application of T on the LDS state (xb, lam) -> (xn, lam).  Ru, X, V and
-// means are scratch.  Entered and left with the block synchronised.
+// One chunk of window units: positions, masks and the constraint stage of
+// every window (V = w_pair (pairs + obstacles) + w_box box), and with `part`
+// the windows' shares of W^T V into part[w][S] (added when `accumulate`).
+// Leaves the block synchronised.
 template <int NT>
-__device__ __forceinline__ void sf_iteration(const Ctx& C, const float* xb, float* xn, float* lam, float* Ru,
-                             float* means, float2* X, float2* V, const float* cx, bool last,
-                             float& dzsq, float* part) {
-  const int n = C.n, nc = C.nc, T = C.T, S = C.S, tid = C.tid;
-  float d1 = 0.f, d2 = 0.f;
-  for (int k0 = 0; k0 < T; k0 += C.Tc) {
-    const Geo g = C.geo(k0);
-    C.wchunk<NT>(k0, g.Tce);
-    C.positions<NT>(xb, X, g);
-    stage_constraints_culled(X, V, n, C.obs, C.masks, C.a, C.pmin0, C.pmin1, C.pmax0, C.pmax1,
-                             false, d1, d2, g, tid, NT);
-    __syncthreads();
-    stage_wtmap_part(C.W, nc, reinterpret_cast<const float*>(V), n, g.Tce, g.Tcs, part, S,
-                     k0 > 0, tid >> 6, NT >> 6, tid & 63);
-  }
-  __syncthreads();
-  combine_lambda_means(part, S, lam, Ru, xb, n, nc, C.rho, last, dzsq, means, tid, NT);
-  __syncthreads();
-  const int nc2 = nc * nc;
-  for (int s = tid; s < S; s += NT) {
-    const int ax = s / (n * nc), rem = s - ax * n * nc, i = rem / nc, c = rem - i * nc;
-    const int row = ax * n * nc + i * nc;
-    float v = mode_row(C.fac, C.fac + nc2, Ru + row, means + ax * nc, nc, c, cx[s]);
-    v = mode_row(C.fac + 2 * nc2, C.fac + 3 * nc2, xb + row, means + 2 * nc + ax * nc, nc, c,
-                 v);
-    xn[s] = v;
-    if (last) {
-      const float d = v - xb[s];
-      dzsq = fmaf(d, d, dzsq);
+__device__ __forceinline__ void chunk_units(const Ctx& C, int Tce, const float* xb, float2* X,
+                                            float2* V, float* part, bool accumulate, bool accum,
+                                            float& r1sq, float& r2sq, float w_pair,
+                                            float w_box) {
+  const int lane = C.tid & 63, wave = C.tid >> 6, nwaves = NT >> 6;
+  const int nwin = nwindows(Tce);
+  const int H = parts_per_window(C.n, nwin, nwaves);
+  const int Ts = C.Ts(), nws = C.nws(), pw = C.pw(), ow = C.ow();
+  for (int u = wave; u < nwin * H; u += nwaves) {
+    const int w = u / H, h = u - w * H;
+    xmap_window(C.W, C.nc, xb, C.n, reinterpret_cast<float*>(X), Ts, w, Tce,
+                reinterpret_cast<float*>(C.box), nws, lane);
+    wave_fence();
+    masks_window(C.box, C.n, C.obs, C.M, C.a, C.masks, nws, pw, ow, w, h, H, lane);
+    wave_fence();
+    constraints_window(X, V, C.n, Ts, C.obs, C.masks, nws, pw, ow, C.a, C.pmin0, C.pmin1,
+                       C.pmax0, C.pmax1, w, Tce, h, H, accum, r1sq, r2sq, w_pair, w_box, lane);
+    if (part) {
+      wave_fence();
+      wtmap_window(C.W, C.nc, reinterpret_cast<const float*>(V), C.n, Ts, w, Tce, h, H,
+                   part + (size_t)w * C.S, accumulate, lane);
     }
   }
+  __syncthreads();
+}
+
+// One application of T on the LDS state (xb, lam) -> (xn, lam).  Ru, X, V,
+// part and means are scratch.  Entered and left with the block synchronised.
+template <int NT>
+__device__ __forceinline__ void sf_iteration(const Ctx& C, const float* xb, float* xn,
+                                             float* lam, float* Ru, float* means, float2* X,
+                                             float2* V, float* part, const float* cx, bool last,
+                                             float& dzsq) {
+  const int lane = C.tid & 63, wave = C.tid >> 6, nwaves = NT >> 6;
+  float d1 = 0.f, d2 = 0.f;
+  for (int k0 = 0; k0 < C.T; k0 += C.Tc) {
+    const int Tce = min(C.Tc, C.T - k0);
+    C.wchunk<NT>(k0, Tce);
+    chunk_units<NT>(C, Tce, xb, X, V, part, k0 > 0, false, d1, d2, 1.f, 1.f);
+  }
+  combine_lambda_means(part, nwindows(min(C.Tc, C.T)), C.S, lam, Ru, xb, C.n, C.nc, C.rho,
+                       last, dzsq, means, wave, nwaves, lane);
+  __syncthreads();
+  const int n = C.n, nc = C.nc;
+  mode_mfma(
+      C.fac, nc, n, Ru, means, 0, xb, means + 2 * nc, 2 * nc * nc, false, cx,
+      [&](int ax, int i, int c, float v) {
+        const int s = ax * n * nc + i * nc + c;
+        xn[s] = v;
+        if (last) {
+          const float d = v - xb[s];
+          dzsq = fmaf(d, d, dzsq);
+        }
+      },
+      wave, nwaves, lane);
   __syncthreads();
 }
 
 // ||r_1||^2 and ||r_2||^2 partials of the iterate xb (block-synchronised on
 // return); V is scratch.
 template <int NT>
-__device__ __forceinline__ void residual_norms(const Ctx& C, const float* xb, float2* X, float2* V, float& r1sq,
-                               float& r2sq) {
+__device__ __forceinline__ void residual_norms(const Ctx& C, const float* xb, float2* X,
+                                               float2* V, float& r1sq, float& r2sq) {
   for (int k0 = 0; k0 < C.T; k0 += C.Tc) {
-    const Geo g = C.geo(k0);
-    C.wchunk<NT>(k0, g.Tce);
-    C.positions<NT>(xb, X, g);
-    stage_constraints_culled(X, V, C.n, C.obs, C.masks, C.a, C.pmin0, C.pmin1, C.pmax0,
-                             C.pmax1, true, r1sq, r2sq, g, C.tid, NT);
-    __syncthreads();
+    const int Tce = min(C.Tc, C.T - k0);
+    C.wchunk<NT>(k0, Tce);
+    chunk_units<NT>(C, Tce, xb, X, V, nullptr, false, true, r1sq, r2sq, 1.f, 1.f);
   }
 }
 
+// LDS floats of the box and mask regions.
+__host__ __device__ inline int box_floats(int Tc, int n_max) {
+  return 4 * n_max * nwindows(Tc);
+}
+__host__ __device__ inline int mask_floats(int Tc, int n_max, int M_max) {
+  return 2 * n_max * nwindows(Tc) * ((n_max + 63) / 64 + (M_max + 63) / 64);
+}
+
 struct FwdLds {
-  float *W, *fac, *xbA, *xbB, *lam, *cx, *Ru, *means, *red, *part;
+  float *W, *fac, *xbA, *xbB, *lam, *cx, *Ru, *part, *means, *red;
   float4* obs;
   float4* box;
   u64* masks;
@@ -862,7 +822,7 @@ __device__ __forceinline__ FwdLds carve_fwd(float* sm, int nc, int Tc, int n_max
   L.lam = p; p += round4(S_max);
   L.cx = p; p += round4(S_max);
   L.Ru = p; p += round4(S_max);
-  L.part = p; p += kSplitMax * round4(S_max);
+  L.part = p; p += nwindows(Tc) * round4(S_max);
   L.means = p; p += kMeans;
   L.red = p; p += kRed;
   L.obs = reinterpret_cast<float4*>(p); p += 4 * M_max;
@@ -877,10 +837,9 @@ __device__ __forceinline__ FwdLds carve_fwd(float* sm, int nc, int Tc, int n_max
 
 size_t fwd_lds_bytes(int nc, int T, int Tc, int n_max, int M_max, int S_max, int) {
   auto r4 = [](int x) { return (size_t)((x + 3) & ~3); };
-  const size_t Tcs = tstride(Tc);
-  size_t f = r4(nc * Tc) + r4(fac_stride(nc)) + (5 + kSplitMax) * r4(S_max) + kMeans + kRed +
+  size_t f = r4(nc * Tc) + r4(fac_stride(nc)) + (5 + nwindows(Tc)) * r4(S_max) + kMeans + kRed +
              4 * (size_t)M_max + box_floats(Tc, n_max) + mask_floats(Tc, n_max, M_max) +
-             4 * (size_t)n_max * Tcs;
+             4 * (size_t)n_max * tstride(Tc);
   return f * sizeof(float);
 }
 
@@ -899,9 +858,8 @@ __global__ __launch_bounds__(NT) void fwd_fused_kernel(FwdArgs A) {
   const int S = 2 * n * nc;
   const int fs = fac_stride(nc);
   FwdLds L = carve_fwd(sm, nc, A.Tc, A.n_max, A.M_max, A.S_max);
-  Ctx C{n,         M,         nc,        T,         A.Tc, S,   tid,   A.rho, P.a,
-        P.pmin[0], P.pmin[1], P.pmax[0], P.pmax[1], L.W, L.fac, A.W,   L.obs,
-        L.box,     L.masks,   A.n_max,   A.M_max,   A.Tc < T};
+  Ctx C{n,         M,         nc,        T,   A.Tc,  S,   tid,   A.rho, P.a,     P.pmin[0],
+        P.pmin[1], P.pmax[0], P.pmax[1], L.W, L.fac, A.W, L.obs, L.box, L.masks, A.Tc < T};
   if (!C.chunked) load_wchunk(A.W, L.W, nc, 0, T, tid, NT);
   for (int t = tid; t < fs; t += NT) L.fac[t] = A.fac[(size_t)P.fac * fs + t];
   for (int m = tid; m < M; m += NT) {
@@ -921,7 +879,7 @@ __global__ __launch_bounds__(NT) void fwd_fused_kernel(FwdArgs A) {
   }
   __syncthreads();
   const float* bnd = A.boundary + (size_t)P.rob_off * 4;
-  robot_means(L.Ru, nullptr, n, nc, L.means, tid, NT);
+  robot_means(L.Ru, nullptr, n, nc, L.means, tid >> 6, NT >> 6, tid & 63);
   boundary_means(bnd, n, L.means + 2 * nc, tid, NT);
   __syncthreads();
   for (int s = tid; s < S; s += NT) {
@@ -944,8 +902,8 @@ __global__ __launch_bounds__(NT) void fwd_fused_kernel(FwdArgs A) {
         ck[A.S_total + s] = L.lam[s];
       }
     }
-    sf_iteration<NT>(C, xb, xn, L.lam, L.Ru, L.means, L.X, L.V, L.cx, l == A.L - 1, dzsq,
-                     L.part);
+    sf_iteration<NT>(C, xb, xn, L.lam, L.Ru, L.means, L.X, L.V, L.part, L.cx, l == A.L - 1,
+                     dzsq);
     float* t = xb;
     xb = xn;
     xn = t;
@@ -1025,7 +983,7 @@ __device__ __forceinline__ BwdLds carve_bwd(float* sm, int nc, int Tc, int n_max
     *bufs[q] = p;
     p += round4(S_max);
   }
-  L.part = p; p += kSplitMax * round4(S_max);
+  L.part = p; p += nwindows(Tc) * round4(S_max);
   L.obs = reinterpret_cast<float4*>(p); p += 4 * M_max;
   L.box = reinterpret_cast<float4*>(p); p += box_floats(Tc, n_max);
   L.masks = reinterpret_cast<u64*>(p); p += mask_floats(Tc, n_max, M_max);
@@ -1035,11 +993,22 @@ __device__ __forceinline__ BwdLds carve_bwd(float* sm, int nc, int Tc, int n_max
   return L;
 }
 
+// g[s] += sum of the per-window partials part[w][s] (w < nwin, window order).
+__device__ __forceinline__ void add_partials(float* __restrict__ g, const float* __restrict__ part,
+                                             int nwin, int S, int tid, int nthr) {
+  for (int s = tid; s < S; s += nthr) {
+    float r = part[s];
+    for (int w = 1; w < nwin; ++w) r += part[(size_t)w * S + s];
+    g[s] += r;
+  }
+}
+
 template <int NT>
 __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
   extern __shared__ float4 sm4[];
   float* sm = reinterpret_cast<float*>(sm4);
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6, nwaves = NT >> 6;
   const int b = A.order[blockIdx.x];
   const ProbDesc P = A.probs[b];
   const int n = P.n, M = P.M, nc = A.nc, T = A.T, Tc = A.Tc;
@@ -1049,9 +1018,10 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
   const float rho = A.rho, w = A.fp_weight;
   const size_t St = (size_t)A.S_total;
   BwdLds L = carve_bwd(sm, nc, Tc, A.n_max, A.M_max, A.S_max);
-  Ctx C{n,         M,         nc,        T,         Tc,   S,   tid,   rho, P.a,
-        P.pmin[0], P.pmin[1], P.pmax[0], P.pmax[1], L.W, L.fac, A.W, L.obs,
-        L.box,     L.masks,   A.n_max,   A.M_max,   Tc < T};
+  Ctx C{n,         M,         nc,        T,   Tc,    S,   tid,   rho,   P.a,     P.pmin[0],
+        P.pmin[1], P.pmax[0], P.pmax[1], L.W, L.fac, A.W, L.obs, L.box, L.masks, Tc < T};
+  const int nwin0 = nwindows(min(Tc, T));
+  const int Ts = C.Ts(), nws = C.nws(), pw = C.pw(), ow = C.ow();
   if (!C.chunked) load_wchunk(A.W, L.W, nc, 0, T, tid, NT);
   for (int t = tid; t < fs; t += NT) L.fac[t] = A.fac[(size_t)P.fac * fs + t];
   for (int m = tid; m < M; m += NT) {
@@ -1081,23 +1051,20 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
     block_sum(v, L.red);
     const float c1 = v[0] > 0.f ? gr1 / sqrtf(v[0]) : 0.f;
     const float c2 = v[1] > 0.f ? gr2 / sqrtf(v[1]) : 0.f;
-    float d1 = 0.f, d2 = 0.f, dz = 0.f;
+    float d1 = 0.f, d2 = 0.f;
     for (int k0 = 0; k0 < T; k0 += Tc) {
-      const Geo g = C.geo(k0);
-      C.wchunk<NT>(k0, g.Tce);
-      C.positions<NT>(L.b0, L.X, g);
-      stage_constraints_culled(L.X, L.H, n, L.obs, L.masks, P.a, P.pmin[0], P.pmin[1],
-                               P.pmax[0], P.pmax[1], false, d1, d2, g, tid, NT, c1, c2);
-      __syncthreads();
-      stage_wtmap_mfma(L.W, nc, reinterpret_cast<const float*>(L.H), n, g.Tce, g.Tcs, gx, true,
-                       nullptr, 0.f, false, dz, tid >> 6, NT >> 6, tid & 63);
+      const int Tce = min(Tc, T - k0);
+      C.wchunk<NT>(k0, Tce);
+      chunk_units<NT>(C, Tce, L.b0, L.X, L.H, L.part, k0 > 0, false, d1, d2, c1, c2);
     }
+    add_partials(gx, L.part, nwin0, S, tid, NT);
     __syncthreads();
   }
 
   const int L_ = A.L, k = A.ckpt_every;
   const int nseg = (L_ + k - 1) / k;
   float dz = 0.f;
+  bool pending = false;   // L.part holds W^T VJP partials not yet added to gx
   for (int seg = nseg - 1; seg >= 0; --seg) {
     const int l0 = seg * k;
     const int l1 = min(L_, l0 + k);
@@ -1114,9 +1081,14 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
         sg[s] = x;
         sg[St + s] = lm;
       }
+      if (pending && l1 - 1 > l0) {
+        // the recompute reuses the partial buffer: fold it into gx first
+        add_partials(gx, L.part, nwin0, S, tid, NT);
+        pending = false;
+      }
       __syncthreads();
       for (int l = l0; l < l1 - 1; ++l) {
-        sf_iteration<NT>(C, xr, xq, L.b2, L.b3, L.means, L.X, L.G, L.cx, false, dz, L.part);
+        sf_iteration<NT>(C, xr, xq, L.b2, L.b3, L.means, L.X, L.G, L.part, L.cx, false, dz);
         float* t = xr;
         xr = xq;
         xq = t;
@@ -1139,49 +1111,74 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
       for (int s = tid; s < S; s += NT) {
         const float xl = cur[s];
         xbl[s] = xl;
+        float g = gx[s];
+        if (pending) {
+          float r = L.part[s];
+          for (int ww = 1; ww < nwin0; ++ww) r += L.part[(size_t)ww * S + s];
+          g += r;
+        }
         if (w != 0.f) {
           const float dxi = nxt[s] - xl;
           const float dla = nxt[St + s] - cur[St + s];
-          gx[s] = fmaf(2.f * w, dxi, gx[s]);
+          g = fmaf(2.f * w, dxi, g);
           fpx[s] = -2.f * w * dxi;
           gR[s] = -2.f * rho * w * dla;
         } else {
           fpx[s] = 0.f;
           gR[s] = 0.f;
         }
+        gx[s] = g;
       }
+      pending = false;
       __syncthreads();
-      robot_means(gx, nullptr, n, nc, L.means, tid, NT);
+      robot_means(gx, nullptr, n, nc, L.means, wave, nwaves, lane);
       __syncthreads();
-      for (int s = tid; s < S; s += NT) {
-        const int ax = s / (n * nc), rem = s - ax * n * nc, i = rem / nc, c = rem - i * nc;
-        const int row = ax * n * nc + i * nc;
-        const float gu =
-            mode_row_t(L.fac, L.fac + nc2, gx + row, L.means + ax * nc, nc, c, 0.f);
-        gn[s] = mode_row_t(L.fac + 2 * nc2, L.fac + 3 * nc2, gx + row, L.means + ax * nc, nc,
-                           c, fpx[s]);
-        gR[s] = fmaf(-2.f * rho, gu, fmaf(-rho, L.glam[s], gR[s]));
-        L.glam[s] += gu;
-        L.gxi[s] += gu;
-      }
+      // g_u = S^T g (mode form) feeds g_R, g_lambda and g_xi; g' = SH^T g + fp term
+      mode_mfma(
+          L.fac, nc, n, gx, L.means, 0, nullptr, nullptr, 0, true, nullptr,
+          [&](int ax, int i, int c, float gu) {
+            const int s = ax * n * nc + i * nc + c;
+            gR[s] = fmaf(-2.f * rho, gu, fmaf(-rho, L.glam[s], gR[s]));
+            L.glam[s] += gu;
+            L.gxi[s] += gu;
+          },
+          wave, nwaves, lane);
+      mode_mfma(
+          L.fac, nc, n, gx, L.means, 2 * nc2, nullptr, nullptr, 0, true, fpx,
+          [&](int ax, int i, int c, float v) { gn[ax * n * nc + i * nc + c] = v; }, wave,
+          nwaves, lane);
       __syncthreads();
       for (int k0 = 0; k0 < T; k0 += Tc) {
-        const Geo g = C.geo(k0);
-        C.wchunk<NT>(k0, g.Tce);
-        stage_xmap_mfma(L.W, nc, gR, n, reinterpret_cast<float*>(L.G), g.Tce, g.Tcs, nullptr, 0,
-                        tid >> 6, NT >> 6, tid & 63);
-        C.positions<NT>(xbl, L.X, g);
-        stage_vjp_culled(L.X, L.G, L.H, n, L.obs, L.masks, P.a, P.pmin[0], P.pmin[1],
-                         P.pmax[0], P.pmax[1], g, tid, NT);
+        const int Tce = min(Tc, T - k0);
+        C.wchunk<NT>(k0, Tce);
+        const int nwin = nwindows(Tce);
+        const int Hp = parts_per_window(n, nwin, nwaves);
+        for (int u = wave; u < nwin * Hp; u += nwaves) {
+          const int wn = u / Hp, h = u - wn * Hp;
+          xmap_window(L.W, nc, xbl, n, reinterpret_cast<float*>(L.X), Ts, wn, Tce,
+                      reinterpret_cast<float*>(L.box), nws, lane);
+          xmap_window(L.W, nc, gR, n, reinterpret_cast<float*>(L.G), Ts, wn, Tce, nullptr, nws,
+                      lane);
+          wave_fence();
+          masks_window(L.box, n, L.obs, M, P.a, L.masks, nws, pw, ow, wn, h, Hp, lane);
+          wave_fence();
+          vjp_window(L.X, L.G, L.H, n, Ts, L.obs, L.masks, nws, pw, ow, P.a, P.pmin[0],
+                     P.pmin[1], P.pmax[0], P.pmax[1], wn, Tce, h, Hp, lane);
+          wave_fence();
+          wtmap_window(L.W, nc, reinterpret_cast<const float*>(L.H), n, Ts, wn, Tce, h, Hp,
+                       L.part + (size_t)wn * S, k0 > 0, lane);
+        }
         __syncthreads();
-        stage_wtmap_mfma(L.W, nc, reinterpret_cast<const float*>(L.H), n, g.Tce, g.Tcs, gn,
-                         true, nullptr, 0.f, false, dz, tid >> 6, NT >> 6, tid & 63);
       }
-      __syncthreads();
+      pending = true;
       float* t = gx;
       gx = gn;
       gn = t;
     }
+  }
+  if (pending) {
+    add_partials(gx, L.part, nwin0, S, tid, NT);
+    __syncthreads();
   }
   for (int s = tid; s < S; s += NT) {
     if (A.g_xi0) A.g_xi0[P.coef_off + s] = gx[s];
@@ -1194,10 +1191,9 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
 
 size_t bwd_lds_bytes(int nc, int T, int Tc, int n_max, int M_max, int S_max, int) {
   auto r4 = [](int x) { return (size_t)((x + 3) & ~3); };
-  const size_t Tcs = tstride(Tc);
-  size_t f = r4(nc * Tc) + r4(fac_stride(nc)) + kRed + kMeans + (9 + kSplitMax) * r4(S_max) +
+  size_t f = r4(nc * Tc) + r4(fac_stride(nc)) + kRed + kMeans + (9 + nwindows(Tc)) * r4(S_max) +
              4 * (size_t)M_max + box_floats(Tc, n_max) + mask_floats(Tc, n_max, M_max) +
-             6 * (size_t)n_max * Tcs;
+             6 * (size_t)n_max * tstride(Tc);
   return f * sizeof(float);
 }
 
@@ -1237,7 +1233,8 @@ hipError_t prepare_kernels(size_t lds) {
 // ---------------------------------------------------------------------------
 // Plain path: the same steps as separate kernels over global memory, one
 // problem per launch and every pair visited (the per-problem baseline the
-// fused launch is compared with).
+// fused launch is compared with).  Blocks of 256 threads; map kernels give one
+// window per wave.
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -1248,7 +1245,7 @@ __global__ __launch_bounds__(256) void plain_prep_kernel(FwdArgs A, PlainBufs Bf
   const float* fac = A.fac + (size_t)P.fac * fac_stride(nc);
   const float* tgt = A.xi + P.coef_off;
   const float* bnd = A.boundary + (size_t)P.rob_off * 4;
-  robot_means(tgt, nullptr, n, nc, means, tid, 256);
+  robot_means(tgt, nullptr, n, nc, means, tid >> 6, 4, tid & 63);
   boundary_means(bnd, n, means + 2 * nc, tid, 256);
   __syncthreads();
   for (int s = tid; s < S; s += 256) {
@@ -1260,12 +1257,14 @@ __global__ __launch_bounds__(256) void plain_prep_kernel(FwdArgs A, PlainBufs Bf
   }
 }
 
+// Positions of every window (one window per wave).
 __global__ __launch_bounds__(256) void plain_xmap_kernel(FwdArgs A, PlainBufs Bf, int b,
                                                          int pp) {
   const ProbDesc P = A.probs[b];
-  stage_xmap_mfma(A.W, A.nc, Bf.xb[pp] + P.coef_off, P.n, Bf.X + (size_t)P.pos_off * 2, A.T,
-                  A.T, nullptr, 0, blockIdx.x * 4 + (threadIdx.x >> 6), gridDim.x * 4,
-                  threadIdx.x & 63);
+  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= nwindows(A.T)) return;
+  xmap_window(A.W, A.nc, Bf.xb[pp] + P.coef_off, P.n, Bf.X + (size_t)P.pos_off * 2, A.T, w, A.T,
+              nullptr, 0, threadIdx.x & 63);
 }
 
 __global__ __launch_bounds__(256) void plain_constraint_kernel(FwdArgs A, PlainBufs Bf,
@@ -1273,26 +1272,31 @@ __global__ __launch_bounds__(256) void plain_constraint_kernel(FwdArgs A, PlainB
   const ProbDesc P = A.probs[b];
   const int tid = blockIdx.x * 256 + threadIdx.x;
   float d1 = 0.f, d2 = 0.f;
-  stage_constraints(reinterpret_cast<const float2*>(Bf.X) + P.pos_off,
-                    reinterpret_cast<float2*>(Bf.V) + P.pos_off, P.n, A.T, A.T,
-                    A.obstacles + (size_t)P.obs_off * 3, P.M, P.a, P.pmin[0], P.pmin[1],
-                    P.pmax[0], P.pmax[1], false, d1, d2, tid, gridDim.x * 256);
+  constraints_full(reinterpret_cast<const float2*>(Bf.X) + P.pos_off,
+                   reinterpret_cast<float2*>(Bf.V) + P.pos_off, P.n, A.T,
+                   A.obstacles + (size_t)P.obs_off * 3, P.M, P.a, P.pmin[0], P.pmin[1],
+                   P.pmax[0], P.pmax[1], false, d1, d2, tid, gridDim.x * 256);
 }
 
+// Per-window partials of W^T V (one window per wave, all column tiles).
 __global__ __launch_bounds__(256) void plain_wtmap_kernel(FwdArgs A, PlainBufs Bf, int b) {
   const ProbDesc P = A.probs[b];
+  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= nwindows(A.T)) return;
   const int S = 2 * P.n * A.nc;
-  stage_wtmap_part(A.W, A.nc, Bf.V + (size_t)P.pos_off * 2, P.n, A.T, A.T,
-                   Bf.part + (size_t)kSplitMax * P.coef_off, S, false,
-                   blockIdx.x * 4 + (threadIdx.x >> 6), gridDim.x * 4, threadIdx.x & 63);
+  wtmap_window(A.W, A.nc, Bf.V + (size_t)P.pos_off * 2, P.n, A.T, w, A.T, 0, 1,
+               Bf.part + (size_t)nwindows(A.T) * P.coef_off + (size_t)w * S, false,
+               threadIdx.x & 63);
 }
 
+// Combine, lambda step, means and the xi_bar step (one block).
 __global__ __launch_bounds__(256) void plain_update_kernel(FwdArgs A, PlainBufs Bf, int b,
                                                            int pp, int last) {
   __shared__ float means[kMeans];
   __shared__ float red[kRed];
   const ProbDesc P = A.probs[b];
-  const int n = P.n, nc = A.nc, S = 2 * n * nc, tid = threadIdx.x, nc2 = nc * nc;
+  const int n = P.n, nc = A.nc, S = 2 * n * nc, tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const float rho = A.rho;
   const float* fac = A.fac + (size_t)P.fac * fac_stride(nc);
   float* R = Bf.R + P.coef_off;
@@ -1301,20 +1305,20 @@ __global__ __launch_bounds__(256) void plain_update_kernel(FwdArgs A, PlainBufs 
   float* xn = Bf.xb[pp ^ 1] + P.coef_off;
   const float* cx = Bf.cxi + P.coef_off;
   float dzsq = 0.f;
-  combine_lambda_means(Bf.part + (size_t)kSplitMax * P.coef_off, S, lam, R, xb, n, nc, rho,
-                       last, dzsq, means, tid, 256);
+  combine_lambda_means(Bf.part + (size_t)nwindows(A.T) * P.coef_off, nwindows(A.T), S, lam, R,
+                       xb, n, nc, rho, last, dzsq, means, wave, 4, lane);
   __syncthreads();
-  for (int s = tid; s < S; s += 256) {
-    const int ax = s / (n * nc), rem = s - ax * n * nc, i = rem / nc, c = rem - i * nc;
-    const int row = ax * n * nc + i * nc;
-    float v = mode_row(fac, fac + nc2, R + row, means + ax * nc, nc, c, cx[s]);
-    v = mode_row(fac + 2 * nc2, fac + 3 * nc2, xb + row, means + 2 * nc + ax * nc, nc, c, v);
-    xn[s] = v;
-    if (last) {
-      const float d = v - xb[s];
-      dzsq = fmaf(d, d, dzsq);
-    }
-  }
+  mode_mfma(
+      fac, nc, n, R, means, 0, xb, means + 2 * nc, 2 * nc * nc, false, cx,
+      [&](int ax, int i, int c, float v) {
+        const int s = ax * n * nc + i * nc + c;
+        xn[s] = v;
+        if (last) {
+          const float d = v - xb[s];
+          dzsq = fmaf(d, d, dzsq);
+        }
+      },
+      wave, 4, lane);
   if (last) {
     float v[1] = {dzsq};
     block_sum(v, red);
@@ -1328,10 +1332,10 @@ __global__ __launch_bounds__(256) void plain_final_kernel(FwdArgs A, PlainBufs B
   const ProbDesc P = A.probs[b];
   const int n = P.n, nc = A.nc, S = 2 * n * nc, tid = threadIdx.x;
   float r1sq = 0.f, r2sq = 0.f, bad = 0.f;
-  stage_constraints(reinterpret_cast<const float2*>(Bf.X) + P.pos_off,
-                    reinterpret_cast<float2*>(Bf.V) + P.pos_off, n, A.T, A.T,
-                    A.obstacles + (size_t)P.obs_off * 3, P.M, P.a, P.pmin[0], P.pmin[1],
-                    P.pmax[0], P.pmax[1], true, r1sq, r2sq, tid, 256);
+  constraints_full(reinterpret_cast<const float2*>(Bf.X) + P.pos_off,
+                   reinterpret_cast<float2*>(Bf.V) + P.pos_off, n, A.T,
+                   A.obstacles + (size_t)P.obs_off * 3, P.M, P.a, P.pmin[0], P.pmin[1],
+                   P.pmax[0], P.pmax[1], true, r1sq, r2sq, tid, 256);
   for (int s = tid; s < S; s += 256) {
     const float x = Bf.xb[pp][P.coef_off + s], lm = Bf.lam[P.coef_off + s];
     A.xi_out[P.coef_off + s] = x;
@@ -1356,25 +1360,24 @@ __global__ void fill_kernel(float* p, float v, int64_t n) {
 
 }  // namespace
 
+size_t plain_part_floats(int T, int64_t coef) { return (size_t)nwindows(T) * (size_t)coef; }
+
 hipError_t launch_plain_problem(const FwdArgs& a, const PlainBufs& pb, int b, hipStream_t s) {
   // grids sized for the batch's largest problem; the kernels stride over the
   // items of problem b
-  const int tiles_x = ((a.T + 15) / 16) * ((2 * a.n_max + 15) / 16);
-  const int tiles_w = ((a.nc + 15) / 16) * ((2 * a.n_max + 15) / 16) * kSplitMax;
-  const int gx = (tiles_x + 3) / 4;             // four waves per block, a tile per wave
-  const int gw = (tiles_w + 3) / 4;
+  const int gw = (nwindows(a.T) + 3) / 4;     // four waves per block, a window per wave
   const int gc = (a.n_max * a.T + 255) / 256;
   hipLaunchKernelGGL(plain_prep_kernel, dim3(1), dim3(256), 0, s, a, pb, b);
   int pp = 0;
   for (int l = 0; l < a.L; ++l) {
-    hipLaunchKernelGGL(plain_xmap_kernel, dim3(gx), dim3(256), 0, s, a, pb, b, pp);
+    hipLaunchKernelGGL(plain_xmap_kernel, dim3(gw), dim3(256), 0, s, a, pb, b, pp);
     hipLaunchKernelGGL(plain_constraint_kernel, dim3(gc), dim3(256), 0, s, a, pb, b);
     hipLaunchKernelGGL(plain_wtmap_kernel, dim3(gw), dim3(256), 0, s, a, pb, b);
     hipLaunchKernelGGL(plain_update_kernel, dim3(1), dim3(256), 0, s, a, pb, b, pp,
                        (int)(l == a.L - 1));
     pp ^= 1;
   }
-  hipLaunchKernelGGL(plain_xmap_kernel, dim3(gx), dim3(256), 0, s, a, pb, b, pp);
+  hipLaunchKernelGGL(plain_xmap_kernel, dim3(gw), dim3(256), 0, s, a, pb, b, pp);
   hipLaunchKernelGGL(plain_final_kernel, dim3(1), dim3(256), 0, s, a, pb, b, pp);
   return hipGetLastError();
 }
