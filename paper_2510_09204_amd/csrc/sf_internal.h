@@ -100,7 +100,7 @@ hipError_t launch_bwd_fused(const BwdArgs& a, int threads, size_t lds, hipStream
 struct PlainBufs {
   float* X;      // [sum n][T][2] positions
   float* V;      // [sum n][T][2] constraint sums
-  float* R;      // coefficient layout
+  float* R;      // coefficient layout: lambda of odd iterations (ping-pong with lam)
   float* xb[2];  // ping-pong xi_bar, coefficient layout
   float* lam;    // coefficient layout
   float* cxi;    // coefficient layout

@@ -24,12 +24,20 @@
 // the coefficient->time map of the window for all robots on MFMA (16x16x4 FP32
 // tiles; the per-window bounding box of every robot falls out of the tile),
 // candidate masks for its robots (a pair or obstacle is a candidate when the
-// boxes come within the constraint distance plus a rounding margin), the exact
-// pair/obstacle/box stage over candidates, and the window's share of the
-// time->coefficient map R = W^T V on MFMA into a per-window partial.  Skipped
-// pairs are inactive at every step of the window and contribute exactly 0.
-// The partials are summed in window order, so every launch shape gives the
-// same bits.  Coefficient updates are MFMA tiles as well.
+// boxes come within the constraint distance plus a rounding margin; lane j
+// tests robot j and a ballot forms the mask), the exact pair/obstacle/box
+// stage over candidates (a 16-lane row per robot walking its own list), and
+// the window's share of the time->coefficient map R = W^T V on MFMA into a
+// per-window partial.  Skipped pairs are inactive at every step of the window
+// and contribute exactly 0.  The partials are summed in window order, so every
+// launch shape gives the same bits.
+//
+// The coefficient update is a set of MFMA tiles (axis x 16 robots x 16
+// coefficients), one per wave: the wave forms its A operand u = lambda -
+// 2 rho R straight from the partials, multiplies by the mode blocks, and gets
+// the robot-mean term as column sums of a second accumulator (lane swaps),
+// exchanged between row tiles through LDS.  Three block barriers per
+// iteration: after the window units, after the column sums, after the update.
 //
 // Data layout: coefficient arrays [axis][robot][coef]; positions and
 // constraint sums [robot][time] as float2 (x, y) with an odd row stride
@@ -61,6 +69,15 @@ __host__ __device__ __forceinline__ int nwindows(int Tc) { return (Tc + 15) >> 4
 // B[l/16][l%16] and holds D[4(l/16)+v][l%16] in element v.
 __device__ __forceinline__ floatx4 mfma_16x16x4(float a, float b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// The lane index through an empty asm statement: values derived from it are
+// recomputed where used instead of being hoisted out of the iteration loop
+// and kept live (and spilled) across it.
+__device__ __forceinline__ int lane_here(int tid) {
+  int l = tid & 63;
+  asm volatile("" : "+v"(l));
+  return l;
 }
 
 // Orders the LDS accesses of one wave (its stores before its later loads).
@@ -100,11 +117,28 @@ __device__ __forceinline__ unsigned quad_or(unsigned v) {
   return v;
 }
 
-__device__ __forceinline__ u64 readlane64(u64 v, int lane) {
-  const unsigned lo = __builtin_amdgcn_readlane((unsigned)v, lane);
-  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(v >> 32), lane);
-  return ((u64)hi << 32) | lo;
+// Combine the four 16-lane rows of a wave column-wise (lanes m, m+16, m+32,
+// m+48): lanes l and l^32 first, then l and l^16, through the gfx950 lane-swap
+// instructions (VALU, no LDS trip).  Every lane gets the result; the order of
+// the operations is the same in every lane (op is commutative).
+template <typename Op>
+__device__ __forceinline__ float rows_reduce(float v, Op op) {
+  const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false,
+                                                  false);
+  v = op(__uint_as_float(p[0]), __uint_as_float(p[1]));
+  const auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false,
+                                                  false);
+  return op(__uint_as_float(q[0]), __uint_as_float(q[1]));
 }
+struct OpAdd {
+  __device__ float operator()(float a, float b) const { return a + b; }
+};
+struct OpMin {
+  __device__ float operator()(float a, float b) const { return fminf(a, b); }
+};
+struct OpMax {
+  __device__ float operator()(float a, float b) const { return fmaxf(a, b); }
+};
 
 // Deterministic block sum of up to 4 values: wave sums, then a fixed-order
 // pass over the per-wave partials.  All threads get the totals.
@@ -140,184 +174,217 @@ __device__ __forceinline__ int part_robot(int t, int h, int H) {
   return ((t >> 3) * H + h) * 8 + (t & 7);
 }
 
+// Robots in part h (h < number of 8-robot groups).
+__device__ __forceinline__ int part_count(int n, int h, int H) {
+  const int ng = (n + 7) >> 3;
+  const int mine = (ng - h + H - 1) / H;
+  int cnt = 8 * mine;
+  if ((ng - 1) % H == h) cnt -= 8 * ng - n;
+  return cnt;
+}
+
 // Coefficient -> time map of window w for all robots: X[i][16w + r].axis =
 // sum_c W[16w + r][c] xb[axis][i][c] for steps < Tce (padding rows repeat the
-// last step), and with `boxf` each robot's box (xmin, xmax, ymin, ymax) over
-// the window's steps.
+// last step), and with BOX each robot's box (xmin, xmax, ymin, ymax) over the
+// window's steps.  Column tiles are taken four at a time with all their
+// operand loads issued before the MFMA chains.
+template <int KS, bool BOX>
 __device__ __forceinline__ void xmap_window(const float* __restrict__ W, int nc,
                                             const float* __restrict__ xb, int n,
                                             float* __restrict__ Xf, int Ts, int w, int Tce,
                                             float* __restrict__ boxf, int nws, int lane) {
   const int ncol = (2 * n + 15) >> 4;
-  const int ks = (nc + 3) >> 2;
   const int m = lane & 15, kq = lane >> 4;
   const int row = min(w * 16 + m, Tce - 1);
-  float av[kMaxCoef / 4];
+  float av[KS];
 #pragma unroll
-  for (int s = 0; s < kMaxCoef / 4; ++s) {
+  for (int s = 0; s < KS; ++s) {
     const int c = 4 * s + kq;
-    av[s] = (s < ks && c < nc) ? W[row * nc + c] : 0.f;
+    const float v = W[row * nc + min(c, nc - 1)];
+    av[s] = c < nc ? v : 0.f;
   }
   const int k0 = w * 16 + 4 * kq;
-  for (int nt = 0; nt < ncol; ++nt) {
-    const int col = nt * 16 + m;
-    const int i = col >> 1, ax = col & 1;
-    const bool colok = i < n;
-    const float* brow = xb + ax * n * nc + (colok ? i : 0) * nc;
-    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+  for (int nt0 = 0; nt0 < ncol; nt0 += 4) {
+    float bv[4][KS];
 #pragma unroll
-    for (int s = 0; s < kMaxCoef / 4; ++s) {
-      if (s < ks) {
+    for (int g = 0; g < 4; ++g) {
+      const int col = (nt0 + g) * 16 + m;
+      const bool ok = (col >> 1) < n;
+      const int i = min(col >> 1, n - 1), ax = col & 1;
+      const float* brow = xb + ax * n * nc + i * nc;
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
         const int c = 4 * s + kq;
-        acc = mfma_16x16x4(av[s], (c < nc && colok) ? brow[c] : 0.f, acc);
+        const float v = brow[min(c, nc - 1)];
+        bv[g][s] = (ok && c < nc) ? v : 0.f;
       }
     }
-    if (colok) {
+    floatx4 acc[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        if (k0 + v < Tce) Xf[((size_t)i * Ts + k0 + v) * 2 + ax] = acc[v];
+    for (int g = 0; g < 4; ++g) {
+      acc[g] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < KS; ++s) acc[g] = mfma_16x16x4(av[s], bv[g][s], acc[g]);
     }
-    if (boxf) {
-      float lo = fminf(fminf(acc[0], acc[1]), fminf(acc[2], acc[3]));
-      float hi = fmaxf(fmaxf(acc[0], acc[1]), fmaxf(acc[2], acc[3]));
-      lo = fminf(lo, __shfl_xor(lo, 16, 64));
-      hi = fmaxf(hi, __shfl_xor(hi, 16, 64));
-      lo = fminf(lo, __shfl_xor(lo, 32, 64));
-      hi = fmaxf(hi, __shfl_xor(hi, 32, 64));
-      if (lane < 16 && colok) {
-        float* bx = boxf + ((size_t)i * nws + w) * 4 + 2 * ax;
-        bx[0] = lo;
-        bx[1] = hi;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      if (nt0 + g >= ncol) break;
+      const int col = (nt0 + g) * 16 + m;
+      const int i = col >> 1, ax = col & 1;
+      const bool colok = i < n;
+      if (colok) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (k0 + v < Tce) Xf[((size_t)i * Ts + k0 + v) * 2 + ax] = acc[g][v];
+      }
+      if (BOX) {
+        float lo = fminf(fminf(acc[g][0], acc[g][1]), fminf(acc[g][2], acc[g][3]));
+        float hi = fmaxf(fmaxf(acc[g][0], acc[g][1]), fmaxf(acc[g][2], acc[g][3]));
+        lo = rows_reduce(lo, OpMin());
+        hi = rows_reduce(hi, OpMax());
+        if (lane < 16 && colok)
+          *reinterpret_cast<float2*>(boxf + ((size_t)i * nws + w) * 4 + 2 * ax) =
+              make_float2(lo, hi);
       }
     }
   }
 }
 
-// Candidate masks of window w for the robots of part h: bit j of word q set
-// when robot 64q+j (j != i) has a box within a (plus margin) of robot i's box
-// in both axes; bit m of the obstacle words when obstacle m's disc (plus
-// margin) meets robot i's box.  Four lanes (a DPP quad) per robot.  The
-// margin covers rounding of the box comparison and of the exact test at
-// coordinates up to the box's magnitude plus the threshold.
+// Candidate masks of window w for the robots of part h: bit j of the pair
+// word set when robot j (j != i) has a box within a (plus margin) of robot
+// i's box in both axes; bit m of obstacle word q when obstacle 64q+m's disc
+// (plus margin) meets robot i's box.  Lane j tests robot j (or obstacle j) and
+// a ballot forms the word.  The margin covers rounding of the box comparison
+// and of the exact test at coordinates up to the box's magnitude plus the
+// threshold.
 __device__ __forceinline__ void masks_window(const float4* __restrict__ box, int n,
                                              const float4* __restrict__ obs, int M, float a,
-                                             u64* __restrict__ masks, int nws, int pw, int ow,
-                                             int w, int h, int H, int lane) {
-  const int mw = pw + ow;
-  const int q = lane & 3;
-  for (int t0 = 0; part_robot(t0, h, H) < n; t0 += 16) {
-    const int i0 = part_robot(t0 + (lane >> 2), h, H);
-    const bool live = i0 < n;
-    const int i = live ? i0 : 0;
-    const float4 bi = box[i * nws + w];
-    const float si = fmaxf(fmaxf(fabsf(bi.x), fabsf(bi.y)), fmaxf(fabsf(bi.z), fabsf(bi.w)));
-    const float am = a * 1.0001f + 4e-6f * (1.f + si + 2.f * a);
-    u64* out = masks + (size_t)(i * nws + w) * mw;
-    for (int wd = 0; wd < pw; ++wd) {
-      unsigned lo = 0u, hi = 0u;
-      const int jend = min(n - wd * 64, 64);
-      for (int jj = q; jj < jend; jj += 4) {
-        const int j = wd * 64 + jj;
-        const float4 bj = box[j * nws + w];
-        const bool c = (j != i) && (bi.x < bj.y + am) && (bj.x < bi.y + am) &&
-                       (bi.z < bj.w + am) && (bj.z < bi.w + am);
-        const unsigned bit = c ? (1u << (jj & 31)) : 0u;
-        if (jj < 32) lo |= bit; else hi |= bit;
-      }
-      lo = quad_or(lo);
-      hi = quad_or(hi);
-      if (live && q == 0) out[wd] = ((u64)hi << 32) | lo;
+                                             u64* __restrict__ masks, int nws, int ow, int w,
+                                             int h, int H, int lane) {
+  const int mw = 1 + ow;
+  const int cnt = part_count(n, h, H);
+  {
+    const float4 bj = box[min(lane, n - 1) * nws + w];
+    const bool jl = lane < n;
+#pragma unroll 4
+    for (int t = 0; t < cnt; ++t) {
+      const int i = part_robot(t, h, H);
+      const float4 bi = box[i * nws + w];
+      const float si = fmaxf(fmaxf(fabsf(bi.x), fabsf(bi.y)), fmaxf(fabsf(bi.z), fabsf(bi.w)));
+      const float am = a * 1.0001f + 4e-6f * (1.f + si + 2.f * a);
+      const bool c = jl && (lane != i) && (bi.x < bj.y + am) && (bj.x < bi.y + am) &&
+                     (bi.z < bj.w + am) && (bj.z < bi.w + am);
+      const u64 mk = __builtin_amdgcn_ballot_w64(c);
+      if (lane == 0) masks[(size_t)(i * nws + w) * mw] = mk;
     }
-    for (int wd = 0; wd < ow; ++wd) {
-      unsigned lo = 0u, hi = 0u;
-      const int mend = min(M - wd * 64, 64);
-      for (int mm = q; mm < mend; mm += 4) {
-        const float4 o = obs[wd * 64 + mm];
-        const float r = o.z * 1.0001f + 4e-6f * (1.f + si + 2.f * o.z);
-        const bool c = (o.x - r < bi.y) && (bi.x < o.x + r) && (o.y - r < bi.w) && (bi.z < o.y + r);
-        const unsigned bit = c ? (1u << (mm & 31)) : 0u;
-        if (mm < 32) lo |= bit; else hi |= bit;
-      }
-      lo = quad_or(lo);
-      hi = quad_or(hi);
-      if (live && q == 0) out[pw + wd] = ((u64)hi << 32) | lo;
+  }
+  for (int wd = 0; wd < ow; ++wd) {
+    const int mo = wd * 64 + lane;
+    const float4 o = obs[min(mo, M - 1)];
+    const bool ml = mo < M;
+#pragma unroll 4
+    for (int t = 0; t < cnt; ++t) {
+      const int i = part_robot(t, h, H);
+      const float4 bi = box[i * nws + w];
+      const float si = fmaxf(fmaxf(fabsf(bi.x), fabsf(bi.y)), fmaxf(fabsf(bi.z), fabsf(bi.w)));
+      const float r = o.z * 1.0001f + 4e-6f * (1.f + si + 2.f * o.z);
+      const bool c = ml && (o.x - r < bi.y) && (bi.x < o.x + r) && (o.y - r < bi.w) &&
+                     (bi.z < o.y + r);
+      const u64 mk = __builtin_amdgcn_ballot_w64(c);
+      if (lane == 0) masks[(size_t)(i * nws + w) * mw + 1 + wd] = mk;
     }
   }
 }
 
-// Union over the wave's four 16-lane rows of the rows' candidate words.
-__device__ __forceinline__ u64 wave_union(u64 m) {
-  return readlane64(m, 0) | readlane64(m, 16) | readlane64(m, 32) | readlane64(m, 48);
+// Next candidate of a lane's mask (lowest set bit), or `none` when empty.
+__device__ __forceinline__ int pop_candidate(u64& u, int none) {
+  const bool ok = u != 0ull;
+  const int j = ok ? (int)__builtin_ctzll(u) : none;
+  u &= u - 1ull;
+  return j;
+}
+
+// Residual vector of a pair at difference (dx, dy) with d2 = |D|^2 < a^2:
+// (1 - a/|D|) D, and (-a, 0) from robot i's side of a coincident pair with
+// i < j (alpha = atan2(0, 0) = 0), (a, 0) from the other side.
+__device__ __forceinline__ void pair_residual(float dx, float dy, float d2, float a, bool lower,
+                                              float& rx, float& ry) {
+  if (d2 > 0.f) {
+    const float f = 1.f - a * rsqrtf(d2);
+    rx = f * dx;
+    ry = f * dy;
+  } else {
+    rx = lower ? -a : a;
+    ry = 0.f;
+  }
 }
 
 // Exact constraint stage of window w for the robots of part h (a 16-lane row
-// per robot): V = w_pair (pair + obstacle sums) + w_box (box residual), pairs
-// visited in increasing robot index, then obstacles, then the box.  With
-// `accum`, ||r_1||^2 (each unordered pair once) and ||r_2||^2.
+// per robot, one lane per step): V = w_pair (pair + obstacle sums) + w_box
+// (box residual).  Each row walks its own robot's candidates in increasing
+// index (pairs, then obstacles), four per round so their loads overlap;
+// skipped pairs are inactive and would add exactly 0.  With `accum`,
+// ||r_1||^2 (each unordered pair once) and ||r_2||^2.
 __device__ __forceinline__ void constraints_window(
     const float2* __restrict__ X, float2* __restrict__ V, int n, int Ts,
-    const float4* __restrict__ obs, const u64* __restrict__ masks, int nws, int pw, int ow,
-    float a, float pmin0, float pmin1, float pmax0, float pmax1, int w, int Tce, int h, int H,
+    const float4* __restrict__ obs, const u64* __restrict__ masks, int nws, int ow, float a,
+    float pmin0, float pmin1, float pmax0, float pmax1, int w, int Tce, int h, int H,
     bool accum, float& r1sq, float& r2sq, float w_pair, float w_box, int lane) {
   const float a2 = a * a;
-  const int mw = pw + ow;
+  const int mw = 1 + ow;
   const int kk = w * 16 + (lane & 15);
   const int kq = min(kk, Tce - 1);
-  for (int t0 = 0; part_robot(t0, h, H) < n; t0 += 4) {
-    const int i0 = part_robot(t0 + (lane >> 4), h, H);
-    const bool live = i0 < n;
-    const int i = live ? i0 : 0;
-    const bool valid = live && kk < Tce;
+  const int cnt = part_count(n, h, H);
+  for (int t0 = 0; t0 < cnt; t0 += 4) {
+    const int t = t0 + (lane >> 4);
+    const bool live = t < cnt;
+    const int i = part_robot(live ? t : t0, h, H);
     const u64* my = masks + (size_t)(i * nws + w) * mw;
     const float2 p = X[i * Ts + kq];
     float vx = 0.f, vy = 0.f, s1 = 0.f;
-    for (int q = 0; q < pw; ++q) {
-      u64 u = wave_union(live ? my[q] : 0ull);
-      while (u) {
-        const int j = q * 64 + __builtin_ctzll(u);
-        u &= u - 1;
-        const float2 o = X[j * Ts + kq];
-        const float dx = p.x - o.x;
-        const float dy = p.y - o.y;
+    u64 u = live ? my[0] : 0ull;
+    while (u != 0ull) {
+      int j[4];
+      float2 o[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) j[q] = pop_candidate(u, -1);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) o[q] = X[max(j[q], 0) * Ts + kq];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float dx = p.x - o[q].x;
+        const float dy = p.y - o[q].y;
         const float d2 = fmaf(dy, dy, dx * dx);
-        if (d2 < a2 && j != i) {
+        if (j[q] >= 0 && d2 < a2) {
           float rx, ry;
-          if (d2 > 0.f) {
-            const float f = 1.f - a * rsqrtf(d2);
-            rx = f * dx;
-            ry = f * dy;
-          } else {  // coincident: alpha = atan2(0, 0) = 0 for the row (min, max)
-            rx = (i < j) ? -a : a;
-            ry = 0.f;
-          }
+          pair_residual(dx, dy, d2, a, i < j[q], rx, ry);
           vx += rx;
           vy += ry;
-          if (j > i) s1 = fmaf(rx, rx, fmaf(ry, ry, s1));
+          if (j[q] > i) s1 = fmaf(rx, rx, fmaf(ry, ry, s1));
         }
       }
     }
-    for (int q = 0; q < ow; ++q) {
-      u64 u = wave_union(live ? my[pw + q] : 0ull);
-      while (u) {
-        const int m = q * 64 + __builtin_ctzll(u);
-        u &= u - 1;
-        const float4 ob = obs[m];
-        const float dx = p.x - ob.x;
-        const float dy = p.y - ob.y;
-        const float d2 = fmaf(dy, dy, dx * dx);
-        if (d2 < ob.w) {
-          float rx, ry;
-          if (d2 > 0.f) {
-            const float f = 1.f - ob.z * rsqrtf(d2);
-            rx = f * dx;
-            ry = f * dy;
-          } else {
-            rx = -ob.z;
-            ry = 0.f;
+    for (int wd = 0; wd < ow; ++wd) {
+      u = live ? my[1 + wd] : 0ull;
+      while (u != 0ull) {
+        int mq[4];
+        float4 ob[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) mq[q] = pop_candidate(u, -1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ob[q] = obs[wd * 64 + max(mq[q], 0)];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float dx = p.x - ob[q].x;
+          const float dy = p.y - ob[q].y;
+          const float d2 = fmaf(dy, dy, dx * dx);
+          if (mq[q] >= 0 && d2 < ob[q].w) {
+            float rx, ry;
+            pair_residual(dx, dy, d2, ob[q].z, true, rx, ry);
+            vx += rx;
+            vy += ry;
+            s1 = fmaf(rx, rx, fmaf(ry, ry, s1));
           }
-          vx += rx;
-          vy += ry;
-          s1 = fmaf(rx, rx, fmaf(ry, ry, s1));
         }
       }
     }
@@ -325,7 +392,7 @@ __device__ __forceinline__ void constraints_window(
     const float hy = fmaxf(p.y - pmax1, 0.f), ly = fmaxf(pmin1 - p.y, 0.f);
     vx = fmaf(w_box, hx - lx, w_pair * vx);
     vy = fmaf(w_box, hy - ly, w_pair * vy);
-    if (valid) {
+    if (live && kk < Tce) {
       V[i * Ts + kk] = make_float2(vx, vy);
       if (accum) {
         r1sq += s1;
@@ -335,78 +402,83 @@ __device__ __forceinline__ void constraints_window(
   }
 }
 
+// Contribution of one active pair or obstacle to the vector-Jacobian product:
+// J(D) w with J(D) = (1 - f) I + f u u^T, f = a/|D|, u = D/|D|; at D = 0 the
+// e of the alpha/d steps is locally constant, so J = I.
+__device__ __forceinline__ void vjp_term(float dx, float dy, float d2, float a, float wx,
+                                         float wy, float& hx, float& hy) {
+  if (d2 > 0.f) {
+    const float inv = rsqrtf(d2);
+    const float f = a * inv;
+    const float ux = dx * inv, uy = dy * inv;
+    const float dot = fmaf(ux, wx, uy * wy);
+    hx += fmaf(1.f - f, wx, f * ux * dot);
+    hy += fmaf(1.f - f, wy, f * uy * dot);
+  } else {
+    hx += wx;
+    hy += wy;
+  }
+}
+
 // Vector-Jacobian product of the constraint stage over window w for the robots
 // of part h: given the cotangent G of V at positions X,
 //   H_i = sum_{j != i} J(X_i - X_j) (G_i - G_j) + sum_m J_o(X_i - c_m) G_i
 //         + box'(X_i) G_i,
-// where J(D) = (1 - f) I + f u u^T, f = a/|D|, u = D/|D| is the Jacobian of
-// r(D) = D - e(D) for an active pair (|D| < a) and 0 otherwise; at D = 0 the
-// e of the alpha/d steps is locally constant, so J = I.
+// J the Jacobian of r(D) = D - e(D) on active pairs (|D| < a), 0 otherwise.
+// Same walk over candidates as the constraint stage.
 __device__ __forceinline__ void vjp_window(const float2* __restrict__ X,
                                            const float2* __restrict__ G, float2* __restrict__ Hb,
                                            int n, int Ts, const float4* __restrict__ obs,
-                                           const u64* __restrict__ masks, int nws, int pw, int ow,
-                                           float a, float pmin0, float pmin1, float pmax0,
-                                           float pmax1, int w, int Tce, int h, int H, int lane) {
+                                           const u64* __restrict__ masks, int nws, int ow, float a,
+                                           float pmin0, float pmin1, float pmax0, float pmax1,
+                                           int w, int Tce, int h, int H, int lane) {
   const float a2 = a * a;
-  const int mw = pw + ow;
+  const int mw = 1 + ow;
   const int kk = w * 16 + (lane & 15);
   const int kq = min(kk, Tce - 1);
-  for (int t0 = 0; part_robot(t0, h, H) < n; t0 += 4) {
-    const int i0 = part_robot(t0 + (lane >> 4), h, H);
-    const bool live = i0 < n;
-    const int i = live ? i0 : 0;
+  const int cnt = part_count(n, h, H);
+  for (int t0 = 0; t0 < cnt; t0 += 4) {
+    const int t = t0 + (lane >> 4);
+    const bool live = t < cnt;
+    const int i = part_robot(live ? t : t0, h, H);
     const u64* my = masks + (size_t)(i * nws + w) * mw;
     const float2 p = X[i * Ts + kq];
     const float2 gi = G[i * Ts + kq];
     float hx = 0.f, hy = 0.f;
-    for (int q = 0; q < pw; ++q) {
-      u64 u = wave_union(live ? my[q] : 0ull);
-      while (u) {
-        const int j = q * 64 + __builtin_ctzll(u);
-        u &= u - 1;
-        const float2 o = X[j * Ts + kq];
-        const float dx = p.x - o.x;
-        const float dy = p.y - o.y;
+    u64 u = live ? my[0] : 0ull;
+    while (u != 0ull) {
+      int j[4];
+      float2 o[4], gj[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) j[q] = pop_candidate(u, -1);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        o[q] = X[max(j[q], 0) * Ts + kq];
+        gj[q] = G[max(j[q], 0) * Ts + kq];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float dx = p.x - o[q].x;
+        const float dy = p.y - o[q].y;
         const float d2 = fmaf(dy, dy, dx * dx);
-        if (d2 < a2 && j != i) {
-          const float2 gj = G[j * Ts + kq];
-          const float wx = gi.x - gj.x, wy = gi.y - gj.y;
-          if (d2 > 0.f) {
-            const float inv = rsqrtf(d2);
-            const float f = a * inv;
-            const float ux = dx * inv, uy = dy * inv;
-            const float dot = fmaf(ux, wx, uy * wy);
-            hx += fmaf(1.f - f, wx, f * ux * dot);
-            hy += fmaf(1.f - f, wy, f * uy * dot);
-          } else {
-            hx += wx;
-            hy += wy;
-          }
-        }
+        if (j[q] >= 0 && d2 < a2) vjp_term(dx, dy, d2, a, gi.x - gj[q].x, gi.y - gj[q].y, hx, hy);
       }
     }
-    for (int q = 0; q < ow; ++q) {
-      u64 u = wave_union(live ? my[pw + q] : 0ull);
-      while (u) {
-        const int m = q * 64 + __builtin_ctzll(u);
-        u &= u - 1;
-        const float4 ob = obs[m];
-        const float dx = p.x - ob.x;
-        const float dy = p.y - ob.y;
-        const float d2 = fmaf(dy, dy, dx * dx);
-        if (d2 < ob.w) {
-          if (d2 > 0.f) {
-            const float inv = rsqrtf(d2);
-            const float f = ob.z * inv;
-            const float ux = dx * inv, uy = dy * inv;
-            const float dot = fmaf(ux, gi.x, uy * gi.y);
-            hx += fmaf(1.f - f, gi.x, f * ux * dot);
-            hy += fmaf(1.f - f, gi.y, f * uy * dot);
-          } else {
-            hx += gi.x;
-            hy += gi.y;
-          }
+    for (int wd = 0; wd < ow; ++wd) {
+      u = live ? my[1 + wd] : 0ull;
+      while (u != 0ull) {
+        int mq[4];
+        float4 ob[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) mq[q] = pop_candidate(u, -1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ob[q] = obs[wd * 64 + max(mq[q], 0)];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float dx = p.x - ob[q].x;
+          const float dy = p.y - ob[q].y;
+          const float d2 = fmaf(dy, dy, dx * dx);
+          if (mq[q] >= 0 && d2 < ob[q].w) vjp_term(dx, dy, d2, ob[q].z, gi.x, gi.y, hx, hy);
         }
       }
     }
@@ -418,36 +490,46 @@ __device__ __forceinline__ void vjp_window(const float2* __restrict__ X,
 
 // Window w's share of the time->coefficient map for the column tiles of part
 // h (tiles nt = h, h+H, ...): part_w[axis][i][c] (+)= sum over the window's
-// steps of W[k][c] V[i][k].axis.
+// steps of W[k][c] V[i][k].axis.  The W^T operands of the window stay in
+// registers across the column tiles.
+template <int KS>
 __device__ __forceinline__ void wtmap_window(const float* __restrict__ W, int nc,
                                              const float* __restrict__ Vf, int n, int Ts, int w,
                                              int Tce, int h, int H, float* __restrict__ part_w,
                                              bool accumulate, int lane) {
+  constexpr int NCT = (KS + 3) / 4;   // coefficient tiles of 16
   const int nct = (nc + 15) >> 4;
   const int ncol = (2 * n + 15) >> 4;
   const int m = lane & 15, kq = lane >> 4;
+  float av[NCT][4];
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct) {
+    const int ca = ct * 16 + m;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int kk = w * 16 + 4 * s + kq;
+      const float v = W[min(kk, Tce - 1) * nc + min(ca, nc - 1)];
+      av[ct][s] = (kk < Tce && ca < nc) ? v : 0.f;
+    }
+  }
   for (int nt = h; nt < ncol; nt += H) {
     const int col = nt * 16 + m;
     const int i = col >> 1, ax = col & 1;
     const bool colok = i < n;
-    const float* vrow = Vf + (size_t)(colok ? i : 0) * Ts * 2 + ax;
+    const float* vrow = Vf + (size_t)min(i, n - 1) * Ts * 2 + ax;
     float bv[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int kk = w * 16 + 4 * s + kq;
-      bv[s] = (kk < Tce && colok) ? vrow[2 * kk] : 0.f;
+      const float v = vrow[2 * min(kk, Tce - 1)];
+      bv[s] = (kk < Tce && colok) ? v : 0.f;
     }
-    for (int ct = 0; ct < nct; ++ct) {
-      const int ca = ct * 16 + m;
-      float av[4];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int kk = w * 16 + 4 * s + kq;
-        av[s] = (kk < Tce && ca < nc) ? W[kk * nc + ca] : 0.f;
-      }
+    for (int ct = 0; ct < NCT; ++ct) {
+      if (ct >= nct) break;
       floatx4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int s = 0; s < 4; ++s) acc = mfma_16x16x4(av[s], bv[s], acc);
+      for (int s = 0; s < 4; ++s) acc = mfma_16x16x4(av[ct][s], bv[s], acc);
       if (colok) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -474,53 +556,13 @@ __device__ __forceinline__ int parts_per_window(int n, int nwin, int nwaves) {
 // Coefficient-space stages.
 // ---------------------------------------------------------------------------
 
-// R = per-window partials summed in window order; lambda' = lambda - rho R;
-// u = lambda - 2 rho R into Ru; robot means of u (means[axis*nc + c]) and of xb
-// (means[2nc + axis*nc + c]).  One wave per column, lanes over robots.
-__device__ __forceinline__ void combine_lambda_means(const float* __restrict__ part, int nwin,
-                                                     int S, float* __restrict__ lam,
-                                                     float* __restrict__ Ru,
-                                                     const float* __restrict__ xb, int n, int nc,
-                                                     float rho, bool want_dz, float& dzsq,
-                                                     float* __restrict__ means, int wave,
-                                                     int nwaves, int lane) {
-  const float inv = 1.f / (float)n;
-  for (int col = wave; col < 4 * nc; col += nwaves) {
-    const bool ucol = col < 2 * nc;
-    const int cc = ucol ? col : col - 2 * nc;
-    const int ax = cc / nc, c = cc - ax * nc;
-    float acc = 0.f;
-    for (int i = lane; i < n; i += 64) {
-      const int sidx = ax * n * nc + i * nc + c;
-      if (ucol) {
-        float r = part[sidx];
-        for (int w = 1; w < nwin; ++w) r += part[(size_t)w * S + sidx];
-        const float lm = lam[sidx];
-        lam[sidx] = fmaf(-rho, r, lm);
-        const float u = fmaf(-2.f * rho, r, lm);
-        Ru[sidx] = u;
-        acc += u;
-        if (want_dz) dzsq = fmaf(rho * r, rho * r, dzsq);
-      } else {
-        acc += xb[sidx];
-      }
-    }
-    acc = wave_sum_dpp(acc);
-    if (lane == 0) means[col] = acc * inv;
-  }
-}
-
-// Robot means of the columns of one coefficient array (or two) into out.
-__device__ __forceinline__ void robot_means(const float* __restrict__ src0,
-                                            const float* __restrict__ src1, int n, int nc,
+// Robot means of the columns of one coefficient array into out[axis*nc + c].
+__device__ __forceinline__ void robot_means(const float* __restrict__ src, int n, int nc,
                                             float* __restrict__ out, int wave, int nwaves,
                                             int lane) {
   const float inv = 1.f / (float)n;
-  const int cols = (src1 ? 4 : 2) * nc;
-  for (int col = wave; col < cols; col += nwaves) {
-    const float* src = col < 2 * nc ? src0 : src1;
-    const int cc = col < 2 * nc ? col : col - 2 * nc;
-    const int ax = cc / nc, c = cc - ax * nc;
+  for (int col = wave; col < 2 * nc; col += nwaves) {
+    const int ax = col / nc, c = col - ax * nc;
     const float* base = src + ax * n * nc + c;
     float s = 0.f;
     for (int i = lane; i < n; i += 64) s += base[i * nc];
@@ -529,57 +571,167 @@ __device__ __forceinline__ void robot_means(const float* __restrict__ src0,
   }
 }
 
-// Mode operators on MFMA tiles (rows = robots, columns = coefficients):
-//   out[axis][i][c] = init + sum_q P0[c][q] Y0_i[q] + D0[c][q] Ym0[q]
-//                          (+ sum_q P1[c][q] Y1_i[q] + D1[c][q] Ym1[q])
-// with (P, D) pairs at fac + f0 and fac + f1 (D = P_par - P_perp), means
-// Ym[axis*nc + q]; `trans` applies P^T and D^T instead.  K runs over the
-// (Y, Ym[, Y1, Ym1]) blocks, nc each.  Calls emit(axis, i, c, value).
-template <typename Emit>
-__device__ __forceinline__ void mode_mfma(const float* __restrict__ fac, int nc, int n,
-                                          const float* __restrict__ Y0,
-                                          const float* __restrict__ Ym0, int f0,
-                                          const float* __restrict__ Y1,
-                                          const float* __restrict__ Ym1, int f1, bool trans,
-                                          const float* __restrict__ init, Emit emit, int wave,
-                                          int nwaves, int lane) {
+// Mode products on MFMA tiles.  A problem's operator acts on a coefficient
+// array Y (rows = robots) as
+//   (S Y)_i = P_perp Y_i + (P_par - P_perp) mean_j(Y_j)
+// (S^T: transposed blocks).  A tile covers one axis, 16 robots (row tile rt)
+// and 16 output coefficients (column tile ct); lanes supply A[m][k] =
+// Y[16 rt + m][4 s + kq] (m = lane % 16, kq = lane / 16) for s < KS, and hold
+// outputs [16 rt + 4 kq + v][16 ct + m].  The mean term is formed as the
+// column sums of D Y over the block's robots (rows past n are zero), summed
+// over row tiles through LDS between two block-synchronised phases.
+constexpr int kTilesMax = 16;    // 2 axes x 4 row tiles x 2 column tiles
+constexpr int kColSums = 2 * 2 * 4 * 16;
+
+__host__ __device__ constexpr int tiles_per_wave(int NT) {
+  return (kTilesMax + (NT >> 6) - 1) / (NT >> 6);
+}
+
+struct Tile {
+  int ax, rt, ct;
+};
+__device__ __forceinline__ bool mode_tile_of(int tile, int n, int nc, Tile& t) {
   const int nrt = (n + 15) >> 4, nct = (nc + 15) >> 4;
+  if (tile >= 2 * nrt * nct) return false;
+  t.ax = tile / (nrt * nct);
+  const int rem = tile - t.ax * nrt * nct;
+  t.rt = rem / nct;
+  t.ct = rem - t.rt * nct;
+  return true;
+}
+__device__ __forceinline__ int colsum_slot(const Tile& t, int rt) {
+  return ((t.ax * 2 + t.ct) * 4 + rt) * 16;
+}
+
+// accP += Y P^(T) and accD += Y D^(T) for the block (P, D) at fac + fo.
+template <int KS>
+__device__ __forceinline__ void mode_tile(const float* __restrict__ fac, int nc, int fo,
+                                          bool trans, int cb, const float (&a)[KS],
+                                          floatx4& accP, floatx4& accD, int lane) {
+  const int kq = lane >> 4;
   const int nc2 = nc * nc;
-  const int blocks = Y1 ? 4 : 2;
-  const int ks = (blocks * nc + 3) >> 2;
+  const int cbc = min(cb, nc - 1);
+  float bp[KS], bd[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    const int k = 4 * s + kq;
+    const int kc = min(k, nc - 1);
+    const bool ok = k < nc && cb < nc;
+    const int idx = trans ? kc * nc + cbc : cbc * nc + kc;
+    const float p = fac[fo + idx], d = fac[fo + nc2 + idx];
+    bp[s] = ok ? p : 0.f;
+    bd[s] = ok ? d : 0.f;
+  }
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    accP = mfma_16x16x4(a[s], bp[s], accP);
+    accD = mfma_16x16x4(a[s], bd[s], accD);
+  }
+}
+
+// Column sum of a D accumulator over the tile's 16 robots, written for the
+// later mean.
+__device__ __forceinline__ void put_colsum(const floatx4& accD, float* __restrict__ csum,
+                                           const Tile& t, int lane) {
+  const float cs = rows_reduce((accD[0] + accD[1]) + (accD[2] + accD[3]), OpAdd());
+  if (lane < 16) csum[colsum_slot(t, t.rt) + lane] = cs;
+}
+__device__ __forceinline__ float get_mean(const float* __restrict__ csum, const Tile& t, int n,
+                                          int lane) {
+  const int nrt = (n + 15) >> 4;
+  float s = 0.f;
+  for (int r = 0; r < nrt; ++r) s += csum[colsum_slot(t, r) + (lane & 15)];
+  return s * (1.f / (float)n);
+}
+
+// Forward update, phase 1 (tiles of this wave): R = sum of the per-window
+// partials in window order; lambda' = lambda - rho R into lam_n; u = lambda -
+// 2 rho R; accP = c_xi + P_S u + P_SH xb; column sums of D_S u + D_SH xb.
+// With `last`, dzsq gets ||rho R||^2.
+template <int NT, int KS>
+__device__ __forceinline__ void update_fwd_p1(const float* __restrict__ fac, int nc, int n,
+                                              const float* __restrict__ part, int nwin, int S,
+                                              const float* __restrict__ lam,
+                                              float* __restrict__ lam_n,
+                                              const float* __restrict__ xb,
+                                              const float* __restrict__ cx, float rho, bool last,
+                                              float& dzsq, float* __restrict__ csum,
+                                              floatx4 (&accP)[tiles_per_wave(NT)], int wave,
+                                              int lane) {
+  constexpr int TPW = tiles_per_wave(NT);
   const int m = lane & 15, kq = lane >> 4;
-  for (int tile = wave; tile < 2 * nrt * nct; tile += nwaves) {
-    const int ax = tile / (nrt * nct);
-    const int rem = tile - ax * nrt * nct;
-    const int rt = rem / nct, ct = rem - rt * nct;
-    const int ia = rt * 16 + m;
-    const int cb = ct * 16 + m;
-    floatx4 acc;
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) {
+    Tile t;
+    if (!mode_tile_of(wave + q * (NT >> 6), n, nc, t)) continue;
+    const int i = t.rt * 16 + m;
+    const int ic = min(i, n - 1);
+    int sidx[KS];
+    float r[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      sidx[s] = t.ax * n * nc + ic * nc + min(4 * s + kq, nc - 1);
+      r[s] = part[sidx[s]];
+    }
+    for (int w = 1; w < nwin; ++w) {
+#pragma unroll
+      for (int s = 0; s < KS; ++s) r[s] += part[(size_t)w * S + sidx[s]];
+    }
+    float au[KS], axb[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const bool ok = i < n && 4 * s + kq < nc;
+      const float lm = lam[sidx[s]];
+      const float xv = xb[sidx[s]];
+      au[s] = ok ? fmaf(-2.f * rho, r[s], lm) : 0.f;
+      axb[s] = ok ? xv : 0.f;
+      if (ok && t.ct == 0) {
+        lam_n[sidx[s]] = fmaf(-rho, r[s], lm);
+        if (last) dzsq = fmaf(rho * r[s], rho * r[s], dzsq);
+      }
+    }
+    const int cb = t.ct * 16 + m;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int io = rt * 16 + 4 * kq + v;
-      acc[v] = (init && io < n && cb < nc) ? init[ax * n * nc + io * nc + cb] : 0.f;
+      const int io = t.rt * 16 + 4 * kq + v;
+      const float c0 = cx[t.ax * n * nc + min(io, n - 1) * nc + min(cb, nc - 1)];
+      accP[q][v] = (io < n && cb < nc) ? c0 : 0.f;
     }
-    for (int s = 0; s < ks; ++s) {
-      const int k = 4 * s + kq;
-      const int blk = (k >= nc) + (k >= 2 * nc) + (k >= 3 * nc);
-      const int q = k - blk * nc;
-      float a = 0.f, b = 0.f;
-      if (blk < blocks && cb < nc) {
-        const int fo = (blk < 2 ? f0 : f1) + (blk & 1) * nc2;
-        b = trans ? fac[fo + q * nc + cb] : fac[fo + cb * nc + q];
-      }
-      if (blk < blocks && ia < n) {
-        const float* Y = blk < 2 ? Y0 : Y1;
-        const float* Ym = blk < 2 ? Ym0 : Ym1;
-        a = (blk & 1) ? Ym[ax * nc + q] : Y[ax * n * nc + ia * nc + q];
-      }
-      acc = mfma_16x16x4(a, b, acc);
-    }
+    floatx4 accD = {0.f, 0.f, 0.f, 0.f};
+    mode_tile<KS>(fac, nc, 0, false, cb, au, accP[q], accD, lane);
+    mode_tile<KS>(fac, nc, 2 * nc * nc, false, cb, axb, accP[q], accD, lane);
+    put_colsum(accD, csum, t, lane);
+  }
+}
+
+// Forward update, phase 2: xn = accP + mean term.  With `last`, dzsq gets
+// ||xn - xb||^2.
+template <int NT>
+__device__ __forceinline__ void update_fwd_p2(int nc, int n, const float* __restrict__ csum,
+                                              const floatx4 (&accP)[tiles_per_wave(NT)],
+                                              const float* __restrict__ xb,
+                                              float* __restrict__ xn, bool last, float& dzsq,
+                                              int wave, int lane) {
+  constexpr int TPW = tiles_per_wave(NT);
+  const int m = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) {
+    Tile t;
+    if (!mode_tile_of(wave + q * (NT >> 6), n, nc, t)) continue;
+    const float mean = get_mean(csum, t, n, lane);
+    const int cb = t.ct * 16 + m;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int io = rt * 16 + 4 * kq + v;
-      if (io < n && cb < nc) emit(ax, io, cb, acc[v]);
+      const int io = t.rt * 16 + 4 * kq + v;
+      if (io < n && cb < nc) {
+        const int s = t.ax * n * nc + io * nc + cb;
+        const float val = accP[q][v] + mean;
+        xn[s] = val;
+        if (last) {
+          const float d = val - xb[s];
+          dzsq = fmaf(d, d, dzsq);
+        }
+      }
     }
   }
 }
@@ -706,7 +858,6 @@ struct Ctx {
 
   __device__ __forceinline__ int Ts() const { return tstride(Tc); }
   __device__ __forceinline__ int nws() const { return nwindows(Tc); }
-  __device__ __forceinline__ int pw() const { return (n + 63) >> 6; }
   __device__ __forceinline__ int ow() const { return (M + 63) >> 6; }
 
   // Make the LDS W table hold rows k0 .. k0+Tce-1 (block-wide; no-op when
@@ -724,74 +875,66 @@ struct Ctx {
 // every window (V = w_pair (pairs + obstacles) + w_box box), and with `part`
 // the windows' shares of W^T V into part[w][S] (added when `accumulate`).
 // Leaves the block synchronised.
-template <int NT>
+template <int NT, int KS>
 __device__ __forceinline__ void chunk_units(const Ctx& C, int Tce, const float* xb, float2* X,
                                             float2* V, float* part, bool accumulate, bool accum,
                                             float& r1sq, float& r2sq, float w_pair,
                                             float w_box) {
-  const int lane = C.tid & 63, wave = C.tid >> 6, nwaves = NT >> 6;
+  const int lane = lane_here(C.tid), wave = C.tid >> 6, nwaves = NT >> 6;
   const int nwin = nwindows(Tce);
   const int H = parts_per_window(C.n, nwin, nwaves);
-  const int Ts = C.Ts(), nws = C.nws(), pw = C.pw(), ow = C.ow();
+  const int Ts = C.Ts(), nws = C.nws(), ow = C.ow();
   for (int u = wave; u < nwin * H; u += nwaves) {
     const int w = u / H, h = u - w * H;
-    xmap_window(C.W, C.nc, xb, C.n, reinterpret_cast<float*>(X), Ts, w, Tce,
-                reinterpret_cast<float*>(C.box), nws, lane);
+    xmap_window<KS, true>(C.W, C.nc, xb, C.n, reinterpret_cast<float*>(X), Ts, w, Tce,
+                          reinterpret_cast<float*>(C.box), nws, lane);
     wave_fence();
-    masks_window(C.box, C.n, C.obs, C.M, C.a, C.masks, nws, pw, ow, w, h, H, lane);
+    masks_window(C.box, C.n, C.obs, C.M, C.a, C.masks, nws, ow, w, h, H, lane);
     wave_fence();
-    constraints_window(X, V, C.n, Ts, C.obs, C.masks, nws, pw, ow, C.a, C.pmin0, C.pmin1,
-                       C.pmax0, C.pmax1, w, Tce, h, H, accum, r1sq, r2sq, w_pair, w_box, lane);
+    constraints_window(X, V, C.n, Ts, C.obs, C.masks, nws, ow, C.a, C.pmin0, C.pmin1, C.pmax0,
+                       C.pmax1, w, Tce, h, H, accum, r1sq, r2sq, w_pair, w_box, lane);
     if (part) {
       wave_fence();
-      wtmap_window(C.W, C.nc, reinterpret_cast<const float*>(V), C.n, Ts, w, Tce, h, H,
-                   part + (size_t)w * C.S, accumulate, lane);
+      wtmap_window<KS>(C.W, C.nc, reinterpret_cast<const float*>(V), C.n, Ts, w, Tce, h, H,
+                       part + (size_t)w * C.S, accumulate, lane);
     }
   }
   __syncthreads();
 }
 
-// One application of T on the LDS state (xb, lam) -> (xn, lam).  Ru, X, V,
-// part and means are scratch.  Entered and left with the block synchronised.
-template <int NT>
+// One application of T on the LDS state: (xb, lam) -> (xn, lam_n).  X, V,
+// part and csum are scratch.  Entered and left with the block synchronised.
+template <int NT, int KS>
 __device__ __forceinline__ void sf_iteration(const Ctx& C, const float* xb, float* xn,
-                                             float* lam, float* Ru, float* means, float2* X,
-                                             float2* V, float* part, const float* cx, bool last,
-                                             float& dzsq) {
-  const int lane = C.tid & 63, wave = C.tid >> 6, nwaves = NT >> 6;
+                                             const float* lam, float* lam_n, float* csum,
+                                             float2* X, float2* V, float* part, const float* cx,
+                                             bool last, float& dzsq) {
+  const int wave = C.tid >> 6;
   float d1 = 0.f, d2 = 0.f;
   for (int k0 = 0; k0 < C.T; k0 += C.Tc) {
     const int Tce = min(C.Tc, C.T - k0);
     C.wchunk<NT>(k0, Tce);
-    chunk_units<NT>(C, Tce, xb, X, V, part, k0 > 0, false, d1, d2, 1.f, 1.f);
+    chunk_units<NT, KS>(C, Tce, xb, X, V, part, k0 > 0, false, d1, d2, 1.f, 1.f);
   }
-  combine_lambda_means(part, nwindows(min(C.Tc, C.T)), C.S, lam, Ru, xb, C.n, C.nc, C.rho,
-                       last, dzsq, means, wave, nwaves, lane);
+  floatx4 accP[tiles_per_wave(NT)];
+  int lane = lane_here(C.tid);
+  update_fwd_p1<NT, KS>(C.fac, C.nc, C.n, part, nwindows(min(C.Tc, C.T)), C.S, lam, lam_n, xb,
+                        cx, C.rho, last, dzsq, csum, accP, wave, lane);
   __syncthreads();
-  const int n = C.n, nc = C.nc;
-  mode_mfma(
-      C.fac, nc, n, Ru, means, 0, xb, means + 2 * nc, 2 * nc * nc, false, cx,
-      [&](int ax, int i, int c, float v) {
-        const int s = ax * n * nc + i * nc + c;
-        xn[s] = v;
-        if (last) {
-          const float d = v - xb[s];
-          dzsq = fmaf(d, d, dzsq);
-        }
-      },
-      wave, nwaves, lane);
+  lane = lane_here(C.tid);
+  update_fwd_p2<NT>(C.nc, C.n, csum, accP, xb, xn, last, dzsq, wave, lane);
   __syncthreads();
 }
 
 // ||r_1||^2 and ||r_2||^2 partials of the iterate xb (block-synchronised on
 // return); V is scratch.
-template <int NT>
+template <int NT, int KS>
 __device__ __forceinline__ void residual_norms(const Ctx& C, const float* xb, float2* X,
                                                float2* V, float& r1sq, float& r2sq) {
   for (int k0 = 0; k0 < C.T; k0 += C.Tc) {
     const int Tce = min(C.Tc, C.T - k0);
     C.wchunk<NT>(k0, Tce);
-    chunk_units<NT>(C, Tce, xb, X, V, nullptr, false, true, r1sq, r2sq, 1.f, 1.f);
+    chunk_units<NT, KS>(C, Tce, xb, X, V, nullptr, false, true, r1sq, r2sq, 1.f, 1.f);
   }
 }
 
@@ -804,7 +947,7 @@ __host__ __device__ inline int mask_floats(int Tc, int n_max, int M_max) {
 }
 
 struct FwdLds {
-  float *W, *fac, *xbA, *xbB, *lam, *cx, *Ru, *part, *means, *red;
+  float *W, *fac, *xbA, *xbB, *lamA, *lamB, *cx, *part, *means, *red, *csum;
   float4* obs;
   float4* box;
   u64* masks;
@@ -819,12 +962,13 @@ __device__ __forceinline__ FwdLds carve_fwd(float* sm, int nc, int Tc, int n_max
   L.fac = p; p += round4(fac_stride(nc));
   L.xbA = p; p += round4(S_max);
   L.xbB = p; p += round4(S_max);
-  L.lam = p; p += round4(S_max);
+  L.lamA = p; p += round4(S_max);
+  L.lamB = p; p += round4(S_max);
   L.cx = p; p += round4(S_max);
-  L.Ru = p; p += round4(S_max);
   L.part = p; p += nwindows(Tc) * round4(S_max);
   L.means = p; p += kMeans;
   L.red = p; p += kRed;
+  L.csum = p; p += kColSums;
   L.obs = reinterpret_cast<float4*>(p); p += 4 * M_max;
   L.box = reinterpret_cast<float4*>(p); p += box_floats(Tc, n_max);
   L.masks = reinterpret_cast<u64*>(p); p += mask_floats(Tc, n_max, M_max);
@@ -838,7 +982,7 @@ __device__ __forceinline__ FwdLds carve_fwd(float* sm, int nc, int Tc, int n_max
 size_t fwd_lds_bytes(int nc, int T, int Tc, int n_max, int M_max, int S_max, int) {
   auto r4 = [](int x) { return (size_t)((x + 3) & ~3); };
   size_t f = r4(nc * Tc) + r4(fac_stride(nc)) + (5 + nwindows(Tc)) * r4(S_max) + kMeans + kRed +
-             4 * (size_t)M_max + box_floats(Tc, n_max) + mask_floats(Tc, n_max, M_max) +
+             kColSums + 4 * (size_t)M_max + box_floats(Tc, n_max) + mask_floats(Tc, n_max, M_max) +
              4 * (size_t)n_max * tstride(Tc);
   return f * sizeof(float);
 }
@@ -847,7 +991,7 @@ size_t fwd_lds_bytes(int nc, int T, int Tc, int n_max, int M_max, int S_max, int
 // Fused forward: one workgroup runs all L iterations of one problem with the
 // whole state in LDS.  Launch slot -> problem through `order` (longest first).
 // ---------------------------------------------------------------------------
-template <int NT>
+template <int NT, int KS>
 __global__ __launch_bounds__(NT) void fwd_fused_kernel(FwdArgs A) {
   extern __shared__ float4 sm4[];
   float* sm = reinterpret_cast<float*>(sm4);
@@ -874,17 +1018,17 @@ __global__ __launch_bounds__(NT) void fwd_fused_kernel(FwdArgs A) {
   }
   for (int s = tid; s < S; s += NT) {
     L.xbA[s] = A.xi0[P.coef_off + s];
-    L.lam[s] = A.lam0[P.coef_off + s];
-    L.Ru[s] = A.xi[P.coef_off + s];
+    L.lamA[s] = A.lam0[P.coef_off + s];
+    L.lamB[s] = A.xi[P.coef_off + s];   // target xi, staged for c_xi
   }
   __syncthreads();
   const float* bnd = A.boundary + (size_t)P.rob_off * 4;
-  robot_means(L.Ru, nullptr, n, nc, L.means, tid >> 6, NT >> 6, tid & 63);
+  robot_means(L.lamB, n, nc, L.means, tid >> 6, NT >> 6, tid & 63);
   boundary_means(bnd, n, L.means + 2 * nc, tid, NT);
   __syncthreads();
   for (int s = tid; s < S; s += NT) {
     const int ax = s / (n * nc), rem = s - ax * n * nc, i = rem / nc, c = rem - i * nc;
-    const float v = cxi_entry(L.fac, nc, L.Ru, L.means, bnd + i * 4, L.means + 2 * nc, n,
+    const float v = cxi_entry(L.fac, nc, L.lamB, L.means, bnd + i * 4, L.means + 2 * nc, n,
                               ax, i, c);
     L.cx[s] = v;
     if (A.save) A.ws_cxi[P.coef_off + s] = v;
@@ -893,25 +1037,30 @@ __global__ __launch_bounds__(NT) void fwd_fused_kernel(FwdArgs A) {
 
   float* xb = L.xbA;
   float* xn = L.xbB;
+  float* lam = L.lamA;
+  float* lamn = L.lamB;
   float dzsq = 0.f;
   for (int l = 0; l < A.L; ++l) {
     if (A.save && (l % A.ckpt_every) == 0) {
       float* ck = A.ws_ckpt + (size_t)(l / A.ckpt_every) * 2 * A.S_total + P.coef_off;
       for (int s = tid; s < S; s += NT) {
         ck[s] = xb[s];
-        ck[A.S_total + s] = L.lam[s];
+        ck[A.S_total + s] = lam[s];
       }
     }
-    sf_iteration<NT>(C, xb, xn, L.lam, L.Ru, L.means, L.X, L.V, L.part, L.cx, l == A.L - 1,
-                     dzsq);
+    sf_iteration<NT, KS>(C, xb, xn, lam, lamn, L.csum, L.X, L.V, L.part, L.cx, l == A.L - 1,
+                         dzsq);
     float* t = xb;
     xb = xn;
     xn = t;
+    t = lam;
+    lam = lamn;
+    lamn = t;
   }
 
   float bad = 0.f;
   for (int s = tid; s < S; s += NT) {
-    const float x = xb[s], lm = L.lam[s];
+    const float x = xb[s], lm = lam[s];
     if (A.save) {
       A.ws_final[P.coef_off + s] = x;
       A.ws_final[A.S_total + P.coef_off + s] = lm;
@@ -922,7 +1071,7 @@ __global__ __launch_bounds__(NT) void fwd_fused_kernel(FwdArgs A) {
   }
   // residual of the returned iterate
   float r1sq = 0.f, r2sq = 0.f;
-  residual_norms<NT>(C, xb, L.X, L.V, r1sq, r2sq);
+  residual_norms<NT, KS>(C, xb, L.X, L.V, r1sq, r2sq);
   float v[4] = {r1sq, r2sq, dzsq, bad};
   block_sum(v, L.red);
   if (tid == 0) {
@@ -934,22 +1083,31 @@ __global__ __launch_bounds__(NT) void fwd_fused_kernel(FwdArgs A) {
   }
 }
 
-hipError_t launch_fwd_fused(const FwdArgs& a, int threads, size_t lds, hipStream_t s) {
+// MFMA K steps of 4 coefficients: 4 covers n_coef <= 16, 8 covers <= 32.
+__host__ __device__ inline int ks_class(int nc) { return nc <= 16 ? 4 : 8; }
+
+template <int KS>
+hipError_t launch_fwd_ks(const FwdArgs& a, int threads, size_t lds, hipStream_t s) {
   dim3 grid(a.B);
   switch (threads) {
     case 256:
-      hipLaunchKernelGGL(fwd_fused_kernel<256>, grid, dim3(256), lds, s, a);
+      hipLaunchKernelGGL((fwd_fused_kernel<256, KS>), grid, dim3(256), lds, s, a);
       break;
     case 512:
-      hipLaunchKernelGGL(fwd_fused_kernel<512>, grid, dim3(512), lds, s, a);
+      hipLaunchKernelGGL((fwd_fused_kernel<512, KS>), grid, dim3(512), lds, s, a);
       break;
     case 1024:
-      hipLaunchKernelGGL(fwd_fused_kernel<1024>, grid, dim3(1024), lds, s, a);
+      hipLaunchKernelGGL((fwd_fused_kernel<1024, KS>), grid, dim3(1024), lds, s, a);
       break;
     default:
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_fwd_fused(const FwdArgs& a, int threads, size_t lds, hipStream_t s) {
+  return ks_class(a.nc) == 4 ? launch_fwd_ks<4>(a, threads, lds, s)
+                             : launch_fwd_ks<8>(a, threads, lds, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -963,7 +1121,7 @@ hipError_t launch_fwd_fused(const FwdArgs& a, int threads, size_t lds, hipStream
 namespace {
 
 struct BwdLds {
-  float *W, *fac, *red, *means, *gA, *gB, *glam, *gxi, *cx, *b0, *b1, *b2, *b3, *part;
+  float *W, *fac, *red, *csum, *gA, *gB, *glam, *gxi, *cx, *b0, *b1, *b2, *b3, *part;
   float4* obs;
   float4* box;
   u64* masks;
@@ -977,7 +1135,7 @@ __device__ __forceinline__ BwdLds carve_bwd(float* sm, int nc, int Tc, int n_max
   L.W = p; p += round4(nc * Tc);
   L.fac = p; p += round4(fac_stride(nc));
   L.red = p; p += kRed;
-  L.means = p; p += kMeans;
+  L.csum = p; p += 2 * kColSums;
   float** bufs[9] = {&L.gA, &L.gB, &L.glam, &L.gxi, &L.cx, &L.b0, &L.b1, &L.b2, &L.b3};
   for (int q = 0; q < 9; ++q) {
     *bufs[q] = p;
@@ -1003,25 +1161,162 @@ __device__ __forceinline__ void add_partials(float* __restrict__ g, const float*
   }
 }
 
+// Adjoint update, phase 1 (tiles of this wave): the A operand is the
+// cotangent g of xi_bar^{l+1}, plus the pending W^T VJP partials (part, when
+// not null) and, with a fixed-point weight fw, 2 fw (xi_bar^{l+1} - xi_bar^l);
+// accU = S^T g, accN = SH^T g - 2 fw (xi_bar^{l+1} - xi_bar^l); column sums of
+// the D^T blocks into csU / csN.  cur and nxt are the iterates l and l+1
+// ([2][S_total] slices: xi_bar, then lambda at +St).
+template <int NT, int KS>
+__device__ __forceinline__ void update_bwd_p1(const float* __restrict__ fac, int nc, int n,
+                                              const float* __restrict__ gx,
+                                              const float* __restrict__ part, int nwin, int S,
+                                              const float* __restrict__ cur,
+                                              const float* __restrict__ nxt, float fw,
+                                              float* __restrict__ csU, float* __restrict__ csN,
+                                              floatx4 (&accU)[tiles_per_wave(NT)],
+                                              floatx4 (&accN)[tiles_per_wave(NT)], int wave,
+                                              int lane) {
+  constexpr int TPW = tiles_per_wave(NT);
+  const int m = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) {
+    Tile t;
+    if (!mode_tile_of(wave + q * (NT >> 6), n, nc, t)) continue;
+    const int i = t.rt * 16 + m;
+    const int ic = min(i, n - 1);
+    int sidx[KS];
+    float g[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      sidx[s] = t.ax * n * nc + ic * nc + min(4 * s + kq, nc - 1);
+      g[s] = gx[sidx[s]];
+    }
+    if (part) {
+      float r[KS];
+#pragma unroll
+      for (int s = 0; s < KS; ++s) r[s] = part[sidx[s]];
+      for (int w = 1; w < nwin; ++w) {
+#pragma unroll
+        for (int s = 0; s < KS; ++s) r[s] += part[(size_t)w * S + sidx[s]];
+      }
+#pragma unroll
+      for (int s = 0; s < KS; ++s) g[s] += r[s];
+    }
+    if (fw != 0.f) {
+#pragma unroll
+      for (int s = 0; s < KS; ++s) g[s] = fmaf(2.f * fw, nxt[sidx[s]] - cur[sidx[s]], g[s]);
+    }
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const bool ok = i < n && 4 * s + kq < nc;
+      g[s] = ok ? g[s] : 0.f;
+    }
+    const int cb = t.ct * 16 + m;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int io = t.rt * 16 + 4 * kq + v;
+      float f0 = 0.f;
+      if (fw != 0.f && io < n && cb < nc) {
+        const int s = t.ax * n * nc + io * nc + cb;
+        f0 = -2.f * fw * (nxt[s] - cur[s]);
+      }
+      accU[q][v] = 0.f;
+      accN[q][v] = f0;
+    }
+    floatx4 dU = {0.f, 0.f, 0.f, 0.f}, dN = {0.f, 0.f, 0.f, 0.f};
+    mode_tile<KS>(fac, nc, 0, true, cb, g, accU[q], dU, lane);
+    mode_tile<KS>(fac, nc, 2 * nc * nc, true, cb, g, accN[q], dN, lane);
+    put_colsum(dU, csU, t, lane);
+    put_colsum(dN, csN, t, lane);
+  }
+}
+
+// Adjoint update, phase 2: g_u = accU + mean term (the cotangent reaching u =
+// lambda - 2 rho R, hence also the target xi and lambda); g_R = -2 rho g_u -
+// rho g_lambda' (- 2 rho fw (lambda^{l+1} - lambda^l)); g_lambda += g_u;
+// g_xi += g_u; the new g_xi_bar (before its W^T VJP part) = accN + mean term.
 template <int NT>
+__device__ __forceinline__ void update_bwd_p2(int nc, int n, const float* __restrict__ csU,
+                                              const float* __restrict__ csN,
+                                              const floatx4 (&accU)[tiles_per_wave(NT)],
+                                              const floatx4 (&accN)[tiles_per_wave(NT)],
+                                              float rho, float fw, const float* __restrict__ cur,
+                                              const float* __restrict__ nxt, size_t St,
+                                              float* __restrict__ glam, float* __restrict__ gxi,
+                                              float* __restrict__ gR, float* __restrict__ gn,
+                                              int wave, int lane) {
+  constexpr int TPW = tiles_per_wave(NT);
+  const int m = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) {
+    Tile t;
+    if (!mode_tile_of(wave + q * (NT >> 6), n, nc, t)) continue;
+    const float mu = get_mean(csU, t, n, lane);
+    const float mn = get_mean(csN, t, n, lane);
+    const int cb = t.ct * 16 + m;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int io = t.rt * 16 + 4 * kq + v;
+      if (io < n && cb < nc) {
+        const int s = t.ax * n * nc + io * nc + cb;
+        const float gu = accU[q][v] + mu;
+        const float gfp = fw != 0.f ? -2.f * rho * fw * (nxt[St + s] - cur[St + s]) : 0.f;
+        const float gl = glam[s];
+        gR[s] = fmaf(-2.f * rho, gu, fmaf(-rho, gl, gfp));
+        glam[s] = gl + gu;
+        gxi[s] += gu;
+        gn[s] = accN[q][v] + mn;
+      }
+    }
+  }
+}
+
+// Window units of one reverse iteration: positions X = W xb (with boxes) and
+// G = W g_R, masks, the VJP H and its W^T share into part.
+template <int NT, int KS>
+__device__ __forceinline__ void adjoint_units(const Ctx& C, int Tce, const float* xb,
+                                              const float* gR, float2* X, float2* G, float2* Hb,
+                                              float* part, bool accumulate) {
+  const int lane = lane_here(C.tid), wave = C.tid >> 6, nwaves = NT >> 6;
+  const int nwin = nwindows(Tce);
+  const int H = parts_per_window(C.n, nwin, nwaves);
+  const int Ts = C.Ts(), nws = C.nws(), ow = C.ow();
+  for (int u = wave; u < nwin * H; u += nwaves) {
+    const int w = u / H, h = u - w * H;
+    xmap_window<KS, true>(C.W, C.nc, xb, C.n, reinterpret_cast<float*>(X), Ts, w, Tce,
+                          reinterpret_cast<float*>(C.box), nws, lane);
+    xmap_window<KS, false>(C.W, C.nc, gR, C.n, reinterpret_cast<float*>(G), Ts, w, Tce,
+                           nullptr, nws, lane);
+    wave_fence();
+    masks_window(C.box, C.n, C.obs, C.M, C.a, C.masks, nws, ow, w, h, H, lane);
+    wave_fence();
+    vjp_window(X, G, Hb, C.n, Ts, C.obs, C.masks, nws, ow, C.a, C.pmin0, C.pmin1, C.pmax0,
+               C.pmax1, w, Tce, h, H, lane);
+    wave_fence();
+    wtmap_window<KS>(C.W, C.nc, reinterpret_cast<const float*>(Hb), C.n, Ts, w, Tce, h, H,
+                     part + (size_t)w * C.S, accumulate, lane);
+  }
+  __syncthreads();
+}
+
+template <int NT, int KS>
 __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
   extern __shared__ float4 sm4[];
   float* sm = reinterpret_cast<float*>(sm4);
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6, nwaves = NT >> 6;
+  const int wave = tid >> 6;
   const int b = A.order[blockIdx.x];
   const ProbDesc P = A.probs[b];
   const int n = P.n, M = P.M, nc = A.nc, T = A.T, Tc = A.Tc;
   const int S = 2 * n * nc;
   const int fs = fac_stride(nc);
-  const int nc2 = nc * nc;
-  const float rho = A.rho, w = A.fp_weight;
+  const float rho = A.rho, fw = A.fp_weight;
   const size_t St = (size_t)A.S_total;
   BwdLds L = carve_bwd(sm, nc, Tc, A.n_max, A.M_max, A.S_max);
   Ctx C{n,         M,         nc,        T,   Tc,    S,   tid,   rho,   P.a,     P.pmin[0],
         P.pmin[1], P.pmax[0], P.pmax[1], L.W, L.fac, A.W, L.obs, L.box, L.masks, Tc < T};
   const int nwin0 = nwindows(min(Tc, T));
-  const int Ts = C.Ts(), nws = C.nws(), pw = C.pw(), ow = C.ow();
   if (!C.chunked) load_wchunk(A.W, L.W, nc, 0, T, tid, NT);
   for (int t = tid; t < fs; t += NT) L.fac[t] = A.fac[(size_t)P.fac * fs + t];
   for (int m = tid; m < M; m += NT) {
@@ -1046,7 +1341,7 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
     for (int s = tid; s < S; s += NT) L.b0[s] = A.fin[P.coef_off + s];
     __syncthreads();
     float r1sq = 0.f, r2sq = 0.f;
-    residual_norms<NT>(C, L.b0, L.X, L.G, r1sq, r2sq);
+    residual_norms<NT, KS>(C, L.b0, L.X, L.G, r1sq, r2sq);
     float v[2] = {r1sq, r2sq};
     block_sum(v, L.red);
     const float c1 = v[0] > 0.f ? gr1 / sqrtf(v[0]) : 0.f;
@@ -1055,7 +1350,7 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
     for (int k0 = 0; k0 < T; k0 += Tc) {
       const int Tce = min(Tc, T - k0);
       C.wchunk<NT>(k0, Tce);
-      chunk_units<NT>(C, Tce, L.b0, L.X, L.H, L.part, k0 > 0, false, d1, d2, c1, c2);
+      chunk_units<NT, KS>(C, Tce, L.b0, L.X, L.H, L.part, k0 > 0, false, d1, d2, c1, c2);
     }
     add_partials(gx, L.part, nwin0, S, tid, NT);
     __syncthreads();
@@ -1065,6 +1360,7 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
   const int nseg = (L_ + k - 1) / k;
   float dz = 0.f;
   bool pending = false;   // L.part holds W^T VJP partials not yet added to gx
+  floatx4 accU[tiles_per_wave(NT)], accN[tiles_per_wave(NT)];
   for (int seg = nseg - 1; seg >= 0; --seg) {
     const int l0 = seg * k;
     const int l1 = min(L_, l0 + k);
@@ -1072,12 +1368,14 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
     {
       float* xr = L.b0;
       float* xq = L.b1;
+      float* lr = L.b2;
+      float* lq = L.b3;
       const float* ck = A.ckpt + (size_t)seg * 2 * St + P.coef_off;
       float* sg = A.seg + P.coef_off;
       for (int s = tid; s < S; s += NT) {
         const float x = ck[s], lm = ck[St + s];
         xr[s] = x;
-        L.b2[s] = lm;
+        lr[s] = lm;
         sg[s] = x;
         sg[St + s] = lm;
       }
@@ -1088,14 +1386,17 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
       }
       __syncthreads();
       for (int l = l0; l < l1 - 1; ++l) {
-        sf_iteration<NT>(C, xr, xq, L.b2, L.b3, L.means, L.X, L.G, L.part, L.cx, false, dz);
+        sf_iteration<NT, KS>(C, xr, xq, lr, lq, L.csum, L.X, L.G, L.part, L.cx, false, dz);
         float* t = xr;
         xr = xq;
         xq = t;
+        t = lr;
+        lr = lq;
+        lq = t;
         float* dst = A.seg + (size_t)(l + 1 - l0) * 2 * St + P.coef_off;
         for (int s = tid; s < S; s += NT) {
           dst[s] = xr[s];
-          dst[St + s] = L.b2[s];
+          dst[St + s] = lr[s];
         }
       }
       __syncthreads();
@@ -1107,68 +1408,20 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
                                       : A.ckpt + (size_t)(seg + 1) * 2 * St + P.coef_off;
       float* xbl = L.b0;
       float* gR = L.b2;
-      float* fpx = L.b3;
-      for (int s = tid; s < S; s += NT) {
-        const float xl = cur[s];
-        xbl[s] = xl;
-        float g = gx[s];
-        if (pending) {
-          float r = L.part[s];
-          for (int ww = 1; ww < nwin0; ++ww) r += L.part[(size_t)ww * S + s];
-          g += r;
-        }
-        if (w != 0.f) {
-          const float dxi = nxt[s] - xl;
-          const float dla = nxt[St + s] - cur[St + s];
-          g = fmaf(2.f * w, dxi, g);
-          fpx[s] = -2.f * w * dxi;
-          gR[s] = -2.f * rho * w * dla;
-        } else {
-          fpx[s] = 0.f;
-          gR[s] = 0.f;
-        }
-        gx[s] = g;
-      }
+      for (int s = tid; s < S; s += NT) xbl[s] = cur[s];
+      int lane = lane_here(tid);
+      update_bwd_p1<NT, KS>(L.fac, nc, n, gx, pending ? L.part : nullptr, nwin0, S, cur, nxt, fw,
+                            L.csum, L.csum + kColSums, accU, accN, wave, lane);
       pending = false;
       __syncthreads();
-      robot_means(gx, nullptr, n, nc, L.means, wave, nwaves, lane);
-      __syncthreads();
-      // g_u = S^T g (mode form) feeds g_R, g_lambda and g_xi; g' = SH^T g + fp term
-      mode_mfma(
-          L.fac, nc, n, gx, L.means, 0, nullptr, nullptr, 0, true, nullptr,
-          [&](int ax, int i, int c, float gu) {
-            const int s = ax * n * nc + i * nc + c;
-            gR[s] = fmaf(-2.f * rho, gu, fmaf(-rho, L.glam[s], gR[s]));
-            L.glam[s] += gu;
-            L.gxi[s] += gu;
-          },
-          wave, nwaves, lane);
-      mode_mfma(
-          L.fac, nc, n, gx, L.means, 2 * nc2, nullptr, nullptr, 0, true, fpx,
-          [&](int ax, int i, int c, float v) { gn[ax * n * nc + i * nc + c] = v; }, wave,
-          nwaves, lane);
+      lane = lane_here(tid);
+      update_bwd_p2<NT>(nc, n, L.csum, L.csum + kColSums, accU, accN, rho, fw, cur, nxt, St,
+                        L.glam, L.gxi, gR, gn, wave, lane);
       __syncthreads();
       for (int k0 = 0; k0 < T; k0 += Tc) {
         const int Tce = min(Tc, T - k0);
         C.wchunk<NT>(k0, Tce);
-        const int nwin = nwindows(Tce);
-        const int Hp = parts_per_window(n, nwin, nwaves);
-        for (int u = wave; u < nwin * Hp; u += nwaves) {
-          const int wn = u / Hp, h = u - wn * Hp;
-          xmap_window(L.W, nc, xbl, n, reinterpret_cast<float*>(L.X), Ts, wn, Tce,
-                      reinterpret_cast<float*>(L.box), nws, lane);
-          xmap_window(L.W, nc, gR, n, reinterpret_cast<float*>(L.G), Ts, wn, Tce, nullptr, nws,
-                      lane);
-          wave_fence();
-          masks_window(L.box, n, L.obs, M, P.a, L.masks, nws, pw, ow, wn, h, Hp, lane);
-          wave_fence();
-          vjp_window(L.X, L.G, L.H, n, Ts, L.obs, L.masks, nws, pw, ow, P.a, P.pmin[0],
-                     P.pmin[1], P.pmax[0], P.pmax[1], wn, Tce, h, Hp, lane);
-          wave_fence();
-          wtmap_window(L.W, nc, reinterpret_cast<const float*>(L.H), n, Ts, wn, Tce, h, Hp,
-                       L.part + (size_t)wn * S, k0 > 0, lane);
-        }
-        __syncthreads();
+        adjoint_units<NT, KS>(C, Tce, xbl, gR, L.X, L.G, L.H, L.part, k0 > 0);
       }
       pending = true;
       float* t = gx;
@@ -1191,23 +1444,24 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
 
 size_t bwd_lds_bytes(int nc, int T, int Tc, int n_max, int M_max, int S_max, int) {
   auto r4 = [](int x) { return (size_t)((x + 3) & ~3); };
-  size_t f = r4(nc * Tc) + r4(fac_stride(nc)) + kRed + kMeans + (9 + nwindows(Tc)) * r4(S_max) +
+  size_t f = r4(nc * Tc) + r4(fac_stride(nc)) + kRed + 2 * kColSums + (9 + nwindows(Tc)) * r4(S_max) +
              4 * (size_t)M_max + box_floats(Tc, n_max) + mask_floats(Tc, n_max, M_max) +
              6 * (size_t)n_max * tstride(Tc);
   return f * sizeof(float);
 }
 
-hipError_t launch_bwd_fused(const BwdArgs& a, int threads, size_t lds, hipStream_t s) {
+template <int KS>
+hipError_t launch_bwd_ks(const BwdArgs& a, int threads, size_t lds, hipStream_t s) {
   dim3 grid(a.B);
   switch (threads) {
     case 256:
-      hipLaunchKernelGGL(bwd_fused_kernel<256>, grid, dim3(256), lds, s, a);
+      hipLaunchKernelGGL((bwd_fused_kernel<256, KS>), grid, dim3(256), lds, s, a);
       break;
     case 512:
-      hipLaunchKernelGGL(bwd_fused_kernel<512>, grid, dim3(512), lds, s, a);
+      hipLaunchKernelGGL((bwd_fused_kernel<512, KS>), grid, dim3(512), lds, s, a);
       break;
     case 1024:
-      hipLaunchKernelGGL(bwd_fused_kernel<1024>, grid, dim3(1024), lds, s, a);
+      hipLaunchKernelGGL((bwd_fused_kernel<1024, KS>), grid, dim3(1024), lds, s, a);
       break;
     default:
       return hipErrorInvalidValue;
@@ -1215,14 +1469,25 @@ hipError_t launch_bwd_fused(const BwdArgs& a, int threads, size_t lds, hipStream
   return hipGetLastError();
 }
 
+hipError_t launch_bwd_fused(const BwdArgs& a, int threads, size_t lds, hipStream_t s) {
+  return ks_class(a.nc) == 4 ? launch_bwd_ks<4>(a, threads, lds, s)
+                             : launch_bwd_ks<8>(a, threads, lds, s);
+}
+
 hipError_t prepare_kernels(size_t lds) {
   const void* fns[] = {
-      reinterpret_cast<const void*>(&fwd_fused_kernel<256>),
-      reinterpret_cast<const void*>(&fwd_fused_kernel<512>),
-      reinterpret_cast<const void*>(&fwd_fused_kernel<1024>),
-      reinterpret_cast<const void*>(&bwd_fused_kernel<256>),
-      reinterpret_cast<const void*>(&bwd_fused_kernel<512>),
-      reinterpret_cast<const void*>(&bwd_fused_kernel<1024>)};
+      reinterpret_cast<const void*>(&fwd_fused_kernel<256, 4>),
+      reinterpret_cast<const void*>(&fwd_fused_kernel<512, 4>),
+      reinterpret_cast<const void*>(&fwd_fused_kernel<1024, 4>),
+      reinterpret_cast<const void*>(&fwd_fused_kernel<256, 8>),
+      reinterpret_cast<const void*>(&fwd_fused_kernel<512, 8>),
+      reinterpret_cast<const void*>(&fwd_fused_kernel<1024, 8>),
+      reinterpret_cast<const void*>(&bwd_fused_kernel<256, 4>),
+      reinterpret_cast<const void*>(&bwd_fused_kernel<512, 4>),
+      reinterpret_cast<const void*>(&bwd_fused_kernel<1024, 4>),
+      reinterpret_cast<const void*>(&bwd_fused_kernel<256, 8>),
+      reinterpret_cast<const void*>(&bwd_fused_kernel<512, 8>),
+      reinterpret_cast<const void*>(&bwd_fused_kernel<1024, 8>)};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -1245,7 +1510,7 @@ __global__ __launch_bounds__(256) void plain_prep_kernel(FwdArgs A, PlainBufs Bf
   const float* fac = A.fac + (size_t)P.fac * fac_stride(nc);
   const float* tgt = A.xi + P.coef_off;
   const float* bnd = A.boundary + (size_t)P.rob_off * 4;
-  robot_means(tgt, nullptr, n, nc, means, tid >> 6, 4, tid & 63);
+  robot_means(tgt, n, nc, means, tid >> 6, 4, tid & 63);
   boundary_means(bnd, n, means + 2 * nc, tid, 256);
   __syncthreads();
   for (int s = tid; s < S; s += 256) {
@@ -1258,13 +1523,14 @@ __global__ __launch_bounds__(256) void plain_prep_kernel(FwdArgs A, PlainBufs Bf
 }
 
 // Positions of every window (one window per wave).
+template <int KS>
 __global__ __launch_bounds__(256) void plain_xmap_kernel(FwdArgs A, PlainBufs Bf, int b,
                                                          int pp) {
   const ProbDesc P = A.probs[b];
   const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (w >= nwindows(A.T)) return;
-  xmap_window(A.W, A.nc, Bf.xb[pp] + P.coef_off, P.n, Bf.X + (size_t)P.pos_off * 2, A.T, w, A.T,
-              nullptr, 0, threadIdx.x & 63);
+  xmap_window<KS, false>(A.W, A.nc, Bf.xb[pp] + P.coef_off, P.n, Bf.X + (size_t)P.pos_off * 2,
+                         A.T, w, A.T, nullptr, 0, threadIdx.x & 63);
 }
 
 __global__ __launch_bounds__(256) void plain_constraint_kernel(FwdArgs A, PlainBufs Bf,
@@ -1279,46 +1545,43 @@ __global__ __launch_bounds__(256) void plain_constraint_kernel(FwdArgs A, PlainB
 }
 
 // Per-window partials of W^T V (one window per wave, all column tiles).
+template <int KS>
 __global__ __launch_bounds__(256) void plain_wtmap_kernel(FwdArgs A, PlainBufs Bf, int b) {
   const ProbDesc P = A.probs[b];
   const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (w >= nwindows(A.T)) return;
   const int S = 2 * P.n * A.nc;
-  wtmap_window(A.W, A.nc, Bf.V + (size_t)P.pos_off * 2, P.n, A.T, w, A.T, 0, 1,
-               Bf.part + (size_t)nwindows(A.T) * P.coef_off + (size_t)w * S, false,
-               threadIdx.x & 63);
+  wtmap_window<KS>(A.W, A.nc, Bf.V + (size_t)P.pos_off * 2, P.n, A.T, w, A.T, 0, 1,
+                   Bf.part + (size_t)nwindows(A.T) * P.coef_off + (size_t)w * S, false,
+                   threadIdx.x & 63);
 }
 
-// Combine, lambda step, means and the xi_bar step (one block).
+// lambda buffer of ping-pong parity pp (the plain path alternates lam and R).
+__device__ __forceinline__ float* plain_lam(const PlainBufs& Bf, int pp) {
+  return pp ? Bf.R : Bf.lam;
+}
+
+// Combine, lambda step and the xi_bar step (one block, the fused update).
+template <int KS>
 __global__ __launch_bounds__(256) void plain_update_kernel(FwdArgs A, PlainBufs Bf, int b,
                                                            int pp, int last) {
-  __shared__ float means[kMeans];
+  __shared__ float csum[kColSums];
   __shared__ float red[kRed];
   const ProbDesc P = A.probs[b];
   const int n = P.n, nc = A.nc, S = 2 * n * nc, tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const float rho = A.rho;
   const float* fac = A.fac + (size_t)P.fac * fac_stride(nc);
-  float* R = Bf.R + P.coef_off;
-  float* lam = Bf.lam + P.coef_off;
-  float* xb = Bf.xb[pp] + P.coef_off;
+  const float* xb = Bf.xb[pp] + P.coef_off;
   float* xn = Bf.xb[pp ^ 1] + P.coef_off;
   const float* cx = Bf.cxi + P.coef_off;
   float dzsq = 0.f;
-  combine_lambda_means(Bf.part + (size_t)nwindows(A.T) * P.coef_off, nwindows(A.T), S, lam, R,
-                       xb, n, nc, rho, last, dzsq, means, wave, 4, lane);
+  floatx4 accP[tiles_per_wave(256)];
+  update_fwd_p1<256, KS>(fac, nc, n, Bf.part + (size_t)nwindows(A.T) * P.coef_off,
+                         nwindows(A.T), S, plain_lam(Bf, pp) + P.coef_off,
+                         plain_lam(Bf, pp ^ 1) + P.coef_off, xb, cx, A.rho, last, dzsq, csum,
+                         accP, wave, lane);
   __syncthreads();
-  mode_mfma(
-      fac, nc, n, R, means, 0, xb, means + 2 * nc, 2 * nc * nc, false, cx,
-      [&](int ax, int i, int c, float v) {
-        const int s = ax * n * nc + i * nc + c;
-        xn[s] = v;
-        if (last) {
-          const float d = v - xb[s];
-          dzsq = fmaf(d, d, dzsq);
-        }
-      },
-      wave, 4, lane);
+  update_fwd_p2<256>(nc, n, csum, accP, xb, xn, last, dzsq, wave, lane);
   if (last) {
     float v[1] = {dzsq};
     block_sum(v, red);
@@ -1337,7 +1600,7 @@ __global__ __launch_bounds__(256) void plain_final_kernel(FwdArgs A, PlainBufs B
                    A.obstacles + (size_t)P.obs_off * 3, P.M, P.a, P.pmin[0], P.pmin[1],
                    P.pmax[0], P.pmax[1], true, r1sq, r2sq, tid, 256);
   for (int s = tid; s < S; s += 256) {
-    const float x = Bf.xb[pp][P.coef_off + s], lm = Bf.lam[P.coef_off + s];
+    const float x = Bf.xb[pp][P.coef_off + s], lm = plain_lam(Bf, pp)[P.coef_off + s];
     A.xi_out[P.coef_off + s] = x;
     A.lam_out[P.coef_off + s] = lm;
     if (!isfinite(x) || !isfinite(lm)) bad = 1.f;
@@ -1368,16 +1631,19 @@ hipError_t launch_plain_problem(const FwdArgs& a, const PlainBufs& pb, int b, hi
   const int gw = (nwindows(a.T) + 3) / 4;     // four waves per block, a window per wave
   const int gc = (a.n_max * a.T + 255) / 256;
   hipLaunchKernelGGL(plain_prep_kernel, dim3(1), dim3(256), 0, s, a, pb, b);
+  const bool k4 = ks_class(a.nc) == 4;
+  auto xmap = k4 ? plain_xmap_kernel<4> : plain_xmap_kernel<8>;
+  auto wtmap = k4 ? plain_wtmap_kernel<4> : plain_wtmap_kernel<8>;
+  auto update = k4 ? plain_update_kernel<4> : plain_update_kernel<8>;
   int pp = 0;
   for (int l = 0; l < a.L; ++l) {
-    hipLaunchKernelGGL(plain_xmap_kernel, dim3(gw), dim3(256), 0, s, a, pb, b, pp);
+    hipLaunchKernelGGL(xmap, dim3(gw), dim3(256), 0, s, a, pb, b, pp);
     hipLaunchKernelGGL(plain_constraint_kernel, dim3(gc), dim3(256), 0, s, a, pb, b);
-    hipLaunchKernelGGL(plain_wtmap_kernel, dim3(gw), dim3(256), 0, s, a, pb, b);
-    hipLaunchKernelGGL(plain_update_kernel, dim3(1), dim3(256), 0, s, a, pb, b, pp,
-                       (int)(l == a.L - 1));
+    hipLaunchKernelGGL(wtmap, dim3(gw), dim3(256), 0, s, a, pb, b);
+    hipLaunchKernelGGL(update, dim3(1), dim3(256), 0, s, a, pb, b, pp, (int)(l == a.L - 1));
     pp ^= 1;
   }
-  hipLaunchKernelGGL(plain_xmap_kernel, dim3(gw), dim3(256), 0, s, a, pb, b, pp);
+  hipLaunchKernelGGL(xmap, dim3(gw), dim3(256), 0, s, a, pb, b, pp);
   hipLaunchKernelGGL(plain_final_kernel, dim3(1), dim3(256), 0, s, a, pb, b, pp);
   return hipGetLastError();
 }
