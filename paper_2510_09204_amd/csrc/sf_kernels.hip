@@ -80,6 +80,13 @@ __device__ __forceinline__ int lane_here(int tid) {
   return l;
 }
 
+// The wave's index in the block as a wave-uniform (scalar) value, so that
+// everything derived from it (unit, window, part, tile, robot ranges) is
+// scalar code and uniform control flow.
+__device__ __forceinline__ int wave_id(int tid) {
+  return __builtin_amdgcn_readfirstlane(tid >> 6);
+}
+
 // Orders the LDS accesses of one wave (its stores before its later loads).
 __device__ __forceinline__ void wave_fence() {
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -183,16 +190,39 @@ __device__ __forceinline__ int part_count(int n, int h, int H) {
   return cnt;
 }
 
+// Rounding margins of the candidate tests for a robot whose window box has
+// largest coordinate magnitude s: pairs use a(1 + 1e-4) + 4e-6 (1 + s + 2a),
+// obstacles r_o(1 + 1e-4) + 8e-6 r_o (on the obstacle's side) plus
+// 4e-6 (1 + s) (on the robot's side).  They exceed the distance threshold by
+// far more than the float rounding of the exact tests and of the box sums, so
+// a pair or obstacle outside them is inactive at every step of the window.
+//
+// Candidate lists are kept across iterations with a skin d (neighbour lists
+// in the molecular-dynamics sense): they are built with the pair margin
+// widened by 2d and the robot-side obstacle margin by d, together with a
+// reference copy of every robot's box.  As long as no robot's box has grown
+// by more than d beyond its reference in any direction, every pair or
+// obstacle that can be active is still on the lists; the first iteration in
+// which one has, rebuilds the window's lists.  Culling stays exact.
+__device__ __forceinline__ float pair_margin(float a, float s) {
+  return fmaf(4e-6f, 1.f + s + 2.f * a, a * 1.0001f);
+}
+__device__ __forceinline__ float robot_obs_margin(float s) { return 4e-6f * (1.f + s); }
+__device__ __forceinline__ float obs_margin(float ao) { return fmaf(8e-6f, ao, ao * 1.0001f); }
+
 // Coefficient -> time map of window w for all robots: X[i][16w + r].axis =
 // sum_c W[16w + r][c] xb[axis][i][c] for steps < Tce (padding rows repeat the
-// last step), and with BOX each robot's box (xmin, xmax, ymin, ymax) over the
-// window's steps.  Column tiles are taken four at a time with all their
-// operand loads issued before the MFMA chains.
+// last step).  With BOX, each robot's window box is stored three ways at
+// box3[(i nws + w) 3 + {0, 1, 2}]: as is (xmin, xmax, ymin, ymax), widened by
+// the pair margin, and widened by the robot-side obstacle margin.  Column tiles
+// are taken four at a time with all their operand loads issued before the
+// MFMA chains.
 template <int KS, bool BOX>
 __device__ __forceinline__ void xmap_window(const float* __restrict__ W, int nc,
                                             const float* __restrict__ xb, int n,
                                             float* __restrict__ Xf, int Ts, int w, int Tce,
-                                            float* __restrict__ boxf, int nws, int lane) {
+                                            float* __restrict__ box3, int nws, float a,
+                                            float skin, int lane) {
   const int ncol = (2 * n + 15) >> 4;
   const int m = lane & 15, kq = lane >> 4;
   const int row = min(w * 16 + m, Tce - 1);
@@ -200,10 +230,13 @@ __device__ __forceinline__ void xmap_window(const float* __restrict__ W, int nc,
 #pragma unroll
   for (int s = 0; s < KS; ++s) {
     const int c = 4 * s + kq;
-    const float v = W[row * nc + min(c, nc - 1)];
+    const float v = W[__umul24(row, nc) + min(c, nc - 1)];
     av[s] = c < nc ? v : 0.f;
   }
   const int k0 = w * 16 + 4 * kq;
+  // all 16 rows may be stored when the window is full or the row stride has
+  // room for the padding rows (which repeat the last step)
+  const bool whole = w * 16 + 16 <= Tce || Ts >= ((Tce + 15) & ~15);
   for (int nt0 = 0; nt0 < ncol; nt0 += 4) {
     float bv[4][KS];
 #pragma unroll
@@ -211,7 +244,7 @@ __device__ __forceinline__ void xmap_window(const float* __restrict__ W, int nc,
       const int col = (nt0 + g) * 16 + m;
       const bool ok = (col >> 1) < n;
       const int i = min(col >> 1, n - 1), ax = col & 1;
-      const float* brow = xb + ax * n * nc + i * nc;
+      const float* brow = xb + __umul24(ax * n + i, nc);
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
         const int c = 4 * s + kq;
@@ -233,75 +266,109 @@ __device__ __forceinline__ void xmap_window(const float* __restrict__ W, int nc,
       const int i = col >> 1, ax = col & 1;
       const bool colok = i < n;
       if (colok) {
+        float* xr = Xf + (__umul24(i, Ts) + k0) * 2 + ax;
+        if (whole) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-          if (k0 + v < Tce) Xf[((size_t)i * Ts + k0 + v) * 2 + ax] = acc[g][v];
+          for (int v = 0; v < 4; ++v) xr[2 * v] = acc[g][v];
+        } else {
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (k0 + v < Tce) xr[2 * v] = acc[g][v];
+        }
       }
       if (BOX) {
         float lo = fminf(fminf(acc[g][0], acc[g][1]), fminf(acc[g][2], acc[g][3]));
         float hi = fmaxf(fmaxf(acc[g][0], acc[g][1]), fmaxf(acc[g][2], acc[g][3]));
         lo = rows_reduce(lo, OpMin());
         hi = rows_reduce(hi, OpMax());
-        if (lane < 16 && colok)
-          *reinterpret_cast<float2*>(boxf + ((size_t)i * nws + w) * 4 + 2 * ax) =
-              make_float2(lo, hi);
+        // the other axis of the same robot sits in the neighbouring lane
+        float sv = fmaxf(fabsf(lo), fabsf(hi));
+        sv = fmaxf(sv, dpp_f<0xB1, 0xF>(0.f, sv));
+        const float am = fmaf(2.f, skin, pair_margin(a, sv));
+        const float e = robot_obs_margin(sv) + skin;
+        if (lane < 16 && colok) {
+          float* bx = box3 + (__umul24(i, nws) + w) * 12 + 2 * ax;
+          *reinterpret_cast<float2*>(bx) = make_float2(lo, hi);
+          *reinterpret_cast<float2*>(bx + 4) = make_float2(lo - am, hi + am);
+          *reinterpret_cast<float2*>(bx + 8) = make_float2(lo - e, hi + e);
+        }
       }
     }
   }
 }
 
-// Candidate masks of window w for the robots of part h: bit j of the pair
-// word set when robot j (j != i) has a box within a (plus margin) of robot
-// i's box in both axes; bit m of obstacle word q when obstacle 64q+m's disc
-// (plus margin) meets robot i's box.  Lane j tests robot j (or obstacle j) and
-// a ballot forms the word.  The margin covers rounding of the box comparison
-// and of the exact test at coordinates up to the box's magnitude plus the
-// threshold.
-__device__ __forceinline__ void masks_window(const float4* __restrict__ box, int n,
-                                             const float4* __restrict__ obs, int M, float a,
-                                             u64* __restrict__ masks, int nws, int ow, int w,
-                                             int h, int H, int lane) {
-  const int mw = 1 + ow;
+// Candidate masks (32-bit words) of window w for the robots of part h.  Word q
+// of robot i's pair mask (at mw[q * mrow + i]) has bit jj set when robot
+// j = 32 q + jj (j != i) has a window box meeting robot i's pair-widened box;
+// obstacle word q (at mw[(mpw + q) * mrow + i]) likewise for obstacle 32 q + jj
+// against the robot-side widened box, with obstacle boxes already widened by
+// their own margin.  A ballot tests two robots at once (lane = 32 slot + jj)
+// and one 64-bit store writes both words: robots t0 and t0 + 1 of a part are
+// adjacent rows.
+__device__ __forceinline__ void masks_window(const float4* __restrict__ box3, int n,
+                                             const float4* __restrict__ obox, int M,
+                                             unsigned* __restrict__ mw, int mrow, int mpw,
+                                             int nws, int w, int h, int H, int lane) {
   const int cnt = part_count(n, h, H);
-  {
-    const float4 bj = box[min(lane, n - 1) * nws + w];
-    const bool jl = lane < n;
-#pragma unroll 4
-    for (int t = 0; t < cnt; ++t) {
-      const int i = part_robot(t, h, H);
-      const float4 bi = box[i * nws + w];
-      const float si = fmaxf(fmaxf(fabsf(bi.x), fabsf(bi.y)), fmaxf(fabsf(bi.z), fabsf(bi.w)));
-      const float am = a * 1.0001f + 4e-6f * (1.f + si + 2.f * a);
-      const bool c = jl && (lane != i) && (bi.x < bj.y + am) && (bj.x < bi.y + am) &&
-                     (bi.z < bj.w + am) && (bj.z < bi.w + am);
-      const u64 mk = __builtin_amdgcn_ballot_w64(c);
-      if (lane == 0) masks[(size_t)(i * nws + w) * mw] = mk;
+  const int slot = lane >> 5, jj = lane & 31;
+  for (int q = 0; q < ((n + 31) >> 5); ++q) {
+    const int j = q * 32 + jj;
+    const float4 bj = box3[(__umul24(min(j, n - 1), nws) + w) * 3];
+    const bool jl = j < n;
+    for (int t0 = 0; t0 < cnt; t0 += 2) {
+      const bool tl = t0 + slot < cnt;
+      const int i = part_robot(tl ? t0 + slot : t0, h, H);
+      const float4 ei = box3[(__umul24(i, nws) + w) * 3 + 1];
+      const bool c = tl && jl && (j != i) && (ei.x < bj.y) && (bj.x < ei.y) && (ei.z < bj.w) &&
+                     (bj.z < ei.w);
+      const u64 b = __builtin_amdgcn_ballot_w64(c);
+      if (lane == 0)
+        *reinterpret_cast<u64*>(mw + q * mrow + part_robot(t0, h, H)) = b;
     }
   }
-  for (int wd = 0; wd < ow; ++wd) {
-    const int mo = wd * 64 + lane;
-    const float4 o = obs[min(mo, M - 1)];
+  for (int q = 0; q < ((M + 31) >> 5); ++q) {
+    const int mo = q * 32 + jj;
+    const float4 ob = obox[min(mo, M - 1)];
     const bool ml = mo < M;
-#pragma unroll 4
-    for (int t = 0; t < cnt; ++t) {
-      const int i = part_robot(t, h, H);
-      const float4 bi = box[i * nws + w];
-      const float si = fmaxf(fmaxf(fabsf(bi.x), fabsf(bi.y)), fmaxf(fabsf(bi.z), fabsf(bi.w)));
-      const float r = o.z * 1.0001f + 4e-6f * (1.f + si + 2.f * o.z);
-      const bool c = ml && (o.x - r < bi.y) && (bi.x < o.x + r) && (o.y - r < bi.w) &&
-                     (bi.z < o.y + r);
-      const u64 mk = __builtin_amdgcn_ballot_w64(c);
-      if (lane == 0) masks[(size_t)(i * nws + w) * mw + 1 + wd] = mk;
+    for (int t0 = 0; t0 < cnt; t0 += 2) {
+      const bool tl = t0 + slot < cnt;
+      const int i = part_robot(tl ? t0 + slot : t0, h, H);
+      const float4 ei = box3[(__umul24(i, nws) + w) * 3 + 2];
+      const bool c = tl && ml && (ob.x < ei.y) && (ei.x < ob.y) && (ob.z < ei.w) && (ei.z < ob.w);
+      const u64 b = __builtin_amdgcn_ballot_w64(c);
+      if (lane == 0)
+        *reinterpret_cast<u64*>(mw + (mpw + q) * mrow + part_robot(t0, h, H)) = b;
     }
   }
 }
 
-// Next candidate of a lane's mask (lowest set bit), or `none` when empty.
-__device__ __forceinline__ int pop_candidate(u64& u, int none) {
-  const bool ok = u != 0ull;
-  const int j = ok ? (int)__builtin_ctzll(u) : none;
-  u &= u - 1ull;
-  return j;
+// Neighbour-list check of window w (one lane per robot): true when some
+// robot's box has grown by more than the skin beyond its reference box (or a
+// box is not finite); the references for the next check are written to
+// ref_next (the current boxes after a rebuild, else unchanged).  Every wave
+// that works on the window computes the same answer from the same data.
+__device__ __forceinline__ bool lists_stale(const float4* __restrict__ box3,
+                                            const float4* __restrict__ ref,
+                                            float4* __restrict__ ref_next, int n, int nws, int w,
+                                            float skin, int lane) {
+  const int i = min(lane, n - 1);
+  const float4 b = box3[(__umul24(i, nws) + w) * 3];
+  const float4 r = ref[i];
+  const float g = fmaxf(fmaxf(r.x - b.x, b.y - r.y), fmaxf(r.z - b.z, b.w - r.w));
+  const bool moved = lane < n && !(g <= skin);
+  const bool stale = __builtin_amdgcn_ballot_w64(moved) != 0ull;
+  if (lane < n)
+    ref_next[i] = make_float4(stale ? b.x : r.x, stale ? b.y : r.y, stale ? b.z : r.z,
+                              stale ? b.w : r.w);
+  return stale;
+}
+
+// Next candidate of a lane's mask word (lowest set bit) plus base (a multiple
+// of 32), or -1 when the word is empty (find-first-bit gives -1 there).
+__device__ __forceinline__ int pop_candidate(unsigned& u, int base) {
+  const int b = __ffs(u) - 1;
+  u &= u - 1u;
+  return b | base;
 }
 
 // Residual vector of a pair at difference (dx, dy) with d2 = |D|^2 < a^2:
@@ -322,16 +389,15 @@ __device__ __forceinline__ void pair_residual(float dx, float dy, float d2, floa
 // Exact constraint stage of window w for the robots of part h (a 16-lane row
 // per robot, one lane per step): V = w_pair (pair + obstacle sums) + w_box
 // (box residual).  Each row walks its own robot's candidates in increasing
-// index (pairs, then obstacles), four per round so their loads overlap;
+// index (pairs, then obstacles), two per round so their loads overlap;
 // skipped pairs are inactive and would add exactly 0.  With `accum`,
 // ||r_1||^2 (each unordered pair once) and ||r_2||^2.
 __device__ __forceinline__ void constraints_window(
     const float2* __restrict__ X, float2* __restrict__ V, int n, int Ts,
-    const float4* __restrict__ obs, const u64* __restrict__ masks, int nws, int ow, float a,
-    float pmin0, float pmin1, float pmax0, float pmax1, int w, int Tce, int h, int H,
+    const float4* __restrict__ obs, int M, const unsigned* __restrict__ mw, int mrow, int mpw,
+    float a, float pmin0, float pmin1, float pmax0, float pmax1, int w, int Tce, int h, int H,
     bool accum, float& r1sq, float& r2sq, float w_pair, float w_box, int lane) {
   const float a2 = a * a;
-  const int mw = 1 + ow;
   const int kk = w * 16 + (lane & 15);
   const int kq = min(kk, Tce - 1);
   const int cnt = part_count(n, h, H);
@@ -339,19 +405,19 @@ __device__ __forceinline__ void constraints_window(
     const int t = t0 + (lane >> 4);
     const bool live = t < cnt;
     const int i = part_robot(live ? t : t0, h, H);
-    const u64* my = masks + (size_t)(i * nws + w) * mw;
-    const float2 p = X[i * Ts + kq];
+    const float2 p = X[__umul24(i, Ts) + kq];
     float vx = 0.f, vy = 0.f, s1 = 0.f;
-    u64 u = live ? my[0] : 0ull;
-    while (u != 0ull) {
-      int j[4];
-      float2 o[4];
+    for (int wq = 0; wq < ((n + 31) >> 5); ++wq) {
+    unsigned u = live ? mw[wq * mrow + i] : 0u;
+    while (u != 0u) {
+      int j[2];
+      float2 o[2];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) j[q] = pop_candidate(u, -1);
+      for (int q = 0; q < 2; ++q) j[q] = pop_candidate(u, wq * 32);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) o[q] = X[max(j[q], 0) * Ts + kq];
+      for (int q = 0; q < 2; ++q) o[q] = X[__umul24(max(j[q], 0), Ts) + kq];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < 2; ++q) {
         const float dx = p.x - o[q].x;
         const float dy = p.y - o[q].y;
         const float d2 = fmaf(dy, dy, dx * dx);
@@ -364,17 +430,18 @@ __device__ __forceinline__ void constraints_window(
         }
       }
     }
-    for (int wd = 0; wd < ow; ++wd) {
-      u = live ? my[1 + wd] : 0ull;
-      while (u != 0ull) {
-        int mq[4];
-        float4 ob[4];
+    }
+    for (int wd = 0; wd < ((M + 31) >> 5); ++wd) {
+      unsigned u = live ? mw[(mpw + wd) * mrow + i] : 0u;
+      while (u != 0u) {
+        int mq[2];
+        float4 ob[2];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) mq[q] = pop_candidate(u, -1);
+        for (int q = 0; q < 2; ++q) mq[q] = pop_candidate(u, wd * 32);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) ob[q] = obs[wd * 64 + max(mq[q], 0)];
+        for (int q = 0; q < 2; ++q) ob[q] = obs[max(mq[q], 0)];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < 2; ++q) {
           const float dx = p.x - ob[q].x;
           const float dy = p.y - ob[q].y;
           const float d2 = fmaf(dy, dy, dx * dx);
@@ -393,7 +460,7 @@ __device__ __forceinline__ void constraints_window(
     vx = fmaf(w_box, hx - lx, w_pair * vx);
     vy = fmaf(w_box, hy - ly, w_pair * vy);
     if (live && kk < Tce) {
-      V[i * Ts + kk] = make_float2(vx, vy);
+      V[__umul24(i, Ts) + kk] = make_float2(vx, vy);
       if (accum) {
         r1sq += s1;
         r2sq += hx * hx + lx * lx + hy * hy + ly * ly;
@@ -429,11 +496,11 @@ __device__ __forceinline__ void vjp_term(float dx, float dy, float d2, float a, 
 __device__ __forceinline__ void vjp_window(const float2* __restrict__ X,
                                            const float2* __restrict__ G, float2* __restrict__ Hb,
                                            int n, int Ts, const float4* __restrict__ obs,
-                                           const u64* __restrict__ masks, int nws, int ow, float a,
-                                           float pmin0, float pmin1, float pmax0, float pmax1,
-                                           int w, int Tce, int h, int H, int lane) {
+                                           int M, const unsigned* __restrict__ mw, int mrow,
+                                           int mpw, float a, float pmin0, float pmin1,
+                                           float pmax0, float pmax1, int w, int Tce, int h, int H,
+                                           int lane) {
   const float a2 = a * a;
-  const int mw = 1 + ow;
   const int kk = w * 16 + (lane & 15);
   const int kq = min(kk, Tce - 1);
   const int cnt = part_count(n, h, H);
@@ -441,40 +508,41 @@ __device__ __forceinline__ void vjp_window(const float2* __restrict__ X,
     const int t = t0 + (lane >> 4);
     const bool live = t < cnt;
     const int i = part_robot(live ? t : t0, h, H);
-    const u64* my = masks + (size_t)(i * nws + w) * mw;
-    const float2 p = X[i * Ts + kq];
-    const float2 gi = G[i * Ts + kq];
+    const float2 p = X[__umul24(i, Ts) + kq];
+    const float2 gi = G[__umul24(i, Ts) + kq];
     float hx = 0.f, hy = 0.f;
-    u64 u = live ? my[0] : 0ull;
-    while (u != 0ull) {
-      int j[4];
-      float2 o[4], gj[4];
+    for (int wq = 0; wq < ((n + 31) >> 5); ++wq) {
+    unsigned u = live ? mw[wq * mrow + i] : 0u;
+    while (u != 0u) {
+      int j[2];
+      float2 o[2], gj[2];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) j[q] = pop_candidate(u, -1);
+      for (int q = 0; q < 2; ++q) j[q] = pop_candidate(u, wq * 32);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        o[q] = X[max(j[q], 0) * Ts + kq];
-        gj[q] = G[max(j[q], 0) * Ts + kq];
+      for (int q = 0; q < 2; ++q) {
+        o[q] = X[__umul24(max(j[q], 0), Ts) + kq];
+        gj[q] = G[__umul24(max(j[q], 0), Ts) + kq];
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < 2; ++q) {
         const float dx = p.x - o[q].x;
         const float dy = p.y - o[q].y;
         const float d2 = fmaf(dy, dy, dx * dx);
         if (j[q] >= 0 && d2 < a2) vjp_term(dx, dy, d2, a, gi.x - gj[q].x, gi.y - gj[q].y, hx, hy);
       }
     }
-    for (int wd = 0; wd < ow; ++wd) {
-      u = live ? my[1 + wd] : 0ull;
-      while (u != 0ull) {
-        int mq[4];
-        float4 ob[4];
+    }
+    for (int wd = 0; wd < ((M + 31) >> 5); ++wd) {
+      unsigned u = live ? mw[(mpw + wd) * mrow + i] : 0u;
+      while (u != 0u) {
+        int mq[2];
+        float4 ob[2];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) mq[q] = pop_candidate(u, -1);
+        for (int q = 0; q < 2; ++q) mq[q] = pop_candidate(u, wd * 32);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) ob[q] = obs[wd * 64 + max(mq[q], 0)];
+        for (int q = 0; q < 2; ++q) ob[q] = obs[max(mq[q], 0)];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < 2; ++q) {
           const float dx = p.x - ob[q].x;
           const float dy = p.y - ob[q].y;
           const float d2 = fmaf(dy, dy, dx * dx);
@@ -484,7 +552,7 @@ __device__ __forceinline__ void vjp_window(const float2* __restrict__ X,
     }
     if (p.x > pmax0 || p.x < pmin0) hx += gi.x;
     if (p.y > pmax1 || p.y < pmin1) hy += gi.y;
-    if (live && kk < Tce) Hb[i * Ts + kk] = make_float2(hx, hy);
+    if (live && kk < Tce) Hb[__umul24(i, Ts) + kk] = make_float2(hx, hy);
   }
 }
 
@@ -508,7 +576,7 @@ __device__ __forceinline__ void wtmap_window(const float* __restrict__ W, int nc
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int kk = w * 16 + 4 * s + kq;
-      const float v = W[min(kk, Tce - 1) * nc + min(ca, nc - 1)];
+      const float v = W[__umul24(min(kk, Tce - 1), nc) + min(ca, nc - 1)];
       av[ct][s] = (kk < Tce && ca < nc) ? v : 0.f;
     }
   }
@@ -516,7 +584,7 @@ __device__ __forceinline__ void wtmap_window(const float* __restrict__ W, int nc
     const int col = nt * 16 + m;
     const int i = col >> 1, ax = col & 1;
     const bool colok = i < n;
-    const float* vrow = Vf + (size_t)min(i, n - 1) * Ts * 2 + ax;
+    const float* vrow = Vf + __umul24(min(i, n - 1), Ts) * 2 + ax;
     float bv[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -535,7 +603,7 @@ __device__ __forceinline__ void wtmap_window(const float* __restrict__ W, int nc
         for (int v = 0; v < 4; ++v) {
           const int c = ct * 16 + 4 * kq + v;
           if (c >= nc) continue;
-          const int sidx = ax * n * nc + i * nc + c;
+          const int sidx = __umul24(ax * n + i, nc) + c;
           part_w[sidx] = accumulate ? part_w[sidx] + acc[v] : acc[v];
         }
       }
@@ -617,7 +685,7 @@ __device__ __forceinline__ void mode_tile(const float* __restrict__ fac, int nc,
     const int k = 4 * s + kq;
     const int kc = min(k, nc - 1);
     const bool ok = k < nc && cb < nc;
-    const int idx = trans ? kc * nc + cbc : cbc * nc + kc;
+    const int idx = trans ? __umul24(kc, nc) + cbc : __umul24(cbc, nc) + kc;
     const float p = fac[fo + idx], d = fac[fo + nc2 + idx];
     bp[s] = ok ? p : 0.f;
     bd[s] = ok ? d : 0.f;
@@ -670,12 +738,12 @@ __device__ __forceinline__ void update_fwd_p1(const float* __restrict__ fac, int
     float r[KS];
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
-      sidx[s] = t.ax * n * nc + ic * nc + min(4 * s + kq, nc - 1);
+      sidx[s] = __umul24(t.ax * n + ic, nc) + min(4 * s + kq, nc - 1);
       r[s] = part[sidx[s]];
     }
     for (int w = 1; w < nwin; ++w) {
 #pragma unroll
-      for (int s = 0; s < KS; ++s) r[s] += part[(size_t)w * S + sidx[s]];
+      for (int s = 0; s < KS; ++s) r[s] += part[w * S + sidx[s]];
     }
     float au[KS], axb[KS];
 #pragma unroll
@@ -694,7 +762,7 @@ __device__ __forceinline__ void update_fwd_p1(const float* __restrict__ fac, int
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int io = t.rt * 16 + 4 * kq + v;
-      const float c0 = cx[t.ax * n * nc + min(io, n - 1) * nc + min(cb, nc - 1)];
+      const float c0 = cx[__umul24(t.ax * n + min(io, n - 1), nc) + min(cb, nc - 1)];
       accP[q][v] = (io < n && cb < nc) ? c0 : 0.f;
     }
     floatx4 accD = {0.f, 0.f, 0.f, 0.f};
@@ -724,7 +792,7 @@ __device__ __forceinline__ void update_fwd_p2(int nc, int n, const float* __rest
     for (int v = 0; v < 4; ++v) {
       const int io = t.rt * 16 + 4 * kq + v;
       if (io < n && cb < nc) {
-        const int s = t.ax * n * nc + io * nc + cb;
+        const int s = __umul24(t.ax * n + io, nc) + cb;
         const float val = accP[q][v] + mean;
         xn[s] = val;
         if (last) {
@@ -846,19 +914,46 @@ __device__ __forceinline__ void load_wchunk(const float* __restrict__ Wg, float*
   for (int t = tid; t < Tce * nc; t += nthr) W[t] = Wg[k0 * nc + t];
 }
 
+// Rows of the mask arrays (robots, padded so that a ballot's two robots and
+// its 64-bit store stay inside) and 32-bit words per window.
+__host__ __device__ inline int mask_rows(int n_max) { return (n_max + 7) & ~7; }
+__host__ __device__ inline int mask_words(int n_max, int M_max) {
+  return (((n_max + 31) >> 5) + ((M_max + 31) >> 5)) * mask_rows(n_max);
+}
+
 struct Ctx {
   int n, M, nc, T, Tc, S, tid;
   float rho, a, pmin0, pmin1, pmax0, pmax1;
   float* W;
   const float *fac, *Wg;
-  const float4* obs;
-  float4* box;
-  u64* masks;
+  const float4* obs;    // (cx, cy, a_o, a_o^2)
+  const float4* obox;   // obstacle boxes widened by their margin
+  float* box3;          // window boxes: raw, pair-widened, robot-side widened
+  unsigned* masks;      // [chunk window][word][row]
+  float4* vref;         // [2][chunk window][n_max] reference boxes of the lists
+  int mrow, mpw, mstride, nwt, n_max;
+  float skin;
   bool chunked;  // T > Tc: the LDS W table holds one time chunk at a time
 
   __device__ __forceinline__ int Ts() const { return tstride(Tc); }
   __device__ __forceinline__ int nws() const { return nwindows(Tc); }
-  __device__ __forceinline__ int ow() const { return (M + 63) >> 6; }
+  __device__ __forceinline__ unsigned* mwin(int gw) const { return masks + gw * mstride; }
+
+  // Check window gw's candidate lists against the boxes just computed for
+  // local window w and rebuild this part's lists when they are stale.  The
+  // reference boxes alternate between two buffers from pass to pass (parity).
+  __device__ __forceinline__ void refresh_lists(int gw, int w, int h, int H, int parity,
+                                                int lane) const {
+    const float4* b3 = reinterpret_cast<const float4*>(box3);
+    if (chunked) {
+      masks_window(b3, n, obox, M, mwin(w), mrow, mpw, nws(), w, h, H, lane);
+      return;
+    }
+    const float4* ref = vref + (parity * nwt + gw) * n_max;
+    float4* nxt = vref + ((parity ^ 1) * nwt + gw) * n_max;
+    if (lists_stale(b3, ref, nxt, n, nws(), w, skin, lane))
+      masks_window(b3, n, obox, M, mwin(gw), mrow, mpw, nws(), w, h, H, lane);
+  }
 
   // Make the LDS W table hold rows k0 .. k0+Tce-1 (block-wide; no-op when
   // the whole horizon is resident).
@@ -876,27 +971,29 @@ struct Ctx {
 // the windows' shares of W^T V into part[w][S] (added when `accumulate`).
 // Leaves the block synchronised.
 template <int NT, int KS>
-__device__ __forceinline__ void chunk_units(const Ctx& C, int Tce, const float* xb, float2* X,
-                                            float2* V, float* part, bool accumulate, bool accum,
-                                            float& r1sq, float& r2sq, float w_pair,
-                                            float w_box) {
-  const int lane = lane_here(C.tid), wave = C.tid >> 6, nwaves = NT >> 6;
+__device__ __forceinline__ void chunk_units(const Ctx& C, int chunk, int Tce, const float* xb,
+                                            float2* X, float2* V, float* part, bool accumulate,
+                                            bool accum, float& r1sq, float& r2sq, float w_pair,
+                                            float w_box, int parity) {
+  const int lane = lane_here(C.tid), wave = wave_id(C.tid), nwaves = NT >> 6;
   const int nwin = nwindows(Tce);
   const int H = parts_per_window(C.n, nwin, nwaves);
-  const int Ts = C.Ts(), nws = C.nws(), ow = C.ow();
+  const int Ts = C.Ts(), nws = C.nws();
   for (int u = wave; u < nwin * H; u += nwaves) {
     const int w = u / H, h = u - w * H;
-    xmap_window<KS, true>(C.W, C.nc, xb, C.n, reinterpret_cast<float*>(X), Ts, w, Tce,
-                          reinterpret_cast<float*>(C.box), nws, lane);
+    const int gw = chunk * nws + w;
+    xmap_window<KS, true>(C.W, C.nc, xb, C.n, reinterpret_cast<float*>(X), Ts, w, Tce, C.box3,
+                          nws, C.a, C.skin, lane);
     wave_fence();
-    masks_window(C.box, C.n, C.obs, C.M, C.a, C.masks, nws, ow, w, h, H, lane);
+    C.refresh_lists(gw, w, h, H, parity, lane);
     wave_fence();
-    constraints_window(X, V, C.n, Ts, C.obs, C.masks, nws, ow, C.a, C.pmin0, C.pmin1, C.pmax0,
-                       C.pmax1, w, Tce, h, H, accum, r1sq, r2sq, w_pair, w_box, lane);
+    constraints_window(X, V, C.n, Ts, C.obs, C.M, C.mwin(C.chunked ? w : gw), C.mrow, C.mpw, C.a,
+                       C.pmin0, C.pmin1, C.pmax0, C.pmax1, w, Tce, h, H, accum, r1sq, r2sq,
+                       w_pair, w_box, lane);
     if (part) {
       wave_fence();
       wtmap_window<KS>(C.W, C.nc, reinterpret_cast<const float*>(V), C.n, Ts, w, Tce, h, H,
-                       part + (size_t)w * C.S, accumulate, lane);
+                       part + w * C.S, accumulate, lane);
     }
   }
   __syncthreads();
@@ -908,14 +1005,15 @@ template <int NT, int KS>
 __device__ __forceinline__ void sf_iteration(const Ctx& C, const float* xb, float* xn,
                                              const float* lam, float* lam_n, float* csum,
                                              float2* X, float2* V, float* part, const float* cx,
-                                             bool last, float& dzsq) {
-  const int wave = C.tid >> 6;
+                                             bool last, float& dzsq, int& epoch) {
+  const int wave = wave_id(C.tid);
   float d1 = 0.f, d2 = 0.f;
-  for (int k0 = 0; k0 < C.T; k0 += C.Tc) {
+  for (int k0 = 0, ch = 0; k0 < C.T; k0 += C.Tc, ++ch) {
     const int Tce = min(C.Tc, C.T - k0);
     C.wchunk<NT>(k0, Tce);
-    chunk_units<NT, KS>(C, Tce, xb, X, V, part, k0 > 0, false, d1, d2, 1.f, 1.f);
+    chunk_units<NT, KS>(C, ch, Tce, xb, X, V, part, k0 > 0, false, d1, d2, 1.f, 1.f, epoch & 1);
   }
+  ++epoch;
   floatx4 accP[tiles_per_wave(NT)];
   int lane = lane_here(C.tid);
   update_fwd_p1<NT, KS>(C.fac, C.nc, C.n, part, nwindows(min(C.Tc, C.T)), C.S, lam, lam_n, xb,
@@ -930,32 +1028,52 @@ __device__ __forceinline__ void sf_iteration(const Ctx& C, const float* xb, floa
 // return); V is scratch.
 template <int NT, int KS>
 __device__ __forceinline__ void residual_norms(const Ctx& C, const float* xb, float2* X,
-                                               float2* V, float& r1sq, float& r2sq) {
-  for (int k0 = 0; k0 < C.T; k0 += C.Tc) {
+                                               float2* V, float& r1sq, float& r2sq, int& epoch) {
+  for (int k0 = 0, ch = 0; k0 < C.T; k0 += C.Tc, ++ch) {
     const int Tce = min(C.Tc, C.T - k0);
     C.wchunk<NT>(k0, Tce);
-    chunk_units<NT, KS>(C, Tce, xb, X, V, nullptr, false, true, r1sq, r2sq, 1.f, 1.f);
+    chunk_units<NT, KS>(C, ch, Tce, xb, X, V, nullptr, false, true, r1sq, r2sq, 1.f, 1.f,
+                        epoch & 1);
   }
+  ++epoch;
 }
 
 // LDS floats of the box and mask regions.
 __host__ __device__ inline int box_floats(int Tc, int n_max) {
-  return 4 * n_max * nwindows(Tc);
+  return 12 * n_max * nwindows(Tc);
 }
-__host__ __device__ inline int mask_floats(int Tc, int n_max, int M_max) {
-  return 2 * n_max * nwindows(Tc) * ((n_max + 63) / 64 + (M_max + 63) / 64);
+// Windows whose candidate lists are stored: all windows of the horizon when
+// it is LDS-resident (lists persist across iterations), else those of one time
+// chunk (lists are rebuilt on every pass).
+__host__ __device__ inline int horizon_windows(int T, int Tc) {
+  return Tc >= T ? nwindows(T) : nwindows(Tc);
+}
+__host__ __device__ inline int mask_floats(int T, int Tc, int n_max, int M_max) {
+  return horizon_windows(T, Tc) * mask_words(n_max, M_max);
+}
+__host__ __device__ inline int vref_floats(int T, int Tc, int n_max) {
+  return 2 * horizon_windows(T, Tc) * n_max * 4;
+}
+
+// Skin of the candidate lists: a quarter of the robot size.
+__device__ __forceinline__ float list_skin(float a) { return 0.25f * a; }
+
+// Empty reference boxes: the first check of every window rebuilds its lists.
+__device__ __forceinline__ void clear_refs(float4* __restrict__ vref, int count, int tid,
+                                           int nthr) {
+  const float inf = __builtin_inff();
+  for (int t = tid; t < count; t += nthr) vref[t] = make_float4(inf, -inf, inf, -inf);
 }
 
 struct FwdLds {
-  float *W, *fac, *xbA, *xbB, *lamA, *lamB, *cx, *part, *means, *red, *csum;
-  float4* obs;
-  float4* box;
-  u64* masks;
+  float *W, *fac, *xbA, *xbB, *lamA, *lamB, *cx, *part, *means, *red, *csum, *box3;
+  float4 *obs, *obox, *vref;
+  unsigned* masks;
   float2 *X, *V;
 };
 
-__device__ __forceinline__ FwdLds carve_fwd(float* sm, int nc, int Tc, int n_max, int M_max,
-                                            int S_max) {
+__device__ __forceinline__ FwdLds carve_fwd(float* sm, int nc, int T, int Tc, int n_max,
+                                            int M_max, int S_max) {
   FwdLds L;
   float* p = sm;
   L.W = p; p += round4(nc * Tc);
@@ -970,8 +1088,10 @@ __device__ __forceinline__ FwdLds carve_fwd(float* sm, int nc, int Tc, int n_max
   L.red = p; p += kRed;
   L.csum = p; p += kColSums;
   L.obs = reinterpret_cast<float4*>(p); p += 4 * M_max;
-  L.box = reinterpret_cast<float4*>(p); p += box_floats(Tc, n_max);
-  L.masks = reinterpret_cast<u64*>(p); p += mask_floats(Tc, n_max, M_max);
+  L.obox = reinterpret_cast<float4*>(p); p += 4 * M_max;
+  L.box3 = p; p += box_floats(Tc, n_max);
+  L.masks = reinterpret_cast<unsigned*>(p); p += mask_floats(T, Tc, n_max, M_max);
+  L.vref = reinterpret_cast<float4*>(p); p += vref_floats(T, Tc, n_max);
   L.X = reinterpret_cast<float2*>(p); p += 2 * n_max * tstride(Tc);
   L.V = reinterpret_cast<float2*>(p);
   return L;
@@ -982,7 +1102,7 @@ __device__ __forceinline__ FwdLds carve_fwd(float* sm, int nc, int Tc, int n_max
 size_t fwd_lds_bytes(int nc, int T, int Tc, int n_max, int M_max, int S_max, int) {
   auto r4 = [](int x) { return (size_t)((x + 3) & ~3); };
   size_t f = r4(nc * Tc) + r4(fac_stride(nc)) + (5 + nwindows(Tc)) * r4(S_max) + kMeans + kRed +
-             kColSums + 4 * (size_t)M_max + box_floats(Tc, n_max) + mask_floats(Tc, n_max, M_max) +
+             kColSums + 8 * (size_t)M_max + box_floats(Tc, n_max) + mask_floats(T, Tc, n_max, M_max) + vref_floats(T, Tc, n_max) +
              4 * (size_t)n_max * tstride(Tc);
   return f * sizeof(float);
 }
@@ -1001,14 +1121,22 @@ __global__ __launch_bounds__(NT) void fwd_fused_kernel(FwdArgs A) {
   const int n = P.n, M = P.M, nc = A.nc, T = A.T;
   const int S = 2 * n * nc;
   const int fs = fac_stride(nc);
-  FwdLds L = carve_fwd(sm, nc, A.Tc, A.n_max, A.M_max, A.S_max);
-  Ctx C{n,         M,         nc,        T,   A.Tc,  S,   tid,   A.rho, P.a,     P.pmin[0],
-        P.pmin[1], P.pmax[0], P.pmax[1], L.W, L.fac, A.W, L.obs, L.box, L.masks, A.Tc < T};
+  FwdLds L = carve_fwd(sm, nc, T, A.Tc, A.n_max, A.M_max, A.S_max);
+  Ctx C{n,      M,         nc,        T,         A.Tc,      S,
+        tid,    A.rho,     P.a,       P.pmin[0], P.pmin[1], P.pmax[0],
+        P.pmax[1], L.W,    L.fac,     A.W,       L.obs,     L.obox,
+        L.box3, L.masks,   L.vref,    mask_rows(A.n_max), (A.n_max + 31) >> 5,
+        mask_words(A.n_max, A.M_max), horizon_windows(T, A.Tc), A.n_max,
+        A.Tc < T ? 0.f : list_skin(P.a), A.Tc < T};
+  int epoch = 0;   // passes over the horizon (parity of the list reference buffers)
+  clear_refs(L.vref, vref_floats(T, A.Tc, A.n_max) / 4, tid, NT);
   if (!C.chunked) load_wchunk(A.W, L.W, nc, 0, T, tid, NT);
   for (int t = tid; t < fs; t += NT) L.fac[t] = A.fac[(size_t)P.fac * fs + t];
   for (int m = tid; m < M; m += NT) {
     const float* o = A.obstacles + ((size_t)P.obs_off + m) * 3;
     L.obs[m] = make_float4(o[0], o[1], o[2], o[2] * o[2]);
+    const float f = obs_margin(o[2]);
+    L.obox[m] = make_float4(o[0] - f, o[0] + f, o[1] - f, o[1] + f);
     if (A.save) {
       float* d = A.ws_obs + ((size_t)P.obs_off + m) * 3;
       d[0] = o[0];
@@ -1023,7 +1151,7 @@ __global__ __launch_bounds__(NT) void fwd_fused_kernel(FwdArgs A) {
   }
   __syncthreads();
   const float* bnd = A.boundary + (size_t)P.rob_off * 4;
-  robot_means(L.lamB, n, nc, L.means, tid >> 6, NT >> 6, tid & 63);
+  robot_means(L.lamB, n, nc, L.means, wave_id(tid), NT >> 6, tid & 63);
   boundary_means(bnd, n, L.means + 2 * nc, tid, NT);
   __syncthreads();
   for (int s = tid; s < S; s += NT) {
@@ -1049,7 +1177,7 @@ __global__ __launch_bounds__(NT) void fwd_fused_kernel(FwdArgs A) {
       }
     }
     sf_iteration<NT, KS>(C, xb, xn, lam, lamn, L.csum, L.X, L.V, L.part, L.cx, l == A.L - 1,
-                         dzsq);
+                         dzsq, epoch);
     float* t = xb;
     xb = xn;
     xn = t;
@@ -1071,7 +1199,7 @@ __global__ __launch_bounds__(NT) void fwd_fused_kernel(FwdArgs A) {
   }
   // residual of the returned iterate
   float r1sq = 0.f, r2sq = 0.f;
-  residual_norms<NT, KS>(C, xb, L.X, L.V, r1sq, r2sq);
+  residual_norms<NT, KS>(C, xb, L.X, L.V, r1sq, r2sq, epoch);
   float v[4] = {r1sq, r2sq, dzsq, bad};
   block_sum(v, L.red);
   if (tid == 0) {
@@ -1121,15 +1249,14 @@ hipError_t launch_fwd_fused(const FwdArgs& a, int threads, size_t lds, hipStream
 namespace {
 
 struct BwdLds {
-  float *W, *fac, *red, *csum, *gA, *gB, *glam, *gxi, *cx, *b0, *b1, *b2, *b3, *part;
-  float4* obs;
-  float4* box;
-  u64* masks;
+  float *W, *fac, *red, *csum, *gA, *gB, *glam, *gxi, *cx, *b0, *b1, *b2, *b3, *part, *box3;
+  float4 *obs, *obox, *vref;
+  unsigned* masks;
   float2 *X, *G, *H;
 };
 
-__device__ __forceinline__ BwdLds carve_bwd(float* sm, int nc, int Tc, int n_max, int M_max,
-                                            int S_max) {
+__device__ __forceinline__ BwdLds carve_bwd(float* sm, int nc, int T, int Tc, int n_max,
+                                            int M_max, int S_max) {
   BwdLds L;
   float* p = sm;
   L.W = p; p += round4(nc * Tc);
@@ -1143,8 +1270,10 @@ __device__ __forceinline__ BwdLds carve_bwd(float* sm, int nc, int Tc, int n_max
   }
   L.part = p; p += nwindows(Tc) * round4(S_max);
   L.obs = reinterpret_cast<float4*>(p); p += 4 * M_max;
-  L.box = reinterpret_cast<float4*>(p); p += box_floats(Tc, n_max);
-  L.masks = reinterpret_cast<u64*>(p); p += mask_floats(Tc, n_max, M_max);
+  L.obox = reinterpret_cast<float4*>(p); p += 4 * M_max;
+  L.box3 = p; p += box_floats(Tc, n_max);
+  L.masks = reinterpret_cast<unsigned*>(p); p += mask_floats(T, Tc, n_max, M_max);
+  L.vref = reinterpret_cast<float4*>(p); p += vref_floats(T, Tc, n_max);
   L.X = reinterpret_cast<float2*>(p); p += 2 * n_max * tstride(Tc);
   L.G = reinterpret_cast<float2*>(p); p += 2 * n_max * tstride(Tc);
   L.H = reinterpret_cast<float2*>(p);
@@ -1156,7 +1285,7 @@ __device__ __forceinline__ void add_partials(float* __restrict__ g, const float*
                                              int nwin, int S, int tid, int nthr) {
   for (int s = tid; s < S; s += nthr) {
     float r = part[s];
-    for (int w = 1; w < nwin; ++w) r += part[(size_t)w * S + s];
+    for (int w = 1; w < nwin; ++w) r += part[w * S + s];
     g[s] += r;
   }
 }
@@ -1189,7 +1318,7 @@ __device__ __forceinline__ void update_bwd_p1(const float* __restrict__ fac, int
     float g[KS];
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
-      sidx[s] = t.ax * n * nc + ic * nc + min(4 * s + kq, nc - 1);
+      sidx[s] = __umul24(t.ax * n + ic, nc) + min(4 * s + kq, nc - 1);
       g[s] = gx[sidx[s]];
     }
     if (part) {
@@ -1198,7 +1327,7 @@ __device__ __forceinline__ void update_bwd_p1(const float* __restrict__ fac, int
       for (int s = 0; s < KS; ++s) r[s] = part[sidx[s]];
       for (int w = 1; w < nwin; ++w) {
 #pragma unroll
-        for (int s = 0; s < KS; ++s) r[s] += part[(size_t)w * S + sidx[s]];
+        for (int s = 0; s < KS; ++s) r[s] += part[w * S + sidx[s]];
       }
 #pragma unroll
       for (int s = 0; s < KS; ++s) g[s] += r[s];
@@ -1218,7 +1347,7 @@ __device__ __forceinline__ void update_bwd_p1(const float* __restrict__ fac, int
       const int io = t.rt * 16 + 4 * kq + v;
       float f0 = 0.f;
       if (fw != 0.f && io < n && cb < nc) {
-        const int s = t.ax * n * nc + io * nc + cb;
+        const int s = __umul24(t.ax * n + io, nc) + cb;
         f0 = -2.f * fw * (nxt[s] - cur[s]);
       }
       accU[q][v] = 0.f;
@@ -1259,7 +1388,7 @@ __device__ __forceinline__ void update_bwd_p2(int nc, int n, const float* __rest
     for (int v = 0; v < 4; ++v) {
       const int io = t.rt * 16 + 4 * kq + v;
       if (io < n && cb < nc) {
-        const int s = t.ax * n * nc + io * nc + cb;
+        const int s = __umul24(t.ax * n + io, nc) + cb;
         const float gu = accU[q][v] + mu;
         const float gfp = fw != 0.f ? -2.f * rho * fw * (nxt[St + s] - cur[St + s]) : 0.f;
         const float gl = glam[s];
@@ -1275,27 +1404,28 @@ __device__ __forceinline__ void update_bwd_p2(int nc, int n, const float* __rest
 // Window units of one reverse iteration: positions X = W xb (with boxes) and
 // G = W g_R, masks, the VJP H and its W^T share into part.
 template <int NT, int KS>
-__device__ __forceinline__ void adjoint_units(const Ctx& C, int Tce, const float* xb,
+__device__ __forceinline__ void adjoint_units(const Ctx& C, int chunk, int Tce, const float* xb,
                                               const float* gR, float2* X, float2* G, float2* Hb,
-                                              float* part, bool accumulate) {
-  const int lane = lane_here(C.tid), wave = C.tid >> 6, nwaves = NT >> 6;
+                                              float* part, bool accumulate, int parity) {
+  const int lane = lane_here(C.tid), wave = wave_id(C.tid), nwaves = NT >> 6;
   const int nwin = nwindows(Tce);
   const int H = parts_per_window(C.n, nwin, nwaves);
-  const int Ts = C.Ts(), nws = C.nws(), ow = C.ow();
+  const int Ts = C.Ts(), nws = C.nws();
   for (int u = wave; u < nwin * H; u += nwaves) {
     const int w = u / H, h = u - w * H;
-    xmap_window<KS, true>(C.W, C.nc, xb, C.n, reinterpret_cast<float*>(X), Ts, w, Tce,
-                          reinterpret_cast<float*>(C.box), nws, lane);
+    const int gw = chunk * nws + w;
+    xmap_window<KS, true>(C.W, C.nc, xb, C.n, reinterpret_cast<float*>(X), Ts, w, Tce, C.box3,
+                          nws, C.a, C.skin, lane);
     xmap_window<KS, false>(C.W, C.nc, gR, C.n, reinterpret_cast<float*>(G), Ts, w, Tce,
-                           nullptr, nws, lane);
+                           nullptr, nws, C.a, C.skin, lane);
     wave_fence();
-    masks_window(C.box, C.n, C.obs, C.M, C.a, C.masks, nws, ow, w, h, H, lane);
+    C.refresh_lists(gw, w, h, H, parity, lane);
     wave_fence();
-    vjp_window(X, G, Hb, C.n, Ts, C.obs, C.masks, nws, ow, C.a, C.pmin0, C.pmin1, C.pmax0,
-               C.pmax1, w, Tce, h, H, lane);
+    vjp_window(X, G, Hb, C.n, Ts, C.obs, C.M, C.mwin(C.chunked ? w : gw), C.mrow, C.mpw, C.a,
+               C.pmin0, C.pmin1, C.pmax0, C.pmax1, w, Tce, h, H, lane);
     wave_fence();
     wtmap_window<KS>(C.W, C.nc, reinterpret_cast<const float*>(Hb), C.n, Ts, w, Tce, h, H,
-                     part + (size_t)w * C.S, accumulate, lane);
+                     part + w * C.S, accumulate, lane);
   }
   __syncthreads();
 }
@@ -1305,7 +1435,7 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
   extern __shared__ float4 sm4[];
   float* sm = reinterpret_cast<float*>(sm4);
   const int tid = threadIdx.x;
-  const int wave = tid >> 6;
+  const int wave = wave_id(tid);
   const int b = A.order[blockIdx.x];
   const ProbDesc P = A.probs[b];
   const int n = P.n, M = P.M, nc = A.nc, T = A.T, Tc = A.Tc;
@@ -1313,15 +1443,23 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
   const int fs = fac_stride(nc);
   const float rho = A.rho, fw = A.fp_weight;
   const size_t St = (size_t)A.S_total;
-  BwdLds L = carve_bwd(sm, nc, Tc, A.n_max, A.M_max, A.S_max);
-  Ctx C{n,         M,         nc,        T,   Tc,    S,   tid,   rho,   P.a,     P.pmin[0],
-        P.pmin[1], P.pmax[0], P.pmax[1], L.W, L.fac, A.W, L.obs, L.box, L.masks, Tc < T};
+  BwdLds L = carve_bwd(sm, nc, T, Tc, A.n_max, A.M_max, A.S_max);
+  Ctx C{n,      M,         nc,        T,         Tc,        S,
+        tid,    rho,       P.a,       P.pmin[0], P.pmin[1], P.pmax[0],
+        P.pmax[1], L.W,    L.fac,     A.W,       L.obs,     L.obox,
+        L.box3, L.masks,   L.vref,    mask_rows(A.n_max), (A.n_max + 31) >> 5,
+        mask_words(A.n_max, A.M_max), horizon_windows(T, Tc), A.n_max,
+        Tc < T ? 0.f : list_skin(P.a), Tc < T};
+  int epoch = 0;   // passes over the horizon (parity of the list reference buffers)
+  clear_refs(L.vref, vref_floats(T, Tc, A.n_max) / 4, tid, NT);
   const int nwin0 = nwindows(min(Tc, T));
   if (!C.chunked) load_wchunk(A.W, L.W, nc, 0, T, tid, NT);
   for (int t = tid; t < fs; t += NT) L.fac[t] = A.fac[(size_t)P.fac * fs + t];
   for (int m = tid; m < M; m += NT) {
     const float* o = A.obs + ((size_t)P.obs_off + m) * 3;
     L.obs[m] = make_float4(o[0], o[1], o[2], o[2] * o[2]);
+    const float f = obs_margin(o[2]);
+    L.obox[m] = make_float4(o[0] - f, o[0] + f, o[1] - f, o[1] + f);
   }
   for (int s = tid; s < S; s += NT) {
     L.cx[s] = A.cxi[P.coef_off + s];
@@ -1341,17 +1479,19 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
     for (int s = tid; s < S; s += NT) L.b0[s] = A.fin[P.coef_off + s];
     __syncthreads();
     float r1sq = 0.f, r2sq = 0.f;
-    residual_norms<NT, KS>(C, L.b0, L.X, L.G, r1sq, r2sq);
+    residual_norms<NT, KS>(C, L.b0, L.X, L.G, r1sq, r2sq, epoch);
     float v[2] = {r1sq, r2sq};
     block_sum(v, L.red);
     const float c1 = v[0] > 0.f ? gr1 / sqrtf(v[0]) : 0.f;
     const float c2 = v[1] > 0.f ? gr2 / sqrtf(v[1]) : 0.f;
     float d1 = 0.f, d2 = 0.f;
-    for (int k0 = 0; k0 < T; k0 += Tc) {
+    for (int k0 = 0, ch = 0; k0 < T; k0 += Tc, ++ch) {
       const int Tce = min(Tc, T - k0);
       C.wchunk<NT>(k0, Tce);
-      chunk_units<NT, KS>(C, Tce, L.b0, L.X, L.H, L.part, k0 > 0, false, d1, d2, c1, c2);
+      chunk_units<NT, KS>(C, ch, Tce, L.b0, L.X, L.H, L.part, k0 > 0, false, d1, d2, c1, c2,
+                          epoch & 1);
     }
+    ++epoch;
     add_partials(gx, L.part, nwin0, S, tid, NT);
     __syncthreads();
   }
@@ -1386,7 +1526,7 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
       }
       __syncthreads();
       for (int l = l0; l < l1 - 1; ++l) {
-        sf_iteration<NT, KS>(C, xr, xq, lr, lq, L.csum, L.X, L.G, L.part, L.cx, false, dz);
+        sf_iteration<NT, KS>(C, xr, xq, lr, lq, L.csum, L.X, L.G, L.part, L.cx, false, dz, epoch);
         float* t = xr;
         xr = xq;
         xq = t;
@@ -1418,11 +1558,12 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
       update_bwd_p2<NT>(nc, n, L.csum, L.csum + kColSums, accU, accN, rho, fw, cur, nxt, St,
                         L.glam, L.gxi, gR, gn, wave, lane);
       __syncthreads();
-      for (int k0 = 0; k0 < T; k0 += Tc) {
+      for (int k0 = 0, ch = 0; k0 < T; k0 += Tc, ++ch) {
         const int Tce = min(Tc, T - k0);
         C.wchunk<NT>(k0, Tce);
-        adjoint_units<NT, KS>(C, Tce, xbl, gR, L.X, L.G, L.H, L.part, k0 > 0);
+        adjoint_units<NT, KS>(C, ch, Tce, xbl, gR, L.X, L.G, L.H, L.part, k0 > 0, epoch & 1);
       }
+      ++epoch;
       pending = true;
       float* t = gx;
       gx = gn;
@@ -1445,7 +1586,7 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
 size_t bwd_lds_bytes(int nc, int T, int Tc, int n_max, int M_max, int S_max, int) {
   auto r4 = [](int x) { return (size_t)((x + 3) & ~3); };
   size_t f = r4(nc * Tc) + r4(fac_stride(nc)) + kRed + 2 * kColSums + (9 + nwindows(Tc)) * r4(S_max) +
-             4 * (size_t)M_max + box_floats(Tc, n_max) + mask_floats(Tc, n_max, M_max) +
+             8 * (size_t)M_max + box_floats(Tc, n_max) + mask_floats(T, Tc, n_max, M_max) + vref_floats(T, Tc, n_max) +
              6 * (size_t)n_max * tstride(Tc);
   return f * sizeof(float);
 }
@@ -1510,7 +1651,7 @@ __global__ __launch_bounds__(256) void plain_prep_kernel(FwdArgs A, PlainBufs Bf
   const float* fac = A.fac + (size_t)P.fac * fac_stride(nc);
   const float* tgt = A.xi + P.coef_off;
   const float* bnd = A.boundary + (size_t)P.rob_off * 4;
-  robot_means(tgt, n, nc, means, tid >> 6, 4, tid & 63);
+  robot_means(tgt, n, nc, means, wave_id(tid), 4, tid & 63);
   boundary_means(bnd, n, means + 2 * nc, tid, 256);
   __syncthreads();
   for (int s = tid; s < S; s += 256) {
@@ -1527,10 +1668,10 @@ template <int KS>
 __global__ __launch_bounds__(256) void plain_xmap_kernel(FwdArgs A, PlainBufs Bf, int b,
                                                          int pp) {
   const ProbDesc P = A.probs[b];
-  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int w = blockIdx.x * 4 + wave_id(threadIdx.x);
   if (w >= nwindows(A.T)) return;
   xmap_window<KS, false>(A.W, A.nc, Bf.xb[pp] + P.coef_off, P.n, Bf.X + (size_t)P.pos_off * 2,
-                         A.T, w, A.T, nullptr, 0, threadIdx.x & 63);
+                         A.T, w, A.T, nullptr, 0, P.a, 0.f, threadIdx.x & 63);
 }
 
 __global__ __launch_bounds__(256) void plain_constraint_kernel(FwdArgs A, PlainBufs Bf,
@@ -1548,7 +1689,7 @@ __global__ __launch_bounds__(256) void plain_constraint_kernel(FwdArgs A, PlainB
 template <int KS>
 __global__ __launch_bounds__(256) void plain_wtmap_kernel(FwdArgs A, PlainBufs Bf, int b) {
   const ProbDesc P = A.probs[b];
-  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int w = blockIdx.x * 4 + wave_id(threadIdx.x);
   if (w >= nwindows(A.T)) return;
   const int S = 2 * P.n * A.nc;
   wtmap_window<KS>(A.W, A.nc, Bf.V + (size_t)P.pos_off * 2, P.n, A.T, w, A.T, 0, 1,
@@ -1569,7 +1710,7 @@ __global__ __launch_bounds__(256) void plain_update_kernel(FwdArgs A, PlainBufs 
   __shared__ float red[kRed];
   const ProbDesc P = A.probs[b];
   const int n = P.n, nc = A.nc, S = 2 * n * nc, tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63, wave = wave_id(tid);
   const float* fac = A.fac + (size_t)P.fac * fac_stride(nc);
   const float* xb = Bf.xb[pp] + P.coef_off;
   float* xn = Bf.xb[pp ^ 1] + P.coef_off;
