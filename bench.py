@@ -60,6 +60,26 @@ def algorithmic_flops(problems, T, nc, L, kind):
     return tot
 
 
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    counter summary (FETCH_SIZE and WRITE_SIZE, calibrated on a copy of known
+    size), or None when there is none or the library sources have changed since
+    the counters were taken."""
+    from paper_2510_09204_amd.build import source_digest
+    path = os.path.join(ROOT, "profiles", f"sf_fused_{workload}_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.strip().startswith(("source-digest", "traffic-bytes")):
+            k, v = line.strip().split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source-digest") != source_digest():
+        return None
+    v = vals.get(f"traffic-bytes {kernel}")
+    return int(v) if v else None
+
+
 def cpu_baseline(problem, L, budget_s=20.0):
     """The FP64 oracle on one problem of the workload, on one host core:
     forward iterations for ~half the budget, then the oracle adjoint (forward +
@@ -193,7 +213,8 @@ def main(argv=None):
     ach = dom[1] / (dom[2] / 1e3) / 1e12
     roofline = dict(bound="alu", kernel=dom[0], achieved=round(ach, 3),
                     peak=round(PEAK_ALU_TFLOPS, 2), unit="TFLOP/s",
-                    frac=round(ach / PEAK_ALU_TFLOPS, 4), traffic=None,
+                    frac=round(ach / PEAK_ALU_TFLOPS, 4),
+                    traffic=measured_traffic(f"c{a.config}", dom[0]),
                     frac_vs_packed_fp32_peak=round(ach / PEAK_FP32_PACKED_TFLOPS, 4),
                     kernels={"sf_fwd_fused": dict(ms=round(fwd_ms, 4),
                                                   tflops=round(f_fwd / fwd_ms / 1e9, 3)),

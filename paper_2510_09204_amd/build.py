@@ -24,6 +24,18 @@ HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
              f"-I{INCLUDE}", f"-I{CSRC}"]
 
 
+def source_digest() -> str:
+    """SHA-256 over the library's sources (kernels, internal header, host
+    runtime, public header): identifies the kernels a measurement was taken
+    on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in (*SOURCES, CSRC / "sf_internal.h", INCLUDE / "sf.h"):
+        h.update(f.name.encode())
+        h.update(f.read_bytes())
+    return h.hexdigest()
+
+
 def hipcc() -> str:
     for cand in (os.environ.get("HIPCC"), shutil.which("hipcc"), "/opt/rocm/bin/hipcc"):
         if cand and Path(cand).exists():
