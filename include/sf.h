@@ -157,6 +157,32 @@ const char* sf_last_error_detail(void);
 /* Threads per workgroup the plan's fused kernels use (after autotuning). */
 int sf_plan_threads(const sf_plan_t* plan);
 
+/*
+ * Optional per-problem early exit of later sf_project calls on this plan
+ * (iteration control around eq. fixed_point; the residual is that of eq.
+ * primal_residual, read as sqrt(||r_1||^2 + ||r_2||^2)).  With check_every = c
+ * > 0, at every iteration l that is a multiple of c the residual of the
+ * current iterate xi_bar^l is formed as part of that iteration's constraint
+ * pass; if it is <= tol, the problem completes iteration l and stops, so it
+ * returns xi_bar^{l+1}, lambda^{l+1} (and their residual, as always).  Other
+ * problems of the batch continue.  n_iters stays the upper bound.  The
+ * iterations each problem ran are available from sf_project_iterations, and
+ * sf_project_backward differentiates each problem's own chain.
+ *
+ *   tol          >= 0, finite (metres).
+ *   check_every  0 turns early exit off (the default); otherwise >= 1.
+ * Not available with SF_PLAIN (sf_project then fails with SF_ERR_INVALID_ARG).
+ */
+int sf_set_early_exit(sf_plan_t* plan, float tol, int32_t check_every);
+
+/*
+ * Copy the number of iterations each problem ran in the last sf_project call
+ * on this plan (n_iters for every problem without early exit) into iters,
+ * device int32[B], asynchronously on stream.
+ */
+int sf_project_iterations(const sf_plan_t* plan, const void* workspace, int32_t* iters,
+                          void* stream);
+
 #ifdef __cplusplus
 }
 #endif

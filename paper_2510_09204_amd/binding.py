@@ -25,7 +25,8 @@ _ERRORS = {0: "SF_OK", -1: "SF_ERR_INVALID_ARG", -2: "SF_ERR_SHAPE",
            -6: "SF_ERR_NONFINITE"}
 
 EXPORTED = ("sf_setup", "sf_project", "sf_project_backward", "sf_destroy",
-            "sf_error_string", "sf_last_error_detail", "sf_plan_threads")
+            "sf_error_string", "sf_last_error_detail", "sf_plan_threads", "sf_set_early_exit",
+            "sf_project_iterations")
 
 
 class SFError(RuntimeError):
@@ -73,6 +74,10 @@ def load_library(path: Optional[Path] = None) -> ctypes.CDLL:
     lib.sf_last_error_detail.restype = ctypes.c_char_p
     lib.sf_plan_threads.argtypes = [vp]
     lib.sf_plan_threads.restype = ctypes.c_int
+    lib.sf_set_early_exit.argtypes = [vp, ctypes.c_float, i32]
+    lib.sf_set_early_exit.restype = ctypes.c_int
+    lib.sf_project_iterations.argtypes = [vp, vp, vp, vp]
+    lib.sf_project_iterations.restype = ctypes.c_int
     if path is None:
         _lib = lib
     return lib
@@ -135,6 +140,20 @@ class SFPlan:
     @property
     def threads(self) -> int:
         return int(self.lib.sf_plan_threads(self._plan))
+
+    def set_early_exit(self, tol: float, check_every: int) -> None:
+        """sf_set_early_exit: stop a problem once its residual is <= tol at a
+        check every `check_every` iterations (0 = off)."""
+        _check(self.lib, self.lib.sf_set_early_exit(self._plan, float(tol), int(check_every)))
+
+    def iterations(self) -> torch.Tensor:
+        """sf_project_iterations: iterations each problem ran in the last
+        project call, int32[B] on the device (on the current stream)."""
+        out = torch.empty(self.B, dtype=torch.int32, device=self.device)
+        _check(self.lib, self.lib.sf_project_iterations(
+            self._plan, ctypes.c_void_p(self.workspace.data_ptr()), out.data_ptr(),
+            self._stream()))
+        return out
 
     def close(self) -> None:
         if getattr(self, "_plan", None):

@@ -138,6 +138,12 @@ bool mode_factors(const std::vector<double>& W, int nc, int T, double rho, doubl
   return true;
 }
 
+uint32_t float_bits(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, sizeof(u));
+  return u;
+}
+
 int choose_tc(int nc, int T, int n_max, int M_max, int S_max, int threads, bool bwd) {
   auto bytes = [&](int tc) {
     return bwd ? sf::bwd_lds_bytes(nc, T, tc, n_max, M_max, S_max, threads)
@@ -182,10 +188,13 @@ struct sf_plan {
   size_t off_desc = 0, off_order = 0, off_W = 0, off_fac = 0, off_cxi = 0,
          off_obs = 0, off_ckpt = 0, off_final = 0, off_seg = 0, off_X = 0, off_V = 0,
          off_R = 0, off_xb0 = 0, off_xb1 = 0, off_lam = 0, off_pcxi = 0, off_red = 0, off_part = 0,
-         total = 0;
+         off_iters = 0, total = 0;
   char* ws = nullptr;
   bool saved = false;
   int saved_L = 0;
+  bool saved_early = false;   // the saved forward ran with early exit
+  float exit_tol = 0.f;       // early exit (sf_set_early_exit); check_every 0 = off
+  int exit_every = 0;
   std::vector<GraphEntry> graphs;
 
   ~sf_plan() {
@@ -353,6 +362,7 @@ int build_plan(const sf_config_t* cfg, int B, const int32_t* n_robots, const int
   p->off_pcxi = take(F * coef);
   p->off_red = take(F * 4 * B);
   p->off_part = take(F * sf::plain_part_floats(T, coef));
+  p->off_iters = take(sizeof(int32_t) * B);
   p->total = off;
   out = std::move(p);
   return SF_OK;
@@ -378,6 +388,7 @@ sf::FwdArgs fwd_args(const sf_plan* p, const float* xi, const float* xi0, const 
   a.ws_obs = p->at<float>(p->off_obs);
   a.ws_ckpt = p->at<float>(p->off_ckpt);
   a.ws_final = p->at<float>(p->off_final);
+  a.ws_iters = p->at<int32_t>(p->off_iters);
   a.S_total = p->S_total;
   a.B = p->B;
   a.nc = p->cfg.n_coef;
@@ -389,6 +400,8 @@ sf::FwdArgs fwd_args(const sf_plan* p, const float* xi, const float* xi0, const 
   a.L = L;
   a.ckpt_every = p->cfg.checkpoint_every;
   a.save = save ? 1 : 0;
+  a.check_every = p->exit_every;
+  a.tol = p->exit_tol;
   a.rho = (float)p->cfg.rho;
   return a;
 }
@@ -564,6 +577,8 @@ int sf_project(sf_plan_t* plan, void* workspace, const float* xi, const float* x
   const bool save = flags & SF_SAVE_FOR_BACKWARD;
   const bool plain = flags & SF_PLAIN;
   if (save && plain) return fail(SF_ERR_INVALID_ARG, "SF_SAVE_FOR_BACKWARD with SF_PLAIN");
+  if (plain && plan->exit_every > 0)
+    return fail(SF_ERR_INVALID_ARG, "early exit is not available with SF_PLAIN");
   if (save && n_iters > plan->cfg.max_iters)
     return fail(SF_ERR_INVALID_ARG, "n_iters exceeds cfg.max_iters for a saved forward");
   if (xi_out == xi || xi_out == xi0 || lam_out == lam0 || xi_out == lam_out)
@@ -610,7 +625,8 @@ int sf_project(sf_plan_t* plan, void* workspace, const float* xi, const float* x
     std::vector<uint64_t> key = {(uint64_t)xi,      (uint64_t)xi0,     (uint64_t)lam0,
                                  (uint64_t)boundary, (uint64_t)obstacles, (uint64_t)xi_out,
                                  (uint64_t)lam_out, (uint64_t)residual, (uint64_t)n_iters,
-                                 (uint64_t)save,    (uint64_t)plan->threads, (uint64_t)s};
+                                 (uint64_t)save,    (uint64_t)plan->threads, (uint64_t)s,
+                                 (uint64_t)plan->exit_every, (uint64_t)float_bits(plan->exit_tol)};
     GraphEntry* hit = nullptr;
     for (auto& g : plan->graphs)
       if (g.key == key) hit = &g;
@@ -637,6 +653,7 @@ int sf_project(sf_plan_t* plan, void* workspace, const float* xi, const float* x
   }
   plan->saved = save;
   plan->saved_L = n_iters;
+  plan->saved_early = plan->exit_every > 0;
   return SF_OK;
 }
 
@@ -666,6 +683,7 @@ int sf_project_backward(sf_plan_t* plan, void* workspace, const float* g_xi_out,
   a.g_xi = g_xi;
   a.g_xi0 = g_xi0;
   a.g_lam0 = g_lam0;
+  a.iters = plan->saved_early ? plan->at<int32_t>(plan->off_iters) : nullptr;
   a.S_total = plan->S_total;
   a.B = plan->B;
   a.nc = plan->cfg.n_coef;
@@ -717,5 +735,28 @@ const char* sf_error_string(int code) {
 const char* sf_last_error_detail(void) { return g_detail.c_str(); }
 
 int sf_plan_threads(const sf_plan_t* plan) { return plan ? plan->threads : 0; }
+
+int sf_set_early_exit(sf_plan_t* plan, float tol, int32_t check_every) {
+  g_detail.clear();
+  if (!plan) return fail(SF_ERR_INVALID_ARG, "plan is NULL");
+  if (check_every < 0) return fail(SF_ERR_INVALID_ARG, "check_every < 0");
+  if (!std::isfinite(tol) || tol < 0.f) return fail(SF_ERR_INVALID_ARG, "tol must be finite, >= 0");
+  plan->exit_every = check_every;
+  plan->exit_tol = tol;
+  return SF_OK;
+}
+
+int sf_project_iterations(const sf_plan_t* plan, const void* workspace, int32_t* iters,
+                          void* stream) {
+  g_detail.clear();
+  if (!plan) return fail(SF_ERR_INVALID_ARG, "plan is NULL");
+  if (workspace != plan->ws)
+    return fail(SF_ERR_INVALID_ARG, "workspace differs from the one bound at sf_setup");
+  if (!iters) return fail(SF_ERR_INVALID_ARG, "iters is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  SF_HIP_CHECK(hipMemcpyAsync(iters, plan->ws + plan->off_iters, sizeof(int32_t) * plan->B,
+                              hipMemcpyDeviceToDevice, s));
+  return SF_OK;
+}
 
 }  // extern "C"

@@ -49,6 +49,7 @@ struct FwdArgs {
   float* ws_obs;          // saved obstacles
   float* ws_ckpt;         // [n_ckpt][2][S_total]
   float* ws_final;        // [2][S_total]
+  int32_t* ws_iters;      // [B] iterations each problem ran
   int64_t S_total;        // floats in one coefficient array
   int32_t B;
   int32_t nc;
@@ -58,6 +59,8 @@ struct FwdArgs {
   int32_t L;
   int32_t ckpt_every;
   int32_t save;
+  int32_t check_every;    // early exit: test the residual every this many iterations (0 = off)
+  float tol;              // early exit threshold on sqrt(||r_1||^2 + ||r_2||^2)
   float rho;
 };
 
@@ -77,6 +80,7 @@ struct BwdArgs {
   float* g_xi;            // nullable
   float* g_xi0;           // nullable
   float* g_lam0;          // nullable
+  const int32_t* iters;   // nullable [B]: iterations each problem ran (early exit)
   int64_t S_total;
   int32_t B;
   int32_t nc;

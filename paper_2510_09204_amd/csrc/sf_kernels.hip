@@ -1000,28 +1000,53 @@ __device__ __forceinline__ void chunk_units(const Ctx& C, int chunk, int Tce, co
 }
 
 // One application of T on the LDS state: (xb, lam) -> (xn, lam_n).  X, V,
-// part and csum are scratch.  Entered and left with the block synchronised.
+// part and csum are scratch.  With want_dz, dzsq gets this thread's share of
+// ||z' - z||^2.  With check, the residual of xb is formed on the way (wave
+// sums through red) and the return value says whether it is <= tol; the
+// update is completed either way.  Entered and left with the block
+// synchronised.
 template <int NT, int KS>
-__device__ __forceinline__ void sf_iteration(const Ctx& C, const float* xb, float* xn,
+__device__ __forceinline__ bool sf_iteration(const Ctx& C, const float* xb, float* xn,
                                              const float* lam, float* lam_n, float* csum,
                                              float2* X, float2* V, float* part, const float* cx,
-                                             bool last, float& dzsq, int& epoch) {
+                                             bool want_dz, float& dzsq, int& epoch,
+                                             bool check = false, float tol = 0.f,
+                                             float* red = nullptr) {
   const int wave = wave_id(C.tid);
   float d1 = 0.f, d2 = 0.f;
   for (int k0 = 0, ch = 0; k0 < C.T; k0 += C.Tc, ++ch) {
     const int Tce = min(C.Tc, C.T - k0);
     C.wchunk<NT>(k0, Tce);
-    chunk_units<NT, KS>(C, ch, Tce, xb, X, V, part, k0 > 0, false, d1, d2, 1.f, 1.f, epoch & 1);
+    chunk_units<NT, KS>(C, ch, Tce, xb, X, V, part, k0 > 0, check, d1, d2, 1.f, 1.f,
+                        epoch & 1);
   }
   ++epoch;
+  if (check) {
+    d1 = wave_sum_dpp(d1);
+    d2 = wave_sum_dpp(d2);
+    if ((C.tid & 63) == 0) {
+      red[2 * wave] = d1;
+      red[2 * wave + 1] = d2;
+    }
+  }
   floatx4 accP[tiles_per_wave(NT)];
   int lane = lane_here(C.tid);
   update_fwd_p1<NT, KS>(C.fac, C.nc, C.n, part, nwindows(min(C.Tc, C.T)), C.S, lam, lam_n, xb,
-                        cx, C.rho, last, dzsq, csum, accP, wave, lane);
+                        cx, C.rho, want_dz, dzsq, csum, accP, wave, lane);
   __syncthreads();
+  bool stop = false;
+  if (check) {
+    float r1 = 0.f, r2 = 0.f;
+    for (int q = 0; q < (NT >> 6); ++q) {
+      r1 += red[2 * q];
+      r2 += red[2 * q + 1];
+    }
+    stop = sqrtf(r1 + r2) <= tol;
+  }
   lane = lane_here(C.tid);
-  update_fwd_p2<NT>(C.nc, C.n, csum, accP, xb, xn, last, dzsq, wave, lane);
+  update_fwd_p2<NT>(C.nc, C.n, csum, accP, xb, xn, want_dz, dzsq, wave, lane);
   __syncthreads();
+  return stop;
 }
 
 // ||r_1||^2 and ||r_2||^2 partials of the iterate xb (block-synchronised on
@@ -1168,6 +1193,7 @@ __global__ __launch_bounds__(NT) void fwd_fused_kernel(FwdArgs A) {
   float* lam = L.lamA;
   float* lamn = L.lamB;
   float dzsq = 0.f;
+  int ran = A.L;
   for (int l = 0; l < A.L; ++l) {
     if (A.save && (l % A.ckpt_every) == 0) {
       float* ck = A.ws_ckpt + (size_t)(l / A.ckpt_every) * 2 * A.S_total + P.coef_off;
@@ -1176,15 +1202,23 @@ __global__ __launch_bounds__(NT) void fwd_fused_kernel(FwdArgs A) {
         ck[A.S_total + s] = lam[s];
       }
     }
-    sf_iteration<NT, KS>(C, xb, xn, lam, lamn, L.csum, L.X, L.V, L.part, L.cx, l == A.L - 1,
-                         dzsq, epoch);
+    const bool check = A.check_every > 0 && (l % A.check_every) == 0;
+    const bool want_dz = check || l == A.L - 1;
+    if (want_dz) dzsq = 0.f;   // the reported ||dz|| is that of the last update
+    const bool stop = sf_iteration<NT, KS>(C, xb, xn, lam, lamn, L.csum, L.X, L.V, L.part, L.cx,
+                                           want_dz, dzsq, epoch, check, A.tol, L.red);
     float* t = xb;
     xb = xn;
     xn = t;
     t = lam;
     lam = lamn;
     lamn = t;
+    if (stop) {
+      ran = l + 1;
+      break;
+    }
   }
+  if (tid == 0) A.ws_iters[b] = ran;
 
   float bad = 0.f;
   for (int s = tid; s < S; s += NT) {
@@ -1496,7 +1530,7 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
     __syncthreads();
   }
 
-  const int L_ = A.L, k = A.ckpt_every;
+  const int L_ = A.iters ? min(A.L, A.iters[b]) : A.L, k = A.ckpt_every;
   const int nseg = (L_ + k - 1) / k;
   float dz = 0.f;
   bool pending = false;   // L.part holds W^T VJP partials not yet added to gx
@@ -1749,6 +1783,7 @@ __global__ __launch_bounds__(256) void plain_final_kernel(FwdArgs A, PlainBufs B
   float v[3] = {r1sq, r2sq, bad};
   block_sum(v, red);
   if (tid == 0) {
+    A.ws_iters[b] = A.L;
     float* res = A.residual + (size_t)b * 4;
     res[0] = sqrtf(v[0]);
     res[1] = sqrtf(v[1]);

@@ -139,3 +139,26 @@ def compare_forward(problems, out, rho, L, idx=None, rel_tol=REL_TOL, res_tol=RE
             raise AssertionError(rec)
         assert e_tot <= res_tol + RES_REL_TOL * ref.residual, rec
     return errs
+
+
+def oracle_early_exit(inp, rho, L, tol, every, rel_margin=1e-3):
+    """The oracle's iterates under the early-exit rule of sf_set_early_exit:
+    at every iteration l that is a multiple of `every`, if the residual of
+    xi_bar^l is <= tol, iteration l is completed and the run stops.  Returns
+    (iterations run, xi_bar, lambda, near) with `near` set when a tested
+    residual lies within rel_margin of tol (FP32 may then decide otherwise)."""
+    orc = SFOracle(inp["n"], inp["M"], inp["n_coef"], inp["n_steps"], rho, inp["a"],
+                   inp["box"], inp["obstacles"], inp["boundary"])
+    xi = orc.flat(inp["xi"])
+    xib, lam = orc.flat(inp["xi0"]).copy(), orc.flat(inp["lam0"]).copy()
+    near = False
+    for l in range(L):
+        stop = False
+        if l % every == 0:
+            res = orc.residual_of(xib)
+            near = near or abs(res - tol) <= rel_margin * tol
+            stop = res <= tol
+        xib, lam, _, _ = orc.step(xi, xib, lam)
+        if stop:
+            return l + 1, orc.shaped(xib), orc.shaped(lam), near
+    return L, orc.shaped(xib), orc.shaped(lam), near
