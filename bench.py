@@ -9,8 +9,11 @@ FP64-oracle residual is <= 1e-3 (determined offline by oracle/lstar.py).
 
 Prints one JSON line.  Extra fields: the forward-only rate, the plain
 per-problem path's forward rate (one problem per launch group, per-stage
-kernels) and the batched/plain ratio, the residual check on the GPU outputs,
-the roofline of the dominant kernel and the FP64 oracle timed on host cores.
+kernels) and the batched/plain ratio, the batched-but-unfused forward rate (the
+same per-stage kernels, each launch over the whole batch) so that the gain can
+be attributed to batching and to fusion, the plan setup time (host FP64
+factors and workspace tables), the residual check on the GPU outputs, the
+roofline of the dominant kernel and the FP64 oracle timed on host cores.
 """
 from __future__ import annotations
 
@@ -149,8 +152,12 @@ def main(argv=None):
     probs = make_batch(cfg)
     pk = pack(probs)
     B = len(probs)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter()
     plan = SFPlan(pk.n_robots, pk.n_obs, pk.robot_a, pk.box, pk.n_coef, pk.n_steps, RHO,
                   checkpoint_every=CKPT, max_iters=L, threads=a.threads, device=dev)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t_setup) * 1e3
     t = to_device(pk, dev)
     args = (t["xi"], t["xi0"], t["lam0"], t["boundary"], t["obstacles"])
     g_out = torch.ones_like(t["xi"])
@@ -196,6 +203,16 @@ def main(argv=None):
     torch.cuda.synchronize()
     fwd_only_ms = e0.elapsed_time(e1) / a.steps
 
+    unfused = None
+    if not a.no_plain:
+        e0.record(stream)
+        xu, lu, ru = plan.project(*args, L, unfused=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        unfused_ms = e0.elapsed_time(e1)
+        unfused = dict(ms=unfused_ms, problems_per_s=B / (unfused_ms / 1e3),
+                       max_abs_diff_vs_batched=float((xu - out[0]).abs().max().item()))
+
     plain = None
     if not a.no_plain:
         e0.record(stream)
@@ -239,6 +256,13 @@ def main(argv=None):
                 batched_over_plain_fwd=None if plain is None else
                 round((B / (fwd_only_ms / 1e3)) / plain["problems_per_s"], 2),
                 plain_max_abs_diff=None if plain is None else plain["max_abs_diff_vs_batched"],
+                unfused_fwd_problems_per_s=None if unfused is None else
+                round(unfused["problems_per_s"], 2),
+                batched_over_unfused_fwd=None if unfused is None else
+                round((B / (fwd_only_ms / 1e3)) / unfused["problems_per_s"], 2),
+                unfused_max_abs_diff=None if unfused is None else
+                unfused["max_abs_diff_vs_batched"],
+                setup_ms=round(setup_ms, 2),
                 residual_max=float(resid.max()), residual_median=float(np.median(resid)),
                 frac_residual_le_tol=float(np.mean(resid <= 1e-3)),
                 status_nonzero=int(np.sum(res[:, 3] != 0)),

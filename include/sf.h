@@ -55,6 +55,8 @@ extern "C" {
 #define SF_SAVE_FOR_BACKWARD 1 /* keep checkpoints for sf_project_backward */
 #define SF_PLAIN 2             /* unfused per-stage kernels, one problem per launch */
 #define SF_GRAPH 4             /* capture the launch once per argument set, replay after */
+#define SF_UNFUSED 8           /* the per-stage kernels of SF_PLAIN, each launch covering the
+                                  whole batch (batched but unfused) */
 
 typedef struct sf_plan sf_plan_t;
 
@@ -113,8 +115,10 @@ int sf_setup(const sf_config_t* cfg, int32_t n_problems, const int32_t* n_robots
  *   xi0, lam0   warm start, coefficient layout.
  *   boundary    [sum n][2][2]; obstacles [sum M][3] (may be NULL if sum M = 0).
  *   n_iters     L >= 0 (L = 0 copies the warm start and reports its residual).
- *   flags       SF_SAVE_FOR_BACKWARD | SF_PLAIN | SF_GRAPH.  Saving requires
- *               n_iters <= cfg.max_iters and is not combined with SF_PLAIN.
+ *   flags       SF_SAVE_FOR_BACKWARD | SF_PLAIN | SF_UNFUSED | SF_GRAPH.  Saving
+ *               requires n_iters <= cfg.max_iters and is not combined with
+ *               SF_PLAIN or SF_UNFUSED; SF_PLAIN and SF_UNFUSED exclude each
+ *               other.  All paths compute the same bits.
  *   xi_out, lam_out  coefficient layout, must not alias the inputs.
  *   residual    [B][4] (see the layout notes above).
  * Input arrays are read during the call's kernels only.

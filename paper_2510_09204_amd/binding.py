@@ -19,6 +19,7 @@ LIB_PATH = Path(__file__).resolve().parent / "libsf.so"
 SF_SAVE_FOR_BACKWARD = 1
 SF_PLAIN = 2
 SF_GRAPH = 4
+SF_UNFUSED = 8
 
 _ERRORS = {0: "SF_OK", -1: "SF_ERR_INVALID_ARG", -2: "SF_ERR_SHAPE",
            -3: "SF_ERR_WORKSPACE_SMALL", -4: "SF_ERR_NOT_SAVED", -5: "SF_ERR_HIP",
@@ -177,7 +178,7 @@ class SFPlan:
         return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
 
     def project(self, xi, xi0, lam0, boundary, obstacles, n_iters: int, save: bool = False,
-                plain: bool = False, graph: bool = False,
+                plain: bool = False, graph: bool = False, unfused: bool = False,
                 out: Optional[Tuple[torch.Tensor, torch.Tensor, torch.Tensor]] = None):
         """Run sf_project; returns (xi_out, lam_out, residual[B][4])."""
         for t, name in ((xi, "xi"), (xi0, "xi0"), (lam0, "lam0")):
@@ -197,7 +198,7 @@ class SFPlan:
         else:
             xi_out, lam_out, res = out
         flags = (SF_SAVE_FOR_BACKWARD if save else 0) | (SF_PLAIN if plain else 0) | \
-                (SF_GRAPH if graph else 0)
+                (SF_GRAPH if graph else 0) | (SF_UNFUSED if unfused else 0)
         _check(self.lib, self.lib.sf_project(
             self._plan, ctypes.c_void_p(self.workspace.data_ptr()), xi.data_ptr(),
             xi0.data_ptr(), lam0.data_ptr(), boundary.data_ptr(),

@@ -572,13 +572,17 @@ int sf_project(sf_plan_t* plan, void* workspace, const float* xi, const float* x
   if (plan->obs_total > 0 && !obstacles)
     return fail(SF_ERR_INVALID_ARG, "obstacles is NULL but the plan has obstacles");
   if (n_iters < 0) return fail(SF_ERR_INVALID_ARG, "n_iters < 0");
-  if (flags & ~(SF_SAVE_FOR_BACKWARD | SF_PLAIN | SF_GRAPH))
+  if (flags & ~(SF_SAVE_FOR_BACKWARD | SF_PLAIN | SF_GRAPH | SF_UNFUSED))
     return fail(SF_ERR_INVALID_ARG, "unknown flag bits");
   const bool save = flags & SF_SAVE_FOR_BACKWARD;
-  const bool plain = flags & SF_PLAIN;
-  if (save && plain) return fail(SF_ERR_INVALID_ARG, "SF_SAVE_FOR_BACKWARD with SF_PLAIN");
+  const bool unfused = flags & SF_UNFUSED;
+  const bool plain = (flags & SF_PLAIN) || unfused;
+  if ((flags & SF_PLAIN) && unfused)
+    return fail(SF_ERR_INVALID_ARG, "SF_PLAIN and SF_UNFUSED together");
+  if (save && plain)
+    return fail(SF_ERR_INVALID_ARG, "SF_SAVE_FOR_BACKWARD with SF_PLAIN or SF_UNFUSED");
   if (plain && plan->exit_every > 0)
-    return fail(SF_ERR_INVALID_ARG, "early exit is not available with SF_PLAIN");
+    return fail(SF_ERR_INVALID_ARG, "early exit is not available with SF_PLAIN or SF_UNFUSED");
   if (save && n_iters > plan->cfg.max_iters)
     return fail(SF_ERR_INVALID_ARG, "n_iters exceeds cfg.max_iters for a saved forward");
   if (xi_out == xi || xi_out == xi0 || lam_out == lam0 || xi_out == lam_out)
@@ -598,7 +602,11 @@ int sf_project(sf_plan_t* plan, void* workspace, const float* xi, const float* x
     pb.cxi = plan->at<float>(plan->off_pcxi);
     pb.red = plan->at<float>(plan->off_red);
     pb.part = plan->at<float>(plan->off_part);
-    for (int b = 0; b < plan->B; ++b) SF_HIP_CHECK(sf::launch_plain_problem(a, pb, b, s));
+    if (unfused) {
+      SF_HIP_CHECK(sf::launch_plain_problem(a, pb, -1, s));
+    } else {
+      for (int b = 0; b < plan->B; ++b) SF_HIP_CHECK(sf::launch_plain_problem(a, pb, b, s));
+    }
     return SF_OK;
   }
   if ((flags & SF_GRAPH) && s == nullptr)

@@ -111,6 +111,7 @@ struct PlainBufs {
   float* red;    // [B][4] residual partials
   float* part;   // per-problem per-window partial sums [windows][coefficient layout]
 };
+// Problem b (b >= 0), or with b < 0 the whole batch in every launch.
 hipError_t launch_plain_problem(const FwdArgs& a, const PlainBufs& pb, int b,
                                 hipStream_t s);
 

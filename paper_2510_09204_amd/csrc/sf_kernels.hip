@@ -1678,8 +1678,15 @@ hipError_t prepare_kernels(size_t lds) {
 // ---------------------------------------------------------------------------
 namespace {
 
+// Problem of a plain-path block: b itself, or with b < 0 (a launch over the
+// whole batch) the problem of grid row blockIdx.y.
+__device__ __forceinline__ int plain_problem(const FwdArgs& A, int b) {
+  return b >= 0 ? b : A.order[blockIdx.y];
+}
+
 __global__ __launch_bounds__(256) void plain_prep_kernel(FwdArgs A, PlainBufs Bf, int b) {
   __shared__ float means[kMeans];
+  b = plain_problem(A, b);
   const ProbDesc P = A.probs[b];
   const int n = P.n, nc = A.nc, S = 2 * n * nc, tid = threadIdx.x;
   const float* fac = A.fac + (size_t)P.fac * fac_stride(nc);
@@ -1701,6 +1708,7 @@ __global__ __launch_bounds__(256) void plain_prep_kernel(FwdArgs A, PlainBufs Bf
 template <int KS>
 __global__ __launch_bounds__(256) void plain_xmap_kernel(FwdArgs A, PlainBufs Bf, int b,
                                                          int pp) {
+  b = plain_problem(A, b);
   const ProbDesc P = A.probs[b];
   const int w = blockIdx.x * 4 + wave_id(threadIdx.x);
   if (w >= nwindows(A.T)) return;
@@ -1710,6 +1718,7 @@ __global__ __launch_bounds__(256) void plain_xmap_kernel(FwdArgs A, PlainBufs Bf
 
 __global__ __launch_bounds__(256) void plain_constraint_kernel(FwdArgs A, PlainBufs Bf,
                                                                int b) {
+  b = plain_problem(A, b);
   const ProbDesc P = A.probs[b];
   const int tid = blockIdx.x * 256 + threadIdx.x;
   float d1 = 0.f, d2 = 0.f;
@@ -1719,16 +1728,24 @@ __global__ __launch_bounds__(256) void plain_constraint_kernel(FwdArgs A, PlainB
                    P.pmax[0], P.pmax[1], false, d1, d2, tid, gridDim.x * 256);
 }
 
-// Per-window partials of W^T V (one window per wave, all column tiles).
+// Per-window partials of W^T V (one window per wave, all column tiles), with
+// the fused kernels' window boundaries: 16-step windows local to each time
+// chunk of Tc steps, chunk contributions added in chunk order.
 template <int KS>
 __global__ __launch_bounds__(256) void plain_wtmap_kernel(FwdArgs A, PlainBufs Bf, int b) {
+  b = plain_problem(A, b);
   const ProbDesc P = A.probs[b];
   const int w = blockIdx.x * 4 + wave_id(threadIdx.x);
-  if (w >= nwindows(A.T)) return;
+  if (w >= nwindows(min(A.Tc, A.T))) return;
   const int S = 2 * P.n * A.nc;
-  wtmap_window<KS>(A.W, A.nc, Bf.V + (size_t)P.pos_off * 2, P.n, A.T, w, A.T, 0, 1,
-                   Bf.part + (size_t)nwindows(A.T) * P.coef_off + (size_t)w * S, false,
-                   threadIdx.x & 63);
+  const float* V = Bf.V + (size_t)P.pos_off * 2;
+  float* part = Bf.part + (size_t)nwindows(A.T) * P.coef_off + (size_t)w * S;
+  for (int k0 = 0; k0 < A.T; k0 += A.Tc) {
+    const int Tce = min(A.Tc, A.T - k0);
+    if (w < nwindows(Tce))
+      wtmap_window<KS>(A.W + (size_t)k0 * A.nc, A.nc, V + (size_t)k0 * 2, P.n, A.T, w, Tce, 0,
+                       1, part, k0 > 0, threadIdx.x & 63);
+  }
 }
 
 // lambda buffer of ping-pong parity pp (the plain path alternates lam and R).
@@ -1742,6 +1759,7 @@ __global__ __launch_bounds__(256) void plain_update_kernel(FwdArgs A, PlainBufs 
                                                            int pp, int last) {
   __shared__ float csum[kColSums];
   __shared__ float red[kRed];
+  b = plain_problem(A, b);
   const ProbDesc P = A.probs[b];
   const int n = P.n, nc = A.nc, S = 2 * n * nc, tid = threadIdx.x;
   const int lane = tid & 63, wave = wave_id(tid);
@@ -1752,7 +1770,7 @@ __global__ __launch_bounds__(256) void plain_update_kernel(FwdArgs A, PlainBufs 
   float dzsq = 0.f;
   floatx4 accP[tiles_per_wave(256)];
   update_fwd_p1<256, KS>(fac, nc, n, Bf.part + (size_t)nwindows(A.T) * P.coef_off,
-                         nwindows(A.T), S, plain_lam(Bf, pp) + P.coef_off,
+                         nwindows(min(A.Tc, A.T)), S, plain_lam(Bf, pp) + P.coef_off,
                          plain_lam(Bf, pp ^ 1) + P.coef_off, xb, cx, A.rho, last, dzsq, csum,
                          accP, wave, lane);
   __syncthreads();
@@ -1767,6 +1785,7 @@ __global__ __launch_bounds__(256) void plain_update_kernel(FwdArgs A, PlainBufs 
 __global__ __launch_bounds__(256) void plain_final_kernel(FwdArgs A, PlainBufs Bf, int b,
                                                           int pp) {
   __shared__ float red[kRed];
+  b = plain_problem(A, b);
   const ProbDesc P = A.probs[b];
   const int n = P.n, nc = A.nc, S = 2 * n * nc, tid = threadIdx.x;
   float r1sq = 0.f, r2sq = 0.f, bad = 0.f;
@@ -1802,25 +1821,28 @@ __global__ void fill_kernel(float* p, float v, int64_t n) {
 size_t plain_part_floats(int T, int64_t coef) { return (size_t)nwindows(T) * (size_t)coef; }
 
 hipError_t launch_plain_problem(const FwdArgs& a, const PlainBufs& pb, int b, hipStream_t s) {
-  // grids sized for the batch's largest problem; the kernels stride over the
-  // items of problem b
+  // b >= 0: one problem per launch; b < 0: every launch covers the batch
+  // (grid y = problem).  Grids are sized for the batch's largest problem; the
+  // kernels stride over the items of their problem.
+  const unsigned gy = b >= 0 ? 1u : (unsigned)a.B;
   const int gw = (nwindows(a.T) + 3) / 4;     // four waves per block, a window per wave
+  const int gp = (nwindows(std::min(a.Tc, a.T)) + 3) / 4;
   const int gc = (a.n_max * a.T + 255) / 256;
-  hipLaunchKernelGGL(plain_prep_kernel, dim3(1), dim3(256), 0, s, a, pb, b);
+  hipLaunchKernelGGL(plain_prep_kernel, dim3(1, gy), dim3(256), 0, s, a, pb, b);
   const bool k4 = ks_class(a.nc) == 4;
   auto xmap = k4 ? plain_xmap_kernel<4> : plain_xmap_kernel<8>;
   auto wtmap = k4 ? plain_wtmap_kernel<4> : plain_wtmap_kernel<8>;
   auto update = k4 ? plain_update_kernel<4> : plain_update_kernel<8>;
   int pp = 0;
   for (int l = 0; l < a.L; ++l) {
-    hipLaunchKernelGGL(xmap, dim3(gw), dim3(256), 0, s, a, pb, b, pp);
-    hipLaunchKernelGGL(plain_constraint_kernel, dim3(gc), dim3(256), 0, s, a, pb, b);
-    hipLaunchKernelGGL(wtmap, dim3(gw), dim3(256), 0, s, a, pb, b);
-    hipLaunchKernelGGL(update, dim3(1), dim3(256), 0, s, a, pb, b, pp, (int)(l == a.L - 1));
+    hipLaunchKernelGGL(xmap, dim3(gw, gy), dim3(256), 0, s, a, pb, b, pp);
+    hipLaunchKernelGGL(plain_constraint_kernel, dim3(gc, gy), dim3(256), 0, s, a, pb, b);
+    hipLaunchKernelGGL(wtmap, dim3(gp, gy), dim3(256), 0, s, a, pb, b);
+    hipLaunchKernelGGL(update, dim3(1, gy), dim3(256), 0, s, a, pb, b, pp, (int)(l == a.L - 1));
     pp ^= 1;
   }
-  hipLaunchKernelGGL(xmap, dim3(gw), dim3(256), 0, s, a, pb, b, pp);
-  hipLaunchKernelGGL(plain_final_kernel, dim3(1), dim3(256), 0, s, a, pb, b, pp);
+  hipLaunchKernelGGL(xmap, dim3(gw, gy), dim3(256), 0, s, a, pb, b, pp);
+  hipLaunchKernelGGL(plain_final_kernel, dim3(1, gy), dim3(256), 0, s, a, pb, b, pp);
   return hipGetLastError();
 }
 

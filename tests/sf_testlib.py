@@ -57,7 +57,7 @@ def make_plan(problems, rho, L=0, ckpt=1, threads=0, device="cuda"):
 
 
 def gpu_forward(problems, rho, L, save=False, ckpt=1, threads=0, plain=False, graph=False,
-                packed=None, plan=None):
+                packed=None, plan=None, unfused=False):
     import torch
     from paper_2510_09204_amd import to_device
     if plan is None:
@@ -68,7 +68,7 @@ def gpu_forward(problems, rho, L, save=False, ckpt=1, threads=0, plain=False, gr
         pk = packed
     t = to_device(pk)
     xo, lo, res = plan.project(t["xi"], t["xi0"], t["lam0"], t["boundary"], t["obstacles"],
-                               L, save=save, plain=plain, graph=graph)
+                               L, save=save, plain=plain, graph=graph, unfused=unfused)
     torch.cuda.synchronize()
     return dict(plan=plan, packed=pk, t=t, xi=xo.cpu().numpy(), lam=lo.cpu().numpy(),
                 res=res.cpu().numpy())

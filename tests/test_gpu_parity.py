@@ -150,6 +150,15 @@ def test_plain_path_matches_fused_bitwise(gpu):
     np.testing.assert_allclose(plain["res"], fused["res"], rtol=1e-5, atol=1e-7)
 
 
+def test_batched_unfused_path_matches_fused_bitwise(gpu):
+    probs = make_batch(CONFIGS[4], batch=6)      # uneven sizes in every launch
+    fused = gpu_forward(probs, RHO, 40)
+    unfused = gpu_forward(probs, RHO, 40, unfused=True)
+    np.testing.assert_array_equal(unfused["xi"], fused["xi"])
+    np.testing.assert_array_equal(unfused["lam"], fused["lam"])
+    np.testing.assert_allclose(unfused["res"], fused["res"], rtol=1e-5, atol=1e-7)
+
+
 @pytest.mark.parametrize("threads", [256, 512, 1024])
 def test_thread_counts_give_identical_coefficients(gpu, threads):
     probs = make_batch(CONFIGS[4], batch=6)
