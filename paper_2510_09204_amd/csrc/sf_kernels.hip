@@ -140,11 +140,15 @@ __device__ __forceinline__ float rows_reduce(float v, Op op) {
 struct OpAdd {
   __device__ float operator()(float a, float b) const { return a + b; }
 };
+// Min/max as compare-and-select (no NaN canonicalisation; a non-finite box
+// only has to fail its tests, which it does either way).
+__device__ __forceinline__ float min_sel(float a, float b) { return b < a ? b : a; }
+__device__ __forceinline__ float max_sel(float a, float b) { return b > a ? b : a; }
 struct OpMin {
-  __device__ float operator()(float a, float b) const { return fminf(a, b); }
+  __device__ float operator()(float a, float b) const { return min_sel(a, b); }
 };
 struct OpMax {
-  __device__ float operator()(float a, float b) const { return fmaxf(a, b); }
+  __device__ float operator()(float a, float b) const { return max_sel(a, b); }
 };
 
 // Deterministic block sum of up to 4 values: wave sums, then a fixed-order
@@ -212,17 +216,15 @@ __device__ __forceinline__ float obs_margin(float ao) { return fmaf(8e-6f, ao, a
 
 // Coefficient -> time map of window w for all robots: X[i][16w + r].axis =
 // sum_c W[16w + r][c] xb[axis][i][c] for steps < Tce (padding rows repeat the
-// last step).  With BOX, each robot's window box is stored three ways at
-// box3[(i nws + w) 3 + {0, 1, 2}]: as is (xmin, xmax, ymin, ymax), widened by
-// the pair margin, and widened by the robot-side obstacle margin.  Column tiles
-// are taken four at a time with all their operand loads issued before the
-// MFMA chains.
-template <int KS, bool BOX>
+// last step).  With BOX, each robot's window box (xmin, xmax, ymin, ymax) goes
+// to box[i nws + w].  PADDED: rows have room for the padding steps, which are
+// then stored too (no per-row guard).  Column tiles are taken four at a time
+// with all their operand loads issued before the MFMA chains.
+template <int KS, bool BOX, bool PADDED>
 __device__ __forceinline__ void xmap_window(const float* __restrict__ W, int nc,
                                             const float* __restrict__ xb, int n,
                                             float* __restrict__ Xf, int Ts, int w, int Tce,
-                                            float* __restrict__ box3, int nws, float a,
-                                            float skin, int lane) {
+                                            float* __restrict__ box, int nws, int lane) {
   const int ncol = (2 * n + 15) >> 4;
   const int m = lane & 15, kq = lane >> 4;
   const int row = min(w * 16 + m, Tce - 1);
@@ -234,9 +236,6 @@ __device__ __forceinline__ void xmap_window(const float* __restrict__ W, int nc,
     av[s] = c < nc ? v : 0.f;
   }
   const int k0 = w * 16 + 4 * kq;
-  // all 16 rows may be stored when the window is full or the row stride has
-  // room for the padding rows (which repeat the last step)
-  const bool whole = w * 16 + 16 <= Tce || Ts >= ((Tce + 15) & ~15);
   for (int nt0 = 0; nt0 < ncol; nt0 += 4) {
     float bv[4][KS];
 #pragma unroll
@@ -267,31 +266,18 @@ __device__ __forceinline__ void xmap_window(const float* __restrict__ W, int nc,
       const bool colok = i < n;
       if (colok) {
         float* xr = Xf + (__umul24(i, Ts) + k0) * 2 + ax;
-        if (whole) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v) xr[2 * v] = acc[g][v];
-        } else {
-#pragma unroll
-          for (int v = 0; v < 4; ++v)
-            if (k0 + v < Tce) xr[2 * v] = acc[g][v];
-        }
+        for (int v = 0; v < 4; ++v)
+          if (PADDED || k0 + v < Tce) xr[2 * v] = acc[g][v];
       }
       if (BOX) {
-        float lo = fminf(fminf(acc[g][0], acc[g][1]), fminf(acc[g][2], acc[g][3]));
-        float hi = fmaxf(fmaxf(acc[g][0], acc[g][1]), fmaxf(acc[g][2], acc[g][3]));
+        float lo = min_sel(min_sel(acc[g][0], acc[g][1]), min_sel(acc[g][2], acc[g][3]));
+        float hi = max_sel(max_sel(acc[g][0], acc[g][1]), max_sel(acc[g][2], acc[g][3]));
         lo = rows_reduce(lo, OpMin());
         hi = rows_reduce(hi, OpMax());
-        // the other axis of the same robot sits in the neighbouring lane
-        float sv = fmaxf(fabsf(lo), fabsf(hi));
-        sv = fmaxf(sv, dpp_f<0xB1, 0xF>(0.f, sv));
-        const float am = fmaf(2.f, skin, pair_margin(a, sv));
-        const float e = robot_obs_margin(sv) + skin;
-        if (lane < 16 && colok) {
-          float* bx = box3 + (__umul24(i, nws) + w) * 12 + 2 * ax;
-          *reinterpret_cast<float2*>(bx) = make_float2(lo, hi);
-          *reinterpret_cast<float2*>(bx + 4) = make_float2(lo - am, hi + am);
-          *reinterpret_cast<float2*>(bx + 8) = make_float2(lo - e, hi + e);
-        }
+        if (lane < 16 && colok)
+          *reinterpret_cast<float2*>(box + (__umul24(i, nws) + w) * 4 + 2 * ax) =
+              make_float2(lo, hi);
       }
     }
   }
@@ -299,26 +285,34 @@ __device__ __forceinline__ void xmap_window(const float* __restrict__ W, int nc,
 
 // Candidate masks (32-bit words) of window w for the robots of part h.  Word q
 // of robot i's pair mask (at mw[q * mrow + i]) has bit jj set when robot
-// j = 32 q + jj (j != i) has a window box meeting robot i's pair-widened box;
-// obstacle word q (at mw[(mpw + q) * mrow + i]) likewise for obstacle 32 q + jj
-// against the robot-side widened box, with obstacle boxes already widened by
-// their own margin.  A ballot tests two robots at once (lane = 32 slot + jj)
-// and one 64-bit store writes both words: robots t0 and t0 + 1 of a part are
-// adjacent rows.
-__device__ __forceinline__ void masks_window(const float4* __restrict__ box3, int n,
-                                             const float4* __restrict__ obox, int M,
-                                             unsigned* __restrict__ mw, int mrow, int mpw,
-                                             int nws, int w, int h, int H, int lane) {
+// j = 32 q + jj (j != i) has a window box meeting robot i's box widened by the
+// pair margin plus twice the skin; obstacle word q (at mw[(mpw + q) * mrow + i])
+// likewise for obstacle 32 q + jj, whose box is already widened by its own
+// margin, against robot i's box widened by the robot-side margin plus the
+// skin.  A ballot tests two robots at once (lane = 32 slot + jj) and one 64-bit
+// store writes both words: robots t0 and t0 + 1 of a part are adjacent rows.
+__device__ __forceinline__ float4 widened(float4 b, float d) {
+  return make_float4(b.x - d, b.y + d, b.z - d, b.w + d);
+}
+__device__ __forceinline__ float box_magnitude(float4 b) {
+  return fmaxf(fmaxf(fabsf(b.x), fabsf(b.y)), fmaxf(fabsf(b.z), fabsf(b.w)));
+}
+
+__device__ __forceinline__ void masks_window(const float4* __restrict__ box, int n,
+                                             const float4* __restrict__ obox, int M, float a,
+                                             float skin, unsigned* __restrict__ mw, int mrow,
+                                             int mpw, int nws, int w, int h, int H, int lane) {
   const int cnt = part_count(n, h, H);
   const int slot = lane >> 5, jj = lane & 31;
   for (int q = 0; q < ((n + 31) >> 5); ++q) {
     const int j = q * 32 + jj;
-    const float4 bj = box3[(__umul24(min(j, n - 1), nws) + w) * 3];
+    const float4 bj = box[__umul24(min(j, n - 1), nws) + w];
     const bool jl = j < n;
     for (int t0 = 0; t0 < cnt; t0 += 2) {
       const bool tl = t0 + slot < cnt;
       const int i = part_robot(tl ? t0 + slot : t0, h, H);
-      const float4 ei = box3[(__umul24(i, nws) + w) * 3 + 1];
+      const float4 bi = box[__umul24(i, nws) + w];
+      const float4 ei = widened(bi, fmaf(2.f, skin, pair_margin(a, box_magnitude(bi))));
       const bool c = tl && jl && (j != i) && (ei.x < bj.y) && (bj.x < ei.y) && (ei.z < bj.w) &&
                      (bj.z < ei.w);
       const u64 b = __builtin_amdgcn_ballot_w64(c);
@@ -333,7 +327,8 @@ __device__ __forceinline__ void masks_window(const float4* __restrict__ box3, in
     for (int t0 = 0; t0 < cnt; t0 += 2) {
       const bool tl = t0 + slot < cnt;
       const int i = part_robot(tl ? t0 + slot : t0, h, H);
-      const float4 ei = box3[(__umul24(i, nws) + w) * 3 + 2];
+      const float4 bi = box[__umul24(i, nws) + w];
+      const float4 ei = widened(bi, robot_obs_margin(box_magnitude(bi)) + skin);
       const bool c = tl && ml && (ob.x < ei.y) && (ei.x < ob.y) && (ob.z < ei.w) && (ei.z < ob.w);
       const u64 b = __builtin_amdgcn_ballot_w64(c);
       if (lane == 0)
@@ -352,7 +347,7 @@ __device__ __forceinline__ bool lists_stale(const float4* __restrict__ box3,
                                             float4* __restrict__ ref_next, int n, int nws, int w,
                                             float skin, int lane) {
   const int i = min(lane, n - 1);
-  const float4 b = box3[(__umul24(i, nws) + w) * 3];
+  const float4 b = box3[__umul24(i, nws) + w];
   const float4 r = ref[i];
   const float g = fmaxf(fmaxf(r.x - b.x, b.y - r.y), fmaxf(r.z - b.z, b.w - r.w));
   const bool moved = lane < n && !(g <= skin);
@@ -658,14 +653,14 @@ __host__ __device__ constexpr int tiles_per_wave(int NT) {
 struct Tile {
   int ax, rt, ct;
 };
+// Tile slots: ax | rt << 1 | ct << 3 (16 slots for up to 4 row tiles and 2
+// column tiles); slots beyond the problem's tiles are empty.  The active
+// slots of small problems are the first ones, so they land on different SIMDs.
 __device__ __forceinline__ bool mode_tile_of(int tile, int n, int nc, Tile& t) {
-  const int nrt = (n + 15) >> 4, nct = (nc + 15) >> 4;
-  if (tile >= 2 * nrt * nct) return false;
-  t.ax = tile / (nrt * nct);
-  const int rem = tile - t.ax * nrt * nct;
-  t.rt = rem / nct;
-  t.ct = rem - t.rt * nct;
-  return true;
+  t.ax = tile & 1;
+  t.rt = (tile >> 1) & 3;
+  t.ct = tile >> 3;
+  return t.rt < ((n + 15) >> 4) && t.ct < ((nc + 15) >> 4);
 }
 __device__ __forceinline__ int colsum_slot(const Tile& t, int rt) {
   return ((t.ax * 2 + t.ct) * 4 + rt) * 16;
@@ -928,7 +923,7 @@ struct Ctx {
   const float *fac, *Wg;
   const float4* obs;    // (cx, cy, a_o, a_o^2)
   const float4* obox;   // obstacle boxes widened by their margin
-  float* box3;          // window boxes: raw, pair-widened, robot-side widened
+  float* box3;          // window boxes [robot][window] (xmin, xmax, ymin, ymax)
   unsigned* masks;      // [chunk window][word][row]
   float4* vref;         // [2][chunk window][n_max] reference boxes of the lists
   int mrow, mpw, mstride, nwt, n_max;
@@ -946,13 +941,13 @@ struct Ctx {
                                                 int lane) const {
     const float4* b3 = reinterpret_cast<const float4*>(box3);
     if (chunked) {
-      masks_window(b3, n, obox, M, mwin(w), mrow, mpw, nws(), w, h, H, lane);
+      masks_window(b3, n, obox, M, a, skin, mwin(w), mrow, mpw, nws(), w, h, H, lane);
       return;
     }
     const float4* ref = vref + (parity * nwt + gw) * n_max;
     float4* nxt = vref + ((parity ^ 1) * nwt + gw) * n_max;
     if (lists_stale(b3, ref, nxt, n, nws(), w, skin, lane))
-      masks_window(b3, n, obox, M, mwin(gw), mrow, mpw, nws(), w, h, H, lane);
+      masks_window(b3, n, obox, M, a, skin, mwin(gw), mrow, mpw, nws(), w, h, H, lane);
   }
 
   // Make the LDS W table hold rows k0 .. k0+Tce-1 (block-wide; no-op when
@@ -982,8 +977,8 @@ __device__ __forceinline__ void chunk_units(const Ctx& C, int chunk, int Tce, co
   for (int u = wave; u < nwin * H; u += nwaves) {
     const int w = u / H, h = u - w * H;
     const int gw = chunk * nws + w;
-    xmap_window<KS, true>(C.W, C.nc, xb, C.n, reinterpret_cast<float*>(X), Ts, w, Tce, C.box3,
-                          nws, C.a, C.skin, lane);
+    xmap_window<KS, true, true>(C.W, C.nc, xb, C.n, reinterpret_cast<float*>(X), Ts, w, Tce,
+                                C.box3, nws, lane);
     wave_fence();
     C.refresh_lists(gw, w, h, H, parity, lane);
     wave_fence();
@@ -1065,7 +1060,7 @@ __device__ __forceinline__ void residual_norms(const Ctx& C, const float* xb, fl
 
 // LDS floats of the box and mask regions.
 __host__ __device__ inline int box_floats(int Tc, int n_max) {
-  return 12 * n_max * nwindows(Tc);
+  return 4 * n_max * nwindows(Tc);
 }
 // Windows whose candidate lists are stored: all windows of the horizon when
 // it is LDS-resident (lists persist across iterations), else those of one time
@@ -1448,10 +1443,10 @@ __device__ __forceinline__ void adjoint_units(const Ctx& C, int chunk, int Tce, 
   for (int u = wave; u < nwin * H; u += nwaves) {
     const int w = u / H, h = u - w * H;
     const int gw = chunk * nws + w;
-    xmap_window<KS, true>(C.W, C.nc, xb, C.n, reinterpret_cast<float*>(X), Ts, w, Tce, C.box3,
-                          nws, C.a, C.skin, lane);
-    xmap_window<KS, false>(C.W, C.nc, gR, C.n, reinterpret_cast<float*>(G), Ts, w, Tce,
-                           nullptr, nws, C.a, C.skin, lane);
+    xmap_window<KS, true, true>(C.W, C.nc, xb, C.n, reinterpret_cast<float*>(X), Ts, w, Tce,
+                                C.box3, nws, lane);
+    xmap_window<KS, false, true>(C.W, C.nc, gR, C.n, reinterpret_cast<float*>(G), Ts, w, Tce,
+                                 nullptr, nws, lane);
     wave_fence();
     C.refresh_lists(gw, w, h, H, parity, lane);
     wave_fence();
@@ -1712,8 +1707,9 @@ __global__ __launch_bounds__(256) void plain_xmap_kernel(FwdArgs A, PlainBufs Bf
   const ProbDesc P = A.probs[b];
   const int w = blockIdx.x * 4 + wave_id(threadIdx.x);
   if (w >= nwindows(A.T)) return;
-  xmap_window<KS, false>(A.W, A.nc, Bf.xb[pp] + P.coef_off, P.n, Bf.X + (size_t)P.pos_off * 2,
-                         A.T, w, A.T, nullptr, 0, P.a, 0.f, threadIdx.x & 63);
+  xmap_window<KS, false, false>(A.W, A.nc, Bf.xb[pp] + P.coef_off, P.n,
+                                Bf.X + (size_t)P.pos_off * 2, A.T, w, A.T, nullptr, 0,
+                                threadIdx.x & 63);
 }
 
 __global__ __launch_bounds__(256) void plain_constraint_kernel(FwdArgs A, PlainBufs Bf,
