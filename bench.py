@@ -2,7 +2,10 @@
 
 One step = one batched forward (sf_project, L* iterations, checkpoints saved)
 plus the adjoint (sf_project_backward) over the whole batch: every step of the
-hot path.  Default workload: 64 independent problems of 32 robots and 20
+hot path.  The checkpoint interval k is chosen from the device memory: every
+iterate is kept when the history fits in a quarter of the free HBM (the
+adjoint then recomputes nothing), else the smallest k that fits; a workload
+that specifies k uses it.  The rate at k = 10 is reported beside it.  Default workload: 64 independent problems of 32 robots and 20
 obstacles (12 m arena, 11 Bernstein coefficients per axis, 100 time steps),
 run for L* iterations, the smallest multiple of 10 at which every problem's
 FP64-oracle residual is <= 1e-3 (determined offline by oracle/lstar.py).
@@ -33,7 +36,19 @@ METRIC = "SF problems/s (fwd, fwd+bwd) at 32 robots, residual≤1e-3; batched vs
 RHO = 0.5
 # L* per workload at rho = 0.5 (oracle/lstar.py; recorded with its output in the design doc)
 LSTAR = {1: 100, 2: 400, 3: 2000, 4: 2000, 5: 2000}
-CKPT = 10
+CKPT_SPECIFIED = {5: 10}     # workloads whose description fixes the checkpoint interval
+CKPT_REFERENCE = 10
+
+
+def choose_checkpoint_interval(L, coef_total, free_bytes, budget_frac=0.25):
+    """Smallest k whose checkpoint area (ceil(L/k) iterates of 2 coefficient
+    arrays, FP32) fits in budget_frac of the free device memory."""
+    per_iterate = 2 * coef_total * 4
+    budget = budget_frac * free_bytes
+    k = 1
+    while k < max(L, 1) and -(-L // k) * per_iterate > budget:
+        k += 1
+    return k
 # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz; FMA = 2 flops.  Packed FP32
 # is disabled in this build, so scalar FP32 FMA is the attainable ceiling.
 PEAK_ALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12          # 78.6
@@ -120,6 +135,7 @@ def main(argv=None):
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--ckpt", type=int, default=0, help="checkpoint interval (0 = from memory)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
@@ -153,9 +169,15 @@ def main(argv=None):
     pk = pack(probs)
     B = len(probs)
     torch.cuda.synchronize()
+    if a.ckpt:
+        ckpt = a.ckpt
+    elif a.config in CKPT_SPECIFIED:
+        ckpt = CKPT_SPECIFIED[a.config]
+    else:
+        ckpt = choose_checkpoint_interval(L, int(pk.xi.size), torch.cuda.mem_get_info(dev)[0])
     t_setup = time.perf_counter()
     plan = SFPlan(pk.n_robots, pk.n_obs, pk.robot_a, pk.box, pk.n_coef, pk.n_steps, RHO,
-                  checkpoint_every=CKPT, max_iters=L, threads=a.threads, device=dev)
+                  checkpoint_every=ckpt, max_iters=L, threads=a.threads, device=dev)
     torch.cuda.synchronize()
     setup_ms = (time.perf_counter() - t_setup) * 1e3
     t = to_device(pk, dev)
@@ -213,6 +235,23 @@ def main(argv=None):
         unfused = dict(ms=unfused_ms, problems_per_s=B / (unfused_ms / 1e3),
                        max_abs_diff_vs_batched=float((xu - out[0]).abs().max().item()))
 
+    # the same step with checkpoints every CKPT_REFERENCE iterates (recompute in the adjoint)
+    ref_rate = None
+    if ckpt != CKPT_REFERENCE:
+        plan_k = SFPlan(pk.n_robots, pk.n_obs, pk.robot_a, pk.box, pk.n_coef, pk.n_steps, RHO,
+                        checkpoint_every=CKPT_REFERENCE, max_iters=L, threads=a.threads,
+                        device=dev)
+        plan_k.project(*args, L, save=True)
+        plan_k.backward(g_out, None, g_res)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            plan_k.project(*args, L, save=True)
+            plan_k.backward(g_out, None, g_res)
+        torch.cuda.synchronize()
+        ref_rate = B / ((time.perf_counter() - t0) / a.steps)
+        plan_k.close()
+
     plain = None
     if not a.no_plain:
         e0.record(stream)
@@ -248,9 +287,10 @@ def main(argv=None):
                 data="synthetic",
                 config=dict(workload=f"{cfg.name}: {cfg.description}", global_batch=B,
                             robots=int(pk.n_robots.max()), obstacles=int(pk.n_obs.max()),
-                            n_coef=nc, n_steps=T, iters=L, rho=RHO, checkpoint_every=CKPT,
+                            n_coef=nc, n_steps=T, iters=L, rho=RHO, checkpoint_every=ckpt,
                             threads_fwd=plan.threads, residual_tol=1e-3),
                 fwd_problems_per_s=round(B / (fwd_only_ms / 1e3), 2),
+                fwd_bwd_problems_per_s_ckpt10=None if ref_rate is None else round(ref_rate, 2),
                 fwd_ms=round(fwd_only_ms, 4),
                 plain_fwd_problems_per_s=None if plain is None else round(plain["problems_per_s"], 2),
                 batched_over_plain_fwd=None if plain is None else

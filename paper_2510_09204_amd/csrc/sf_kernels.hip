@@ -53,6 +53,7 @@ namespace {
 constexpr int kRed = 64;      // floats of LDS reduction scratch
 constexpr int kMeans = 4 * kMaxCoef + 8;
 constexpr int kMaxParts = 4;  // waves sharing one window
+constexpr int kMaxWaves = 16; // waves of the largest workgroup
 
 typedef unsigned long long u64;
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -337,25 +338,32 @@ __device__ __forceinline__ void masks_window(const float4* __restrict__ box, int
   }
 }
 
-// Neighbour-list check of window w (one lane per robot): true when some
-// robot's box has grown by more than the skin beyond its reference box (or a
-// box is not finite); the references for the next check are written to
-// ref_next (the current boxes after a rebuild, else unchanged).  Every wave
-// that works on the window computes the same answer from the same data.
-__device__ __forceinline__ bool lists_stale(const float4* __restrict__ box3,
-                                            const float4* __restrict__ ref,
-                                            float4* __restrict__ ref_next, int n, int nws, int w,
-                                            float skin, int lane) {
-  const int i = min(lane, n - 1);
-  const float4 b = box3[__umul24(i, nws) + w];
-  const float4 r = ref[i];
-  const float g = fmaxf(fmaxf(r.x - b.x, b.y - r.y), fmaxf(r.z - b.z, b.w - r.w));
-  const bool moved = lane < n && !(g <= skin);
-  const bool stale = __builtin_amdgcn_ballot_w64(moved) != 0ull;
-  if (lane < n)
-    ref_next[i] = make_float4(stale ? b.x : r.x, stale ? b.y : r.y, stale ? b.z : r.z,
-                              stale ? b.w : r.w);
-  return stale;
+// Validity of the candidate lists, checked on coefficients.  A robot's
+// position is a convex combination of its coefficients (Bernstein basis of eq.
+// poly: non-negative weights summing to one), so on each axis no position moves
+// further than the largest change of that axis's coefficients.  The lists stay
+// valid while no coefficient differs from its value at the last rebuild by more
+// than the skin.  Each wave records in its slot whether a coefficient it
+// compared moved further; the units rebuild when any slot is set.
+__device__ __forceinline__ void note_moved(bool moved, int* __restrict__ slots, int wave,
+                                           int lane) {
+  const bool any = __builtin_amdgcn_ballot_w64(moved) != 0ull;
+  if (lane == 0) slots[wave] = any ? 1 : 0;
+}
+__device__ __forceinline__ bool lists_moved(const int* __restrict__ slots, int nwaves,
+                                            int lane) {
+  const int v = lane < nwaves ? slots[lane] : 0;
+  return __builtin_amdgcn_ballot_w64(v != 0) != 0ull;
+}
+// Block-wide check of the iterate x against the reference coefficients; a
+// thread compares the entries it wrote itself, so no barrier is needed before.
+template <int NT>
+__device__ __forceinline__ void check_lists(const float* __restrict__ x,
+                                            const float* __restrict__ ref, int S, float skin,
+                                            int* __restrict__ slots, int tid) {
+  bool moved = false;
+  for (int s = tid; s < S; s += NT) moved |= !(fabsf(x[s] - ref[s]) <= skin);
+  note_moved(moved, slots, wave_id(tid), tid & 63);
 }
 
 // Next candidate of a lane's mask word (lowest set bit) plus base (a multiple
@@ -774,9 +782,12 @@ __device__ __forceinline__ void update_fwd_p2(int nc, int n, const float* __rest
                                               const floatx4 (&accP)[tiles_per_wave(NT)],
                                               const float* __restrict__ xb,
                                               float* __restrict__ xn, bool last, float& dzsq,
-                                              int wave, int lane) {
+                                              const float* __restrict__ refc,
+                                              int* __restrict__ lslot, float skin, int wave,
+                                              int lane) {
   constexpr int TPW = tiles_per_wave(NT);
   const int m = lane & 15, kq = lane >> 4;
+  bool moved = false;
 #pragma unroll
   for (int q = 0; q < TPW; ++q) {
     Tile t;
@@ -790,6 +801,7 @@ __device__ __forceinline__ void update_fwd_p2(int nc, int n, const float* __rest
         const int s = __umul24(t.ax * n + io, nc) + cb;
         const float val = accP[q][v] + mean;
         xn[s] = val;
+        if (lslot) moved |= !(fabsf(val - refc[s]) <= skin);
         if (last) {
           const float d = val - xb[s];
           dzsq = fmaf(d, d, dzsq);
@@ -797,6 +809,7 @@ __device__ __forceinline__ void update_fwd_p2(int nc, int n, const float* __rest
       }
     }
   }
+  if (lslot) note_moved(moved, lslot, wave, lane);
 }
 
 // Constant term c_xi = S xi + N b, mode form (first block of K^{-1} applied to
@@ -924,30 +937,28 @@ struct Ctx {
   const float4* obs;    // (cx, cy, a_o, a_o^2)
   const float4* obox;   // obstacle boxes widened by their margin
   float* box3;          // window boxes [robot][window] (xmin, xmax, ymin, ymax)
-  unsigned* masks;      // [chunk window][word][row]
-  float4* vref;         // [2][chunk window][n_max] reference boxes of the lists
-  int mrow, mpw, mstride, nwt, n_max;
+  unsigned* masks;      // [window][word][row]
+  float* refc;          // coefficients at the last list rebuild
+  int* lslot;           // per-wave "moved" flags of the list check
+  int mrow, mpw, mstride;
   float skin;
   bool chunked;  // T > Tc: the LDS W table holds one time chunk at a time
 
   __device__ __forceinline__ int Ts() const { return tstride(Tc); }
   __device__ __forceinline__ int nws() const { return nwindows(Tc); }
-  __device__ __forceinline__ unsigned* mwin(int gw) const { return masks + gw * mstride; }
+  __device__ __forceinline__ unsigned* mwin(int w) const { return masks + w * mstride; }
 
-  // Check window gw's candidate lists against the boxes just computed for
-  // local window w and rebuild this part's lists when they are stale.  The
-  // reference boxes alternate between two buffers from pass to pass (parity).
-  __device__ __forceinline__ void refresh_lists(int gw, int w, int h, int H, int parity,
+  // After a rebuild of window 0's lists: this part's robots' coefficients
+  // become the reference of the list check.
+  __device__ __forceinline__ void set_reference(const float* __restrict__ xb, int h, int H,
                                                 int lane) const {
-    const float4* b3 = reinterpret_cast<const float4*>(box3);
-    if (chunked) {
-      masks_window(b3, n, obox, M, a, skin, mwin(w), mrow, mpw, nws(), w, h, H, lane);
-      return;
+    const int cnt = part_count(n, h, H), per = 2 * nc;
+    for (int e = lane; e < cnt * per; e += 64) {
+      const int t = e / per, r = e - t * per;
+      const int ax = r >= nc, c = r - ax * nc;
+      const int s = __umul24(ax * n + part_robot(t, h, H), nc) + c;
+      refc[s] = xb[s];
     }
-    const float4* ref = vref + (parity * nwt + gw) * n_max;
-    float4* nxt = vref + ((parity ^ 1) * nwt + gw) * n_max;
-    if (lists_stale(b3, ref, nxt, n, nws(), w, skin, lane))
-      masks_window(b3, n, obox, M, a, skin, mwin(gw), mrow, mpw, nws(), w, h, H, lane);
   }
 
   // Make the LDS W table hold rows k0 .. k0+Tce-1 (block-wide; no-op when
@@ -969,20 +980,27 @@ template <int NT, int KS>
 __device__ __forceinline__ void chunk_units(const Ctx& C, int chunk, int Tce, const float* xb,
                                             float2* X, float2* V, float* part, bool accumulate,
                                             bool accum, float& r1sq, float& r2sq, float w_pair,
-                                            float w_box, int parity) {
+                                            float w_box) {
   const int lane = lane_here(C.tid), wave = wave_id(C.tid), nwaves = NT >> 6;
+  const bool rebuild = C.chunked || lists_moved(C.lslot, nwaves, lane);
   const int nwin = nwindows(Tce);
   const int H = parts_per_window(C.n, nwin, nwaves);
   const int Ts = C.Ts(), nws = C.nws();
   for (int u = wave; u < nwin * H; u += nwaves) {
     const int w = u / H, h = u - w * H;
-    const int gw = chunk * nws + w;
-    xmap_window<KS, true, true>(C.W, C.nc, xb, C.n, reinterpret_cast<float*>(X), Ts, w, Tce,
-                                C.box3, nws, lane);
+    if (rebuild) {
+      xmap_window<KS, true, true>(C.W, C.nc, xb, C.n, reinterpret_cast<float*>(X), Ts, w, Tce,
+                                  C.box3, nws, lane);
+      wave_fence();
+      masks_window(reinterpret_cast<const float4*>(C.box3), C.n, C.obox, C.M, C.a, C.skin,
+                   C.mwin(w), C.mrow, C.mpw, nws, w, h, H, lane);
+      if (w == 0 && !C.chunked) C.set_reference(xb, h, H, lane);
+    } else {
+      xmap_window<KS, false, true>(C.W, C.nc, xb, C.n, reinterpret_cast<float*>(X), Ts, w, Tce,
+                                   nullptr, nws, lane);
+    }
     wave_fence();
-    C.refresh_lists(gw, w, h, H, parity, lane);
-    wave_fence();
-    constraints_window(X, V, C.n, Ts, C.obs, C.M, C.mwin(C.chunked ? w : gw), C.mrow, C.mpw, C.a,
+    constraints_window(X, V, C.n, Ts, C.obs, C.M, C.mwin(w), C.mrow, C.mpw, C.a,
                        C.pmin0, C.pmin1, C.pmax0, C.pmax1, w, Tce, h, H, accum, r1sq, r2sq,
                        w_pair, w_box, lane);
     if (part) {
@@ -1004,7 +1022,7 @@ template <int NT, int KS>
 __device__ __forceinline__ bool sf_iteration(const Ctx& C, const float* xb, float* xn,
                                              const float* lam, float* lam_n, float* csum,
                                              float2* X, float2* V, float* part, const float* cx,
-                                             bool want_dz, float& dzsq, int& epoch,
+                                             bool want_dz, float& dzsq,
                                              bool check = false, float tol = 0.f,
                                              float* red = nullptr) {
   const int wave = wave_id(C.tid);
@@ -1012,10 +1030,8 @@ __device__ __forceinline__ bool sf_iteration(const Ctx& C, const float* xb, floa
   for (int k0 = 0, ch = 0; k0 < C.T; k0 += C.Tc, ++ch) {
     const int Tce = min(C.Tc, C.T - k0);
     C.wchunk<NT>(k0, Tce);
-    chunk_units<NT, KS>(C, ch, Tce, xb, X, V, part, k0 > 0, check, d1, d2, 1.f, 1.f,
-                        epoch & 1);
+    chunk_units<NT, KS>(C, ch, Tce, xb, X, V, part, k0 > 0, check, d1, d2, 1.f, 1.f);
   }
-  ++epoch;
   if (check) {
     d1 = wave_sum_dpp(d1);
     d2 = wave_sum_dpp(d2);
@@ -1039,7 +1055,8 @@ __device__ __forceinline__ bool sf_iteration(const Ctx& C, const float* xb, floa
     stop = sqrtf(r1 + r2) <= tol;
   }
   lane = lane_here(C.tid);
-  update_fwd_p2<NT>(C.nc, C.n, csum, accP, xb, xn, want_dz, dzsq, wave, lane);
+  update_fwd_p2<NT>(C.nc, C.n, csum, accP, xb, xn, want_dz, dzsq, C.refc,
+                    C.chunked ? nullptr : C.lslot, C.skin, wave, lane);
   __syncthreads();
   return stop;
 }
@@ -1048,14 +1065,12 @@ __device__ __forceinline__ bool sf_iteration(const Ctx& C, const float* xb, floa
 // return); V is scratch.
 template <int NT, int KS>
 __device__ __forceinline__ void residual_norms(const Ctx& C, const float* xb, float2* X,
-                                               float2* V, float& r1sq, float& r2sq, int& epoch) {
+                                               float2* V, float& r1sq, float& r2sq) {
   for (int k0 = 0, ch = 0; k0 < C.T; k0 += C.Tc, ++ch) {
     const int Tce = min(C.Tc, C.T - k0);
     C.wchunk<NT>(k0, Tce);
-    chunk_units<NT, KS>(C, ch, Tce, xb, X, V, nullptr, false, true, r1sq, r2sq, 1.f, 1.f,
-                        epoch & 1);
+    chunk_units<NT, KS>(C, ch, Tce, xb, X, V, nullptr, false, true, r1sq, r2sq, 1.f, 1.f);
   }
-  ++epoch;
 }
 
 // LDS floats of the box and mask regions.
@@ -1066,28 +1081,27 @@ __host__ __device__ inline int box_floats(int Tc, int n_max) {
 // it is LDS-resident (lists persist across iterations), else those of one time
 // chunk (lists are rebuilt on every pass).
 __host__ __device__ inline int horizon_windows(int T, int Tc) {
-  return Tc >= T ? nwindows(T) : nwindows(Tc);
+  return nwindows(min(T, Tc));
 }
 __host__ __device__ inline int mask_floats(int T, int Tc, int n_max, int M_max) {
   return horizon_windows(T, Tc) * mask_words(n_max, M_max);
 }
-__host__ __device__ inline int vref_floats(int T, int Tc, int n_max) {
-  return 2 * horizon_windows(T, Tc) * n_max * 4;
-}
+// Reference coefficients of the list check and the per-wave flags.
+__host__ __device__ inline int list_floats(int S_max) { return ((S_max + 3) & ~3) + kMaxWaves; }
 
 // Skin of the candidate lists: a quarter of the robot size.
 __device__ __forceinline__ float list_skin(float a) { return 0.25f * a; }
 
-// Empty reference boxes: the first check of every window rebuilds its lists.
-__device__ __forceinline__ void clear_refs(float4* __restrict__ vref, int count, int tid,
-                                           int nthr) {
-  const float inf = __builtin_inff();
-  for (int t = tid; t < count; t += nthr) vref[t] = make_float4(inf, -inf, inf, -inf);
+// Every wave flags "moved": the first pass builds all lists.
+__device__ __forceinline__ void force_rebuild(int* __restrict__ lslot, int tid) {
+  if (tid < kMaxWaves) lslot[tid] = 1;
 }
 
 struct FwdLds {
   float *W, *fac, *xbA, *xbB, *lamA, *lamB, *cx, *part, *means, *red, *csum, *box3;
-  float4 *obs, *obox, *vref;
+  float4 *obs, *obox;
+  float* refc;
+  int* lslot;
   unsigned* masks;
   float2 *X, *V;
 };
@@ -1111,7 +1125,9 @@ __device__ __forceinline__ FwdLds carve_fwd(float* sm, int nc, int T, int Tc, in
   L.obox = reinterpret_cast<float4*>(p); p += 4 * M_max;
   L.box3 = p; p += box_floats(Tc, n_max);
   L.masks = reinterpret_cast<unsigned*>(p); p += mask_floats(T, Tc, n_max, M_max);
-  L.vref = reinterpret_cast<float4*>(p); p += vref_floats(T, Tc, n_max);
+  L.refc = p;
+  L.lslot = reinterpret_cast<int*>(p + ((S_max + 3) & ~3));
+  p += list_floats(S_max);
   L.X = reinterpret_cast<float2*>(p); p += 2 * n_max * tstride(Tc);
   L.V = reinterpret_cast<float2*>(p);
   return L;
@@ -1122,7 +1138,7 @@ __device__ __forceinline__ FwdLds carve_fwd(float* sm, int nc, int T, int Tc, in
 size_t fwd_lds_bytes(int nc, int T, int Tc, int n_max, int M_max, int S_max, int) {
   auto r4 = [](int x) { return (size_t)((x + 3) & ~3); };
   size_t f = r4(nc * Tc) + r4(fac_stride(nc)) + (5 + nwindows(Tc)) * r4(S_max) + kMeans + kRed +
-             kColSums + 8 * (size_t)M_max + box_floats(Tc, n_max) + mask_floats(T, Tc, n_max, M_max) + vref_floats(T, Tc, n_max) +
+             kColSums + 8 * (size_t)M_max + box_floats(Tc, n_max) + mask_floats(T, Tc, n_max, M_max) + list_floats(S_max) +
              4 * (size_t)n_max * tstride(Tc);
   return f * sizeof(float);
 }
@@ -1145,11 +1161,9 @@ __global__ __launch_bounds__(NT) void fwd_fused_kernel(FwdArgs A) {
   Ctx C{n,      M,         nc,        T,         A.Tc,      S,
         tid,    A.rho,     P.a,       P.pmin[0], P.pmin[1], P.pmax[0],
         P.pmax[1], L.W,    L.fac,     A.W,       L.obs,     L.obox,
-        L.box3, L.masks,   L.vref,    mask_rows(A.n_max), (A.n_max + 31) >> 5,
-        mask_words(A.n_max, A.M_max), horizon_windows(T, A.Tc), A.n_max,
-        A.Tc < T ? 0.f : list_skin(P.a), A.Tc < T};
-  int epoch = 0;   // passes over the horizon (parity of the list reference buffers)
-  clear_refs(L.vref, vref_floats(T, A.Tc, A.n_max) / 4, tid, NT);
+        L.box3, L.masks,   L.refc,    L.lslot,   mask_rows(A.n_max), (A.n_max + 31) >> 5,
+        mask_words(A.n_max, A.M_max), A.Tc < T ? 0.f : list_skin(P.a), A.Tc < T};
+  force_rebuild(L.lslot, tid);
   if (!C.chunked) load_wchunk(A.W, L.W, nc, 0, T, tid, NT);
   for (int t = tid; t < fs; t += NT) L.fac[t] = A.fac[(size_t)P.fac * fs + t];
   for (int m = tid; m < M; m += NT) {
@@ -1201,7 +1215,7 @@ __global__ __launch_bounds__(NT) void fwd_fused_kernel(FwdArgs A) {
     const bool want_dz = check || l == A.L - 1;
     if (want_dz) dzsq = 0.f;   // the reported ||dz|| is that of the last update
     const bool stop = sf_iteration<NT, KS>(C, xb, xn, lam, lamn, L.csum, L.X, L.V, L.part, L.cx,
-                                           want_dz, dzsq, epoch, check, A.tol, L.red);
+                                           want_dz, dzsq, check, A.tol, L.red);
     float* t = xb;
     xb = xn;
     xn = t;
@@ -1228,7 +1242,7 @@ __global__ __launch_bounds__(NT) void fwd_fused_kernel(FwdArgs A) {
   }
   // residual of the returned iterate
   float r1sq = 0.f, r2sq = 0.f;
-  residual_norms<NT, KS>(C, xb, L.X, L.V, r1sq, r2sq, epoch);
+  residual_norms<NT, KS>(C, xb, L.X, L.V, r1sq, r2sq);
   float v[4] = {r1sq, r2sq, dzsq, bad};
   block_sum(v, L.red);
   if (tid == 0) {
@@ -1279,7 +1293,9 @@ namespace {
 
 struct BwdLds {
   float *W, *fac, *red, *csum, *gA, *gB, *glam, *gxi, *cx, *b0, *b1, *b2, *b3, *part, *box3;
-  float4 *obs, *obox, *vref;
+  float4 *obs, *obox;
+  float* refc;
+  int* lslot;
   unsigned* masks;
   float2 *X, *G, *H;
 };
@@ -1302,7 +1318,9 @@ __device__ __forceinline__ BwdLds carve_bwd(float* sm, int nc, int T, int Tc, in
   L.obox = reinterpret_cast<float4*>(p); p += 4 * M_max;
   L.box3 = p; p += box_floats(Tc, n_max);
   L.masks = reinterpret_cast<unsigned*>(p); p += mask_floats(T, Tc, n_max, M_max);
-  L.vref = reinterpret_cast<float4*>(p); p += vref_floats(T, Tc, n_max);
+  L.refc = p;
+  L.lslot = reinterpret_cast<int*>(p + ((S_max + 3) & ~3));
+  p += list_floats(S_max);
   L.X = reinterpret_cast<float2*>(p); p += 2 * n_max * tstride(Tc);
   L.G = reinterpret_cast<float2*>(p); p += 2 * n_max * tstride(Tc);
   L.H = reinterpret_cast<float2*>(p);
@@ -1435,22 +1453,29 @@ __device__ __forceinline__ void update_bwd_p2(int nc, int n, const float* __rest
 template <int NT, int KS>
 __device__ __forceinline__ void adjoint_units(const Ctx& C, int chunk, int Tce, const float* xb,
                                               const float* gR, float2* X, float2* G, float2* Hb,
-                                              float* part, bool accumulate, int parity) {
+                                              float* part, bool accumulate) {
   const int lane = lane_here(C.tid), wave = wave_id(C.tid), nwaves = NT >> 6;
+  const bool rebuild = C.chunked || lists_moved(C.lslot, nwaves, lane);
   const int nwin = nwindows(Tce);
   const int H = parts_per_window(C.n, nwin, nwaves);
   const int Ts = C.Ts(), nws = C.nws();
   for (int u = wave; u < nwin * H; u += nwaves) {
     const int w = u / H, h = u - w * H;
-    const int gw = chunk * nws + w;
-    xmap_window<KS, true, true>(C.W, C.nc, xb, C.n, reinterpret_cast<float*>(X), Ts, w, Tce,
-                                C.box3, nws, lane);
+    if (rebuild) {
+      xmap_window<KS, true, true>(C.W, C.nc, xb, C.n, reinterpret_cast<float*>(X), Ts, w, Tce,
+                                  C.box3, nws, lane);
+      wave_fence();
+      masks_window(reinterpret_cast<const float4*>(C.box3), C.n, C.obox, C.M, C.a, C.skin,
+                   C.mwin(w), C.mrow, C.mpw, nws, w, h, H, lane);
+      if (w == 0 && !C.chunked) C.set_reference(xb, h, H, lane);
+    } else {
+      xmap_window<KS, false, true>(C.W, C.nc, xb, C.n, reinterpret_cast<float*>(X), Ts, w, Tce,
+                                   nullptr, nws, lane);
+    }
     xmap_window<KS, false, true>(C.W, C.nc, gR, C.n, reinterpret_cast<float*>(G), Ts, w, Tce,
                                  nullptr, nws, lane);
     wave_fence();
-    C.refresh_lists(gw, w, h, H, parity, lane);
-    wave_fence();
-    vjp_window(X, G, Hb, C.n, Ts, C.obs, C.M, C.mwin(C.chunked ? w : gw), C.mrow, C.mpw, C.a,
+    vjp_window(X, G, Hb, C.n, Ts, C.obs, C.M, C.mwin(w), C.mrow, C.mpw, C.a,
                C.pmin0, C.pmin1, C.pmax0, C.pmax1, w, Tce, h, H, lane);
     wave_fence();
     wtmap_window<KS>(C.W, C.nc, reinterpret_cast<const float*>(Hb), C.n, Ts, w, Tce, h, H,
@@ -1476,11 +1501,9 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
   Ctx C{n,      M,         nc,        T,         Tc,        S,
         tid,    rho,       P.a,       P.pmin[0], P.pmin[1], P.pmax[0],
         P.pmax[1], L.W,    L.fac,     A.W,       L.obs,     L.obox,
-        L.box3, L.masks,   L.vref,    mask_rows(A.n_max), (A.n_max + 31) >> 5,
-        mask_words(A.n_max, A.M_max), horizon_windows(T, Tc), A.n_max,
-        Tc < T ? 0.f : list_skin(P.a), Tc < T};
-  int epoch = 0;   // passes over the horizon (parity of the list reference buffers)
-  clear_refs(L.vref, vref_floats(T, Tc, A.n_max) / 4, tid, NT);
+        L.box3, L.masks,   L.refc,    L.lslot,   mask_rows(A.n_max), (A.n_max + 31) >> 5,
+        mask_words(A.n_max, A.M_max), Tc < T ? 0.f : list_skin(P.a), Tc < T};
+  force_rebuild(L.lslot, tid);
   const int nwin0 = nwindows(min(Tc, T));
   if (!C.chunked) load_wchunk(A.W, L.W, nc, 0, T, tid, NT);
   for (int t = tid; t < fs; t += NT) L.fac[t] = A.fac[(size_t)P.fac * fs + t];
@@ -1508,7 +1531,7 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
     for (int s = tid; s < S; s += NT) L.b0[s] = A.fin[P.coef_off + s];
     __syncthreads();
     float r1sq = 0.f, r2sq = 0.f;
-    residual_norms<NT, KS>(C, L.b0, L.X, L.G, r1sq, r2sq, epoch);
+    residual_norms<NT, KS>(C, L.b0, L.X, L.G, r1sq, r2sq);
     float v[2] = {r1sq, r2sq};
     block_sum(v, L.red);
     const float c1 = v[0] > 0.f ? gr1 / sqrtf(v[0]) : 0.f;
@@ -1517,10 +1540,8 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
     for (int k0 = 0, ch = 0; k0 < T; k0 += Tc, ++ch) {
       const int Tce = min(Tc, T - k0);
       C.wchunk<NT>(k0, Tce);
-      chunk_units<NT, KS>(C, ch, Tce, L.b0, L.X, L.H, L.part, k0 > 0, false, d1, d2, c1, c2,
-                          epoch & 1);
+      chunk_units<NT, KS>(C, ch, Tce, L.b0, L.X, L.H, L.part, k0 > 0, false, d1, d2, c1, c2);
     }
-    ++epoch;
     add_partials(gx, L.part, nwin0, S, tid, NT);
     __syncthreads();
   }
@@ -1548,6 +1569,7 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
         sg[s] = x;
         sg[St + s] = lm;
       }
+      if (!C.chunked) check_lists<NT>(xr, L.refc, S, C.skin, L.lslot, tid);
       if (pending && l1 - 1 > l0) {
         // the recompute reuses the partial buffer: fold it into gx first
         add_partials(gx, L.part, nwin0, S, tid, NT);
@@ -1555,7 +1577,7 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
       }
       __syncthreads();
       for (int l = l0; l < l1 - 1; ++l) {
-        sf_iteration<NT, KS>(C, xr, xq, lr, lq, L.csum, L.X, L.G, L.part, L.cx, false, dz, epoch);
+        sf_iteration<NT, KS>(C, xr, xq, lr, lq, L.csum, L.X, L.G, L.part, L.cx, false, dz);
         float* t = xr;
         xr = xq;
         xq = t;
@@ -1578,6 +1600,7 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
       float* xbl = L.b0;
       float* gR = L.b2;
       for (int s = tid; s < S; s += NT) xbl[s] = cur[s];
+      if (!C.chunked) check_lists<NT>(xbl, L.refc, S, C.skin, L.lslot, tid);
       int lane = lane_here(tid);
       update_bwd_p1<NT, KS>(L.fac, nc, n, gx, pending ? L.part : nullptr, nwin0, S, cur, nxt, fw,
                             L.csum, L.csum + kColSums, accU, accN, wave, lane);
@@ -1590,9 +1613,8 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
       for (int k0 = 0, ch = 0; k0 < T; k0 += Tc, ++ch) {
         const int Tce = min(Tc, T - k0);
         C.wchunk<NT>(k0, Tce);
-        adjoint_units<NT, KS>(C, ch, Tce, xbl, gR, L.X, L.G, L.H, L.part, k0 > 0, epoch & 1);
+        adjoint_units<NT, KS>(C, ch, Tce, xbl, gR, L.X, L.G, L.H, L.part, k0 > 0);
       }
-      ++epoch;
       pending = true;
       float* t = gx;
       gx = gn;
@@ -1615,7 +1637,7 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
 size_t bwd_lds_bytes(int nc, int T, int Tc, int n_max, int M_max, int S_max, int) {
   auto r4 = [](int x) { return (size_t)((x + 3) & ~3); };
   size_t f = r4(nc * Tc) + r4(fac_stride(nc)) + kRed + 2 * kColSums + (9 + nwindows(Tc)) * r4(S_max) +
-             8 * (size_t)M_max + box_floats(Tc, n_max) + mask_floats(T, Tc, n_max, M_max) + vref_floats(T, Tc, n_max) +
+             8 * (size_t)M_max + box_floats(Tc, n_max) + mask_floats(T, Tc, n_max, M_max) + list_floats(S_max) +
              6 * (size_t)n_max * tstride(Tc);
   return f * sizeof(float);
 }
@@ -1770,7 +1792,7 @@ __global__ __launch_bounds__(256) void plain_update_kernel(FwdArgs A, PlainBufs 
                          plain_lam(Bf, pp ^ 1) + P.coef_off, xb, cx, A.rho, last, dzsq, csum,
                          accP, wave, lane);
   __syncthreads();
-  update_fwd_p2<256>(nc, n, csum, accP, xb, xn, last, dzsq, wave, lane);
+  update_fwd_p2<256>(nc, n, csum, accP, xb, xn, last, dzsq, nullptr, nullptr, 0.f, wave, lane);
   if (last) {
     float v[1] = {dzsq};
     block_sum(v, red);
