@@ -138,6 +138,8 @@ def main(argv=None):
     ap.add_argument("--ckpt", type=int, default=0, help="checkpoint interval (0 = from memory)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-ref", action="store_true",
+                    help="skip the rate at the reference checkpoint interval")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (counter calibration)")
@@ -237,7 +239,7 @@ def main(argv=None):
 
     # the same step with checkpoints every CKPT_REFERENCE iterates (recompute in the adjoint)
     ref_rate = None
-    if ckpt != CKPT_REFERENCE:
+    if ckpt != CKPT_REFERENCE and not a.no_ref:
         plan_k = SFPlan(pk.n_robots, pk.n_obs, pk.robot_a, pk.box, pk.n_coef, pk.n_steps, RHO,
                         checkpoint_every=CKPT_REFERENCE, max_iters=L, threads=a.threads,
                         device=dev)
