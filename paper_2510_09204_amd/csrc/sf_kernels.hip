@@ -238,19 +238,15 @@ __device__ __forceinline__ void xmap_window(const float* __restrict__ W, int nc,
   }
   const int k0 = w * 16 + 4 * kq;
   for (int nt0 = 0; nt0 < ncol; nt0 += 4) {
+    // B at clamped entries: A is zero past nc, padded columns are not stored
     float bv[4][KS];
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
       const int col = (nt0 + g) * 16 + m;
-      const bool ok = (col >> 1) < n;
       const int i = min(col >> 1, n - 1), ax = col & 1;
       const float* brow = xb + __umul24(ax * n + i, nc);
 #pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        const int c = 4 * s + kq;
-        const float v = brow[min(c, nc - 1)];
-        bv[g][s] = (ok && c < nc) ? v : 0.f;
-      }
+      for (int s = 0; s < KS; ++s) bv[g][s] = brow[min(4 * s + kq, nc - 1)];
     }
     floatx4 acc[4];
 #pragma unroll
@@ -588,13 +584,11 @@ __device__ __forceinline__ void wtmap_window(const float* __restrict__ W, int nc
     const int i = col >> 1, ax = col & 1;
     const bool colok = i < n;
     const float* vrow = Vf + __umul24(min(i, n - 1), Ts) * 2 + ax;
+    // V at clamped steps: the W^T operand is zero past Tce, padded columns
+    // are not stored
     float bv[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int kk = w * 16 + 4 * s + kq;
-      const float v = vrow[2 * min(kk, Tce - 1)];
-      bv[s] = (kk < Tce && colok) ? v : 0.f;
-    }
+    for (int s = 0; s < 4; ++s) bv[s] = vrow[2 * min(w * 16 + 4 * s + kq, Tce - 1)];
 #pragma unroll
     for (int ct = 0; ct < NCT; ++ct) {
       if (ct >= nct) break;
@@ -682,16 +676,15 @@ __device__ __forceinline__ void mode_tile(const float* __restrict__ fac, int nc,
   const int kq = lane >> 4;
   const int nc2 = nc * nc;
   const int cbc = min(cb, nc - 1);
+  // B is read at clamped (finite) entries: A is zero at padded k, and padded
+  // output columns are never used
   float bp[KS], bd[KS];
 #pragma unroll
   for (int s = 0; s < KS; ++s) {
-    const int k = 4 * s + kq;
-    const int kc = min(k, nc - 1);
-    const bool ok = k < nc && cb < nc;
+    const int kc = min(4 * s + kq, nc - 1);
     const int idx = trans ? __umul24(kc, nc) + cbc : __umul24(cbc, nc) + kc;
-    const float p = fac[fo + idx], d = fac[fo + nc2 + idx];
-    bp[s] = ok ? p : 0.f;
-    bd[s] = ok ? d : 0.f;
+    bp[s] = fac[fo + idx];
+    bd[s] = fac[fo + nc2 + idx];
   }
 #pragma unroll
   for (int s = 0; s < KS; ++s) {
@@ -762,11 +755,12 @@ __device__ __forceinline__ void update_fwd_p1(const float* __restrict__ fac, int
       }
     }
     const int cb = t.ct * 16 + m;
+    // rows past n and columns past nc of the tile are never stored: their
+    // accumulators may start from any finite value
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int io = t.rt * 16 + 4 * kq + v;
-      const float c0 = cx[__umul24(t.ax * n + min(io, n - 1), nc) + min(cb, nc - 1)];
-      accP[q][v] = (io < n && cb < nc) ? c0 : 0.f;
+      accP[q][v] = cx[__umul24(t.ax * n + min(io, n - 1), nc) + min(cb, nc - 1)];
     }
     floatx4 accD = {0.f, 0.f, 0.f, 0.f};
     mode_tile<KS>(fac, nc, 0, false, cb, au, accP[q], accD, lane);
