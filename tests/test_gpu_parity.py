@@ -53,6 +53,25 @@ def test_c3_full_batch_sampled(gpu):
     compare_forward(probs, out, RHO, 100, idx=[0, 37, 63])
 
 
+def test_c3_benchmark_configuration_full_length(gpu):
+    """The benchmark's launch: all 64 problems, L* = 2000 iterations, every
+    iterate saved, autotuned workgroup size, then the adjoint.  Two sampled
+    problems against the oracle at full length (a mismatch is accepted only on
+    an instance the oracle itself shows to be rounding-decided); every output
+    and gradient finite."""
+    import torch
+    probs = make_batch(CONFIGS[3])
+    L = 2000
+    plan, _ = make_plan(probs, RHO, L=L, ckpt=1, threads=0)
+    out = gpu_forward(probs, RHO, L, save=True, plan=plan)
+    assert np.all(out["res"][:, 3] == 0.0)
+    g = plan.backward(torch.ones_like(out["t"]["xi"]), None, None)
+    torch.cuda.synchronize()
+    for x in g:
+        assert torch.isfinite(x).all()
+    compare_forward(probs, out, RHO, L, idx=[5, 40], allow_ill_conditioned=True)
+
+
 def test_c4_uneven_batch_sampled(gpu):
     probs = make_batch(CONFIGS[4])
     out = gpu_forward(probs, RHO, 150)
