@@ -16,7 +16,8 @@ kernels) and the batched/plain ratio, the batched-but-unfused forward rate (the
 same per-stage kernels, each launch over the whole batch) so that the gain can
 be attributed to batching and to fusion, the plan setup time (host FP64
 factors and workspace tables), the residual check on the GPU outputs, the
-roofline of the dominant kernel and the FP64 oracle timed on host cores.
+roofline of the dominant kernel and the FP64 oracle timed on one host core
+and on all available cores (one process per problem).
 """
 from __future__ import annotations
 
@@ -98,10 +99,11 @@ def measured_traffic(workload, kernel):
     return int(v) if v else None
 
 
-def cpu_baseline(problem, L, budget_s=20.0):
-    """The FP64 oracle on one problem of the workload, on one host core:
-    forward iterations for ~half the budget, then the oracle adjoint (forward +
-    reverse sweep) for the rest; scaled to problems/s at L iterations."""
+def _oracle_times(problem, budget_s):
+    """Seconds per forward iteration and per forward+adjoint iteration of the
+    FP64 oracle on one problem, on one thread: forward iterations for about
+    half the budget, then an adjoint (forward + reverse sweep) sized to about a
+    quarter of it.  Returns (t_fwd, n_fwd, t_fwd_bwd, n_fwd_bwd)."""
     from threadpoolctl import threadpool_limits
 
     from oracle import SFAdjoint, SFOracle
@@ -120,11 +122,43 @@ def cpu_baseline(problem, L, budget_s=20.0):
         t1 = time.perf_counter()
         SFAdjoint(orc).gradient(problem.xi, problem.xi, None, n_b, g, np.zeros_like(g))
         t_fb = (time.perf_counter() - t1) / n_b
-    return dict(value=1.0 / (t_fb * L), unit="problems/s", cores=1, kind="oracle",
-                sample=f"1 problem ({problem.n} robots, {problem.M} obstacles): {n_f} forward "
-                       f"iterations ({t_f * 1e3:.1f} ms each) and a {n_b}-iteration forward+"
-                       f"adjoint ({t_fb * 1e3:.1f} ms per iteration), scaled to {L} iterations",
-                fwd_value=1.0 / (t_f * L))
+    return t_f, n_f, t_fb, n_b
+
+
+def _pool_worker(job):
+    problem, budget_s = job
+    return _oracle_times(problem, budget_s)
+
+
+def cpu_pool_rates(problems, L, budget_s=8.0):
+    """The same oracle timing on every available host core at once (at most
+    16), one process per core, each on its own problem of the workload;
+    aggregate problems/s at L iterations.  Run before the GPU is touched (the
+    workers are forked)."""
+    import multiprocessing as mp
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    jobs = [(problems[w % len(problems)], budget_s) for w in range(workers)]
+    with mp.get_context("fork").Pool(workers) as pool:
+        times = pool.map(_pool_worker, jobs)
+    return dict(value=sum(1.0 / (t[2] * L) for t in times), unit="problems/s",
+                cores=workers, fwd_value=sum(1.0 / (t[0] * L) for t in times),
+                sample=f"{workers} problems, one per process, each timed as the one-core "
+                       f"sample with a {budget_s:g} s budget")
+
+
+def cpu_baseline(problem, L, budget_s=20.0, pool=None):
+    """The FP64 oracle on one problem of the workload, on one host core,
+    scaled to problems/s at L iterations; `pool` (the all-cores rate) is
+    attached when given."""
+    t_f, n_f, t_fb, n_b = _oracle_times(problem, budget_s)
+    out = dict(value=1.0 / (t_fb * L), unit="problems/s", cores=1, kind="oracle",
+               sample=f"1 problem ({problem.n} robots, {problem.M} obstacles): {n_f} forward "
+                      f"iterations ({t_f * 1e3:.1f} ms each) and a {n_b}-iteration forward+"
+                      f"adjoint ({t_fb * 1e3:.1f} ms per iteration), scaled to {L} iterations",
+               fwd_value=1.0 / (t_f * L))
+    if pool is not None:
+        out["all_cores"] = pool
+    return out
 
 
 def main(argv=None):
@@ -141,6 +175,8 @@ def main(argv=None):
     ap.add_argument("--no-ref", action="store_true",
                     help="skip the rate at the reference checkpoint interval")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--cpu-pool-budget", type=float, default=8.0,
+                    help="seconds per process of the all-cores oracle timing (0 = skip)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (counter calibration)")
     a = ap.parse_args(argv)
@@ -158,16 +194,21 @@ def main(argv=None):
               "them across GPUs without communication.", file=sys.stderr)
         return 2
 
-    import torch
-
-    from paper_2510_09204_amd import SFPlan, load_library, to_device
     from workloads import CONFIGS, make_batch, pack
 
-    load_library()
-    dev = torch.device("cuda:0")
     cfg = CONFIGS[a.config]
     L = a.iters if a.iters is not None else LSTAR[a.config]
     probs = make_batch(cfg)
+    pool = None
+    if not a.no_cpu and a.cpu_pool_budget > 0:
+        pool = cpu_pool_rates(probs, L, a.cpu_pool_budget)
+
+    import torch
+
+    from paper_2510_09204_amd import SFPlan, load_library, to_device
+
+    load_library()
+    dev = torch.device("cuda:0")
     pk = pack(probs)
     B = len(probs)
     torch.cuda.synchronize()
@@ -280,7 +321,7 @@ def main(argv=None):
                                                   tflops=round(f_bwd / bwd_ms / 1e9, 3))})
     cpu = None
     if not a.no_cpu:
-        cpu = cpu_baseline(probs[0], L, a.cpu_budget)
+        cpu = cpu_baseline(probs[0], L, a.cpu_budget, pool)
 
     value = B / (ms_per_step / 1e3)
     line = dict(metric=METRIC, value=round(value, 2), unit="problems/s", n_gpus=1,
