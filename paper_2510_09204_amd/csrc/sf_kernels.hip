@@ -26,7 +26,8 @@
 // candidate masks for its robots (a pair or obstacle is a candidate when the
 // boxes come within the constraint distance plus a rounding margin; lane j
 // tests robot j and a ballot forms the mask), the exact pair/obstacle/box
-// stage over candidates (a 16-lane row per robot walking its own list), and
+// stage over candidates (four lanes of four steps per robot, each robot
+// walking its own list), and
 // the window's share of the time->coefficient map R = W^T V on MFMA into a
 // per-window partial.  Skipped pairs are inactive at every step of the window
 // and contribute exactly 0.  The partials are summed in window order, so every
@@ -370,65 +371,89 @@ __device__ __forceinline__ int pop_candidate(unsigned& u, int base) {
   return b | base;
 }
 
-// Residual vector of a pair at difference (dx, dy) with d2 = |D|^2 < a^2:
-// (1 - a/|D|) D, and (-a, 0) from robot i's side of a coincident pair with
-// i < j (alpha = atan2(0, 0) = 0), (a, 0) from the other side.
-__device__ __forceinline__ void pair_residual(float dx, float dy, float d2, float a, bool lower,
-                                              float& rx, float& ry) {
-  if (d2 > 0.f) {
-    const float f = 1.f - a * rsqrtf(d2);
-    rx = f * dx;
-    ry = f * dy;
-  } else {
-    rx = lower ? -a : a;
-    ry = 0.f;
-  }
+// 1/sqrt(d2) by the hardware reciprocal square root (1 ulp) on an input held
+// at or above the smallest normal float, so that no input is flushed; only the
+// coincident case d2 = 0 reaches the clamp, and its result is not used.
+__device__ __forceinline__ float rsqrt_clamped(float d2) {
+  return __builtin_amdgcn_rsqf(fmaxf(d2, 1.17549435e-38f));
 }
 
-// Exact constraint stage of window w for the robots of part h (a 16-lane row
-// per robot, one lane per step): V = w_pair (pair + obstacle sums) + w_box
-// (box residual).  Each row walks its own robot's candidates in increasing
-// index (pairs, then obstacles), two per round so their loads overlap;
-// skipped pairs are inactive and would add exactly 0.  With `accum`,
-// ||r_1||^2 (each unordered pair once) and ||r_2||^2.
+// Residual vector of a pair at difference (dx, dy) with d2 = |D|^2 < a^2:
+// (1 - a/|D|) D, and (-a, 0) from robot i's side of a coincident pair with
+// i < j (alpha = atan2(0, 0) = 0), (a, 0) from the other side.  Branch-free.
+__device__ __forceinline__ void pair_residual(float dx, float dy, float d2, float a, bool lower,
+                                              float& rx, float& ry) {
+  const float f = fmaf(-a, rsqrt_clamped(d2), 1.f);
+  const bool tie = !(d2 > 0.f);
+  rx = tie ? (lower ? -a : a) : f * dx;
+  ry = tie ? 0.f : f * dy;
+}
+
+// Exact constraint stage of window w for the robots of part h: 16 robots per
+// pass, four lanes per robot and four consecutive steps per lane, so that a
+// popped candidate serves 4 steps of each lane and the pass overhead is shared
+// by 16 robots.  V = w_pair (pair + obstacle sums) + w_box (box residual).
+// Each robot walks its own candidates in increasing index (pairs, then
+// obstacles), two per round so their loads overlap; skipped pairs are
+// inactive and would add exactly 0.  Every step's sums are formed in candidate
+// order.  Position rows hold finite values up to the window's last padding
+// step, so the reads need no clamp.  With `accum`, ||r_1||^2 (each unordered
+// pair once) and ||r_2||^2.
+constexpr int kStepsPerLane = 4;
+
 __device__ __forceinline__ void constraints_window(
     const float2* __restrict__ X, float2* __restrict__ V, int n, int Ts,
     const float4* __restrict__ obs, int M, const unsigned* __restrict__ mw, int mrow, int mpw,
     float a, float pmin0, float pmin1, float pmax0, float pmax1, int w, int Tce, int h, int H,
     bool accum, float& r1sq, float& r2sq, float w_pair, float w_box, int lane) {
+  constexpr int E = kStepsPerLane, LPR = 16 / E;
   const float a2 = a * a;
-  const int kk = w * 16 + (lane & 15);
-  const int kq = min(kk, Tce - 1);
+  const int k0 = w * 16 + E * (lane & (LPR - 1));
   const int cnt = part_count(n, h, H);
-  for (int t0 = 0; t0 < cnt; t0 += 4) {
-    const int t = t0 + (lane >> 4);
+  for (int t0 = 0; t0 < cnt; t0 += 64 / LPR) {
+    const int t = t0 + lane / LPR;
     const bool live = t < cnt;
     const int i = part_robot(live ? t : t0, h, H);
-    const float2 p = X[__umul24(i, Ts) + kq];
-    float vx = 0.f, vy = 0.f, s1 = 0.f;
+    const float2* xi = X + __umul24(i, Ts) + k0;
+    float2 p[E];
+    float vx[E], vy[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      p[e] = xi[e];
+      vx[e] = 0.f;
+      vy[e] = 0.f;
+    }
+    float s1 = 0.f;
     for (int wq = 0; wq < ((n + 31) >> 5); ++wq) {
-    unsigned u = live ? mw[wq * mrow + i] : 0u;
-    while (u != 0u) {
-      int j[2];
-      float2 o[2];
+      unsigned u = live ? mw[wq * mrow + i] : 0u;
+      while (u != 0u) {
+        int j[2];
+        float2 o[2][E];
 #pragma unroll
-      for (int q = 0; q < 2; ++q) j[q] = pop_candidate(u, wq * 32);
+        for (int q = 0; q < 2; ++q) j[q] = pop_candidate(u, wq * 32);
 #pragma unroll
-      for (int q = 0; q < 2; ++q) o[q] = X[__umul24(max(j[q], 0), Ts) + kq];
+        for (int q = 0; q < 2; ++q) {
+          const float2* xj = X + __umul24(max(j[q], 0), Ts) + k0;
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const float dx = p.x - o[q].x;
-        const float dy = p.y - o[q].y;
-        const float d2 = fmaf(dy, dy, dx * dx);
-        if (j[q] >= 0 && d2 < a2) {
-          float rx, ry;
-          pair_residual(dx, dy, d2, a, i < j[q], rx, ry);
-          vx += rx;
-          vy += ry;
-          if (j[q] > i) s1 = fmaf(rx, rx, fmaf(ry, ry, s1));
+          for (int e = 0; e < E; ++e) o[q][e] = xj[e];
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            const float dx = p[e].x - o[q][e].x;
+            const float dy = p[e].y - o[q][e].y;
+            const float d2 = fmaf(dy, dy, dx * dx);
+            if (j[q] >= 0 && d2 < a2) {
+              float rx, ry;
+              pair_residual(dx, dy, d2, a, i < j[q], rx, ry);
+              vx[e] += rx;
+              vy[e] += ry;
+              if (j[q] > i && k0 + e < Tce) s1 = fmaf(rx, rx, fmaf(ry, ry, s1));
+            }
+          }
         }
       }
-    }
     }
     for (int wd = 0; wd < ((M + 31) >> 5); ++wd) {
       unsigned u = live ? mw[(mpw + wd) * mrow + i] : 0u;
@@ -441,30 +466,34 @@ __device__ __forceinline__ void constraints_window(
         for (int q = 0; q < 2; ++q) ob[q] = obs[max(mq[q], 0)];
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-          const float dx = p.x - ob[q].x;
-          const float dy = p.y - ob[q].y;
-          const float d2 = fmaf(dy, dy, dx * dx);
-          if (mq[q] >= 0 && d2 < ob[q].w) {
-            float rx, ry;
-            pair_residual(dx, dy, d2, ob[q].z, true, rx, ry);
-            vx += rx;
-            vy += ry;
-            s1 = fmaf(rx, rx, fmaf(ry, ry, s1));
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            const float dx = p[e].x - ob[q].x;
+            const float dy = p[e].y - ob[q].y;
+            const float d2 = fmaf(dy, dy, dx * dx);
+            if (mq[q] >= 0 && d2 < ob[q].w) {
+              float rx, ry;
+              pair_residual(dx, dy, d2, ob[q].z, true, rx, ry);
+              vx[e] += rx;
+              vy[e] += ry;
+              if (k0 + e < Tce) s1 = fmaf(rx, rx, fmaf(ry, ry, s1));
+            }
           }
         }
       }
     }
-    const float hx = fmaxf(p.x - pmax0, 0.f), lx = fmaxf(pmin0 - p.x, 0.f);
-    const float hy = fmaxf(p.y - pmax1, 0.f), ly = fmaxf(pmin1 - p.y, 0.f);
-    vx = fmaf(w_box, hx - lx, w_pair * vx);
-    vy = fmaf(w_box, hy - ly, w_pair * vy);
-    if (live && kk < Tce) {
-      V[__umul24(i, Ts) + kk] = make_float2(vx, vy);
-      if (accum) {
-        r1sq += s1;
-        r2sq += hx * hx + lx * lx + hy * hy + ly * ly;
-      }
+    if (!live) continue;
+    float2* vi = V + __umul24(i, Ts) + k0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if (k0 + e >= Tce) break;
+      const float hx = fmaxf(p[e].x - pmax0, 0.f), lx = fmaxf(pmin0 - p[e].x, 0.f);
+      const float hy = fmaxf(p[e].y - pmax1, 0.f), ly = fmaxf(pmin1 - p[e].y, 0.f);
+      vi[e] = make_float2(fmaf(w_box, hx - lx, w_pair * vx[e]),
+                          fmaf(w_box, hy - ly, w_pair * vy[e]));
+      if (accum) r2sq += hx * hx + lx * lx + hy * hy + ly * ly;
     }
+    if (accum) r1sq += s1;
   }
 }
 
@@ -473,17 +502,13 @@ __device__ __forceinline__ void constraints_window(
 // e of the alpha/d steps is locally constant, so J = I.
 __device__ __forceinline__ void vjp_term(float dx, float dy, float d2, float a, float wx,
                                          float wy, float& hx, float& hy) {
-  if (d2 > 0.f) {
-    const float inv = rsqrtf(d2);
-    const float f = a * inv;
-    const float ux = dx * inv, uy = dy * inv;
-    const float dot = fmaf(ux, wx, uy * wy);
-    hx += fmaf(1.f - f, wx, f * ux * dot);
-    hy += fmaf(1.f - f, wy, f * uy * dot);
-  } else {
-    hx += wx;
-    hy += wy;
-  }
+  const float inv = rsqrt_clamped(d2);
+  const float f = a * inv;
+  const float ux = dx * inv, uy = dy * inv;
+  const float dot = fmaf(ux, wx, uy * wy);
+  const bool tie = !(d2 > 0.f);
+  hx += tie ? wx : fmaf(1.f - f, wx, f * ux * dot);
+  hy += tie ? wy : fmaf(1.f - f, wy, f * uy * dot);
 }
 
 // Vector-Jacobian product of the constraint stage over window w for the robots
@@ -499,37 +524,53 @@ __device__ __forceinline__ void vjp_window(const float2* __restrict__ X,
                                            int mpw, float a, float pmin0, float pmin1,
                                            float pmax0, float pmax1, int w, int Tce, int h, int H,
                                            int lane) {
+  constexpr int E = kStepsPerLane, LPR = 16 / E;
   const float a2 = a * a;
-  const int kk = w * 16 + (lane & 15);
-  const int kq = min(kk, Tce - 1);
+  const int k0 = w * 16 + E * (lane & (LPR - 1));
   const int cnt = part_count(n, h, H);
-  for (int t0 = 0; t0 < cnt; t0 += 4) {
-    const int t = t0 + (lane >> 4);
+  for (int t0 = 0; t0 < cnt; t0 += 64 / LPR) {
+    const int t = t0 + lane / LPR;
     const bool live = t < cnt;
     const int i = part_robot(live ? t : t0, h, H);
-    const float2 p = X[__umul24(i, Ts) + kq];
-    const float2 gi = G[__umul24(i, Ts) + kq];
-    float hx = 0.f, hy = 0.f;
-    for (int wq = 0; wq < ((n + 31) >> 5); ++wq) {
-    unsigned u = live ? mw[wq * mrow + i] : 0u;
-    while (u != 0u) {
-      int j[2];
-      float2 o[2], gj[2];
+    const float2* xi = X + __umul24(i, Ts) + k0;
+    const float2* gip = G + __umul24(i, Ts) + k0;
+    float2 p[E], gi[E];
+    float hx[E], hy[E];
 #pragma unroll
-      for (int q = 0; q < 2; ++q) j[q] = pop_candidate(u, wq * 32);
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        o[q] = X[__umul24(max(j[q], 0), Ts) + kq];
-        gj[q] = G[__umul24(max(j[q], 0), Ts) + kq];
-      }
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const float dx = p.x - o[q].x;
-        const float dy = p.y - o[q].y;
-        const float d2 = fmaf(dy, dy, dx * dx);
-        if (j[q] >= 0 && d2 < a2) vjp_term(dx, dy, d2, a, gi.x - gj[q].x, gi.y - gj[q].y, hx, hy);
-      }
+    for (int e = 0; e < E; ++e) {
+      p[e] = xi[e];
+      gi[e] = gip[e];
+      hx[e] = 0.f;
+      hy[e] = 0.f;
     }
+    for (int wq = 0; wq < ((n + 31) >> 5); ++wq) {
+      unsigned u = live ? mw[wq * mrow + i] : 0u;
+      while (u != 0u) {
+        int j[2];
+        float2 o[2][E], gj[2][E];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) j[q] = pop_candidate(u, wq * 32);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int row = __umul24(max(j[q], 0), Ts) + k0;
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            o[q][e] = X[row + e];
+            gj[q][e] = G[row + e];
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            const float dx = p[e].x - o[q][e].x;
+            const float dy = p[e].y - o[q][e].y;
+            const float d2 = fmaf(dy, dy, dx * dx);
+            if (j[q] >= 0 && d2 < a2)
+              vjp_term(dx, dy, d2, a, gi[e].x - gj[q][e].x, gi[e].y - gj[q][e].y, hx[e], hy[e]);
+          }
+        }
+      }
     }
     for (int wd = 0; wd < ((M + 31) >> 5); ++wd) {
       unsigned u = live ? mw[(mpw + wd) * mrow + i] : 0u;
@@ -542,16 +583,27 @@ __device__ __forceinline__ void vjp_window(const float2* __restrict__ X,
         for (int q = 0; q < 2; ++q) ob[q] = obs[max(mq[q], 0)];
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-          const float dx = p.x - ob[q].x;
-          const float dy = p.y - ob[q].y;
-          const float d2 = fmaf(dy, dy, dx * dx);
-          if (mq[q] >= 0 && d2 < ob[q].w) vjp_term(dx, dy, d2, ob[q].z, gi.x, gi.y, hx, hy);
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            const float dx = p[e].x - ob[q].x;
+            const float dy = p[e].y - ob[q].y;
+            const float d2 = fmaf(dy, dy, dx * dx);
+            if (mq[q] >= 0 && d2 < ob[q].w)
+              vjp_term(dx, dy, d2, ob[q].z, gi[e].x, gi[e].y, hx[e], hy[e]);
+          }
         }
       }
     }
-    if (p.x > pmax0 || p.x < pmin0) hx += gi.x;
-    if (p.y > pmax1 || p.y < pmin1) hy += gi.y;
-    if (live && kk < Tce) Hb[__umul24(i, Ts) + kk] = make_float2(hx, hy);
+    if (!live) continue;
+    float2* hi = Hb + __umul24(i, Ts) + k0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if (k0 + e >= Tce) break;
+      float ox = hx[e], oy = hy[e];
+      if (p[e].x > pmax0 || p[e].x < pmin0) ox += gi[e].x;
+      if (p[e].y > pmax1 || p[e].y < pmin1) oy += gi[e].y;
+      hi[e] = make_float2(ox, oy);
+    }
   }
 }
 
@@ -668,17 +720,16 @@ __device__ __forceinline__ int colsum_slot(const Tile& t, int rt) {
   return ((t.ax * 2 + t.ct) * 4 + rt) * 16;
 }
 
-// accP += Y P^(T) and accD += Y D^(T) for the block (P, D) at fac + fo.
+// B operands of the block (P, D) at fac + fo (transposed with `trans`) for
+// output column cb.  B is read at clamped (finite) entries: A is zero at
+// padded k, and padded output columns are never used.
 template <int KS>
-__device__ __forceinline__ void mode_tile(const float* __restrict__ fac, int nc, int fo,
-                                          bool trans, int cb, const float (&a)[KS],
-                                          floatx4& accP, floatx4& accD, int lane) {
+__device__ __forceinline__ void mode_operands(const float* __restrict__ fac, int nc, int fo,
+                                              bool trans, int cb, float (&bp)[KS],
+                                              float (&bd)[KS], int lane) {
   const int kq = lane >> 4;
   const int nc2 = nc * nc;
   const int cbc = min(cb, nc - 1);
-  // B is read at clamped (finite) entries: A is zero at padded k, and padded
-  // output columns are never used
-  float bp[KS], bd[KS];
 #pragma unroll
   for (int s = 0; s < KS; ++s) {
     const int kc = min(4 * s + kq, nc - 1);
@@ -686,10 +737,46 @@ __device__ __forceinline__ void mode_tile(const float* __restrict__ fac, int nc,
     bp[s] = fac[fo + idx];
     bd[s] = fac[fo + nc2 + idx];
   }
+}
+
+// accP += Y P^(T) and accD += Y D^(T) from the operands of mode_operands.
+template <int KS>
+__device__ __forceinline__ void mode_mfma(const float (&a)[KS], const float (&bp)[KS],
+                                          const float (&bd)[KS], floatx4& accP, floatx4& accD) {
 #pragma unroll
   for (int s = 0; s < KS; ++s) {
     accP = mfma_16x16x4(a[s], bp[s], accP);
     accD = mfma_16x16x4(a[s], bd[s], accD);
+  }
+}
+
+// R entries of a tile's lanes: the per-window partials summed in window order
+// (r = part_0 + part_1 + ...), the reads of up to 8 windows (2 for KS = 8)
+// issued together (reads past the last window are clamped and unused).
+template <int KS>
+__device__ __forceinline__ void window_sum(const float* __restrict__ part, int nwin, int S,
+                                           const int (&sidx)[KS], float (&r)[KS]) {
+  constexpr int G = KS == 4 ? 8 : 2;
+#pragma unroll
+  for (int s = 0; s < KS; ++s) r[s] = 0.f;   // replaced by window 0, not added to
+  for (int w0 = 0; w0 < nwin; w0 += G) {
+    float pv[G][KS];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const float* pw = part + min(w0 + g, nwin - 1) * S;
+#pragma unroll
+      for (int s = 0; s < KS; ++s) pv[g][s] = pw[sidx[s]];
+    }
+    // selects, not branches, so that every read above stays ahead of the adds
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const bool first = w0 + g == 0, live = w0 + g < nwin;
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const float sum = r[s] + pv[g][s];
+        r[s] = first ? pv[g][s] : (live ? sum : r[s]);
+      }
+    }
   }
 }
 
@@ -702,9 +789,15 @@ __device__ __forceinline__ void put_colsum(const floatx4& accD, float* __restric
 }
 __device__ __forceinline__ float get_mean(const float* __restrict__ csum, const Tile& t, int n,
                                           int lane) {
+  // all four row-tile slots are read at once; those past the problem's row
+  // tiles (stale contents) are not added
   const int nrt = (n + 15) >> 4;
+  float v[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) v[r] = csum[colsum_slot(t, r) + (lane & 15)];
   float s = 0.f;
-  for (int r = 0; r < nrt; ++r) s += csum[colsum_slot(t, r) + (lane & 15)];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) s = r < nrt ? s + v[r] : s;
   return s * (1.f / (float)n);
 }
 
@@ -730,17 +823,16 @@ __device__ __forceinline__ void update_fwd_p1(const float* __restrict__ fac, int
     if (!mode_tile_of(wave + q * (NT >> 6), n, nc, t)) continue;
     const int i = t.rt * 16 + m;
     const int ic = min(i, n - 1);
+    const int cb = t.ct * 16 + m;
+    // every read of the tile is issued before its arithmetic
+    float bS[KS], dS[KS], bH[KS], dH[KS];
+    mode_operands<KS>(fac, nc, 0, false, cb, bS, dS, lane);
+    mode_operands<KS>(fac, nc, 2 * nc * nc, false, cb, bH, dH, lane);
     int sidx[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) sidx[s] = __umul24(t.ax * n + ic, nc) + min(4 * s + kq, nc - 1);
     float r[KS];
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      sidx[s] = __umul24(t.ax * n + ic, nc) + min(4 * s + kq, nc - 1);
-      r[s] = part[sidx[s]];
-    }
-    for (int w = 1; w < nwin; ++w) {
-#pragma unroll
-      for (int s = 0; s < KS; ++s) r[s] += part[w * S + sidx[s]];
-    }
+    window_sum<KS>(part, nwin, S, sidx, r);
     float au[KS], axb[KS];
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
@@ -754,7 +846,6 @@ __device__ __forceinline__ void update_fwd_p1(const float* __restrict__ fac, int
         if (last) dzsq = fmaf(rho * r[s], rho * r[s], dzsq);
       }
     }
-    const int cb = t.ct * 16 + m;
     // rows past n and columns past nc of the tile are never stored: their
     // accumulators may start from any finite value
 #pragma unroll
@@ -763,8 +854,8 @@ __device__ __forceinline__ void update_fwd_p1(const float* __restrict__ fac, int
       accP[q][v] = cx[__umul24(t.ax * n + min(io, n - 1), nc) + min(cb, nc - 1)];
     }
     floatx4 accD = {0.f, 0.f, 0.f, 0.f};
-    mode_tile<KS>(fac, nc, 0, false, cb, au, accP[q], accD, lane);
-    mode_tile<KS>(fac, nc, 2 * nc * nc, false, cb, axb, accP[q], accD, lane);
+    mode_mfma<KS>(au, bS, dS, accP[q], accD);
+    mode_mfma<KS>(axb, bH, dH, accP[q], accD);
     put_colsum(accD, csum, t, lane);
   }
 }
@@ -861,14 +952,7 @@ __device__ __forceinline__ void constraints_full(
       const float d2 = fmaf(dy, dy, dx * dx);
       if (d2 < a2 && j != i) {
         float rx, ry;
-        if (d2 > 0.f) {
-          const float f = 1.f - a * rsqrtf(d2);
-          rx = f * dx;
-          ry = f * dy;
-        } else {
-          rx = (i < j) ? -a : a;
-          ry = 0.f;
-        }
+        pair_residual(dx, dy, d2, a, i < j, rx, ry);
         vx += rx;
         vy += ry;
         if (j > i) s1 = fmaf(rx, rx, fmaf(ry, ry, s1));
@@ -881,14 +965,7 @@ __device__ __forceinline__ void constraints_full(
       const float d2 = fmaf(dy, dy, dx * dx);
       if (d2 < ao * ao) {
         float rx, ry;
-        if (d2 > 0.f) {
-          const float f = 1.f - ao * rsqrtf(d2);
-          rx = f * dx;
-          ry = f * dy;
-        } else {
-          rx = -ao;
-          ry = 0.f;
-        }
+        pair_residual(dx, dy, d2, ao, true, rx, ry);
         vx += rx;
         vy += ry;
         s1 = fmaf(rx, rx, fmaf(ry, ry, s1));
@@ -1355,6 +1432,11 @@ __device__ __forceinline__ void update_bwd_p1(const float* __restrict__ fac, int
     if (!mode_tile_of(wave + q * (NT >> 6), n, nc, t)) continue;
     const int i = t.rt * 16 + m;
     const int ic = min(i, n - 1);
+    const int cb = t.ct * 16 + m;
+    // every read of the tile is issued before its arithmetic
+    float bU[KS], dU_[KS], bN[KS], dN_[KS];
+    mode_operands<KS>(fac, nc, 0, true, cb, bU, dU_, lane);
+    mode_operands<KS>(fac, nc, 2 * nc * nc, true, cb, bN, dN_, lane);
     int sidx[KS];
     float g[KS];
 #pragma unroll
@@ -1364,12 +1446,7 @@ __device__ __forceinline__ void update_bwd_p1(const float* __restrict__ fac, int
     }
     if (part) {
       float r[KS];
-#pragma unroll
-      for (int s = 0; s < KS; ++s) r[s] = part[sidx[s]];
-      for (int w = 1; w < nwin; ++w) {
-#pragma unroll
-        for (int s = 0; s < KS; ++s) r[s] += part[w * S + sidx[s]];
-      }
+      window_sum<KS>(part, nwin, S, sidx, r);
 #pragma unroll
       for (int s = 0; s < KS; ++s) g[s] += r[s];
     }
@@ -1382,7 +1459,6 @@ __device__ __forceinline__ void update_bwd_p1(const float* __restrict__ fac, int
       const bool ok = i < n && 4 * s + kq < nc;
       g[s] = ok ? g[s] : 0.f;
     }
-    const int cb = t.ct * 16 + m;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int io = t.rt * 16 + 4 * kq + v;
@@ -1395,8 +1471,8 @@ __device__ __forceinline__ void update_bwd_p1(const float* __restrict__ fac, int
       accN[q][v] = f0;
     }
     floatx4 dU = {0.f, 0.f, 0.f, 0.f}, dN = {0.f, 0.f, 0.f, 0.f};
-    mode_tile<KS>(fac, nc, 0, true, cb, g, accU[q], dU, lane);
-    mode_tile<KS>(fac, nc, 2 * nc * nc, true, cb, g, accN[q], dN, lane);
+    mode_mfma<KS>(g, bU, dU_, accU[q], dU);
+    mode_mfma<KS>(g, bN, dN_, accN[q], dN);
     put_colsum(dU, csU, t, lane);
     put_colsum(dN, csN, t, lane);
   }
