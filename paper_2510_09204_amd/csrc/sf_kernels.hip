@@ -546,28 +546,37 @@ __device__ __forceinline__ void vjp_window(const float2* __restrict__ X,
     for (int wq = 0; wq < ((n + 31) >> 5); ++wq) {
       unsigned u = live ? mw[wq * mrow + i] : 0u;
       while (u != 0u) {
-        int j[2];
-        float2 o[2][E], gj[2][E];
+        int j[2], row[2];
+        float2 o[2][E];
 #pragma unroll
         for (int q = 0; q < 2; ++q) j[q] = pop_candidate(u, wq * 32);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-          const int row = __umul24(max(j[q], 0), Ts) + k0;
+          row[q] = __umul24(max(j[q], 0), Ts) + k0;
 #pragma unroll
-          for (int e = 0; e < E; ++e) {
-            o[q][e] = X[row + e];
-            gj[q][e] = G[row + e];
-          }
+          for (int e = 0; e < E; ++e) o[q][e] = X[row[q] + e];
         }
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
+          float dx[E], dy[E], d2[E];
+          bool act[E], any = false;
 #pragma unroll
           for (int e = 0; e < E; ++e) {
-            const float dx = p[e].x - o[q][e].x;
-            const float dy = p[e].y - o[q][e].y;
-            const float d2 = fmaf(dy, dy, dx * dx);
-            if (j[q] >= 0 && d2 < a2)
-              vjp_term(dx, dy, d2, a, gi[e].x - gj[q][e].x, gi[e].y - gj[q][e].y, hx[e], hy[e]);
+            dx[e] = p[e].x - o[q][e].x;
+            dy[e] = p[e].y - o[q][e].y;
+            d2[e] = fmaf(dy[e], dy[e], dx[e] * dx[e]);
+            act[e] = j[q] >= 0 && d2[e] < a2;
+            any |= act[e];
+          }
+          // the candidate's cotangents are read only when one of its tests
+          // is active
+          if (any) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+              const float2 gj = G[row[q] + e];
+              if (act[e])
+                vjp_term(dx[e], dy[e], d2[e], a, gi[e].x - gj.x, gi[e].y - gj.y, hx[e], hy[e]);
+            }
           }
         }
       }
@@ -751,12 +760,11 @@ __device__ __forceinline__ void mode_mfma(const float (&a)[KS], const float (&bp
 }
 
 // R entries of a tile's lanes: the per-window partials summed in window order
-// (r = part_0 + part_1 + ...), the reads of up to 8 windows (2 for KS = 8)
-// issued together (reads past the last window are clamped and unused).
-template <int KS>
+// (r = part_0 + part_1 + ...), the reads of G windows issued together (reads
+// past the last window are clamped and unused).
+template <int KS, int G>
 __device__ __forceinline__ void window_sum(const float* __restrict__ part, int nwin, int S,
                                            const int (&sidx)[KS], float (&r)[KS]) {
-  constexpr int G = KS == 4 ? 8 : 2;
 #pragma unroll
   for (int s = 0; s < KS; ++s) r[s] = 0.f;   // replaced by window 0, not added to
   for (int w0 = 0; w0 < nwin; w0 += G) {
@@ -832,7 +840,7 @@ __device__ __forceinline__ void update_fwd_p1(const float* __restrict__ fac, int
 #pragma unroll
     for (int s = 0; s < KS; ++s) sidx[s] = __umul24(t.ax * n + ic, nc) + min(4 * s + kq, nc - 1);
     float r[KS];
-    window_sum<KS>(part, nwin, S, sidx, r);
+    window_sum<KS, KS == 4 ? 8 : 2>(part, nwin, S, sidx, r);
     float au[KS], axb[KS];
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
@@ -1446,7 +1454,7 @@ __device__ __forceinline__ void update_bwd_p1(const float* __restrict__ fac, int
     }
     if (part) {
       float r[KS];
-      window_sum<KS>(part, nwin, S, sidx, r);
+      window_sum<KS, KS == 4 ? 4 : 2>(part, nwin, S, sidx, r);
 #pragma unroll
       for (int s = 0; s < KS; ++s) g[s] += r[s];
     }
@@ -1620,27 +1628,31 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
   const int nseg = (L_ + k - 1) / k;
   float dz = 0.f;
   bool pending = false;   // L.part holds W^T VJP partials not yet added to gx
+  // positions of the current reverse step (xbl) and a staging buffer (xalt)
+  // for the next one, read ahead from global memory while this step's update
+  // runs whenever that iterate needs no recompute
+  float* xbl = L.b0;
+  float* xalt = L.b1;
+  bool staged = false;
   floatx4 accU[tiles_per_wave(NT)], accN[tiles_per_wave(NT)];
   for (int seg = nseg - 1; seg >= 0; --seg) {
     const int l0 = seg * k;
     const int l1 = min(L_, l0 + k);
-    // recompute iterates l0 .. l1-1 into the segment scratch
-    {
+    // the segment's first iterate is its checkpoint; recompute iterates
+    // l0+1 .. l1-1 into the segment scratch (slot l - l0)
+    const float* ck = A.ckpt + (size_t)seg * 2 * St + P.coef_off;
+    if (l1 - 1 > l0) {
       float* xr = L.b0;
       float* xq = L.b1;
       float* lr = L.b2;
       float* lq = L.b3;
-      const float* ck = A.ckpt + (size_t)seg * 2 * St + P.coef_off;
-      float* sg = A.seg + P.coef_off;
+      staged = false;
       for (int s = tid; s < S; s += NT) {
-        const float x = ck[s], lm = ck[St + s];
-        xr[s] = x;
-        lr[s] = lm;
-        sg[s] = x;
-        sg[St + s] = lm;
+        xr[s] = ck[s];
+        lr[s] = ck[St + s];
       }
       if (!C.chunked) check_lists<NT>(xr, L.refc, S, C.skin, L.lslot, tid);
-      if (pending && l1 - 1 > l0) {
+      if (pending) {
         // the recompute reuses the partial buffer: fold it into gx first
         add_partials(gx, L.part, nwin0, S, tid, NT);
         pending = false;
@@ -1663,14 +1675,24 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
       __syncthreads();
     }
     for (int l = l1 - 1; l >= l0; --l) {
-      const float* cur = A.seg + (size_t)(l - l0) * 2 * St + P.coef_off;
+      const float* cur = l == l0 ? ck : A.seg + (size_t)(l - l0) * 2 * St + P.coef_off;
       const float* nxt = (l + 1 < l1) ? A.seg + (size_t)(l + 1 - l0) * 2 * St + P.coef_off
                          : (l1 == L_) ? A.fin + P.coef_off
                                       : A.ckpt + (size_t)(seg + 1) * 2 * St + P.coef_off;
-      float* xbl = L.b0;
       float* gR = L.b2;
-      for (int s = tid; s < S; s += NT) xbl[s] = cur[s];
+      if (!staged)
+        for (int s = tid; s < S; s += NT) xbl[s] = cur[s];
+      staged = false;
       if (!C.chunked) check_lists<NT>(xbl, L.refc, S, C.skin, L.lslot, tid);
+      const float* ahead = l > l0                ? (l - 1 == l0 ? ck : cur - 2 * St)
+                           : (k == 1 && seg > 0) ? ck - 2 * St
+                                                 : nullptr;
+      const bool read_ahead = ahead != nullptr && S <= 2 * NT;
+      float pv0 = 0.f, pv1 = 0.f;
+      if (read_ahead) {
+        if (tid < S) pv0 = ahead[tid];
+        if (tid + NT < S) pv1 = ahead[tid + NT];
+      }
       int lane = lane_here(tid);
       update_bwd_p1<NT, KS>(L.fac, nc, n, gx, pending ? L.part : nullptr, nwin0, S, cur, nxt, fw,
                             L.csum, L.csum + kColSums, accU, accN, wave, lane);
@@ -1680,10 +1702,20 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
       update_bwd_p2<NT>(nc, n, L.csum, L.csum + kColSums, accU, accN, rho, fw, cur, nxt, St,
                         L.glam, L.gxi, gR, gn, wave, lane);
       __syncthreads();
+      if (read_ahead) {
+        if (tid < S) xalt[tid] = pv0;
+        if (tid + NT < S) xalt[tid + NT] = pv1;
+      }
       for (int k0 = 0, ch = 0; k0 < T; k0 += Tc, ++ch) {
         const int Tce = min(Tc, T - k0);
         C.wchunk<NT>(k0, Tce);
         adjoint_units<NT, KS>(C, ch, Tce, xbl, gR, L.X, L.G, L.H, L.part, k0 > 0);
+      }
+      if (read_ahead) {
+        float* t = xbl;
+        xbl = xalt;
+        xalt = t;
+        staged = true;
       }
       pending = true;
       float* t = gx;
