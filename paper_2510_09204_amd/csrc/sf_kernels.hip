@@ -19,26 +19,28 @@
 // F^T F + G^T G = ((n + M + 2) I - 1 1^T) (x) W^T W: a problem's operator is
 // P_perp Y_i + (P_par - P_perp) mean_i(Y) per axis with nc x nc matrices.
 //
-// Work decomposition.  Time is cut into windows of 16 steps.  A wave owns a
-// (window, robot part) unit and runs it end to end without block barriers:
-// the coefficient->time map of the window for all robots on MFMA (16x16x4 FP32
-// tiles; the per-window bounding box of every robot falls out of the tile),
-// candidate masks for its robots (a pair or obstacle is a candidate when the
-// boxes come within the constraint distance plus a rounding margin; lane j
-// tests robot j and a ballot forms the mask), the exact pair/obstacle/box
-// stage over candidates (four lanes of four steps per robot, each robot
-// walking its own list), and
-// the window's share of the time->coefficient map R = W^T V on MFMA into a
-// per-window partial.  Skipped pairs are inactive at every step of the window
-// and contribute exactly 0.  The partials are summed in window order, so every
-// launch shape gives the same bits.
+// Work decomposition.  Time is cut into windows of 16 steps.  A map phase
+// computes the coefficient->time map of every window on MFMA (16x16x4 FP32
+// tiles, one (window, column tile) job per wave in turn; on a list rebuild the
+// per-window bounding box of every robot falls out of the tile).  After a
+// block barrier, a wave owns a (window, robot part) unit and runs it end to
+// end: candidate masks for its robots on a rebuild (a pair or obstacle is a
+// candidate when the boxes come within the constraint distance plus a
+// rounding margin; lane j tests robot j and a ballot forms the mask), the
+// exact pair/obstacle/box stage over candidates (four lanes of four steps per
+// robot, each robot walking its own list), and the window's share of the
+// time->coefficient map R = W^T V on MFMA into a per-window partial.  Skipped
+// pairs are inactive at every step of the window and contribute exactly 0.
+// The partials are summed in window order, so every launch shape gives the
+// same bits.
 //
 // The coefficient update is a set of MFMA tiles (axis x 16 robots x 16
 // coefficients), one per wave: the wave forms its A operand u = lambda -
 // 2 rho R straight from the partials, multiplies by the mode blocks, and gets
 // the robot-mean term as column sums of a second accumulator (lane swaps),
-// exchanged between row tiles through LDS.  Three block barriers per
-// iteration: after the window units, after the column sums, after the update.
+// exchanged between row tiles through LDS.  Four block barriers per
+// iteration: after the map phase, after the window units, after the column
+// sums, after the update.
 //
 // Data layout: coefficient arrays [axis][robot][coef]; positions and
 // constraint sums [robot][time] as float2 (x, y) with an odd row stride
@@ -277,6 +279,69 @@ __device__ __forceinline__ void xmap_window(const float* __restrict__ W, int nc,
           *reinterpret_cast<float2*>(box + (__umul24(i, nws) + w) * 4 + 2 * ax) =
               make_float2(lo, hi);
       }
+    }
+  }
+}
+
+// One job of the fused kernels' map phase: column tile nt (8 robots x 2 axes)
+// of window w, X[i][16w + r].axis = sum_c W[16w + r][c] xb[axis][i][c], the
+// padding rows stored too (rows have room for them); with BOX the tile's
+// window boxes go to box[i nws + w].  Same MFMA chain, hence the same bits, as
+// the tile in xmap_window.
+template <int KS, bool BOX>
+__device__ __forceinline__ void xmap_tile(const float* __restrict__ W, int nc,
+                                          const float* __restrict__ xb, int n,
+                                          float* __restrict__ Xf, int Ts, int w, int nt, int Tce,
+                                          float* __restrict__ box, int nws, int lane) {
+  const int m = lane & 15, kq = lane >> 4;
+  const int row = min(w * 16 + m, Tce - 1);
+  const int col = nt * 16 + m;
+  const int i = min(col >> 1, n - 1), ax = col & 1;
+  const float* brow = xb + __umul24(ax * n + i, nc);
+  float av[KS], bv[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    const int c = 4 * s + kq;
+    const float v = W[__umul24(row, nc) + min(c, nc - 1)];
+    av[s] = c < nc ? v : 0.f;
+    bv[s] = brow[min(c, nc - 1)];
+  }
+  floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int s = 0; s < KS; ++s) acc = mfma_16x16x4(av[s], bv[s], acc);
+  const bool colok = (col >> 1) < n;
+  if (colok) {
+    float* xr = Xf + (__umul24(i, Ts) + w * 16 + 4 * kq) * 2 + ax;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) xr[2 * v] = acc[v];
+  }
+  if (BOX) {
+    float lo = min_sel(min_sel(acc[0], acc[1]), min_sel(acc[2], acc[3]));
+    float hi = max_sel(max_sel(acc[0], acc[1]), max_sel(acc[2], acc[3]));
+    lo = rows_reduce(lo, OpMin());
+    hi = rows_reduce(hi, OpMax());
+    if (lane < 16 && colok)
+      *reinterpret_cast<float2*>(box + (__umul24(i, nws) + w) * 4 + 2 * ax) = make_float2(lo, hi);
+  }
+}
+
+// Map phase of a chunk: the (window, column tile) jobs dealt to the block's
+// waves round-robin, so each window's positions are computed once rather than
+// by every unit of the window.
+template <int NT, int KS, bool BOX>
+__device__ __forceinline__ void map_chunk(const float* __restrict__ W, int nc,
+                                          const float* __restrict__ src, int n,
+                                          float* __restrict__ dst, int Ts, int Tce,
+                                          float* __restrict__ box, int nws, int wave, int lane) {
+  constexpr int nwaves = NT >> 6;
+  const int nwin = nwindows(Tce), ncol = (2 * n + 15) >> 4;
+  int w = wave / ncol, nt = wave - w * ncol;
+  for (; w < nwin;) {
+    xmap_tile<KS, BOX>(W, nc, src, n, dst, Ts, w, nt, Tce, box, nws, lane);
+    nt += nwaves;
+    while (nt >= ncol) {
+      nt -= ncol;
+      ++w;
     }
   }
 }
@@ -1065,20 +1130,21 @@ __device__ __forceinline__ void chunk_units(const Ctx& C, int chunk, int Tce, co
   const int nwin = nwindows(Tce);
   const int H = parts_per_window(C.n, nwin, nwaves);
   const int Ts = C.Ts(), nws = C.nws();
+  if (rebuild)
+    map_chunk<NT, KS, true>(C.W, C.nc, xb, C.n, reinterpret_cast<float*>(X), Ts, Tce, C.box3,
+                            nws, wave, lane);
+  else
+    map_chunk<NT, KS, false>(C.W, C.nc, xb, C.n, reinterpret_cast<float*>(X), Ts, Tce, nullptr,
+                             nws, wave, lane);
+  __syncthreads();
   for (int u = wave; u < nwin * H; u += nwaves) {
     const int w = u / H, h = u - w * H;
     if (rebuild) {
-      xmap_window<KS, true, true>(C.W, C.nc, xb, C.n, reinterpret_cast<float*>(X), Ts, w, Tce,
-                                  C.box3, nws, lane);
-      wave_fence();
       masks_window(reinterpret_cast<const float4*>(C.box3), C.n, C.obox, C.M, C.a, C.skin,
                    C.mwin(w), C.mrow, C.mpw, nws, w, h, H, lane);
       if (w == 0 && !C.chunked) C.set_reference(xb, h, H, lane);
-    } else {
-      xmap_window<KS, false, true>(C.W, C.nc, xb, C.n, reinterpret_cast<float*>(X), Ts, w, Tce,
-                                   nullptr, nws, lane);
+      wave_fence();
     }
-    wave_fence();
     constraints_window(X, V, C.n, Ts, C.obs, C.M, C.mwin(w), C.mrow, C.mpw, C.a,
                        C.pmin0, C.pmin1, C.pmax0, C.pmax1, w, Tce, h, H, accum, r1sq, r2sq,
                        w_pair, w_box, lane);
@@ -1537,22 +1603,23 @@ __device__ __forceinline__ void adjoint_units(const Ctx& C, int chunk, int Tce, 
   const int nwin = nwindows(Tce);
   const int H = parts_per_window(C.n, nwin, nwaves);
   const int Ts = C.Ts(), nws = C.nws();
+  if (rebuild)
+    map_chunk<NT, KS, true>(C.W, C.nc, xb, C.n, reinterpret_cast<float*>(X), Ts, Tce, C.box3,
+                            nws, wave, lane);
+  else
+    map_chunk<NT, KS, false>(C.W, C.nc, xb, C.n, reinterpret_cast<float*>(X), Ts, Tce, nullptr,
+                             nws, wave, lane);
+  map_chunk<NT, KS, false>(C.W, C.nc, gR, C.n, reinterpret_cast<float*>(G), Ts, Tce, nullptr,
+                           nws, wave, lane);
+  __syncthreads();
   for (int u = wave; u < nwin * H; u += nwaves) {
     const int w = u / H, h = u - w * H;
     if (rebuild) {
-      xmap_window<KS, true, true>(C.W, C.nc, xb, C.n, reinterpret_cast<float*>(X), Ts, w, Tce,
-                                  C.box3, nws, lane);
-      wave_fence();
       masks_window(reinterpret_cast<const float4*>(C.box3), C.n, C.obox, C.M, C.a, C.skin,
                    C.mwin(w), C.mrow, C.mpw, nws, w, h, H, lane);
       if (w == 0 && !C.chunked) C.set_reference(xb, h, H, lane);
-    } else {
-      xmap_window<KS, false, true>(C.W, C.nc, xb, C.n, reinterpret_cast<float*>(X), Ts, w, Tce,
-                                   nullptr, nws, lane);
+      wave_fence();
     }
-    xmap_window<KS, false, true>(C.W, C.nc, gR, C.n, reinterpret_cast<float*>(G), Ts, w, Tce,
-                                 nullptr, nws, lane);
-    wave_fence();
     vjp_window(X, G, Hb, C.n, Ts, C.obs, C.M, C.mwin(w), C.mrow, C.mpw, C.a,
                C.pmin0, C.pmin1, C.pmax0, C.pmax1, w, Tce, h, H, lane);
     wave_fence();
