@@ -437,21 +437,23 @@ __device__ __forceinline__ int pop_candidate(unsigned& u, int base) {
 }
 
 // 1/sqrt(d2) by the hardware reciprocal square root (1 ulp) on an input held
-// at or above the smallest normal float, so that no input is flushed; only the
-// coincident case d2 = 0 reaches the clamp, and its result is not used.
+// at or above the smallest normal float (a median-of-three clamp), so that no
+// input is flushed; only the coincident case d2 = 0 reaches the clamp.
 __device__ __forceinline__ float rsqrt_clamped(float d2) {
-  return __builtin_amdgcn_rsqf(fmaxf(d2, 1.17549435e-38f));
+  return __builtin_amdgcn_rsqf(__builtin_amdgcn_fmed3f(d2, 1.17549435e-38f, 3.40282347e+38f));
 }
 
 // Residual vector of a pair at difference (dx, dy) with d2 = |D|^2 < a^2:
 // (1 - a/|D|) D, and (-a, 0) from robot i's side of a coincident pair with
-// i < j (alpha = atan2(0, 0) = 0), (a, 0) from the other side.  Branch-free.
+// i < j (alpha = atan2(0, 0) = 0), (a, 0) from the other side.  Branch-free:
+// at D = 0 the products f D are zero (f is finite there) and the tie adds
+// its (-+a, 0).
 __device__ __forceinline__ void pair_residual(float dx, float dy, float d2, float a, bool lower,
                                               float& rx, float& ry) {
   const float f = fmaf(-a, rsqrt_clamped(d2), 1.f);
-  const bool tie = !(d2 > 0.f);
-  rx = tie ? (lower ? -a : a) : f * dx;
-  ry = tie ? 0.f : f * dy;
+  const float tie = d2 > 0.f ? 0.f : (lower ? -a : a);
+  rx = fmaf(f, dx, tie);
+  ry = f * dy;
 }
 
 // Exact constraint stage of window w for the robots of part h: 16 robots per
@@ -462,15 +464,16 @@ __device__ __forceinline__ void pair_residual(float dx, float dy, float d2, floa
 // obstacles), two per round so their loads overlap; skipped pairs are
 // inactive and would add exactly 0.  Every step's sums are formed in candidate
 // order.  Position rows hold finite values up to the window's last padding
-// step, so the reads need no clamp.  With `accum`, ||r_1||^2 (each unordered
+// step, so the reads need no clamp.  With ACCUM, ||r_1||^2 (each unordered
 // pair once) and ||r_2||^2.
 constexpr int kStepsPerLane = 4;
 
+template <bool ACCUM>
 __device__ __forceinline__ void constraints_window(
     const float2* __restrict__ X, float2* __restrict__ V, int n, int Ts,
     const float4* __restrict__ obs, int M, const unsigned* __restrict__ mw, int mrow, int mpw,
     float a, float pmin0, float pmin1, float pmax0, float pmax1, int w, int Tce, int h, int H,
-    bool accum, float& r1sq, float& r2sq, float w_pair, float w_box, int lane) {
+    float& r1sq, float& r2sq, float w_pair, float w_box, int lane) {
   constexpr int E = kStepsPerLane, LPR = 16 / E;
   const float a2 = a * a;
   const int k0 = w * 16 + E * (lane & (LPR - 1));
@@ -514,7 +517,7 @@ __device__ __forceinline__ void constraints_window(
               pair_residual(dx, dy, d2, a, i < j[q], rx, ry);
               vx[e] += rx;
               vy[e] += ry;
-              if (j[q] > i && k0 + e < Tce) s1 = fmaf(rx, rx, fmaf(ry, ry, s1));
+              if (ACCUM && j[q] > i && k0 + e < Tce) s1 = fmaf(rx, rx, fmaf(ry, ry, s1));
             }
           }
         }
@@ -541,7 +544,7 @@ __device__ __forceinline__ void constraints_window(
               pair_residual(dx, dy, d2, ob[q].z, true, rx, ry);
               vx[e] += rx;
               vy[e] += ry;
-              if (k0 + e < Tce) s1 = fmaf(rx, rx, fmaf(ry, ry, s1));
+              if (ACCUM && k0 + e < Tce) s1 = fmaf(rx, rx, fmaf(ry, ry, s1));
             }
           }
         }
@@ -556,9 +559,9 @@ __device__ __forceinline__ void constraints_window(
       const float hy = fmaxf(p[e].y - pmax1, 0.f), ly = fmaxf(pmin1 - p[e].y, 0.f);
       vi[e] = make_float2(fmaf(w_box, hx - lx, w_pair * vx[e]),
                           fmaf(w_box, hy - ly, w_pair * vy[e]));
-      if (accum) r2sq += hx * hx + lx * lx + hy * hy + ly * ly;
+      if (ACCUM) r2sq += hx * hx + lx * lx + hy * hy + ly * ly;
     }
-    if (accum) r1sq += s1;
+    if (ACCUM) r1sq += s1;
   }
 }
 
@@ -1145,9 +1148,14 @@ __device__ __forceinline__ void chunk_units(const Ctx& C, int chunk, int Tce, co
       if (w == 0 && !C.chunked) C.set_reference(xb, h, H, lane);
       wave_fence();
     }
-    constraints_window(X, V, C.n, Ts, C.obs, C.M, C.mwin(w), C.mrow, C.mpw, C.a,
-                       C.pmin0, C.pmin1, C.pmax0, C.pmax1, w, Tce, h, H, accum, r1sq, r2sq,
-                       w_pair, w_box, lane);
+    if (accum)
+      constraints_window<true>(X, V, C.n, Ts, C.obs, C.M, C.mwin(w), C.mrow, C.mpw, C.a,
+                               C.pmin0, C.pmin1, C.pmax0, C.pmax1, w, Tce, h, H, r1sq, r2sq,
+                               w_pair, w_box, lane);
+    else
+      constraints_window<false>(X, V, C.n, Ts, C.obs, C.M, C.mwin(w), C.mrow, C.mpw, C.a,
+                                C.pmin0, C.pmin1, C.pmax0, C.pmax1, w, Tce, h, H, r1sq, r2sq,
+                                w_pair, w_box, lane);
     if (part) {
       wave_fence();
       wtmap_window<KS>(C.W, C.nc, reinterpret_cast<const float*>(V), C.n, Ts, w, Tce, h, H,
