@@ -568,15 +568,17 @@ __device__ __forceinline__ void constraints_window(
 // Contribution of one active pair or obstacle to the vector-Jacobian product:
 // J(D) w with J(D) = (1 - f) I + f u u^T, f = a/|D|, u = D/|D|; at D = 0 the
 // e of the alpha/d steps is locally constant, so J = I.
+// Branch-free: at D = 0, f is set to 0 (J = I) and u = 0; a zero w adds
+// exactly nothing, which is how inactive tests are masked.
 __device__ __forceinline__ void vjp_term(float dx, float dy, float d2, float a, float wx,
                                          float wy, float& hx, float& hy) {
   const float inv = rsqrt_clamped(d2);
-  const float f = a * inv;
+  const float f = d2 > 0.f ? a * inv : 0.f;
   const float ux = dx * inv, uy = dy * inv;
-  const float dot = fmaf(ux, wx, uy * wy);
-  const bool tie = !(d2 > 0.f);
-  hx += tie ? wx : fmaf(1.f - f, wx, f * ux * dot);
-  hy += tie ? wy : fmaf(1.f - f, wy, f * uy * dot);
+  const float c = f * fmaf(ux, wx, uy * wy);
+  const float omf = 1.f - f;
+  hx = fmaf(c, ux, fmaf(omf, wx, hx));
+  hy = fmaf(c, uy, fmaf(omf, wy, hy));
 }
 
 // Vector-Jacobian product of the constraint stage over window w for the robots
@@ -637,13 +639,17 @@ __device__ __forceinline__ void vjp_window(const float2* __restrict__ X,
             any |= act[e];
           }
           // the candidate's cotangents are read only when one of its tests
-          // is active
+          // is active; then all four steps are formed, inactive ones with a
+          // zero cotangent
           if (any) {
+            float2 gj[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) gj[e] = G[row[q] + e];
 #pragma unroll
             for (int e = 0; e < E; ++e) {
-              const float2 gj = G[row[q] + e];
-              if (act[e])
-                vjp_term(dx[e], dy[e], d2[e], a, gi[e].x - gj.x, gi[e].y - gj.y, hx[e], hy[e]);
+              const float wx = act[e] ? gi[e].x - gj[e].x : 0.f;
+              const float wy = act[e] ? gi[e].y - gj[e].y : 0.f;
+              vjp_term(dx[e], dy[e], d2[e], a, wx, wy, hx[e], hy[e]);
             }
           }
         }
