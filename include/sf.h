@@ -187,6 +187,57 @@ int sf_set_early_exit(sf_plan_t* plan, float tol, int32_t check_every);
 int sf_project_iterations(const sf_plan_t* plan, const void* workspace, int32_t* iters,
                           void* stream);
 
+/*
+ * Candidate selection around the SF (the planning pipeline of the paper's
+ * "Validation and Benchmarking" section: its three-stage figure and
+ * "Qualitative Validation").  Sampled candidate trajectories of one context
+ * are ranked by their primal residual (eq. primal_residual), the k best are
+ * refined by sf_project, and the refined candidate returned is the feasible
+ * one with the least smoothness cost.  A candidate's residual row is the
+ * [4]-row of sf_project (n_iters = 0 gives the residual of the warm start, i.e.
+ * of the raw sample when xi0 = xi); its ranking key is ||r_1||^2 + ||r_2||^2
+ * in float32 with each operation rounded separately, +inf when the status word
+ * is set or the key is not finite.  Ties go to the lower index.
+ */
+
+/*
+ * Smoothness cost of each problem's trajectory xi (the plan's coefficient
+ * layout): (1/n) sum_i sum_k |d^2 p_i/dt^2 (t_k)|^2, the squared acceleration
+ * norm summed over the T time steps and averaged over the robots ("Smoothness
+ * Cost" of "Implementation Details"), with t = tau t_final.  cost: device
+ * float[B].  t_final > 0 (seconds).  Asynchronous on stream.
+ */
+int sf_smoothness(const sf_plan_t* plan, const void* workspace, const float* xi,
+                  float t_final, float* cost, void* stream);
+
+/*
+ * Indices of the k candidates with the smallest ranking keys, in increasing
+ * key order (ties: lower index first).  residual: device float[n][4];
+ * idx: device int32[k].  1 <= k <= n <= 8192.  Asynchronous on stream.
+ */
+int sf_rank_residual(const float* residual, int32_t n_candidates, int32_t k, int32_t* idx,
+                     void* stream);
+
+/*
+ * Index of the chosen candidate: among those whose key is <= tol^2 (tol^2
+ * rounded in float32; "feasible") the least cost, ties by key then index;
+ * when none is feasible, the least key, ties by index.  A non-finite cost
+ * counts as +inf.  residual: device float[n][4]; cost: device float[n];
+ * idx: device int32[1].  1 <= n <= 8192, tol >= 0.  Asynchronous on stream.
+ */
+int sf_select_best(const float* residual, const float* cost, int32_t n_candidates, float tol,
+                   int32_t* idx, void* stream);
+
+/*
+ * Gather of equal-size blocks (e.g. the coefficient blocks of candidates that
+ * share n): dst[q] = src[idx[q]] for q < k, blocks of block_floats floats.
+ * src: device float[n_blocks][block_floats]; idx: device int32[k]; dst:
+ * device float[k][block_floats].  An index outside 0..n_blocks-1 yields a
+ * block of NaN.  k <= 65535.  Asynchronous on stream.
+ */
+int sf_gather_blocks(const float* src, int32_t n_blocks, const int32_t* idx, int32_t k,
+                     int32_t block_floats, float* dst, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -27,7 +27,8 @@ _ERRORS = {0: "SF_OK", -1: "SF_ERR_INVALID_ARG", -2: "SF_ERR_SHAPE",
 
 EXPORTED = ("sf_setup", "sf_project", "sf_project_backward", "sf_destroy",
             "sf_error_string", "sf_last_error_detail", "sf_plan_threads", "sf_set_early_exit",
-            "sf_project_iterations")
+            "sf_project_iterations", "sf_smoothness", "sf_rank_residual", "sf_select_best",
+            "sf_gather_blocks")
 
 
 class SFError(RuntimeError):
@@ -79,6 +80,14 @@ def load_library(path: Optional[Path] = None) -> ctypes.CDLL:
     lib.sf_set_early_exit.restype = ctypes.c_int
     lib.sf_project_iterations.argtypes = [vp, vp, vp, vp]
     lib.sf_project_iterations.restype = ctypes.c_int
+    lib.sf_smoothness.argtypes = [vp, vp, f32p, ctypes.c_float, f32p, vp]
+    lib.sf_smoothness.restype = ctypes.c_int
+    lib.sf_rank_residual.argtypes = [f32p, i32, i32, vp, vp]
+    lib.sf_rank_residual.restype = ctypes.c_int
+    lib.sf_select_best.argtypes = [f32p, f32p, i32, ctypes.c_float, vp, vp]
+    lib.sf_select_best.restype = ctypes.c_int
+    lib.sf_gather_blocks.argtypes = [f32p, i32, vp, i32, i32, f32p, vp]
+    lib.sf_gather_blocks.restype = ctypes.c_int
     if path is None:
         _lib = lib
     return lib
@@ -155,6 +164,16 @@ class SFPlan:
             self._plan, ctypes.c_void_p(self.workspace.data_ptr()), out.data_ptr(),
             self._stream()))
         return out
+
+    def smoothness(self, xi: torch.Tensor, t_final: float) -> torch.Tensor:
+        """sf_smoothness: squared acceleration norm summed over the time steps
+        and averaged over the robots, per problem; float32[B] on the device."""
+        self._coef(xi, "xi")
+        cost = torch.empty(self.B, dtype=torch.float32, device=self.device)
+        _check(self.lib, self.lib.sf_smoothness(
+            self._plan, ctypes.c_void_p(self.workspace.data_ptr()), xi.data_ptr(),
+            float(t_final), cost.data_ptr(), self._stream()))
+        return cost
 
     def close(self) -> None:
         if getattr(self, "_plan", None):
@@ -250,6 +269,102 @@ class SFProject(torch.autograd.Function):
                               None if g_lam_out is None else g_lam_out.contiguous(),
                               g_res, ctx.fp_weight, need=tuple(bool(x) for x in need))
         return g[0], g[1], g[2], None, None, None, None, None
+
+
+def _device_f32(t: torch.Tensor, name: str, numel: int) -> torch.Tensor:
+    if t.dtype != torch.float32 or not t.is_contiguous() or t.device.type != "cuda" \
+            or t.numel() != numel:
+        raise SFError(-2, f"{name} must be a contiguous float32 device tensor of {numel} "
+                          "elements")
+    return t
+
+
+def rank_residual(residual: torch.Tensor, k: int) -> torch.Tensor:
+    """sf_rank_residual: indices (int32[k], device) of the k candidates with the
+    least ||r_1||^2 + ||r_2||^2, in increasing order, ties by index."""
+    lib = load_library()
+    n = residual.shape[0]
+    _device_f32(residual, "residual", 4 * n)
+    idx = torch.empty(int(k), dtype=torch.int32, device=residual.device)
+    _check(lib, lib.sf_rank_residual(residual.data_ptr(), int(n), int(k), idx.data_ptr(),
+                                     ctypes.c_void_p(torch.cuda.current_stream(
+                                         residual.device).cuda_stream)))
+    return idx
+
+
+def select_best(residual: torch.Tensor, cost: torch.Tensor, tol: float) -> torch.Tensor:
+    """sf_select_best: int32[1] on the device, the feasible candidate (key <=
+    tol^2) of least cost, else the least residual."""
+    lib = load_library()
+    n = residual.shape[0]
+    _device_f32(residual, "residual", 4 * n)
+    _device_f32(cost, "cost", n)
+    idx = torch.empty(1, dtype=torch.int32, device=residual.device)
+    _check(lib, lib.sf_select_best(residual.data_ptr(), cost.data_ptr(), int(n), float(tol),
+                                   idx.data_ptr(), ctypes.c_void_p(torch.cuda.current_stream(
+                                       residual.device).cuda_stream)))
+    return idx
+
+
+def gather_blocks(src: torch.Tensor, idx: torch.Tensor, block_floats: int) -> torch.Tensor:
+    """sf_gather_blocks: dst[q] = src[idx[q]] for blocks of block_floats floats."""
+    lib = load_library()
+    if src.numel() % int(block_floats):
+        raise SFError(-2, "src is not a whole number of blocks")
+    n_blocks = src.numel() // int(block_floats)
+    _device_f32(src, "src", src.numel())
+    if idx.dtype != torch.int32 or not idx.is_contiguous() or idx.device != src.device:
+        raise SFError(-1, "idx must be a contiguous int32 tensor on the device of src")
+    k = idx.numel()
+    dst = torch.empty(k * int(block_floats), dtype=torch.float32, device=src.device)
+    _check(lib, lib.sf_gather_blocks(src.data_ptr(), int(n_blocks), idx.data_ptr(), int(k),
+                                     int(block_floats), dst.data_ptr(),
+                                     ctypes.c_void_p(torch.cuda.current_stream(
+                                         src.device).cuda_stream)))
+    return dst
+
+
+def select_candidates(xi: torch.Tensor, n: int, M: int, robot_a: float, box, boundary,
+                      obstacles, n_coef: int, n_steps: int, rho: float, k: int, n_iters: int,
+                      tol: float, t_final: float, threads: int = 0, plans=None):
+    """The planning pipeline around the SF for candidates of one context:
+    xi holds n_cand candidates ([n_cand][2][n][n_coef], float32, device);
+    boundary [n][2][2] and obstacles [M][3] are the context's.  Ranks the raw
+    samples by residual, refines the k best with n_iters SF iterations
+    (warm start xi_bar^0 = xi, lambda^0 = 0) and picks the feasible refined
+    candidate (residual <= tol) of least smoothness cost (t_final seconds).
+    Returns a dict of device tensors: raw residual rows, top-k indices, the
+    refined trajectories, their residuals and costs, and `best` (an index into
+    the top-k list), plus the two plans, which a later call with the same
+    shapes may pass back as `plans` to skip their setup."""
+    S = 2 * int(n) * int(n_coef)
+    nc_all = xi.numel() // S
+    dev = xi.device
+    bnd, obs = boundary.reshape(1, -1), None if M == 0 else obstacles.reshape(1, -1)
+
+    def plan_for(count, max_iters):
+        return SFPlan([n] * count, [M] * count, [robot_a] * count,
+                      np.tile(np.asarray(box, np.float32).reshape(1, 2, 2), (count, 1, 1)),
+                      n_coef, n_steps, rho, max_iters=max_iters, threads=threads, device=dev)
+
+    def ctx_rows(count):
+        b = bnd.expand(count, -1).contiguous().reshape(-1)
+        o = None if obs is None else obs.expand(count, -1).contiguous().reshape(-1)
+        return b, o
+
+    plan_raw, plan_k = plans if plans is not None else (plan_for(nc_all, 0),
+                                                        plan_for(int(k), n_iters))
+    b_all, o_all = ctx_rows(nc_all)
+    zeros = torch.zeros_like(xi)
+    _, _, res_raw = plan_raw.project(xi, xi, zeros, b_all, o_all, 0)
+    top = rank_residual(res_raw, k)
+    xi_k = gather_blocks(xi, top, S)
+    b_k, o_k = ctx_rows(int(k))
+    xo, lo, res_k = plan_k.project(xi_k, xi_k, torch.zeros_like(xi_k), b_k, o_k, n_iters)
+    cost = plan_k.smoothness(xo, t_final)
+    best = select_best(res_k, cost, tol)
+    return dict(residual_raw=res_raw, topk=top, xi_refined=xo, lam_refined=lo,
+                residual_refined=res_k, cost=cost, best=best, plans=(plan_raw, plan_k))
 
 
 def to_device(packed, device="cuda"):

@@ -64,6 +64,22 @@ std::vector<double> bernstein(int nc, int T) {
   return W;
 }
 
+// Second derivative in tau of the Bernstein basis, [T][nc]: for degree N,
+// B''_{c,N} = N (N - 1) (B_{c-2,N-2} - 2 B_{c-1,N-2} + B_{c,N-2}) (terms with
+// an index outside 0..N-2 vanish); all zero for N < 2.
+std::vector<double> bernstein_dd(int nc, int T) {
+  std::vector<double> D((size_t)T * nc, 0.0);
+  const int N = nc - 1;
+  if (N < 2) return D;
+  const std::vector<double> low = bernstein(N - 1, T);  // degree N - 2: N - 1 functions
+  for (int k = 0; k < T; ++k)
+    for (int c = 0; c < nc; ++c) {
+      auto b = [&](int j) { return (j < 0 || j > N - 2) ? 0.0 : low[(size_t)k * (N - 1) + j]; };
+      D[(size_t)k * nc + c] = (double)N * (N - 1) * (b(c - 2) - 2.0 * b(c - 1) + b(c));
+    }
+  return D;
+}
+
 // In-place Gauss-Jordan inverse with partial pivoting; false if singular.
 bool invert(std::vector<double>& A, int m) {
   std::vector<double> I((size_t)m * m, 0.0);
@@ -173,7 +189,7 @@ struct sf_plan {
   int B = 0;
   std::vector<sf::ProbDesc> desc;
   std::vector<int32_t> order;
-  std::vector<float> W, fac;
+  std::vector<float> W, Wdd, fac;
   int nfac = 0;
   int n_max = 0, M_max = 0, S_max = 0;
   int64_t S_total = 0, pos_total = 0, obs_total = 0, rob_total = 0;
@@ -185,7 +201,7 @@ struct sf_plan {
   int Tc_fwd = 0, Tc_bwd = 0;
   size_t lds_fwd = 0, lds_bwd = 0;
   // workspace layout (byte offsets)
-  size_t off_desc = 0, off_order = 0, off_W = 0, off_fac = 0, off_cxi = 0,
+  size_t off_desc = 0, off_order = 0, off_W = 0, off_Wdd = 0, off_fac = 0, off_cxi = 0,
          off_obs = 0, off_ckpt = 0, off_final = 0, off_seg = 0, off_X = 0, off_V = 0,
          off_R = 0, off_xb0 = 0, off_xb1 = 0, off_lam = 0, off_pcxi = 0, off_red = 0, off_part = 0,
          off_iters = 0, total = 0;
@@ -242,6 +258,9 @@ int build_plan(const sf_config_t* cfg, int B, const int32_t* n_robots, const int
   const std::vector<double> W = bernstein(nc, T);
   p->W.resize((size_t)T * nc);
   for (size_t q = 0; q < p->W.size(); ++q) p->W[q] = (float)W[q];
+  const std::vector<double> Wdd = bernstein_dd(nc, T);
+  p->Wdd.resize(Wdd.size());
+  for (size_t q = 0; q < Wdd.size(); ++q) p->Wdd[q] = (float)Wdd[q];
   std::map<std::pair<int, int>, int> fac_index;
   const int fs = sf::fac_stride(nc);
   int64_t coef = 0, rob = 0, obs = 0, pos = 0;
@@ -347,6 +366,7 @@ int build_plan(const sf_config_t* cfg, int B, const int32_t* n_robots, const int
   p->off_desc = take(sizeof(sf::ProbDesc) * B);
   p->off_order = take(sizeof(int32_t) * B);
   p->off_W = take(F * T * nc);
+  p->off_Wdd = take(F * T * nc);
   p->off_fac = take(F * p->fac.size());
   p->off_cxi = take(F * coef);
   p->off_obs = take(F * 3 * obs);
@@ -550,6 +570,8 @@ int sf_setup(const sf_config_t* cfg, int32_t n_problems, const int32_t* n_robots
   SF_HIP_CHECK(hipMemcpyAsync(p->ws + p->off_order, p->order.data(), sizeof(int32_t) * p->B,
                               hipMemcpyHostToDevice, s));
   SF_HIP_CHECK(hipMemcpyAsync(p->ws + p->off_W, p->W.data(), sizeof(float) * p->W.size(),
+                              hipMemcpyHostToDevice, s));
+  SF_HIP_CHECK(hipMemcpyAsync(p->ws + p->off_Wdd, p->Wdd.data(), sizeof(float) * p->Wdd.size(),
                               hipMemcpyHostToDevice, s));
   SF_HIP_CHECK(hipMemcpyAsync(p->ws + p->off_fac, p->fac.data(), sizeof(float) * p->fac.size(),
                               hipMemcpyHostToDevice, s));
@@ -764,6 +786,59 @@ int sf_project_iterations(const sf_plan_t* plan, const void* workspace, int32_t*
   hipStream_t s = static_cast<hipStream_t>(stream);
   SF_HIP_CHECK(hipMemcpyAsync(iters, plan->ws + plan->off_iters, sizeof(int32_t) * plan->B,
                               hipMemcpyDeviceToDevice, s));
+  return SF_OK;
+}
+
+int sf_smoothness(const sf_plan_t* plan, const void* workspace, const float* xi,
+                  float t_final, float* cost, void* stream) {
+  g_detail.clear();
+  if (!plan) return fail(SF_ERR_INVALID_ARG, "plan is NULL");
+  if (workspace != plan->ws)
+    return fail(SF_ERR_INVALID_ARG, "workspace differs from the one bound at sf_setup");
+  if (!xi || !cost) return fail(SF_ERR_INVALID_ARG, "xi or cost is NULL");
+  if (!(t_final > 0.f) || !std::isfinite(t_final))
+    return fail(SF_ERR_INVALID_ARG, "t_final must be positive and finite");
+  const double tf2 = (double)t_final * (double)t_final;
+  const float inv_tf4 = (float)(1.0 / (tf2 * tf2));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  SF_HIP_CHECK(sf::launch_smoothness(plan->at<sf::ProbDesc>(plan->off_desc), plan->B,
+                                     plan->at<float>(plan->off_Wdd), xi, plan->cfg.n_coef,
+                                     plan->cfg.n_steps, inv_tf4, cost, s));
+  return SF_OK;
+}
+
+int sf_rank_residual(const float* residual, int32_t n_candidates, int32_t k, int32_t* idx,
+                     void* stream) {
+  g_detail.clear();
+  if (!residual || !idx) return fail(SF_ERR_INVALID_ARG, "residual or idx is NULL");
+  if (n_candidates < 1 || n_candidates > sf::kSelectMaxBatch)
+    return fail(SF_ERR_SHAPE, "n_candidates must be in 1.." + std::to_string(sf::kSelectMaxBatch));
+  if (k < 1 || k > n_candidates) return fail(SF_ERR_INVALID_ARG, "k must be in 1..n_candidates");
+  SF_HIP_CHECK(sf::launch_topk(residual, n_candidates, k, idx, static_cast<hipStream_t>(stream)));
+  return SF_OK;
+}
+
+int sf_select_best(const float* residual, const float* cost, int32_t n_candidates, float tol,
+                   int32_t* idx, void* stream) {
+  g_detail.clear();
+  if (!residual || !cost || !idx) return fail(SF_ERR_INVALID_ARG, "residual, cost or idx is NULL");
+  if (n_candidates < 1 || n_candidates > sf::kSelectMaxBatch)
+    return fail(SF_ERR_SHAPE, "n_candidates must be in 1.." + std::to_string(sf::kSelectMaxBatch));
+  if (!(tol >= 0.f) || !std::isfinite(tol))
+    return fail(SF_ERR_INVALID_ARG, "tol must be finite and non-negative");
+  SF_HIP_CHECK(sf::launch_best(residual, cost, n_candidates, tol, idx,
+                               static_cast<hipStream_t>(stream)));
+  return SF_OK;
+}
+
+int sf_gather_blocks(const float* src, int32_t n_blocks, const int32_t* idx, int32_t k,
+                     int32_t block_floats, float* dst, void* stream) {
+  g_detail.clear();
+  if (!src || !idx || !dst) return fail(SF_ERR_INVALID_ARG, "src, idx or dst is NULL");
+  if (n_blocks < 1 || k < 1 || block_floats < 1 || k > 65535)
+    return fail(SF_ERR_INVALID_ARG, "n_blocks, k and block_floats must be positive (k <= 65535)");
+  SF_HIP_CHECK(sf::launch_gather(src, idx, k, block_floats, n_blocks, dst,
+                                 static_cast<hipStream_t>(stream)));
   return SF_OK;
 }
 

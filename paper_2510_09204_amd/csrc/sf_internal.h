@@ -123,4 +123,15 @@ size_t plain_part_floats(int T, int64_t coef);
 // Raise the dynamic-LDS limit of the fused kernels to `lds` bytes.
 hipError_t prepare_kernels(size_t lds);
 
+// Candidate selection (sf_select.hip).  Batches of at most kSelectMaxBatch
+// candidates (the ranking keys live in LDS).
+constexpr int kSelectMaxBatch = 8192;
+hipError_t launch_topk(const float* residual, int B, int k, int32_t* idx, hipStream_t s);
+hipError_t launch_best(const float* residual, const float* cost, int B, float tol, int32_t* idx,
+                       hipStream_t s);
+hipError_t launch_smoothness(const ProbDesc* probs, int B, const float* Wdd, const float* xi,
+                             int nc, int T, float inv_tf4, float* cost, hipStream_t s);
+hipError_t launch_gather(const float* src, const int32_t* idx, int k, int S, int B, float* dst,
+                         hipStream_t s);
+
 }  // namespace sf

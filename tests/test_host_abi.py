@@ -115,6 +115,24 @@ def test_calls_without_plan_fail_cleanly(lib):
     assert lib.sf_plan_threads(None) == 0
     assert lib.sf_set_early_exit(None, 1e-3, 10) == -1
     assert lib.sf_project_iterations(None, None, None, None) == -1
+    assert lib.sf_smoothness(None, None, None, 5.0, None, None) == -1
+
+
+def test_selection_calls_validate_before_launching(lib):
+    """Argument checks of the selection entry points (no pointer is touched
+    and nothing is launched when they fail)."""
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fails its checks
+    assert lib.sf_rank_residual(None, 4, 2, fake, None) == -1
+    assert lib.sf_rank_residual(fake, 0, 1, fake, None) == -2
+    assert lib.sf_rank_residual(fake, 9000, 1, fake, None) == -2
+    assert lib.sf_rank_residual(fake, 4, 5, fake, None) == -1
+    assert lib.sf_rank_residual(fake, 4, 0, fake, None) == -1
+    assert lib.sf_select_best(fake, None, 4, 1e-3, fake, None) == -1
+    assert lib.sf_select_best(fake, fake, 4, -1.0, fake, None) == -1
+    assert lib.sf_select_best(fake, fake, 4, float("nan"), fake, None) == -1
+    assert lib.sf_gather_blocks(fake, 4, None, 2, 8, fake, None) == -1
+    assert lib.sf_gather_blocks(fake, 4, fake, 0, 8, fake, None) == -1
+    assert lib.sf_gather_blocks(fake, 4, fake, 70000, 8, fake, None) == -1
 
 
 def test_error_strings(lib):
