@@ -101,6 +101,8 @@ def test_candidate_pipeline_matches_oracle(gpu):
     top = out["topk"].cpu().numpy()
     # the GPU ranking is exactly the oracle ranking of the GPU's own rows
     np.testing.assert_array_equal(top, o_rank(raw, k))
+    print(f"top-k GPU {list(top)} oracle {list(ref['topk'])}; chosen GPU "
+          f"{int(top[int(out['best'].cpu()[0])])} oracle {int(ref['topk'][ref['best']])}")
     if set(top) != set(ref["topk"]):
         keys = np.hypot(ref["residual_raw"][:, 0], ref["residual_raw"][:, 1])
         edge = np.sort(keys)[k - 1:k + 1]
