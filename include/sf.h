@@ -71,7 +71,23 @@ typedef struct {
   int32_t threads;          /* threads per workgroup for the fused kernels:
                                256, 512 or 1024; 0 = autotuned */
   double rho;               /* augmented-Lagrangian penalty rho > 0 (eq. aug_lag) */
+  int32_t objective;        /* SF_OBJECTIVE_PROJECTION (0) or SF_OBJECTIVE_ACCEL (1) */
 } sf_config_t;
+
+/*
+ * Objectives of the xi_bar step.  PROJECTION is the safety filter: the cost
+ * 1/2 ||xi_bar - xi||^2 of the projection problem (eq. proj_cost), whose
+ * KKT matrix is [I + rho H, A^T; A, 0].  ACCEL replaces the distance to the
+ * sample by the smoothness cost 1/2 sum over robots, axes and time samples of
+ * the squared second derivative in tau (the trajectory optimiser of the paper's
+ * problem formulation, used to build its dataset): the identity block becomes
+ * Q = Wdd^T Wdd per robot and axis, Wdd the second tau-derivative of the
+ * Bernstein basis at the T samples.  The constraints, their updates and the
+ * mode split are unchanged.  With ACCEL the xi argument of sf_project is not
+ * read (it may be NULL) and sf_project_backward returns g_xi = 0.
+ */
+#define SF_OBJECTIVE_PROJECTION 0
+#define SF_OBJECTIVE_ACCEL 1
 
 /*
  * Build a plan for a batch of B problems and report the workspace it needs.

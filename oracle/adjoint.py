@@ -129,7 +129,8 @@ class SFAdjoint:
             g_eta = sol[:Sz]
             # eta = rho F^T e + lambda^{l+1} + xi + rho G^T (h - s)
             g_lam1 = g_l + g_eta
-            g_xi += g_eta
+            if o.objective == "projection":
+                g_xi += g_eta                         # the sample enters eta only there
             g_e = rho * (F @ g_eta)
             g_s = -rho * (G @ g_eta) if o.include_G else np.zeros(G.shape[0])
             # lambda^{l+1} = lambda^l - rho F^T r_1 - rho G^T r_2

@@ -24,6 +24,10 @@ Readings of the paper that this oracle fixes (each is a named choice):
   R15 without an initialisation network xi_bar^0 = xi, lambda^0 = 0.
   R16 tau_k = k/(T-1): both ends of the horizon are sampled.
   R17 boundary rows are positions at k = 0 and k = K only.
+  O1  objective="accel" (the trajectory optimiser of the problem formulation,
+      used for the paper's dataset): the identity block of the KKT matrix
+      becomes Wdd^T Wdd per robot and axis (Wdd the second tau-derivative of
+      the basis) and the sample drops out of eta; everything else is the SF.
 """
 from __future__ import annotations
 
@@ -34,6 +38,8 @@ from typing import List, Optional
 import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
+
+from .basis import accel_basis
 
 N_DIM = 2
 
@@ -108,11 +114,28 @@ def build_operators(n: int, M: int, n_coef: int, n_steps: int) -> Operators:
                      F_r.shape[0], F_o.shape[0])
 
 
-def kkt_matrix(ops: Operators, rho: float, include_G: bool = True) -> np.ndarray:
-    """K = [[I + rho (F^T F + G^T G), A^T], [A, 0]] (R1, R11)."""
+def objective_block(ops: Operators, objective: str) -> np.ndarray:
+    """Quadratic term of the xi_bar step's objective: I for the projection
+    (eq. proj_cost, 1/2 ||xi_bar - xi||^2); for the acceleration objective
+    (the smoothness cost of the trajectory optimiser, 1/2 sum ||Wdd xi_bar||^2
+    per robot and axis, Wdd the second tau-derivative of the basis) the block
+    diagonal of Wdd^T Wdd."""
+    Sz = ops.F.shape[1]
+    if objective == "projection":
+        return np.eye(Sz)
+    if objective == "accel":
+        D = accel_basis(ops.n_coef, ops.n_steps)
+        return np.kron(np.eye(N_DIM * ops.n), D.T @ D)
+    raise ValueError(objective)
+
+
+def kkt_matrix(ops: Operators, rho: float, include_G: bool = True,
+               objective: str = "projection") -> np.ndarray:
+    """K = [[Q + rho (F^T F + G^T G), A^T], [A, 0]] with Q = I for the
+    projection (R1, R11)."""
     Sz = ops.F.shape[1]
     FtF = (ops.F.T @ ops.F).toarray()
-    Q = np.eye(Sz) + rho * FtF
+    Q = objective_block(ops, objective) + rho * FtF
     if include_G:
         Q += rho * (ops.G.T @ ops.G).toarray()
     nA = ops.A.shape[0]
@@ -219,7 +242,8 @@ class SFOracle:
 
     def __init__(self, n: int, M: int, n_coef: int, n_steps: int, rho: float,
                  a: float, box: np.ndarray, obstacles: np.ndarray,
-                 boundary: np.ndarray, include_G: bool = True):
+                 boundary: np.ndarray, include_G: bool = True,
+                 objective: str = "projection"):
         self.ops = build_operators(n, M, n_coef, n_steps)
         self.rho = float(rho)
         self.a = float(a)
@@ -229,7 +253,8 @@ class SFOracle:
         self.h = h_vector(self.ops, self.box)
         self.b = b_vector(np.asarray(boundary, dtype=np.float64))
         self.obs_cen, self.obs_ao = obstacle_rows(self.ops, self.obstacles)
-        self.K = kkt_matrix(self.ops, self.rho, include_G)
+        self.objective = objective
+        self.K = kkt_matrix(self.ops, self.rho, include_G, objective)
         self.K_lu = sla.lu_factor(self.K)            # pre-stored factorisation
         self.Sz = self.ops.F.shape[1]
 
@@ -262,7 +287,9 @@ class SFOracle:
         rho, F, G = self.rho, self.ops.F, self.ops.G
         r1, r2, e, s, _ = self.residual_terms(xib)
         lam_new = lam - rho * (F.T @ r1) - rho * (G.T @ r2)             # lambda_step
-        eta_top = rho * (F.T @ e) + lam_new + xi
+        eta_top = rho * (F.T @ e) + lam_new
+        if self.objective == "projection":
+            eta_top = eta_top + xi                                       # the sample
         if self.include_G:
             eta_top = eta_top + rho * (G.T @ (self.h - s))               # R1
         sol = sla.lu_solve(self.K_lu, np.concatenate([eta_top, self.b]))

@@ -20,6 +20,8 @@ SF_SAVE_FOR_BACKWARD = 1
 SF_PLAIN = 2
 SF_GRAPH = 4
 SF_UNFUSED = 8
+SF_OBJECTIVE_PROJECTION = 0
+SF_OBJECTIVE_ACCEL = 1
 
 _ERRORS = {0: "SF_OK", -1: "SF_ERR_INVALID_ARG", -2: "SF_ERR_SHAPE",
            -3: "SF_ERR_WORKSPACE_SMALL", -4: "SF_ERR_NOT_SAVED", -5: "SF_ERR_HIP",
@@ -42,7 +44,7 @@ class SFConfigC(ctypes.Structure):
     _fields_ = [("n_dim", ctypes.c_int32), ("n_coef", ctypes.c_int32),
                 ("n_steps", ctypes.c_int32), ("checkpoint_every", ctypes.c_int32),
                 ("max_iters", ctypes.c_int32), ("threads", ctypes.c_int32),
-                ("rho", ctypes.c_double)]
+                ("rho", ctypes.c_double), ("objective", ctypes.c_int32)]
 
 
 _lib = None
@@ -116,7 +118,7 @@ class SFPlan:
     def __init__(self, n_robots: Sequence[int], n_obs: Sequence[int],
                  robot_a: Sequence[float], box, n_coef: int, n_steps: int, rho: float,
                  checkpoint_every: int = 1, max_iters: int = 0, threads: int = 0,
-                 device="cuda"):
+                 device="cuda", objective: int = SF_OBJECTIVE_PROJECTION):
         self.lib = load_library()
         dev = torch.device(device)
         if dev.type == "cuda" and dev.index is None:
@@ -128,8 +130,9 @@ class SFPlan:
         self.box = _host(box, np.float32).reshape(-1, 2, 2)
         self.B = int(self.n_robots.size)
         self.n_coef, self.n_steps, self.rho = int(n_coef), int(n_steps), float(rho)
+        self.objective = int(objective)
         self.cfg = SFConfigC(2, self.n_coef, self.n_steps, int(checkpoint_every),
-                             int(max_iters), int(threads), self.rho)
+                             int(max_iters), int(threads), self.rho, self.objective)
         self.coef_size = int(2 * self.n_robots.astype(np.int64).sum() * self.n_coef)
         self.n_rob_total = int(self.n_robots.sum())
         self.n_obs_total = int(self.n_obs.sum())
@@ -199,9 +202,13 @@ class SFPlan:
     def project(self, xi, xi0, lam0, boundary, obstacles, n_iters: int, save: bool = False,
                 plain: bool = False, graph: bool = False, unfused: bool = False,
                 out: Optional[Tuple[torch.Tensor, torch.Tensor, torch.Tensor]] = None):
-        """Run sf_project; returns (xi_out, lam_out, residual[B][4])."""
+        """Run sf_project; returns (xi_out, lam_out, residual[B][4]).  With the
+        acceleration objective xi is not read and may be None."""
+        if xi is None and self.objective != SF_OBJECTIVE_ACCEL:
+            raise SFError(-1, "xi is required by the projection objective")
         for t, name in ((xi, "xi"), (xi0, "xi0"), (lam0, "lam0")):
-            self._coef(t, name)
+            if t is not None:
+                self._coef(t, name)
         if boundary.numel() != self.n_rob_total * 4 or boundary.dtype != torch.float32 \
                 or not boundary.is_contiguous() or boundary.device != self.device:
             raise SFError(-2, "boundary must be contiguous float32 [sum n][2][2] on device")
@@ -211,15 +218,15 @@ class SFPlan:
                     or obstacles.device != self.device:
                 raise SFError(-2, "obstacles must be contiguous float32 [sum M][3] on device")
         if out is None:
-            xi_out = torch.empty_like(xi)
-            lam_out = torch.empty_like(xi)
+            xi_out = torch.empty_like(xi0)
+            lam_out = torch.empty_like(xi0)
             res = torch.empty((self.B, 4), dtype=torch.float32, device=self.device)
         else:
             xi_out, lam_out, res = out
         flags = (SF_SAVE_FOR_BACKWARD if save else 0) | (SF_PLAIN if plain else 0) | \
                 (SF_GRAPH if graph else 0) | (SF_UNFUSED if unfused else 0)
         _check(self.lib, self.lib.sf_project(
-            self._plan, ctypes.c_void_p(self.workspace.data_ptr()), xi.data_ptr(),
+            self._plan, ctypes.c_void_p(self.workspace.data_ptr()), _ptr(xi),
             xi0.data_ptr(), lam0.data_ptr(), boundary.data_ptr(),
             _ptr(obstacles) if self.n_obs_total else None, int(n_iters), flags,
             xi_out.data_ptr(), lam_out.data_ptr(), res.data_ptr(), self._stream()))

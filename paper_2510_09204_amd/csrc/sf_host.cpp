@@ -117,8 +117,10 @@ struct ModeFactors {
   std::vector<double> S, SH, N;  // [nc][nc], [nc][nc], [nc][2]
 };
 
-bool mode_factors(const std::vector<double>& W, int nc, int T, double rho, double c,
-                  ModeFactors& out) {
+// Q0: the objective's block per robot and axis ([nc][nc]; the identity for
+// the projection, Wdd^T Wdd for the acceleration objective).
+bool mode_factors(const std::vector<double>& W, const std::vector<double>& Q0, int nc, int T,
+                  double rho, double c, ModeFactors& out) {
   std::vector<double> WtW((size_t)nc * nc, 0.0);
   for (int p = 0; p < nc; ++p)
     for (int q = 0; q < nc; ++q) {
@@ -129,8 +131,8 @@ bool mode_factors(const std::vector<double>& W, int nc, int T, double rho, doubl
   const int m = nc + 2;
   std::vector<double> K((size_t)m * m, 0.0);
   for (int p = 0; p < nc; ++p) {
-    for (int q = 0; q < nc; ++q) K[(size_t)p * m + q] = rho * c * WtW[(size_t)p * nc + q];
-    K[(size_t)p * m + p] += 1.0;
+    for (int q = 0; q < nc; ++q)
+      K[(size_t)p * m + q] = Q0[(size_t)p * nc + q] + rho * c * WtW[(size_t)p * nc + q];
     K[(size_t)p * m + nc] = W[p];                          // A1 row 0: position at k = 0
     K[(size_t)p * m + nc + 1] = W[(size_t)(T - 1) * nc + p];  // A1 row 1: k = K
     K[(size_t)nc * m + p] = W[p];
@@ -204,7 +206,7 @@ struct sf_plan {
   size_t off_desc = 0, off_order = 0, off_W = 0, off_Wdd = 0, off_fac = 0, off_cxi = 0,
          off_obs = 0, off_ckpt = 0, off_final = 0, off_seg = 0, off_X = 0, off_V = 0,
          off_R = 0, off_xb0 = 0, off_xb1 = 0, off_lam = 0, off_pcxi = 0, off_red = 0, off_part = 0,
-         off_iters = 0, total = 0;
+         off_iters = 0, off_zero = 0, total = 0;
   char* ws = nullptr;
   bool saved = false;
   int saved_L = 0;
@@ -241,6 +243,8 @@ int validate_cfg(const sf_config_t* cfg) {
   if (cfg->threads != 0 && cfg->threads != 256 && cfg->threads != 512 &&
       cfg->threads != 1024)
     return fail(SF_ERR_INVALID_ARG, "threads must be 0, 256, 512 or 1024");
+  if (cfg->objective != SF_OBJECTIVE_PROJECTION && cfg->objective != SF_OBJECTIVE_ACCEL)
+    return fail(SF_ERR_INVALID_ARG, "objective must be SF_OBJECTIVE_PROJECTION or _ACCEL");
   return SF_OK;
 }
 
@@ -261,6 +265,17 @@ int build_plan(const sf_config_t* cfg, int B, const int32_t* n_robots, const int
   const std::vector<double> Wdd = bernstein_dd(nc, T);
   p->Wdd.resize(Wdd.size());
   for (size_t q = 0; q < Wdd.size(); ++q) p->Wdd[q] = (float)Wdd[q];
+  std::vector<double> Q0((size_t)nc * nc, 0.0);
+  if (cfg->objective == SF_OBJECTIVE_ACCEL) {
+    for (int a = 0; a < nc; ++a)
+      for (int c = 0; c < nc; ++c) {
+        double s = 0.0;
+        for (int k = 0; k < T; ++k) s += Wdd[(size_t)k * nc + a] * Wdd[(size_t)k * nc + c];
+        Q0[(size_t)a * nc + c] = s;
+      }
+  } else {
+    for (int a = 0; a < nc; ++a) Q0[(size_t)a * nc + a] = 1.0;
+  }
   std::map<std::pair<int, int>, int> fac_index;
   const int fs = sf::fac_stride(nc);
   int64_t coef = 0, rob = 0, obs = 0, pos = 0;
@@ -285,8 +300,8 @@ int build_plan(const sf_config_t* cfg, int B, const int32_t* n_robots, const int
     int fi;
     if (it == fac_index.end()) {
       ModeFactors perp, par;
-      if (!mode_factors(W, nc, T, cfg->rho, (double)(n + M + 2), perp) ||
-          !mode_factors(W, nc, T, cfg->rho, (double)(M + 2), par))
+      if (!mode_factors(W, Q0, nc, T, cfg->rho, (double)(n + M + 2), perp) ||
+          !mode_factors(W, Q0, nc, T, cfg->rho, (double)(M + 2), par))
         return fail(SF_ERR_SHAPE, "singular KKT matrix");
       fi = p->nfac++;
       fac_index[key] = fi;
@@ -383,6 +398,7 @@ int build_plan(const sf_config_t* cfg, int B, const int32_t* n_robots, const int
   p->off_red = take(F * 4 * B);
   p->off_part = take(F * sf::plain_part_floats(T, coef));
   p->off_iters = take(sizeof(int32_t) * B);
+  p->off_zero = take(F * coef);   // the target read by the acceleration objective
   p->total = off;
   out = std::move(p);
   return SF_OK;
@@ -396,7 +412,8 @@ sf::FwdArgs fwd_args(const sf_plan* p, const float* xi, const float* xi0, const 
   a.order = p->at<int32_t>(p->off_order);
   a.W = p->at<float>(p->off_W);
   a.fac = p->at<float>(p->off_fac);
-  a.xi = xi;
+  // the acceleration objective has no target: its linear term is zero
+  a.xi = p->cfg.objective == SF_OBJECTIVE_ACCEL ? p->at<float>(p->off_zero) : xi;
   a.xi0 = xi0;
   a.lam0 = lam0;
   a.boundary = boundary;
@@ -575,6 +592,8 @@ int sf_setup(const sf_config_t* cfg, int32_t n_problems, const int32_t* n_robots
                               hipMemcpyHostToDevice, s));
   SF_HIP_CHECK(hipMemcpyAsync(p->ws + p->off_fac, p->fac.data(), sizeof(float) * p->fac.size(),
                               hipMemcpyHostToDevice, s));
+  SF_HIP_CHECK(sf::launch_fill(reinterpret_cast<float*>(p->ws + p->off_zero), 0.f,
+                               (int64_t)p->S_total, s));
   SF_HIP_CHECK(hipStreamSynchronize(s));
   *workspace_bytes = p->total;
   *plan = p.release();
@@ -589,7 +608,8 @@ int sf_project(sf_plan_t* plan, void* workspace, const float* xi, const float* x
   if (!plan) return fail(SF_ERR_INVALID_ARG, "plan is NULL");
   if (workspace != plan->ws)
     return fail(SF_ERR_INVALID_ARG, "workspace differs from the one bound at sf_setup");
-  if (!xi || !xi0 || !lam0 || !boundary || !xi_out || !lam_out || !residual)
+  const bool accel = plan->cfg.objective == SF_OBJECTIVE_ACCEL;
+  if ((!xi && !accel) || !xi0 || !lam0 || !boundary || !xi_out || !lam_out || !residual)
     return fail(SF_ERR_INVALID_ARG, "NULL input or output pointer");
   if (plan->obs_total > 0 && !obstacles)
     return fail(SF_ERR_INVALID_ARG, "obstacles is NULL but the plan has obstacles");
@@ -744,6 +764,8 @@ int sf_project_backward(sf_plan_t* plan, void* workspace, const float* g_xi_out,
     plan->tune_bwd = false;
   }
   SF_HIP_CHECK(sf::launch_bwd_fused(a, plan->threads_bwd, plan->lds_bwd, s));
+  if (g_xi && plan->cfg.objective == SF_OBJECTIVE_ACCEL)
+    SF_HIP_CHECK(sf::launch_fill(g_xi, 0.f, plan->S_total, s));   // xi is not an input there
   return SF_OK;
 }
 

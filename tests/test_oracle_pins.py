@@ -376,3 +376,78 @@ def test_pins_catch_a_kkt_without_workspace_terms():
         grads.append((_aug_lagrangian(orc, xib1 + hstep * d, x, e, s, lam1)
                       - _aug_lagrangian(orc, xib1 - hstep * d, x, e, s, lam1)) / (2 * hstep))
     assert max(abs(g) for g in grads) > 1e-3
+
+
+# ------------------------------------- acceleration objective (trajectory optimiser)
+def test_accel_objective_reaches_the_straight_line_without_constraints():
+    """With the smoothness cost, one robot, no obstacles and an inactive box,
+    the xi_bar steps are proximal steps on 1/2 ||Wdd xi_bar||^2 subject to the
+    boundary rows; its unique minimiser is the zero-acceleration trajectory,
+    the straight line between the endpoints."""
+    nc, T = 7, 40
+    starts, goals = np.array([[-1.0, 0.5]]), np.array([[1.5, -0.5]])
+    rng = np.random.default_rng(2)
+    xi0 = straight_coefficients(starts, goals, nc) + 0.3 * rng.standard_normal((2, 1, nc))
+    box = np.array([[-50.0, -50.0], [50.0, 50.0]])
+    bnd = np.stack([starts, goals], axis=1)
+    orc = O.SFOracle(1, 0, nc, T, RHO, 0.4, box, np.zeros((0, 3)), bnd, objective="accel")
+    r = orc.solve(np.zeros_like(xi0), xi0, None, 3000)
+    np.testing.assert_allclose(r.xi_bar, straight_coefficients(starts, goals, nc), atol=1e-8)
+
+
+def test_accel_objective_ignores_the_sample():
+    """The sample xi enters only the projection's cost: with the acceleration
+    objective two different samples give the same iterates."""
+    cfg = scaled(CONFIGS[3], n_robots=(3, 3), n_obs=(2, 2), arena=4.0, n_steps=25)
+    p = make_problem(cfg, 1)
+    orc = O.SFOracle(p.n, p.M, p.n_coef, p.n_steps, RHO, p.a, p.box, p.obstacles, p.boundary,
+                     objective="accel")
+    a = orc.solve(p.xi, p.xi, None, 30).xi_bar
+    b = orc.solve(np.zeros_like(p.xi), p.xi, None, 30).xi_bar
+    np.testing.assert_array_equal(a, b)
+
+
+def test_accel_xi_step_minimises_its_lagrangian_on_the_equality_set():
+    """One xi_bar step with the acceleration objective minimises
+    1/2 xi'^T Q xi' + rho/2 ||F xi' - e||^2 + rho/2 ||G xi' - h + s||^2
+    - lambda'^T xi' ... on {A xi' = b}: the gradient there lies in range(A^T)."""
+    cfg = scaled(CONFIGS[3], n_robots=(3, 3), n_obs=(2, 2), arena=4.0, n_steps=25)
+    p = make_problem(cfg, 2)
+    orc = O.SFOracle(p.n, p.M, p.n_coef, p.n_steps, RHO, p.a, p.box, p.obstacles, p.boundary,
+                     objective="accel")
+    xib = orc.flat(p.xi)
+    lam = 0.1 * np.random.default_rng(4).standard_normal(xib.size)
+    xn, lam_n, _, _ = orc.step(np.zeros_like(xib), xib, lam)
+    r1, r2, e, s, _ = orc.residual_terms(xib)
+    Q = O.objective_block(orc.ops, "accel")
+    F, G = orc.ops.F, orc.ops.G
+    grad = Q @ xn + RHO * (F.T @ (F @ xn - e)) + RHO * (G.T @ (G @ xn - orc.h + s)) - lam_n
+    A = orc.ops.A
+    nu, *_ = np.linalg.lstsq(A.T, grad, rcond=None)
+    assert np.linalg.norm(grad - A.T @ nu) <= 1e-9 * max(1.0, np.linalg.norm(grad))
+    np.testing.assert_allclose(A @ xn, orc.b, atol=1e-10)
+
+
+def test_accel_objective_adjoint_matches_central_finite_differences(fd_case):
+    p, _, rng = fd_case
+    orc = O.SFOracle(p.n, p.M, p.n_coef, p.n_steps, RHO, p.a, p.box, p.obstacles, p.boundary,
+                     objective="accel")
+    L = 12
+    lam0 = 0.05 * rng.standard_normal(p.xi.shape)
+    its = orc.solve(p.xi, p.xi, lam0, L, keep_iterates=True).iterates
+    assert _kink_margin(orc, its) > 1e-4
+    w_xi = rng.standard_normal(p.xi.shape)
+    w_lam = rng.standard_normal(p.xi.shape)
+    g = SFAdjoint(orc).gradient(p.xi, p.xi, lam0, L, w_xi, w_lam)
+    assert np.all(g.g_xi == 0.0)
+    h = 1e-6
+    for which, gv in ((1, g.g_xi0), (2, g.g_lam0)):
+        for _ in range(4):
+            idx = tuple(int(rng.integers(0, s)) for s in p.xi.shape)
+            args = [p.xi.copy(), p.xi.copy(), lam0.copy()]
+            args[which][idx] += h
+            fp = loss_value(orc, *args, L, w_xi, w_lam)
+            args[which][idx] -= 2 * h
+            fm = loss_value(orc, *args, L, w_xi, w_lam)
+            fd = (fp - fm) / (2 * h)
+            assert abs(fd - gv[idx]) <= 1e-6 * max(1.0, abs(fd)), (which, idx, fd, gv[idx])
