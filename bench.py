@@ -170,8 +170,8 @@ def candidate_pipeline_timing(dev, steps=5):
     import torch
 
     from paper_2510_09204_amd import select_candidates
-    from workloads import CONFIGS, make_batch, pack
-    probs = make_batch(CONFIGS[2])
+    from workloads import WORKLOADS, make_batch, pack
+    probs = make_batch(WORKLOADS[2])
     p0, pk = probs[0], pack(probs)
     xi = torch.from_numpy(pk.xi).to(dev)
     bnd = torch.from_numpy(pk.boundary[:p0.n * 4].copy()).to(dev)
@@ -191,7 +191,7 @@ def candidate_pipeline_timing(dev, steps=5):
     torch.cuda.synchronize()
     res = out["residual_refined"].cpu().numpy()
     best = int(out["best"].cpu()[0])
-    return dict(workload=f"{CONFIGS[2].name}: 32 candidates -> top {k} -> SF {L} iterations -> "
+    return dict(workload=f"{WORKLOADS[2].name}: 32 candidates -> top {k} -> SF {L} iterations -> "
                          "best by feasibility and smoothness",
                 ms=round(e0.elapsed_time(e1) / steps, 4),
                 chosen=int(out["topk"].cpu()[best]),
@@ -232,9 +232,9 @@ def main(argv=None):
               "them across GPUs without communication.", file=sys.stderr)
         return 2
 
-    from workloads import CONFIGS, make_batch, pack
+    from workloads import WORKLOADS, make_batch, pack
 
-    cfg = CONFIGS[a.config]
+    cfg = WORKLOADS[a.config]
     L = a.iters if a.iters is not None else LSTAR[a.config]
     probs = make_batch(cfg)
     pool = None

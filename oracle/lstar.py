@@ -25,8 +25,8 @@ def _history(args):
     cfg_id, b, rho, cap = args
     os.environ.setdefault("OMP_NUM_THREADS", "1")
     from oracle.sf import SFOracle
-    from workloads import CONFIGS, make_batch
-    cfg = CONFIGS[cfg_id]
+    from workloads import WORKLOADS, make_batch
+    cfg = WORKLOADS[cfg_id]
     p = make_batch(cfg, batch=b + 1)[b]
     orc = SFOracle.for_problem(p, rho)
     res = orc.solve(p.xi, n_iters=cap, keep_history=True)
@@ -36,8 +36,8 @@ def _history(args):
 
 def lstar(cfg_id: int, rho: float, problems: int, cap: int = 2000, tol: float = 1e-3,
           jobs: int = 8):
-    from workloads import CONFIGS
-    cfg = CONFIGS[cfg_id]
+    from workloads import WORKLOADS
+    cfg = WORKLOADS[cfg_id]
     with Pool(jobs) as pool:
         hist = dict(pool.imap_unordered(_history, [(cfg_id, b, rho, cap)
                                                    for b in range(problems)]))
@@ -66,8 +66,8 @@ def main(argv=None):
     ap.add_argument("--jobs", type=int, default=8)
     ap.add_argument("--tol", type=float, default=1e-3)
     a = ap.parse_args(argv)
-    from workloads import CONFIGS
-    n = a.problems or CONFIGS[a.config].batch
+    from workloads import WORKLOADS
+    n = a.problems or WORKLOADS[a.config].batch
     print(json.dumps(lstar(a.config, a.rho, n, a.cap, a.tol, a.jobs)))
 
 

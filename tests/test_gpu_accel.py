@@ -7,7 +7,7 @@ import pytest
 from oracle import SFOracle
 from oracle.adjoint import SFAdjoint
 from sf_testlib import GRAD_REL_TOL, oracle_inputs, rel_err
-from workloads import CONFIGS, make_batch, make_problem, pack, scaled, unpack_coefs
+from workloads import WORKLOADS, make_batch, make_problem, pack, scaled, unpack_coefs
 
 pytestmark = pytest.mark.gpu
 RHO = 0.5
@@ -39,7 +39,7 @@ def _run(problems, L, plain=False):
 
 @pytest.mark.parametrize("cfg_id,batch,L", [(1, None, 100), (3, 3, 60), (4, 4, 40)])
 def test_accel_objective_matches_oracle(gpu, cfg_id, batch, L):
-    probs = make_batch(CONFIGS[cfg_id], batch=batch)
+    probs = make_batch(WORKLOADS[cfg_id], batch=batch)
     pk, xo, lo, res = _run(probs, L)
     inps = oracle_inputs(pk, probs)
     gx, gl = unpack_coefs(xo, probs), unpack_coefs(lo, probs)
@@ -53,7 +53,7 @@ def test_accel_objective_matches_oracle(gpu, cfg_id, batch, L):
 
 
 def test_accel_objective_plain_path_matches_fused_bitwise(gpu):
-    probs = make_batch(CONFIGS[3], batch=3)
+    probs = make_batch(WORKLOADS[3], batch=3)
     _, xf, lf, _ = _run(probs, 30)
     _, xp, lp, _ = _run(probs, 30, plain=True)
     np.testing.assert_array_equal(xp, xf)
@@ -63,7 +63,7 @@ def test_accel_objective_plain_path_matches_fused_bitwise(gpu):
 def test_accel_objective_adjoint_matches_oracle(gpu):
     import torch
     from paper_2510_09204_amd import to_device
-    cfg = scaled(CONFIGS[3], n_robots=(4, 4), n_obs=(3, 3), arena=4.0)
+    cfg = scaled(WORKLOADS[3], n_robots=(4, 4), n_obs=(3, 3), arena=4.0)
     probs = [make_problem(cfg, i) for i in range(2)]
     L = 20
     plan, pk = _plan(probs, L=L)

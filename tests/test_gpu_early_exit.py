@@ -5,7 +5,7 @@ import pytest
 
 from sf_testlib import (GRAD_REL_TOL, REL_TOL, make_plan, oracle_early_exit, oracle_grad,
                         oracle_inputs, oracle_residual_terms, rel_err)
-from workloads import CONFIGS, make_batch, make_problem, scaled, unpack_coefs
+from workloads import WORKLOADS, make_batch, make_problem, scaled, unpack_coefs
 
 pytestmark = pytest.mark.gpu
 RHO = 0.5
@@ -25,7 +25,7 @@ def _forward(probs, L, tol, every, save=False, ckpt=1):
 
 
 def test_early_exit_matches_oracle_rule(gpu):
-    probs = make_batch(CONFIGS[2], batch=6)
+    probs = make_batch(WORKLOADS[2], batch=6)
     L, tol, every = 300, 1e-3, 10
     _, pk, xo, lo, res, its = _forward(probs, L, tol, every)
     inps = oracle_inputs(pk, probs)
@@ -48,7 +48,7 @@ def test_early_exit_matches_oracle_rule(gpu):
 
 
 def test_iterations_without_early_exit_and_switching_off(gpu):
-    probs = make_batch(CONFIGS[2], batch=3)
+    probs = make_batch(WORKLOADS[2], batch=3)
     _, _, _, _, _, its = _forward(probs, 40, 1e-3, 0)
     assert (its == 40).all()
     # a tolerance every iterate meets: each problem runs exactly one iteration
@@ -59,7 +59,7 @@ def test_iterations_without_early_exit_and_switching_off(gpu):
 def test_early_exit_rejected_with_plain_path(gpu):
     import torch
     from paper_2510_09204_amd import SFError, to_device
-    probs = make_batch(CONFIGS[2], batch=2)
+    probs = make_batch(WORKLOADS[2], batch=2)
     plan, pk = make_plan(probs, RHO)
     plan.set_early_exit(1e-3, 5)
     t = to_device(pk)
@@ -72,7 +72,7 @@ def test_early_exit_rejected_with_plain_path(gpu):
 
 def test_adjoint_follows_each_problems_own_chain(gpu):
     import torch
-    cfg = scaled(CONFIGS[3], n_robots=(4, 4), n_obs=(3, 3), arena=4.0)
+    cfg = scaled(WORKLOADS[3], n_robots=(4, 4), n_obs=(3, 3), arena=4.0)
     probs = [make_problem(cfg, i) for i in range(4)]
     L, tol, every = 60, 2e-2, 4
     plan, pk, xo, lo, res, its = _forward(probs, L, tol, every, save=True, ckpt=3)

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 from sf_testlib import GRAD_REL_TOL, make_plan, oracle_grad, oracle_inputs, rel_err
-from workloads import CONFIGS, make_batch, make_problem, pack, scaled, unpack_coefs
+from workloads import WORKLOADS, make_batch, make_problem, pack, scaled, unpack_coefs
 
 pytestmark = pytest.mark.gpu
 RHO = 0.5
@@ -48,7 +48,7 @@ def _check(problems, pk, grads, L, g_xi, g_lam, g_res=None, fp_weight=0.0, idx=N
 
 @pytest.mark.parametrize("L", [20, 100])
 def test_adjoint_four_robot_copy(gpu, L):
-    cfg = scaled(CONFIGS[3], n_robots=(4, 4), n_obs=(3, 3), arena=4.0)
+    cfg = scaled(WORKLOADS[3], n_robots=(4, 4), n_obs=(3, 3), arena=4.0)
     probs = [make_problem(cfg, i) for i in range(3)]
     g_xi, g_lam = _cotangents(probs, 0)
     pk, grads, _ = _run(probs, L, 1, g_xi, g_lam)
@@ -56,7 +56,7 @@ def test_adjoint_four_robot_copy(gpu, L):
 
 
 def test_adjoint_with_residual_and_fixed_point_terms(gpu):
-    cfg = scaled(CONFIGS[3], n_robots=(6, 6), n_obs=(4, 4), arena=4.0)
+    cfg = scaled(WORKLOADS[3], n_robots=(6, 6), n_obs=(4, 4), arena=4.0)
     probs = [make_problem(cfg, i) for i in range(2)]
     g_xi, g_lam = _cotangents(probs, 1)
     g_res = np.array([[0.7, 0.4, 0.0, 0.0], [1.3, 0.0, 0.0, 0.0]])
@@ -65,7 +65,7 @@ def test_adjoint_with_residual_and_fixed_point_terms(gpu):
 
 
 def test_adjoint_c3_problem(gpu):
-    probs = make_batch(CONFIGS[3], batch=2)
+    probs = make_batch(WORKLOADS[3], batch=2)
     g_xi, g_lam = _cotangents(probs, 2)
     pk, grads, _ = _run(probs, 40, 10, g_xi, g_lam)
     _check(probs, pk, grads, 40, g_xi, g_lam)
@@ -73,7 +73,7 @@ def test_adjoint_c3_problem(gpu):
 
 @pytest.mark.parametrize("ckpt", [3, 7, 40])
 def test_checkpoint_interval_does_not_change_gradients(gpu, ckpt):
-    probs = make_batch(CONFIGS[4], batch=4)
+    probs = make_batch(WORKLOADS[4], batch=4)
     g_xi, g_lam = _cotangents(probs, 3)
     g_res = np.tile([[0.5, 0.5, 0.0, 0.0]], (4, 1))
     _, ref, _ = _run(probs, 40, 1, g_xi, g_lam, g_res, fp_weight=0.1)
@@ -84,7 +84,7 @@ def test_checkpoint_interval_does_not_change_gradients(gpu, ckpt):
 
 
 def test_c5_shape_adjoint_with_time_chunks(gpu):
-    probs = make_batch(CONFIGS[5], batch=1)
+    probs = make_batch(WORKLOADS[5], batch=1)
     g_xi, g_lam = _cotangents(probs, 4)
     pk, grads, _ = _run(probs, 12, 5, g_xi, g_lam)
     _check(probs, pk, grads, 12, g_xi, g_lam)
@@ -95,7 +95,7 @@ def test_autograd_function_matches_oracle_loss_gradient(gpu):
     SFProject; gradient w.r.t. the flow sample and the warm start."""
     import torch
     from paper_2510_09204_amd import SFProject, to_device
-    cfg = scaled(CONFIGS[3], n_robots=(4, 4), n_obs=(3, 3), arena=4.0)
+    cfg = scaled(WORKLOADS[3], n_robots=(4, 4), n_obs=(3, 3), arena=4.0)
     probs = [make_problem(cfg, i) for i in range(2)]
     L = 25
     plan, pk = make_plan(probs, RHO, L=L, ckpt=5)
@@ -126,7 +126,7 @@ def test_autograd_function_matches_oracle_loss_gradient(gpu):
 def test_backward_without_saved_forward_is_an_error(gpu):
     import torch
     from paper_2510_09204_amd import SFError, to_device
-    probs = make_batch(CONFIGS[3], batch=1)
+    probs = make_batch(WORKLOADS[3], batch=1)
     plan, pk = make_plan(probs, RHO, L=10)
     t = to_device(pk)
     plan.project(t["xi"], t["xi0"], t["lam0"], t["boundary"], t["obstacles"], 10, save=False)

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from sf_testlib import compare_forward, gpu_forward, make_plan, rel_err
-from workloads import CONFIGS, make_batch, make_problem, pack, scaled, straight_coefficients
+from workloads import WORKLOADS, make_batch, make_problem, pack, scaled, straight_coefficients
 from workloads.gen import Problem
 
 pytestmark = pytest.mark.gpu
@@ -17,19 +17,19 @@ RHO = 0.5
 
 
 def test_c1_single_problem(gpu):
-    probs = make_batch(CONFIGS[1])
+    probs = make_batch(WORKLOADS[1])
     out = gpu_forward(probs, RHO, 100)
     compare_forward(probs, out, RHO, 100)
 
 
 def test_c2_candidates_subset(gpu):
-    probs = make_batch(CONFIGS[2], batch=6)
+    probs = make_batch(WORKLOADS[2], batch=6)
     out = gpu_forward(probs, RHO, 200)
     compare_forward(probs, out, RHO, 200)
 
 
 def test_c3_subset(gpu):
-    probs = make_batch(CONFIGS[3], batch=3)
+    probs = make_batch(WORKLOADS[3], batch=3)
     out = gpu_forward(probs, RHO, 100)
     compare_forward(probs, out, RHO, 100)
 
@@ -37,7 +37,7 @@ def test_c3_subset(gpu):
 def test_converged_candidates_residual_within_1e5(gpu):
     """Candidates run past the point where the oracle's residual is <= 1e-3:
     the GPU residual within 1e-5 (absolute) of the oracle's."""
-    probs = make_batch(CONFIGS[2], batch=4)
+    probs = make_batch(WORKLOADS[2], batch=4)
     out = gpu_forward(probs, RHO, 400)
     errs = compare_forward(probs, out, RHO, 400)
     for e in errs:
@@ -47,7 +47,7 @@ def test_converged_candidates_residual_within_1e5(gpu):
 def test_c3_full_batch_sampled(gpu):
     """All 64 problems in one launch (the benchmark's configuration); sampled
     problems against the oracle, every problem's outputs finite."""
-    probs = make_batch(CONFIGS[3])
+    probs = make_batch(WORKLOADS[3])
     out = gpu_forward(probs, RHO, 100)
     assert np.all(out["res"][:, 3] == 0.0)
     compare_forward(probs, out, RHO, 100, idx=[0, 37, 63])
@@ -60,7 +60,7 @@ def test_c3_benchmark_configuration_full_length(gpu):
     an instance the oracle itself shows to be rounding-decided); every output
     and gradient finite."""
     import torch
-    probs = make_batch(CONFIGS[3])
+    probs = make_batch(WORKLOADS[3])
     L = 2000
     plan, _ = make_plan(probs, RHO, L=L, ckpt=1, threads=0)
     out = gpu_forward(probs, RHO, L, save=True, plan=plan)
@@ -73,7 +73,7 @@ def test_c3_benchmark_configuration_full_length(gpu):
 
 
 def test_c4_uneven_batch_sampled(gpu):
-    probs = make_batch(CONFIGS[4])
+    probs = make_batch(WORKLOADS[4])
     out = gpu_forward(probs, RHO, 150)
     ns = np.array([p.n for p in probs])
     pick = [int(np.argmin(ns)), int(np.argmax(ns)), 5, 17]
@@ -81,13 +81,13 @@ def test_c4_uneven_batch_sampled(gpu):
 
 
 def test_c5_shape_short_run(gpu):
-    probs = make_batch(CONFIGS[5], batch=2)
+    probs = make_batch(WORKLOADS[5], batch=2)
     out = gpu_forward(probs, RHO, 30)
     compare_forward(probs, out, RHO, 30)
 
 
 def test_long_horizon_uses_several_time_chunks(gpu):
-    cfg = scaled(CONFIGS[3], n_robots=(40, 40), n_obs=(6, 6), n_steps=1500, arena=8.0)
+    cfg = scaled(WORKLOADS[3], n_robots=(40, 40), n_obs=(6, 6), n_steps=1500, arena=8.0)
     probs = [make_problem(cfg, 0)]
     plan, _ = make_plan(probs, RHO)
     out = gpu_forward(probs, RHO, 15, plan=plan)
@@ -95,7 +95,7 @@ def test_long_horizon_uses_several_time_chunks(gpu):
 
 
 def test_zero_iterations_returns_warm_start_and_its_residual(gpu):
-    probs = make_batch(CONFIGS[3], batch=2)
+    probs = make_batch(WORKLOADS[3], batch=2)
     out = gpu_forward(probs, RHO, 0)
     pk = out["packed"]
     np.testing.assert_array_equal(out["xi"], pk.xi0)
@@ -104,7 +104,7 @@ def test_zero_iterations_returns_warm_start_and_its_residual(gpu):
 
 
 def test_one_iteration(gpu):
-    probs = make_batch(CONFIGS[3], batch=2)
+    probs = make_batch(WORKLOADS[3], batch=2)
     out = gpu_forward(probs, RHO, 1)
     compare_forward(probs, out, RHO, 1)
 
@@ -161,7 +161,7 @@ def test_edge_box_violations_and_mixed_batch(gpu):
 
 
 def test_plain_path_matches_fused_bitwise(gpu):
-    probs = make_batch(CONFIGS[3], batch=4)
+    probs = make_batch(WORKLOADS[3], batch=4)
     fused = gpu_forward(probs, RHO, 60)
     plain = gpu_forward(probs, RHO, 60, plain=True)
     np.testing.assert_array_equal(plain["xi"], fused["xi"])
@@ -170,7 +170,7 @@ def test_plain_path_matches_fused_bitwise(gpu):
 
 
 def test_batched_unfused_path_matches_fused_bitwise(gpu):
-    probs = make_batch(CONFIGS[4], batch=6)      # uneven sizes in every launch
+    probs = make_batch(WORKLOADS[4], batch=6)      # uneven sizes in every launch
     fused = gpu_forward(probs, RHO, 40)
     unfused = gpu_forward(probs, RHO, 40, unfused=True)
     np.testing.assert_array_equal(unfused["xi"], fused["xi"])
@@ -180,7 +180,7 @@ def test_batched_unfused_path_matches_fused_bitwise(gpu):
 
 @pytest.mark.parametrize("threads", [256, 512, 1024])
 def test_thread_counts_give_identical_coefficients(gpu, threads):
-    probs = make_batch(CONFIGS[4], batch=6)
+    probs = make_batch(WORKLOADS[4], batch=6)
     ref = gpu_forward(probs, RHO, 40, threads=256)
     out = gpu_forward(probs, RHO, 40, threads=threads)
     np.testing.assert_array_equal(out["xi"], ref["xi"])
@@ -189,7 +189,7 @@ def test_thread_counts_give_identical_coefficients(gpu, threads):
 
 
 def test_repeat_is_bitwise_deterministic(gpu):
-    probs = make_batch(CONFIGS[2], batch=8)
+    probs = make_batch(WORKLOADS[2], batch=8)
     a = gpu_forward(probs, RHO, 80)
     b = gpu_forward(probs, RHO, 80)
     np.testing.assert_array_equal(a["xi"], b["xi"])
@@ -198,7 +198,7 @@ def test_repeat_is_bitwise_deterministic(gpu):
 
 def test_graph_replays_match_eager(gpu):
     import torch
-    probs = make_batch(CONFIGS[3], batch=5)
+    probs = make_batch(WORKLOADS[3], batch=5)
     eager = gpu_forward(probs, RHO, 50)
     plan = eager["plan"]
     t = eager["t"]
@@ -223,7 +223,7 @@ def test_resume_equals_one_long_run(gpu):
     """(xi_bar, lambda) is the whole fixed-point state: L1 + L2 iterations in two
     calls equal L1 + L2 in one."""
     import torch
-    probs = make_batch(CONFIGS[3], batch=3)
+    probs = make_batch(WORKLOADS[3], batch=3)
     full = gpu_forward(probs, RHO, 70)
     first = gpu_forward(probs, RHO, 30)
     plan, t = first["plan"], first["t"]
@@ -236,7 +236,7 @@ def test_resume_equals_one_long_run(gpu):
 
 
 def test_nonfinite_input_is_flagged_not_crashed(gpu):
-    probs = make_batch(CONFIGS[3], batch=2)
+    probs = make_batch(WORKLOADS[3], batch=2)
     pk = pack(probs)
     pk.xi0[5] = np.nan
     out = gpu_forward(probs, RHO, 10, packed=pk)

@@ -11,7 +11,7 @@ from oracle.select import select_best as o_best
 from oracle.select import select_candidates as o_select
 from oracle.select import smoothness_cost
 from sf_testlib import make_plan, rel_err
-from workloads import CONFIGS, make_batch, pack, unpack_coefs
+from workloads import WORKLOADS, make_batch, pack, unpack_coefs
 
 pytestmark = pytest.mark.gpu
 RHO = 0.5
@@ -34,7 +34,7 @@ def _f32(problems):
 @pytest.mark.parametrize("cfg_id", [2, 4, 5])
 def test_smoothness_matches_oracle(gpu, cfg_id):
     import torch
-    probs = make_batch(CONFIGS[cfg_id], batch=6)
+    probs = make_batch(WORKLOADS[cfg_id], batch=6)
     plan, pk = make_plan(probs, RHO)
     xi = torch.from_numpy(pk.xi).cuda()
     cost = plan.smoothness(xi, T_FINAL).cpu().numpy()
@@ -85,7 +85,7 @@ def test_candidate_pipeline_matches_oracle(gpu):
     agrees unless the oracle itself sees a near-tie."""
     import torch
     from paper_2510_09204_amd import select_candidates
-    probs = _f32(make_batch(CONFIGS[2]))
+    probs = _f32(make_batch(WORKLOADS[2]))
     k, L, tol = 10, 200, 1e-3
     p0 = probs[0]
     pk = pack(probs)

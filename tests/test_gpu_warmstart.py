@@ -4,7 +4,7 @@ weight, and a short training run lowers the objective."""
 import numpy as np
 import pytest
 
-from workloads import CONFIGS, make_batch, pack, scaled
+from workloads import WORKLOADS, make_batch, pack, scaled
 
 pytestmark = pytest.mark.gpu
 RHO = 0.5
@@ -13,7 +13,7 @@ RHO = 0.5
 def _batch(B=16, L=20):
     import torch
     from paper_2510_09204_amd import SFPlan
-    cfg = scaled(CONFIGS[3], n_robots=(4, 4), n_obs=(3, 3), arena=4.0, n_steps=50)
+    cfg = scaled(WORKLOADS[3], n_robots=(4, 4), n_obs=(3, 3), arena=4.0, n_steps=50)
     probs = make_batch(cfg, batch=B)
     pk = pack(probs)
     n, M, nc = probs[0].n, probs[0].M, probs[0].n_coef

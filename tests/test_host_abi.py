@@ -10,7 +10,7 @@ import pytest
 
 from paper_2510_09204_amd import EXPORTED, load_library
 from paper_2510_09204_amd.binding import SFConfigC
-from workloads import CONFIGS, make_batch, make_problem, pack
+from workloads import WORKLOADS, make_batch, make_problem, pack
 
 ROOT = Path(__file__).resolve().parents[1]
 
@@ -66,7 +66,7 @@ def test_workspace_size_query(lib):
 
 
 def test_workspace_size_for_uneven_batch(lib):
-    probs = make_batch(CONFIGS[4])
+    probs = make_batch(WORKLOADS[4])
     pk = pack(probs)
     rc, nbytes, _ = _setup(lib, _cfg(max_iters=150), pk.n_robots, pk.n_obs, pk.robot_a, pk.box)
     assert rc == 0 and nbytes > 0
@@ -142,7 +142,7 @@ def test_error_strings(lib):
 
 
 def test_generator_is_deterministic_and_well_formed():
-    cfg = CONFIGS[3]
+    cfg = WORKLOADS[3]
     a, b = make_problem(cfg, 5), make_problem(cfg, 5)
     np.testing.assert_array_equal(a.xi, b.xi)
     np.testing.assert_array_equal(a.obstacles, b.obstacles)
@@ -162,7 +162,7 @@ def test_generator_is_deterministic_and_well_formed():
 
 
 def test_candidates_share_their_context():
-    cfg = CONFIGS[2]
+    cfg = WORKLOADS[2]
     ps = make_batch(cfg, batch=3)
     np.testing.assert_array_equal(ps[0].obstacles, ps[2].obstacles)
     np.testing.assert_array_equal(ps[0].boundary, ps[1].boundary)
@@ -170,7 +170,7 @@ def test_candidates_share_their_context():
 
 
 def test_uneven_workload_ranges():
-    ps = make_batch(CONFIGS[4])
+    ps = make_batch(WORKLOADS[4])
     ns = np.array([p.n for p in ps])
     Ms = np.array([p.M for p in ps])
     assert ns.min() >= 8 and ns.max() <= 64 and Ms.min() >= 0 and Ms.max() <= 30

@@ -12,7 +12,7 @@ from scipy.interpolate import BPoly
 
 from oracle import sf as O
 from oracle.adjoint import SFAdjoint, loss_value
-from workloads import CONFIGS, make_problem, scaled, straight_coefficients
+from workloads import WORKLOADS, make_problem, scaled, straight_coefficients
 
 RHO = 0.5
 
@@ -125,7 +125,7 @@ def _aug_lagrangian(orc, xib, xi, e, s, lam):
 
 
 def test_xi_step_minimises_augmented_lagrangian_on_the_equality_set():
-    cfg = scaled(CONFIGS[3], n_robots=(4, 4), n_obs=(3, 3), arena=3.0, n_steps=20)
+    cfg = scaled(WORKLOADS[3], n_robots=(4, 4), n_obs=(3, 3), arena=3.0, n_steps=20)
     p = make_problem(cfg, 3)
     orc = O.SFOracle.for_problem(p, RHO)
     xi = orc.flat(p.xi)
@@ -190,7 +190,7 @@ def _solve(p, L=60, **over):
 
 @pytest.fixture(scope="module")
 def small_problem():
-    cfg = scaled(CONFIGS[3], n_robots=(5, 5), n_obs=(3, 3), arena=3.5, n_steps=30)
+    cfg = scaled(WORKLOADS[3], n_robots=(5, 5), n_obs=(3, 3), arena=3.5, n_steps=30)
     return make_problem(cfg, 1)
 
 
@@ -284,7 +284,7 @@ def test_head_on_residual_has_hand_computable_magnitude():
 # ---------------------------------------------------------------- P10: adjoint
 @pytest.fixture(scope="module")
 def fd_case():
-    cfg = scaled(CONFIGS[3], n_robots=(4, 4), n_obs=(3, 3), arena=4.0, n_steps=30)
+    cfg = scaled(WORKLOADS[3], n_robots=(4, 4), n_obs=(3, 3), arena=4.0, n_steps=30)
     p = make_problem(cfg, 0)
     orc = O.SFOracle.for_problem(p, RHO)
     rng = np.random.default_rng(5)
@@ -398,7 +398,7 @@ def test_accel_objective_reaches_the_straight_line_without_constraints():
 def test_accel_objective_ignores_the_sample():
     """The sample xi enters only the projection's cost: with the acceleration
     objective two different samples give the same iterates."""
-    cfg = scaled(CONFIGS[3], n_robots=(3, 3), n_obs=(2, 2), arena=4.0, n_steps=25)
+    cfg = scaled(WORKLOADS[3], n_robots=(3, 3), n_obs=(2, 2), arena=4.0, n_steps=25)
     p = make_problem(cfg, 1)
     orc = O.SFOracle(p.n, p.M, p.n_coef, p.n_steps, RHO, p.a, p.box, p.obstacles, p.boundary,
                      objective="accel")
@@ -411,7 +411,7 @@ def test_accel_xi_step_minimises_its_lagrangian_on_the_equality_set():
     """One xi_bar step with the acceleration objective minimises
     1/2 xi'^T Q xi' + rho/2 ||F xi' - e||^2 + rho/2 ||G xi' - h + s||^2
     - lambda'^T xi' ... on {A xi' = b}: the gradient there lies in range(A^T)."""
-    cfg = scaled(CONFIGS[3], n_robots=(3, 3), n_obs=(2, 2), arena=4.0, n_steps=25)
+    cfg = scaled(WORKLOADS[3], n_robots=(3, 3), n_obs=(2, 2), arena=4.0, n_steps=25)
     p = make_problem(cfg, 2)
     orc = O.SFOracle(p.n, p.M, p.n_coef, p.n_steps, RHO, p.a, p.box, p.obstacles, p.boundary,
                      objective="accel")

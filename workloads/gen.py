@@ -63,7 +63,7 @@ class SFConfig:
 
 # The five workloads.  Values marked "proposed" are not fixed by the workload
 # statement and were chosen to match its neighbours.
-CONFIGS = {
+WORKLOADS = {
     1: SFConfig(1, "c1_single_4r", (4, 4), (3, 3), 4.0, 0.15, (0.2, 0.4), 11, 50,
                 batch=1, iters=100, sigma=0.3, layout="antipodal", circle_radius=1.5,
                 description="plain SF, one problem: 4 robots swapping antipodal "
