@@ -204,6 +204,21 @@ int sf_project_iterations(const sf_plan_t* plan, const void* workspace, int32_t*
                           void* stream);
 
 /*
+ * Moving obstacles (the dynamic-obstacle scenarios of the paper's evaluation,
+ * where obstacles come with their velocity): obstacle m's centre at
+ * tau = k / (T - 1) is c_m + d_m tau, with d_m the displacement over the
+ * horizon (velocity times its duration).  displacement: device float[sum M][2]
+ * in the obstacles' order, copied into the workspace (asynchronously on
+ * stream); NULL makes every obstacle static again (the default).  It applies
+ * to later sf_project calls and invalidates a saved forward.  The constraint
+ * stage, the candidate lists (per-window obstacle boxes) and the adjoint use
+ * the moving centres; the centres do not depend on xi, so the adjoint gains
+ * no term.
+ */
+int sf_set_obstacle_motion(sf_plan_t* plan, void* workspace, const float* displacement,
+                           void* stream);
+
+/*
  * Candidate selection around the SF (the planning pipeline of the paper's
  * "Validation and Benchmarking" section: its three-stage figure and
  * "Qualitative Validation").  Sampled candidate trajectories of one context

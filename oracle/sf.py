@@ -24,6 +24,8 @@ Readings of the paper that this oracle fixes (each is a named choice):
   R15 without an initialisation network xi_bar^0 = xi, lambda^0 = 0.
   R16 tau_k = k/(T-1): both ends of the horizon are sampled.
   R17 boundary rows are positions at k = 0 and k = K only.
+  D1  moving obstacles: centre c_m + d_m tau_k at time sample k (d_m the
+      displacement over the horizon); F and K are unchanged, only e moves.
   O1  objective="accel" (the trajectory optimiser of the problem formulation,
       used for the paper's dataset): the identity block of the KKT matrix
       becomes Wdd^T Wdd per robot and axis (Wdd the second tau-derivative of
@@ -164,13 +166,18 @@ def b_vector(boundary: np.ndarray) -> np.ndarray:
     return np.concatenate([boundary[:, :, ax].reshape(n * 2) for ax in range(N_DIM)])
 
 
-def obstacle_rows(ops: Operators, obstacles: np.ndarray):
-    """x_o, y_o stacked over (robot, obstacle, time) as F_o's rows, and a_o."""
+def obstacle_rows(ops: Operators, obstacles: np.ndarray, displacement=None):
+    """x_o, y_o stacked over (robot, obstacle, time) as F_o's rows, and a_o.
+    With a displacement d ([M][2]) obstacle m's centre at time sample k is
+    c_m + d_m tau_k (moving obstacles; tau_k = k/(T-1))."""
     n, M, T = ops.n, ops.M, ops.n_steps
     if M == 0:
         z = np.zeros(0)
         return [z, z], z
-    cen = [np.tile(np.repeat(obstacles[:, ax], T), n) for ax in range(N_DIM)]
+    tau = np.arange(T, dtype=np.float64) / (T - 1)
+    d = np.zeros((M, N_DIM)) if displacement is None else np.asarray(displacement, np.float64)
+    cen = [np.tile((obstacles[:, ax][:, None] + d[:, ax][:, None] * tau[None, :]).reshape(-1), n)
+           for ax in range(N_DIM)]
     a_o = np.tile(np.repeat(obstacles[:, 2], T), n)
     return cen, a_o
 
@@ -243,7 +250,7 @@ class SFOracle:
     def __init__(self, n: int, M: int, n_coef: int, n_steps: int, rho: float,
                  a: float, box: np.ndarray, obstacles: np.ndarray,
                  boundary: np.ndarray, include_G: bool = True,
-                 objective: str = "projection"):
+                 objective: str = "projection", obstacle_displacement=None):
         self.ops = build_operators(n, M, n_coef, n_steps)
         self.rho = float(rho)
         self.a = float(a)
@@ -252,7 +259,8 @@ class SFOracle:
         self.include_G = include_G
         self.h = h_vector(self.ops, self.box)
         self.b = b_vector(np.asarray(boundary, dtype=np.float64))
-        self.obs_cen, self.obs_ao = obstacle_rows(self.ops, self.obstacles)
+        self.obs_cen, self.obs_ao = obstacle_rows(self.ops, self.obstacles,
+                                                  obstacle_displacement)
         self.objective = objective
         self.K = kkt_matrix(self.ops, self.rho, include_G, objective)
         self.K_lu = sla.lu_factor(self.K)            # pre-stored factorisation

@@ -30,7 +30,7 @@ _ERRORS = {0: "SF_OK", -1: "SF_ERR_INVALID_ARG", -2: "SF_ERR_SHAPE",
 EXPORTED = ("sf_setup", "sf_project", "sf_project_backward", "sf_destroy",
             "sf_error_string", "sf_last_error_detail", "sf_plan_threads", "sf_set_early_exit",
             "sf_project_iterations", "sf_smoothness", "sf_rank_residual", "sf_select_best",
-            "sf_gather_blocks")
+            "sf_gather_blocks", "sf_set_obstacle_motion")
 
 
 class SFError(RuntimeError):
@@ -82,6 +82,8 @@ def load_library(path: Optional[Path] = None) -> ctypes.CDLL:
     lib.sf_set_early_exit.restype = ctypes.c_int
     lib.sf_project_iterations.argtypes = [vp, vp, vp, vp]
     lib.sf_project_iterations.restype = ctypes.c_int
+    lib.sf_set_obstacle_motion.argtypes = [vp, vp, f32p, vp]
+    lib.sf_set_obstacle_motion.restype = ctypes.c_int
     lib.sf_smoothness.argtypes = [vp, vp, f32p, ctypes.c_float, f32p, vp]
     lib.sf_smoothness.restype = ctypes.c_int
     lib.sf_rank_residual.argtypes = [f32p, i32, i32, vp, vp]
@@ -167,6 +169,19 @@ class SFPlan:
             self._plan, ctypes.c_void_p(self.workspace.data_ptr()), out.data_ptr(),
             self._stream()))
         return out
+
+    def set_obstacle_motion(self, displacement: Optional[torch.Tensor]) -> None:
+        """sf_set_obstacle_motion: obstacle centres move as c + d tau (d:
+        float32 [sum M][2] on the device, the displacement over the horizon);
+        None makes them static again."""
+        if displacement is not None and (displacement.numel() != 2 * self.n_obs_total
+                                         or displacement.dtype != torch.float32
+                                         or not displacement.is_contiguous()
+                                         or displacement.device != self.device):
+            raise SFError(-2, "displacement must be contiguous float32 [sum M][2] on device")
+        _check(self.lib, self.lib.sf_set_obstacle_motion(
+            self._plan, ctypes.c_void_p(self.workspace.data_ptr()), _ptr(displacement),
+            self._stream()))
 
     def smoothness(self, xi: torch.Tensor, t_final: float) -> torch.Tensor:
         """sf_smoothness: squared acceleration norm summed over the time steps

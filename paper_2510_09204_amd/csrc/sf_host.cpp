@@ -206,7 +206,8 @@ struct sf_plan {
   size_t off_desc = 0, off_order = 0, off_W = 0, off_Wdd = 0, off_fac = 0, off_cxi = 0,
          off_obs = 0, off_ckpt = 0, off_final = 0, off_seg = 0, off_X = 0, off_V = 0,
          off_R = 0, off_xb0 = 0, off_xb1 = 0, off_lam = 0, off_pcxi = 0, off_red = 0, off_part = 0,
-         off_iters = 0, off_zero = 0, total = 0;
+         off_iters = 0, off_zero = 0, off_ovel = 0, total = 0;
+  bool moving = false;        // obstacle displacements set (sf_set_obstacle_motion)
   char* ws = nullptr;
   bool saved = false;
   int saved_L = 0;
@@ -399,6 +400,7 @@ int build_plan(const sf_config_t* cfg, int B, const int32_t* n_robots, const int
   p->off_part = take(F * sf::plain_part_floats(T, coef));
   p->off_iters = take(sizeof(int32_t) * B);
   p->off_zero = take(F * coef);   // the target read by the acceleration objective
+  p->off_ovel = take(F * 2 * obs);  // obstacle displacements
   p->total = off;
   out = std::move(p);
   return SF_OK;
@@ -414,6 +416,7 @@ sf::FwdArgs fwd_args(const sf_plan* p, const float* xi, const float* xi0, const 
   a.fac = p->at<float>(p->off_fac);
   // the acceleration objective has no target: its linear term is zero
   a.xi = p->cfg.objective == SF_OBJECTIVE_ACCEL ? p->at<float>(p->off_zero) : xi;
+  a.ovel = p->moving ? p->at<float>(p->off_ovel) : nullptr;
   a.xi0 = xi0;
   a.lam0 = lam0;
   a.boundary = boundary;
@@ -676,7 +679,8 @@ int sf_project(sf_plan_t* plan, void* workspace, const float* xi, const float* x
                                  (uint64_t)boundary, (uint64_t)obstacles, (uint64_t)xi_out,
                                  (uint64_t)lam_out, (uint64_t)residual, (uint64_t)n_iters,
                                  (uint64_t)save,    (uint64_t)plan->threads, (uint64_t)s,
-                                 (uint64_t)plan->exit_every, (uint64_t)float_bits(plan->exit_tol)};
+                                 (uint64_t)plan->exit_every, (uint64_t)float_bits(plan->exit_tol),
+                                 (uint64_t)plan->moving};
     GraphEntry* hit = nullptr;
     for (auto& g : plan->graphs)
       if (g.key == key) hit = &g;
@@ -724,6 +728,7 @@ int sf_project_backward(sf_plan_t* plan, void* workspace, const float* g_xi_out,
   a.fac = plan->at<float>(plan->off_fac);
   a.cxi = plan->at<float>(plan->off_cxi);
   a.obs = plan->at<float>(plan->off_obs);
+  a.ovel = plan->moving ? plan->at<float>(plan->off_ovel) : nullptr;
   a.ckpt = plan->at<float>(plan->off_ckpt);
   a.fin = plan->at<float>(plan->off_final);
   a.seg = plan->at<float>(plan->off_seg);
@@ -808,6 +813,25 @@ int sf_project_iterations(const sf_plan_t* plan, const void* workspace, int32_t*
   hipStream_t s = static_cast<hipStream_t>(stream);
   SF_HIP_CHECK(hipMemcpyAsync(iters, plan->ws + plan->off_iters, sizeof(int32_t) * plan->B,
                               hipMemcpyDeviceToDevice, s));
+  return SF_OK;
+}
+
+int sf_set_obstacle_motion(sf_plan_t* plan, void* workspace, const float* displacement,
+                           void* stream) {
+  g_detail.clear();
+  if (!plan) return fail(SF_ERR_INVALID_ARG, "plan is NULL");
+  if (workspace != plan->ws)
+    return fail(SF_ERR_INVALID_ARG, "workspace differs from the one bound at sf_setup");
+  plan->saved = false;   // a saved forward no longer matches the obstacles
+  if (!displacement) {
+    plan->moving = false;
+    return SF_OK;
+  }
+  if (plan->obs_total > 0)
+    SF_HIP_CHECK(hipMemcpyAsync(plan->ws + plan->off_ovel, displacement,
+                                sizeof(float) * 2 * (size_t)plan->obs_total,
+                                hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)));
+  plan->moving = plan->obs_total > 0;
   return SF_OK;
 }
 

@@ -42,6 +42,7 @@ struct FwdArgs {
   const float* lam0;
   const float* boundary;
   const float* obstacles;
+  const float* ovel;      // obstacle displacements [sum M][2] over the horizon, or null (static)
   float* xi_out;
   float* lam_out;
   float* residual;        // [B][4]
@@ -71,6 +72,7 @@ struct BwdArgs {
   const float* fac;
   const float* cxi;       // saved constant term
   const float* obs;       // saved obstacles
+  const float* ovel;      // obstacle displacements, or null (static)
   const float* ckpt;      // [n_ckpt][2][S_total]
   const float* fin;       // [2][S_total]
   float* seg;             // recompute scratch [ckpt_every][2][S_total]

@@ -468,15 +468,20 @@ __device__ __forceinline__ void pair_residual(float dx, float dy, float d2, floa
 // pair once) and ||r_2||^2.
 constexpr int kStepsPerLane = 4;
 
-template <bool ACCUM>
+template <bool ACCUM, bool MOVING>
 __device__ __forceinline__ void constraints_window(
     const float2* __restrict__ X, float2* __restrict__ V, int n, int Ts,
-    const float4* __restrict__ obs, int M, const unsigned* __restrict__ mw, int mrow, int mpw,
+    const float4* __restrict__ obs, const float2* __restrict__ ovel, int kg, float inv_Tm1,
+    int M, const unsigned* __restrict__ mw, int mrow, int mpw,
     float a, float pmin0, float pmin1, float pmax0, float pmax1, int w, int Tce, int h, int H,
     float& r1sq, float& r2sq, float w_pair, float w_box, int lane) {
   constexpr int E = kStepsPerLane, LPR = 16 / E;
   const float a2 = a * a;
   const int k0 = w * 16 + E * (lane & (LPR - 1));
+  // tau of this lane's steps (global step kg + k0 + e), for moving obstacles
+  float tau[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) tau[e] = MOVING ? (float)(kg + k0 + e) * inv_Tm1 : 0.f;
   const int cnt = part_count(n, h, H);
   for (int t0 = 0; t0 < cnt; t0 += 64 / LPR) {
     const int t = t0 + lane / LPR;
@@ -528,16 +533,22 @@ __device__ __forceinline__ void constraints_window(
       while (u != 0u) {
         int mq[2];
         float4 ob[2];
+        float2 ov[2];
 #pragma unroll
         for (int q = 0; q < 2; ++q) mq[q] = pop_candidate(u, wd * 32);
 #pragma unroll
-        for (int q = 0; q < 2; ++q) ob[q] = obs[max(mq[q], 0)];
+        for (int q = 0; q < 2; ++q) {
+          ob[q] = obs[max(mq[q], 0)];
+          if (MOVING) ov[q] = ovel[max(mq[q], 0)];
+        }
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
 #pragma unroll
           for (int e = 0; e < E; ++e) {
-            const float dx = p[e].x - ob[q].x;
-            const float dy = p[e].y - ob[q].y;
+            const float cx = MOVING ? fmaf(ov[q].x, tau[e], ob[q].x) : ob[q].x;
+            const float cy = MOVING ? fmaf(ov[q].y, tau[e], ob[q].y) : ob[q].y;
+            const float dx = p[e].x - cx;
+            const float dy = p[e].y - cy;
             const float d2 = fmaf(dy, dy, dx * dx);
             if (mq[q] >= 0 && d2 < ob[q].w) {
               float rx, ry;
@@ -587,16 +598,22 @@ __device__ __forceinline__ void vjp_term(float dx, float dy, float d2, float a, 
 //         + box'(X_i) G_i,
 // J the Jacobian of r(D) = D - e(D) on active pairs (|D| < a), 0 otherwise.
 // Same walk over candidates as the constraint stage.
+template <bool MOVING>
 __device__ __forceinline__ void vjp_window(const float2* __restrict__ X,
                                            const float2* __restrict__ G, float2* __restrict__ Hb,
                                            int n, int Ts, const float4* __restrict__ obs,
-                                           int M, const unsigned* __restrict__ mw, int mrow,
+                                           const float2* __restrict__ ovel, int kg,
+                                           float inv_Tm1, int M,
+                                           const unsigned* __restrict__ mw, int mrow,
                                            int mpw, float a, float pmin0, float pmin1,
                                            float pmax0, float pmax1, int w, int Tce, int h, int H,
                                            int lane) {
   constexpr int E = kStepsPerLane, LPR = 16 / E;
   const float a2 = a * a;
   const int k0 = w * 16 + E * (lane & (LPR - 1));
+  float tau[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) tau[e] = MOVING ? (float)(kg + k0 + e) * inv_Tm1 : 0.f;
   const int cnt = part_count(n, h, H);
   for (int t0 = 0; t0 < cnt; t0 += 64 / LPR) {
     const int t = t0 + lane / LPR;
@@ -660,16 +677,22 @@ __device__ __forceinline__ void vjp_window(const float2* __restrict__ X,
       while (u != 0u) {
         int mq[2];
         float4 ob[2];
+        float2 ov[2];
 #pragma unroll
         for (int q = 0; q < 2; ++q) mq[q] = pop_candidate(u, wd * 32);
 #pragma unroll
-        for (int q = 0; q < 2; ++q) ob[q] = obs[max(mq[q], 0)];
+        for (int q = 0; q < 2; ++q) {
+          ob[q] = obs[max(mq[q], 0)];
+          if (MOVING) ov[q] = ovel[max(mq[q], 0)];
+        }
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
 #pragma unroll
           for (int e = 0; e < E; ++e) {
-            const float dx = p[e].x - ob[q].x;
-            const float dy = p[e].y - ob[q].y;
+            const float cx = MOVING ? fmaf(ov[q].x, tau[e], ob[q].x) : ob[q].x;
+            const float cy = MOVING ? fmaf(ov[q].y, tau[e], ob[q].y) : ob[q].y;
+            const float dx = p[e].x - cx;
+            const float dy = p[e].y - cy;
             const float d2 = fmaf(dy, dy, dx * dx);
             if (mq[q] >= 0 && d2 < ob[q].w)
               vjp_term(dx, dy, d2, ob[q].z, gi[e].x, gi[e].y, hx[e], hy[e]);
@@ -1019,8 +1042,10 @@ __device__ __forceinline__ void boundary_means(const float* __restrict__ bnd, in
 // memory, one thread per (robot, step)), in the culled stage's order.
 __device__ __forceinline__ void constraints_full(
     const float2* __restrict__ X, float2* __restrict__ V, int n, int T,
-    const float* __restrict__ obs, int M, float a, float pmin0, float pmin1, float pmax0,
-    float pmax1, bool accum, float& r1sq, float& r2sq, int tid, int nthr) {
+    const float* __restrict__ obs, const float* __restrict__ ovel, int M, float a, float pmin0,
+    float pmin1, float pmax0, float pmax1, bool accum, float& r1sq, float& r2sq, int tid,
+    int nthr) {
+  const float inv_Tm1 = 1.f / (float)(T - 1);
   const float a2 = a * a;
   for (int idx = tid; idx < n * T; idx += nthr) {
     const int i = idx / T;
@@ -1040,8 +1065,11 @@ __device__ __forceinline__ void constraints_full(
         if (j > i) s1 = fmaf(rx, rx, fmaf(ry, ry, s1));
       }
     }
+    const float tau = (float)kk * inv_Tm1;
     for (int m = 0; m < M; ++m) {
-      const float cx = obs[3 * m], cy = obs[3 * m + 1], ao = obs[3 * m + 2];
+      const float ao = obs[3 * m + 2];
+      const float cx = ovel ? fmaf(ovel[2 * m], tau, obs[3 * m]) : obs[3 * m];
+      const float cy = ovel ? fmaf(ovel[2 * m + 1], tau, obs[3 * m + 1]) : obs[3 * m + 1];
       const float dx = p.x - cx;
       const float dy = p.y - cy;
       const float d2 = fmaf(dy, dy, dx * dx);
@@ -1087,8 +1115,8 @@ struct Ctx {
   float rho, a, pmin0, pmin1, pmax0, pmax1;
   float* W;
   const float *fac, *Wg;
-  const float4* obs;    // (cx, cy, a_o, a_o^2)
-  const float4* obox;   // obstacle boxes widened by their margin
+  const float4* obs;    // (cx, cy, a_o, a_o^2) at tau = 0
+  float4* obox;         // obstacle window boxes [window][M_max], widened by their margin
   float* box3;          // window boxes [robot][window] (xmin, xmax, ymin, ymax)
   unsigned* masks;      // [window][word][row]
   float* refc;          // coefficients at the last list rebuild
@@ -1096,6 +1124,10 @@ struct Ctx {
   int mrow, mpw, mstride;
   float skin;
   bool chunked;  // T > Tc: the LDS W table holds one time chunk at a time
+  const float2* ovel;   // obstacle displacement over the horizon (centre at tau: c + d tau)
+  int ostride;          // M_max: window stride of obox
+  float inv_Tm1;        // 1 / (T - 1): tau of global step k is k * inv_Tm1
+  bool moving;          // some obstacle moves (displacements were set)
 
   __device__ __forceinline__ int Ts() const { return tstride(Tc); }
   __device__ __forceinline__ int nws() const { return nwindows(Tc); }
@@ -1125,6 +1157,29 @@ struct Ctx {
   }
 };
 
+// Window boxes of the obstacles for the windows of the chunk that starts at
+// global step kg (Tce steps): a centre moves linearly in tau (c + d tau), so
+// its extent over a window is that of the window's first and last steps (the
+// centres the walks form with the same rounded operations are monotone in
+// the step); widened by the obstacle-side margin.  Static obstacles (d = 0)
+// get the same box in every window.
+__device__ __forceinline__ void obstacle_boxes(const Ctx& C, int kg, int Tce, int tid,
+                                               int nthr) {
+  const int nwin = nwindows(Tce);
+  for (int e = tid; e < nwin * C.M; e += nthr) {
+    const int w = e / C.M, m = e - w * C.M;
+    const float4 o = C.obs[m];
+    const float2 d = C.ovel[m];
+    const float f = obs_margin(o.z);
+    const float t0 = (float)(kg + w * 16) * C.inv_Tm1;
+    const float t1 = (float)(kg + min(w * 16 + 15, Tce - 1)) * C.inv_Tm1;
+    const float x0 = fmaf(d.x, t0, o.x), x1 = fmaf(d.x, t1, o.x);
+    const float y0 = fmaf(d.y, t0, o.y), y1 = fmaf(d.y, t1, o.y);
+    C.obox[w * C.ostride + m] = make_float4(fminf(x0, x1) - f, fmaxf(x0, x1) + f,
+                                            fminf(y0, y1) - f, fmaxf(y0, y1) + f);
+  }
+}
+
 // One chunk of window units: positions, masks and the constraint stage of
 // every window (V = w_pair (pairs + obstacles) + w_box box), and with `part`
 // the windows' shares of W^T V into part[w][S] (added when `accumulate`).
@@ -1139,29 +1194,36 @@ __device__ __forceinline__ void chunk_units(const Ctx& C, int chunk, int Tce, co
   const int nwin = nwindows(Tce);
   const int H = parts_per_window(C.n, nwin, nwaves);
   const int Ts = C.Ts(), nws = C.nws();
-  if (rebuild)
+  const int kg = chunk * C.Tc;   // global step of the chunk's first step
+  if (rebuild) {
+    obstacle_boxes(C, kg, Tce, C.tid, NT);
     map_chunk<NT, KS, true>(C.W, C.nc, xb, C.n, reinterpret_cast<float*>(X), Ts, Tce, C.box3,
                             nws, wave, lane);
-  else
+  } else {
     map_chunk<NT, KS, false>(C.W, C.nc, xb, C.n, reinterpret_cast<float*>(X), Ts, Tce, nullptr,
                              nws, wave, lane);
+  }
   __syncthreads();
   for (int u = wave; u < nwin * H; u += nwaves) {
     const int w = u / H, h = u - w * H;
     if (rebuild) {
-      masks_window(reinterpret_cast<const float4*>(C.box3), C.n, C.obox, C.M, C.a, C.skin,
-                   C.mwin(w), C.mrow, C.mpw, nws, w, h, H, lane);
+      masks_window(reinterpret_cast<const float4*>(C.box3), C.n, C.obox + w * C.ostride, C.M,
+                   C.a, C.skin, C.mwin(w), C.mrow, C.mpw, nws, w, h, H, lane);
       if (w == 0 && !C.chunked) C.set_reference(xb, h, H, lane);
       wave_fence();
     }
-    if (accum)
-      constraints_window<true>(X, V, C.n, Ts, C.obs, C.M, C.mwin(w), C.mrow, C.mpw, C.a,
-                               C.pmin0, C.pmin1, C.pmax0, C.pmax1, w, Tce, h, H, r1sq, r2sq,
-                               w_pair, w_box, lane);
-    else
-      constraints_window<false>(X, V, C.n, Ts, C.obs, C.M, C.mwin(w), C.mrow, C.mpw, C.a,
-                                C.pmin0, C.pmin1, C.pmax0, C.pmax1, w, Tce, h, H, r1sq, r2sq,
-                                w_pair, w_box, lane);
+#define SF_CONSTRAINTS(ACC, MOV)                                                               \
+  constraints_window<ACC, MOV>(X, V, C.n, Ts, C.obs, C.ovel, kg, C.inv_Tm1, C.M, C.mwin(w),    \
+                               C.mrow, C.mpw, C.a, C.pmin0, C.pmin1, C.pmax0, C.pmax1, w, Tce, \
+                               h, H, r1sq, r2sq, w_pair, w_box, lane)
+    if (C.moving) {
+      if (accum) SF_CONSTRAINTS(true, true);
+      else SF_CONSTRAINTS(false, true);
+    } else {
+      if (accum) SF_CONSTRAINTS(true, false);
+      else SF_CONSTRAINTS(false, false);
+    }
+#undef SF_CONSTRAINTS
     if (part) {
       wave_fence();
       wtmap_window<KS>(C.W, C.nc, reinterpret_cast<const float*>(V), C.n, Ts, w, Tce, h, H,
@@ -1232,6 +1294,12 @@ __device__ __forceinline__ void residual_norms(const Ctx& C, const float* xb, fl
   }
 }
 
+// LDS floats of the obstacle data: centres and sizes, window boxes of a
+// chunk, displacements.
+__host__ __device__ inline size_t obstacle_floats(int Tc, int M_max) {
+  return 4 * (size_t)M_max * (1 + nwindows(Tc)) + (size_t)((2 * M_max + 3) & ~3);
+}
+
 // LDS floats of the box and mask regions.
 __host__ __device__ inline int box_floats(int Tc, int n_max) {
   return 4 * n_max * nwindows(Tc);
@@ -1262,6 +1330,7 @@ struct FwdLds {
   float* refc;
   int* lslot;
   unsigned* masks;
+  float2* ovel;
   float2 *X, *V;
 };
 
@@ -1281,7 +1350,8 @@ __device__ __forceinline__ FwdLds carve_fwd(float* sm, int nc, int T, int Tc, in
   L.red = p; p += kRed;
   L.csum = p; p += kColSums;
   L.obs = reinterpret_cast<float4*>(p); p += 4 * M_max;
-  L.obox = reinterpret_cast<float4*>(p); p += 4 * M_max;
+  L.obox = reinterpret_cast<float4*>(p); p += 4 * M_max * nwindows(Tc);
+  L.ovel = reinterpret_cast<float2*>(p); p += round4(2 * M_max);
   L.box3 = p; p += box_floats(Tc, n_max);
   L.masks = reinterpret_cast<unsigned*>(p); p += mask_floats(T, Tc, n_max, M_max);
   L.refc = p;
@@ -1297,7 +1367,7 @@ __device__ __forceinline__ FwdLds carve_fwd(float* sm, int nc, int T, int Tc, in
 size_t fwd_lds_bytes(int nc, int T, int Tc, int n_max, int M_max, int S_max, int) {
   auto r4 = [](int x) { return (size_t)((x + 3) & ~3); };
   size_t f = r4(nc * Tc) + r4(fac_stride(nc)) + (5 + nwindows(Tc)) * r4(S_max) + kMeans + kRed +
-             kColSums + 8 * (size_t)M_max + box_floats(Tc, n_max) + mask_floats(T, Tc, n_max, M_max) + list_floats(S_max) +
+             kColSums + obstacle_floats(Tc, M_max) + box_floats(Tc, n_max) + mask_floats(T, Tc, n_max, M_max) + list_floats(S_max) +
              4 * (size_t)n_max * tstride(Tc);
   return f * sizeof(float);
 }
@@ -1321,15 +1391,17 @@ __global__ __launch_bounds__(NT) void fwd_fused_kernel(FwdArgs A) {
         tid,    A.rho,     P.a,       P.pmin[0], P.pmin[1], P.pmax[0],
         P.pmax[1], L.W,    L.fac,     A.W,       L.obs,     L.obox,
         L.box3, L.masks,   L.refc,    L.lslot,   mask_rows(A.n_max), (A.n_max + 31) >> 5,
-        mask_words(A.n_max, A.M_max), A.Tc < T ? 0.f : list_skin(P.a), A.Tc < T};
+        mask_words(A.n_max, A.M_max), A.Tc < T ? 0.f : list_skin(P.a), A.Tc < T,
+        L.ovel, A.M_max, 1.f / (float)(T - 1), A.ovel != nullptr};
   force_rebuild(L.lslot, tid);
   if (!C.chunked) load_wchunk(A.W, L.W, nc, 0, T, tid, NT);
   for (int t = tid; t < fs; t += NT) L.fac[t] = A.fac[(size_t)P.fac * fs + t];
   for (int m = tid; m < M; m += NT) {
     const float* o = A.obstacles + ((size_t)P.obs_off + m) * 3;
     L.obs[m] = make_float4(o[0], o[1], o[2], o[2] * o[2]);
-    const float f = obs_margin(o[2]);
-    L.obox[m] = make_float4(o[0] - f, o[0] + f, o[1] - f, o[1] + f);
+    L.ovel[m] = A.ovel ? make_float2(A.ovel[((size_t)P.obs_off + m) * 2],
+                                     A.ovel[((size_t)P.obs_off + m) * 2 + 1])
+                       : make_float2(0.f, 0.f);
     if (A.save) {
       float* d = A.ws_obs + ((size_t)P.obs_off + m) * 3;
       d[0] = o[0];
@@ -1456,6 +1528,7 @@ struct BwdLds {
   float* refc;
   int* lslot;
   unsigned* masks;
+  float2* ovel;
   float2 *X, *G, *H;
 };
 
@@ -1474,7 +1547,8 @@ __device__ __forceinline__ BwdLds carve_bwd(float* sm, int nc, int T, int Tc, in
   }
   L.part = p; p += nwindows(Tc) * round4(S_max);
   L.obs = reinterpret_cast<float4*>(p); p += 4 * M_max;
-  L.obox = reinterpret_cast<float4*>(p); p += 4 * M_max;
+  L.obox = reinterpret_cast<float4*>(p); p += 4 * M_max * nwindows(Tc);
+  L.ovel = reinterpret_cast<float2*>(p); p += round4(2 * M_max);
   L.box3 = p; p += box_floats(Tc, n_max);
   L.masks = reinterpret_cast<unsigned*>(p); p += mask_floats(T, Tc, n_max, M_max);
   L.refc = p;
@@ -1617,25 +1691,32 @@ __device__ __forceinline__ void adjoint_units(const Ctx& C, int chunk, int Tce, 
   const int nwin = nwindows(Tce);
   const int H = parts_per_window(C.n, nwin, nwaves);
   const int Ts = C.Ts(), nws = C.nws();
-  if (rebuild)
+  const int kg = chunk * C.Tc;
+  if (rebuild) {
+    obstacle_boxes(C, kg, Tce, C.tid, NT);
     map_chunk<NT, KS, true>(C.W, C.nc, xb, C.n, reinterpret_cast<float*>(X), Ts, Tce, C.box3,
                             nws, wave, lane);
-  else
+  } else {
     map_chunk<NT, KS, false>(C.W, C.nc, xb, C.n, reinterpret_cast<float*>(X), Ts, Tce, nullptr,
                              nws, wave, lane);
+  }
   map_chunk<NT, KS, false>(C.W, C.nc, gR, C.n, reinterpret_cast<float*>(G), Ts, Tce, nullptr,
                            nws, wave, lane);
   __syncthreads();
   for (int u = wave; u < nwin * H; u += nwaves) {
     const int w = u / H, h = u - w * H;
     if (rebuild) {
-      masks_window(reinterpret_cast<const float4*>(C.box3), C.n, C.obox, C.M, C.a, C.skin,
-                   C.mwin(w), C.mrow, C.mpw, nws, w, h, H, lane);
+      masks_window(reinterpret_cast<const float4*>(C.box3), C.n, C.obox + w * C.ostride, C.M,
+                   C.a, C.skin, C.mwin(w), C.mrow, C.mpw, nws, w, h, H, lane);
       if (w == 0 && !C.chunked) C.set_reference(xb, h, H, lane);
       wave_fence();
     }
-    vjp_window(X, G, Hb, C.n, Ts, C.obs, C.M, C.mwin(w), C.mrow, C.mpw, C.a,
-               C.pmin0, C.pmin1, C.pmax0, C.pmax1, w, Tce, h, H, lane);
+    if (C.moving)
+      vjp_window<true>(X, G, Hb, C.n, Ts, C.obs, C.ovel, kg, C.inv_Tm1, C.M, C.mwin(w), C.mrow,
+                       C.mpw, C.a, C.pmin0, C.pmin1, C.pmax0, C.pmax1, w, Tce, h, H, lane);
+    else
+      vjp_window<false>(X, G, Hb, C.n, Ts, C.obs, C.ovel, kg, C.inv_Tm1, C.M, C.mwin(w), C.mrow,
+                        C.mpw, C.a, C.pmin0, C.pmin1, C.pmax0, C.pmax1, w, Tce, h, H, lane);
     wave_fence();
     wtmap_window<KS>(C.W, C.nc, reinterpret_cast<const float*>(Hb), C.n, Ts, w, Tce, h, H,
                      part + w * C.S, accumulate, lane);
@@ -1661,7 +1742,8 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
         tid,    rho,       P.a,       P.pmin[0], P.pmin[1], P.pmax[0],
         P.pmax[1], L.W,    L.fac,     A.W,       L.obs,     L.obox,
         L.box3, L.masks,   L.refc,    L.lslot,   mask_rows(A.n_max), (A.n_max + 31) >> 5,
-        mask_words(A.n_max, A.M_max), Tc < T ? 0.f : list_skin(P.a), Tc < T};
+        mask_words(A.n_max, A.M_max), Tc < T ? 0.f : list_skin(P.a), Tc < T,
+        L.ovel, A.M_max, 1.f / (float)(T - 1), A.ovel != nullptr};
   force_rebuild(L.lslot, tid);
   const int nwin0 = nwindows(min(Tc, T));
   if (!C.chunked) load_wchunk(A.W, L.W, nc, 0, T, tid, NT);
@@ -1669,8 +1751,9 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
   for (int m = tid; m < M; m += NT) {
     const float* o = A.obs + ((size_t)P.obs_off + m) * 3;
     L.obs[m] = make_float4(o[0], o[1], o[2], o[2] * o[2]);
-    const float f = obs_margin(o[2]);
-    L.obox[m] = make_float4(o[0] - f, o[0] + f, o[1] - f, o[1] + f);
+    L.ovel[m] = A.ovel ? make_float2(A.ovel[((size_t)P.obs_off + m) * 2],
+                                     A.ovel[((size_t)P.obs_off + m) * 2 + 1])
+                       : make_float2(0.f, 0.f);
   }
   for (int s = tid; s < S; s += NT) {
     L.cx[s] = A.cxi[P.coef_off + s];
@@ -1820,7 +1903,7 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
 size_t bwd_lds_bytes(int nc, int T, int Tc, int n_max, int M_max, int S_max, int) {
   auto r4 = [](int x) { return (size_t)((x + 3) & ~3); };
   size_t f = r4(nc * Tc) + r4(fac_stride(nc)) + kRed + 2 * kColSums + (9 + nwindows(Tc)) * r4(S_max) +
-             8 * (size_t)M_max + box_floats(Tc, n_max) + mask_floats(T, Tc, n_max, M_max) + list_floats(S_max) +
+             obstacle_floats(Tc, M_max) + box_floats(Tc, n_max) + mask_floats(T, Tc, n_max, M_max) + list_floats(S_max) +
              6 * (size_t)n_max * tstride(Tc);
   return f * sizeof(float);
 }
@@ -1925,8 +2008,9 @@ __global__ __launch_bounds__(256) void plain_constraint_kernel(FwdArgs A, PlainB
   float d1 = 0.f, d2 = 0.f;
   constraints_full(reinterpret_cast<const float2*>(Bf.X) + P.pos_off,
                    reinterpret_cast<float2*>(Bf.V) + P.pos_off, P.n, A.T,
-                   A.obstacles + (size_t)P.obs_off * 3, P.M, P.a, P.pmin[0], P.pmin[1],
-                   P.pmax[0], P.pmax[1], false, d1, d2, tid, gridDim.x * 256);
+                   A.obstacles + (size_t)P.obs_off * 3,
+                   A.ovel ? A.ovel + (size_t)P.obs_off * 2 : nullptr, P.M, P.a, P.pmin[0],
+                   P.pmin[1], P.pmax[0], P.pmax[1], false, d1, d2, tid, gridDim.x * 256);
 }
 
 // Per-window partials of W^T V (one window per wave, all column tiles), with
@@ -1992,8 +2076,9 @@ __global__ __launch_bounds__(256) void plain_final_kernel(FwdArgs A, PlainBufs B
   float r1sq = 0.f, r2sq = 0.f, bad = 0.f;
   constraints_full(reinterpret_cast<const float2*>(Bf.X) + P.pos_off,
                    reinterpret_cast<float2*>(Bf.V) + P.pos_off, n, A.T,
-                   A.obstacles + (size_t)P.obs_off * 3, P.M, P.a, P.pmin[0], P.pmin[1],
-                   P.pmax[0], P.pmax[1], true, r1sq, r2sq, tid, 256);
+                   A.obstacles + (size_t)P.obs_off * 3,
+                   A.ovel ? A.ovel + (size_t)P.obs_off * 2 : nullptr, P.M, P.a, P.pmin[0],
+                   P.pmin[1], P.pmax[0], P.pmax[1], true, r1sq, r2sq, tid, 256);
   for (int s = tid; s < S; s += 256) {
     const float x = Bf.xb[pp][P.coef_off + s], lm = plain_lam(Bf, pp)[P.coef_off + s];
     A.xi_out[P.coef_off + s] = x;

@@ -451,3 +451,61 @@ def test_accel_objective_adjoint_matches_central_finite_differences(fd_case):
             fm = loss_value(orc, *args, L, w_xi, w_lam)
             fd = (fp - fm) / (2 * h)
             assert abs(fd - gv[idx]) <= 1e-6 * max(1.0, abs(fd)), (which, idx, fd, gv[idx])
+
+
+# ------------------------------------------------------------- moving obstacles
+def test_moving_obstacle_residual_is_the_closed_form_overlap():
+    """A robot parked at the origin and an obstacle crossing it along x from
+    -1 to +1 over the horizon: at sample k the obstacle row's residual has
+    length max(0, a_o - |c(tau_k)|), |c(tau_k)| = |2 tau_k - 1| (metres)."""
+    T, nc, ao = 41, 7, 0.3
+    xi = np.zeros((2, 1, nc))
+    box = np.array([[-5.0, -5.0], [5.0, 5.0]])
+    bnd = np.zeros((1, 2, 2))
+    obs = np.array([[-1.0, 0.0, ao]])
+    orc = O.SFOracle(1, 1, nc, T, RHO, 0.4, box, obs, bnd,
+                     obstacle_displacement=np.array([[2.0, 0.0]]))
+    r1, r2, _, _, _ = orc.residual_terms(orc.flat(xi))
+    tau = np.arange(T) / (T - 1)
+    expect = np.sqrt(np.sum(np.maximum(0.0, ao - np.abs(2 * tau - 1)) ** 2))
+    assert abs(np.linalg.norm(r1) - expect) < 1e-12
+    assert np.linalg.norm(r2) == 0.0
+
+
+def test_zero_displacement_is_the_static_oracle():
+    cfg = scaled(WORKLOADS[3], n_robots=(3, 3), n_obs=(2, 2), arena=4.0, n_steps=25)
+    p = make_problem(cfg, 3)
+    a = O.SFOracle.for_problem(p, RHO).solve(p.xi, n_iters=15).xi_bar
+    b = O.SFOracle(p.n, p.M, p.n_coef, p.n_steps, RHO, p.a, p.box, p.obstacles, p.boundary,
+                   obstacle_displacement=np.zeros((p.M, 2))).solve(p.xi, n_iters=15).xi_bar
+    np.testing.assert_array_equal(a, b)
+
+
+def test_moving_obstacle_adjoint_matches_central_finite_differences(fd_case):
+    p, _, rng = fd_case
+    L = 12
+    # first displacement (fixed seeds) whose iterates keep every pair,
+    # obstacle and box quantity away from its kink (else reseed)
+    for seed in range(20):
+        disp = np.random.default_rng(100 + seed).uniform(-1.0, 1.0, (p.M, 2))
+        orc = O.SFOracle(p.n, p.M, p.n_coef, p.n_steps, RHO, p.a, p.box, p.obstacles,
+                         p.boundary, obstacle_displacement=disp)
+        its = orc.solve(p.xi, p.xi, None, L, keep_iterates=True).iterates
+        if _kink_margin(orc, its) > 1e-4:
+            break
+    else:
+        pytest.fail("no kink-free displacement among the seeds")
+    w_xi = rng.standard_normal(p.xi.shape)
+    w_lam = rng.standard_normal(p.xi.shape)
+    g = SFAdjoint(orc).gradient(p.xi, p.xi, None, L, w_xi, w_lam)
+    h = 1e-6
+    for which, gv in ((0, g.g_xi), (1, g.g_xi0)):
+        for _ in range(4):
+            idx = tuple(int(rng.integers(0, s)) for s in p.xi.shape)
+            args = [p.xi.copy(), p.xi.copy(), None]
+            args[which][idx] += h
+            fp = loss_value(orc, *args, L, w_xi, w_lam)
+            args[which][idx] -= 2 * h
+            fm = loss_value(orc, *args, L, w_xi, w_lam)
+            fd = (fp - fm) / (2 * h)
+            assert abs(fd - gv[idx]) <= 1e-6 * max(1.0, abs(fd)), (which, idx, fd, gv[idx])
