@@ -62,6 +62,8 @@ class SFGrad:
 
 class SFAdjoint:
     def __init__(self, orc: SFOracle):
+        if orc.dim != 2:
+            raise NotImplementedError("the oracle adjoint covers the 2D SF")
         self.o = orc
 
     def _geometry(self, q):

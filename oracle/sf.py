@@ -30,6 +30,15 @@ Readings of the paper that this oracle fixes (each is a named choice):
       used for the paper's dataset): the identity block of the KKT matrix
       becomes Wdd^T Wdd per robot and axis (Wdd the second tau-derivative of
       the basis) and the sample drops out of eta; everything else is the SF.
+  Q1  3D (dim=3, spheroids (a, a, b) and (a_o, a_o, b_o), eqs.
+      inter_robot_polar, workspace_polar, f_e): the alpha, beta and d steps
+      are all taken at xi_bar^l (Jacobi order as R13).  alpha = atan2(dy, dx)
+      is the exact minimiser over alpha.  beta = atan2(rho_xy / a, dz / b) with
+      rho_xy = dx cos(alpha) + dy sin(alpha): the printed closed form divides
+      dx by a cos(alpha), which equals rho_xy / a wherever cos(alpha) != 0 and
+      stays defined where it is 0.  d is the exact minimiser over d >= 1 of
+      ||Delta - d u(alpha, beta)||^2.  At Delta = 0: alpha = beta = 0, so
+      u = (0, 0, b) and e = (0, 0, b) (the tie convention of R12 in 3D).
 """
 from __future__ import annotations
 
@@ -43,7 +52,7 @@ import scipy.sparse as sp
 
 from .basis import accel_basis
 
-N_DIM = 2
+N_DIM = 2          # the planar SF; dim=3 selects the spheroid variant (Q1)
 
 
 # --------------------------------------------------------------------------
@@ -95,9 +104,10 @@ class Operators:
     A: np.ndarray
     n_pair_rows: int          # P*T rows per axis
     n_obs_rows: int           # n*M*T rows per axis
+    dim: int = N_DIM          # workspace dimension n_d (2 or 3)
 
 
-def build_operators(n: int, M: int, n_coef: int, n_steps: int) -> Operators:
+def build_operators(n: int, M: int, n_coef: int, n_steps: int, dim: int = N_DIM) -> Operators:
     W = bernstein_W(n_coef, n_steps)
     Ws = sp.csr_matrix(W)
     D = sp.csr_matrix(pair_incidence(n))
@@ -109,11 +119,11 @@ def build_operators(n: int, M: int, n_coef: int, n_steps: int) -> Operators:
     G_axis = sp.vstack([Wbar, -Wbar], format="csr")                      # R7
     A1 = np.stack([W[0], W[-1]])                                         # R17
     A_axis = np.kron(np.eye(n), A1)
-    F = sp.block_diag([F_axis] * N_DIM, format="csr")
-    G = sp.block_diag([G_axis] * N_DIM, format="csr")
-    A = sla.block_diag(*([A_axis] * N_DIM))
+    F = sp.block_diag([F_axis] * dim, format="csr")
+    G = sp.block_diag([G_axis] * dim, format="csr")
+    A = sla.block_diag(*([A_axis] * dim))
     return Operators(n, M, n_coef, n_steps, W, F_axis, G_axis, A_axis, F, G, A,
-                     F_r.shape[0], F_o.shape[0])
+                     F_r.shape[0], F_o.shape[0], dim)
 
 
 def objective_block(ops: Operators, objective: str) -> np.ndarray:
@@ -127,7 +137,7 @@ def objective_block(ops: Operators, objective: str) -> np.ndarray:
         return np.eye(Sz)
     if objective == "accel":
         D = accel_basis(ops.n_coef, ops.n_steps)
-        return np.kron(np.eye(N_DIM * ops.n), D.T @ D)
+        return np.kron(np.eye(ops.dim * ops.n), D.T @ D)
     raise ValueError(objective)
 
 
@@ -155,31 +165,33 @@ def h_vector(ops: Operators, box: np.ndarray) -> np.ndarray:
     """h = [p_max 1; -p_min 1] per axis (eq. workspace_con, R7)."""
     nT = ops.n * ops.n_steps
     parts = []
-    for ax in range(N_DIM):
+    for ax in range(ops.dim):
         parts.append(np.concatenate([np.full(nT, box[1, ax]), np.full(nT, -box[0, ax])]))
     return np.concatenate(parts)
 
 
 def b_vector(boundary: np.ndarray) -> np.ndarray:
     """b = (b_{i,0}, b_{i,K}) per robot, axis-major (eq. boundary_con)."""
-    n = boundary.shape[0]
-    return np.concatenate([boundary[:, :, ax].reshape(n * 2) for ax in range(N_DIM)])
+    n, dim = boundary.shape[0], boundary.shape[2]
+    return np.concatenate([boundary[:, :, ax].reshape(n * 2) for ax in range(dim)])
 
 
 def obstacle_rows(ops: Operators, obstacles: np.ndarray, displacement=None):
-    """x_o, y_o stacked over (robot, obstacle, time) as F_o's rows, and a_o.
-    With a displacement d ([M][2]) obstacle m's centre at time sample k is
+    """Obstacle centres per axis stacked over (robot, obstacle, time) as F_o's
+    rows, and the sizes: a_o in 2D (obstacles [M][3] = x, y, a_o); the pair
+    (a_o, b_o) in 3D (obstacles [M][5] = x, y, z, a_o, b_o).  With a
+    displacement d ([M][dim]) obstacle m's centre at time sample k is
     c_m + d_m tau_k (moving obstacles; tau_k = k/(T-1))."""
-    n, M, T = ops.n, ops.M, ops.n_steps
+    n, M, T, dim = ops.n, ops.M, ops.n_steps, ops.dim
     if M == 0:
         z = np.zeros(0)
-        return [z, z], z
+        return [z] * dim, (z if dim == 2 else (z, z))
     tau = np.arange(T, dtype=np.float64) / (T - 1)
-    d = np.zeros((M, N_DIM)) if displacement is None else np.asarray(displacement, np.float64)
+    d = np.zeros((M, dim)) if displacement is None else np.asarray(displacement, np.float64)
     cen = [np.tile((obstacles[:, ax][:, None] + d[:, ax][:, None] * tau[None, :]).reshape(-1), n)
-           for ax in range(N_DIM)]
-    a_o = np.tile(np.repeat(obstacles[:, 2], T), n)
-    return cen, a_o
+           for ax in range(dim)]
+    size = [np.tile(np.repeat(obstacles[:, q], T), n) for q in range(dim, 2 * dim - 1)]
+    return cen, (size[0] if dim == 2 else tuple(size))
 
 
 # --------------------------------------------------------------------------
@@ -201,8 +213,8 @@ def s_step(Gxi: np.ndarray, h: np.ndarray) -> np.ndarray:
     return np.maximum(0.0, h - Gxi)
 
 
-def split_axes(v: np.ndarray, rows_per_axis: int):
-    return [v[ax * rows_per_axis:(ax + 1) * rows_per_axis] for ax in range(N_DIM)]
+def split_axes(v: np.ndarray, rows_per_axis: int, dim: int = N_DIM):
+    return [v[ax * rows_per_axis:(ax + 1) * rows_per_axis] for ax in range(dim)]
 
 
 def e_vector(ops: Operators, Fxi: np.ndarray, a: float, obs_cen, obs_ao):
@@ -226,6 +238,53 @@ def e_vector(ops: Operators, Fxi: np.ndarray, a: float, obs_cen, obs_ao):
 
 
 # --------------------------------------------------------------------------
+# 3D closed-form steps (eqs. inter_robot_polar, workspace_polar, alpha_step,
+# beta_step, d_step; reading Q1).  Delta = (dx, dy, dz), spheroid sizes (a, b).
+# --------------------------------------------------------------------------
+def beta_step(dx, dy, dz, alpha, a, b):
+    """beta = atan2(rho_xy / a, dz / b), rho_xy = dx cos(alpha) + dy sin(alpha)."""
+    rho_xy = dx * np.cos(alpha) + dy * np.sin(alpha)
+    return np.arctan2(rho_xy / a, dz / b)
+
+
+def spheroid_direction(alpha, beta, a, b):
+    """u(alpha, beta) = (a cos(alpha) sin(beta), a sin(alpha) sin(beta), b cos(beta))."""
+    return (a * np.cos(alpha) * np.sin(beta), a * np.sin(alpha) * np.sin(beta),
+            b * np.cos(beta))
+
+
+def d_step_3d(dx, dy, dz, alpha, beta, a, b):
+    """argmin over 1 <= d <= inf of ||Delta - d u(alpha, beta)||^2: the least-squares
+    d = <Delta, u> / <u, u>, clipped below at 1."""
+    ux, uy, uz = spheroid_direction(alpha, beta, a, b)
+    return np.maximum(1.0, (dx * ux + dy * uy + dz * uz) / (ux * ux + uy * uy + uz * uz))
+
+
+def e_block_3d(dx, dy, dz, a, b):
+    """e - centre = d u(alpha, beta) after the alpha, beta and d steps at Delta."""
+    alpha = alpha_step(dx, dy)
+    beta = beta_step(dx, dy, dz, alpha, a, b)
+    d = d_step_3d(dx, dy, dz, alpha, beta, a, b)
+    ux, uy, uz = spheroid_direction(alpha, beta, a, b)
+    return d * ux, d * uy, d * uz
+
+
+def e_vector_3d(ops: Operators, Fxi: np.ndarray, a: float, b: float, obs_cen, obs_ab):
+    """e(alpha, beta, d) of eq. f_e in 3D (x, y, z blocks of F's rows)."""
+    R = ops.n_pair_rows + ops.n_obs_rows
+    comp = split_axes(Fxi, R, 3)
+    Pr = ops.n_pair_rows
+    ep = e_block_3d(comp[0][:Pr], comp[1][:Pr], comp[2][:Pr], a, b)
+    if ops.M > 0:
+        off = [comp[ax][Pr:] - obs_cen[ax] for ax in range(3)]
+        eo = e_block_3d(off[0], off[1], off[2], obs_ab[0], obs_ab[1])
+        eo = [obs_cen[ax] + eo[ax] for ax in range(3)]
+    else:
+        eo = [np.zeros(0)] * 3
+    return np.concatenate([np.concatenate([ep[ax], eo[ax]]) for ax in range(3)]), None
+
+
+# --------------------------------------------------------------------------
 # The SF solver.
 # --------------------------------------------------------------------------
 @dataclass
@@ -245,17 +304,24 @@ class SFResult:
 
 
 class SFOracle:
-    """Literal SF for one problem (one context + one target xi)."""
+    """Literal SF for one problem (one context + one target xi).  dim=3 is the
+    spheroid variant: robot_b is b, obstacles are [M][5] = x, y, z, a_o, b_o,
+    box [2][3], boundary [n][2][3]."""
 
     def __init__(self, n: int, M: int, n_coef: int, n_steps: int, rho: float,
                  a: float, box: np.ndarray, obstacles: np.ndarray,
                  boundary: np.ndarray, include_G: bool = True,
-                 objective: str = "projection", obstacle_displacement=None):
-        self.ops = build_operators(n, M, n_coef, n_steps)
+                 objective: str = "projection", obstacle_displacement=None,
+                 dim: int = N_DIM, robot_b: Optional[float] = None):
+        if dim not in (2, 3):
+            raise ValueError("dim must be 2 or 3")
+        self.dim = dim
+        self.ops = build_operators(n, M, n_coef, n_steps, dim)
         self.rho = float(rho)
         self.a = float(a)
+        self.robot_b = float(a if robot_b is None else robot_b)
         self.box = np.asarray(box, dtype=np.float64)
-        self.obstacles = np.asarray(obstacles, dtype=np.float64).reshape(M, 3)
+        self.obstacles = np.asarray(obstacles, dtype=np.float64).reshape(M, 2 * dim - 1)
         self.include_G = include_G
         self.h = h_vector(self.ops, self.box)
         self.b = b_vector(np.asarray(boundary, dtype=np.float64))
@@ -268,6 +334,9 @@ class SFOracle:
 
     @classmethod
     def for_problem(cls, prob, rho: float, **kw) -> "SFOracle":
+        dim = getattr(prob, "dim", N_DIM)
+        if dim == 3:
+            kw = dict(kw, dim=3, robot_b=prob.b)
         return cls(prob.n, prob.M, prob.n_coef, prob.n_steps, rho, prob.a,
                    prob.box, prob.obstacles, prob.boundary, **kw)
 
@@ -276,12 +345,15 @@ class SFOracle:
         return np.asarray(x, dtype=np.float64).reshape(-1)
 
     def shaped(self, v: np.ndarray) -> np.ndarray:
-        return v.reshape(N_DIM, self.ops.n, self.ops.n_coef).copy()
+        return v.reshape(self.dim, self.ops.n, self.ops.n_coef).copy()
 
     def residual_terms(self, xib: np.ndarray):
         """r_1, r_2, e, s at xi_bar (steps alpha..s of one iteration)."""
         Fxi = self.ops.F @ xib
-        e, geo = e_vector(self.ops, Fxi, self.a, self.obs_cen, self.obs_ao)
+        if self.dim == 3:
+            e, geo = e_vector_3d(self.ops, Fxi, self.a, self.robot_b, self.obs_cen, self.obs_ao)
+        else:
+            e, geo = e_vector(self.ops, Fxi, self.a, self.obs_cen, self.obs_ao)
         Gxi = self.ops.G @ xib
         s = s_step(Gxi, self.h)
         r1 = Fxi - e                                                     # R3
