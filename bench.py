@@ -17,6 +17,7 @@ same per-stage kernels, each launch over the whole batch) so that the gain can
 be attributed to batching and to fusion, the plan setup time (host FP64
 factors and workspace tables), the residual check on the GPU outputs, the
 candidate-selection pipeline around the SF on the 32-candidate context, the
+3D (spheroid) forward on 64 problems of 32 robots, the
 roofline of the dominant kernel and the FP64 oracle timed on one host core
 and on all available cores (one process per problem).
 """
@@ -199,6 +200,66 @@ def candidate_pipeline_timing(dev, steps=5):
                 chosen_cost=float(out["cost"].cpu()[best]))
 
 
+def algorithmic_flops3d(problems, T, nc, L):
+    """The forward count of algorithmic_flops for the 3D (spheroid) SF: a
+    distance test costs 8 flops per unordered robot pair and robot-obstacle
+    pair per step, box residuals 4 per coordinate, the maps and mode products
+    run over three axes."""
+    tot = 0.0
+    for p in problems:
+        n, M = p.n, p.M
+        Sc = 3 * n * nc
+        tests = 8.0 * (n * (n - 1) / 2 + n * M) * T + 4.0 * 3 * n * T
+        maps = 2.0 * 3 * n * T * nc
+        modes = 2.0 * Sc * nc
+        tot += (tests + 2 * maps + 2 * modes + 10.0 * Sc) * L + tests + maps
+    return tot
+
+
+def spheroid_3d_timing(dev, steps=5):
+    """The 3D (spheroid) forward on 64 problems of 32 robots and 20 obstacles
+    (sf_setup with n_dim = 3), for the workload's iteration count and 10x
+    that; ms per launch from HIP events on the stream."""
+    import torch
+
+    from paper_2510_09204_amd import SFPlan
+    from workloads.gen3d import WORKLOADS_3D, make_batch3d, pack3d
+    cfg = WORKLOADS_3D[32]
+    probs = make_batch3d(cfg)
+    pk = pack3d(probs)
+    plan = SFPlan(pk.n_robots, pk.n_obs, pk.robot_ab, pk.box, pk.n_coef, pk.n_steps, RHO,
+                  n_dim=3, device=dev)
+    t = {k: torch.from_numpy(getattr(pk, k)).to(dev) for k in ("xi", "xi0", "lam0",
+                                                                "boundary", "obstacles")}
+    stream = torch.cuda.current_stream(dev)
+    out = {}
+    for L in (cfg.iters, 10 * cfg.iters):
+        args = (t["xi"], t["xi0"], t["lam0"], t["boundary"], t["obstacles"], L)
+        plan.project(*args)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            xo, lo, res = plan.project(*args)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        r = np.hypot(res[:, 0].cpu().numpy(), res[:, 1].cpu().numpy())
+        ach = algorithmic_flops3d(probs, pk.n_steps, pk.n_coef, L) / (ms / 1e3) / 1e12
+        out[f"L{L}"] = dict(ms=round(ms, 4), problems_per_s=round(len(probs) / (ms / 1e3), 2),
+                            us_per_iter=round(ms * 1e3 / L, 3),
+                            residual_median=float(np.median(r)),
+                            frac_residual_le_tol=float(np.mean(r <= 1e-3)),
+                            status_nonzero=int(np.sum(res[:, 3].cpu().numpy() != 0)),
+                            roofline=dict(bound="alu", kernel="fwd3_kernel",
+                                          achieved=round(ach, 3),
+                                          peak=round(PEAK_ALU_TFLOPS, 2), unit="TFLOP/s",
+                                          frac=round(ach / PEAK_ALU_TFLOPS, 4)))
+    return dict(workload=f"{cfg.name}: {cfg.description}", batch=len(probs),
+                robots=int(pk.n_robots.max()), obstacles=int(pk.n_obs.max()),
+                n_coef=pk.n_coef, n_steps=pk.n_steps, threads=plan.threads, **out)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -217,7 +278,15 @@ def main(argv=None):
                     help="seconds per process of the all-cores oracle timing (0 = skip)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (counter calibration)")
+    ap.add_argument("--spheroid-3d-only", action="store_true",
+                    help="only time the 3D (spheroid) forward and print its JSON object")
     a = ap.parse_args(argv)
+    if a.spheroid_3d_only:
+        import torch
+        from paper_2510_09204_amd import load_library
+        load_library()
+        print(json.dumps(spheroid_3d_timing(torch.device("cuda:0"), steps=a.steps)), flush=True)
+        return 0
     if a.copy_probe:
         import torch
         src = torch.ones(a.copy_probe * (1 << 18), dtype=torch.float32, device="cuda:0")
@@ -358,6 +427,7 @@ def main(argv=None):
                              "sf_bwd_fused": dict(ms=round(bwd_ms, 4),
                                                   tflops=round(f_bwd / bwd_ms / 1e9, 3))})
     pipeline = None if a.no_plain else candidate_pipeline_timing(dev)
+    sph3d = None if a.no_plain else spheroid_3d_timing(dev)
     cpu = None
     if not a.no_cpu:
         cpu = cpu_baseline(probs[0], L, a.cpu_budget, pool)
@@ -388,7 +458,8 @@ def main(argv=None):
                 residual_max=float(resid.max()), residual_median=float(np.median(resid)),
                 frac_residual_le_tol=float(np.mean(resid <= 1e-3)),
                 status_nonzero=int(np.sum(res[:, 3] != 0)),
-                candidate_pipeline=pipeline, roofline=roofline, cpu_baseline=cpu)
+                candidate_pipeline=pipeline, spheroid_3d=sph3d, roofline=roofline,
+                cpu_baseline=cpu)
     print(json.dumps(line), flush=True)
     return 0
 

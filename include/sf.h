@@ -6,7 +6,9 @@
  * equalities (projection problem, eqs. proj_cost..proj_robot) by L
  * applications of the fixed-point operator T (eq. fixed_point), whose steps are
  * the alternating-minimisation updates of the Appendix (eqs. alpha_step ..
- * xi_step) on the augmented Lagrangian (eq. aug_lag).  2D workspace only.
+ * xi_step) on the augmented Lagrangian (eq. aug_lag).  The planar SF (n_dim =
+ * 2) has every entry point; the 3D spheroid variant (n_dim = 3, below) has the
+ * fused forward only.
  *
  * Layouts (all float32, contiguous, device memory unless marked host):
  *   coefficient arrays (xi, xi_bar, lambda and their gradients): problems
@@ -20,6 +22,21 @@
  *     as a float (0 = finite outputs, 1 = non-finite value in the outputs).
  *   The robot size a is the minimum centre-to-centre distance (diag(a, a)
  *   is M_r of the inter-robot constraint); box = p_min, p_max per problem.
+ *
+ * 3D (cfg.n_dim = 3; problem formulation and Appendix eqs. inter_robot_polar,
+ * workspace_polar, f_e): robots are axis-aligned spheroids with minimum
+ * centre distances a (x, y) and b (z), M_r = diag(a, a, b); obstacles are
+ * spheroids diag(a_o, a_o, b_o) inflated by the robot.  Layouts change to
+ *   coefficient arrays: [3][n_b][n_coef] per problem (x, then y, then z);
+ *   boundary: [sum_b n_b][2][3]; obstacles: [sum_b M_b][5] = x, y, z, a_o, b_o;
+ *   robot_a (sf_setup): [B][2] = a, b; box: [B][2][3].
+ * The beta step is read as beta = atan2(rho_xy / a, dz / b) with rho_xy =
+ * dx cos(alpha) + dy sin(alpha) (the printed dx / (a cos(alpha)) where that is
+ * defined), and d as the exact minimiser over d >= 1; together they put e on
+ * the ray of Delta.  Only sf_project without SF_SAVE_FOR_BACKWARD, SF_PLAIN and
+ * SF_UNFUSED runs for n_dim = 3 (SF_GRAPH works); sf_project_backward,
+ * early exit, obstacle motion and sf_smoothness return SF_ERR_INVALID_ARG or
+ * SF_ERR_NOT_SAVED.  Each workgroup visits every robot pair.
  *
  * Ownership: the caller allocates every array and the workspace; the library
  * owns only the host-side plan.  Calls never retain caller pointers (the
@@ -61,7 +78,7 @@ extern "C" {
 typedef struct sf_plan sf_plan_t;
 
 typedef struct {
-  int32_t n_dim;            /* workspace dimension n_d; must be 2 */
+  int32_t n_dim;            /* workspace dimension n_d: 2, or 3 (spheroids, forward only) */
   int32_t n_coef;           /* basis size n_xi per axis, 2..32 (Bernstein, eq. poly) */
   int32_t n_steps;          /* time samples T = K + 1, 2..4096 */
   int32_t checkpoint_every; /* k >= 1: the forward stores (xi_bar, lambda) every k
@@ -102,8 +119,8 @@ typedef struct {
  *   n_problems     B >= 1.
  *   n_robots       host int32[B], each 1..64.
  *   n_obs          host int32[B], each 0..4096.
- *   robot_a        host float[B], a > 0.
- *   box            host float[B][2][2] = p_min, p_max; p_min < p_max.
+ *   robot_a        host float[B], a > 0 (n_dim = 3: float[B][2] = a, b > 0).
+ *   box            host float[B][2][n_dim] = p_min, p_max; p_min < p_max per axis.
  *   workspace      NULL: only *workspace_bytes is set and *plan is left alone.
  *                  Otherwise a device buffer of at least *workspace_bytes bytes,
  *                  256-byte aligned, that this plan uses until sf_destroy; the
@@ -129,7 +146,8 @@ int sf_setup(const sf_config_t* cfg, int32_t n_problems, const int32_t* n_robots
  *
  *   xi          flow sample xi (the projection target), coefficient layout.
  *   xi0, lam0   warm start, coefficient layout.
- *   boundary    [sum n][2][2]; obstacles [sum M][3] (may be NULL if sum M = 0).
+ *   boundary    [sum n][2][n_dim]; obstacles [sum M][3] ([sum M][5] for n_dim = 3;
+ *               may be NULL if sum M = 0).
  *   n_iters     L >= 0 (L = 0 copies the warm start and reports its residual).
  *   flags       SF_SAVE_FOR_BACKWARD | SF_PLAIN | SF_UNFUSED | SF_GRAPH.  Saving
  *               requires n_iters <= cfg.max_iters and is not combined with

@@ -113,14 +113,16 @@ def _host(a, dtype) -> np.ndarray:
 class SFPlan:
     """A batch of SF problems sharing (n_coef, n_steps, rho) and its workspace.
 
-    n_robots, n_obs, robot_a and box ([B][2][2] = p_min, p_max) describe each
-    problem; the FP64 KKT factors are built on the host and the workspace is a
-    torch uint8 tensor on `device`."""
+    n_robots, n_obs, robot_a and box ([B][2][n_dim] = p_min, p_max) describe
+    each problem; the FP64 KKT factors are built on the host and the workspace
+    is a torch uint8 tensor on `device`.  n_dim = 3 is the spheroid variant:
+    robot_a is then [B][2] = (a, b), boundary [sum n][2][3], obstacles
+    [sum M][5] = (x, y, z, a_o, b_o), and only the fused forward runs."""
 
     def __init__(self, n_robots: Sequence[int], n_obs: Sequence[int],
                  robot_a: Sequence[float], box, n_coef: int, n_steps: int, rho: float,
                  checkpoint_every: int = 1, max_iters: int = 0, threads: int = 0,
-                 device="cuda", objective: int = SF_OBJECTIVE_PROJECTION):
+                 device="cuda", objective: int = SF_OBJECTIVE_PROJECTION, n_dim: int = 2):
         self.lib = load_library()
         dev = torch.device(device)
         if dev.type == "cuda" and dev.index is None:
@@ -128,14 +130,17 @@ class SFPlan:
         self.device = dev
         self.n_robots = _host(n_robots, np.int32)
         self.n_obs = _host(n_obs, np.int32)
+        self.n_dim = int(n_dim)
         self.robot_a = _host(robot_a, np.float32)
-        self.box = _host(box, np.float32).reshape(-1, 2, 2)
+        self.box = _host(box, np.float32).reshape(-1, 2, self.n_dim)
         self.B = int(self.n_robots.size)
+        if self.robot_a.size != self.B * (self.n_dim - 1):
+            raise SFError(-1, f"robot_a must hold {self.n_dim - 1} value(s) per problem")
         self.n_coef, self.n_steps, self.rho = int(n_coef), int(n_steps), float(rho)
         self.objective = int(objective)
-        self.cfg = SFConfigC(2, self.n_coef, self.n_steps, int(checkpoint_every),
+        self.cfg = SFConfigC(self.n_dim, self.n_coef, self.n_steps, int(checkpoint_every),
                              int(max_iters), int(threads), self.rho, self.objective)
-        self.coef_size = int(2 * self.n_robots.astype(np.int64).sum() * self.n_coef)
+        self.coef_size = int(self.n_dim * self.n_robots.astype(np.int64).sum() * self.n_coef)
         self.n_rob_total = int(self.n_robots.sum())
         self.n_obs_total = int(self.n_obs.sum())
         nbytes = ctypes.c_size_t(0)
@@ -224,14 +229,16 @@ class SFPlan:
         for t, name in ((xi, "xi"), (xi0, "xi0"), (lam0, "lam0")):
             if t is not None:
                 self._coef(t, name)
-        if boundary.numel() != self.n_rob_total * 4 or boundary.dtype != torch.float32 \
+        D = self.n_dim
+        if boundary.numel() != self.n_rob_total * 2 * D or boundary.dtype != torch.float32 \
                 or not boundary.is_contiguous() or boundary.device != self.device:
-            raise SFError(-2, "boundary must be contiguous float32 [sum n][2][2] on device")
+            raise SFError(-2, f"boundary must be contiguous float32 [sum n][2][{D}] on device")
         if self.n_obs_total:
-            if obstacles is None or obstacles.numel() != self.n_obs_total * 3 \
+            if obstacles is None or obstacles.numel() != self.n_obs_total * (2 * D - 1) \
                     or obstacles.dtype != torch.float32 or not obstacles.is_contiguous() \
                     or obstacles.device != self.device:
-                raise SFError(-2, "obstacles must be contiguous float32 [sum M][3] on device")
+                raise SFError(-2, f"obstacles must be contiguous float32 [sum M][{2 * D - 1}] "
+                                  "on device")
         if out is None:
             xi_out = torch.empty_like(xi0)
             lam_out = torch.empty_like(xi0)

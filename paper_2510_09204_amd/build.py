@@ -14,7 +14,8 @@ PKG = Path(__file__).resolve().parent
 CSRC = PKG / "csrc"
 INCLUDE = PKG.parent / "include"
 LIB = PKG / "libsf.so"
-SOURCES = [CSRC / "sf_kernels.hip", CSRC / "sf_select.hip", CSRC / "sf_host.cpp"]
+SOURCES = [CSRC / "sf_kernels.hip", CSRC / "sf_kernels3d.hip", CSRC / "sf_select.hip",
+           CSRC / "sf_host.cpp"]
 
 # Packed FP32 instructions stay off: the compiler would otherwise form
 # v_pk_* FP32 ops from scalar and float2 code.

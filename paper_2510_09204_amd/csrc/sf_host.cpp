@@ -232,7 +232,7 @@ namespace {
 
 int validate_cfg(const sf_config_t* cfg) {
   if (!cfg) return fail(SF_ERR_INVALID_ARG, "cfg is NULL");
-  if (cfg->n_dim != 2) return fail(SF_ERR_SHAPE, "only n_dim = 2 is supported");
+  if (cfg->n_dim != 2 && cfg->n_dim != 3) return fail(SF_ERR_SHAPE, "n_dim must be 2 or 3");
   if (cfg->n_coef < 2 || cfg->n_coef > sf::kMaxCoef)
     return fail(SF_ERR_SHAPE, "n_coef must be in [2, 32]");
   if (cfg->n_steps < 2 || cfg->n_steps > 4096)
@@ -277,6 +277,7 @@ int build_plan(const sf_config_t* cfg, int B, const int32_t* n_robots, const int
   } else {
     for (int a = 0; a < nc; ++a) Q0[(size_t)a * nc + a] = 1.0;
   }
+  const int D = cfg->n_dim;
   std::map<std::pair<int, int>, int> fac_index;
   const int fs = sf::fac_stride(nc);
   int64_t coef = 0, rob = 0, obs = 0, pos = 0;
@@ -287,15 +288,17 @@ int build_plan(const sf_config_t* cfg, int B, const int32_t* n_robots, const int
       return fail(SF_ERR_SHAPE, "problem " + std::to_string(b) + ": n_robots out of [1, 1024]");
     if (M < 0 || M > kMaxObs)
       return fail(SF_ERR_SHAPE, "problem " + std::to_string(b) + ": n_obs out of [0, 4096]");
-    const float a = robot_a[b];
-    if (!(a > 0.f) || !std::isfinite(a))
-      return fail(SF_ERR_INVALID_ARG, "problem " + std::to_string(b) + ": robot_a must be > 0");
-    const float* bx = box + (size_t)b * 4;
-    for (int q = 0; q < 4; ++q)
+    const float a = robot_a[(size_t)b * (D - 1)];
+    const float rb = D == 3 ? robot_a[(size_t)b * 2 + 1] : a;
+    if (!(a > 0.f) || !std::isfinite(a) || !(rb > 0.f) || !std::isfinite(rb))
+      return fail(SF_ERR_INVALID_ARG, "problem " + std::to_string(b) + ": robot sizes must be > 0");
+    const float* bx = box + (size_t)b * 2 * D;
+    for (int q = 0; q < 2 * D; ++q)
       if (!std::isfinite(bx[q]))
         return fail(SF_ERR_NONFINITE, "problem " + std::to_string(b) + ": box not finite");
-    if (!(bx[0] < bx[2]) || !(bx[1] < bx[3]))
-      return fail(SF_ERR_INVALID_ARG, "problem " + std::to_string(b) + ": p_min >= p_max");
+    for (int q = 0; q < D; ++q)
+      if (!(bx[q] < bx[D + q]))
+        return fail(SF_ERR_INVALID_ARG, "problem " + std::to_string(b) + ": p_min >= p_max");
     auto key = std::make_pair(n, M);
     auto it = fac_index.find(key);
     int fi;
@@ -332,18 +335,19 @@ int build_plan(const sf_config_t* cfg, int B, const int32_t* n_robots, const int
     d.fac = fi;
     d.pos_off = (int32_t)pos;
     d.a = a;
-    d.pmin[0] = bx[0];
-    d.pmin[1] = bx[1];
-    d.pmax[0] = bx[2];
-    d.pmax[1] = bx[3];
+    d.b = rb;
+    for (int q = 0; q < D; ++q) {
+      d.pmin[q] = bx[q];
+      d.pmax[q] = bx[D + q];
+    }
     p->desc.push_back(d);
-    coef += 2LL * n * nc;
+    coef += (int64_t)D * n * nc;
     rob += n;
     obs += M;
     pos += (int64_t)n * T;
     p->n_max = std::max(p->n_max, n);
     p->M_max = std::max(p->M_max, M);
-    p->S_max = std::max(p->S_max, 2 * n * nc);
+    p->S_max = std::max(p->S_max, D * n * nc);
     cost[b] = (double)T * (0.5 * n * (n - 1) + (double)n * M + n) + 4.0 * n * nc * nc;
   }
   if (coef > (int64_t)1 << 30 || pos > (int64_t)1 << 30)
@@ -360,15 +364,34 @@ int build_plan(const sf_config_t* cfg, int B, const int32_t* n_robots, const int
   p->threads = cfg->threads ? cfg->threads : 512;
   p->threads_bwd = p->threads;
   p->tune_fwd = p->tune_bwd = (cfg->threads == 0);
+  if (D == 3) {
+    // 3D: the forward kernel of sf_kernels3d.hip, the longest time chunk that
+    // fits in LDS (balanced), fixed threads (no autotuning)
+    p->tune_fwd = p->tune_bwd = false;
+    int best = 0;
+    for (int tc = T; tc >= 1; --tc)
+      if (sf::fwd3_lds_bytes(nc, T, tc, p->n_max, p->M_max, p->S_max) <= kLdsBudget) {
+        best = tc;
+        break;
+      }
+    if (best == 0)
+      return fail(SF_ERR_SHAPE, "problem state does not fit the LDS of one workgroup");
+    const int chunks = (T + best - 1) / best;
+    p->Tc_fwd = p->Tc_bwd = (T + chunks - 1) / chunks;
+    p->lds_fwd = sf::fwd3_lds_bytes(nc, T, p->Tc_fwd, p->n_max, p->M_max, p->S_max);
+    p->lds_bwd = 0;
+  }
   // One time-chunk length for both kernels: the adjoint recomputes forward
   // iterates and must sum in the same order to reproduce them bitwise.
-  p->Tc_fwd = choose_tc(nc, T, p->n_max, p->M_max, p->S_max, p->threads, false);
-  p->Tc_bwd = choose_tc(nc, T, p->n_max, p->M_max, p->S_max, p->threads, true);
-  if (p->Tc_fwd == 0 || p->Tc_bwd == 0)
-    return fail(SF_ERR_SHAPE, "problem state does not fit the LDS of one workgroup");
-  p->Tc_fwd = p->Tc_bwd = std::min(p->Tc_fwd, p->Tc_bwd);
-  p->lds_fwd = sf::fwd_lds_bytes(nc, T, p->Tc_fwd, p->n_max, p->M_max, p->S_max, p->threads);
-  p->lds_bwd = sf::bwd_lds_bytes(nc, T, p->Tc_bwd, p->n_max, p->M_max, p->S_max, p->threads);
+  if (D == 2) {
+    p->Tc_fwd = choose_tc(nc, T, p->n_max, p->M_max, p->S_max, p->threads, false);
+    p->Tc_bwd = choose_tc(nc, T, p->n_max, p->M_max, p->S_max, p->threads, true);
+    if (p->Tc_fwd == 0 || p->Tc_bwd == 0)
+      return fail(SF_ERR_SHAPE, "problem state does not fit the LDS of one workgroup");
+    p->Tc_fwd = p->Tc_bwd = std::min(p->Tc_fwd, p->Tc_bwd);
+    p->lds_fwd = sf::fwd_lds_bytes(nc, T, p->Tc_fwd, p->n_max, p->M_max, p->S_max, p->threads);
+    p->lds_bwd = sf::bwd_lds_bytes(nc, T, p->Tc_bwd, p->n_max, p->M_max, p->S_max, p->threads);
+  }
   const int L = cfg->max_iters, k = cfg->checkpoint_every;
   p->n_ckpt = L > 0 ? (L + k - 1) / k : 0;
   // workspace layout
@@ -385,7 +408,7 @@ int build_plan(const sf_config_t* cfg, int B, const int32_t* n_robots, const int
   p->off_Wdd = take(F * T * nc);
   p->off_fac = take(F * p->fac.size());
   p->off_cxi = take(F * coef);
-  p->off_obs = take(F * 3 * obs);
+  p->off_obs = take(F * (2 * D - 1) * obs);
   p->off_ckpt = take(F * 2 * coef * (size_t)p->n_ckpt);
   p->off_final = take(F * 2 * coef);
   p->off_seg = take(F * 2 * coef * (size_t)k);
@@ -582,7 +605,10 @@ int sf_setup(const sf_config_t* cfg, int32_t n_problems, const int32_t* n_robots
   if ((size_t)lds_max < std::max(p->lds_fwd, p->lds_bwd))
     return fail(SF_ERR_SHAPE, "device LDS per workgroup (" + std::to_string(lds_max) +
                                   ") below the plan's need");
-  SF_HIP_CHECK(sf::prepare_kernels(std::max(p->lds_fwd, p->lds_bwd)));
+  if (p->cfg.n_dim == 3)
+    SF_HIP_CHECK(sf::prepare_kernels3(p->lds_fwd));
+  else
+    SF_HIP_CHECK(sf::prepare_kernels(std::max(p->lds_fwd, p->lds_bwd)));
   p->ws = static_cast<char*>(workspace);
   hipStream_t s = static_cast<hipStream_t>(stream);
   SF_HIP_CHECK(hipMemcpyAsync(p->ws + p->off_desc, p->desc.data(),
@@ -632,10 +658,21 @@ int sf_project(sf_plan_t* plan, void* workspace, const float* xi, const float* x
     return fail(SF_ERR_INVALID_ARG, "n_iters exceeds cfg.max_iters for a saved forward");
   if (xi_out == xi || xi_out == xi0 || lam_out == lam0 || xi_out == lam_out)
     return fail(SF_ERR_INVALID_ARG, "outputs must not alias inputs");
+  const bool dim3 = plan->cfg.n_dim == 3;
+  if (dim3 && (flags & (SF_SAVE_FOR_BACKWARD | SF_PLAIN | SF_UNFUSED)))
+    return fail(SF_ERR_INVALID_ARG,
+                "n_dim = 3 runs the fused forward only (no SF_SAVE_FOR_BACKWARD, SF_PLAIN, "
+                "SF_UNFUSED)");
+  if (dim3 && (plan->exit_every > 0 || plan->moving))
+    return fail(SF_ERR_INVALID_ARG, "n_dim = 3 has no early exit and no obstacle motion");
   hipStream_t s = static_cast<hipStream_t>(stream);
   plan->saved = false;
   sf::FwdArgs a = fwd_args(plan, xi, xi0, lam0, boundary, obstacles, n_iters, save, xi_out,
                            lam_out, residual);
+  auto launch_fused = [&](const sf::FwdArgs& args, int th) {
+    return dim3 ? sf::launch_fwd3(args, th, plan->lds_fwd, s)
+                : sf::launch_fwd_fused(args, th, plan->lds_fwd, s);
+  };
   if (plain) {
     sf::PlainBufs pb{};
     pb.X = plan->at<float>(plan->off_X);
@@ -688,7 +725,7 @@ int sf_project(sf_plan_t* plan, void* workspace, const float* xi, const float* x
       GraphEntry g;
       g.key = key;
       SF_HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      hipError_t le = sf::launch_fwd_fused(a, plan->threads, plan->lds_fwd, s);
+      hipError_t le = launch_fused(a, plan->threads);
       hipError_t ce = hipStreamEndCapture(s, &g.graph);
       SF_HIP_CHECK(le);
       SF_HIP_CHECK(ce);
@@ -703,7 +740,7 @@ int sf_project(sf_plan_t* plan, void* workspace, const float* xi, const float* x
     }
     SF_HIP_CHECK(hipGraphLaunch(hit->exec, s));
   } else {
-    SF_HIP_CHECK(sf::launch_fwd_fused(a, plan->threads, plan->lds_fwd, s));
+    SF_HIP_CHECK(launch_fused(a, plan->threads));
   }
   plan->saved = save;
   plan->saved_L = n_iters;
@@ -798,6 +835,8 @@ int sf_set_early_exit(sf_plan_t* plan, float tol, int32_t check_every) {
   if (!plan) return fail(SF_ERR_INVALID_ARG, "plan is NULL");
   if (check_every < 0) return fail(SF_ERR_INVALID_ARG, "check_every < 0");
   if (!std::isfinite(tol) || tol < 0.f) return fail(SF_ERR_INVALID_ARG, "tol must be finite, >= 0");
+  if (plan->cfg.n_dim == 3 && check_every > 0)
+    return fail(SF_ERR_INVALID_ARG, "n_dim = 3 has no early exit");
   plan->exit_every = check_every;
   plan->exit_tol = tol;
   return SF_OK;
@@ -822,6 +861,8 @@ int sf_set_obstacle_motion(sf_plan_t* plan, void* workspace, const float* displa
   if (!plan) return fail(SF_ERR_INVALID_ARG, "plan is NULL");
   if (workspace != plan->ws)
     return fail(SF_ERR_INVALID_ARG, "workspace differs from the one bound at sf_setup");
+  if (plan->cfg.n_dim == 3 && displacement)
+    return fail(SF_ERR_INVALID_ARG, "n_dim = 3 has no obstacle motion");
   plan->saved = false;   // a saved forward no longer matches the obstacles
   if (!displacement) {
     plan->moving = false;
@@ -841,6 +882,7 @@ int sf_smoothness(const sf_plan_t* plan, const void* workspace, const float* xi,
   if (!plan) return fail(SF_ERR_INVALID_ARG, "plan is NULL");
   if (workspace != plan->ws)
     return fail(SF_ERR_INVALID_ARG, "workspace differs from the one bound at sf_setup");
+  if (plan->cfg.n_dim == 3) return fail(SF_ERR_INVALID_ARG, "sf_smoothness covers n_dim = 2");
   if (!xi || !cost) return fail(SF_ERR_INVALID_ARG, "xi or cost is NULL");
   if (!(t_final > 0.f) || !std::isfinite(t_final))
     return fail(SF_ERR_INVALID_ARG, "t_final must be positive and finite");

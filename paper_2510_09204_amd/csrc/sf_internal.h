@@ -20,10 +20,10 @@ struct ProbDesc {
   int32_t fac;       // index of this problem's factor block
   int32_t pos_off;   // first (robot, step) slot in the plain-path position buffers
   int32_t pad0;
-  float a;           // minimum robot centre distance
-  float pmin[2];
-  float pmax[2];
-  float pad1[3];
+  float a;           // minimum robot centre distance (horizontal in 3D)
+  float pmin[3];     // box per axis (the planar SF reads the first two)
+  float pmax[3];
+  float b;           // 3D: minimum centre distance along z
 };
 static_assert(sizeof(ProbDesc) == 64, "descriptor layout");
 
@@ -124,6 +124,13 @@ size_t plain_part_floats(int T, int64_t coef);
 
 // Raise the dynamic-LDS limit of the fused kernels to `lds` bytes.
 hipError_t prepare_kernels(size_t lds);
+
+// 3D (spheroid) forward (sf_kernels3d.hip): one workgroup per problem; the
+// coefficient arrays hold [3][n][nc] per problem, boundary [n][2][3],
+// obstacles [M][5] = x, y, z, a_o, b_o.  Tc: time steps held in LDS at once.
+size_t fwd3_lds_bytes(int nc, int T, int Tc, int n_max, int M_max, int S_max);
+hipError_t prepare_kernels3(size_t lds);
+hipError_t launch_fwd3(const FwdArgs& a, int threads, size_t lds, hipStream_t s);
 
 // Candidate selection (sf_select.hip).  Batches of at most kSelectMaxBatch
 // candidates (the ranking keys live in LDS).

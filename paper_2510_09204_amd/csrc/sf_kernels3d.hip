@@ -1,0 +1,372 @@
+// 3D (spheroid) SF forward: one workgroup per problem, the problem's state in
+// LDS for all L iterations.
+//
+// Robots are axis-aligned spheroids (a/2, a/2, b/2) and obstacles spheroids
+// (a_o, a_o, b_o) inflated by the robot (problem formulation; Appendix eqs.
+// inter_robot_polar, workspace_polar).  The alpha, beta and d steps (eqs.
+// alpha_step, beta_step, d_step) with beta = atan2(rho_xy / a, dz / b) put e
+// on the ray of Delta: with s^2 = (dx^2 + dy^2)/a^2 + dz^2/b^2, e = Delta for
+// s >= 1 and e = Delta / s inside, so r_1 = (1 - 1/s) Delta there (and at
+// Delta = 0, alpha = beta = 0 gives e = (0, 0, b)).  The xi_bar step is the
+// planar one applied per axis: F, G and A are block diagonal over the three
+// axes with identical blocks, so the planar (n, M) factor block serves each
+// axis.
+//
+// One iteration, in time chunks of Tc steps held in LDS:
+//   positions X = W xi_bar                       [3][n][Tc]
+//   V = F^T r_1 + G^T r_2 per (robot, step)      [3][n][Tc] (every pair visited)
+//   R += W^T V
+// then lambda' = lambda - rho R, u = lambda - 2 rho R and the mode-form
+// xi_bar' = c_xi + S u + SH xi_bar (S, SH: perpendicular block per robot plus
+// the parallel-minus-perpendicular block on the robot mean).
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+
+#include "sf_internal.h"
+
+namespace sf {
+namespace {
+
+constexpr int kRed3 = 64;          // block-reduction scratch (3 values x 16 waves)
+constexpr int kObsFloats = 8;      // x, y, z, 1/a_o^2, 1/b_o^2, b_o, pad, pad
+
+__host__ __device__ inline int r4(int x) { return (x + 3) & ~3; }
+
+__device__ __forceinline__ float wave_sum3(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sums of v[0..2] over the block, returned to every thread.
+template <int NT>
+__device__ __forceinline__ void block_sum3(float (&v)[3], float* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int NW = NT >> 6;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) v[q] = wave_sum3(v[q]);
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) red[q * NW + wave] = v[q];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    float s = 0.f;
+    for (int w = 0; w < NW; ++w) s += red[q * NW + w];
+    v[q] = s;
+  }
+  __syncthreads();
+}
+
+// r_1 of one spheroid pair row: Delta (dx, dy, dz), ia2 = 1/a^2, ib2 = 1/b^2;
+// `tie` is the z value of r_1 at Delta = 0 (-b for the row's own orientation).
+// Adds r_1 to (vx, vy, vz) and |r_1|^2 to sq.  Inactive rows add nothing.
+__device__ __forceinline__ void spheroid_residual(float dx, float dy, float dz, float ia2,
+                                                  float ib2, float tie, float& vx, float& vy,
+                                                  float& vz, float& sq) {
+  const float s2 = fmaf(dz * dz, ib2, fmaf(dx, dx, dy * dy) * ia2);
+  if (s2 < 1.f) {
+    float rx, ry, rz;
+    if (s2 > 0.f) {
+      const float f = 1.f - __builtin_amdgcn_rsqf(s2);
+      rx = f * dx;
+      ry = f * dy;
+      rz = f * dz;
+    } else {
+      rx = 0.f;
+      ry = 0.f;
+      rz = tie;
+    }
+    vx += rx;
+    vy += ry;
+    vz += rz;
+    sq = fmaf(rx, rx, fmaf(ry, ry, fmaf(rz, rz, sq)));
+  }
+}
+
+struct Lds3 {
+  float *W, *fac, *xb[2], *lam, *cxi, *R, *means, *obs, *X, *V, *red;
+};
+
+__device__ __forceinline__ Lds3 carve3(float* p, int nc, int Tc, int n_max, int M_max,
+                                       int S_max) {
+  Lds3 L;
+  L.W = p; p += r4(Tc * nc);
+  L.fac = p; p += r4(fac_stride(nc));
+  L.xb[0] = p; p += r4(S_max);
+  L.xb[1] = p; p += r4(S_max);
+  L.lam = p; p += r4(S_max);
+  L.cxi = p; p += r4(S_max);
+  L.R = p; p += r4(S_max);
+  L.means = p; p += 6 * kMaxCoef + 8;
+  L.obs = p; p += kObsFloats * M_max;
+  L.red = p; p += kRed3;
+  L.X = p; p += 3 * n_max * Tc;
+  L.V = p;
+  return L;
+}
+
+// One pass over the horizon at xi_bar = xb: positions X, constraint sums V
+// and (unless `final`) R = W^T V; with `final` the residual sums instead.
+template <int NT>
+__device__ __forceinline__ void sweep3(const FwdArgs& A, const ProbDesc& P, const Lds3& L,
+                                       const float* xb, bool final, float& r1sq, float& r2sq) {
+  const int n = P.n, M = P.M, nc = A.nc, T = A.T, Tc = A.Tc, tid = threadIdx.x;
+  const int S = 3 * n * nc;
+  const bool chunked = Tc < T;
+  const float ia2 = 1.f / (P.a * P.a), ib2 = 1.f / (P.b * P.b);
+  for (int k0 = 0; k0 < T; k0 += Tc) {
+    const int Tce = min(Tc, T - k0);
+    if (chunked) {
+      for (int t = tid; t < Tce * nc; t += NT) L.W[t] = A.W[k0 * nc + t];
+      __syncthreads();
+    }
+    const float* Wc = chunked ? L.W : L.W + k0 * nc;
+    // positions
+    for (int t = tid; t < 3 * n * Tce; t += NT) {
+      const int row = t / Tce, kk = t - row * Tce;   // row = ax * n + i
+      const float* x = xb + row * nc;
+      const float* w = Wc + kk * nc;
+      float s = 0.f;
+      for (int c = 0; c < nc; ++c) s = fmaf(w[c], x[c], s);
+      L.X[row * Tce + kk] = s;
+    }
+    __syncthreads();
+    // constraint rows (every robot pair, every obstacle, the box)
+    const int plane = n * Tce;
+    for (int t = tid; t < plane; t += NT) {
+      const int i = t / Tce, kk = t - i * Tce;
+      const float px = L.X[t], py = L.X[plane + t], pz = L.X[2 * plane + t];
+      float vx = 0.f, vy = 0.f, vz = 0.f, sq = 0.f, sq_half = 0.f;
+      for (int j = 0; j < n; ++j) {
+        if (j == i) continue;
+        const int u = j * Tce + kk;
+        float s1 = 0.f;
+        spheroid_residual(px - L.X[u], py - L.X[plane + u], pz - L.X[2 * plane + u], ia2,
+                          ib2, i < j ? -P.b : P.b, vx, vy, vz, s1);
+        if (j > i) sq_half += s1;      // each unordered pair once
+      }
+      for (int m = 0; m < M; ++m) {
+        const float* o = L.obs + m * kObsFloats;
+        spheroid_residual(px - o[0], py - o[1], pz - o[2], o[3], o[4], -o[5], vx, vy, vz,
+                          sq);
+      }
+      const float hx = fmaxf(px - P.pmax[0], 0.f), lx = fmaxf(P.pmin[0] - px, 0.f);
+      const float hy = fmaxf(py - P.pmax[1], 0.f), ly = fmaxf(P.pmin[1] - py, 0.f);
+      const float hz = fmaxf(pz - P.pmax[2], 0.f), lz = fmaxf(P.pmin[2] - pz, 0.f);
+      if (final) {
+        r1sq += sq + sq_half;
+        r2sq += hx * hx + lx * lx + hy * hy + ly * ly + hz * hz + lz * lz;
+      } else {
+        L.V[t] = vx + (hx - lx);
+        L.V[plane + t] = vy + (hy - ly);
+        L.V[2 * plane + t] = vz + (hz - lz);
+      }
+    }
+    __syncthreads();
+    if (!final) {
+      // R (+)= W^T V over this chunk's steps
+      for (int t = tid; t < S; t += NT) {
+        const int row = t / nc, c = t - row * nc;
+        const float* v = L.V + row * Tce;
+        float s = 0.f;
+        for (int kk = 0; kk < Tce; ++kk) s = fmaf(Wc[kk * nc + c], v[kk], s);
+        L.R[t] = k0 == 0 ? s : L.R[t] + s;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void fwd3_kernel(FwdArgs A) {
+  extern __shared__ float lds3[];
+  const int b = A.order[blockIdx.x];
+  const ProbDesc P = A.probs[b];
+  const int n = P.n, M = P.M, nc = A.nc, T = A.T, Tc = A.Tc, tid = threadIdx.x;
+  const int nn = n * nc, S = 3 * nn, nc2 = nc * nc;
+  const Lds3 L = carve3(lds3, nc, Tc, A.n_max, A.M_max, A.S_max);
+  const float rho = A.rho;
+  const float* bnd = A.boundary + (size_t)P.rob_off * 6;
+  const bool chunked = Tc < T;
+
+  // --- set-up: factor block, W (whole table when unchunked), obstacles, state
+  const float* facg = A.fac + (size_t)P.fac * fac_stride(nc);
+  for (int t = tid; t < fac_stride(nc); t += NT) L.fac[t] = facg[t];
+  if (!chunked)
+    for (int t = tid; t < T * nc; t += NT) L.W[t] = A.W[t];
+  for (int m = tid; m < M; m += NT) {
+    const float* o = A.obstacles + (size_t)(P.obs_off + m) * 5;
+    float* d = L.obs + m * kObsFloats;
+    d[0] = o[0];
+    d[1] = o[1];
+    d[2] = o[2];
+    d[3] = 1.f / (o[3] * o[3]);
+    d[4] = 1.f / (o[4] * o[4]);
+    d[5] = o[4];
+  }
+  for (int t = tid; t < S; t += NT) {
+    L.xb[0][t] = A.xi0[P.coef_off + t];
+    L.lam[t] = A.lam0[P.coef_off + t];
+    L.R[t] = A.xi[P.coef_off + t];      // the target, until c_xi is formed
+  }
+  __syncthreads();
+  // robot means of the target ([3][nc]) and of the boundary ([3][2])
+  for (int t = tid; t < 3 * nc + 6; t += NT) {
+    float s = 0.f;
+    if (t < 3 * nc) {
+      const int ax = t / nc, c = t - ax * nc;
+      for (int i = 0; i < n; ++i) s += L.R[ax * nn + i * nc + c];
+    } else {
+      const int q = t - 3 * nc, ax = q >> 1, e = q & 1;
+      for (int i = 0; i < n; ++i) s += bnd[i * 6 + e * 3 + ax];
+    }
+    L.means[t] = s / (float)n;
+  }
+  __syncthreads();
+  {
+    const float* Np = L.fac + 4 * nc2;
+    const float* DN = Np + 2 * nc;
+    const float* bm = L.means + 3 * nc;
+    for (int t = tid; t < S; t += NT) {
+      const int ax = t / nn, rem = t - ax * nn, i = rem / nc, c = rem - i * nc;
+      const float* Sp = L.fac + c * nc;
+      const float* DS = L.fac + nc2 + c * nc;
+      const float* y = L.R + ax * nn + i * nc;
+      const float* ym = L.means + ax * nc;
+      float out = 0.f;
+      for (int q = 0; q < nc; ++q) out = fmaf(Sp[q], y[q], fmaf(DS[q], ym[q], out));
+      for (int e = 0; e < 2; ++e) {
+        out = fmaf(Np[c * 2 + e], bnd[i * 6 + e * 3 + ax], out);
+        out = fmaf(DN[c * 2 + e], bm[ax * 2 + e], out);
+      }
+      L.cxi[t] = out;
+    }
+  }
+  __syncthreads();
+
+  // ping-pong by pointer swap (an index into L.xb would put L in scratch)
+  float* xcur = L.xb[0];
+  float* xnext = L.xb[1];
+  float dzsq = 0.f;
+  for (int l = 0; l < A.L; ++l) {
+    const bool last = l == A.L - 1;
+    float z0 = 0.f, z1 = 0.f;
+    sweep3<NT>(A, P, L, xcur, false, z0, z1);
+    // lambda step and u = lambda - 2 rho R (u replaces R)
+    for (int t = tid; t < S; t += NT) {
+      const float r = L.R[t], lm = L.lam[t];
+      L.lam[t] = fmaf(-rho, r, lm);
+      L.R[t] = fmaf(-2.f * rho, r, lm);
+      if (last) dzsq = fmaf(rho * r, rho * r, dzsq);
+    }
+    __syncthreads();
+    // robot means of u and xb: means[0..3nc) and means[3nc..6nc)
+    for (int t = tid; t < 6 * nc; t += NT) {
+      const int which = t / (3 * nc), q = t - which * 3 * nc, ax = q / nc, c = q - ax * nc;
+      const float* src = (which ? xcur : L.R) + ax * nn + c;
+      float s = 0.f;
+      for (int i = 0; i < n; ++i) s += src[i * nc];
+      L.means[t] = s / (float)n;
+    }
+    __syncthreads();
+    // xi_bar step
+    {
+      const float* xb = xcur;
+      float* xn = xnext;
+      for (int t = tid; t < S; t += NT) {
+        const int ax = t / nn, rem = t - ax * nn, i = rem / nc, c = rem - i * nc;
+        const float* Sp = L.fac + c * nc;
+        const float* DS = Sp + nc2;
+        const float* SH = Sp + 2 * nc2;
+        const float* DSH = Sp + 3 * nc2;
+        const float* u = L.R + ax * nn + i * nc;
+        const float* x = xb + ax * nn + i * nc;
+        const float* um = L.means + ax * nc;
+        const float* xm = L.means + 3 * nc + ax * nc;
+        float v = L.cxi[t];
+        for (int q = 0; q < nc; ++q) {
+          v = fmaf(Sp[q], u[q], v);
+          v = fmaf(DS[q], um[q], v);
+          v = fmaf(SH[q], x[q], v);
+          v = fmaf(DSH[q], xm[q], v);
+        }
+        xn[t] = v;
+        if (last) {
+          const float d = v - xb[t];
+          dzsq = fmaf(d, d, dzsq);
+        }
+      }
+    }
+    __syncthreads();
+    float* tmp = xcur;
+    xcur = xnext;
+    xnext = tmp;
+  }
+
+  // residual of the returned iterate, outputs, status
+  float v[3] = {0.f, 0.f, 0.f};
+  sweep3<NT>(A, P, L, xcur, true, v[0], v[1]);
+  float bad = 0.f;
+  for (int t = tid; t < S; t += NT) {
+    const float x = xcur[t], lm = L.lam[t];
+    A.xi_out[P.coef_off + t] = x;
+    A.lam_out[P.coef_off + t] = lm;
+    if (!isfinite(x) || !isfinite(lm)) bad = 1.f;
+  }
+  v[2] = bad;
+  block_sum3<NT>(v, L.red);
+  float dz[3] = {dzsq, 0.f, 0.f};
+  block_sum3<NT>(dz, L.red);
+  if (tid == 0) {
+    A.ws_iters[b] = A.L;
+    float* res = A.residual + (size_t)b * 4;
+    res[0] = sqrtf(v[0]);
+    res[1] = sqrtf(v[1]);
+    res[2] = A.L > 0 ? sqrtf(dz[0]) : 0.f;
+    res[3] = (v[2] > 0.f || !isfinite(v[0]) || !isfinite(v[1])) ? 1.f : 0.f;
+  }
+}
+
+}  // namespace
+
+size_t fwd3_lds_bytes(int nc, int T, int Tc, int n_max, int M_max, int S_max) {
+  (void)T;
+  const size_t f = (size_t)r4(Tc * nc) + r4(fac_stride(nc)) + 5 * (size_t)r4(S_max) +
+                   6 * kMaxCoef + 8 + (size_t)kObsFloats * M_max + kRed3 +
+                   6 * (size_t)n_max * Tc;
+  return f * sizeof(float);
+}
+
+hipError_t prepare_kernels3(size_t lds) {
+  const void* fns[] = {reinterpret_cast<const void*>(&fwd3_kernel<256>),
+                       reinterpret_cast<const void*>(&fwd3_kernel<512>),
+                       reinterpret_cast<const void*>(&fwd3_kernel<1024>)};
+  for (const void* f : fns) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_fwd3(const FwdArgs& a, int threads, size_t lds, hipStream_t s) {
+  dim3 grid(a.B);
+  switch (threads) {
+    case 256:
+      hipLaunchKernelGGL(fwd3_kernel<256>, grid, dim3(256), lds, s, a);
+      break;
+    case 512:
+      hipLaunchKernelGGL(fwd3_kernel<512>, grid, dim3(512), lds, s, a);
+      break;
+    case 1024:
+      hipLaunchKernelGGL(fwd3_kernel<1024>, grid, dim3(1024), lds, s, a);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace sf

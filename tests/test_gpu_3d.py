@@ -1,0 +1,176 @@
+"""The 3D (spheroid) SF forward (sf_setup with n_dim = 3, sf_project through
+the C ABI) against the FP64 oracle with dim=3 on the same float32 inputs."""
+import numpy as np
+import pytest
+
+from oracle import SFOracle
+from sf_testlib import REL_TOL, RES_REL_TOL, RES_TOL, rel_err
+from workloads import WORKLOADS, make_batch, pack, unpack_coefs
+from workloads.gen3d import WORKLOADS_3D, make_batch3d, pack3d, scaled3d, unpack3d
+
+pytestmark = pytest.mark.gpu
+RHO = 0.5
+
+
+def _inputs3d(pk, probs):
+    xi = unpack3d(pk.xi.astype(np.float64), probs)
+    xi0 = unpack3d(pk.xi0.astype(np.float64), probs)
+    lam0 = unpack3d(pk.lam0.astype(np.float64), probs)
+    out, r, o = [], 0, 0
+    for b, p in enumerate(probs):
+        out.append(dict(
+            n=p.n, M=p.M, n_coef=p.n_coef, n_steps=p.n_steps,
+            a=float(pk.robot_ab[b, 0]), b=float(pk.robot_ab[b, 1]),
+            box=pk.box[b].astype(np.float64),
+            obstacles=pk.obstacles[o * 5:(o + p.M) * 5].astype(np.float64).reshape(p.M, 5),
+            boundary=pk.boundary[r * 6:(r + p.n) * 6].astype(np.float64).reshape(p.n, 2, 3),
+            xi=xi[b], xi0=xi0[b], lam0=lam0[b]))
+        r += p.n
+        o += p.M
+    return out
+
+
+def _oracle(inp, objective="projection"):
+    return SFOracle(inp["n"], inp["M"], inp["n_coef"], inp["n_steps"], RHO, inp["a"],
+                    inp["box"], inp["obstacles"], inp["boundary"], dim=3, robot_b=inp["b"],
+                    objective=objective)
+
+
+def _plan(pk, threads=0, objective=0):
+    from paper_2510_09204_amd import SFPlan
+    return SFPlan(pk.n_robots, pk.n_obs, pk.robot_ab, pk.box, pk.n_coef, pk.n_steps, RHO,
+                  threads=threads, n_dim=3, objective=objective)
+
+
+def _run(probs, L, threads=0, objective=0):
+    import torch
+    pk = pack3d(probs)
+    plan = _plan(pk, threads, objective)
+    t = {k: torch.from_numpy(getattr(pk, k)).cuda() for k in ("xi", "xi0", "lam0",
+                                                               "boundary", "obstacles")}
+    xi = None if objective else t["xi"]
+    xo, lo, res = plan.project(xi, t["xi0"], t["lam0"], t["boundary"],
+                               t["obstacles"] if pk.obstacles.size else None, L)
+    torch.cuda.synchronize()
+    return pk, xo.cpu().numpy(), lo.cpu().numpy(), res.cpu().numpy(), plan, t
+
+
+def _compare(probs, L, objective="projection", **kw):
+    pk, xo, lo, res = _run(probs, L, objective=0 if objective == "projection" else 1, **kw)[:4]
+    gx, gl = unpack3d(xo, probs), unpack3d(lo, probs)
+    for b, inp in enumerate(_inputs3d(pk, probs)):
+        xi = inp["xi"] if objective == "projection" else np.zeros_like(inp["xi"])
+        ref = _oracle(inp, objective).solve(xi, inp["xi0"], inp["lam0"], L)
+        assert res[b, 3] == 0.0
+        e = rel_err(gx[b], ref.xi_bar)
+        assert e <= REL_TOL, (b, e)
+        scale = max(np.linalg.norm(ref.lam), np.linalg.norm(ref.xi_bar))
+        assert np.linalg.norm(gl[b] - ref.lam) / scale <= REL_TOL, b
+        got = np.hypot(res[b, 0], res[b, 1])
+        assert abs(got - ref.residual) <= RES_TOL + RES_REL_TOL * ref.residual, \
+            (b, got, ref.residual)
+    return pk, xo, lo, res
+
+
+@pytest.mark.parametrize("cfg_id,batch,L", [(16, 3, 60), (48, 6, 40), (32, 2, 40)])
+def test_3d_matches_oracle(gpu, cfg_id, batch, L):
+    _compare(make_batch3d(WORKLOADS_3D[cfg_id], batch=batch), L)
+
+
+def test_3d_chunked_horizon_matches_oracle(gpu):
+    """64 robots, 15 coefficients, 120 steps: the horizon runs in two LDS time
+    chunks."""
+    cfg = scaled3d(WORKLOADS_3D[32], n_robots=(64, 64), n_obs=(30, 30), side=16.0,
+                   height=8.0, n_coef=15, n_steps=120)
+    _compare(make_batch3d(cfg, batch=1), 12)
+
+
+def test_3d_single_robot_without_obstacles_and_zero_iterations(gpu):
+    cfg = scaled3d(WORKLOADS_3D[16], n_robots=(1, 1), n_obs=(0, 0), side=2.0, height=1.0)
+    probs = make_batch3d(cfg, batch=2)
+    _compare(probs, 25)
+    pk, xo, lo, res = _run(probs, 0)[:4]
+    np.testing.assert_array_equal(xo, pk.xi0)
+    np.testing.assert_array_equal(lo, pk.lam0)
+    assert np.all(res[:, 2] == 0.0)
+
+
+def test_3d_accel_objective_matches_oracle(gpu):
+    _compare(make_batch3d(WORKLOADS_3D[16], batch=2), 40, objective="accel")
+
+
+def test_3d_threads_and_graph_give_the_same_bits(gpu):
+    """Each output entry is summed in a fixed order whatever the block size;
+    graph replays (eager work between them) repeat the eager bits."""
+    import torch
+    probs = make_batch3d(WORKLOADS_3D[48], batch=5)
+    base = _run(probs, 30, threads=512)
+    for th in (256, 1024):
+        got = _run(probs, 30, threads=th)
+        np.testing.assert_array_equal(got[1], base[1])
+        np.testing.assert_array_equal(got[2], base[2])
+    plan, t = base[4], base[5]
+    outs = (torch.empty_like(t["xi"]), torch.empty_like(t["xi"]),
+            torch.empty((len(probs), 4), device=t["xi"].device))
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    for rep in range(3):
+        with torch.cuda.stream(side):
+            outs[0].fill_(float("nan"))
+            plan.project(t["xi"], t["xi0"], t["lam0"], t["boundary"], t["obstacles"], 30,
+                         graph=True, out=outs)
+        side.synchronize()
+        _ = (t["xi"] * 2.0).sum().item()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(outs[0].cpu().numpy(), base[1])
+        np.testing.assert_array_equal(outs[2].cpu().numpy(), base[3])
+
+
+def test_3d_flat_problem_matches_the_planar_gpu_path(gpu):
+    """A 3D problem with every z value 0 is the planar problem: its x, y
+    coefficients match the planar fused kernel's within float32 rounding."""
+    import torch
+    from sf_testlib import gpu_forward
+    probs = make_batch(WORKLOADS[3], batch=2)
+    pk2 = pack(probs)
+    x2 = unpack_coefs(gpu_forward(probs, RHO, 50)["xi"], probs)
+    from paper_2510_09204_amd import SFPlan
+    B = len(probs)
+    ab = np.stack([pk2.robot_a, np.full(B, 0.5, np.float32)], axis=1)
+    box = np.concatenate([pk2.box, np.array([[[-1.0], [1.0]]] * B, np.float32)], axis=2)
+    xi3 = np.concatenate([np.concatenate([p.xi.astype(np.float32), np.zeros((1, p.n, p.n_coef),
+                                          np.float32)]).ravel() for p in probs])
+    bnd3 = np.concatenate([np.concatenate([p.boundary.astype(np.float32),
+                                           np.zeros((p.n, 2, 1), np.float32)], axis=2).ravel()
+                           for p in probs])
+    obs3 = np.concatenate([np.column_stack([p.obstacles[:, :2], np.zeros(p.M), p.obstacles[:, 2],
+                                            np.full(p.M, 0.6)]).astype(np.float32).ravel()
+                           for p in probs])
+    plan = SFPlan(pk2.n_robots, pk2.n_obs, ab, box, pk2.n_coef, pk2.n_steps, RHO, n_dim=3)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    xo, _, res = plan.project(dev(xi3), dev(xi3), dev(np.zeros_like(xi3)), dev(bnd3), dev(obs3),
+                              50)
+    torch.cuda.synchronize()
+    x3 = unpack3d(xo.cpu().numpy(), [type("P", (), dict(n=p.n, n_coef=p.n_coef))
+                                     for p in probs])
+    for b in range(B):
+        assert rel_err(x3[b][:2], x2[b]) <= 2e-5, b
+        assert np.max(np.abs(x3[b][2])) <= 1e-6
+
+
+def test_3d_unsupported_calls_fail_loudly(gpu):
+    import torch
+    from paper_2510_09204_amd import SFError
+    probs = make_batch3d(WORKLOADS_3D[16], batch=1)
+    pk = pack3d(probs)
+    plan = _plan(pk)
+    t = {k: torch.from_numpy(getattr(pk, k)).cuda() for k in ("xi", "xi0", "lam0",
+                                                               "boundary", "obstacles")}
+    args = (t["xi"], t["xi0"], t["lam0"], t["boundary"], t["obstacles"], 5)
+    for kw in (dict(save=True), dict(plain=True), dict(unfused=True)):
+        with pytest.raises(SFError):
+            plan.project(*args, **kw)
+    with pytest.raises(SFError):
+        plan.set_early_exit(1e-3, 10)
+    with pytest.raises(SFError):
+        plan.backward(t["xi0"], None, None)

@@ -73,7 +73,7 @@ def test_workspace_size_for_uneven_batch(lib):
 
 
 @pytest.mark.parametrize("kw,code", [
-    (dict(n_dim=3), -2), (dict(n_coef=1), -2), (dict(n_coef=33), -2), (dict(n_steps=1), -2),
+    (dict(n_dim=4), -2), (dict(n_dim=1), -2), (dict(n_coef=1), -2), (dict(n_coef=33), -2), (dict(n_steps=1), -2),
     (dict(rho=0.0), -1), (dict(rho=float("nan")), -1), (dict(threads=300), -1),
     (dict(checkpoint_every=0), -1), (dict(max_iters=-1), -1)])
 def test_invalid_config_is_rejected(lib, kw, code):
@@ -88,6 +88,32 @@ def test_invalid_config_is_rejected(lib, kw, code):
 def test_invalid_problem_is_rejected(lib, n, M, a, box, code):
     rc, _, detail = _setup(lib, _cfg(), n, M, a, box)
     assert rc == code and detail
+
+
+BOX3 = [[[-5.8, -5.8, -2.7], [5.8, 5.8, 2.7]]]
+
+
+def test_3d_workspace_size_query(lib):
+    """n_dim = 3: robot sizes (a, b) per problem, box [2][3]; coefficient
+    arrays hold three axes."""
+    rc, nbytes, detail = _setup(lib, _cfg(n_dim=3, max_iters=0), [32], [20], [[0.4, 0.6]], BOX3)
+    assert rc == 0, detail
+    assert nbytes >= 4 * 3 * 32 * 11 * 5          # coefficient-sized areas of three axes
+
+
+@pytest.mark.parametrize("a,box,code", [
+    ([[0.4, 0.0]], BOX3, -1), ([[0.4, float("inf")]], BOX3, -1),
+    ([[0.4, 0.6]], [[[-1.0, -1.0, 1.0], [1.0, 1.0, -1.0]]], -1),
+    ([[0.4, 0.6]], [[[-1.0, -1.0, float("nan")], [1.0, 1.0, 1.0]]], -6)])
+def test_invalid_3d_problem_is_rejected(lib, a, box, code):
+    rc, _, detail = _setup(lib, _cfg(n_dim=3), [4], [3], a, box)
+    assert rc == code and detail
+
+
+def test_3d_state_too_large_for_lds_is_a_shape_error(lib):
+    rc, _, detail = _setup(lib, _cfg(n_dim=3, n_coef=32, n_steps=100), [512], [0],
+                           [[0.3, 0.3]], BOX3)
+    assert rc == -2 and "LDS" in detail
 
 
 def test_state_too_large_for_lds_is_a_shape_error(lib):
