@@ -34,9 +34,9 @@
  * dx cos(alpha) + dy sin(alpha) (the printed dx / (a cos(alpha)) where that is
  * defined), and d as the exact minimiser over d >= 1; together they put e on
  * the ray of Delta.  Only sf_project without SF_SAVE_FOR_BACKWARD, SF_PLAIN and
- * SF_UNFUSED runs for n_dim = 3 (SF_GRAPH works); sf_project_backward,
- * early exit, obstacle motion and sf_smoothness return SF_ERR_INVALID_ARG or
- * SF_ERR_NOT_SAVED.  Each workgroup visits every robot pair.
+ * SF_UNFUSED runs for n_dim = 3 (SF_GRAPH and obstacle motion work);
+ * sf_project_backward, early exit and sf_smoothness return SF_ERR_INVALID_ARG
+ * or SF_ERR_NOT_SAVED.  Each workgroup visits every robot pair.
  *
  * Ownership: the caller allocates every array and the workspace; the library
  * owns only the host-side plan.  Calls never retain caller pointers (the
@@ -225,8 +225,8 @@ int sf_project_iterations(const sf_plan_t* plan, const void* workspace, int32_t*
  * Moving obstacles (the dynamic-obstacle scenarios of the paper's evaluation,
  * where obstacles come with their velocity): obstacle m's centre at
  * tau = k / (T - 1) is c_m + d_m tau, with d_m the displacement over the
- * horizon (velocity times its duration).  displacement: device float[sum M][2]
- * in the obstacles' order, copied into the workspace (asynchronously on
+ * horizon (velocity times its duration).  displacement: device
+ * float[sum M][n_dim] in the obstacles' order, copied into the workspace (asynchronously on
  * stream); NULL makes every obstacle static again (the default).  It applies
  * to later sf_project calls and invalidates a saved forward.  The constraint
  * stage, the candidate lists (per-window obstacle boxes) and the adjoint use

@@ -177,13 +177,14 @@ class SFPlan:
 
     def set_obstacle_motion(self, displacement: Optional[torch.Tensor]) -> None:
         """sf_set_obstacle_motion: obstacle centres move as c + d tau (d:
-        float32 [sum M][2] on the device, the displacement over the horizon);
-        None makes them static again."""
-        if displacement is not None and (displacement.numel() != 2 * self.n_obs_total
+        float32 [sum M][n_dim] on the device, the displacement over the
+        horizon); None makes them static again."""
+        if displacement is not None and (displacement.numel() != self.n_dim * self.n_obs_total
                                          or displacement.dtype != torch.float32
                                          or not displacement.is_contiguous()
                                          or displacement.device != self.device):
-            raise SFError(-2, "displacement must be contiguous float32 [sum M][2] on device")
+            raise SFError(-2, f"displacement must be contiguous float32 [sum M][{self.n_dim}] "
+                              "on device")
         _check(self.lib, self.lib.sf_set_obstacle_motion(
             self._plan, ctypes.c_void_p(self.workspace.data_ptr()), _ptr(displacement),
             self._stream()))

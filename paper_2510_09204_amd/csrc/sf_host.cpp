@@ -366,8 +366,10 @@ int build_plan(const sf_config_t* cfg, int B, const int32_t* n_robots, const int
   p->tune_fwd = p->tune_bwd = (cfg->threads == 0);
   if (D == 3) {
     // 3D: the forward kernel of sf_kernels3d.hip, the longest time chunk that
-    // fits in LDS (balanced), fixed threads (no autotuning)
+    // fits in LDS (balanced); 1024 threads unless set (measured fastest on
+    // 16 and 32 robots: 15 / 40 us per iteration against 20 / 50 at 512)
     p->tune_fwd = p->tune_bwd = false;
+    if (cfg->threads == 0) p->threads = p->threads_bwd = 1024;
     int best = 0;
     for (int tc = T; tc >= 1; --tc)
       if (sf::fwd3_lds_bytes(nc, T, tc, p->n_max, p->M_max, p->S_max) <= kLdsBudget) {
@@ -423,7 +425,7 @@ int build_plan(const sf_config_t* cfg, int B, const int32_t* n_robots, const int
   p->off_part = take(F * sf::plain_part_floats(T, coef));
   p->off_iters = take(sizeof(int32_t) * B);
   p->off_zero = take(F * coef);   // the target read by the acceleration objective
-  p->off_ovel = take(F * 2 * obs);  // obstacle displacements
+  p->off_ovel = take(F * D * obs);  // obstacle displacements
   p->total = off;
   out = std::move(p);
   return SF_OK;
@@ -663,8 +665,8 @@ int sf_project(sf_plan_t* plan, void* workspace, const float* xi, const float* x
     return fail(SF_ERR_INVALID_ARG,
                 "n_dim = 3 runs the fused forward only (no SF_SAVE_FOR_BACKWARD, SF_PLAIN, "
                 "SF_UNFUSED)");
-  if (dim3 && (plan->exit_every > 0 || plan->moving))
-    return fail(SF_ERR_INVALID_ARG, "n_dim = 3 has no early exit and no obstacle motion");
+  if (dim3 && plan->exit_every > 0)
+    return fail(SF_ERR_INVALID_ARG, "n_dim = 3 has no early exit");
   hipStream_t s = static_cast<hipStream_t>(stream);
   plan->saved = false;
   sf::FwdArgs a = fwd_args(plan, xi, xi0, lam0, boundary, obstacles, n_iters, save, xi_out,
@@ -861,8 +863,6 @@ int sf_set_obstacle_motion(sf_plan_t* plan, void* workspace, const float* displa
   if (!plan) return fail(SF_ERR_INVALID_ARG, "plan is NULL");
   if (workspace != plan->ws)
     return fail(SF_ERR_INVALID_ARG, "workspace differs from the one bound at sf_setup");
-  if (plan->cfg.n_dim == 3 && displacement)
-    return fail(SF_ERR_INVALID_ARG, "n_dim = 3 has no obstacle motion");
   plan->saved = false;   // a saved forward no longer matches the obstacles
   if (!displacement) {
     plan->moving = false;
@@ -870,7 +870,7 @@ int sf_set_obstacle_motion(sf_plan_t* plan, void* workspace, const float* displa
   }
   if (plan->obs_total > 0)
     SF_HIP_CHECK(hipMemcpyAsync(plan->ws + plan->off_ovel, displacement,
-                                sizeof(float) * 2 * (size_t)plan->obs_total,
+                                sizeof(float) * plan->cfg.n_dim * (size_t)plan->obs_total,
                                 hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)));
   plan->moving = plan->obs_total > 0;
   return SF_OK;

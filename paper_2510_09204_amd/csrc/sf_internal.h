@@ -42,7 +42,7 @@ struct FwdArgs {
   const float* lam0;
   const float* boundary;
   const float* obstacles;
-  const float* ovel;      // obstacle displacements [sum M][2] over the horizon, or null (static)
+  const float* ovel;      // obstacle displacements [sum M][n_dim] over the horizon, or null (static)
   float* xi_out;
   float* lam_out;
   float* residual;        // [B][4]

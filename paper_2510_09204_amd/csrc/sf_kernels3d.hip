@@ -29,7 +29,7 @@ namespace sf {
 namespace {
 
 constexpr int kRed3 = 64;          // block-reduction scratch (3 values x 16 waves)
-constexpr int kObsFloats = 8;      // x, y, z, 1/a_o^2, 1/b_o^2, b_o, pad, pad
+constexpr int kObsFloats = 12;     // x, y, z, 1/a_o^2, 1/b_o^2, b_o, dx, dy, dz, pad x3
 
 __host__ __device__ inline int r4(int x) { return (x + 3) & ~3; }
 
@@ -60,29 +60,28 @@ __device__ __forceinline__ void block_sum3(float (&v)[3], float* red) {
   __syncthreads();
 }
 
-// r_1 of one spheroid pair row: Delta (dx, dy, dz), ia2 = 1/a^2, ib2 = 1/b^2;
-// `tie` is the z value of r_1 at Delta = 0 (-b for the row's own orientation).
-// Adds r_1 to (vx, vy, vz) and |r_1|^2 to sq.  Inactive rows add nothing.
+// r_1 of one spheroid row: Delta (dx, dy, dz), ia2 = 1/a^2, ib2 = 1/b^2;
+// `tie` is the z value of r_1 at Delta = 0 (-b for the row's own
+// orientation); rows with `live` false (a robot against itself) add nothing.
+// Adds r_1 to (vx, vy, vz) and, with SQ, |r_1|^2 to sq.  Active rows (s < 1)
+// are rare, so the residual sits behind a branch that a wave skips when none
+// of its lanes has one (the test alone is the common cost).  At Delta = 0 the
+// clamped reciprocal square root is finite, so f * 0 = 0 and the tie term
+// alone remains.
+template <bool SQ>
 __device__ __forceinline__ void spheroid_residual(float dx, float dy, float dz, float ia2,
-                                                  float ib2, float tie, float& vx, float& vy,
-                                                  float& vz, float& sq) {
+                                                  float ib2, float tie, bool live, float& vx,
+                                                  float& vy, float& vz, float& sq) {
   const float s2 = fmaf(dz * dz, ib2, fmaf(dx, dx, dy * dy) * ia2);
-  if (s2 < 1.f) {
-    float rx, ry, rz;
-    if (s2 > 0.f) {
-      const float f = 1.f - __builtin_amdgcn_rsqf(s2);
-      rx = f * dx;
-      ry = f * dy;
-      rz = f * dz;
-    } else {
-      rx = 0.f;
-      ry = 0.f;
-      rz = tie;
-    }
+  if (live && s2 < 1.f) {
+    const float f = 1.f - __builtin_amdgcn_rsqf(fmaxf(s2, FLT_MIN));
+    const float rx = f * dx;
+    const float ry = f * dy;
+    const float rz = fmaf(f, dz, s2 == 0.f ? tie : 0.f);
     vx += rx;
     vy += ry;
     vz += rz;
-    sq = fmaf(rx, rx, fmaf(ry, ry, fmaf(rz, rz, sq)));
+    if (SQ) sq = fmaf(rx, rx, fmaf(ry, ry, fmaf(rz, rz, sq)));
   }
 }
 
@@ -109,14 +108,16 @@ __device__ __forceinline__ Lds3 carve3(float* p, int nc, int Tc, int n_max, int 
 }
 
 // One pass over the horizon at xi_bar = xb: positions X, constraint sums V
-// and (unless `final`) R = W^T V; with `final` the residual sums instead.
-template <int NT>
+// and (unless FINAL) R = W^T V; with FINAL the residual sums instead.
+template <int NT, bool FINAL>
 __device__ __forceinline__ void sweep3(const FwdArgs& A, const ProbDesc& P, const Lds3& L,
-                                       const float* xb, bool final, float& r1sq, float& r2sq) {
+                                       const float* xb, float& r1sq, float& r2sq) {
   const int n = P.n, M = P.M, nc = A.nc, T = A.T, Tc = A.Tc, tid = threadIdx.x;
   const int S = 3 * n * nc;
   const bool chunked = Tc < T;
   const float ia2 = 1.f / (P.a * P.a), ib2 = 1.f / (P.b * P.b);
+  const float inv_Tm1 = 1.f / (float)(T - 1);
+  const bool moving = A.ovel != nullptr;
   for (int k0 = 0; k0 < T; k0 += Tc) {
     const int Tce = min(Tc, T - k0);
     if (chunked) {
@@ -129,9 +130,16 @@ __device__ __forceinline__ void sweep3(const FwdArgs& A, const ProbDesc& P, cons
       const int row = t / Tce, kk = t - row * Tce;   // row = ax * n + i
       const float* x = xb + row * nc;
       const float* w = Wc + kk * nc;
-      float s = 0.f;
-      for (int c = 0; c < nc; ++c) s = fmaf(w[c], x[c], s);
-      L.X[row * Tce + kk] = s;
+      float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;   // four chains in flight
+      int c = 0;
+      for (; c + 4 <= nc; c += 4) {
+        s0 = fmaf(w[c], x[c], s0);
+        s1 = fmaf(w[c + 1], x[c + 1], s1);
+        s2 = fmaf(w[c + 2], x[c + 2], s2);
+        s3 = fmaf(w[c + 3], x[c + 3], s3);
+      }
+      for (; c < nc; ++c) s0 = fmaf(w[c], x[c], s0);
+      L.X[row * Tce + kk] = (s0 + s1) + (s2 + s3);
     }
     __syncthreads();
     // constraint rows (every robot pair, every obstacle, the box)
@@ -139,25 +147,55 @@ __device__ __forceinline__ void sweep3(const FwdArgs& A, const ProbDesc& P, cons
     for (int t = tid; t < plane; t += NT) {
       const int i = t / Tce, kk = t - i * Tce;
       const float px = L.X[t], py = L.X[plane + t], pz = L.X[2 * plane + t];
-      float vx = 0.f, vy = 0.f, vz = 0.f, sq = 0.f, sq_half = 0.f;
-      for (int j = 0; j < n; ++j) {
-        if (j == i) continue;
+      float vx = 0.f, vy = 0.f, vz = 0.f, sq = 0.f;
+      // partners in groups of four, every read of a group issued first
+      int j0 = 0;
+      for (; j0 + 4 <= n; j0 += 4) {
+        float qx[4], qy[4], qz[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int u = (j0 + e) * Tce + kk;
+          qx[e] = L.X[u];
+          qy[e] = L.X[plane + u];
+          qz[e] = L.X[2 * plane + u];
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int j = j0 + e;
+          float s1 = 0.f;
+          spheroid_residual<FINAL>(px - qx[e], py - qy[e], pz - qz[e], ia2, ib2,
+                                   i < j ? -P.b : P.b, j != i, vx, vy, vz, s1);
+          if (FINAL) sq += j > i ? s1 : 0.f;   // each unordered pair once
+        }
+      }
+      for (int j = j0; j < n; ++j) {
         const int u = j * Tce + kk;
         float s1 = 0.f;
-        spheroid_residual(px - L.X[u], py - L.X[plane + u], pz - L.X[2 * plane + u], ia2,
-                          ib2, i < j ? -P.b : P.b, vx, vy, vz, s1);
-        if (j > i) sq_half += s1;      // each unordered pair once
+        spheroid_residual<FINAL>(px - L.X[u], py - L.X[plane + u], pz - L.X[2 * plane + u], ia2,
+                                 ib2, i < j ? -P.b : P.b, j != i, vx, vy, vz, s1);
+        if (FINAL) sq += j > i ? s1 : 0.f;
       }
-      for (int m = 0; m < M; ++m) {
-        const float* o = L.obs + m * kObsFloats;
-        spheroid_residual(px - o[0], py - o[1], pz - o[2], o[3], o[4], -o[5], vx, vy, vz,
-                          sq);
+      // obstacle centres at tau_k = k / (T - 1): c + d tau
+      if (moving) {
+        const float tau = (float)(k0 + kk) * inv_Tm1;
+        for (int m = 0; m < M; ++m) {
+          const float* o = L.obs + m * kObsFloats;
+          spheroid_residual<FINAL>(px - fmaf(o[6], tau, o[0]), py - fmaf(o[7], tau, o[1]),
+                                   pz - fmaf(o[8], tau, o[2]), o[3], o[4], -o[5], true, vx,
+                                   vy, vz, sq);
+        }
+      } else {
+        for (int m = 0; m < M; ++m) {
+          const float* o = L.obs + m * kObsFloats;
+          spheroid_residual<FINAL>(px - o[0], py - o[1], pz - o[2], o[3], o[4], -o[5], true,
+                                   vx, vy, vz, sq);
+        }
       }
       const float hx = fmaxf(px - P.pmax[0], 0.f), lx = fmaxf(P.pmin[0] - px, 0.f);
       const float hy = fmaxf(py - P.pmax[1], 0.f), ly = fmaxf(P.pmin[1] - py, 0.f);
       const float hz = fmaxf(pz - P.pmax[2], 0.f), lz = fmaxf(P.pmin[2] - pz, 0.f);
-      if (final) {
-        r1sq += sq + sq_half;
+      if (FINAL) {
+        r1sq += sq;
         r2sq += hx * hx + lx * lx + hy * hy + ly * ly + hz * hz + lz * lz;
       } else {
         L.V[t] = vx + (hx - lx);
@@ -166,13 +204,21 @@ __device__ __forceinline__ void sweep3(const FwdArgs& A, const ProbDesc& P, cons
       }
     }
     __syncthreads();
-    if (!final) {
+    if (!FINAL) {
       // R (+)= W^T V over this chunk's steps
       for (int t = tid; t < S; t += NT) {
         const int row = t / nc, c = t - row * nc;
         const float* v = L.V + row * Tce;
-        float s = 0.f;
-        for (int kk = 0; kk < Tce; ++kk) s = fmaf(Wc[kk * nc + c], v[kk], s);
+        float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+        int kk = 0;
+        for (; kk + 4 <= Tce; kk += 4) {
+          s0 = fmaf(Wc[kk * nc + c], v[kk], s0);
+          s1 = fmaf(Wc[(kk + 1) * nc + c], v[kk + 1], s1);
+          s2 = fmaf(Wc[(kk + 2) * nc + c], v[kk + 2], s2);
+          s3 = fmaf(Wc[(kk + 3) * nc + c], v[kk + 3], s3);
+        }
+        for (; kk < Tce; ++kk) s0 = fmaf(Wc[kk * nc + c], v[kk], s0);
+        const float s = (s0 + s1) + (s2 + s3);
         L.R[t] = k0 == 0 ? s : L.R[t] + s;
       }
       __syncthreads();
@@ -206,6 +252,11 @@ __global__ __launch_bounds__(NT) void fwd3_kernel(FwdArgs A) {
     d[3] = 1.f / (o[3] * o[3]);
     d[4] = 1.f / (o[4] * o[4]);
     d[5] = o[4];
+    // displacement over the horizon (moving obstacles), zero when static
+    const float* v = A.ovel ? A.ovel + (size_t)(P.obs_off + m) * 3 : nullptr;
+    d[6] = v ? v[0] : 0.f;
+    d[7] = v ? v[1] : 0.f;
+    d[8] = v ? v[2] : 0.f;
   }
   for (int t = tid; t < S; t += NT) {
     L.xb[0][t] = A.xi0[P.coef_off + t];
@@ -254,7 +305,7 @@ __global__ __launch_bounds__(NT) void fwd3_kernel(FwdArgs A) {
   for (int l = 0; l < A.L; ++l) {
     const bool last = l == A.L - 1;
     float z0 = 0.f, z1 = 0.f;
-    sweep3<NT>(A, P, L, xcur, false, z0, z1);
+    sweep3<NT, false>(A, P, L, xcur, z0, z1);
     // lambda step and u = lambda - 2 rho R (u replaces R)
     for (int t = tid; t < S; t += NT) {
       const float r = L.R[t], lm = L.lam[t];
@@ -267,9 +318,16 @@ __global__ __launch_bounds__(NT) void fwd3_kernel(FwdArgs A) {
     for (int t = tid; t < 6 * nc; t += NT) {
       const int which = t / (3 * nc), q = t - which * 3 * nc, ax = q / nc, c = q - ax * nc;
       const float* src = (which ? xcur : L.R) + ax * nn + c;
-      float s = 0.f;
-      for (int i = 0; i < n; ++i) s += src[i * nc];
-      L.means[t] = s / (float)n;
+      float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;   // four chains in flight
+      int i = 0;
+      for (; i + 4 <= n; i += 4) {
+        s0 += src[i * nc];
+        s1 += src[(i + 1) * nc];
+        s2 += src[(i + 2) * nc];
+        s3 += src[(i + 3) * nc];
+      }
+      for (; i < n; ++i) s0 += src[i * nc];
+      L.means[t] = ((s0 + s1) + (s2 + s3)) / (float)n;
     }
     __syncthreads();
     // xi_bar step
@@ -286,13 +344,14 @@ __global__ __launch_bounds__(NT) void fwd3_kernel(FwdArgs A) {
         const float* x = xb + ax * nn + i * nc;
         const float* um = L.means + ax * nc;
         const float* xm = L.means + 3 * nc + ax * nc;
-        float v = L.cxi[t];
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;   // one chain per block
         for (int q = 0; q < nc; ++q) {
-          v = fmaf(Sp[q], u[q], v);
-          v = fmaf(DS[q], um[q], v);
-          v = fmaf(SH[q], x[q], v);
-          v = fmaf(DSH[q], xm[q], v);
+          a0 = fmaf(Sp[q], u[q], a0);
+          a1 = fmaf(DS[q], um[q], a1);
+          a2 = fmaf(SH[q], x[q], a2);
+          a3 = fmaf(DSH[q], xm[q], a3);
         }
+        const float v = L.cxi[t] + ((a0 + a1) + (a2 + a3));
         xn[t] = v;
         if (last) {
           const float d = v - xb[t];
@@ -308,7 +367,7 @@ __global__ __launch_bounds__(NT) void fwd3_kernel(FwdArgs A) {
 
   // residual of the returned iterate, outputs, status
   float v[3] = {0.f, 0.f, 0.f};
-  sweep3<NT>(A, P, L, xcur, true, v[0], v[1]);
+  sweep3<NT, true>(A, P, L, xcur, v[0], v[1]);
   float bad = 0.f;
   for (int t = tid; t < S; t += NT) {
     const float x = xcur[t], lm = L.lam[t];

@@ -174,3 +174,40 @@ def test_3d_unsupported_calls_fail_loudly(gpu):
         plan.set_early_exit(1e-3, 10)
     with pytest.raises(SFError):
         plan.backward(t["xi0"], None, None)
+
+
+@pytest.mark.parametrize("cfg_id,batch,L", [(16, 3, 50), (48, 5, 40)])
+def test_3d_moving_obstacles_match_oracle(gpu, cfg_id, batch, L):
+    """Obstacle centres c + d tau (sf_set_obstacle_motion with [sum M][3]);
+    resetting the motion restores the static result bit for bit."""
+    import torch
+    probs = make_batch3d(WORKLOADS_3D[cfg_id], batch=batch)
+    pk = pack3d(probs)
+    disp = np.random.default_rng(cfg_id).uniform(-2.0, 2.0, (int(pk.n_obs.sum()), 3))
+    disp = disp.astype(np.float32)
+    static = _run(probs, L)
+    plan, t = static[4], static[5]
+    plan.set_obstacle_motion(torch.from_numpy(disp).cuda())
+    xo, lo, res = plan.project(t["xi"], t["xi0"], t["lam0"], t["boundary"], t["obstacles"], L)
+    torch.cuda.synchronize()
+    xo, lo, res = xo.cpu().numpy(), lo.cpu().numpy(), res.cpu().numpy()
+    assert not np.array_equal(xo, static[1])
+    gx, gl = unpack3d(xo, probs), unpack3d(lo, probs)
+    o = 0
+    for b, inp in enumerate(_inputs3d(pk, probs)):
+        d = disp[o:o + inp["M"]].astype(np.float64)
+        o += inp["M"]
+        ref = SFOracle(inp["n"], inp["M"], inp["n_coef"], inp["n_steps"], RHO, inp["a"],
+                       inp["box"], inp["obstacles"], inp["boundary"], dim=3,
+                       robot_b=inp["b"], obstacle_displacement=d).solve(
+                           inp["xi"], inp["xi0"], inp["lam0"], L)
+        assert res[b, 3] == 0.0
+        assert rel_err(gx[b], ref.xi_bar) <= REL_TOL, b
+        scale = max(np.linalg.norm(ref.lam), np.linalg.norm(ref.xi_bar))
+        assert np.linalg.norm(gl[b] - ref.lam) / scale <= REL_TOL, b
+        got = np.hypot(res[b, 0], res[b, 1])
+        assert abs(got - ref.residual) <= RES_TOL + RES_REL_TOL * ref.residual
+    plan.set_obstacle_motion(None)
+    back, _, _ = plan.project(t["xi"], t["xi0"], t["lam0"], t["boundary"], t["obstacles"], L)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(back.cpu().numpy(), static[1])

@@ -155,3 +155,28 @@ def test_3d_residual_decreases_on_a_generated_problem():
     res = _solve3(p, 200)
     h = np.hypot(res.history[:, 0], res.history[:, 1])
     assert h[0] > 1e-2 and res.residual < 0.05 * h[0]
+
+
+def test_moving_obstacles_are_galilean_equivariant():
+    """Obstacles moving by d over the horizon (centre c + d tau) against the
+    same problem seen from a frame moving with them: there the obstacles are
+    static and every robot's sample and boundary are shifted by -d tau, i.e.
+    by -d c/(n_coef - 1) on coefficient c (linear precision of the Bernstein
+    basis).  Pair differences are unchanged and the box is far away, so the
+    iterates differ by exactly that shift."""
+    p = _tight3d(2)
+    box = np.array([[-50.0] * 3, [50.0] * 3])
+    d = np.array([0.7, -0.4, 0.3])
+    L = 40
+    disp = np.tile(d, (p.M, 1))
+    mov = O.SFOracle(p.n, p.M, p.n_coef, p.n_steps, RHO, p.a, box, p.obstacles, p.boundary,
+                     dim=3, robot_b=p.b, obstacle_displacement=disp).solve(
+                         p.xi, n_iters=L, keep_history=True)
+    assert mov.history[0, 0] > 1e-3
+    shift = d[:, None, None] * (np.arange(p.n_coef) / (p.n_coef - 1))[None, None, :]
+    bnd = p.boundary - np.stack([np.zeros(3), d])[None]
+    sta = O.SFOracle(p.n, p.M, p.n_coef, p.n_steps, RHO, p.a, box, p.obstacles, bnd,
+                     dim=3, robot_b=p.b).solve(p.xi - shift, n_iters=L)
+    np.testing.assert_allclose(mov.xi_bar - shift, sta.xi_bar, rtol=0, atol=1e-9)
+    np.testing.assert_allclose(mov.lam, sta.lam, rtol=0, atol=1e-9)
+    assert mov.residual == pytest.approx(sta.residual, rel=1e-8, abs=1e-12)
