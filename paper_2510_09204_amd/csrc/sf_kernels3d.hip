@@ -85,6 +85,10 @@ __device__ __forceinline__ void spheroid_residual(float dx, float dy, float dz, 
   }
 }
 
+// Robots per thread in the constraint stage: more robots share each LDS read,
+// fewer threads have work; four from 24 robots, two from 8.
+__device__ __forceinline__ int robots_per_thread(int n) { return n >= 24 ? 4 : (n >= 8 ? 2 : 1); }
+
 struct Lds3 {
   float *W, *fac, *xb[2], *lam, *cxi, *R, *means, *obs, *X, *V, *red;
 };
@@ -109,7 +113,7 @@ __device__ __forceinline__ Lds3 carve3(float* p, int nc, int Tc, int n_max, int 
 
 // One pass over the horizon at xi_bar = xb: positions X, constraint sums V
 // and (unless FINAL) R = W^T V; with FINAL the residual sums instead.
-template <int NT, bool FINAL>
+template <int NT, bool FINAL, int kRob>
 __device__ __forceinline__ void sweep3(const FwdArgs& A, const ProbDesc& P, const Lds3& L,
                                        const float* xb, float& r1sq, float& r2sq) {
   const int n = P.n, M = P.M, nc = A.nc, T = A.T, Tc = A.Tc, tid = threadIdx.x;
@@ -142,12 +146,26 @@ __device__ __forceinline__ void sweep3(const FwdArgs& A, const ProbDesc& P, cons
       L.X[row * Tce + kk] = (s0 + s1) + (s2 + s3);
     }
     __syncthreads();
-    // constraint rows (every robot pair, every obstacle, the box)
+    // constraint rows (every robot pair, every obstacle, the box).  A thread
+    // takes kRob robots at one step, so each partner position and obstacle
+    // read from LDS serves kRob rows; every row still sums its terms in the
+    // same order (partners j = 0..n-1, then obstacles).  kRob depends on the
+    // problem's robot count only (robots_per_thread), not on the block size.
     const int plane = n * Tce;
-    for (int t = tid; t < plane; t += NT) {
-      const int i = t / Tce, kk = t - i * Tce;
-      const float px = L.X[t], py = L.X[plane + t], pz = L.X[2 * plane + t];
-      float vx = 0.f, vy = 0.f, vz = 0.f, sq = 0.f;
+    const int ngrp = (n + kRob - 1) / kRob;
+    for (int t = tid; t < ngrp * Tce; t += NT) {
+      const int g = t / Tce, kk = t - g * Tce;
+      float px[kRob], py[kRob], pz[kRob], vx[kRob], vy[kRob], vz[kRob], sq[kRob];
+      int ir[kRob];
+#pragma unroll
+      for (int r = 0; r < kRob; ++r) {
+        ir[r] = g * kRob + r;
+        const int u = min(ir[r], n - 1) * Tce + kk;
+        px[r] = L.X[u];
+        py[r] = L.X[plane + u];
+        pz[r] = L.X[2 * plane + u];
+        vx[r] = vy[r] = vz[r] = sq[r] = 0.f;
+      }
       // partners in groups of four, every read of a group issued first
       int j0 = 0;
       for (; j0 + 4 <= n; j0 += 4) {
@@ -162,45 +180,55 @@ __device__ __forceinline__ void sweep3(const FwdArgs& A, const ProbDesc& P, cons
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int j = j0 + e;
-          float s1 = 0.f;
-          spheroid_residual<FINAL>(px - qx[e], py - qy[e], pz - qz[e], ia2, ib2,
-                                   i < j ? -P.b : P.b, j != i, vx, vy, vz, s1);
-          if (FINAL) sq += j > i ? s1 : 0.f;   // each unordered pair once
+#pragma unroll
+          for (int r = 0; r < kRob; ++r) {
+            float s1 = 0.f;
+            spheroid_residual<FINAL>(px[r] - qx[e], py[r] - qy[e], pz[r] - qz[e], ia2, ib2,
+                                     ir[r] < j ? -P.b : P.b, j != ir[r], vx[r], vy[r], vz[r],
+                                     s1);
+            if (FINAL) sq[r] += j > ir[r] ? s1 : 0.f;   // each unordered pair once
+          }
         }
       }
       for (int j = j0; j < n; ++j) {
         const int u = j * Tce + kk;
-        float s1 = 0.f;
-        spheroid_residual<FINAL>(px - L.X[u], py - L.X[plane + u], pz - L.X[2 * plane + u], ia2,
-                                 ib2, i < j ? -P.b : P.b, j != i, vx, vy, vz, s1);
-        if (FINAL) sq += j > i ? s1 : 0.f;
+        const float qx = L.X[u], qy = L.X[plane + u], qz = L.X[2 * plane + u];
+#pragma unroll
+        for (int r = 0; r < kRob; ++r) {
+          float s1 = 0.f;
+          spheroid_residual<FINAL>(px[r] - qx, py[r] - qy, pz[r] - qz, ia2, ib2,
+                                   ir[r] < j ? -P.b : P.b, j != ir[r], vx[r], vy[r], vz[r], s1);
+          if (FINAL) sq[r] += j > ir[r] ? s1 : 0.f;
+        }
       }
       // obstacle centres at tau_k = k / (T - 1): c + d tau
-      if (moving) {
-        const float tau = (float)(k0 + kk) * inv_Tm1;
-        for (int m = 0; m < M; ++m) {
-          const float* o = L.obs + m * kObsFloats;
-          spheroid_residual<FINAL>(px - fmaf(o[6], tau, o[0]), py - fmaf(o[7], tau, o[1]),
-                                   pz - fmaf(o[8], tau, o[2]), o[3], o[4], -o[5], true, vx,
-                                   vy, vz, sq);
-        }
-      } else {
-        for (int m = 0; m < M; ++m) {
-          const float* o = L.obs + m * kObsFloats;
-          spheroid_residual<FINAL>(px - o[0], py - o[1], pz - o[2], o[3], o[4], -o[5], true,
-                                   vx, vy, vz, sq);
-        }
+      const float tau = (float)(k0 + kk) * inv_Tm1;
+      for (int m = 0; m < M; ++m) {
+        const float* o = L.obs + m * kObsFloats;
+        const float cx = moving ? fmaf(o[6], tau, o[0]) : o[0];
+        const float cy = moving ? fmaf(o[7], tau, o[1]) : o[1];
+        const float cz = moving ? fmaf(o[8], tau, o[2]) : o[2];
+        const float oa = o[3], ob = o[4], tie = -o[5];
+#pragma unroll
+        for (int r = 0; r < kRob; ++r)
+          spheroid_residual<FINAL>(px[r] - cx, py[r] - cy, pz[r] - cz, oa, ob, tie, true,
+                                   vx[r], vy[r], vz[r], sq[r]);
       }
-      const float hx = fmaxf(px - P.pmax[0], 0.f), lx = fmaxf(P.pmin[0] - px, 0.f);
-      const float hy = fmaxf(py - P.pmax[1], 0.f), ly = fmaxf(P.pmin[1] - py, 0.f);
-      const float hz = fmaxf(pz - P.pmax[2], 0.f), lz = fmaxf(P.pmin[2] - pz, 0.f);
-      if (FINAL) {
-        r1sq += sq;
-        r2sq += hx * hx + lx * lx + hy * hy + ly * ly + hz * hz + lz * lz;
-      } else {
-        L.V[t] = vx + (hx - lx);
-        L.V[plane + t] = vy + (hy - ly);
-        L.V[2 * plane + t] = vz + (hz - lz);
+#pragma unroll
+      for (int r = 0; r < kRob; ++r) {
+        if (ir[r] >= n) continue;
+        const int u = ir[r] * Tce + kk;
+        const float hx = fmaxf(px[r] - P.pmax[0], 0.f), lx = fmaxf(P.pmin[0] - px[r], 0.f);
+        const float hy = fmaxf(py[r] - P.pmax[1], 0.f), ly = fmaxf(P.pmin[1] - py[r], 0.f);
+        const float hz = fmaxf(pz[r] - P.pmax[2], 0.f), lz = fmaxf(P.pmin[2] - pz[r], 0.f);
+        if (FINAL) {
+          r1sq += sq[r];
+          r2sq += hx * hx + lx * lx + hy * hy + ly * ly + hz * hz + lz * lz;
+        } else {
+          L.V[u] = vx[r] + (hx - lx);
+          L.V[plane + u] = vy[r] + (hy - ly);
+          L.V[2 * plane + u] = vz[r] + (hz - lz);
+        }
       }
     }
     __syncthreads();
@@ -237,6 +265,7 @@ __global__ __launch_bounds__(NT) void fwd3_kernel(FwdArgs A) {
   const float rho = A.rho;
   const float* bnd = A.boundary + (size_t)P.rob_off * 6;
   const bool chunked = Tc < T;
+  const int rpt = robots_per_thread(n);
 
   // --- set-up: factor block, W (whole table when unchunked), obstacles, state
   const float* facg = A.fac + (size_t)P.fac * fac_stride(nc);
@@ -305,7 +334,12 @@ __global__ __launch_bounds__(NT) void fwd3_kernel(FwdArgs A) {
   for (int l = 0; l < A.L; ++l) {
     const bool last = l == A.L - 1;
     float z0 = 0.f, z1 = 0.f;
-    sweep3<NT, false>(A, P, L, xcur, z0, z1);
+    if (rpt == 4)
+      sweep3<NT, false, 4>(A, P, L, xcur, z0, z1);
+    else if (rpt == 2)
+      sweep3<NT, false, 2>(A, P, L, xcur, z0, z1);
+    else
+      sweep3<NT, false, 1>(A, P, L, xcur, z0, z1);
     // lambda step and u = lambda - 2 rho R (u replaces R)
     for (int t = tid; t < S; t += NT) {
       const float r = L.R[t], lm = L.lam[t];
@@ -367,7 +401,12 @@ __global__ __launch_bounds__(NT) void fwd3_kernel(FwdArgs A) {
 
   // residual of the returned iterate, outputs, status
   float v[3] = {0.f, 0.f, 0.f};
-  sweep3<NT, true>(A, P, L, xcur, v[0], v[1]);
+  if (rpt == 4)
+    sweep3<NT, true, 4>(A, P, L, xcur, v[0], v[1]);
+  else if (rpt == 2)
+    sweep3<NT, true, 2>(A, P, L, xcur, v[0], v[1]);
+  else
+    sweep3<NT, true, 1>(A, P, L, xcur, v[0], v[1]);
   float bad = 0.f;
   for (int t = tid; t < S; t += NT) {
     const float x = xcur[t], lm = L.lam[t];
