@@ -33,6 +33,14 @@ constexpr int kObsFloats = 12;     // x, y, z, 1/a_o^2, 1/b_o^2, b_o, dx, dy, dz
 
 __host__ __device__ inline int r4(int x) { return (x + 3) & ~3; }
 
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// C += A B on a 16x16x4 FP32 MFMA tile (A[m][k] and B[k][m] from lane
+// m + 16 k; C[4 k + v][m] in accumulator v of lane m + 16 k).
+__device__ __forceinline__ floatx4 mfma_16x16x4(float a, float b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
 __device__ __forceinline__ float wave_sum3(float v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -117,7 +125,6 @@ template <int NT, bool FINAL, int kRob>
 __device__ __forceinline__ void sweep3(const FwdArgs& A, const ProbDesc& P, const Lds3& L,
                                        const float* xb, float& r1sq, float& r2sq) {
   const int n = P.n, M = P.M, nc = A.nc, T = A.T, Tc = A.Tc, tid = threadIdx.x;
-  const int S = 3 * n * nc;
   const bool chunked = Tc < T;
   const float ia2 = 1.f / (P.a * P.a), ib2 = 1.f / (P.b * P.b);
   const float inv_Tm1 = 1.f / (float)(T - 1);
@@ -129,21 +136,32 @@ __device__ __forceinline__ void sweep3(const FwdArgs& A, const ProbDesc& P, cons
       __syncthreads();
     }
     const float* Wc = chunked ? L.W : L.W + k0 * nc;
-    // positions
-    for (int t = tid; t < 3 * n * Tce; t += NT) {
-      const int row = t / Tce, kk = t - row * Tce;   // row = ax * n + i
-      const float* x = xb + row * nc;
-      const float* w = Wc + kk * nc;
-      float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;   // four chains in flight
-      int c = 0;
-      for (; c + 4 <= nc; c += 4) {
-        s0 = fmaf(w[c], x[c], s0);
-        s1 = fmaf(w[c + 1], x[c + 1], s1);
-        s2 = fmaf(w[c + 2], x[c + 2], s2);
-        s3 = fmaf(w[c + 3], x[c + 3], s3);
+    // positions X[row][kk] = sum_c W[kk][c] xb[row][c] on MFMA 16x16x4 tiles
+    // of 16 steps x 16 rows (row = axis * n + robot), the wave's tiles dealt
+    // round-robin.  A lane supplies A[m][k] = W[16 wt + m][4 s + k'] and
+    // B[k][m] = xb[16 ct + m][4 s + k'] (m = lane % 16, k' = lane / 16) and
+    // holds X[16 ct + m][16 wt + 4 k' + v]; coefficients past nc enter as 0.
+    {
+      const int lane = tid & 63, wave = tid >> 6, m = lane & 15, kq = lane >> 4;
+      const int nwt = (Tce + 15) >> 4, nct = (3 * n + 15) >> 4, ks = (nc + 3) >> 2;
+      for (int q = wave; q < nwt * nct; q += NT >> 6) {
+        const int wt = q / nct, ct = q - wt * nct;
+        const int stepA = min(wt * 16 + m, Tce - 1), colB = min(ct * 16 + m, 3 * n - 1);
+        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+        for (int s4 = 0; s4 < ks; ++s4) {
+          const int c = 4 * s4 + kq, cc = min(c, nc - 1);
+          const float a = c < nc ? Wc[stepA * nc + cc] : 0.f;
+          acc = mfma_16x16x4(a, xb[colB * nc + cc], acc);
+        }
+        const int col = ct * 16 + m;
+        if (col < 3 * n) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int step = wt * 16 + 4 * kq + v;
+            if (step < Tce) L.X[col * Tce + step] = acc[v];
+          }
+        }
       }
-      for (; c < nc; ++c) s0 = fmaf(w[c], x[c], s0);
-      L.X[row * Tce + kk] = (s0 + s1) + (s2 + s3);
     }
     __syncthreads();
     // constraint rows (every robot pair, every obstacle, the box).  A thread
@@ -233,21 +251,43 @@ __device__ __forceinline__ void sweep3(const FwdArgs& A, const ProbDesc& P, cons
     }
     __syncthreads();
     if (!FINAL) {
-      // R (+)= W^T V over this chunk's steps
-      for (int t = tid; t < S; t += NT) {
-        const int row = t / nc, c = t - row * nc;
-        const float* v = L.V + row * Tce;
-        float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-        int kk = 0;
-        for (; kk + 4 <= Tce; kk += 4) {
-          s0 = fmaf(Wc[kk * nc + c], v[kk], s0);
-          s1 = fmaf(Wc[(kk + 1) * nc + c], v[kk + 1], s1);
-          s2 = fmaf(Wc[(kk + 2) * nc + c], v[kk + 2], s2);
-          s3 = fmaf(Wc[(kk + 3) * nc + c], v[kk + 3], s3);
+      // R (+)= W^T V over this chunk's steps on MFMA 16x16x4 tiles of 16 rows
+      // x 16 coefficients: A[m][k] = V[16 rt + m][4 s + k'], B[k][m] =
+      // W[4 s + k'][16 ct + m]; steps past Tce enter as 0.  Two accumulators
+      // (even and odd s) added at the end.
+      const int lane = tid & 63, wave = tid >> 6, m = lane & 15, kq = lane >> 4;
+      const int nrt = (3 * n + 15) >> 4, nct = (nc + 15) >> 4, nk = (Tce + 3) >> 2;
+      for (int q = wave; q < nrt * nct; q += NT >> 6) {
+        const int rt = q / nct, ct = q - rt * nct;
+        const int rowA = min(rt * 16 + m, 3 * n - 1), cB = min(ct * 16 + m, nc - 1);
+        const float* vrow = L.V + rowA * Tce;
+        floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+        int s4 = 0;
+        for (; s4 + 2 <= nk; s4 += 2) {
+          const int k0s = 4 * s4 + kq, k1s = k0s + 4;
+          const float a0 = k0s < Tce ? vrow[min(k0s, Tce - 1)] : 0.f;
+          const float a1 = k1s < Tce ? vrow[min(k1s, Tce - 1)] : 0.f;
+          const float b0 = Wc[min(k0s, Tce - 1) * nc + cB];
+          const float b1 = Wc[min(k1s, Tce - 1) * nc + cB];
+          acc0 = mfma_16x16x4(a0, b0, acc0);
+          acc1 = mfma_16x16x4(a1, b1, acc1);
         }
-        for (; kk < Tce; ++kk) s0 = fmaf(Wc[kk * nc + c], v[kk], s0);
-        const float s = (s0 + s1) + (s2 + s3);
-        L.R[t] = k0 == 0 ? s : L.R[t] + s;
+        if (s4 < nk) {
+          const int k0s = 4 * s4 + kq;
+          const float a0 = k0s < Tce ? vrow[min(k0s, Tce - 1)] : 0.f;
+          acc0 = mfma_16x16x4(a0, Wc[min(k0s, Tce - 1) * nc + cB], acc0);
+        }
+        const int c = ct * 16 + m;
+        if (c < nc) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = rt * 16 + 4 * kq + v;
+            if (row < 3 * n) {
+              const float sum = acc0[v] + acc1[v];
+              L.R[row * nc + c] = k0 == 0 ? sum : L.R[row * nc + c] + sum;
+            }
+          }
+        }
       }
       __syncthreads();
     }
