@@ -29,7 +29,7 @@ namespace sf {
 namespace {
 
 constexpr int kRed3 = 64;          // block-reduction scratch (3 values x 16 waves)
-constexpr int kObsFloats = 12;     // x, y, z, 1/a_o^2, 1/b_o^2, b_o, dx, dy, dz, pad x3
+constexpr int kObsFloats = 12;     // obstacle table entry (10 used, see the set-up)
 
 __host__ __device__ inline int r4(int x) { return (x + 3) & ~3; }
 
@@ -68,24 +68,25 @@ __device__ __forceinline__ void block_sum3(float (&v)[3], float* red) {
   __syncthreads();
 }
 
-// r_1 of one spheroid row: Delta (dx, dy, dz), ia2 = 1/a^2, ib2 = 1/b^2;
-// `tie` is the z value of r_1 at Delta = 0 (-b for the row's own
-// orientation); rows with `live` false (a robot against itself) add nothing.
-// Adds r_1 to (vx, vy, vz) and, with SQ, |r_1|^2 to sq.  Active rows (s < 1)
-// are rare, so the residual sits behind a branch that a wave skips when none
-// of its lanes has one (the test alone is the common cost).  At Delta = 0 the
-// clamped reciprocal square root is finite, so f * 0 = 0 and the tie term
-// alone remains.
+// r_1 of one spheroid row from its scaled offset (ex, ey, ez) = (dx/sa,
+// dy/sa, dz/sb), (sa, sb) the spheroid's semi-axes pair (a, b) or (a_o, b_o):
+// s^2 = ex^2 + ey^2 + ez^2 and r_1 = (1 - 1/s) Delta for s < 1.  `tie` is the z
+// value of r_1 at Delta = 0 (-b for the row's own orientation); rows with
+// `live` false (a robot against itself) add nothing.  Adds r_1 to (vx, vy, vz)
+// and, with SQ, |r_1|^2 to sq.  Active rows are rare, so the residual sits
+// behind a branch that a wave skips when none of its lanes has one (the test
+// alone is the common cost).  At Delta = 0 the clamped reciprocal square root
+// is finite, so f * 0 = 0 and the tie term alone remains.
 template <bool SQ>
-__device__ __forceinline__ void spheroid_residual(float dx, float dy, float dz, float ia2,
-                                                  float ib2, float tie, bool live, float& vx,
+__device__ __forceinline__ void spheroid_residual(float ex, float ey, float ez, float sa,
+                                                  float sb, float tie, bool live, float& vx,
                                                   float& vy, float& vz, float& sq) {
-  const float s2 = fmaf(dz * dz, ib2, fmaf(dx, dx, dy * dy) * ia2);
+  const float s2 = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
   if (live && s2 < 1.f) {
     const float f = 1.f - __builtin_amdgcn_rsqf(fmaxf(s2, FLT_MIN));
-    const float rx = f * dx;
-    const float ry = f * dy;
-    const float rz = fmaf(f, dz, s2 == 0.f ? tie : 0.f);
+    const float rx = f * (sa * ex);
+    const float ry = f * (sa * ey);
+    const float rz = fmaf(f, sb * ez, s2 == 0.f ? tie : 0.f);
     vx += rx;
     vy += ry;
     vz += rz;
@@ -126,7 +127,7 @@ __device__ __forceinline__ void sweep3(const FwdArgs& A, const ProbDesc& P, cons
                                        const float* xb, float& r1sq, float& r2sq) {
   const int n = P.n, M = P.M, nc = A.nc, T = A.T, Tc = A.Tc, tid = threadIdx.x;
   const bool chunked = Tc < T;
-  const float ia2 = 1.f / (P.a * P.a), ib2 = 1.f / (P.b * P.b);
+  const float inv_a = 1.f / P.a, inv_b = 1.f / P.b;
   const float inv_Tm1 = 1.f / (float)(T - 1);
   const bool moving = A.ovel != nullptr;
   for (int k0 = 0; k0 < T; k0 += Tc) {
@@ -153,12 +154,14 @@ __device__ __forceinline__ void sweep3(const FwdArgs& A, const ProbDesc& P, cons
           const float a = c < nc ? Wc[stepA * nc + cc] : 0.f;
           acc = mfma_16x16x4(a, xb[colB * nc + cc], acc);
         }
+        // stored scaled by the robot's semi-axes: x/a, y/a, z/b
         const int col = ct * 16 + m;
+        const float sc = col < 2 * n ? inv_a : inv_b;
         if (col < 3 * n) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int step = wt * 16 + 4 * kq + v;
-            if (step < Tce) L.X[col * Tce + step] = acc[v];
+            if (step < Tce) L.X[col * Tce + step] = acc[v] * sc;
           }
         }
       }
@@ -201,7 +204,7 @@ __device__ __forceinline__ void sweep3(const FwdArgs& A, const ProbDesc& P, cons
 #pragma unroll
           for (int r = 0; r < kRob; ++r) {
             float s1 = 0.f;
-            spheroid_residual<FINAL>(px[r] - qx[e], py[r] - qy[e], pz[r] - qz[e], ia2, ib2,
+            spheroid_residual<FINAL>(px[r] - qx[e], py[r] - qy[e], pz[r] - qz[e], P.a, P.b,
                                      ir[r] < j ? -P.b : P.b, j != ir[r], vx[r], vy[r], vz[r],
                                      s1);
             if (FINAL) sq[r] += j > ir[r] ? s1 : 0.f;   // each unordered pair once
@@ -214,31 +217,33 @@ __device__ __forceinline__ void sweep3(const FwdArgs& A, const ProbDesc& P, cons
 #pragma unroll
         for (int r = 0; r < kRob; ++r) {
           float s1 = 0.f;
-          spheroid_residual<FINAL>(px[r] - qx, py[r] - qy, pz[r] - qz, ia2, ib2,
+          spheroid_residual<FINAL>(px[r] - qx, py[r] - qy, pz[r] - qz, P.a, P.b,
                                    ir[r] < j ? -P.b : P.b, j != ir[r], vx[r], vy[r], vz[r], s1);
           if (FINAL) sq[r] += j > ir[r] ? s1 : 0.f;
         }
       }
-      // obstacle centres at tau_k = k / (T - 1): c + d tau
+      // obstacle offsets in the obstacle's scaling: (a x' - c - d tau) / a_o
+      // (x' the stored x / a), i.e. x' (a / a_o) - c / a_o - (d / a_o) tau
       const float tau = (float)(k0 + kk) * inv_Tm1;
       for (int m = 0; m < M; ++m) {
         const float* o = L.obs + m * kObsFloats;
-        const float cx = moving ? fmaf(o[6], tau, o[0]) : o[0];
-        const float cy = moving ? fmaf(o[7], tau, o[1]) : o[1];
-        const float cz = moving ? fmaf(o[8], tau, o[2]) : o[2];
-        const float oa = o[3], ob = o[4], tie = -o[5];
+        const float cx = moving ? fmaf(o[7], tau, o[2]) : o[2];
+        const float cy = moving ? fmaf(o[8], tau, o[3]) : o[3];
+        const float cz = moving ? fmaf(o[9], tau, o[4]) : o[4];
+        const float ra = o[0], rb = o[1], oa = o[5], ob = o[6];
 #pragma unroll
         for (int r = 0; r < kRob; ++r)
-          spheroid_residual<FINAL>(px[r] - cx, py[r] - cy, pz[r] - cz, oa, ob, tie, true,
-                                   vx[r], vy[r], vz[r], sq[r]);
+          spheroid_residual<FINAL>(fmaf(px[r], ra, cx), fmaf(py[r], ra, cy), fmaf(pz[r], rb, cz),
+                                   oa, ob, -ob, true, vx[r], vy[r], vz[r], sq[r]);
       }
 #pragma unroll
       for (int r = 0; r < kRob; ++r) {
         if (ir[r] >= n) continue;
         const int u = ir[r] * Tce + kk;
-        const float hx = fmaxf(px[r] - P.pmax[0], 0.f), lx = fmaxf(P.pmin[0] - px[r], 0.f);
-        const float hy = fmaxf(py[r] - P.pmax[1], 0.f), ly = fmaxf(P.pmin[1] - py[r], 0.f);
-        const float hz = fmaxf(pz[r] - P.pmax[2], 0.f), lz = fmaxf(P.pmin[2] - pz[r], 0.f);
+        const float x = P.a * px[r], y = P.a * py[r], z = P.b * pz[r];
+        const float hx = fmaxf(x - P.pmax[0], 0.f), lx = fmaxf(P.pmin[0] - x, 0.f);
+        const float hy = fmaxf(y - P.pmax[1], 0.f), ly = fmaxf(P.pmin[1] - y, 0.f);
+        const float hz = fmaxf(z - P.pmax[2], 0.f), lz = fmaxf(P.pmin[2] - z, 0.f);
         if (FINAL) {
           r1sq += sq[r];
           r2sq += hx * hx + lx * lx + hy * hy + ly * ly + hz * hz + lz * lz;
@@ -315,17 +320,21 @@ __global__ __launch_bounds__(NT) void fwd3_kernel(FwdArgs A) {
   for (int m = tid; m < M; m += NT) {
     const float* o = A.obstacles + (size_t)(P.obs_off + m) * 5;
     float* d = L.obs + m * kObsFloats;
-    d[0] = o[0];
-    d[1] = o[1];
-    d[2] = o[2];
-    d[3] = 1.f / (o[3] * o[3]);
-    d[4] = 1.f / (o[4] * o[4]);
-    d[5] = o[4];
-    // displacement over the horizon (moving obstacles), zero when static
+    // the offset from a robot in the obstacle's scaling (a_o, a_o, b_o), from
+    // the robot's stored scaled position: a / a_o, b / b_o, -c / (a_o, a_o,
+    // b_o), the semi-axes, -d / (a_o, a_o, b_o) for moving obstacles
+    const float ia = 1.f / o[3], ib = 1.f / o[4];
+    d[0] = P.a * ia;
+    d[1] = P.b * ib;
+    d[2] = -o[0] * ia;
+    d[3] = -o[1] * ia;
+    d[4] = -o[2] * ib;
+    d[5] = o[3];
+    d[6] = o[4];
     const float* v = A.ovel ? A.ovel + (size_t)(P.obs_off + m) * 3 : nullptr;
-    d[6] = v ? v[0] : 0.f;
-    d[7] = v ? v[1] : 0.f;
-    d[8] = v ? v[2] : 0.f;
+    d[7] = v ? -v[0] * ia : 0.f;
+    d[8] = v ? -v[1] * ia : 0.f;
+    d[9] = v ? -v[2] * ib : 0.f;
   }
   for (int t = tid; t < S; t += NT) {
     L.xb[0][t] = A.xi0[P.coef_off + t];
