@@ -13,9 +13,9 @@
 // axis.
 //
 // One iteration, in time chunks of Tc steps held in LDS:
-//   positions X = W xi_bar                       [3][n][Tc]
-//   V = F^T r_1 + G^T r_2 per (robot, step)      [3][n][Tc] (every pair visited)
-//   R += W^T V
+//   positions X = W xi_bar (MFMA tiles), stored as x/a, y/a, z/b   [3][n][Tc]
+//   V = F^T r_1 + G^T r_2 per (robot, step), every pair visited    [3][n][Tc]
+//   R += W^T V (MFMA tiles)
 // then lambda' = lambda - rho R, u = lambda - 2 rho R and the mode-form
 // xi_bar' = c_xi + S u + SH xi_bar (S, SH: perpendicular block per robot plus
 // the parallel-minus-perpendicular block on the robot mean).
