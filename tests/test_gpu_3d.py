@@ -85,6 +85,16 @@ def test_3d_chunked_horizon_matches_oracle(gpu):
     _compare(make_batch3d(cfg, batch=1), 12)
 
 
+def test_3d_large_ragged_problem_matches_oracle(gpu):
+    """98 robots (a ragged last group of the four-robots-per-thread stage),
+    13 coefficients (a partial MFMA K step), 77 steps in three LDS time
+    chunks of 26 (partial step tiles), 294 position rows (a partial row
+    tile)."""
+    cfg = scaled3d(WORKLOADS_3D[32], n_robots=(98, 98), n_obs=(7, 7), side=14.0, height=7.0,
+                   n_coef=13, n_steps=77)
+    _compare(make_batch3d(cfg, batch=1), 6)
+
+
 def test_3d_single_robot_without_obstacles_and_zero_iterations(gpu):
     cfg = scaled3d(WORKLOADS_3D[16], n_robots=(1, 1), n_obs=(0, 0), side=2.0, height=1.0)
     probs = make_batch3d(cfg, batch=2)
