@@ -180,3 +180,27 @@ def test_moving_obstacles_are_galilean_equivariant():
     np.testing.assert_allclose(mov.xi_bar - shift, sta.xi_bar, rtol=0, atol=1e-9)
     np.testing.assert_allclose(mov.lam, sta.lam, rtol=0, atol=1e-9)
     assert mov.residual == pytest.approx(sta.residual, rel=1e-8, abs=1e-12)
+
+
+def test_pins_catch_swapped_spheroid_axes(monkeypatch):
+    """A planted mistake in the beta step (a and b swapped) breaks the
+    z-scaling equivariance that the pin above checks."""
+    p = _tight3d(3)
+    L = 20
+    kappa = 1.7
+
+    def wrong_beta(dx, dy, dz, alpha, a, b):
+        rho_xy = dx * np.cos(alpha) + dy * np.sin(alpha)
+        return np.arctan2(rho_xy / b, dz / a)
+
+    monkeypatch.setattr(O, "beta_step", wrong_beta)
+    base = _solve3(p, L)
+    S = np.diag([1.0, 1.0, kappa])
+    obs = p.obstacles.copy()
+    obs[:, 2] *= kappa
+    obs[:, 4] *= kappa
+    got = _solve3(p, L, b=p.b * kappa, obstacles=obs, box=p.box @ S,
+                  xi=np.einsum("xy,yic->xic", S, p.xi), boundary=p.boundary @ S)
+    dev = max(np.max(np.abs(got.xi_bar[:2] - base.xi_bar[:2])),
+              np.max(np.abs(got.xi_bar[2] - kappa * base.xi_bar[2])))
+    assert dev > 1e-6
