@@ -30,10 +30,14 @@
  *   coefficient arrays: [3][n_b][n_coef] per problem (x, then y, then z);
  *   boundary: [sum_b n_b][2][3]; obstacles: [sum_b M_b][5] = x, y, z, a_o, b_o;
  *   robot_a (sf_setup): [B][2] = a, b; box: [B][2][3].
- * The beta step is read as beta = atan2(rho_xy / a, dz / b) with rho_xy =
- * dx cos(alpha) + dy sin(alpha) (the printed dx / (a cos(alpha)) where that is
- * defined), and d as the exact minimiser over d >= 1; together they put e on
- * the ray of Delta.  Only sf_project without SF_SAVE_FOR_BACKWARD, SF_PLAIN and
+ * The paper gives a closed form for the alpha step only (Appendix, after eq.
+ * d_step) and refers the beta and d steps to prior work.  This library reads
+ * them as: beta = atan2(rho_xy / a, dz / b) with rho_xy = dx cos(alpha) +
+ * dy sin(alpha), the polar angle of Delta in the spheroid's scaled coordinates
+ * (for a != b this is not the Euclidean argmin of eq. beta_step with d held
+ * fixed), and d = max(1, s) with s the scaled length of Delta, the exact
+ * minimiser over d >= 1 in scaled coordinates; together they put e on the ray
+ * of Delta.  Only sf_project without SF_SAVE_FOR_BACKWARD, SF_PLAIN and
  * SF_UNFUSED runs for n_dim = 3 (SF_GRAPH and obstacle motion work);
  * sf_project_backward, early exit and sf_smoothness return SF_ERR_INVALID_ARG
  * or SF_ERR_NOT_SAVED.  Each workgroup visits every robot pair.
@@ -112,12 +116,15 @@ typedef struct {
  * The KKT matrix of the xi_bar step (Appendix, "Solution Process": M, with
  * the workspace terms rho G^T G kept) does not depend on xi, so its inverse is
  * factored once here, in FP64 on the host, per distinct (robot, obstacle)
- * count, and stored in float32 (Appendix, eq. batch_comp: "factorizations can
- * be pre-stored"; the factor must be rebuilt when rho or the basis changes).
+ * count, and stored in float32 (Appendix, eq. batch_comp and the remark
+ * before it: the matrix does not depend on the sample, so its factor is
+ * computed ahead of the iterations; it must be rebuilt when rho or the basis
+ * changes).
  *
  *   cfg            host; see sf_config_t.
  *   n_problems     B >= 1.
- *   n_robots       host int32[B], each 1..64.
+ *   n_robots       host int32[B], each 1..1024 (a problem's state must also fit
+ *                  the LDS of one workgroup, else SF_ERR_SHAPE).
  *   n_obs          host int32[B], each 0..4096.
  *   robot_a        host float[B], a > 0 (n_dim = 3: float[B][2] = a, b > 0).
  *   box            host float[B][2][n_dim] = p_min, p_max; p_min < p_max per axis.
@@ -194,6 +201,17 @@ const char* sf_last_error_detail(void);
 
 /* Threads per workgroup the plan's fused kernels use (after autotuning). */
 int sf_plan_threads(const sf_plan_t* plan);
+
+/*
+ * Forward generation of the plan: the number of sf_project calls (and
+ * sf_set_obstacle_motion calls) made on it so far, -1 for a NULL plan.
+ * sf_project_backward always differentiates the latest saved forward; a
+ * caller that keeps several forwards alive (an autograd graph, say) records
+ * the generation right after its sf_project and compares it before
+ * sf_project_backward: a different value means a later call replaced the
+ * saved state that this backward would use.
+ */
+int64_t sf_forward_generation(const sf_plan_t* plan);
 
 /*
  * Optional per-problem early exit of later sf_project calls on this plan

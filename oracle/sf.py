@@ -32,13 +32,18 @@ Readings of the paper that this oracle fixes (each is a named choice):
       the basis) and the sample drops out of eta; everything else is the SF.
   Q1  3D (dim=3, spheroids (a, a, b) and (a_o, a_o, b_o), eqs.
       inter_robot_polar, workspace_polar, f_e): the alpha, beta and d steps
-      are all taken at xi_bar^l (Jacobi order as R13).  alpha = atan2(dy, dx)
-      is the exact minimiser over alpha.  beta = atan2(rho_xy / a, dz / b) with
-      rho_xy = dx cos(alpha) + dy sin(alpha): the printed closed form divides
-      dx by a cos(alpha), which equals rho_xy / a wherever cos(alpha) != 0 and
-      stays defined where it is 0.  d is the exact minimiser over d >= 1 of
-      ||Delta - d u(alpha, beta)||^2.  At Delta = 0: alpha = beta = 0, so
-      u = (0, 0, b) and e = (0, 0, b) (the tie convention of R12 in 3D).
+      are all taken at xi_bar^l (Jacobi order as R13).  The paper prints a
+      closed form for the alpha step only (after eq. d_step) and refers the
+      rest to prior work.  alpha = atan2(dy, dx), the printed form and the
+      exact minimiser over alpha.  beta is this oracle's reading of eq.
+      beta_step: beta = atan2(rho_xy / a, dz / b) with rho_xy = dx cos(alpha) +
+      dy sin(alpha), the polar angle of Delta in the spheroid's scaled
+      coordinates, so that u(alpha, beta) points along Delta.  For a != b this
+      is not the Euclidean argmin over beta with d held at its previous value;
+      for spheres (a = b) it is.  d is the exact least-squares minimiser over
+      d >= 1 of ||Delta - d u(alpha, beta)||^2 with alpha, beta fixed.  At
+      Delta = 0: alpha = beta = 0, so u = (0, 0, b) and e = (0, 0, b) (the tie
+      convention of R12 in 3D).
 """
 from __future__ import annotations
 
@@ -112,15 +117,21 @@ def build_operators(n: int, M: int, n_coef: int, n_steps: int, dim: int = N_DIM)
     Ws = sp.csr_matrix(W)
     D = sp.csr_matrix(pair_incidence(n))
     F_r = sp.kron(D, Ws, format="csr")                                   # R6
-    P = sp.vstack([Ws] * M, format="csr") if M > 0 else sp.csr_matrix((0, n_coef))
-    F_o = sp.block_diag([P] * n, format="csr") if M > 0 else sp.csr_matrix((0, n * n_coef))
+    # Block-diagonal stacks are written as Kronecker products with identities
+    # (I (x) X has X on its diagonal blocks): the same matrices as stacking
+    # the blocks one by one, built without per-block copies.
+    if M > 0:
+        P = sp.kron(np.ones((M, 1)), Ws, format="csr")                    # 1_M (x) W
+        F_o = sp.kron(sp.identity(n, format="csr"), P, format="csr")      # I_n (x) P
+    else:
+        F_o = sp.csr_matrix((0, n * n_coef))
     F_axis = sp.vstack([F_r, F_o], format="csr")
-    Wbar = sp.block_diag([Ws] * n, format="csr")                         # eq. poly
+    Wbar = sp.kron(sp.identity(n, format="csr"), Ws, format="csr")       # eq. poly
     G_axis = sp.vstack([Wbar, -Wbar], format="csr")                      # R7
     A1 = np.stack([W[0], W[-1]])                                         # R17
     A_axis = np.kron(np.eye(n), A1)
-    F = sp.block_diag([F_axis] * dim, format="csr")
-    G = sp.block_diag([G_axis] * dim, format="csr")
+    F = sp.kron(sp.identity(dim, format="csr"), F_axis, format="csr")
+    G = sp.kron(sp.identity(dim, format="csr"), G_axis, format="csr")
     A = sla.block_diag(*([A_axis] * dim))
     return Operators(n, M, n_coef, n_steps, W, F_axis, G_axis, A_axis, F, G, A,
                      F_r.shape[0], F_o.shape[0], dim)

@@ -30,7 +30,7 @@ _ERRORS = {0: "SF_OK", -1: "SF_ERR_INVALID_ARG", -2: "SF_ERR_SHAPE",
 EXPORTED = ("sf_setup", "sf_project", "sf_project_backward", "sf_destroy",
             "sf_error_string", "sf_last_error_detail", "sf_plan_threads", "sf_set_early_exit",
             "sf_project_iterations", "sf_smoothness", "sf_rank_residual", "sf_select_best",
-            "sf_gather_blocks", "sf_set_obstacle_motion")
+            "sf_gather_blocks", "sf_set_obstacle_motion", "sf_forward_generation")
 
 
 class SFError(RuntimeError):
@@ -78,6 +78,8 @@ def load_library(path: Optional[Path] = None) -> ctypes.CDLL:
     lib.sf_last_error_detail.restype = ctypes.c_char_p
     lib.sf_plan_threads.argtypes = [vp]
     lib.sf_plan_threads.restype = ctypes.c_int
+    lib.sf_forward_generation.argtypes = [vp]
+    lib.sf_forward_generation.restype = ctypes.c_int64
     lib.sf_set_early_exit.argtypes = [vp, ctypes.c_float, i32]
     lib.sf_set_early_exit.restype = ctypes.c_int
     lib.sf_project_iterations.argtypes = [vp, vp, vp, vp]
@@ -160,6 +162,11 @@ class SFPlan:
     @property
     def threads(self) -> int:
         return int(self.lib.sf_plan_threads(self._plan))
+
+    @property
+    def generation(self) -> int:
+        """sf_forward_generation: sf_project (and obstacle-motion) calls so far."""
+        return int(self.lib.sf_forward_generation(self._plan))
 
     def set_early_exit(self, tol: float, check_every: int) -> None:
         """sf_set_early_exit: stop a problem once its residual is <= tol at a
@@ -277,7 +284,9 @@ class SFPlan:
 class SFProject(torch.autograd.Function):
     """(xi, xi0, lam0) -> (xi_bar^L, lambda^L, residual[B][4]) through L unrolled SF
     iterations, with the hand-written adjoint of sf_project_backward.  The
-    plan must have max_iters >= n_iters.  fp_weight adds fp_weight * sum_l L_FP^l
+    plan must have max_iters >= n_iters, and the plan holds one saved forward:
+    backward raises SFError (SF_ERR_NOT_SAVED) if another sf_project ran on the
+    plan after this forward.  fp_weight adds fp_weight * sum_l L_FP^l
     (the fixed-point residual terms of the warm-start loss) to the loss being
     differentiated: its gradient is included in the backward."""
 
@@ -288,11 +297,16 @@ class SFProject(torch.autograd.Function):
                                             lam0.contiguous(), boundary, obstacles, n_iters,
                                             save=True)
         ctx.plan = plan
+        ctx.generation = plan.generation
         ctx.fp_weight = float(fp_weight)
         return xi_out, lam_out, res
 
     @staticmethod
     def backward(ctx, g_xi_out, g_lam_out, g_res):
+        if ctx.plan.generation != ctx.generation:
+            # the plan keeps one saved forward: a later call replaced this one's
+            raise SFError(-4, "a later sf_project on this plan replaced the forward this "
+                              "backward belongs to; use one plan per live graph")
         need = ctx.needs_input_grad[:3]
         g_res = None if g_res is None else g_res.contiguous()
         g = ctx.plan.backward(None if g_xi_out is None else g_xi_out.contiguous(),

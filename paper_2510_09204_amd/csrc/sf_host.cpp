@@ -210,6 +210,7 @@ struct sf_plan {
   bool moving = false;        // obstacle displacements set (sf_set_obstacle_motion)
   char* ws = nullptr;
   bool saved = false;
+  int64_t generation = 0;     // sf_project / sf_set_obstacle_motion calls so far
   int saved_L = 0;
   bool saved_early = false;   // the saved forward ran with early exit
   float exit_tol = 0.f;       // early exit (sf_set_early_exit); check_every 0 = off
@@ -669,6 +670,7 @@ int sf_project(sf_plan_t* plan, void* workspace, const float* xi, const float* x
     return fail(SF_ERR_INVALID_ARG, "n_dim = 3 has no early exit");
   hipStream_t s = static_cast<hipStream_t>(stream);
   plan->saved = false;
+  ++plan->generation;
   sf::FwdArgs a = fwd_args(plan, xi, xi0, lam0, boundary, obstacles, n_iters, save, xi_out,
                            lam_out, residual);
   auto launch_fused = [&](const sf::FwdArgs& args, int th) {
@@ -832,6 +834,8 @@ const char* sf_last_error_detail(void) { return g_detail.c_str(); }
 
 int sf_plan_threads(const sf_plan_t* plan) { return plan ? plan->threads : 0; }
 
+int64_t sf_forward_generation(const sf_plan_t* plan) { return plan ? plan->generation : -1; }
+
 int sf_set_early_exit(sf_plan_t* plan, float tol, int32_t check_every) {
   g_detail.clear();
   if (!plan) return fail(SF_ERR_INVALID_ARG, "plan is NULL");
@@ -864,6 +868,7 @@ int sf_set_obstacle_motion(sf_plan_t* plan, void* workspace, const float* displa
   if (workspace != plan->ws)
     return fail(SF_ERR_INVALID_ARG, "workspace differs from the one bound at sf_setup");
   plan->saved = false;   // a saved forward no longer matches the obstacles
+  ++plan->generation;
   if (!displacement) {
     plan->moving = false;
     return SF_OK;

@@ -3,11 +3,15 @@
 //
 // Robots are axis-aligned spheroids (a/2, a/2, b/2) and obstacles spheroids
 // (a_o, a_o, b_o) inflated by the robot (problem formulation; Appendix eqs.
-// inter_robot_polar, workspace_polar).  The alpha, beta and d steps (eqs.
-// alpha_step, beta_step, d_step) with beta = atan2(rho_xy / a, dz / b) put e
-// on the ray of Delta: with s^2 = (dx^2 + dy^2)/a^2 + dz^2/b^2, e = Delta for
-// s >= 1 and e = Delta / s inside, so r_1 = (1 - 1/s) Delta there (and at
-// Delta = 0, alpha = beta = 0 gives e = (0, 0, b)).  The xi_bar step is the
+// inter_robot_polar, workspace_polar).  The paper gives the alpha step's
+// closed form only; the beta step (eq. beta_step) is read here as the polar
+// angle of Delta in the spheroid's scaled coordinates, beta = atan2(rho_xy / a,
+// dz / b) with rho_xy = dx cos(alpha) + dy sin(alpha) (for a != b not the
+// Euclidean argmin with d held fixed), and d (eq. d_step) as the least-squares
+// minimiser over d >= 1.  Together they put e on the ray of Delta: with
+// s^2 = (dx^2 + dy^2)/a^2 + dz^2/b^2, e = Delta for s >= 1 and e = Delta / s
+// inside, so r_1 = (1 - 1/s) Delta there (and at Delta = 0, alpha = beta = 0
+// gives e = (0, 0, b)).  The xi_bar step is the
 // planar one applied per axis: F, G and A are block diagonal over the three
 // axes with identical blocks, so the planar (n, M) factor block serves each
 // axis.

@@ -7,13 +7,14 @@ import numpy as np
 from oracle import SFAdjoint, SFOracle
 from workloads import N_DIM, pack, unpack_coefs
 
-# Tolerances of the GPU path against the FP64 oracle: per problem, relative L2
-# error of the coefficients, and error of the residual norms (metres):
-# 1e-5 absolute at converged scale plus 1e-4 relative, the share of a
-# residual that a 1e-4 relative coefficient error can move.
+# Tolerances of the GPU path against the FP64 oracle, per problem: relative L2
+# error of the coefficients xi_bar and lambda (each against its own oracle
+# norm) 1e-4; the residual norms (metres: the total R4 residual and the
+# fixed-point residual ||z^L - z^{L-1}||) within 1e-5 absolute.  Where the
+# oracle's lambda is exactly zero (no constraint ever active, or L = 0) the
+# lambda error is taken absolute, against a unit scale.
 REL_TOL = 1e-4
 RES_TOL = 1e-5
-RES_REL_TOL = 1e-4
 GRAD_REL_TOL = 1e-3
 
 
@@ -35,15 +36,22 @@ def oracle_inputs(packed, problems):
     return out
 
 
+def oracle_for(inp, rho):
+    """The oracle of one problem's inputs, built once per (inputs, rho): its
+    set-up (explicit F, G and the KKT factor) dominates small runs."""
+    cache = inp.setdefault("_oracles", {})
+    if rho not in cache:
+        cache[rho] = SFOracle(inp["n"], inp["M"], inp["n_coef"], inp["n_steps"], rho, inp["a"],
+                              inp["box"], inp["obstacles"], inp["boundary"])
+    return cache[rho]
+
+
 def oracle_solve(inp, rho, L):
-    orc = SFOracle(inp["n"], inp["M"], inp["n_coef"], inp["n_steps"], rho, inp["a"],
-                   inp["box"], inp["obstacles"], inp["boundary"])
-    return orc.solve(inp["xi"], inp["xi0"], inp["lam0"], L)
+    return oracle_for(inp, rho).solve(inp["xi"], inp["xi0"], inp["lam0"], L)
 
 
 def oracle_grad(inp, rho, L, g_xi_out, g_lam_out, g_r1=0.0, g_r2=0.0, fp_weight=0.0):
-    orc = SFOracle(inp["n"], inp["M"], inp["n_coef"], inp["n_steps"], rho, inp["a"],
-                   inp["box"], inp["obstacles"], inp["boundary"])
+    orc = oracle_for(inp, rho)
     return SFAdjoint(orc).gradient(inp["xi"], inp["xi0"], inp["lam0"], L, g_xi_out,
                                    g_lam_out, g_r1, g_r2, fp_weight)
 
@@ -81,8 +89,7 @@ def rel_err(a, b):
 
 def oracle_residual_terms(inp, rho, xi_bar):
     """||r_1||, ||r_2|| of a given iterate, in FP64."""
-    orc = SFOracle(inp["n"], inp["M"], inp["n_coef"], inp["n_steps"], rho, inp["a"],
-                   inp["box"], inp["obstacles"], inp["boundary"])
+    orc = oracle_for(inp, rho)
     r1, r2, _, _, _ = orc.residual_terms(orc.flat(xi_bar))
     return float(np.linalg.norm(r1)), float(np.linalg.norm(r2))
 
@@ -102,16 +109,37 @@ def oracle_sensitivity(inp, rho, L, eps=1e-7, seed=0):
 ILL_CONDITIONED = 1e-5   # oracle output change under a 1e-7 input change
 
 
+def lam_err(got, ref):
+    """lambda error relative to the oracle's own norm (absolute where that
+    norm is exactly zero)."""
+    scale = float(np.linalg.norm(ref))
+    return float(np.linalg.norm(np.asarray(got, np.float64) - ref) / (scale if scale > 0 else 1.0))
+
+
+def report(tag, errs):
+    """Print a case's largest errors (shown with pytest -s)."""
+    if not errs:
+        return
+    keys = ("xi", "lam", "total", "dz", "own_r1", "own_r2")
+    worst = {k: max(float(e.get(k, 0.0)) for e in errs) for k in keys}
+    print(f"[parity] {tag}: " + ", ".join(f"{k}={v:.2e}" for k, v in worst.items()),
+          flush=True)
+
+
 def compare_forward(problems, out, rho, L, idx=None, rel_tol=REL_TOL, res_tol=RES_TOL,
-                    allow_ill_conditioned=False):
+                    allow_ill_conditioned=False, tag="forward"):
     """Check GPU outputs against the oracle for the problems in `idx`.
 
-    Per problem: the coefficients (xi_bar, lambda) within rel_tol; the GPU's
-    ||r_1||, ||r_2|| equal to the FP64 residual of the GPU's own iterate (the
-    residual computation itself, 1e-5 + 1e-5 relative); the total residual
-    within 1e-5 + 1e-4 relative of the oracle's.  With allow_ill_conditioned, a
-    coefficient mismatch on an instance the oracle itself flags as
-    rounding-decided is recorded instead of failing."""
+    Per problem: xi_bar and lambda within rel_tol of the oracle's (lambda
+    against its own norm); the total residual sqrt(||r_1||^2 + ||r_2||^2) and
+    the fixed-point residual ||z^L - z^{L-1}|| within res_tol (absolute) of the
+    oracle's; the GPU's ||r_1||, ||r_2|| equal to the FP64 residual of the
+    GPU's own iterate (1e-5 + 1e-5 relative: the residual computation itself).
+    With allow_ill_conditioned, a coefficient mismatch on an instance that the
+    oracle itself shows to be rounding-decided (its output moves by more than
+    1e-5 under a 1e-7 input change) is recorded instead of failing; its
+    residual checks still apply, and at least one checked problem must not be
+    waived."""
     inps = oracle_inputs(out["packed"], problems)
     gx = unpack_coefs(out["xi"], problems)
     gl = unpack_coefs(out["lam"], problems)
@@ -119,16 +147,19 @@ def compare_forward(problems, out, rho, L, idx=None, rel_tol=REL_TOL, res_tol=RE
     for b in (range(len(problems)) if idx is None else idx):
         ref = oracle_solve(inps[b], rho, L)
         e_x = rel_err(gx[b], ref.xi_bar)
-        lam_scale = max(np.linalg.norm(ref.lam), np.linalg.norm(ref.xi_bar))
-        e_l = float(np.linalg.norm(gl[b] - ref.lam) / lam_scale)
+        e_l = lam_err(gl[b], ref.lam)
         g1, g2 = float(out["res"][b, 0]), float(out["res"][b, 1])
         o1, o2 = oracle_residual_terms(inps[b], rho, gx[b])
         e_tot = abs(np.hypot(g1, g2) - ref.residual)
+        e_dz = abs(float(out["res"][b, 2]) - ref.res_dz)
         rec = dict(b=b, xi=e_x, lam=e_l, own_r1=abs(g1 - o1), own_r2=abs(g2 - o2),
-                   total=e_tot, res=ref.residual, status=float(out["res"][b, 3]))
+                   total=e_tot, dz=e_dz, res=ref.residual, res_dz=ref.res_dz,
+                   status=float(out["res"][b, 3]))
         errs.append(rec)
         assert rec["status"] == 0.0, rec
         assert rec["own_r1"] <= 1e-5 + 1e-5 * o1 and rec["own_r2"] <= 1e-5 + 1e-5 * o2, rec
+        assert e_tot <= res_tol, rec
+        assert e_dz <= res_tol, rec
         if e_x > rel_tol or e_l > rel_tol:
             if allow_ill_conditioned:
                 sens = oracle_sensitivity(inps[b], rho, L)
@@ -137,7 +168,9 @@ def compare_forward(problems, out, rho, L, idx=None, rel_tol=REL_TOL, res_tol=RE
                     rec["ill_conditioned"] = True
                     continue
             raise AssertionError(rec)
-        assert e_tot <= res_tol + RES_REL_TOL * ref.residual, rec
+    report(tag, errs)
+    assert any(not e.get("ill_conditioned") for e in errs) or not errs, \
+        f"every checked problem was waived as rounding-decided: {errs}"
     return errs
 
 
@@ -162,3 +195,16 @@ def oracle_early_exit(inp, rho, L, tol, every, rel_margin=1e-3):
         if stop:
             return l + 1, orc.shaped(xib), orc.shaped(lam), near
     return L, orc.shaped(xib), orc.shaped(lam), near
+
+
+def check_against(ref, got_xi, got_lam, res_row, rel_tol=REL_TOL, res_tol=RES_TOL):
+    """One problem's GPU outputs (xi_bar, lambda, its residual row) against an
+    oracle SFResult at the tolerances of compare_forward; returns the errors."""
+    rec = dict(xi=rel_err(got_xi, ref.xi_bar), lam=lam_err(got_lam, ref.lam),
+               total=abs(float(np.hypot(res_row[0], res_row[1])) - ref.residual),
+               dz=abs(float(res_row[2]) - ref.res_dz), res=ref.residual, res_dz=ref.res_dz,
+               status=float(res_row[3]))
+    assert rec["status"] == 0.0, rec
+    assert rec["xi"] <= rel_tol and rec["lam"] <= rel_tol, rec
+    assert rec["total"] <= res_tol and rec["dz"] <= res_tol, rec
+    return rec

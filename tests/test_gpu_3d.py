@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 from oracle import SFOracle
-from sf_testlib import REL_TOL, RES_REL_TOL, RES_TOL, rel_err
+from sf_testlib import check_against, rel_err, report
 from workloads import WORKLOADS, make_batch, pack, unpack_coefs
 from workloads.gen3d import WORKLOADS_3D, make_batch3d, pack3d, scaled3d, unpack3d
 
@@ -58,17 +58,12 @@ def _run(probs, L, threads=0, objective=0):
 def _compare(probs, L, objective="projection", **kw):
     pk, xo, lo, res = _run(probs, L, objective=0 if objective == "projection" else 1, **kw)[:4]
     gx, gl = unpack3d(xo, probs), unpack3d(lo, probs)
+    errs = []
     for b, inp in enumerate(_inputs3d(pk, probs)):
         xi = inp["xi"] if objective == "projection" else np.zeros_like(inp["xi"])
         ref = _oracle(inp, objective).solve(xi, inp["xi0"], inp["lam0"], L)
-        assert res[b, 3] == 0.0
-        e = rel_err(gx[b], ref.xi_bar)
-        assert e <= REL_TOL, (b, e)
-        scale = max(np.linalg.norm(ref.lam), np.linalg.norm(ref.xi_bar))
-        assert np.linalg.norm(gl[b] - ref.lam) / scale <= REL_TOL, b
-        got = np.hypot(res[b, 0], res[b, 1])
-        assert abs(got - ref.residual) <= RES_TOL + RES_REL_TOL * ref.residual, \
-            (b, got, ref.residual)
+        errs.append(check_against(ref, gx[b], gl[b], res[b]))
+    report(f"3d {objective} n={probs[0].n} L={L}", errs)
     return pk, xo, lo, res
 
 
@@ -203,7 +198,7 @@ def test_3d_moving_obstacles_match_oracle(gpu, cfg_id, batch, L):
     xo, lo, res = xo.cpu().numpy(), lo.cpu().numpy(), res.cpu().numpy()
     assert not np.array_equal(xo, static[1])
     gx, gl = unpack3d(xo, probs), unpack3d(lo, probs)
-    o = 0
+    o, errs = 0, []
     for b, inp in enumerate(_inputs3d(pk, probs)):
         d = disp[o:o + inp["M"]].astype(np.float64)
         o += inp["M"]
@@ -211,12 +206,8 @@ def test_3d_moving_obstacles_match_oracle(gpu, cfg_id, batch, L):
                        inp["box"], inp["obstacles"], inp["boundary"], dim=3,
                        robot_b=inp["b"], obstacle_displacement=d).solve(
                            inp["xi"], inp["xi0"], inp["lam0"], L)
-        assert res[b, 3] == 0.0
-        assert rel_err(gx[b], ref.xi_bar) <= REL_TOL, b
-        scale = max(np.linalg.norm(ref.lam), np.linalg.norm(ref.xi_bar))
-        assert np.linalg.norm(gl[b] - ref.lam) / scale <= REL_TOL, b
-        got = np.hypot(res[b, 0], res[b, 1])
-        assert abs(got - ref.residual) <= RES_TOL + RES_REL_TOL * ref.residual
+        errs.append(check_against(ref, gx[b], gl[b], res[b]))
+    report("3d moving", errs)
     plan.set_obstacle_motion(None)
     back, _, _ = plan.project(t["xi"], t["xi0"], t["lam0"], t["boundary"], t["obstacles"], L)
     torch.cuda.synchronize()

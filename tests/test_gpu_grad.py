@@ -40,9 +40,13 @@ def _check(problems, pk, grads, L, g_xi, g_lam, g_res=None, fp_weight=0.0, idx=N
         gr2 = 0.0 if g_res is None else float(np.float32(g_res[b, 1]))
         ref = oracle_grad(inps[b], RHO, L, g_xi[b].astype(np.float32).astype(np.float64),
                           g_lam[b].astype(np.float32).astype(np.float64), gr1, gr2, fp_weight)
+        errs = {}
         for name, gv, rv in (("xi", grads[0][b], ref.g_xi), ("xi0", grads[1][b], ref.g_xi0),
                              ("lam0", grads[2][b], ref.g_lam0)):
-            e = rel_err(gv, rv)
+            errs[name] = rel_err(gv, rv)
+        print(f"[grad] L={L} problem {b}: " + ", ".join(f"{k}={v:.2e}" for k, v in errs.items()),
+              flush=True)
+        for name, e in errs.items():
             assert e <= GRAD_REL_TOL, (b, name, e)
 
 
@@ -134,3 +138,63 @@ def test_backward_without_saved_forward_is_an_error(gpu):
         plan.backward(t["xi"], None, None)
     assert e.value.code == -4
     torch.cuda.synchronize()
+
+
+def test_adjoint_c3_problem_at_configured_length(gpu):
+    """32 robots, 20 obstacles, L = 100 (the differentiable workload's own
+    iteration count), checkpoints every 10: two problems of the batch."""
+    probs = make_batch(WORKLOADS[3], batch=2)
+    g_xi, g_lam = _cotangents(probs, 5)
+    pk, grads, _ = _run(probs, 100, 10, g_xi, g_lam)
+    _check(probs, pk, grads, 100, g_xi, g_lam)
+
+
+@pytest.mark.parametrize("pick", [0, 77])
+def test_c5_adjoint_at_configured_length_sampled(gpu, pick):
+    """The large batched workload as configured: all 128 problems (64 robots,
+    50 obstacles, 15 coefficients, 120 steps) in one launch, 200 iterations
+    saved with a checkpoint every 10, then the adjoint; one sampled problem's
+    forward outputs and gradients against the oracle."""
+    import torch
+    from paper_2510_09204_amd import to_device
+    from sf_testlib import compare_forward
+    probs = make_batch(WORKLOADS[5])
+    L, ckpt = 200, 10
+    plan, pk = make_plan(probs, RHO, L=L, ckpt=ckpt)
+    t = to_device(pk)
+    xo, lo, res = plan.project(t["xi"], t["xi0"], t["lam0"], t["boundary"], t["obstacles"], L,
+                               save=True)
+    g_xi, g_lam = _cotangents(probs, 6)
+    gx = torch.from_numpy(np.concatenate([g.ravel() for g in g_xi]).astype(np.float32)).cuda()
+    gl = torch.from_numpy(np.concatenate([g.ravel() for g in g_lam]).astype(np.float32)).cuda()
+    g = plan.backward(gx, gl, None)
+    torch.cuda.synchronize()
+    print(f"[c5] GPU forward + adjoint done, oracle on problem {pick}", flush=True)
+    out = dict(packed=pk, xi=xo.cpu().numpy(), lam=lo.cpu().numpy(), res=res.cpu().numpy())
+    assert np.all(out["res"][:, 3] == 0.0)
+    for x in g:
+        assert torch.isfinite(x).all()
+    compare_forward(probs, out, RHO, L, idx=[pick], tag=f"c5 L=200 problem {pick}")
+    print("[c5] forward parity done, oracle adjoint next", flush=True)
+    grads = [unpack_coefs(x.cpu().numpy(), probs) for x in g]
+    _check(probs, pk, grads, L, g_xi, g_lam, idx=[pick])
+
+
+def test_second_forward_before_backward_is_an_error(gpu):
+    """A plan keeps one saved forward: a backward through a graph whose
+    forward was replaced by a later SFProject on the same plan raises instead
+    of returning the later forward's gradient; the later graph still works."""
+    import torch
+    from paper_2510_09204_amd import SFError, SFProject, to_device
+    probs = make_batch(WORKLOADS[3], batch=1)
+    plan, pk = make_plan(probs, RHO, L=10)
+    t = to_device(pk)
+    xi = t["xi"].clone().requires_grad_(True)
+    xo1, _, _ = SFProject.apply(xi, t["xi0"], t["lam0"], t["boundary"], t["obstacles"], plan, 10)
+    xo2, _, _ = SFProject.apply(xi, t["xi0"], t["lam0"], t["boundary"], t["obstacles"], plan, 5)
+    with pytest.raises(SFError) as e:
+        xo1.sum().backward()
+    assert e.value.code == -4
+    xo2.sum().backward()
+    torch.cuda.synchronize()
+    assert torch.isfinite(xi.grad).all() and xi.grad.abs().sum() > 0

@@ -242,3 +242,29 @@ def test_nonfinite_input_is_flagged_not_crashed(gpu):
     out = gpu_forward(probs, RHO, 10, packed=pk)
     assert out["res"][0, 3] == 1.0
     assert out["res"][1, 3] == 0.0
+
+
+def test_c3_benchmark_configuration_adjoint_sampled(gpu):
+    """The benchmark's fwd+bwd launch (64 problems, L* = 2000, every iterate
+    saved): the adjoint of one sampled problem against the oracle's reverse
+    sweep over all 2000 iterations, for the cotangent of sum(xi_bar^L)."""
+    import torch
+    from sf_testlib import GRAD_REL_TOL, oracle_grad, oracle_inputs
+    from workloads import unpack_coefs
+    probs = make_batch(WORKLOADS[3])
+    L, pick = 2000, 5
+    plan, _ = make_plan(probs, RHO, L=L, ckpt=1, threads=0)
+    out = gpu_forward(probs, RHO, L, save=True, plan=plan)
+    g = plan.backward(torch.ones_like(out["t"]["xi"]), None, None)
+    torch.cuda.synchronize()
+    print(f"[c3 L=2000] GPU done, oracle adjoint on problem {pick}", flush=True)
+    grads = [unpack_coefs(x.cpu().numpy(), probs)[pick] for x in g]
+    inp = oracle_inputs(out["packed"], probs)[pick]
+    ones = np.ones_like(inp["xi"])
+    ref = oracle_grad(inp, RHO, L, ones, np.zeros_like(ones))
+    errs = {k: rel_err(gv, rv) for k, gv, rv in zip(("xi", "xi0", "lam0"), grads,
+                                                    (ref.g_xi, ref.g_xi0, ref.g_lam0))}
+    print(f"[grad] c3 L=2000 problem {pick}: residual {out['res'][pick, :2]}, "
+          + ", ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
+    for k, e in errs.items():
+        assert e <= GRAD_REL_TOL, (k, e)

@@ -139,6 +139,7 @@ def test_calls_without_plan_fail_cleanly(lib):
                                    None) == -1
     lib.sf_destroy(None)
     assert lib.sf_plan_threads(None) == 0
+    assert lib.sf_forward_generation(None) == -1
     assert lib.sf_set_early_exit(None, 1e-3, 10) == -1
     assert lib.sf_project_iterations(None, None, None, None) == -1
     assert lib.sf_smoothness(None, None, None, 5.0, None, None) == -1
