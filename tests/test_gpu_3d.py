@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 from oracle import SFOracle
-from sf_testlib import check_against, rel_err, report
+from sf_testlib import check_against, finish_parity, rel_err, report
 from workloads import WORKLOADS, make_batch, pack, unpack_coefs
 from workloads.gen3d import WORKLOADS_3D, make_batch3d, pack3d, scaled3d, unpack3d
 
@@ -55,7 +55,7 @@ def _run(probs, L, threads=0, objective=0):
     return pk, xo.cpu().numpy(), lo.cpu().numpy(), res.cpu().numpy(), plan, t
 
 
-def _compare(probs, L, objective="projection", **kw):
+def _compare(probs, L, objective="projection", final=True, **kw):
     pk, xo, lo, res = _run(probs, L, objective=0 if objective == "projection" else 1, **kw)[:4]
     gx, gl = unpack3d(xo, probs), unpack3d(lo, probs)
     errs = []
@@ -64,7 +64,9 @@ def _compare(probs, L, objective="projection", **kw):
         ref = _oracle(inp, objective).solve(xi, inp["xi0"], inp["lam0"], L)
         errs.append(check_against(ref, gx[b], gl[b], res[b]))
     report(f"3d {objective} n={probs[0].n} L={L}", errs)
-    return pk, xo, lo, res
+    if final:
+        finish_parity(errs)
+    return pk, xo, lo, res, errs
 
 
 @pytest.mark.parametrize("cfg_id,batch,L", [(16, 3, 60), (48, 6, 40), (32, 2, 40)])
@@ -93,11 +95,12 @@ def test_3d_large_ragged_problem_matches_oracle(gpu):
 def test_3d_single_robot_without_obstacles_and_zero_iterations(gpu):
     cfg = scaled3d(WORKLOADS_3D[16], n_robots=(1, 1), n_obs=(0, 0), side=2.0, height=1.0)
     probs = make_batch3d(cfg, batch=2)
-    _compare(probs, 25)
+    errs = _compare(probs, 25, final=False)[4]
     pk, xo, lo, res = _run(probs, 0)[:4]
     np.testing.assert_array_equal(xo, pk.xi0)
     np.testing.assert_array_equal(lo, pk.lam0)
     assert np.all(res[:, 2] == 0.0)
+    finish_parity(errs)
 
 
 def test_3d_accel_objective_matches_oracle(gpu):
@@ -212,3 +215,4 @@ def test_3d_moving_obstacles_match_oracle(gpu, cfg_id, batch, L):
     back, _, _ = plan.project(t["xi"], t["xi0"], t["lam0"], t["boundary"], t["obstacles"], L)
     torch.cuda.synchronize()
     np.testing.assert_array_equal(back.cpu().numpy(), static[1])
+    finish_parity(errs)

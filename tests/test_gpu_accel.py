@@ -6,7 +6,7 @@ import pytest
 
 from oracle import SFOracle
 from oracle.adjoint import SFAdjoint
-from sf_testlib import GRAD_REL_TOL, check_against, oracle_inputs, rel_err, report
+from sf_testlib import GRAD_REL_TOL, check_against, finish_parity, oracle_inputs, rel_err, report
 from workloads import WORKLOADS, make_batch, make_problem, pack, scaled, unpack_coefs
 
 pytestmark = pytest.mark.gpu
@@ -48,6 +48,7 @@ def test_accel_objective_matches_oracle(gpu, cfg_id, batch, L):
         ref = _oracle(inp).solve(np.zeros_like(inp["xi"]), inp["xi0"], inp["lam0"], L)
         errs.append(check_against(ref, gx[b], gl[b], res[b]))
     report(f"accel c{cfg_id}", errs)
+    finish_parity(errs)
 
 
 def test_accel_objective_plain_path_matches_fused_bitwise(gpu):

@@ -5,7 +5,8 @@ import pytest
 
 from oracle import SFOracle
 from oracle.adjoint import SFAdjoint
-from sf_testlib import GRAD_REL_TOL, check_against, make_plan, oracle_inputs, rel_err, report
+from sf_testlib import (GRAD_REL_TOL, check_against, finish_parity, make_plan, oracle_inputs,
+                        rel_err, report)
 from workloads import WORKLOADS, make_batch, make_problem, pack, scaled, unpack_coefs
 
 pytestmark = pytest.mark.gpu
@@ -58,6 +59,7 @@ def test_moving_obstacles_match_oracle(gpu, cfg_id, batch, L):
         ref = _oracle(inp, d).solve(inp["xi"], inp["xi0"], inp["lam0"], L)
         errs.append(check_against(ref, gx[b], gl[b], res[b]))
     report(f"moving c{cfg_id}", errs)
+    finish_parity(errs)
 
 
 def test_moving_obstacles_plain_path_matches_fused_bitwise(gpu):
