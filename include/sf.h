@@ -189,6 +189,26 @@ int sf_project_backward(sf_plan_t* plan, void* workspace, const float* g_xi_out,
                         const float* g_lam_out, const float* g_residual, float fp_weight,
                         float* g_xi, float* g_xi0, float* g_lam0, void* stream);
 
+/*
+ * sf_project_backward for callers that cannot allocate device memory (code
+ * under graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same reverse sweep and the same results, bit for bit, but the iterates a
+ * checkpoint segment recomputes go to a static device array of the library
+ * (32 MiB per GPU, held from the first use on that GPU until the process ends)
+ * instead of the plan's workspace, and the thread count is not autotuned (the
+ * plan's current choice is used).  The call allocates nothing.
+ *
+ * Same arguments, layouts and errors as sf_project_backward, plus
+ * SF_ERR_SHAPE when the recompute area, 8 * checkpoint_every * (floats of one
+ * coefficient array of the batch) bytes, exceeds 32 MiB.  Every call on one
+ * GPU shares the array: calls that overlap in time on one GPU (other streams,
+ * other threads, other plans) race and must be serialised by the caller.
+ */
+int sf_project_backward_static(sf_plan_t* plan, void* workspace, const float* g_xi_out,
+                               const float* g_lam_out, const float* g_residual,
+                               float fp_weight, float* g_xi, float* g_xi0, float* g_lam0,
+                               void* stream);
+
 /* Free the plan (host memory and cached graphs).  NULL is accepted.  The
  * workspace stays the caller's. */
 void sf_destroy(sf_plan_t* plan);

@@ -30,7 +30,8 @@ _ERRORS = {0: "SF_OK", -1: "SF_ERR_INVALID_ARG", -2: "SF_ERR_SHAPE",
 EXPORTED = ("sf_setup", "sf_project", "sf_project_backward", "sf_destroy",
             "sf_error_string", "sf_last_error_detail", "sf_plan_threads", "sf_set_early_exit",
             "sf_project_iterations", "sf_smoothness", "sf_rank_residual", "sf_select_best",
-            "sf_gather_blocks", "sf_set_obstacle_motion", "sf_forward_generation")
+            "sf_gather_blocks", "sf_set_obstacle_motion", "sf_forward_generation",
+            "sf_project_backward_static")
 
 
 class SFError(RuntimeError):
@@ -70,6 +71,8 @@ def load_library(path: Optional[Path] = None) -> ctypes.CDLL:
     lib.sf_project_backward.argtypes = [vp, vp, f32p, f32p, f32p, ctypes.c_float, f32p, f32p,
                                         f32p, vp]
     lib.sf_project_backward.restype = ctypes.c_int
+    lib.sf_project_backward_static.argtypes = lib.sf_project_backward.argtypes
+    lib.sf_project_backward_static.restype = ctypes.c_int
     lib.sf_destroy.argtypes = [vp]
     lib.sf_destroy.restype = None
     lib.sf_error_string.argtypes = [ctypes.c_int]
@@ -263,8 +266,11 @@ class SFPlan:
         return xi_out, lam_out, res
 
     def backward(self, g_xi_out=None, g_lam_out=None, g_residual=None, fp_weight: float = 0.0,
-                 need=(True, True, True)):
-        """Run sf_project_backward; returns (g_xi, g_xi0, g_lam0) (None where not needed)."""
+                 need=(True, True, True), out=None, static_area: bool = False):
+        """Run sf_project_backward (sf_project_backward_static with
+        static_area: the recompute area is the library's static device array
+        and nothing is allocated there); returns (g_xi, g_xi0, g_lam0) (None
+        where not needed).  `out` may supply the three output tensors."""
         for t, name in ((g_xi_out, "g_xi_out"), (g_lam_out, "g_lam_out")):
             if t is not None:
                 self._coef(t, name)
@@ -272,9 +278,14 @@ class SFPlan:
                                        or g_residual.dtype != torch.float32
                                        or not g_residual.is_contiguous()):
             raise SFError(-2, "g_residual must be contiguous float32 [B][4]")
-        outs = [torch.empty(self.coef_size, dtype=torch.float32, device=self.device)
-                if need[q] else None for q in range(3)]
-        _check(self.lib, self.lib.sf_project_backward(
+        if out is None:
+            outs = [torch.empty(self.coef_size, dtype=torch.float32, device=self.device)
+                    if need[q] else None for q in range(3)]
+        else:
+            outs = [None if t is None else self._coef(t, "gradient output") for t in out]
+        call = self.lib.sf_project_backward_static if static_area else \
+            self.lib.sf_project_backward
+        _check(self.lib, call(
             self._plan, ctypes.c_void_p(self.workspace.data_ptr()), _ptr(g_xi_out),
             _ptr(g_lam_out), _ptr(g_residual), float(fp_weight), _ptr(outs[0]),
             _ptr(outs[1]), _ptr(outs[2]), self._stream()))

@@ -612,6 +612,10 @@ int sf_setup(const sf_config_t* cfg, int32_t n_problems, const int32_t* n_robots
     SF_HIP_CHECK(sf::prepare_kernels3(p->lds_fwd));
   else
     SF_HIP_CHECK(sf::prepare_kernels(std::max(p->lds_fwd, p->lds_bwd)));
+  {
+    void* area = nullptr;   // look up the static recompute area on this device once
+    SF_HIP_CHECK(sf::static_scratch(&area));
+  }
   p->ws = static_cast<char*>(workspace);
   hipStream_t s = static_cast<hipStream_t>(stream);
   SF_HIP_CHECK(hipMemcpyAsync(p->ws + p->off_desc, p->desc.data(),
@@ -752,9 +756,16 @@ int sf_project(sf_plan_t* plan, void* workspace, const float* xi, const float* x
   return SF_OK;
 }
 
-int sf_project_backward(sf_plan_t* plan, void* workspace, const float* g_xi_out,
-                        const float* g_lam_out, const float* g_residual, float fp_weight,
-                        float* g_xi, float* g_xi0, float* g_lam0, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// sf_project_backward and its variant without a workspace recompute area:
+// with `static_area` the segment recompute goes to the library's static device
+// array, and the call neither autotunes (that creates events) nor allocates.
+int backward_impl(sf_plan_t* plan, void* workspace, const float* g_xi_out,
+                  const float* g_lam_out, const float* g_residual, float fp_weight,
+                  float* g_xi, float* g_xi0, float* g_lam0, void* stream, bool static_area) {
   g_detail.clear();
   if (!plan) return fail(SF_ERR_INVALID_ARG, "plan is NULL");
   if (workspace != plan->ws)
@@ -772,7 +783,19 @@ int sf_project_backward(sf_plan_t* plan, void* workspace, const float* g_xi_out,
   a.ovel = plan->moving ? plan->at<float>(plan->off_ovel) : nullptr;
   a.ckpt = plan->at<float>(plan->off_ckpt);
   a.fin = plan->at<float>(plan->off_final);
-  a.seg = plan->at<float>(plan->off_seg);
+  if (static_area) {
+    const size_t need = sizeof(float) * 2 * (size_t)plan->S_total *
+                        (size_t)plan->cfg.checkpoint_every;
+    if (need > sf::kStaticScratchBytes)
+      return fail(SF_ERR_SHAPE, "recompute area of " + std::to_string(need) +
+                                    " bytes exceeds the static area of " +
+                                    std::to_string(sf::kStaticScratchBytes) + " bytes");
+    void* area = nullptr;
+    SF_HIP_CHECK(sf::static_scratch(&area));
+    a.seg = static_cast<float*>(area);
+  } else {
+    a.seg = plan->at<float>(plan->off_seg);
+  }
   a.g_xi_out = g_xi_out;
   a.g_lam_out = g_lam_out;
   a.g_res = g_residual;
@@ -792,7 +815,7 @@ int sf_project_backward(sf_plan_t* plan, void* workspace, const float* g_xi_out,
   a.ckpt_every = plan->cfg.checkpoint_every;
   a.rho = (float)plan->cfg.rho;
   a.fp_weight = fp_weight;
-  if (plan->tune_bwd && a.L > 0 && !stream_capturing(s)) {
+  if (!static_area && plan->tune_bwd && a.L > 0 && !stream_capturing(s)) {
     const std::string key = tune_key(plan, true);
     int t = 0;
     if (!tune_lookup(key, t)) {
@@ -813,6 +836,25 @@ int sf_project_backward(sf_plan_t* plan, void* workspace, const float* g_xi_out,
   if (g_xi && plan->cfg.objective == SF_OBJECTIVE_ACCEL)
     SF_HIP_CHECK(sf::launch_fill(g_xi, 0.f, plan->S_total, s));   // xi is not an input there
   return SF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sf_project_backward(sf_plan_t* plan, void* workspace, const float* g_xi_out,
+                        const float* g_lam_out, const float* g_residual, float fp_weight,
+                        float* g_xi, float* g_xi0, float* g_lam0, void* stream) {
+  return backward_impl(plan, workspace, g_xi_out, g_lam_out, g_residual, fp_weight, g_xi,
+                       g_xi0, g_lam0, stream, false);
+}
+
+int sf_project_backward_static(sf_plan_t* plan, void* workspace, const float* g_xi_out,
+                               const float* g_lam_out, const float* g_residual,
+                               float fp_weight, float* g_xi, float* g_xi0, float* g_lam0,
+                               void* stream) {
+  return backward_impl(plan, workspace, g_xi_out, g_lam_out, g_residual, fp_weight, g_xi,
+                       g_xi0, g_lam0, stream, true);
 }
 
 void sf_destroy(sf_plan_t* plan) { delete plan; }

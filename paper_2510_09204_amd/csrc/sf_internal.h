@@ -122,6 +122,11 @@ hipError_t launch_fill(float* p, float v, int64_t n, hipStream_t s);
 // Floats of the plain path's per-window partial buffer for `coef` coefficients.
 size_t plain_part_floats(int T, int64_t coef);
 
+// Device address, on the current device, of the library's static recompute
+// area of kStaticScratchBytes bytes (looked up once per device).
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;
+hipError_t static_scratch(void** ptr);
+
 // Raise the dynamic-LDS limit of the fused kernels to `lds` bytes.
 hipError_t prepare_kernels(size_t lds);
 

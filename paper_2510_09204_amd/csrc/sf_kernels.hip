@@ -47,6 +47,8 @@
 // (window multiple + 1) to spread robots over LDS banks; W as [T][nc].
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "sf_internal.h"
 
 namespace sf {
@@ -1930,6 +1932,37 @@ hipError_t launch_bwd_ks(const BwdArgs& a, int threads, size_t lds, hipStream_t 
 hipError_t launch_bwd_fused(const BwdArgs& a, int threads, size_t lds, hipStream_t s) {
   return ks_class(a.nc) == 4 ? launch_bwd_ks<4>(a, threads, lds, s)
                              : launch_bwd_ks<8>(a, threads, lds, s);
+}
+
+// Recompute area of the adjoint for callers that cannot allocate device
+// memory (sf_project_backward_static): a file-scope device array, one copy per
+// GPU, that lives until the process ends.  In host code `scratch` names a
+// host-side stand-in, so host code only ever uses the device address that
+// hipGetSymbolAddress returns for the current device.  The reverse sweep
+// writes every slot before it reads it, so nothing has to be cleared between
+// calls; calls that overlap on one GPU share the array and race.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch(void** ptr) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 hipError_t prepare_kernels(size_t lds) {

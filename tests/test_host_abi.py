@@ -137,6 +137,8 @@ def test_calls_without_plan_fail_cleanly(lib):
                           None) == -1
     assert lib.sf_project_backward(None, None, None, None, None, 0.0, None, None, None,
                                    None) == -1
+    assert lib.sf_project_backward_static(None, None, None, None, None, 0.0, None, None,
+                                          None, None) == -1
     lib.sf_destroy(None)
     assert lib.sf_plan_threads(None) == 0
     assert lib.sf_forward_generation(None) == -1
