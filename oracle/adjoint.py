@@ -16,6 +16,12 @@ Inputs receiving gradients: the flow sample xi, xi_bar^0, lambda^0.
 
 Non-smooth points follow the forward tie conventions (R12): d = 1 exactly and
 x exactly on a box bound are inactive, atan2(0, 0) has zero derivative.
+
+3D (dim=3, reading Q1): the chain runs through the alpha step (atan2 of the
+horizontal components), the beta step (atan2 of the scaled horizontal and
+vertical components), the spheroid direction u(alpha, beta) and the clipped
+least-squares d step, in that order; everything after e is the planar chain
+with three axis blocks.
 """
 from __future__ import annotations
 
@@ -53,6 +59,55 @@ def _e_vjp(dx, dy, size, g_ex, g_ey):
     return g_dx, g_dy
 
 
+def _e3_vjp(dx, dy, dz, a, b, g_ex, g_ey, g_ez):
+    """Cotangent of Delta = (dx, dy, dz) given that of e - centre = d u(alpha,
+    beta), u = (a cos(alpha) sin(beta), a sin(alpha) sin(beta), b cos(beta)),
+    with alpha = atan2(dy, dx), beta = atan2(rho_xy / a, dz / b), rho_xy =
+    dx cos(alpha) + dy sin(alpha), and d = max(1, <Delta, u> / <u, u>)."""
+    rr = dx * dx + dy * dy
+    safe = np.where(rr > 0.0, rr, 1.0)
+    alpha = np.arctan2(dy, dx)
+    ca, sa = np.cos(alpha), np.sin(alpha)
+    rho_xy = dx * ca + dy * sa
+    Y, X = rho_xy / a, dz / b
+    beta = np.arctan2(Y, X)
+    cb, sb = np.cos(beta), np.sin(beta)
+    ux, uy, uz = a * ca * sb, a * sa * sb, b * cb
+    num = dx * ux + dy * uy + dz * uz
+    den = ux * ux + uy * uy + uz * uz
+    d_unc = num / den
+    d = np.maximum(1.0, d_unc)
+    # e = d u
+    g_d = g_ex * ux + g_ey * uy + g_ez * uz
+    g_ux, g_uy, g_uz = d * g_ex, d * g_ey, d * g_ez
+    # d = max(1, num / den); the tie d_unc = 1 takes the unclipped branch
+    pass_d = d_unc >= 1.0
+    g_num = np.where(pass_d, g_d / den, 0.0)
+    g_den = np.where(pass_d, -g_d * num / (den * den), 0.0)
+    g_dx, g_dy, g_dz = g_num * ux, g_num * uy, g_num * uz
+    g_ux = g_ux + g_num * dx + 2.0 * g_den * ux
+    g_uy = g_uy + g_num * dy + 2.0 * g_den * uy
+    g_uz = g_uz + g_num * dz + 2.0 * g_den * uz
+    # u(alpha, beta)
+    g_alpha = a * sb * (-g_ux * sa + g_uy * ca)
+    g_beta = a * cb * (g_ux * ca + g_uy * sa) - b * sb * g_uz
+    # beta = atan2(Y, X), zero derivative at (0, 0)
+    r2 = X * X + Y * Y
+    safe2 = np.where(r2 > 0.0, r2, 1.0)
+    g_Y = np.where(r2 > 0.0, g_beta * X / safe2, 0.0)
+    g_X = np.where(r2 > 0.0, -g_beta * Y / safe2, 0.0)
+    g_dz = g_dz + g_X / b
+    g_rho = g_Y / a
+    # rho_xy = dx cos(alpha) + dy sin(alpha)
+    g_dx = g_dx + g_rho * ca
+    g_dy = g_dy + g_rho * sa
+    g_alpha = g_alpha + g_rho * (-dx * sa + dy * ca)
+    # alpha = atan2(dy, dx), zero derivative at (0, 0)
+    g_dx = g_dx + np.where(rr > 0.0, -dy / safe, 0.0) * g_alpha
+    g_dy = g_dy + np.where(rr > 0.0, dx / safe, 0.0) * g_alpha
+    return g_dx, g_dy, g_dz
+
+
 @dataclass
 class SFGrad:
     g_xi: np.ndarray
@@ -62,34 +117,38 @@ class SFGrad:
 
 class SFAdjoint:
     def __init__(self, orc: SFOracle):
-        if orc.dim != 2:
-            raise NotImplementedError("the oracle adjoint covers the 2D SF")
         self.o = orc
 
     def _geometry(self, q):
         """Split F xi_bar into pair differences and obstacle offsets per axis."""
         o = self.o
         R = o.ops.n_pair_rows + o.ops.n_obs_rows
-        comp = split_axes(q, R)
+        comp = split_axes(q, R, o.dim)
         Pr = o.ops.n_pair_rows
-        pdx, pdy = comp[0][:Pr], comp[1][:Pr]
-        odx = comp[0][Pr:] - o.obs_cen[0]
-        ody = comp[1][Pr:] - o.obs_cen[1]
-        return pdx, pdy, odx, ody
+        pair = [comp[ax][:Pr] for ax in range(o.dim)]
+        obs = [comp[ax][Pr:] - o.obs_cen[ax] for ax in range(o.dim)]
+        return pair, obs
 
     def _eT(self, q, g_e):
         """J_E(q)^T g_e for e(q) stacked like F's rows."""
         o = self.o
         R = o.ops.n_pair_rows + o.ops.n_obs_rows
         Pr = o.ops.n_pair_rows
-        pdx, pdy, odx, ody = self._geometry(q)
-        gx, gy = split_axes(g_e, R)
-        out_x = np.zeros(R)
-        out_y = np.zeros(R)
-        out_x[:Pr], out_y[:Pr] = _e_vjp(pdx, pdy, o.a, gx[:Pr], gy[:Pr])
-        if o.ops.M > 0:
-            out_x[Pr:], out_y[Pr:] = _e_vjp(odx, ody, o.obs_ao, gx[Pr:], gy[Pr:])
-        return np.concatenate([out_x, out_y])
+        pair, obs = self._geometry(q)
+        g = split_axes(g_e, R, o.dim)
+        out = [np.zeros(R) for _ in range(o.dim)]
+        if o.dim == 2:
+            res_p = _e_vjp(*pair, o.a, *(gq[:Pr] for gq in g))
+            res_o = _e_vjp(*obs, o.obs_ao, *(gq[Pr:] for gq in g)) if o.ops.M > 0 else None
+        else:
+            res_p = _e3_vjp(*pair, o.a, o.robot_b, *(gq[:Pr] for gq in g))
+            res_o = _e3_vjp(*obs, o.obs_ao[0], o.obs_ao[1], *(gq[Pr:] for gq in g)) \
+                if o.ops.M > 0 else None
+        for ax in range(o.dim):
+            out[ax][:Pr] = res_p[ax]
+            if res_o is not None:
+                out[ax][Pr:] = res_o[ax]
+        return np.concatenate(out)
 
     def gradient(self, xi, xi0, lam0, n_iters, g_xi_bar, g_lam, g_res1=0.0,
                  g_res2=0.0, fp_weight=0.0) -> SFGrad:

@@ -204,3 +204,94 @@ def test_pins_catch_swapped_spheroid_axes(monkeypatch):
     dev = max(np.max(np.abs(got.xi_bar[:2] - base.xi_bar[:2])),
               np.max(np.abs(got.xi_bar[2] - kappa * base.xi_bar[2])))
     assert dev > 1e-6
+
+
+# ---------------------------------------------------------------- 3D adjoint
+def _kink_margin3(orc, its):
+    """Smallest distance of any pair/obstacle scaled length from 1 (the d
+    step's clip) and of any box coordinate from its bound."""
+    o = orc.ops
+    R, Pr = o.n_pair_rows + o.n_obs_rows, o.n_pair_rows
+    m = np.inf
+    for xib, _ in its:
+        q = o.F @ xib
+        x, y, z = q[:R], q[R:2 * R], q[2 * R:]
+        s = np.sqrt((x[:Pr] ** 2 + y[:Pr] ** 2) / orc.a ** 2 + z[:Pr] ** 2 / orc.robot_b ** 2)
+        m = min(m, np.min(np.abs(s - 1.0))) if Pr else m
+        if o.M:
+            ox, oy, oz = (x[Pr:] - orc.obs_cen[0], y[Pr:] - orc.obs_cen[1],
+                          z[Pr:] - orc.obs_cen[2])
+            so = np.sqrt((ox ** 2 + oy ** 2) / orc.obs_ao[0] ** 2 + oz ** 2 / orc.obs_ao[1] ** 2)
+            m = min(m, np.min(np.abs(so - 1.0)))
+        m = min(m, np.min(np.abs(o.G @ xib - orc.h)))
+    return m
+
+
+@pytest.fixture(scope="module")
+def fd3_case():
+    p = _tight3d(4)
+    orc = O.SFOracle(p.n, p.M, p.n_coef, p.n_steps, RHO, p.a, p.box, p.obstacles, p.boundary,
+                     dim=3, robot_b=p.b)
+    return p, orc, np.random.default_rng(21)
+
+
+def _fd_check(p, orc, rng, L, wr1, wr2, fp_weight, adjoint_cls=None, tol=1e-6):
+    from oracle.adjoint import SFAdjoint, loss_value
+    adjoint_cls = adjoint_cls or SFAdjoint
+    lam0 = 0.05 * rng.standard_normal(p.xi.shape)
+    its = orc.solve(p.xi, p.xi, lam0, L, keep_iterates=True).iterates
+    assert _kink_margin3(orc, its) > 1e-4
+    w_xi = rng.standard_normal(p.xi.shape)
+    w_lam = rng.standard_normal(p.xi.shape)
+    g = adjoint_cls(orc).gradient(p.xi, p.xi, lam0, L, w_xi, w_lam, wr1, wr2, fp_weight)
+    h = 1e-6
+    worst = 0.0
+    for which, gv in ((0, g.g_xi), (1, g.g_xi0), (2, g.g_lam0)):
+        for _ in range(4):
+            idx = tuple(int(rng.integers(0, s)) for s in p.xi.shape)
+            args = [p.xi.copy(), p.xi.copy(), lam0.copy()]
+            args[which][idx] += h
+            fp = loss_value(orc, *args, L, w_xi, w_lam, wr1, wr2, fp_weight)
+            args[which][idx] -= 2 * h
+            fm = loss_value(orc, *args, L, w_xi, w_lam, wr1, wr2, fp_weight)
+            fd = (fp - fm) / (2 * h)
+            worst = max(worst, abs(fd - gv[idx]) / max(1.0, abs(fd)))
+    return worst
+
+
+@pytest.mark.parametrize("fp_weight,wr1,wr2", [(0.0, 0.0, 0.0), (0.3, 0.8, 0.5)])
+def test_3d_oracle_adjoint_matches_central_finite_differences(fd3_case, fp_weight, wr1, wr2):
+    """The reverse sweep through the alpha, beta and d steps (reading Q1) against
+    central differences (h = 1e-6) of the loss it differentiates."""
+    p, orc, rng = fd3_case
+    hist = orc.solve(p.xi, n_iters=15, keep_history=True).history
+    assert hist[0, 0] > 1e-3                    # spheroid constraints were active
+    assert _fd_check(p, orc, rng, 15, wr1, wr2, fp_weight) <= 1e-6
+
+
+def test_3d_oracle_adjoint_dot_product_identity(fd3_case):
+    """<J v, w> = <v, J^T w> for the Jacobian of xi_bar^L w.r.t. lambda^0."""
+    from oracle.adjoint import SFAdjoint
+    p, orc, rng = fd3_case
+    L = 12
+    v = rng.standard_normal(p.xi.shape)
+    w = rng.standard_normal(p.xi.shape)
+    g = SFAdjoint(orc).gradient(p.xi, p.xi, None, L, w, np.zeros_like(w))
+    h = 1e-6
+    jv = (orc.solve(p.xi, p.xi, h * v, L).xi_bar - orc.solve(p.xi, p.xi, -h * v, L).xi_bar) / (2 * h)
+    assert abs(np.sum(jv * w) - np.sum(v * g.g_lam0)) < 1e-6 * max(1.0, abs(np.sum(jv * w)))
+
+
+def test_3d_adjoint_pins_catch_swapped_spheroid_axes(fd3_case, monkeypatch):
+    """A planted mistake in the reverse sweep (the spheroid sizes a and b
+    swapped in the reverse alpha/beta/d chain) fails the finite-difference
+    pin."""
+    import oracle.adjoint as A
+    p, orc, _ = fd3_case
+    real = A._e3_vjp
+
+    def wrong(dx, dy, dz, a, b, g_ex, g_ey, g_ez):
+        return real(dx, dy, dz, b, a, g_ex, g_ey, g_ez)
+
+    monkeypatch.setattr(A, "_e3_vjp", wrong)
+    assert _fd_check(p, orc, np.random.default_rng(21), 15, 0.0, 0.0, 0.0) > 1e-4
