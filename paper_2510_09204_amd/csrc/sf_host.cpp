@@ -201,12 +201,13 @@ struct sf_plan {
   bool tune_fwd = false;  // pick threads on first use (cfg.threads == 0)
   bool tune_bwd = false;
   int Tc_fwd = 0, Tc_bwd = 0;
+  int Tv3 = 0;            // 3D adjoint: VJP time chunk (<= Tc_bwd)
   size_t lds_fwd = 0, lds_bwd = 0;
   // workspace layout (byte offsets)
   size_t off_desc = 0, off_order = 0, off_W = 0, off_Wdd = 0, off_fac = 0, off_cxi = 0,
          off_obs = 0, off_ckpt = 0, off_final = 0, off_seg = 0, off_X = 0, off_V = 0,
          off_R = 0, off_xb0 = 0, off_xb1 = 0, off_lam = 0, off_pcxi = 0, off_red = 0, off_part = 0,
-         off_iters = 0, off_zero = 0, off_ovel = 0, total = 0;
+         off_iters = 0, off_zero = 0, off_ovel = 0, off_gmask = 0, total = 0;
   bool moving = false;        // obstacle displacements set (sf_set_obstacle_motion)
   char* ws = nullptr;
   bool saved = false;
@@ -379,10 +380,30 @@ int build_plan(const sf_config_t* cfg, int B, const int32_t* n_robots, const int
       }
     if (best == 0)
       return fail(SF_ERR_SHAPE, "problem state does not fit the LDS of one workgroup");
+    // The adjoint recomputes forward iterates with the forward's time chunks
+    // (same sums, same bits) and runs its VJP in chunks of Tv <= Tc steps; a
+    // plan that can save a forward takes the longest Tc for which some Tv fits.
+    auto tv_for = [&](int tc) {
+      for (int tv = tc; tv >= 1; --tv)
+        if (sf::bwd3_lds_bytes(nc, tc, tv, p->n_max, p->M_max, p->S_max) <= kLdsBudget)
+          return tv;
+      return 0;
+    };
+    int tv = tv_for(best);
+    if (cfg->max_iters > 0)
+      while (tv == 0 && best > 1) tv = tv_for(--best);
+    if (cfg->max_iters > 0 && tv == 0)
+      return fail(SF_ERR_SHAPE, "adjoint state does not fit the LDS of one workgroup");
     const int chunks = (T + best - 1) / best;
     p->Tc_fwd = p->Tc_bwd = (T + chunks - 1) / chunks;
+    if (tv > 0) {
+      const int vchunks = (T + tv - 1) / tv;
+      p->Tv3 = std::min(p->Tc_bwd, (T + vchunks - 1) / vchunks);
+    }
     p->lds_fwd = sf::fwd3_lds_bytes(nc, T, p->Tc_fwd, p->n_max, p->M_max, p->S_max);
-    p->lds_bwd = 0;
+    p->lds_bwd = p->Tv3 > 0 ? sf::bwd3_lds_bytes(nc, p->Tc_bwd, p->Tv3, p->n_max, p->M_max,
+                                                 p->S_max)
+                            : 0;
   }
   // One time-chunk length for both kernels: the adjoint recomputes forward
   // iterates and must sum in the same order to reproduce them bitwise.
@@ -427,6 +448,8 @@ int build_plan(const sf_config_t* cfg, int B, const int32_t* n_robots, const int
   p->off_iters = take(sizeof(int32_t) * B);
   p->off_zero = take(F * coef);   // the target read by the acceleration objective
   p->off_ovel = take(F * D * obs);  // obstacle displacements
+  if (D == 2)                        // candidate lists of chunked horizons
+    p->off_gmask = take(sf::chunk_list_bytes(T, p->Tc_fwd, p->n_max, p->M_max) * (size_t)B);
   p->total = off;
   out = std::move(p);
   return SF_OK;
@@ -455,6 +478,7 @@ sf::FwdArgs fwd_args(const sf_plan* p, const float* xi, const float* xi0, const 
   a.ws_ckpt = p->at<float>(p->off_ckpt);
   a.ws_final = p->at<float>(p->off_final);
   a.ws_iters = p->at<int32_t>(p->off_iters);
+  a.gmask = p->at<unsigned>(p->off_gmask);
   a.S_total = p->S_total;
   a.B = p->B;
   a.nc = p->cfg.n_coef;
@@ -609,7 +633,7 @@ int sf_setup(const sf_config_t* cfg, int32_t n_problems, const int32_t* n_robots
     return fail(SF_ERR_SHAPE, "device LDS per workgroup (" + std::to_string(lds_max) +
                                   ") below the plan's need");
   if (p->cfg.n_dim == 3)
-    SF_HIP_CHECK(sf::prepare_kernels3(p->lds_fwd));
+    SF_HIP_CHECK(sf::prepare_kernels3(std::max(p->lds_fwd, p->lds_bwd)));
   else
     SF_HIP_CHECK(sf::prepare_kernels(std::max(p->lds_fwd, p->lds_bwd)));
   {
@@ -666,10 +690,9 @@ int sf_project(sf_plan_t* plan, void* workspace, const float* xi, const float* x
   if (xi_out == xi || xi_out == xi0 || lam_out == lam0 || xi_out == lam_out)
     return fail(SF_ERR_INVALID_ARG, "outputs must not alias inputs");
   const bool dim3 = plan->cfg.n_dim == 3;
-  if (dim3 && (flags & (SF_SAVE_FOR_BACKWARD | SF_PLAIN | SF_UNFUSED)))
-    return fail(SF_ERR_INVALID_ARG,
-                "n_dim = 3 runs the fused forward only (no SF_SAVE_FOR_BACKWARD, SF_PLAIN, "
-                "SF_UNFUSED)");
+  if (dim3 && (flags & (SF_PLAIN | SF_UNFUSED)))
+    return fail(SF_ERR_INVALID_ARG, "n_dim = 3 runs the fused kernels only (no SF_PLAIN, "
+                                    "SF_UNFUSED)");
   if (dim3 && plan->exit_every > 0)
     return fail(SF_ERR_INVALID_ARG, "n_dim = 3 has no early exit");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -803,6 +826,7 @@ int backward_impl(sf_plan_t* plan, void* workspace, const float* g_xi_out,
   a.g_xi0 = g_xi0;
   a.g_lam0 = g_lam0;
   a.iters = plan->saved_early ? plan->at<int32_t>(plan->off_iters) : nullptr;
+  a.gmask = plan->at<unsigned>(plan->off_gmask);
   a.S_total = plan->S_total;
   a.B = plan->B;
   a.nc = plan->cfg.n_coef;
@@ -832,7 +856,13 @@ int backward_impl(sf_plan_t* plan, void* workspace, const float* g_xi_out,
     plan->threads_bwd = t;
     plan->tune_bwd = false;
   }
-  SF_HIP_CHECK(sf::launch_bwd_fused(a, plan->threads_bwd, plan->lds_bwd, s));
+  if (plan->cfg.n_dim == 3) {
+    if (plan->Tv3 == 0)
+      return fail(SF_ERR_SHAPE, "the plan has no adjoint layout (max_iters was 0)");
+    SF_HIP_CHECK(sf::launch_bwd3(a, plan->threads_bwd, plan->lds_bwd, plan->Tv3, s));
+  } else {
+    SF_HIP_CHECK(sf::launch_bwd_fused(a, plan->threads_bwd, plan->lds_bwd, s));
+  }
   if (g_xi && plan->cfg.objective == SF_OBJECTIVE_ACCEL)
     SF_HIP_CHECK(sf::launch_fill(g_xi, 0.f, plan->S_total, s));   // xi is not an input there
   return SF_OK;

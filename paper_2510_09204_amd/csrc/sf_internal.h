@@ -51,6 +51,7 @@ struct FwdArgs {
   float* ws_ckpt;         // [n_ckpt][2][S_total]
   float* ws_final;        // [2][S_total]
   int32_t* ws_iters;      // [B] iterations each problem ran
+  unsigned* gmask;        // chunked horizons: [B][chunk_list_bytes / 4] candidate lists
   int64_t S_total;        // floats in one coefficient array
   int32_t B;
   int32_t nc;
@@ -83,6 +84,7 @@ struct BwdArgs {
   float* g_xi0;           // nullable
   float* g_lam0;          // nullable
   const int32_t* iters;   // nullable [B]: iterations each problem ran (early exit)
+  unsigned* gmask;        // chunked horizons: [B][chunk_list_bytes / 4] candidate lists
   int64_t S_total;
   int32_t B;
   int32_t nc;
@@ -94,6 +96,10 @@ struct BwdArgs {
   float rho;
   float fp_weight;
 };
+
+// Bytes per problem of the global copy of the candidate lists that a chunked
+// horizon (Tc < T) keeps between passes; 0 when the horizon is LDS-resident.
+size_t chunk_list_bytes(int T, int Tc, int n_max, int M_max);
 
 // Dynamic LDS bytes of the fused kernels for given batch maxima.
 size_t fwd_lds_bytes(int nc, int T, int Tc, int n_max, int M_max, int S_max, int threads);
@@ -136,6 +142,10 @@ hipError_t prepare_kernels(size_t lds);
 size_t fwd3_lds_bytes(int nc, int T, int Tc, int n_max, int M_max, int S_max);
 hipError_t prepare_kernels3(size_t lds);
 hipError_t launch_fwd3(const FwdArgs& a, int threads, size_t lds, hipStream_t s);
+// 3D adjoint: the forward's layout for time chunks of Tc plus its own buffers
+// for VJP chunks of Tv <= Tc steps.
+size_t bwd3_lds_bytes(int nc, int Tc, int Tv, int n_max, int M_max, int S_max);
+hipError_t launch_bwd3(const BwdArgs& a, int threads, size_t lds, int Tv, hipStream_t s);
 
 // Candidate selection (sf_select.hip).  Batches of at most kSelectMaxBatch
 // candidates (the ranking keys live in LDS).

@@ -1130,6 +1130,7 @@ struct Ctx {
   int ostride;          // M_max: window stride of obox
   float inv_Tm1;        // 1 / (T - 1): tau of global step k is k * inv_Tm1
   bool moving;          // some obstacle moves (displacements were set)
+  unsigned* gmask;      // chunked: this problem's lists of every chunk (global memory)
 
   __device__ __forceinline__ int Ts() const { return tstride(Tc); }
   __device__ __forceinline__ int nws() const { return nwindows(Tc); }
@@ -1145,6 +1146,22 @@ struct Ctx {
       const int ax = r >= nc, c = r - ax * nc;
       const int s = __umul24(ax * n + part_robot(t, h, H), nc) + c;
       refc[s] = xb[s];
+    }
+  }
+
+  // Chunked horizons keep the lists of every chunk between passes in global
+  // memory: after a rebuild the chunk's LDS window slots are stored (out),
+  // otherwise they are loaded before the chunk's units use them.  Block-wide;
+  // the caller orders it with barriers.
+  template <int NT>
+  __device__ __forceinline__ void chunk_lists(int chunk, bool out) const {
+    const int words = nws() * mstride;
+    unsigned* g = gmask + (size_t)chunk * words;
+    for (int t = tid; t < words; t += NT) {
+      if (out)
+        g[t] = masks[t];
+      else
+        masks[t] = g[t];
     }
   }
 
@@ -1192,7 +1209,7 @@ __device__ __forceinline__ void chunk_units(const Ctx& C, int chunk, int Tce, co
                                             bool accum, float& r1sq, float& r2sq, float w_pair,
                                             float w_box) {
   const int lane = lane_here(C.tid), wave = wave_id(C.tid), nwaves = NT >> 6;
-  const bool rebuild = C.chunked || lists_moved(C.lslot, nwaves, lane);
+  const bool rebuild = lists_moved(C.lslot, nwaves, lane);
   const int nwin = nwindows(Tce);
   const int H = parts_per_window(C.n, nwin, nwaves);
   const int Ts = C.Ts(), nws = C.nws();
@@ -1204,6 +1221,7 @@ __device__ __forceinline__ void chunk_units(const Ctx& C, int chunk, int Tce, co
   } else {
     map_chunk<NT, KS, false>(C.W, C.nc, xb, C.n, reinterpret_cast<float*>(X), Ts, Tce, nullptr,
                              nws, wave, lane);
+    if (C.chunked) C.chunk_lists<NT>(chunk, false);
   }
   __syncthreads();
   for (int u = wave; u < nwin * H; u += nwaves) {
@@ -1211,11 +1229,12 @@ __device__ __forceinline__ void chunk_units(const Ctx& C, int chunk, int Tce, co
     if (rebuild) {
       masks_window(reinterpret_cast<const float4*>(C.box3), C.n, C.obox + w * C.ostride, C.M,
                    C.a, C.skin, C.mwin(w), C.mrow, C.mpw, nws, w, h, H, lane);
-      if (w == 0 && !C.chunked) C.set_reference(xb, h, H, lane);
+      if (w == 0 && chunk == 0) C.set_reference(xb, h, H, lane);
       wave_fence();
     }
 #define SF_CONSTRAINTS(ACC, MOV)                                                               \
-  constraints_window<ACC, MOV>(X, V, C.n, Ts, C.obs, C.ovel, kg, C.inv_Tm1, C.M, C.mwin(w),    \
+  constraints_window<ACC, MOV>(X, V, C.n, Ts, C.obs, C.ovel, kg, C.inv_Tm1, C.M,              \
+                               C.mwin(w),                                                 \
                                C.mrow, C.mpw, C.a, C.pmin0, C.pmin1, C.pmax0, C.pmax1, w, Tce, \
                                h, H, r1sq, r2sq, w_pair, w_box, lane)
     if (C.moving) {
@@ -1233,6 +1252,7 @@ __device__ __forceinline__ void chunk_units(const Ctx& C, int chunk, int Tce, co
     }
   }
   __syncthreads();
+  if (rebuild && C.chunked) C.chunk_lists<NT>(chunk, true);
 }
 
 // One application of T on the LDS state: (xb, lam) -> (xn, lam_n).  X, V,
@@ -1279,7 +1299,7 @@ __device__ __forceinline__ bool sf_iteration(const Ctx& C, const float* xb, floa
   }
   lane = lane_here(C.tid);
   update_fwd_p2<NT>(C.nc, C.n, csum, accP, xb, xn, want_dz, dzsq, C.refc,
-                    C.chunked ? nullptr : C.lslot, C.skin, wave, lane);
+                    C.lslot, C.skin, wave, lane);
   __syncthreads();
   return stop;
 }
@@ -1306,14 +1326,20 @@ __host__ __device__ inline size_t obstacle_floats(int Tc, int M_max) {
 __host__ __device__ inline int box_floats(int Tc, int n_max) {
   return 4 * n_max * nwindows(Tc);
 }
-// Windows whose candidate lists are stored: all windows of the horizon when
-// it is LDS-resident (lists persist across iterations), else those of one time
-// chunk (lists are rebuilt on every pass).
+// Windows whose candidate lists are held in LDS: all windows of the horizon
+// when it is LDS-resident, else those of one time chunk (the lists of every
+// chunk then live in global memory between passes, see chunk_lists).
 __host__ __device__ inline int horizon_windows(int T, int Tc) {
   return nwindows(min(T, Tc));
 }
 __host__ __device__ inline int mask_floats(int T, int Tc, int n_max, int M_max) {
   return horizon_windows(T, Tc) * mask_words(n_max, M_max);
+}
+// 32-bit words of one problem's global copy of the lists of every chunk (0
+// when the horizon is LDS-resident).
+__host__ __device__ inline size_t list_words(int T, int Tc, int n_max, int M_max) {
+  if (Tc >= T) return 0;
+  return (size_t)((T + Tc - 1) / Tc) * nwindows(Tc) * mask_words(n_max, M_max);
 }
 // Reference coefficients of the list check and the per-wave flags.
 __host__ __device__ inline int list_floats(int S_max) { return ((S_max + 3) & ~3) + kMaxWaves; }
@@ -1366,6 +1392,10 @@ __device__ __forceinline__ FwdLds carve_fwd(float* sm, int nc, int T, int Tc, in
 
 }  // namespace
 
+size_t chunk_list_bytes(int T, int Tc, int n_max, int M_max) {
+  return sizeof(unsigned) * list_words(T, Tc, n_max, M_max);
+}
+
 size_t fwd_lds_bytes(int nc, int T, int Tc, int n_max, int M_max, int S_max, int) {
   auto r4 = [](int x) { return (size_t)((x + 3) & ~3); };
   size_t f = r4(nc * Tc) + r4(fac_stride(nc)) + (5 + nwindows(Tc)) * r4(S_max) + kMeans + kRed +
@@ -1393,8 +1423,9 @@ __global__ __launch_bounds__(NT) void fwd_fused_kernel(FwdArgs A) {
         tid,    A.rho,     P.a,       P.pmin[0], P.pmin[1], P.pmax[0],
         P.pmax[1], L.W,    L.fac,     A.W,       L.obs,     L.obox,
         L.box3, L.masks,   L.refc,    L.lslot,   mask_rows(A.n_max), (A.n_max + 31) >> 5,
-        mask_words(A.n_max, A.M_max), A.Tc < T ? 0.f : list_skin(P.a), A.Tc < T,
-        L.ovel, A.M_max, 1.f / (float)(T - 1), A.ovel != nullptr};
+        mask_words(A.n_max, A.M_max), list_skin(P.a), A.Tc < T,
+        L.ovel, A.M_max, 1.f / (float)(T - 1), A.ovel != nullptr,
+        A.gmask + (size_t)b * list_words(T, A.Tc, A.n_max, A.M_max)};
   force_rebuild(L.lslot, tid);
   if (!C.chunked) load_wchunk(A.W, L.W, nc, 0, T, tid, NT);
   for (int t = tid; t < fs; t += NT) L.fac[t] = A.fac[(size_t)P.fac * fs + t];
@@ -1689,7 +1720,7 @@ __device__ __forceinline__ void adjoint_units(const Ctx& C, int chunk, int Tce, 
                                               const float* gR, float2* X, float2* G, float2* Hb,
                                               float* part, bool accumulate) {
   const int lane = lane_here(C.tid), wave = wave_id(C.tid), nwaves = NT >> 6;
-  const bool rebuild = C.chunked || lists_moved(C.lslot, nwaves, lane);
+  const bool rebuild = lists_moved(C.lslot, nwaves, lane);
   const int nwin = nwindows(Tce);
   const int H = parts_per_window(C.n, nwin, nwaves);
   const int Ts = C.Ts(), nws = C.nws();
@@ -1701,6 +1732,7 @@ __device__ __forceinline__ void adjoint_units(const Ctx& C, int chunk, int Tce, 
   } else {
     map_chunk<NT, KS, false>(C.W, C.nc, xb, C.n, reinterpret_cast<float*>(X), Ts, Tce, nullptr,
                              nws, wave, lane);
+    if (C.chunked) C.chunk_lists<NT>(chunk, false);
   }
   map_chunk<NT, KS, false>(C.W, C.nc, gR, C.n, reinterpret_cast<float*>(G), Ts, Tce, nullptr,
                            nws, wave, lane);
@@ -1710,20 +1742,23 @@ __device__ __forceinline__ void adjoint_units(const Ctx& C, int chunk, int Tce, 
     if (rebuild) {
       masks_window(reinterpret_cast<const float4*>(C.box3), C.n, C.obox + w * C.ostride, C.M,
                    C.a, C.skin, C.mwin(w), C.mrow, C.mpw, nws, w, h, H, lane);
-      if (w == 0 && !C.chunked) C.set_reference(xb, h, H, lane);
+      if (w == 0 && chunk == 0) C.set_reference(xb, h, H, lane);
       wave_fence();
     }
     if (C.moving)
-      vjp_window<true>(X, G, Hb, C.n, Ts, C.obs, C.ovel, kg, C.inv_Tm1, C.M, C.mwin(w), C.mrow,
+      vjp_window<true>(X, G, Hb, C.n, Ts, C.obs, C.ovel, kg, C.inv_Tm1, C.M, C.mwin(w),
+                       C.mrow,
                        C.mpw, C.a, C.pmin0, C.pmin1, C.pmax0, C.pmax1, w, Tce, h, H, lane);
     else
-      vjp_window<false>(X, G, Hb, C.n, Ts, C.obs, C.ovel, kg, C.inv_Tm1, C.M, C.mwin(w), C.mrow,
+      vjp_window<false>(X, G, Hb, C.n, Ts, C.obs, C.ovel, kg, C.inv_Tm1, C.M, C.mwin(w),
+                        C.mrow,
                         C.mpw, C.a, C.pmin0, C.pmin1, C.pmax0, C.pmax1, w, Tce, h, H, lane);
     wave_fence();
     wtmap_window<KS>(C.W, C.nc, reinterpret_cast<const float*>(Hb), C.n, Ts, w, Tce, h, H,
                      part + w * C.S, accumulate, lane);
   }
   __syncthreads();
+  if (rebuild && C.chunked) C.chunk_lists<NT>(chunk, true);
 }
 
 template <int NT, int KS>
@@ -1744,8 +1779,9 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
         tid,    rho,       P.a,       P.pmin[0], P.pmin[1], P.pmax[0],
         P.pmax[1], L.W,    L.fac,     A.W,       L.obs,     L.obox,
         L.box3, L.masks,   L.refc,    L.lslot,   mask_rows(A.n_max), (A.n_max + 31) >> 5,
-        mask_words(A.n_max, A.M_max), Tc < T ? 0.f : list_skin(P.a), Tc < T,
-        L.ovel, A.M_max, 1.f / (float)(T - 1), A.ovel != nullptr};
+        mask_words(A.n_max, A.M_max), list_skin(P.a), Tc < T,
+        L.ovel, A.M_max, 1.f / (float)(T - 1), A.ovel != nullptr,
+        A.gmask + (size_t)b * list_words(T, Tc, A.n_max, A.M_max)};
   force_rebuild(L.lslot, tid);
   const int nwin0 = nwindows(min(Tc, T));
   if (!C.chunked) load_wchunk(A.W, L.W, nc, 0, T, tid, NT);
@@ -1817,7 +1853,7 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
         xr[s] = ck[s];
         lr[s] = ck[St + s];
       }
-      if (!C.chunked) check_lists<NT>(xr, L.refc, S, C.skin, L.lslot, tid);
+      check_lists<NT>(xr, L.refc, S, C.skin, L.lslot, tid);
       if (pending) {
         // the recompute reuses the partial buffer: fold it into gx first
         add_partials(gx, L.part, nwin0, S, tid, NT);
@@ -1849,7 +1885,7 @@ __global__ __launch_bounds__(NT) void bwd_fused_kernel(BwdArgs A) {
       if (!staged)
         for (int s = tid; s < S; s += NT) xbl[s] = cur[s];
       staged = false;
-      if (!C.chunked) check_lists<NT>(xbl, L.refc, S, C.skin, L.lslot, tid);
+      check_lists<NT>(xbl, L.refc, S, C.skin, L.lslot, tid);
       const float* ahead = l > l0                ? (l - 1 == l0 ? ck : cur - 2 * St)
                            : (k == 1 && seg > 0) ? ck - 2 * St
                                                  : nullptr;

@@ -97,6 +97,20 @@ def test_checkpoint_interval_does_not_change_gradients(gpu, ckpt):
             np.testing.assert_array_equal(out[q][b], ref[q][b])
 
 
+def test_chunked_horizon_checkpoint_interval_does_not_change_gradients(gpu):
+    """Time-chunked horizon (c5 shape): the recompute between checkpoints
+    reproduces the forward's iterates bitwise although its candidate lists are
+    rebuilt at other iterations than the forward's."""
+    probs = make_batch(WORKLOADS[5], batch=2)
+    g_xi, g_lam = _cotangents(probs, 8)
+    g_res = np.tile([[0.5, 0.5, 0.0, 0.0]], (2, 1))
+    _, ref, _ = _run(probs, 30, 1, g_xi, g_lam, g_res, fp_weight=0.1)
+    _, out, _ = _run(probs, 30, 7, g_xi, g_lam, g_res, fp_weight=0.1)
+    for q in range(3):
+        for b in range(2):
+            np.testing.assert_array_equal(out[q][b], ref[q][b])
+
+
 def test_c5_shape_adjoint_with_time_chunks(gpu):
     probs = make_batch(WORKLOADS[5], batch=1)
     g_xi, g_lam = _cotangents(probs, 4)

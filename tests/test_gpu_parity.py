@@ -169,6 +169,19 @@ def test_plain_path_matches_fused_bitwise(gpu):
     np.testing.assert_allclose(plain["res"], fused["res"], rtol=1e-5, atol=1e-7)
 
 
+def test_chunked_horizon_plain_path_matches_fused_bitwise(gpu):
+    """64 robots, 50 obstacles, 120 steps: the horizon runs in LDS time chunks
+    whose candidate lists persist between iterations in global memory (rebuilt
+    only when a coefficient left the skin); every pair and step of the plain
+    path gives the same bits."""
+    probs = make_batch(WORKLOADS[5], batch=2)
+    fused = gpu_forward(probs, RHO, 80)
+    plain = gpu_forward(probs, RHO, 80, plain=True)
+    np.testing.assert_array_equal(plain["xi"], fused["xi"])
+    np.testing.assert_array_equal(plain["lam"], fused["lam"])
+    np.testing.assert_allclose(plain["res"], fused["res"], rtol=1e-5, atol=1e-7)
+
+
 def test_batched_unfused_path_matches_fused_bitwise(gpu):
     probs = make_batch(WORKLOADS[4], batch=6)      # uneven sizes in every launch
     fused = gpu_forward(probs, RHO, 40)
