@@ -8,7 +8,7 @@
  * the alternating-minimisation updates of the Appendix (eqs. alpha_step ..
  * xi_step) on the augmented Lagrangian (eq. aug_lag).  The planar SF (n_dim =
  * 2) has every entry point; the 3D spheroid variant (n_dim = 3, below) has the
- * fused forward only.
+ * fused forward and its adjoint.
  *
  * Layouts (all float32, contiguous, device memory unless marked host):
  *   coefficient arrays (xi, xi_bar, lambda and their gradients): problems
@@ -37,10 +37,12 @@
  * (for a != b this is not the Euclidean argmin of eq. beta_step with d held
  * fixed), and d = max(1, s) with s the scaled length of Delta, the exact
  * minimiser over d >= 1 in scaled coordinates; together they put e on the ray
- * of Delta.  Only sf_project without SF_SAVE_FOR_BACKWARD, SF_PLAIN and
- * SF_UNFUSED runs for n_dim = 3 (SF_GRAPH and obstacle motion work);
- * sf_project_backward, early exit and sf_smoothness return SF_ERR_INVALID_ARG
- * or SF_ERR_NOT_SAVED.  Each workgroup visits every robot pair.
+ * of Delta.  For n_dim = 3, sf_project (SF_SAVE_FOR_BACKWARD and SF_GRAPH
+ * included, obstacle motion too) and sf_project_backward run; the adjoint
+ * chains through the same alpha, beta and d steps, with the Jacobian of r_1 =
+ * (1 - 1/s) Delta on active rows (identity at Delta = 0).  SF_PLAIN,
+ * SF_UNFUSED, early exit and sf_smoothness return SF_ERR_INVALID_ARG.  Each
+ * workgroup visits every robot pair.
  *
  * Ownership: the caller allocates every array and the workspace; the library
  * owns only the host-side plan.  Calls never retain caller pointers (the
@@ -82,7 +84,7 @@ extern "C" {
 typedef struct sf_plan sf_plan_t;
 
 typedef struct {
-  int32_t n_dim;            /* workspace dimension n_d: 2, or 3 (spheroids, forward only) */
+  int32_t n_dim;            /* workspace dimension n_d: 2, or 3 (spheroids) */
   int32_t n_coef;           /* basis size n_xi per axis, 2..32 (Bernstein, eq. poly) */
   int32_t n_steps;          /* time samples T = K + 1, 2..4096 */
   int32_t checkpoint_every; /* k >= 1: the forward stores (xi_bar, lambda) every k

@@ -122,7 +122,8 @@ class SFPlan:
     each problem; the FP64 KKT factors are built on the host and the workspace
     is a torch uint8 tensor on `device`.  n_dim = 3 is the spheroid variant:
     robot_a is then [B][2] = (a, b), boundary [sum n][2][3], obstacles
-    [sum M][5] = (x, y, z, a_o, b_o), and only the fused forward runs."""
+    [sum M][5] = (x, y, z, a_o, b_o), and the fused forward and its adjoint
+    run (no plain or unfused path, no early exit)."""
 
     def __init__(self, n_robots: Sequence[int], n_obs: Sequence[int],
                  robot_a: Sequence[float], box, n_coef: int, n_steps: int, rho: float,

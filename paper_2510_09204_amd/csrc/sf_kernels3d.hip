@@ -98,6 +98,40 @@ __device__ __forceinline__ void spheroid_residual(float ex, float ey, float ez, 
   }
 }
 
+// J^T w for the residual of one spheroid row, J = dr_1/dDelta of r_1 = (1 -
+// 1/s) Delta (s < 1): J^T w = (1 - 1/s) w + (ex/sa, ey/sa, ez/sb) <Delta, w> / s^3
+// with Delta = (sa ex, sa ey, sb ez).  At Delta = 0 e is locally constant, so J = I.
+// Inactive rows (s >= 1 or `live` false) add nothing.  Added to (hx, hy, hz).
+__device__ __forceinline__ void spheroid_vjp(float ex, float ey, float ez, float sa, float sb,
+                                             float wx, float wy, float wz, bool live,
+                                             float& hx, float& hy, float& hz) {
+  const float s2 = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
+  if (live && s2 < 1.f) {
+    const float is = __builtin_amdgcn_rsqf(fmaxf(s2, FLT_MIN));
+    const float f = s2 > 0.f ? 1.f - is : 1.f;
+    const float c = s2 > 0.f ? is * is * is * fmaf(sb * ez, wz, sa * fmaf(ex, wx, ey * wy))
+                             : 0.f;
+    const float isa = 1.f / sa, isb = 1.f / sb;
+    hx = fmaf(f, wx, fmaf(c * isa, ex, hx));
+    hy = fmaf(f, wy, fmaf(c * isa, ey, hy));
+    hz = fmaf(f, wz, fmaf(c * isb, ez, hz));
+  }
+}
+
+// J^T r_1 of one spheroid row (the gradient of 1/2 |r_1|^2 with respect to
+// Delta), from its scaled offset; at Delta = 0, r_1 itself (J = I there).
+__device__ __forceinline__ void spheroid_resgrad(float ex, float ey, float ez, float sa,
+                                                 float sb, float tie, bool live, float& vx,
+                                                 float& vy, float& vz) {
+  const float s2 = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
+  if (live && s2 < 1.f) {
+    const float f = 1.f - __builtin_amdgcn_rsqf(fmaxf(s2, FLT_MIN));
+    const float rx = f * (sa * ex), ry = f * (sa * ey);
+    const float rz = fmaf(f, sb * ez, s2 == 0.f ? tie : 0.f);
+    spheroid_vjp(ex, ey, ez, sa, sb, rx, ry, rz, true, vx, vy, vz);
+  }
+}
+
 // Robots per thread in the constraint stage: more robots share each LDS read,
 // fewer threads have work; four from 24 robots, two from 8.
 __device__ __forceinline__ int robots_per_thread(int n) { return n >= 24 ? 4 : (n >= 8 ? 2 : 1); }
@@ -124,11 +158,23 @@ __device__ __forceinline__ Lds3 carve3(float* p, int nc, int Tc, int n_max, int 
   return L;
 }
 
-// One pass over the horizon at xi_bar = xb: positions X, constraint sums V
-// and (unless FINAL) R = W^T V; with FINAL the residual sums instead.
-template <int NT, bool FINAL, int kRob>
-__device__ __forceinline__ void sweep3(const FwdArgs& A, const ProbDesc& P, const Lds3& L,
-                                       const float* xb, float& r1sq, float& r2sq) {
+// LDS floats of the forward's layout (carve3).
+__host__ __device__ inline size_t lds3_floats(int nc, int Tc, int n_max, int M_max, int S_max) {
+  return (size_t)r4(Tc * nc) + r4(fac_stride(nc)) + 5 * (size_t)r4(S_max) + 6 * kMaxCoef + 8 +
+         (size_t)kObsFloats * M_max + kRed3 + 6 * (size_t)n_max * Tc;
+}
+
+// Passes over the horizon at xi_bar = xb (MODE): kForward gives positions X,
+// constraint sums V and R = W^T V; kFinal the residual sums ||r_1||^2 and
+// ||r_2||^2 instead; kResGrad R = W^T V with V = w1 sum J^T r_1 + w2 (box
+// overshoot), the gradient of w1 ||r_1||^2 / 2 + w2 ||r_2||^2 / 2.
+constexpr int kForward = 0, kFinal = 1, kResGrad = 2;
+
+template <int NT, int MODE, int kRob, typename Args>
+__device__ __forceinline__ void sweep3(const Args& A, const ProbDesc& P, const Lds3& L,
+                                       const float* xb, float& r1sq, float& r2sq,
+                                       float w1 = 1.f, float w2 = 1.f) {
+  constexpr bool FINAL = MODE == kFinal;
   const int n = P.n, M = P.M, nc = A.nc, T = A.T, Tc = A.Tc, tid = threadIdx.x;
   const bool chunked = Tc < T;
   const float inv_a = 1.f / P.a, inv_b = 1.f / P.b;
@@ -208,9 +254,13 @@ __device__ __forceinline__ void sweep3(const FwdArgs& A, const ProbDesc& P, cons
 #pragma unroll
           for (int r = 0; r < kRob; ++r) {
             float s1 = 0.f;
-            spheroid_residual<FINAL>(px[r] - qx[e], py[r] - qy[e], pz[r] - qz[e], P.a, P.b,
-                                     ir[r] < j ? -P.b : P.b, j != ir[r], vx[r], vy[r], vz[r],
-                                     s1);
+            if (MODE == kResGrad)
+              spheroid_resgrad(px[r] - qx[e], py[r] - qy[e], pz[r] - qz[e], P.a, P.b,
+                               ir[r] < j ? -P.b : P.b, j != ir[r], vx[r], vy[r], vz[r]);
+            else
+              spheroid_residual<FINAL>(px[r] - qx[e], py[r] - qy[e], pz[r] - qz[e], P.a, P.b,
+                                       ir[r] < j ? -P.b : P.b, j != ir[r], vx[r], vy[r],
+                                       vz[r], s1);
             if (FINAL) sq[r] += j > ir[r] ? s1 : 0.f;   // each unordered pair once
           }
         }
@@ -221,8 +271,13 @@ __device__ __forceinline__ void sweep3(const FwdArgs& A, const ProbDesc& P, cons
 #pragma unroll
         for (int r = 0; r < kRob; ++r) {
           float s1 = 0.f;
-          spheroid_residual<FINAL>(px[r] - qx, py[r] - qy, pz[r] - qz, P.a, P.b,
-                                   ir[r] < j ? -P.b : P.b, j != ir[r], vx[r], vy[r], vz[r], s1);
+          if (MODE == kResGrad)
+            spheroid_resgrad(px[r] - qx, py[r] - qy, pz[r] - qz, P.a, P.b,
+                             ir[r] < j ? -P.b : P.b, j != ir[r], vx[r], vy[r], vz[r]);
+          else
+            spheroid_residual<FINAL>(px[r] - qx, py[r] - qy, pz[r] - qz, P.a, P.b,
+                                     ir[r] < j ? -P.b : P.b, j != ir[r], vx[r], vy[r], vz[r],
+                                     s1);
           if (FINAL) sq[r] += j > ir[r] ? s1 : 0.f;
         }
       }
@@ -236,9 +291,15 @@ __device__ __forceinline__ void sweep3(const FwdArgs& A, const ProbDesc& P, cons
         const float cz = moving ? fmaf(o[9], tau, o[4]) : o[4];
         const float ra = o[0], rb = o[1], oa = o[5], ob = o[6];
 #pragma unroll
-        for (int r = 0; r < kRob; ++r)
-          spheroid_residual<FINAL>(fmaf(px[r], ra, cx), fmaf(py[r], ra, cy), fmaf(pz[r], rb, cz),
-                                   oa, ob, -ob, true, vx[r], vy[r], vz[r], sq[r]);
+        for (int r = 0; r < kRob; ++r) {
+          if (MODE == kResGrad)
+            spheroid_resgrad(fmaf(px[r], ra, cx), fmaf(py[r], ra, cy), fmaf(pz[r], rb, cz), oa,
+                             ob, -ob, true, vx[r], vy[r], vz[r]);
+          else
+            spheroid_residual<FINAL>(fmaf(px[r], ra, cx), fmaf(py[r], ra, cy),
+                                     fmaf(pz[r], rb, cz), oa, ob, -ob, true, vx[r], vy[r],
+                                     vz[r], sq[r]);
+        }
       }
 #pragma unroll
       for (int r = 0; r < kRob; ++r) {
@@ -251,6 +312,10 @@ __device__ __forceinline__ void sweep3(const FwdArgs& A, const ProbDesc& P, cons
         if (FINAL) {
           r1sq += sq[r];
           r2sq += hx * hx + lx * lx + hy * hy + ly * ly + hz * hz + lz * lz;
+        } else if (MODE == kResGrad) {
+          L.V[u] = fmaf(w2, hx - lx, w1 * vx[r]);
+          L.V[plane + u] = fmaf(w2, hy - ly, w1 * vy[r]);
+          L.V[2 * plane + u] = fmaf(w2, hz - lz, w1 * vz[r]);
         } else {
           L.V[u] = vx[r] + (hx - lx);
           L.V[plane + u] = vy[r] + (hy - ly);
@@ -303,26 +368,33 @@ __device__ __forceinline__ void sweep3(const FwdArgs& A, const ProbDesc& P, cons
   }
 }
 
-template <int NT>
-__global__ __launch_bounds__(NT) void fwd3_kernel(FwdArgs A) {
-  extern __shared__ float lds3[];
-  const int b = A.order[blockIdx.x];
-  const ProbDesc P = A.probs[b];
-  const int n = P.n, M = P.M, nc = A.nc, T = A.T, Tc = A.Tc, tid = threadIdx.x;
-  const int nn = n * nc, S = 3 * nn, nc2 = nc * nc;
-  const Lds3 L = carve3(lds3, nc, Tc, A.n_max, A.M_max, A.S_max);
-  const float rho = A.rho;
-  const float* bnd = A.boundary + (size_t)P.rob_off * 6;
-  const bool chunked = Tc < T;
-  const int rpt = robots_per_thread(n);
+// Sweep dispatch on the problem's robots per thread.
+template <int NT, int MODE, typename Args>
+__device__ __forceinline__ void sweep3_any(const Args& A, const ProbDesc& P, const Lds3& L,
+                                           const float* xb, float& r1sq, float& r2sq,
+                                           float w1 = 1.f, float w2 = 1.f) {
+  const int rpt = robots_per_thread(P.n);
+  if (rpt == 4)
+    sweep3<NT, MODE, 4>(A, P, L, xb, r1sq, r2sq, w1, w2);
+  else if (rpt == 2)
+    sweep3<NT, MODE, 2>(A, P, L, xb, r1sq, r2sq, w1, w2);
+  else
+    sweep3<NT, MODE, 1>(A, P, L, xb, r1sq, r2sq, w1, w2);
+}
 
-  // --- set-up: factor block, W (whole table when unchunked), obstacles, state
+// Set-up shared by the forward and the adjoint: factor block, W (whole table
+// when unchunked) and the obstacle table from obstacles [M][5] (x, y, z, a_o,
+// b_o) and optional displacements [M][3].
+template <int NT, typename Args>
+__device__ __forceinline__ void setup3(const Args& A, const ProbDesc& P, const Lds3& L,
+                                       const float* obstacles) {
+  const int M = P.M, nc = A.nc, T = A.T, tid = threadIdx.x;
   const float* facg = A.fac + (size_t)P.fac * fac_stride(nc);
   for (int t = tid; t < fac_stride(nc); t += NT) L.fac[t] = facg[t];
-  if (!chunked)
+  if (A.Tc >= T)
     for (int t = tid; t < T * nc; t += NT) L.W[t] = A.W[t];
   for (int m = tid; m < M; m += NT) {
-    const float* o = A.obstacles + (size_t)(P.obs_off + m) * 5;
+    const float* o = obstacles + (size_t)(P.obs_off + m) * 5;
     float* d = L.obs + m * kObsFloats;
     // the offset from a robot in the obstacle's scaling (a_o, a_o, b_o), from
     // the robot's stored scaled position: a / a_o, b / b_o, -c / (a_o, a_o,
@@ -340,6 +412,87 @@ __global__ __launch_bounds__(NT) void fwd3_kernel(FwdArgs A) {
     d[8] = v ? -v[1] * ia : 0.f;
     d[9] = v ? -v[2] * ib : 0.f;
   }
+}
+
+// One application of T on the LDS state (xcur, L.lam) -> (xnext, L.lam):
+// the constraint sweep, the lambda step with u = lambda - 2 rho R (u replaces
+// R), robot means of u and xcur, the xi_bar step.  With `last`, dzsq gets
+// this thread's share of ||z' - z||^2.  Entered and left block-synchronised.
+template <int NT, typename Args>
+__device__ __forceinline__ void iterate3(const Args& A, const ProbDesc& P, const Lds3& L,
+                                         const float* xcur, float* xnext, bool last,
+                                         float& dzsq) {
+  const int n = P.n, nc = A.nc, tid = threadIdx.x;
+  const int nn = n * nc, S = 3 * nn, nc2 = nc * nc;
+  const float rho = A.rho;
+  float z0 = 0.f, z1 = 0.f;
+  sweep3_any<NT, kForward>(A, P, L, xcur, z0, z1);
+  for (int t = tid; t < S; t += NT) {
+    const float r = L.R[t], lm = L.lam[t];
+    L.lam[t] = fmaf(-rho, r, lm);
+    L.R[t] = fmaf(-2.f * rho, r, lm);
+    if (last) dzsq = fmaf(rho * r, rho * r, dzsq);
+  }
+  __syncthreads();
+  // robot means of u and xb: means[0..3nc) and means[3nc..6nc)
+  for (int t = tid; t < 6 * nc; t += NT) {
+    const int which = t / (3 * nc), q = t - which * 3 * nc, ax = q / nc, c = q - ax * nc;
+    const float* src = (which ? xcur : L.R) + ax * nn + c;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;   // four chains in flight
+    int i = 0;
+    for (; i + 4 <= n; i += 4) {
+      s0 += src[i * nc];
+      s1 += src[(i + 1) * nc];
+      s2 += src[(i + 2) * nc];
+      s3 += src[(i + 3) * nc];
+    }
+    for (; i < n; ++i) s0 += src[i * nc];
+    L.means[t] = ((s0 + s1) + (s2 + s3)) / (float)n;
+  }
+  __syncthreads();
+  // xi_bar step
+  for (int t = tid; t < S; t += NT) {
+    const int ax = t / nn, rem = t - ax * nn, i = rem / nc, c = rem - i * nc;
+    const float* Sp = L.fac + c * nc;
+    const float* DS = Sp + nc2;
+    const float* SH = Sp + 2 * nc2;
+    const float* DSH = Sp + 3 * nc2;
+    const float* u = L.R + ax * nn + i * nc;
+    const float* x = xcur + ax * nn + i * nc;
+    const float* um = L.means + ax * nc;
+    const float* xm = L.means + 3 * nc + ax * nc;
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;   // one chain per block
+    for (int q = 0; q < nc; ++q) {
+      a0 = fmaf(Sp[q], u[q], a0);
+      a1 = fmaf(DS[q], um[q], a1);
+      a2 = fmaf(SH[q], x[q], a2);
+      a3 = fmaf(DSH[q], xm[q], a3);
+    }
+    const float v = L.cxi[t] + ((a0 + a1) + (a2 + a3));
+    xnext[t] = v;
+    if (last) {
+      const float d = v - xcur[t];
+      dzsq = fmaf(d, d, dzsq);
+    }
+  }
+  __syncthreads();
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void fwd3_kernel(FwdArgs A) {
+  extern __shared__ float lds3[];
+  const int b = A.order[blockIdx.x];
+  const ProbDesc P = A.probs[b];
+  const int n = P.n, M = P.M, nc = A.nc, tid = threadIdx.x;
+  const int nn = n * nc, S = 3 * nn, nc2 = nc * nc;
+  const Lds3 L = carve3(lds3, nc, A.Tc, A.n_max, A.M_max, A.S_max);
+  const float* bnd = A.boundary + (size_t)P.rob_off * 6;
+  const size_t St = (size_t)A.S_total;
+
+  setup3<NT>(A, P, L, A.obstacles);
+  if (A.save)   // the adjoint reads the obstacles from the workspace
+    for (int t = tid; t < 5 * M; t += NT)
+      A.ws_obs[(size_t)P.obs_off * 5 + t] = A.obstacles[(size_t)P.obs_off * 5 + t];
   for (int t = tid; t < S; t += NT) {
     L.xb[0][t] = A.xi0[P.coef_off + t];
     L.lam[t] = A.lam0[P.coef_off + t];
@@ -376,6 +529,7 @@ __global__ __launch_bounds__(NT) void fwd3_kernel(FwdArgs A) {
         out = fmaf(DN[c * 2 + e], bm[ax * 2 + e], out);
       }
       L.cxi[t] = out;
+      if (A.save) A.ws_cxi[P.coef_off + t] = out;
     }
   }
   __syncthreads();
@@ -385,68 +539,14 @@ __global__ __launch_bounds__(NT) void fwd3_kernel(FwdArgs A) {
   float* xnext = L.xb[1];
   float dzsq = 0.f;
   for (int l = 0; l < A.L; ++l) {
-    const bool last = l == A.L - 1;
-    float z0 = 0.f, z1 = 0.f;
-    if (rpt == 4)
-      sweep3<NT, false, 4>(A, P, L, xcur, z0, z1);
-    else if (rpt == 2)
-      sweep3<NT, false, 2>(A, P, L, xcur, z0, z1);
-    else
-      sweep3<NT, false, 1>(A, P, L, xcur, z0, z1);
-    // lambda step and u = lambda - 2 rho R (u replaces R)
-    for (int t = tid; t < S; t += NT) {
-      const float r = L.R[t], lm = L.lam[t];
-      L.lam[t] = fmaf(-rho, r, lm);
-      L.R[t] = fmaf(-2.f * rho, r, lm);
-      if (last) dzsq = fmaf(rho * r, rho * r, dzsq);
-    }
-    __syncthreads();
-    // robot means of u and xb: means[0..3nc) and means[3nc..6nc)
-    for (int t = tid; t < 6 * nc; t += NT) {
-      const int which = t / (3 * nc), q = t - which * 3 * nc, ax = q / nc, c = q - ax * nc;
-      const float* src = (which ? xcur : L.R) + ax * nn + c;
-      float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;   // four chains in flight
-      int i = 0;
-      for (; i + 4 <= n; i += 4) {
-        s0 += src[i * nc];
-        s1 += src[(i + 1) * nc];
-        s2 += src[(i + 2) * nc];
-        s3 += src[(i + 3) * nc];
-      }
-      for (; i < n; ++i) s0 += src[i * nc];
-      L.means[t] = ((s0 + s1) + (s2 + s3)) / (float)n;
-    }
-    __syncthreads();
-    // xi_bar step
-    {
-      const float* xb = xcur;
-      float* xn = xnext;
+    if (A.save && (l % A.ckpt_every) == 0) {
+      float* ck = A.ws_ckpt + (size_t)(l / A.ckpt_every) * 2 * St + P.coef_off;
       for (int t = tid; t < S; t += NT) {
-        const int ax = t / nn, rem = t - ax * nn, i = rem / nc, c = rem - i * nc;
-        const float* Sp = L.fac + c * nc;
-        const float* DS = Sp + nc2;
-        const float* SH = Sp + 2 * nc2;
-        const float* DSH = Sp + 3 * nc2;
-        const float* u = L.R + ax * nn + i * nc;
-        const float* x = xb + ax * nn + i * nc;
-        const float* um = L.means + ax * nc;
-        const float* xm = L.means + 3 * nc + ax * nc;
-        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;   // one chain per block
-        for (int q = 0; q < nc; ++q) {
-          a0 = fmaf(Sp[q], u[q], a0);
-          a1 = fmaf(DS[q], um[q], a1);
-          a2 = fmaf(SH[q], x[q], a2);
-          a3 = fmaf(DSH[q], xm[q], a3);
-        }
-        const float v = L.cxi[t] + ((a0 + a1) + (a2 + a3));
-        xn[t] = v;
-        if (last) {
-          const float d = v - xb[t];
-          dzsq = fmaf(d, d, dzsq);
-        }
+        ck[t] = xcur[t];
+        ck[St + t] = L.lam[t];
       }
     }
-    __syncthreads();
+    iterate3<NT>(A, P, L, xcur, xnext, l == A.L - 1, dzsq);
     float* tmp = xcur;
     xcur = xnext;
     xnext = tmp;
@@ -454,17 +554,16 @@ __global__ __launch_bounds__(NT) void fwd3_kernel(FwdArgs A) {
 
   // residual of the returned iterate, outputs, status
   float v[3] = {0.f, 0.f, 0.f};
-  if (rpt == 4)
-    sweep3<NT, true, 4>(A, P, L, xcur, v[0], v[1]);
-  else if (rpt == 2)
-    sweep3<NT, true, 2>(A, P, L, xcur, v[0], v[1]);
-  else
-    sweep3<NT, true, 1>(A, P, L, xcur, v[0], v[1]);
+  sweep3_any<NT, kFinal>(A, P, L, xcur, v[0], v[1]);
   float bad = 0.f;
   for (int t = tid; t < S; t += NT) {
     const float x = xcur[t], lm = L.lam[t];
     A.xi_out[P.coef_off + t] = x;
     A.lam_out[P.coef_off + t] = lm;
+    if (A.save) {
+      A.ws_final[P.coef_off + t] = x;
+      A.ws_final[St + P.coef_off + t] = lm;
+    }
     if (!isfinite(x) || !isfinite(lm)) bad = 1.f;
   }
   v[2] = bad;
@@ -481,20 +580,334 @@ __global__ __launch_bounds__(NT) void fwd3_kernel(FwdArgs A) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// 3D adjoint: one workgroup per problem walks the checkpoint segments in
+// reverse, recomputing a segment's iterates from its checkpoint with the
+// forward's own iteration (same code, same time chunks, hence the same bits)
+// into the global segment area, then per iteration l, for the cotangent g of
+// xi_bar^{l+1} (plus 2 fw (xi_bar^{l+1} - xi_bar^l) with a fixed-point weight):
+//   g_u      = S^T g          (also the cotangent of the target xi)
+//   g_lambda += g_u,  g_R = -2 rho g_u - rho g_lambda' - 2 rho fw (lambda^{l+1} - lambda^l)
+//   g_xi_bar = SH^T g - 2 fw (xi_bar^{l+1} - xi_bar^l) + W^T VJP(W g_R)
+// S^T and SH^T in mode form: the transposed perpendicular block per robot plus
+// the transposed parallel-minus-perpendicular block on the robot mean of g.
+// The VJP of the constraint sums at X = W xi_bar^l: H_i = sum_j J_ij^T (G_i -
+// G_j) + sum_m J_im^T G_i + box'(X_i) G_i (J the spheroid residual's Jacobian,
+// I at Delta = 0, 0 on inactive rows), over time chunks of Tv steps.
+// ---------------------------------------------------------------------------
+
+// Extra LDS of the adjoint after the forward's layout: cotangents g (two,
+// ping-pong), g_lambda, g_xi, g_R, and G = W g_R over a VJP chunk [3][n][Tv].
+struct Lds3b {
+  float *gA, *gB, *glam, *gxi, *gR, *G;
+};
+
+__device__ __forceinline__ Lds3b carve3b(float* p, int S_max) {
+  Lds3b B;
+  B.gA = p; p += r4(S_max);
+  B.gB = p; p += r4(S_max);
+  B.glam = p; p += r4(S_max);
+  B.gxi = p; p += r4(S_max);
+  B.gR = p; p += r4(S_max);
+  B.G = p;
+  return B;
+}
+
+// VJP sweep over the horizon in chunks of Tv steps: X = W xb (scaled), G = W
+// gR, H = VJP (stored in L.V as [3][n][Tv]), R = W^T H (into L.R).
+template <int NT, int kRob>
+__device__ __forceinline__ void vjp3(const BwdArgs& A, const ProbDesc& P, const Lds3& L,
+                                     const Lds3b& B, const float* xb, int Tv) {
+  const int n = P.n, M = P.M, nc = A.nc, T = A.T, Tc = A.Tc, tid = threadIdx.x;
+  const bool chunked = Tc < T;
+  const float inv_a = 1.f / P.a, inv_b = 1.f / P.b;
+  const float inv_Tm1 = 1.f / (float)(T - 1);
+  const bool moving = A.ovel != nullptr;
+  const int lane = tid & 63, wave = tid >> 6, m = lane & 15, kq = lane >> 4;
+  for (int k0 = 0; k0 < T; k0 += Tv) {
+    const int Tce = min(Tv, T - k0);
+    if (chunked) {
+      __syncthreads();
+      for (int t = tid; t < Tce * nc; t += NT) L.W[t] = A.W[k0 * nc + t];
+      __syncthreads();
+    }
+    const float* Wc = chunked ? L.W : L.W + k0 * nc;
+    // X (scaled as in the forward) and G on MFMA 16x16x4 tiles (the forward's
+    // position tiles, two sources)
+    {
+      const int nwt = (Tce + 15) >> 4, nct = (3 * n + 15) >> 4, ks = (nc + 3) >> 2;
+      for (int q = wave; q < 2 * nwt * nct; q += NT >> 6) {
+        const int src = q >= nwt * nct, qq = q - src * nwt * nct;
+        const int wt = qq / nct, ct = qq - wt * nct;
+        const float* Y = src ? B.gR : xb;
+        const int stepA = min(wt * 16 + m, Tce - 1), colB = min(ct * 16 + m, 3 * n - 1);
+        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+        for (int s4 = 0; s4 < ks; ++s4) {
+          const int c = 4 * s4 + kq, cc = min(c, nc - 1);
+          const float a = c < nc ? Wc[stepA * nc + cc] : 0.f;
+          acc = mfma_16x16x4(a, Y[colB * nc + cc], acc);
+        }
+        const int col = ct * 16 + m;
+        const float sc = src ? 1.f : (col < 2 * n ? inv_a : inv_b);
+        float* dst = src ? B.G : L.X;
+        if (col < 3 * n) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int step = wt * 16 + 4 * kq + v;
+            if (step < Tce) dst[col * Tce + step] = acc[v] * sc;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    const int plane = n * Tce;
+    const int ngrp = (n + kRob - 1) / kRob;
+    for (int t = tid; t < ngrp * Tce; t += NT) {
+      const int g = t / Tce, kk = t - g * Tce;
+      float px[kRob], py[kRob], pz[kRob], gx[kRob], gy[kRob], gz[kRob];
+      float hx[kRob], hy[kRob], hz[kRob];
+      int ir[kRob];
+#pragma unroll
+      for (int r = 0; r < kRob; ++r) {
+        ir[r] = g * kRob + r;
+        const int u = min(ir[r], n - 1) * Tce + kk;
+        px[r] = L.X[u];
+        py[r] = L.X[plane + u];
+        pz[r] = L.X[2 * plane + u];
+        gx[r] = B.G[u];
+        gy[r] = B.G[plane + u];
+        gz[r] = B.G[2 * plane + u];
+        hx[r] = hy[r] = hz[r] = 0.f;
+      }
+      for (int j = 0; j < n; ++j) {
+        const int u = j * Tce + kk;
+        const float qx = L.X[u], qy = L.X[plane + u], qz = L.X[2 * plane + u];
+        const float wx = B.G[u], wy = B.G[plane + u], wz = B.G[2 * plane + u];
+#pragma unroll
+        for (int r = 0; r < kRob; ++r)
+          spheroid_vjp(px[r] - qx, py[r] - qy, pz[r] - qz, P.a, P.b, gx[r] - wx, gy[r] - wy,
+                       gz[r] - wz, j != ir[r], hx[r], hy[r], hz[r]);
+      }
+      const float tau = (float)(k0 + kk) * inv_Tm1;
+      for (int mo = 0; mo < M; ++mo) {
+        const float* o = L.obs + mo * kObsFloats;
+        const float cx = moving ? fmaf(o[7], tau, o[2]) : o[2];
+        const float cy = moving ? fmaf(o[8], tau, o[3]) : o[3];
+        const float cz = moving ? fmaf(o[9], tau, o[4]) : o[4];
+        const float ra = o[0], rb = o[1], oa = o[5], ob = o[6];
+#pragma unroll
+        for (int r = 0; r < kRob; ++r)
+          spheroid_vjp(fmaf(px[r], ra, cx), fmaf(py[r], ra, cy), fmaf(pz[r], rb, cz), oa, ob,
+                       gx[r], gy[r], gz[r], true, hx[r], hy[r], hz[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < kRob; ++r) {
+        if (ir[r] >= n) continue;
+        const int u = ir[r] * Tce + kk;
+        const float x = P.a * px[r], y = P.a * py[r], z = P.b * pz[r];
+        float ox = hx[r], oy = hy[r], oz = hz[r];
+        if (x > P.pmax[0] || x < P.pmin[0]) ox += gx[r];
+        if (y > P.pmax[1] || y < P.pmin[1]) oy += gy[r];
+        if (z > P.pmax[2] || z < P.pmin[2]) oz += gz[r];
+        L.V[u] = ox;
+        L.V[plane + u] = oy;
+        L.V[2 * plane + u] = oz;
+      }
+    }
+    __syncthreads();
+    // R (+)= W^T H, the forward's W^T tiles
+    {
+      const int nrt = (3 * n + 15) >> 4, nct = (nc + 15) >> 4, nk = (Tce + 3) >> 2;
+      for (int q = wave; q < nrt * nct; q += NT >> 6) {
+        const int rt = q / nct, ct = q - rt * nct;
+        const int rowA = min(rt * 16 + m, 3 * n - 1), cB = min(ct * 16 + m, nc - 1);
+        const float* vrow = L.V + rowA * Tce;
+        floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+        int s4 = 0;
+        for (; s4 + 2 <= nk; s4 += 2) {
+          const int k0s = 4 * s4 + kq, k1s = k0s + 4;
+          const float a0 = k0s < Tce ? vrow[min(k0s, Tce - 1)] : 0.f;
+          const float a1 = k1s < Tce ? vrow[min(k1s, Tce - 1)] : 0.f;
+          const float b0 = Wc[min(k0s, Tce - 1) * nc + cB];
+          const float b1 = Wc[min(k1s, Tce - 1) * nc + cB];
+          acc0 = mfma_16x16x4(a0, b0, acc0);
+          acc1 = mfma_16x16x4(a1, b1, acc1);
+        }
+        if (s4 < nk) {
+          const int k0s = 4 * s4 + kq;
+          const float a0 = k0s < Tce ? vrow[min(k0s, Tce - 1)] : 0.f;
+          acc0 = mfma_16x16x4(a0, Wc[min(k0s, Tce - 1) * nc + cB], acc0);
+        }
+        const int c = ct * 16 + m;
+        if (c < nc) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = rt * 16 + 4 * kq + v;
+            if (row < 3 * n) {
+              const float sum = acc0[v] + acc1[v];
+              L.R[row * nc + c] = k0 == 0 ? sum : L.R[row * nc + c] + sum;
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void bwd3_kernel(BwdArgs A, int Tv) {
+  extern __shared__ float lds3[];
+  const int b = A.order[blockIdx.x];
+  const ProbDesc P = A.probs[b];
+  const int n = P.n, nc = A.nc, tid = threadIdx.x;
+  const int nn = n * nc, S = 3 * nn, nc2 = nc * nc;
+  const Lds3 L = carve3(lds3, nc, A.Tc, A.n_max, A.M_max, A.S_max);
+  const Lds3b B = carve3b(lds3 + lds3_floats(nc, A.Tc, A.n_max, A.M_max, A.S_max), A.S_max);
+  const float rho = A.rho, fw = A.fp_weight;
+  const size_t St = (size_t)A.S_total;
+  const int rpt = robots_per_thread(n);
+
+  setup3<NT>(A, P, L, A.obs);
+  for (int t = tid; t < S; t += NT) {
+    L.cxi[t] = A.cxi[P.coef_off + t];
+    B.gA[t] = A.g_xi_out ? A.g_xi_out[P.coef_off + t] : 0.f;
+    B.glam[t] = A.g_lam_out ? A.g_lam_out[P.coef_off + t] : 0.f;
+    B.gxi[t] = 0.f;
+  }
+  __syncthreads();
+  float* gx = B.gA;
+  float* gn = B.gB;
+
+  // cotangents of ||r_1|| and ||r_2|| of the returned iterate
+  const float gr1 = A.g_res ? A.g_res[(size_t)b * 4] : 0.f;
+  const float gr2 = A.g_res ? A.g_res[(size_t)b * 4 + 1] : 0.f;
+  if (gr1 != 0.f || gr2 != 0.f) {
+    float* xf = L.xb[0];
+    for (int t = tid; t < S; t += NT) xf[t] = A.fin[P.coef_off + t];
+    __syncthreads();
+    float v[3] = {0.f, 0.f, 0.f};
+    sweep3_any<NT, kFinal>(A, P, L, xf, v[0], v[1]);
+    block_sum3<NT>(v, L.red);
+    const float c1 = v[0] > 0.f ? gr1 / sqrtf(v[0]) : 0.f;
+    const float c2 = v[1] > 0.f ? gr2 / sqrtf(v[1]) : 0.f;
+    float d0 = 0.f, d1 = 0.f;
+    sweep3_any<NT, kResGrad>(A, P, L, xf, d0, d1, c1, c2);
+    for (int t = tid; t < S; t += NT) gx[t] += L.R[t];
+    __syncthreads();
+  }
+
+  const int L_ = A.L, k = A.ckpt_every;
+  const int nseg = (L_ + k - 1) / k;
+  float dz = 0.f;
+  for (int seg = nseg - 1; seg >= 0; --seg) {
+    const int l0 = seg * k;
+    const int l1 = min(L_, l0 + k);
+    const float* ck = A.ckpt + (size_t)seg * 2 * St + P.coef_off;
+    if (l1 - 1 > l0) {
+      // recompute iterates l0+1 .. l1-1 into the segment area (slot l - l0)
+      float* xc = L.xb[0];
+      float* xq = L.xb[1];
+      for (int t = tid; t < S; t += NT) {
+        xc[t] = ck[t];
+        L.lam[t] = ck[St + t];
+      }
+      __syncthreads();
+      for (int l = l0; l < l1 - 1; ++l) {
+        iterate3<NT>(A, P, L, xc, xq, false, dz);
+        float* tmp = xc;
+        xc = xq;
+        xq = tmp;
+        float* dst = A.seg + (size_t)(l + 1 - l0) * 2 * St + P.coef_off;
+        for (int t = tid; t < S; t += NT) {
+          dst[t] = xc[t];
+          dst[St + t] = L.lam[t];
+        }
+      }
+      __syncthreads();
+    }
+    for (int l = l1 - 1; l >= l0; --l) {
+      const float* cur = l == l0 ? ck : A.seg + (size_t)(l - l0) * 2 * St + P.coef_off;
+      const float* nxt = (l + 1 < l1) ? A.seg + (size_t)(l + 1 - l0) * 2 * St + P.coef_off
+                         : (l1 == L_) ? A.fin + P.coef_off
+                                      : A.ckpt + (size_t)(seg + 1) * 2 * St + P.coef_off;
+      float* xl = L.xb[0];
+      // the cotangent entering the step: g + 2 fw (xi_bar^{l+1} - xi_bar^l)
+      for (int t = tid; t < S; t += NT) {
+        xl[t] = cur[t];
+        if (fw != 0.f) gx[t] = fmaf(2.f * fw, nxt[t] - cur[t], gx[t]);
+      }
+      __syncthreads();
+      // robot means of g: means[0..3nc)
+      for (int t = tid; t < 3 * nc; t += NT) {
+        const int ax = t / nc, c = t - ax * nc;
+        float sm = 0.f;
+        for (int i = 0; i < n; ++i) sm += gx[ax * nn + i * nc + c];
+        L.means[t] = sm / (float)n;
+      }
+      __syncthreads();
+      // g_u = S^T g, g_xi_bar (before the VJP) = SH^T g - 2 fw (dxi), g_R
+      for (int t = tid; t < S; t += NT) {
+        const int ax = t / nn, rem = t - ax * nn, i = rem / nc, q = rem - i * nc;
+        const float* g = gx + ax * nn + i * nc;
+        const float* gm = L.means + ax * nc;
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+        for (int c = 0; c < nc; ++c) {
+          const float* row = L.fac + c * nc + q;     // column q of row c
+          a0 = fmaf(row[0], g[c], a0);
+          a1 = fmaf(row[nc2], gm[c], a1);
+          a2 = fmaf(row[2 * nc2], g[c], a2);
+          a3 = fmaf(row[3 * nc2], gm[c], a3);
+        }
+        const float gu = a0 + a1;
+        const float dxi = fw != 0.f ? nxt[t] - cur[t] : 0.f;
+        const float dla = fw != 0.f ? nxt[St + t] - cur[St + t] : 0.f;
+        const float gl = B.glam[t];
+        B.gR[t] = fmaf(-2.f * rho, gu, fmaf(-rho, gl, -2.f * rho * fw * dla));
+        B.glam[t] = gl + gu;
+        B.gxi[t] += gu;
+        gn[t] = fmaf(-2.f * fw, dxi, a2 + a3);
+      }
+      __syncthreads();
+      if (rpt == 4)
+        vjp3<NT, 4>(A, P, L, B, xl, Tv);
+      else if (rpt == 2)
+        vjp3<NT, 2>(A, P, L, B, xl, Tv);
+      else
+        vjp3<NT, 1>(A, P, L, B, xl, Tv);
+      for (int t = tid; t < S; t += NT) gn[t] += L.R[t];
+      __syncthreads();
+      float* tmp = gx;
+      gx = gn;
+      gn = tmp;
+    }
+  }
+  for (int t = tid; t < S; t += NT) {
+    if (A.g_xi0) A.g_xi0[P.coef_off + t] = gx[t];
+    if (A.g_lam0) A.g_lam0[P.coef_off + t] = B.glam[t];
+    if (A.g_xi) A.g_xi[P.coef_off + t] = B.gxi[t];
+  }
+}
+
 }  // namespace
 
 size_t fwd3_lds_bytes(int nc, int T, int Tc, int n_max, int M_max, int S_max) {
   (void)T;
-  const size_t f = (size_t)r4(Tc * nc) + r4(fac_stride(nc)) + 5 * (size_t)r4(S_max) +
-                   6 * kMaxCoef + 8 + (size_t)kObsFloats * M_max + kRed3 +
-                   6 * (size_t)n_max * Tc;
-  return f * sizeof(float);
+  return lds3_floats(nc, Tc, n_max, M_max, S_max) * sizeof(float);
+}
+
+size_t bwd3_lds_bytes(int nc, int Tc, int Tv, int n_max, int M_max, int S_max) {
+  return (lds3_floats(nc, Tc, n_max, M_max, S_max) + 5 * (size_t)r4(S_max) +
+          3 * (size_t)n_max * Tv) * sizeof(float);
 }
 
 hipError_t prepare_kernels3(size_t lds) {
   const void* fns[] = {reinterpret_cast<const void*>(&fwd3_kernel<256>),
                        reinterpret_cast<const void*>(&fwd3_kernel<512>),
-                       reinterpret_cast<const void*>(&fwd3_kernel<1024>)};
+                       reinterpret_cast<const void*>(&fwd3_kernel<1024>),
+                       reinterpret_cast<const void*>(&bwd3_kernel<256>),
+                       reinterpret_cast<const void*>(&bwd3_kernel<512>),
+                       reinterpret_cast<const void*>(&bwd3_kernel<1024>)};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -513,6 +926,24 @@ hipError_t launch_fwd3(const FwdArgs& a, int threads, size_t lds, hipStream_t s)
       break;
     case 1024:
       hipLaunchKernelGGL(fwd3_kernel<1024>, grid, dim3(1024), lds, s, a);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_bwd3(const BwdArgs& a, int threads, size_t lds, int Tv, hipStream_t s) {
+  dim3 grid(a.B);
+  switch (threads) {
+    case 256:
+      hipLaunchKernelGGL(bwd3_kernel<256>, grid, dim3(256), lds, s, a, Tv);
+      break;
+    case 512:
+      hipLaunchKernelGGL(bwd3_kernel<512>, grid, dim3(512), lds, s, a, Tv);
+      break;
+    case 1024:
+      hipLaunchKernelGGL(bwd3_kernel<1024>, grid, dim3(1024), lds, s, a, Tv);
       break;
     default:
       return hipErrorInvalidValue;

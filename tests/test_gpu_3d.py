@@ -36,10 +36,11 @@ def _oracle(inp, objective="projection"):
                     objective=objective)
 
 
-def _plan(pk, threads=0, objective=0):
+def _plan(pk, threads=0, objective=0, max_iters=0, ckpt=1):
     from paper_2510_09204_amd import SFPlan
     return SFPlan(pk.n_robots, pk.n_obs, pk.robot_ab, pk.box, pk.n_coef, pk.n_steps, RHO,
-                  threads=threads, n_dim=3, objective=objective)
+                  threads=threads, n_dim=3, objective=objective, max_iters=max_iters,
+                  checkpoint_every=ckpt)
 
 
 def _run(probs, L, threads=0, objective=0):
@@ -175,13 +176,15 @@ def test_3d_unsupported_calls_fail_loudly(gpu):
     t = {k: torch.from_numpy(getattr(pk, k)).cuda() for k in ("xi", "xi0", "lam0",
                                                                "boundary", "obstacles")}
     args = (t["xi"], t["xi0"], t["lam0"], t["boundary"], t["obstacles"], 5)
+    # the per-stage baselines are planar only; saving needs max_iters >= L
     for kw in (dict(save=True), dict(plain=True), dict(unfused=True)):
         with pytest.raises(SFError):
             plan.project(*args, **kw)
     with pytest.raises(SFError):
         plan.set_early_exit(1e-3, 10)
-    with pytest.raises(SFError):
+    with pytest.raises(SFError) as e:
         plan.backward(t["xi0"], None, None)
+    assert e.value.code == -4
 
 
 @pytest.mark.parametrize("cfg_id,batch,L", [(16, 3, 50), (48, 5, 40)])
@@ -216,3 +219,118 @@ def test_3d_moving_obstacles_match_oracle(gpu, cfg_id, batch, L):
     torch.cuda.synchronize()
     np.testing.assert_array_equal(back.cpu().numpy(), static[1])
     finish_parity(errs)
+
+
+# ---------------------------------------------------------------- 3D adjoint
+def _run_grad(probs, L, ckpt, seed, g_res=None, fp_weight=0.0, threads=0):
+    import torch
+    pk = pack3d(probs)
+    plan = _plan(pk, threads=threads, max_iters=L, ckpt=ckpt)
+    t = {k: torch.from_numpy(getattr(pk, k)).cuda() for k in ("xi", "xi0", "lam0",
+                                                               "boundary", "obstacles")}
+    xo, lo, res = plan.project(t["xi"], t["xi0"], t["lam0"], t["boundary"],
+                               t["obstacles"] if pk.obstacles.size else None, L, save=True)
+    rng = np.random.default_rng(seed)
+    g_xi = [rng.standard_normal(p.xi.shape) for p in probs]
+    g_lam = [rng.standard_normal(p.xi.shape) for p in probs]
+    dev = lambda gs: torch.from_numpy(np.concatenate([g.ravel() for g in gs])
+                                      .astype(np.float32)).cuda()
+    gr = None if g_res is None else torch.from_numpy(g_res.astype(np.float32)).cuda()
+    g = plan.backward(dev(g_xi), dev(g_lam), gr, fp_weight)
+    torch.cuda.synchronize()
+    return pk, [unpack3d(x.cpu().numpy(), probs) for x in g], g_xi, g_lam, res.cpu().numpy()
+
+
+def _check_grad(probs, pk, grads, L, g_xi, g_lam, g_res=None, fp_weight=0.0, idx=None):
+    from oracle import SFAdjoint
+    from sf_testlib import GRAD_REL_TOL
+    inps = _inputs3d(pk, probs)
+    for b in (range(len(probs)) if idx is None else idx):
+        inp = inps[b]
+        gr1 = 0.0 if g_res is None else float(np.float32(g_res[b, 0]))
+        gr2 = 0.0 if g_res is None else float(np.float32(g_res[b, 1]))
+        ref = SFAdjoint(_oracle(inp)).gradient(
+            inp["xi"], inp["xi0"], inp["lam0"], L,
+            g_xi[b].astype(np.float32).astype(np.float64),
+            g_lam[b].astype(np.float32).astype(np.float64), gr1, gr2, fp_weight)
+        errs = {name: rel_err(gv, rv) for name, gv, rv in
+                (("xi", grads[0][b], ref.g_xi), ("xi0", grads[1][b], ref.g_xi0),
+                 ("lam0", grads[2][b], ref.g_lam0))}
+        print(f"[grad3d] L={L} problem {b} (n={inp['n']}, M={inp['M']}): "
+              + ", ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
+        for name, e in errs.items():
+            assert e <= GRAD_REL_TOL, (b, name, e)
+
+
+@pytest.mark.parametrize("cfg_id,batch,L,ckpt", [(16, 2, 30, 1), (32, 2, 25, 5),
+                                                  (48, 4, 20, 3)])
+def test_3d_adjoint_matches_oracle(gpu, cfg_id, batch, L, ckpt):
+    """The 3D reverse sweep (sf_project_backward, n_dim = 3) against the FP64
+    oracle's on the three 3D workloads, with checkpoint recompute."""
+    probs = make_batch3d(WORKLOADS_3D[cfg_id], batch=batch)
+    pk, grads, g_xi, g_lam, _ = _run_grad(probs, L, ckpt, seed=cfg_id)
+    _check_grad(probs, pk, grads, L, g_xi, g_lam)
+
+
+def test_3d_adjoint_with_residual_and_fixed_point_terms(gpu):
+    cfg = scaled3d(WORKLOADS_3D[16], n_robots=(6, 6), n_obs=(4, 4), side=2.5, height=1.4)
+    probs = make_batch3d(cfg, batch=2)
+    g_res = np.array([[0.7, 0.4, 0.0, 0.0], [1.3, 0.6, 0.0, 0.0]])
+    pk, grads, g_xi, g_lam, res = _run_grad(probs, 12, 4, seed=3, g_res=g_res, fp_weight=0.25)
+    # both residual terms are exercised (pair/obstacle and box, nonzero norms)
+    assert res[:, 0].max() > 1e-2 and res[:, 1].max() > 1e-2, res
+    _check_grad(probs, pk, grads, 12, g_xi, g_lam, g_res, 0.25)
+
+
+def test_3d_adjoint_time_chunked_horizon(gpu):
+    """64 robots, 15 coefficients, 120 steps: the recompute runs the forward's
+    LDS time chunks and the VJP its own shorter chunks."""
+    cfg = scaled3d(WORKLOADS_3D[32], n_robots=(64, 64), n_obs=(30, 30), side=16.0,
+                   height=8.0, n_coef=15, n_steps=120)
+    probs = make_batch3d(cfg, batch=1)
+    pk, grads, g_xi, g_lam, _ = _run_grad(probs, 8, 3, seed=5)
+    _check_grad(probs, pk, grads, 8, g_xi, g_lam)
+
+
+def test_3d_adjoint_checkpoint_interval_and_threads_give_the_same_bits(gpu):
+    probs = make_batch3d(WORKLOADS_3D[48], batch=4)
+    g_res = np.tile([[0.5, 0.5, 0.0, 0.0]], (4, 1))
+    ref = _run_grad(probs, 24, 1, seed=9, g_res=g_res, fp_weight=0.1, threads=1024)[1]
+    for ckpt, th in ((5, 1024), (24, 1024), (5, 256)):
+        got = _run_grad(probs, 24, ckpt, seed=9, g_res=g_res, fp_weight=0.1, threads=th)[1]
+        for q in range(3):
+            for b in range(4):
+                np.testing.assert_array_equal(got[q][b], ref[q][b])
+
+
+def test_3d_autograd_function(gpu):
+    """SFProject on a 3D plan: the loss sum ||xi_bar^L - straight||^2 + ||r_1||^2
+    through the library's forward and adjoint against the oracle's gradient."""
+    import torch
+    from oracle import SFAdjoint
+    from paper_2510_09204_amd import SFProject
+    from sf_testlib import GRAD_REL_TOL
+    cfg = scaled3d(WORKLOADS_3D[16], n_robots=(5, 5), n_obs=(3, 3), side=3.0, height=1.6)
+    probs = make_batch3d(cfg, batch=2)
+    pk = pack3d(probs)
+    L = 15
+    plan = _plan(pk, max_iters=L, ckpt=4)
+    t = {k: torch.from_numpy(getattr(pk, k)).cuda() for k in ("xi", "xi0", "lam0",
+                                                               "boundary", "obstacles")}
+    straight = torch.from_numpy(np.concatenate([p.straight.ravel() for p in probs])
+                                .astype(np.float32)).cuda()
+    xi = t["xi"].clone().requires_grad_(True)
+    xi0 = t["xi0"].clone().requires_grad_(True)
+    xo, lo, res = SFProject.apply(xi, xi0, t["lam0"], t["boundary"], t["obstacles"], plan, L)
+    loss = ((xo - straight) ** 2).sum() + (res[:, 0] ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    g_out = unpack3d(2.0 * (xo.detach().cpu().numpy() - straight.cpu().numpy()), probs)
+    r = res.detach().cpu().numpy()
+    for b, inp in enumerate(_inputs3d(pk, probs)):
+        ref = SFAdjoint(_oracle(inp)).gradient(inp["xi"], inp["xi0"], inp["lam0"], L, g_out[b],
+                                               np.zeros_like(g_out[b]), 2.0 * float(r[b, 0]))
+        got_xi = unpack3d(xi.grad.cpu().numpy(), probs)[b]
+        got_xi0 = unpack3d(xi0.grad.cpu().numpy(), probs)[b]
+        assert rel_err(got_xi, ref.g_xi) <= GRAD_REL_TOL, b
+        assert rel_err(got_xi0, ref.g_xi0) <= GRAD_REL_TOL, b
