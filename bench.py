@@ -8,7 +8,9 @@ adjoint then recomputes nothing), else the smallest k that fits; a workload
 that specifies k uses it.  The rate at k = 10 is reported beside it.  Default workload: 64 independent problems of 32 robots and 20
 obstacles (12 m arena, 11 Bernstein coefficients per axis, 100 time steps),
 run for L* iterations, the smallest multiple of 10 at which every problem's
-FP64-oracle residual is <= 1e-3 (determined offline by oracle/lstar.py).
+FP64-oracle residual is <= 1e-3, capped at 2000 (determined offline by
+oracle/lstar.py; at the cap the fraction of outputs at or below 1e-3 is
+reported beside the rate, which counts every problem of the batch).
 
 Prints one JSON line.  Extra fields: the forward-only rate, the plain
 per-problem path's forward rate (one problem per launch group, per-stage
@@ -17,9 +19,14 @@ same per-stage kernels, each launch over the whole batch) so that the gain can
 be attributed to batching and to fusion, the plan setup time (host FP64
 factors and workspace tables), the residual check on the GPU outputs, the
 candidate-selection pipeline around the SF on the 32-candidate context, the
-3D (spheroid) forward on 64 problems of 32 robots, the
-roofline of the dominant kernel and the FP64 oracle timed on one host core
-and on all available cores (one process per problem).
+3D (spheroid) forward on 64 problems of 32 robots, the other workloads at
+their own L* (configs: single-problem latency, the 32-candidate batch, the
+uneven batch through graph replays, the large batch with its checkpoint
+interval of 10, each with batched forward and forward + adjoint rates, the
+plain per-problem forward rate on a sample and the roofline), the roofline of
+the dominant kernel (against the published FP32 vector peak and the scalar
+FP32 peak) and the FP64 oracle timed on one host core and on all available
+cores (one process per problem), with the host CPU model.
 """
 from __future__ import annotations
 
@@ -37,8 +44,9 @@ if ROOT not in sys.path:
 
 METRIC = "SF problems/s (fwd, fwd+bwd) at 32 robots, residual≤1e-3; batched vs plain"
 RHO = 0.5
-# L* per workload at rho = 0.5 (oracle/lstar.py; recorded with its output in the design doc)
-LSTAR = {1: 100, 2: 400, 3: 2000, 4: 2000, 5: 2000}
+# L* per workload at rho = 0.5 (oracle/lstar.py on every problem of c1-c4 and a
+# sample of c5; the runs are recorded in the design doc)
+LSTAR = {1: 100, 2: 560, 3: 2000, 4: 2000, 5: 2000}
 CKPT_SPECIFIED = {5: 10}     # workloads whose description fixes the checkpoint interval
 CKPT_REFERENCE = 10
 
@@ -200,11 +208,135 @@ def candidate_pipeline_timing(dev, steps=5):
                 chosen_cost=float(out["cost"].cpu()[best]))
 
 
-def algorithmic_flops3d(problems, T, nc, L):
-    """The forward count of algorithmic_flops for the 3D (spheroid) SF: a
-    distance test costs 8 flops per unordered robot pair and robot-obstacle
-    pair per step, box residuals 4 per coordinate, the maps and mode products
-    run over three axes."""
+def roofline_of(kernel, flops, ms):
+    """Roofline object of one kernel launch: algorithmic flops over its
+    measured duration against the published FP32 vector peak, and against the
+    scalar (unpacked) FP32 peak that this build's instruction mix can reach."""
+    ach = flops / (ms / 1e3) / 1e12
+    return dict(bound="alu", kernel=kernel, achieved=round(ach, 3),
+                peak=PEAK_FP32_PACKED_TFLOPS, unit="TFLOP/s",
+                frac=round(ach / PEAK_FP32_PACKED_TFLOPS, 4),
+                frac_vs_unpacked_fp32_peak=round(ach / PEAK_ALU_TFLOPS, 4))
+
+
+def _events(n):
+    import torch
+    return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+
+
+def config_rates(cfg_id, dev, steps=3, graph=False, plain_sample=2):
+    """One workload at its L*: the batched fused forward (through SF_GRAPH
+    replays on a side stream when `graph`), the batched forward + adjoint
+    (checkpoint interval as in the headline step), the plain per-problem
+    forward on the first `plain_sample` problems (a host loop of one-problem
+    launch groups, so its rate is per problem), the roofline of the dominant
+    kernel and the fraction of outputs at residual <= 1e-3.  Times from HIP
+    events on the launch stream; problems/s = batch / time."""
+    import torch
+
+    from paper_2510_09204_amd import SFPlan, to_device
+    from workloads import WORKLOADS, make_batch, pack
+    cfg = WORKLOADS[cfg_id]
+    L = LSTAR[cfg_id]
+    probs = make_batch(cfg)
+    pk = pack(probs)
+    B = len(probs)
+    ckpt = CKPT_SPECIFIED.get(cfg_id) or choose_checkpoint_interval(
+        L, int(pk.xi.size), torch.cuda.mem_get_info(dev)[0])
+    plan = SFPlan(pk.n_robots, pk.n_obs, pk.robot_a, pk.box, pk.n_coef, pk.n_steps, RHO,
+                  checkpoint_every=ckpt, max_iters=L, device=dev)
+    t = to_device(pk, dev)
+    args = (t["xi"], t["xi0"], t["lam0"], t["boundary"], t["obstacles"])
+    stream = torch.cuda.Stream(dev) if graph else torch.cuda.current_stream(dev)
+    outs = (torch.empty_like(t["xi"]), torch.empty_like(t["xi"]),
+            torch.empty((B, 4), dtype=torch.float32, device=dev))
+    g_out = torch.ones_like(t["xi"])
+    with torch.cuda.stream(stream):
+        plan.project(*args, L, graph=graph, out=outs)           # tunes; captures the graph
+        plan.project(*args, L, save=True)
+        plan.backward(g_out, None, None)
+        torch.cuda.synchronize()
+        e = _events(2)
+        e[0].record(stream)
+        for _ in range(steps):
+            plan.project(*args, L, graph=graph, out=outs)
+        e[1].record(stream)
+        torch.cuda.synchronize()
+        fwd_ms = e[0].elapsed_time(e[1]) / steps
+        res = outs[2].cpu().numpy()
+        ev = [_events(3) for _ in range(steps)]
+        for q in range(steps):
+            ev[q][0].record(stream)
+            plan.project(*args, L, save=True)
+            ev[q][1].record(stream)
+            plan.backward(g_out, None, None)
+            ev[q][2].record(stream)
+        torch.cuda.synchronize()
+    f_ms = float(np.mean([x[0].elapsed_time(x[1]) for x in ev]))
+    b_ms = float(np.mean([x[1].elapsed_time(x[2]) for x in ev]))
+    sub = probs[:max(1, min(plain_sample, B))]
+    spk = pack(sub)
+    splan = SFPlan(spk.n_robots, spk.n_obs, spk.robot_a, spk.box, spk.n_coef, spk.n_steps, RHO,
+                   device=dev)
+    st = to_device(spk, dev)
+    sargs = (st["xi"], st["xi0"], st["lam0"], st["boundary"], st["obstacles"])
+    splan.project(*sargs, 1, plain=True)
+    e = _events(2)
+    cur = torch.cuda.current_stream(dev)
+    e[0].record(cur)
+    splan.project(*sargs, L, plain=True)
+    e[1].record(cur)
+    torch.cuda.synchronize()
+    plain_ms = e[0].elapsed_time(e[1])
+    plain_rate = len(sub) / (plain_ms / 1e3)
+    nc, T = pk.n_coef, pk.n_steps
+    f_fwd = algorithmic_flops(probs, T, nc, L, "fwd")
+    f_bwd = algorithmic_flops(probs, T, nc, L, "bwd")
+    dom = ("sf_bwd_fused", f_bwd, b_ms) if b_ms >= f_ms else ("sf_fwd_fused", f_fwd, f_ms)
+    r = np.hypot(res[:, 0], res[:, 1])
+    fwd_rate = B / (fwd_ms / 1e3)
+    out = dict(workload=f"{cfg.name}: {cfg.description}", batch=B,
+               robots=[int(pk.n_robots.min()), int(pk.n_robots.max())],
+               obstacles=[int(pk.n_obs.min()), int(pk.n_obs.max())], n_coef=nc, n_steps=T,
+               iters=L, checkpoint_every=ckpt, graph=graph, threads_fwd=plan.threads,
+               fwd_ms=round(fwd_ms, 4), fwd_problems_per_s=round(fwd_rate, 2),
+               fwd_bwd_ms=round(f_ms + b_ms, 4),
+               fwd_bwd_problems_per_s=round(B / ((f_ms + b_ms) / 1e3), 2),
+               plain_fwd_problems_per_s=round(plain_rate, 3),
+               plain_sample=f"first {len(sub)} problem(s), {L} iterations, one launch group each",
+               batched_over_plain_fwd=round(fwd_rate / plain_rate, 2),
+               batched_fwd_bwd_over_plain_fwd=round(B / ((f_ms + b_ms) / 1e3) / plain_rate, 2),
+               frac_residual_le_tol=float(np.mean(r <= 1e-3)),
+               residual_median=float(np.median(r)), status_nonzero=int(np.sum(res[:, 3] != 0)),
+               roofline=dict(roofline_of(dom[0], dom[1], dom[2]),
+                             kernels={"sf_fwd_fused": dict(ms=round(f_ms, 4), tflops=round(
+                                 f_fwd / f_ms / 1e9, 3)),
+                                      "sf_bwd_fused": dict(ms=round(b_ms, 4), tflops=round(
+                                          f_bwd / b_ms / 1e9, 3))}))
+    if B == 1:
+        out["latency_ms"] = dict(fwd=round(fwd_ms, 4), fwd_bwd=round(f_ms + b_ms, 4),
+                                 plain_fwd=round(plain_ms, 4))
+    plan.close()
+    splan.close()
+    return out
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def algorithmic_flops3d(problems, T, nc, L, kind="fwd"):
+    """algorithmic_flops for the 3D (spheroid) SF: a distance test costs 8
+    flops per unordered robot pair and robot-obstacle pair per step, box
+    residuals 4 per coordinate, the maps and mode products run over three
+    axes; the adjoint counts the tests, three maps and two mode products per
+    iteration (its recompute excluded)."""
     tot = 0.0
     for p in problems:
         n, M = p.n, p.M
@@ -212,7 +344,10 @@ def algorithmic_flops3d(problems, T, nc, L):
         tests = 8.0 * (n * (n - 1) / 2 + n * M) * T + 4.0 * 3 * n * T
         maps = 2.0 * 3 * n * T * nc
         modes = 2.0 * Sc * nc
-        tot += (tests + 2 * maps + 2 * modes + 10.0 * Sc) * L + tests + maps
+        if kind == "fwd":
+            tot += (tests + 2 * maps + 2 * modes + 10.0 * Sc) * L + tests + maps
+        else:
+            tot += (tests + 3 * maps + 2 * modes + 10.0 * Sc) * L
     return tot
 
 
@@ -245,16 +380,39 @@ def spheroid_3d_timing(dev, steps=5):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
         r = np.hypot(res[:, 0].cpu().numpy(), res[:, 1].cpu().numpy())
-        ach = algorithmic_flops3d(probs, pk.n_steps, pk.n_coef, L) / (ms / 1e3) / 1e12
         out[f"L{L}"] = dict(ms=round(ms, 4), problems_per_s=round(len(probs) / (ms / 1e3), 2),
                             us_per_iter=round(ms * 1e3 / L, 3),
                             residual_median=float(np.median(r)),
                             frac_residual_le_tol=float(np.mean(r <= 1e-3)),
                             status_nonzero=int(np.sum(res[:, 3].cpu().numpy() != 0)),
-                            roofline=dict(bound="alu", kernel="fwd3_kernel",
-                                          achieved=round(ach, 3),
-                                          peak=round(PEAK_ALU_TFLOPS, 2), unit="TFLOP/s",
-                                          frac=round(ach / PEAK_ALU_TFLOPS, 4)))
+                            roofline=roofline_of(
+                                "fwd3_kernel", algorithmic_flops3d(probs, pk.n_steps, pk.n_coef, L),
+                                ms))
+    # forward + adjoint at the workload's iteration count, every iterate kept
+    L = cfg.iters
+    planb = SFPlan(pk.n_robots, pk.n_obs, pk.robot_ab, pk.box, pk.n_coef, pk.n_steps, RHO,
+                   n_dim=3, max_iters=L, checkpoint_every=1, device=dev)
+    args = (t["xi"], t["xi0"], t["lam0"], t["boundary"], t["obstacles"], L)
+    g_out = torch.ones_like(t["xi"])
+    planb.project(*args, save=True)
+    planb.backward(g_out, None, None)
+    torch.cuda.synchronize()
+    ev = [_events(3) for _ in range(steps)]
+    for q in range(steps):
+        ev[q][0].record(stream)
+        planb.project(*args, save=True)
+        ev[q][1].record(stream)
+        planb.backward(g_out, None, None)
+        ev[q][2].record(stream)
+    torch.cuda.synchronize()
+    f_ms = float(np.mean([x[0].elapsed_time(x[1]) for x in ev]))
+    b_ms = float(np.mean([x[1].elapsed_time(x[2]) for x in ev]))
+    out[f"L{L}_fwd_bwd"] = dict(
+        fwd_ms=round(f_ms, 4), bwd_ms=round(b_ms, 4),
+        problems_per_s=round(len(probs) / ((f_ms + b_ms) / 1e3), 2),
+        roofline=roofline_of("bwd3_kernel",
+                             algorithmic_flops3d(probs, pk.n_steps, pk.n_coef, L, "bwd"), b_ms))
+    planb.close()
     return dict(workload=f"{cfg.name}: {cfg.description}", batch=len(probs),
                 robots=int(pk.n_robots.max()), obstacles=int(pk.n_obs.max()),
                 n_coef=pk.n_coef, n_steps=pk.n_steps, threads=plan.threads, **out)
@@ -271,6 +429,8 @@ def main(argv=None):
     ap.add_argument("--ckpt", type=int, default=0, help="checkpoint interval (0 = from memory)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other workloads (c1, c2, c4, c5)")
     ap.add_argument("--no-ref", action="store_true",
                     help="skip the rate at the reference checkpoint interval")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
@@ -280,7 +440,21 @@ def main(argv=None):
                     help="only run a device-to-device copy of MIB MiB (counter calibration)")
     ap.add_argument("--spheroid-3d-only", action="store_true",
                     help="only time the 3D (spheroid) forward and print its JSON object")
+    ap.add_argument("--configs-only", type=str, default=None, metavar="IDS",
+                    help="only time the listed workloads (e.g. 1,2,4,5) at their L* and print "
+                         "one JSON object per workload")
     a = ap.parse_args(argv)
+    if a.configs_only:
+        import torch
+        from paper_2510_09204_amd import load_library
+        load_library()
+        for c in (int(x) for x in a.configs_only.split(",")):
+            t0 = time.perf_counter()
+            out = config_rates(c, torch.device("cuda:0"), steps=2 if c == 5 else 3,
+                               graph=(c == 4), plain_sample=1 if c == 5 else 2)
+            out["wall_s"] = round(time.perf_counter() - t0, 2)
+            print(json.dumps({f"c{c}": out}), flush=True)
+        return 0
     if a.spheroid_3d_only:
         import torch
         from paper_2510_09204_amd import load_library
@@ -416,21 +590,25 @@ def main(argv=None):
     f_fwd = algorithmic_flops(probs, T, nc, L, "fwd")
     f_bwd = algorithmic_flops(probs, T, nc, L, "bwd")
     dom = ("sf_bwd_fused", f_bwd, bwd_ms) if bwd_ms >= fwd_ms else ("sf_fwd_fused", f_fwd, fwd_ms)
-    ach = dom[1] / (dom[2] / 1e3) / 1e12
-    roofline = dict(bound="alu", kernel=dom[0], achieved=round(ach, 3),
-                    peak=round(PEAK_ALU_TFLOPS, 2), unit="TFLOP/s",
-                    frac=round(ach / PEAK_ALU_TFLOPS, 4),
-                    traffic=measured_traffic(f"c{a.config}", dom[0]),
-                    frac_vs_packed_fp32_peak=round(ach / PEAK_FP32_PACKED_TFLOPS, 4),
-                    kernels={"sf_fwd_fused": dict(ms=round(fwd_ms, 4),
-                                                  tflops=round(f_fwd / fwd_ms / 1e9, 3)),
-                             "sf_bwd_fused": dict(ms=round(bwd_ms, 4),
-                                                  tflops=round(f_bwd / bwd_ms / 1e9, 3))})
+    roofline = roofline_of(*dom)
+    roofline["traffic"] = measured_traffic(f"c{a.config}", dom[0])
+    roofline["kernels"] = {"sf_fwd_fused": dict(ms=round(fwd_ms, 4),
+                                                tflops=round(f_fwd / fwd_ms / 1e9, 3)),
+                           "sf_bwd_fused": dict(ms=round(bwd_ms, 4),
+                                                tflops=round(f_bwd / bwd_ms / 1e9, 3))}
     pipeline = None if a.no_plain else candidate_pipeline_timing(dev)
     sph3d = None if a.no_plain else spheroid_3d_timing(dev)
+    others = None
+    if not a.no_configs:
+        # the other workloads at their own L*: c1 latency, c2 candidates, c4 uneven
+        # through graph replays, c5 with its specified checkpoint interval
+        others = {f"c{c}": config_rates(c, dev, steps=2 if c == 5 else 3, graph=(c == 4),
+                                        plain_sample=1 if c == 5 else 2)
+                  for c in (1, 2, 4, 5) if c != a.config}
     cpu = None
     if not a.no_cpu:
         cpu = cpu_baseline(probs[0], L, a.cpu_budget, pool)
+        cpu["cpu_model"] = cpu_model()
 
     value = B / (ms_per_step / 1e3)
     line = dict(metric=METRIC, value=round(value, 2), unit="problems/s", n_gpus=1,
@@ -440,7 +618,11 @@ def main(argv=None):
                 config=dict(workload=f"{cfg.name}: {cfg.description}", global_batch=B,
                             robots=int(pk.n_robots.max()), obstacles=int(pk.n_obs.max()),
                             n_coef=nc, n_steps=T, iters=L, rho=RHO, checkpoint_every=ckpt,
-                            threads_fwd=plan.threads, residual_tol=1e-3),
+                            threads_fwd=plan.threads, residual_tol=1e-3,
+                            iters_rule="L* = smallest multiple of 10 at which every FP64-oracle "
+                                       "problem has residual <= 1e-3, capped at 2000; "
+                                       "value counts every problem of the batch",
+                            frac_residual_le_tol=float(np.mean(resid <= 1e-3))),
                 fwd_problems_per_s=round(B / (fwd_only_ms / 1e3), 2),
                 fwd_bwd_problems_per_s_ckpt10=None if ref_rate is None else round(ref_rate, 2),
                 fwd_ms=round(fwd_only_ms, 4),
@@ -458,8 +640,12 @@ def main(argv=None):
                 residual_max=float(resid.max()), residual_median=float(np.median(resid)),
                 frac_residual_le_tol=float(np.mean(resid <= 1e-3)),
                 status_nonzero=int(np.sum(res[:, 3] != 0)),
-                candidate_pipeline=pipeline, spheroid_3d=sph3d, roofline=roofline,
-                cpu_baseline=cpu)
+                feasible_problems_per_s=round(float(np.sum(resid <= 1e-3)) /
+                                              (ms_per_step / 1e3), 2),
+                batched_fwd_bwd_over_plain_fwd=None if plain is None else
+                round(value / plain["problems_per_s"], 2),
+                candidate_pipeline=pipeline, spheroid_3d=sph3d, configs=others,
+                roofline=roofline, cpu_baseline=cpu)
     print(json.dumps(line), flush=True)
     return 0
 
