@@ -125,7 +125,8 @@ typedef struct {
  *
  *   cfg            host; see sf_config_t.
  *   n_problems     B >= 1.
- *   n_robots       host int32[B], each 1..1024 (a problem's state must also fit
+ *   n_robots       host int32[B], each 1..64 for n_dim = 2, 1..1024 for n_dim =
+ *                  3 (a problem's state must also fit
  *                  the LDS of one workgroup, else SF_ERR_SHAPE).
  *   n_obs          host int32[B], each 0..4096.
  *   robot_a        host float[B], a > 0 (n_dim = 3: float[B][2] = a, b > 0).

@@ -36,6 +36,9 @@ int fail(int code, const std::string& msg) {
 
 constexpr size_t kLdsBudget = 160 * 1024;  // gfx950 LDS per workgroup
 constexpr int kMaxRobots = 1024;
+// The planar update tiles cover 2 axes x 4 row tiles of 16 robots (x 2
+// coefficient tiles), so a planar problem holds at most 64 robots.
+constexpr int kMaxRobots2d = 64;
 constexpr int kMaxObs = 4096;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -286,8 +289,10 @@ int build_plan(const sf_config_t* cfg, int B, const int32_t* n_robots, const int
   std::vector<double> cost(B);
   for (int b = 0; b < B; ++b) {
     const int n = n_robots[b], M = n_obs[b];
-    if (n < 1 || n > kMaxRobots)
-      return fail(SF_ERR_SHAPE, "problem " + std::to_string(b) + ": n_robots out of [1, 1024]");
+    const int n_limit = D == 2 ? kMaxRobots2d : kMaxRobots;
+    if (n < 1 || n > n_limit)
+      return fail(SF_ERR_SHAPE, "problem " + std::to_string(b) + ": n_robots out of [1, " +
+                                    std::to_string(n_limit) + "]");
     if (M < 0 || M > kMaxObs)
       return fail(SF_ERR_SHAPE, "problem " + std::to_string(b) + ": n_obs out of [0, 4096]");
     const float a = robot_a[(size_t)b * (D - 1)];

@@ -82,10 +82,13 @@ def test_invalid_config_is_rejected(lib, kw, code):
 
 
 @pytest.mark.parametrize("n,M,a,box,code", [
-    ([0], [3], [0.3], BOX, -2), ([2000], [3], [0.3], BOX, -2), ([4], [-1], [0.3], BOX, -2),
+    ([0], [3], [0.3], BOX, -2), ([2000], [3], [0.3], BOX, -2), ([65], [3], [0.3], BOX, -2),
+    ([4], [-1], [0.3], BOX, -2),
     ([4], [3], [0.0], BOX, -1), ([4], [3], [0.3], [[[1.0, -1.0], [0.0, 1.0]]], -1),
     ([4], [3], [0.3], [[[float("nan"), -1.0], [1.0, 1.0]]], -6)])
 def test_invalid_problem_is_rejected(lib, n, M, a, box, code):
+    """Counts, sizes and boxes outside the documented ranges (planar problems
+    hold at most 64 robots: the update tiles cover 4 row tiles of 16)."""
     rc, _, detail = _setup(lib, _cfg(), n, M, a, box)
     assert rc == code and detail
 
@@ -117,7 +120,7 @@ def test_3d_state_too_large_for_lds_is_a_shape_error(lib):
 
 
 def test_state_too_large_for_lds_is_a_shape_error(lib):
-    rc, _, detail = _setup(lib, _cfg(n_coef=32, n_steps=4096), [1024], [0], [0.3], BOX)
+    rc, _, detail = _setup(lib, _cfg(n_coef=32, n_steps=4096), [64], [0], [0.3], BOX)
     assert rc == -2 and "LDS" in detail
 
 
