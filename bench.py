@@ -367,18 +367,28 @@ def spheroid_3d_timing(dev, steps=5):
     t = {k: torch.from_numpy(getattr(pk, k)).to(dev) for k in ("xi", "xi0", "lam0",
                                                                 "boundary", "obstacles")}
     stream = torch.cuda.current_stream(dev)
-    out = {}
-    for L in (cfg.iters, 10 * cfg.iters):
-        args = (t["xi"], t["xi0"], t["lam0"], t["boundary"], t["obstacles"], L)
+    out = {"candidate_lists": plan.set_candidate_lists(True)}
+
+    def fwd_ms(args):
         plan.project(*args)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for _ in range(steps):
-            xo, lo, res = plan.project(*args)
+            res = plan.project(*args)[2]
         e1.record(stream)
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / steps
+        return e0.elapsed_time(e1) / steps, res
+
+    for L in (cfg.iters, 10 * cfg.iters):
+        args = (t["xi"], t["xi0"], t["lam0"], t["boundary"], t["obstacles"], L)
+        if L == cfg.iters:
+            # every pair and obstacle visited at every step (same bits)
+            plan.set_candidate_lists(False)
+            full_ms = fwd_ms(args)[0]
+            plan.set_candidate_lists(True)
+            out[f"L{L}_full_sweep_ms"] = round(full_ms, 4)
+        ms, res = fwd_ms(args)
         r = np.hypot(res[:, 0].cpu().numpy(), res[:, 1].cpu().numpy())
         out[f"L{L}"] = dict(ms=round(ms, 4), problems_per_s=round(len(probs) / (ms / 1e3), 2),
                             us_per_iter=round(ms * 1e3 / L, 3),
@@ -394,21 +404,29 @@ def spheroid_3d_timing(dev, steps=5):
                    n_dim=3, max_iters=L, checkpoint_every=1, device=dev)
     args = (t["xi"], t["xi0"], t["lam0"], t["boundary"], t["obstacles"], L)
     g_out = torch.ones_like(t["xi"])
-    planb.project(*args, save=True)
-    planb.backward(g_out, None, None)
-    torch.cuda.synchronize()
-    ev = [_events(3) for _ in range(steps)]
-    for q in range(steps):
-        ev[q][0].record(stream)
+
+    def fwd_bwd_ms():
         planb.project(*args, save=True)
-        ev[q][1].record(stream)
         planb.backward(g_out, None, None)
-        ev[q][2].record(stream)
-    torch.cuda.synchronize()
-    f_ms = float(np.mean([x[0].elapsed_time(x[1]) for x in ev]))
-    b_ms = float(np.mean([x[1].elapsed_time(x[2]) for x in ev]))
+        torch.cuda.synchronize()
+        ev = [_events(3) for _ in range(steps)]
+        for q in range(steps):
+            ev[q][0].record(stream)
+            planb.project(*args, save=True)
+            ev[q][1].record(stream)
+            planb.backward(g_out, None, None)
+            ev[q][2].record(stream)
+        torch.cuda.synchronize()
+        return (float(np.mean([x[0].elapsed_time(x[1]) for x in ev])),
+                float(np.mean([x[1].elapsed_time(x[2]) for x in ev])))
+
+    planb.set_candidate_lists(False)
+    full_f, full_b = fwd_bwd_ms()
+    planb.set_candidate_lists(True)
+    f_ms, b_ms = fwd_bwd_ms()
     out[f"L{L}_fwd_bwd"] = dict(
-        fwd_ms=round(f_ms, 4), bwd_ms=round(b_ms, 4),
+        candidate_lists=planb.set_candidate_lists(True), full_sweep_fwd_ms=round(full_f, 4),
+        full_sweep_bwd_ms=round(full_b, 4), fwd_ms=round(f_ms, 4), bwd_ms=round(b_ms, 4),
         problems_per_s=round(len(probs) / ((f_ms + b_ms) / 1e3), 2),
         roofline=roofline_of("bwd3_kernel",
                              algorithmic_flops3d(probs, pk.n_steps, pk.n_coef, L, "bwd"), b_ms))

@@ -255,6 +255,25 @@ int64_t sf_forward_generation(const sf_plan_t* plan);
 int sf_set_early_exit(sf_plan_t* plan, float tol, int32_t check_every);
 
 /*
+ * n_dim = 3: switch the candidate lists of the constraint pass on (the
+ * default) or off for later sf_project and sf_project_backward calls.  The
+ * spheroid rows of eqs. inter_robot_polar and workspace_polar add nothing
+ * unless the scaled offset lies inside the unit ball, so each robot keeps,
+ * per 16-step window, a list of the partners and obstacles that can reach it
+ * there (window boxes widened by a skin, rebuilt when a coefficient has moved
+ * further than the skin since the last build) and visits only those, in the
+ * same order as the full pass: both give the same bits.  Off, every pair and
+ * obstacle is visited at every step (for verification and timing).
+ *
+ *   enable   0 = off, otherwise on.
+ * Returns 1 when the lists are in use after the call, 0 when they are off
+ * (switched off, or their LDS did not fit at sf_setup), SF_ERR_INVALID_ARG
+ * for a NULL plan or n_dim = 2 (the planar fused kernels always use lists;
+ * SF_PLAIN visits every pair).
+ */
+int sf_set_candidate_lists(sf_plan_t* plan, int32_t enable);
+
+/*
  * Copy the number of iterations each problem ran in the last sf_project call
  * on this plan (n_iters for every problem without early exit) into iters,
  * device int32[B], asynchronously on stream.

@@ -31,7 +31,7 @@ EXPORTED = ("sf_setup", "sf_project", "sf_project_backward", "sf_destroy",
             "sf_error_string", "sf_last_error_detail", "sf_plan_threads", "sf_set_early_exit",
             "sf_project_iterations", "sf_smoothness", "sf_rank_residual", "sf_select_best",
             "sf_gather_blocks", "sf_set_obstacle_motion", "sf_forward_generation",
-            "sf_project_backward_static")
+            "sf_project_backward_static", "sf_set_candidate_lists")
 
 
 class SFError(RuntimeError):
@@ -85,6 +85,8 @@ def load_library(path: Optional[Path] = None) -> ctypes.CDLL:
     lib.sf_forward_generation.restype = ctypes.c_int64
     lib.sf_set_early_exit.argtypes = [vp, ctypes.c_float, i32]
     lib.sf_set_early_exit.restype = ctypes.c_int
+    lib.sf_set_candidate_lists.argtypes = [vp, i32]
+    lib.sf_set_candidate_lists.restype = ctypes.c_int
     lib.sf_project_iterations.argtypes = [vp, vp, vp, vp]
     lib.sf_project_iterations.restype = ctypes.c_int
     lib.sf_set_obstacle_motion.argtypes = [vp, vp, f32p, vp]
@@ -176,6 +178,14 @@ class SFPlan:
         """sf_set_early_exit: stop a problem once its residual is <= tol at a
         check every `check_every` iterations (0 = off)."""
         _check(self.lib, self.lib.sf_set_early_exit(self._plan, float(tol), int(check_every)))
+
+    def set_candidate_lists(self, enable: bool) -> bool:
+        """sf_set_candidate_lists (n_dim = 3): visit only listed partners and
+        obstacles (same bits) or every one; True when the lists are in use."""
+        rc = self.lib.sf_set_candidate_lists(self._plan, 1 if enable else 0)
+        if rc < 0:
+            _check(self.lib, rc)
+        return rc == 1
 
     def iterations(self) -> torch.Tensor:
         """sf_project_iterations: iterations each problem ran in the last

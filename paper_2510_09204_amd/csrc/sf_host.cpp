@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -205,6 +206,8 @@ struct sf_plan {
   bool tune_bwd = false;
   int Tc_fwd = 0, Tc_bwd = 0;
   int Tv3 = 0;            // 3D adjoint: VJP time chunk (<= Tc_bwd)
+  bool lists3 = false;    // 3D: the candidate lists fit (the kernels' LDS has room)
+  bool lists3_on = true;  // 3D: sf_set_candidate_lists
   size_t lds_fwd = 0, lds_bwd = 0;
   // workspace layout (byte offsets)
   size_t off_desc = 0, off_order = 0, off_W = 0, off_Wdd = 0, off_fac = 0, off_cxi = 0,
@@ -377,38 +380,68 @@ int build_plan(const sf_config_t* cfg, int B, const int32_t* n_robots, const int
     // 16 and 32 robots: 15 / 40 us per iteration against 20 / 50 at 512)
     p->tune_fwd = p->tune_bwd = false;
     if (cfg->threads == 0) p->threads = p->threads_bwd = 1024;
-    int best = 0;
-    for (int tc = T; tc >= 1; --tc)
-      if (sf::fwd3_lds_bytes(nc, T, tc, p->n_max, p->M_max, p->S_max) <= kLdsBudget) {
-        best = tc;
-        break;
-      }
-    if (best == 0)
-      return fail(SF_ERR_SHAPE, "problem state does not fit the LDS of one workgroup");
     // The adjoint recomputes forward iterates with the forward's time chunks
     // (same sums, same bits) and runs its VJP in chunks of Tv <= Tc steps; a
     // plan that can save a forward takes the longest Tc for which some Tv fits.
-    auto tv_for = [&](int tc) {
-      for (int tv = tc; tv >= 1; --tv)
-        if (sf::bwd3_lds_bytes(nc, tc, tv, p->n_max, p->M_max, p->S_max) <= kLdsBudget)
-          return tv;
-      return 0;
+    // With the candidate lists (when they fit; their LDS covers the whole
+    // horizon) chunks shorter than the horizon are multiples of the list
+    // window.
+    auto pick = [&](bool lists) -> bool {
+      const int win = sf::list_window3();
+      auto len_ok = [&](int len) { return !lists || len >= T || len % win == 0; };
+      auto round_win = [&](int len) { return lists && len < T ? (len + win - 1) / win * win : len; };
+      // longest VJP chunk that fits beside forward chunks of tc (the adjoint's
+      // LDS grows by 3 n_max floats per VJP step)
+      const size_t per_tv = sizeof(float) * 3 * (size_t)p->n_max;
+      auto tv_for = [&](int tc) {
+        const size_t base =
+            sf::bwd3_lds_bytes(nc, T, tc, 0, p->n_max, p->M_max, p->S_max, lists);
+        if (base > kLdsBudget) return 0;
+        int tv = (int)std::min<size_t>((size_t)tc, (kLdsBudget - base) / per_tv);
+        if (lists && tv < T) tv = tv / win * win;
+        return tv;
+      };
+      int best = 0;
+      for (int tc = T; tc >= 1 && best == 0; --tc)
+        if (len_ok(tc) &&
+            sf::fwd3_lds_bytes(nc, T, tc, p->n_max, p->M_max, p->S_max, lists) <= kLdsBudget)
+          best = tc;
+      if (best == 0) return false;
+      int tc = best, tv = 0;
+      if (cfg->max_iters > 0) {
+        // fewest chunk passes per adjoint iteration (recompute plus VJP)
+        int score = INT_MAX;
+        for (int c = best; c >= 1; --c) {
+          const int v = len_ok(c) ? tv_for(c) : 0;
+          if (v == 0) continue;
+          const int sc = (T + c - 1) / c + (T + v - 1) / v;
+          if (sc < score) {
+            score = sc;
+            tc = c;
+            tv = v;
+          }
+        }
+        if (tv == 0) return false;
+      }
+      const int chunks = (T + tc - 1) / tc;
+      p->Tc_fwd = p->Tc_bwd = round_win((T + chunks - 1) / chunks);
+      p->Tv3 = 0;
+      if (tv > 0) {
+        const int vchunks = (T + tv - 1) / tv;
+        p->Tv3 = std::min(p->Tc_bwd, round_win((T + vchunks - 1) / vchunks));
+      }
+      p->lists3 = lists;
+      p->lds_fwd = sf::fwd3_lds_bytes(nc, T, p->Tc_fwd, p->n_max, p->M_max, p->S_max, lists);
+      p->lds_bwd = p->Tv3 > 0 ? sf::bwd3_lds_bytes(nc, T, p->Tc_bwd, p->Tv3, p->n_max,
+                                                   p->M_max, p->S_max, lists)
+                              : 0;
+      return true;
     };
-    int tv = tv_for(best);
-    if (cfg->max_iters > 0)
-      while (tv == 0 && best > 1) tv = tv_for(--best);
-    if (cfg->max_iters > 0 && tv == 0)
-      return fail(SF_ERR_SHAPE, "adjoint state does not fit the LDS of one workgroup");
-    const int chunks = (T + best - 1) / best;
-    p->Tc_fwd = p->Tc_bwd = (T + chunks - 1) / chunks;
-    if (tv > 0) {
-      const int vchunks = (T + tv - 1) / tv;
-      p->Tv3 = std::min(p->Tc_bwd, (T + vchunks - 1) / vchunks);
-    }
-    p->lds_fwd = sf::fwd3_lds_bytes(nc, T, p->Tc_fwd, p->n_max, p->M_max, p->S_max);
-    p->lds_bwd = p->Tv3 > 0 ? sf::bwd3_lds_bytes(nc, p->Tc_bwd, p->Tv3, p->n_max, p->M_max,
-                                                 p->S_max)
-                            : 0;
+    if (!pick(true) && !pick(false))
+      return fail(SF_ERR_SHAPE, cfg->max_iters > 0
+                                    ? "problem or adjoint state does not fit the LDS of one "
+                                      "workgroup"
+                                    : "problem state does not fit the LDS of one workgroup");
   }
   // One time-chunk length for both kernels: the adjoint recomputes forward
   // iterates and must sum in the same order to reproduce them bitwise.
@@ -496,6 +529,7 @@ sf::FwdArgs fwd_args(const sf_plan* p, const float* xi, const float* xi0, const 
   a.ckpt_every = p->cfg.checkpoint_every;
   a.save = save ? 1 : 0;
   a.check_every = p->exit_every;
+  a.lists3 = p->lists3 && p->lists3_on ? 1 : 0;
   a.tol = p->exit_tol;
   a.rho = (float)p->cfg.rho;
   return a;
@@ -753,7 +787,7 @@ int sf_project(sf_plan_t* plan, void* workspace, const float* xi, const float* x
                                  (uint64_t)lam_out, (uint64_t)residual, (uint64_t)n_iters,
                                  (uint64_t)save,    (uint64_t)plan->threads, (uint64_t)s,
                                  (uint64_t)plan->exit_every, (uint64_t)float_bits(plan->exit_tol),
-                                 (uint64_t)plan->moving};
+                                 (uint64_t)plan->moving, (uint64_t)a.lists3};
     GraphEntry* hit = nullptr;
     for (auto& g : plan->graphs)
       if (g.key == key) hit = &g;
@@ -842,6 +876,7 @@ int backward_impl(sf_plan_t* plan, void* workspace, const float* g_xi_out,
   a.S_max = plan->S_max;
   a.L = plan->saved_L;
   a.ckpt_every = plan->cfg.checkpoint_every;
+  a.lists3 = plan->lists3 && plan->lists3_on ? 1 : 0;
   a.rho = (float)plan->cfg.rho;
   a.fp_weight = fp_weight;
   if (!static_area && plan->tune_bwd && a.L > 0 && !stream_capturing(s)) {
@@ -923,6 +958,15 @@ int sf_set_early_exit(sf_plan_t* plan, float tol, int32_t check_every) {
   plan->exit_every = check_every;
   plan->exit_tol = tol;
   return SF_OK;
+}
+
+int sf_set_candidate_lists(sf_plan_t* plan, int32_t enable) {
+  g_detail.clear();
+  if (!plan) return fail(SF_ERR_INVALID_ARG, "plan is NULL");
+  if (plan->cfg.n_dim != 3)
+    return fail(SF_ERR_INVALID_ARG, "candidate lists are switchable for n_dim = 3 only");
+  plan->lists3_on = enable != 0;
+  return plan->lists3 && plan->lists3_on ? 1 : 0;
 }
 
 int sf_project_iterations(const sf_plan_t* plan, const void* workspace, int32_t* iters,

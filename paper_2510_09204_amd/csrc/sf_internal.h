@@ -62,6 +62,7 @@ struct FwdArgs {
   int32_t ckpt_every;
   int32_t save;
   int32_t check_every;    // early exit: test the residual every this many iterations (0 = off)
+  int32_t lists3;         // 3D: candidate lists on
   float tol;              // early exit threshold on sqrt(||r_1||^2 + ||r_2||^2)
   float rho;
 };
@@ -93,6 +94,7 @@ struct BwdArgs {
   int32_t n_max, M_max, S_max;
   int32_t L;
   int32_t ckpt_every;
+  int32_t lists3;         // 3D: candidate lists on
   float rho;
   float fp_weight;
 };
@@ -139,12 +141,17 @@ hipError_t prepare_kernels(size_t lds);
 // 3D (spheroid) forward (sf_kernels3d.hip): one workgroup per problem; the
 // coefficient arrays hold [3][n][nc] per problem, boundary [n][2][3],
 // obstacles [M][5] = x, y, z, a_o, b_o.  Tc: time steps held in LDS at once.
-size_t fwd3_lds_bytes(int nc, int T, int Tc, int n_max, int M_max, int S_max);
+// With `lists`, room for the candidate lists of the whole horizon (time chunks
+// Tc, Tv then a multiple of list_window3() steps unless they cover the
+// horizon).
+int list_window3();
+size_t fwd3_lds_bytes(int nc, int T, int Tc, int n_max, int M_max, int S_max, bool lists);
 hipError_t prepare_kernels3(size_t lds);
 hipError_t launch_fwd3(const FwdArgs& a, int threads, size_t lds, hipStream_t s);
 // 3D adjoint: the forward's layout for time chunks of Tc plus its own buffers
 // for VJP chunks of Tv <= Tc steps.
-size_t bwd3_lds_bytes(int nc, int Tc, int Tv, int n_max, int M_max, int S_max);
+size_t bwd3_lds_bytes(int nc, int T, int Tc, int Tv, int n_max, int M_max, int S_max,
+                      bool lists);
 hipError_t launch_bwd3(const BwdArgs& a, int threads, size_t lds, int Tv, hipStream_t s);
 
 // Candidate selection (sf_select.hip).  Batches of at most kSelectMaxBatch

@@ -136,8 +136,40 @@ __device__ __forceinline__ void spheroid_resgrad(float ex, float ey, float ez, f
 // fewer threads have work; four from 24 robots, two from 8.
 __device__ __forceinline__ int robots_per_thread(int n) { return n >= 24 ? 4 : (n >= 8 ? 2 : 1); }
 
+// Candidate lists.  Each robot keeps, per window of kWin3 steps of the horizon,
+// a bit mask of the partners and obstacles whose rows can be active in that
+// window, built from window boxes of the positions (scaled coordinates) widened
+// by a skin d.  A row with a scaled offset of magnitude >= 1 on some axis is
+// inactive (its s^2 >= 1 in float too, the rounding being monotone), and a
+// robot's positions are convex combinations of its coefficients (Bernstein
+// weights, eq. poly), so the lists stay complete while no coefficient differs
+// from its value at the last rebuild by more than d a (x, y) or d b (z); the
+// first iteration in which one does, rebuilds them.  The sweep then walks the
+// lists in increasing index: the rows it skips add exact zeros in the full
+// sweep, so both give the same bits.
+constexpr int kSlots3 = 16;        // per-wave flags of the list check (waves of 1024 threads)
+constexpr float kSkin3 = 0.25f;    // skin d in scaled units
+constexpr int kWinShift3 = 4;      // list window of 2^kWinShift3 steps
+constexpr int kWin3 = 1 << kWinShift3;
+constexpr int kListRob3 = 4;       // robots per thread of the list walk
+static_assert(kWin3 >= 4, "window boxes of a chunk must fit in the V area");
+
+// 32-bit mask words per (window, robot): partner words, then obstacle words.
+__host__ __device__ inline int mask_words3(int n, int M) {
+  return ((n + 31) >> 5) + ((M + 31) >> 5);
+}
+// LDS floats of the lists: reference coefficients, flags, masks of every
+// window of a T-step horizon.
+__host__ __device__ inline size_t list3_floats(int T, int n_max, int M_max, int S_max) {
+  return (size_t)r4(S_max) + kSlots3 +
+         (size_t)((T + kWin3 - 1) >> kWinShift3) * n_max * mask_words3(n_max, M_max);
+}
+
 struct Lds3 {
   float *W, *fac, *xb[2], *lam, *cxi, *R, *means, *obs, *X, *V, *red;
+  float* refc;       // coefficients at the last list rebuild
+  int* lslot;        // per-wave "moved" flags
+  unsigned* mask;    // [window][n][mask_words3]
 };
 
 __device__ __forceinline__ Lds3 carve3(float* p, int nc, int Tc, int n_max, int M_max,
@@ -153,15 +185,122 @@ __device__ __forceinline__ Lds3 carve3(float* p, int nc, int Tc, int n_max, int 
   L.means = p; p += 6 * kMaxCoef + 8;
   L.obs = p; p += kObsFloats * M_max;
   L.red = p; p += kRed3;
-  L.X = p; p += 3 * n_max * Tc;
-  L.V = p;
+  L.X = p; p += 3 * n_max * (Tc | 1);
+  L.V = p; p += 3 * n_max * (Tc | 1);
+  // list area (used only when the lists are on)
+  L.refc = p; p += r4(S_max);
+  L.lslot = reinterpret_cast<int*>(p); p += kSlots3;
+  L.mask = reinterpret_cast<unsigned*>(p);
   return L;
 }
 
-// LDS floats of the forward's layout (carve3).
-__host__ __device__ inline size_t lds3_floats(int nc, int Tc, int n_max, int M_max, int S_max) {
+// LDS floats of the forward's layout (carve3), with or without the lists.
+__host__ __device__ inline size_t lds3_floats(int nc, int T, int Tc, int n_max, int M_max,
+                                              int S_max, bool lists) {
   return (size_t)r4(Tc * nc) + r4(fac_stride(nc)) + 5 * (size_t)r4(S_max) + 6 * kMaxCoef + 8 +
-         (size_t)kObsFloats * M_max + kRed3 + 6 * (size_t)n_max * Tc;
+         (size_t)kObsFloats * M_max + kRed3 + 6 * (size_t)n_max * (Tc | 1) +
+         (lists ? r4(list3_floats(T, n_max, M_max, S_max)) : 0);
+}
+
+// List check: every wave records whether a coefficient it compared moved
+// further than the skin; all waves read the flags at the next sweep.
+__device__ __forceinline__ void note_moved3(bool moved, int* lslot) {
+  const bool any = __builtin_amdgcn_ballot_w64(moved) != 0ull;
+  if ((threadIdx.x & 63) == 0) lslot[threadIdx.x >> 6] = any ? 1 : 0;
+}
+__device__ __forceinline__ bool lists_moved3(const int* lslot, int nwaves) {
+  const int lane = threadIdx.x & 63;
+  const int v = lane < nwaves ? lslot[lane] : 0;
+  return __builtin_amdgcn_ballot_w64(v != 0) != 0ull;
+}
+// Before the first sweep: every flag set and a NaN reference, so that a check
+// made before the first rebuild still reports a move.
+template <int NT>
+__device__ __forceinline__ void reset_lists3(float* refc, int* lslot, int S) {
+  for (int t = threadIdx.x; t < S; t += NT) refc[t] = __builtin_nanf("");
+  if (threadIdx.x < kSlots3) lslot[threadIdx.x] = 1;
+}
+// Whether coefficient t of x (layout [3][n][nc], nn = n nc) left the skin.
+__device__ __forceinline__ bool coef_moved3(const float* x, const float* ref, int t, int nn,
+                                            float ska, float skb) {
+  return !(fabsf(x[t] - ref[t]) <= (t < 2 * nn ? ska : skb));
+}
+
+// Lists of the windows of a chunk of Tce steps starting at step k0 (a
+// multiple of kWin3), from the scaled positions
+// in L.X.  Window boxes go to L.V first (written again only after the lists).
+// Margins: a pair is kept when its boxes come within 1 + 2 d (both robots may
+// move by d), an obstacle when the box of the offset in the obstacle's scaling
+// comes within 1 + d (r_a, r_b) of the origin; 1e-4 (1 + magnitudes) more on
+// each covers the float rounding of the positions and of the tests, which is
+// orders of magnitude smaller.  A ballot tests two robots against 32
+// candidates at once (lane = 32 slot + jj).
+template <int NT>
+__device__ __forceinline__ void build_lists3(const ProbDesc& P, const Lds3& L, int k0, int Tce,
+                                             int Ts, float inv_Tm1, bool moving) {
+  const int n = P.n, M = P.M, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nwc = (Tce + kWin3 - 1) >> kWinShift3;
+  float* box = L.V;   // [3 n][nwc] (lo, hi)
+  for (int t = tid; t < 3 * n * nwc; t += NT) {
+    const int row = t / nwc, wl = t - row * nwc;
+    const float* x = L.X + row * Ts + wl * kWin3;
+    const int cnt = min(kWin3, Tce - wl * kWin3);
+    float lo = x[0], hi = x[0];
+    for (int s = 1; s < cnt; ++s) {
+      lo = fminf(lo, x[s]);
+      hi = fmaxf(hi, x[s]);
+    }
+    box[2 * t] = lo;
+    box[2 * t + 1] = hi;
+  }
+  __syncthreads();
+  const int pw = (n + 31) >> 5, mw = mask_words3(n, M), np = (n + 1) >> 1;
+  const int slot = lane >> 5, jj = lane & 31;
+  const int per_win = np * mw;
+  for (int q = wave; q < nwc * per_win; q += NT >> 6) {
+    const int wl = q / per_win, rem = q - wl * per_win, ip = rem / mw, word = rem - ip * mw;
+    const int i = 2 * ip + slot, ic = min(i, n - 1);
+    bool c = i < n;
+    if (word < pw) {
+      const int j = 32 * word + jj, jc = min(j, n - 1);
+      c = c && j < n && j != i;
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        const float* bi = box + ((ax * n + ic) * nwc + wl) * 2;
+        const float* bj = box + ((ax * n + jc) * nwc + wl) * 2;
+        const float mag =
+            fmaxf(fmaxf(fabsf(bi[0]), fabsf(bi[1])), fmaxf(fabsf(bj[0]), fabsf(bj[1])));
+        const float thr = 1.f + 2.f * kSkin3 + 1e-4f * (1.f + mag);
+        c = c && (bi[0] - bj[1] < thr) && (bj[0] - bi[1] < thr);
+      }
+    } else {
+      const int mo = 32 * (word - pw) + jj;
+      const float* o = L.obs + min(mo, M - 1) * kObsFloats;
+      c = c && mo < M;
+      // the obstacle's centre term is monotone in the step, so its range over
+      // the window is that of the window's first and last steps
+      const float ta = (float)(k0 + wl * kWin3) * inv_Tm1;
+      const float tb = (float)(k0 + min(wl * kWin3 + kWin3 - 1, Tce - 1)) * inv_Tm1;
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        const float* bi = box + ((ax * n + ic) * nwc + wl) * 2;
+        const float ca = moving ? fmaf(o[7 + ax], ta, o[2 + ax]) : o[2 + ax];
+        const float cb = moving ? fmaf(o[7 + ax], tb, o[2 + ax]) : o[2 + ax];
+        const float r = ax < 2 ? o[0] : o[1];
+        const float elo = fmaf(bi[0], r, fminf(ca, cb)), ehi = fmaf(bi[1], r, fmaxf(ca, cb));
+        const float sl = fmaf(r, kSkin3, 1e-4f * (1.f + fabsf(elo) + fabsf(ehi) +
+                                                   r * (fabsf(bi[0]) + fabsf(bi[1]))));
+        c = c && (elo - sl < 1.f) && (ehi + sl > -1.f);
+      }
+    }
+    const unsigned long long bal = __builtin_amdgcn_ballot_w64(c);
+    if (lane == 0) {
+      unsigned* mk = L.mask + ((size_t)((k0 >> kWinShift3) + wl) * n + 2 * ip) * mw + word;
+      mk[0] = (unsigned)bal;
+      if (2 * ip + 1 < n) mk[mw] = (unsigned)(bal >> 32);
+    }
+  }
+  __syncthreads();
 }
 
 // Passes over the horizon at xi_bar = xb (MODE): kForward gives positions X,
@@ -169,6 +308,52 @@ __host__ __device__ inline size_t lds3_floats(int nc, int Tc, int n_max, int M_m
 // ||r_2||^2 instead; kResGrad R = W^T V with V = w1 sum J^T r_1 + w2 (box
 // overshoot), the gradient of w1 ||r_1||^2 / 2 + w2 ||r_2||^2 / 2.
 constexpr int kForward = 0, kFinal = 1, kResGrad = 2;
+
+// The rows of kRob robots (indices ir, scaled positions p) against partner
+// j at scaled position q: r_1 (kForward, and |r_1|^2 for each unordered pair
+// once in kFinal) or J^T r_1 (kResGrad) added to v.
+template <int MODE, int kRob>
+__device__ __forceinline__ void pair_rows3(const ProbDesc& P, const int (&ir)[kRob], int j,
+                                           const float (&px)[kRob], const float (&py)[kRob],
+                                           const float (&pz)[kRob], float qx, float qy,
+                                           float qz, float (&vx)[kRob], float (&vy)[kRob],
+                                           float (&vz)[kRob], float (&sq)[kRob]) {
+  constexpr bool FINAL = MODE == kFinal;
+#pragma unroll
+  for (int r = 0; r < kRob; ++r) {
+    float s1 = 0.f;
+    if (MODE == kResGrad)
+      spheroid_resgrad(px[r] - qx, py[r] - qy, pz[r] - qz, P.a, P.b, ir[r] < j ? -P.b : P.b,
+                       j != ir[r], vx[r], vy[r], vz[r]);
+    else
+      spheroid_residual<FINAL>(px[r] - qx, py[r] - qy, pz[r] - qz, P.a, P.b,
+                               ir[r] < j ? -P.b : P.b, j != ir[r], vx[r], vy[r], vz[r], s1);
+    if (FINAL) sq[r] += j > ir[r] ? s1 : 0.f;   // each unordered pair once
+  }
+}
+
+// The rows of kRob robots against obstacle entry o (see setup3) at time tau.
+template <int MODE, int kRob>
+__device__ __forceinline__ void obstacle_rows3(const float* o, float tau, bool moving,
+                                               const float (&px)[kRob], const float (&py)[kRob],
+                                               const float (&pz)[kRob], float (&vx)[kRob],
+                                               float (&vy)[kRob], float (&vz)[kRob],
+                                               float (&sq)[kRob]) {
+  const float cx = moving ? fmaf(o[7], tau, o[2]) : o[2];
+  const float cy = moving ? fmaf(o[8], tau, o[3]) : o[3];
+  const float cz = moving ? fmaf(o[9], tau, o[4]) : o[4];
+  const float ra = o[0], rb = o[1], oa = o[5], ob = o[6];
+#pragma unroll
+  for (int r = 0; r < kRob; ++r) {
+    if (MODE == kResGrad)
+      spheroid_resgrad(fmaf(px[r], ra, cx), fmaf(py[r], ra, cy), fmaf(pz[r], rb, cz), oa, ob,
+                       -ob, true, vx[r], vy[r], vz[r]);
+    else
+      spheroid_residual<MODE == kFinal>(fmaf(px[r], ra, cx), fmaf(py[r], ra, cy),
+                                        fmaf(pz[r], rb, cz), oa, ob, -ob, true, vx[r], vy[r],
+                                        vz[r], sq[r]);
+  }
+}
 
 template <int NT, int MODE, int kRob, typename Args>
 __device__ __forceinline__ void sweep3(const Args& A, const ProbDesc& P, const Lds3& L,
@@ -180,8 +365,16 @@ __device__ __forceinline__ void sweep3(const Args& A, const ProbDesc& P, const L
   const float inv_a = 1.f / P.a, inv_b = 1.f / P.b;
   const float inv_Tm1 = 1.f / (float)(T - 1);
   const bool moving = A.ovel != nullptr;
+  // candidate lists: rebuilt in this pass when a wave flagged a move (every
+  // thread reads the flags here; they are cleared after the first map), with
+  // xb as the new reference
+  const bool lists = A.lists3 != 0;
+  const bool rebuild = lists && lists_moved3(L.lslot, NT >> 6);
+  if (rebuild)
+    for (int t = tid; t < 3 * n * nc; t += NT) L.refc[t] = xb[t];
   for (int k0 = 0; k0 < T; k0 += Tc) {
     const int Tce = min(Tc, T - k0);
+    const int Ts = Tce | 1;   // odd row stride of X and V: column reads without bank conflicts
     if (chunked) {
       for (int t = tid; t < Tce * nc; t += NT) L.W[t] = A.W[k0 * nc + t];
       __syncthreads();
@@ -211,19 +404,25 @@ __device__ __forceinline__ void sweep3(const Args& A, const ProbDesc& P, const L
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int step = wt * 16 + 4 * kq + v;
-            if (step < Tce) L.X[col * Tce + step] = acc[v] * sc;
+            if (step < Tce) L.X[col * Ts + step] = acc[v] * sc;
           }
         }
       }
     }
     __syncthreads();
-    // constraint rows (every robot pair, every obstacle, the box).  A thread
-    // takes kRob robots at one step, so each partner position and obstacle
-    // read from LDS serves kRob rows; every row still sums its terms in the
-    // same order (partners j = 0..n-1, then obstacles).  kRob depends on the
+    if (lists && rebuild) {
+      if (k0 == 0 && tid < kSlots3) L.lslot[tid] = 0;   // every thread has read the flags
+      build_lists3<NT>(P, L, k0, Tce, Ts, inv_Tm1, moving);
+    }
+    // constraint rows (robot pairs, obstacles, the box).  A thread takes kRob
+    // robots at one step, so each partner position and obstacle read from LDS
+    // serves kRob rows; every row still sums its terms in the same order
+    // (partners j = 0..n-1, then obstacles), over all of them or, with the
+    // lists, over the union of its robots' lists.  kRob depends on the
     // problem's robot count only (robots_per_thread), not on the block size.
-    const int plane = n * Tce;
+    const int plane = n * Ts;
     const int ngrp = (n + kRob - 1) / kRob;
+    const int pw = (n + 31) >> 5, mw = mask_words3(n, M);
     for (int t = tid; t < ngrp * Tce; t += NT) {
       const int g = t / Tce, kk = t - g * Tce;
       float px[kRob], py[kRob], pz[kRob], vx[kRob], vy[kRob], vz[kRob], sq[kRob];
@@ -231,87 +430,79 @@ __device__ __forceinline__ void sweep3(const Args& A, const ProbDesc& P, const L
 #pragma unroll
       for (int r = 0; r < kRob; ++r) {
         ir[r] = g * kRob + r;
-        const int u = min(ir[r], n - 1) * Tce + kk;
+        const int u = min(ir[r], n - 1) * Ts + kk;
         px[r] = L.X[u];
         py[r] = L.X[plane + u];
         pz[r] = L.X[2 * plane + u];
         vx[r] = vy[r] = vz[r] = sq[r] = 0.f;
       }
-      // partners in groups of four, every read of a group issued first
-      int j0 = 0;
-      for (; j0 + 4 <= n; j0 += 4) {
-        float qx[4], qy[4], qz[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int u = (j0 + e) * Tce + kk;
-          qx[e] = L.X[u];
-          qy[e] = L.X[plane + u];
-          qz[e] = L.X[2 * plane + u];
-        }
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int j = j0 + e;
-#pragma unroll
-          for (int r = 0; r < kRob; ++r) {
-            float s1 = 0.f;
-            if (MODE == kResGrad)
-              spheroid_resgrad(px[r] - qx[e], py[r] - qy[e], pz[r] - qz[e], P.a, P.b,
-                               ir[r] < j ? -P.b : P.b, j != ir[r], vx[r], vy[r], vz[r]);
-            else
-              spheroid_residual<FINAL>(px[r] - qx[e], py[r] - qy[e], pz[r] - qz[e], P.a, P.b,
-                                       ir[r] < j ? -P.b : P.b, j != ir[r], vx[r], vy[r],
-                                       vz[r], s1);
-            if (FINAL) sq[r] += j > ir[r] ? s1 : 0.f;   // each unordered pair once
-          }
-        }
-      }
-      for (int j = j0; j < n; ++j) {
-        const int u = j * Tce + kk;
-        const float qx = L.X[u], qy = L.X[plane + u], qz = L.X[2 * plane + u];
-#pragma unroll
-        for (int r = 0; r < kRob; ++r) {
-          float s1 = 0.f;
-          if (MODE == kResGrad)
-            spheroid_resgrad(px[r] - qx, py[r] - qy, pz[r] - qz, P.a, P.b,
-                             ir[r] < j ? -P.b : P.b, j != ir[r], vx[r], vy[r], vz[r]);
-          else
-            spheroid_residual<FINAL>(px[r] - qx, py[r] - qy, pz[r] - qz, P.a, P.b,
-                                     ir[r] < j ? -P.b : P.b, j != ir[r], vx[r], vy[r], vz[r],
-                                     s1);
-          if (FINAL) sq[r] += j > ir[r] ? s1 : 0.f;
-        }
-      }
       // obstacle offsets in the obstacle's scaling: (a x' - c - d tau) / a_o
       // (x' the stored x / a), i.e. x' (a / a_o) - c / a_o - (d / a_o) tau
       const float tau = (float)(k0 + kk) * inv_Tm1;
-      for (int m = 0; m < M; ++m) {
-        const float* o = L.obs + m * kObsFloats;
-        const float cx = moving ? fmaf(o[7], tau, o[2]) : o[2];
-        const float cy = moving ? fmaf(o[8], tau, o[3]) : o[3];
-        const float cz = moving ? fmaf(o[9], tau, o[4]) : o[4];
-        const float ra = o[0], rb = o[1], oa = o[5], ob = o[6];
+      if (lists) {
+        const unsigned* mk = L.mask + ((size_t)((k0 + kk) >> kWinShift3) * n + g * kRob) * mw;
+        for (int q = 0; q < pw; ++q) {
+          unsigned u = 0u;
 #pragma unroll
-        for (int r = 0; r < kRob; ++r) {
-          if (MODE == kResGrad)
-            spheroid_resgrad(fmaf(px[r], ra, cx), fmaf(py[r], ra, cy), fmaf(pz[r], rb, cz), oa,
-                             ob, -ob, true, vx[r], vy[r], vz[r]);
-          else
-            spheroid_residual<FINAL>(fmaf(px[r], ra, cx), fmaf(py[r], ra, cy),
-                                     fmaf(pz[r], rb, cz), oa, ob, -ob, true, vx[r], vy[r],
-                                     vz[r], sq[r]);
+          for (int r = 0; r < kRob; ++r)
+            if (ir[r] < n) u |= mk[r * mw + q];
+          while (u) {
+            const int j = (__ffs(u) - 1) + 32 * q;
+            u &= u - 1u;
+            const int v = j * Ts + kk;
+            pair_rows3<MODE, kRob>(P, ir, j, px, py, pz, L.X[v], L.X[plane + v],
+                                   L.X[2 * plane + v], vx, vy, vz, sq);
+          }
         }
+        for (int q = 0; q < mw - pw; ++q) {
+          unsigned u = 0u;
+#pragma unroll
+          for (int r = 0; r < kRob; ++r)
+            if (ir[r] < n) u |= mk[r * mw + pw + q];
+          while (u) {
+            const int mo = (__ffs(u) - 1) + 32 * q;
+            u &= u - 1u;
+            obstacle_rows3<MODE, kRob>(L.obs + mo * kObsFloats, tau, moving, px, py, pz, vx,
+                                       vy, vz, sq);
+          }
+        }
+      } else {
+        // partners in groups of four, every read of a group issued first
+        int j0 = 0;
+        for (; j0 + 4 <= n; j0 += 4) {
+          float qx[4], qy[4], qz[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int u = (j0 + e) * Ts + kk;
+            qx[e] = L.X[u];
+            qy[e] = L.X[plane + u];
+            qz[e] = L.X[2 * plane + u];
+          }
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            pair_rows3<MODE, kRob>(P, ir, j0 + e, px, py, pz, qx[e], qy[e], qz[e], vx, vy, vz,
+                                   sq);
+        }
+        for (int j = j0; j < n; ++j) {
+          const int u = j * Ts + kk;
+          pair_rows3<MODE, kRob>(P, ir, j, px, py, pz, L.X[u], L.X[plane + u],
+                                 L.X[2 * plane + u], vx, vy, vz, sq);
+        }
+        for (int mo = 0; mo < M; ++mo)
+          obstacle_rows3<MODE, kRob>(L.obs + mo * kObsFloats, tau, moving, px, py, pz, vx, vy,
+                                     vz, sq);
       }
 #pragma unroll
       for (int r = 0; r < kRob; ++r) {
         if (ir[r] >= n) continue;
-        const int u = ir[r] * Tce + kk;
+        const int u = ir[r] * Ts + kk;
         const float x = P.a * px[r], y = P.a * py[r], z = P.b * pz[r];
         const float hx = fmaxf(x - P.pmax[0], 0.f), lx = fmaxf(P.pmin[0] - x, 0.f);
         const float hy = fmaxf(y - P.pmax[1], 0.f), ly = fmaxf(P.pmin[1] - y, 0.f);
         const float hz = fmaxf(z - P.pmax[2], 0.f), lz = fmaxf(P.pmin[2] - z, 0.f);
-        if (FINAL) {
-          r1sq += sq[r];
-          r2sq += hx * hx + lx * lx + hy * hy + ly * ly + hz * hz + lz * lz;
+        if (FINAL) {   // the row's shares, summed below in a fixed order
+          L.V[u] = sq[r];
+          L.V[plane + u] = hx * hx + lx * lx + hy * hy + ly * ly + hz * hz + lz * lz;
         } else if (MODE == kResGrad) {
           L.V[u] = fmaf(w2, hx - lx, w1 * vx[r]);
           L.V[plane + u] = fmaf(w2, hy - ly, w1 * vy[r]);
@@ -324,7 +515,19 @@ __device__ __forceinline__ void sweep3(const Args& A, const ProbDesc& P, const L
       }
     }
     __syncthreads();
-    if (!FINAL) {
+    if (FINAL) {
+      // ||r_1||^2 and ||r_2||^2 of the chunk: 256 partial sums over rows e =
+      // p (mod 256) in increasing order, the same whatever the block size and
+      // the robots per thread (the caller then adds the partials per wave and
+      // the waves in order)
+      if (tid < 256)
+        for (int e = tid; e < n * Tce; e += 256) {
+          const int i = e / Tce, kk = e - i * Tce;
+          r1sq += L.V[i * Ts + kk];
+          r2sq += L.V[plane + i * Ts + kk];
+        }
+      __syncthreads();
+    } else {
       // R (+)= W^T V over this chunk's steps on MFMA 16x16x4 tiles of 16 rows
       // x 16 coefficients: A[m][k] = V[16 rt + m][4 s + k'], B[k][m] =
       // W[4 s + k'][16 ct + m]; steps past Tce enter as 0.  Two accumulators
@@ -334,7 +537,7 @@ __device__ __forceinline__ void sweep3(const Args& A, const ProbDesc& P, const L
       for (int q = wave; q < nrt * nct; q += NT >> 6) {
         const int rt = q / nct, ct = q - rt * nct;
         const int rowA = min(rt * 16 + m, 3 * n - 1), cB = min(ct * 16 + m, nc - 1);
-        const float* vrow = L.V + rowA * Tce;
+        const float* vrow = L.V + rowA * Ts;
         floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
         int s4 = 0;
         for (; s4 + 2 <= nk; s4 += 2) {
@@ -374,7 +577,9 @@ __device__ __forceinline__ void sweep3_any(const Args& A, const ProbDesc& P, con
                                            const float* xb, float& r1sq, float& r2sq,
                                            float w1 = 1.f, float w2 = 1.f) {
   const int rpt = robots_per_thread(P.n);
-  if (rpt == 4)
+  if (A.lists3)
+    sweep3<NT, MODE, kListRob3>(A, P, L, xb, r1sq, r2sq, w1, w2);
+  else if (rpt == 4)
     sweep3<NT, MODE, 4>(A, P, L, xb, r1sq, r2sq, w1, w2);
   else if (rpt == 2)
     sweep3<NT, MODE, 2>(A, P, L, xb, r1sq, r2sq, w1, w2);
@@ -414,67 +619,113 @@ __device__ __forceinline__ void setup3(const Args& A, const ProbDesc& P, const L
   }
 }
 
-// One application of T on the LDS state (xcur, L.lam) -> (xnext, L.lam):
-// the constraint sweep, the lambda step with u = lambda - 2 rho R (u replaces
-// R), robot means of u and xcur, the xi_bar step.  With `last`, dzsq gets
-// this thread's share of ||z' - z||^2.  Entered and left block-synchronised.
+// Mean-field term of the xi_bar step: wave ax < 3 forms the robot means of
+// u = lambda - 2 rho R and of x for axis ax (lane q + QW p sums the robots
+// i = p (mod 64 / QW) of coefficient q, then a butterfly over p), and
+// bias[ax][c] = sum_q DS[c][q] um[q] + DSH[c][q] xm[q] into L.means[ax nc + c].
+// Needs at least three waves (NT >= 256).
+template <int NT>
+__device__ __forceinline__ void mean_field3(const ProbDesc& P, const Lds3& L, int nc, float rho,
+                                            const float* x) {
+  const int n = P.n, nn = n * nc, nc2 = nc * nc;
+  const int lane = threadIdx.x & 63, ax = threadIdx.x >> 6;
+  if (ax >= 3) return;
+  const int QW = nc <= 16 ? 16 : 32, Pw = 64 / QW;
+  const int q = lane % QW, p = lane / QW, qq = min(q, nc - 1);
+  const float* lam = L.lam + ax * nn + qq;
+  const float* R = L.R + ax * nn + qq;
+  const float* xa = x + ax * nn + qq;
+  float su = 0.f, sx = 0.f;
+  for (int i = p; i < n; i += Pw) {
+    su += fmaf(-2.f * rho, R[i * nc], lam[i * nc]);
+    sx += xa[i * nc];
+  }
+  for (int o = QW; o < 64; o <<= 1) {
+    su += __shfl_xor(su, o, 64);
+    sx += __shfl_xor(sx, o, 64);
+  }
+  const float um = su / (float)n, xm = sx / (float)n;
+  const float* DS = L.fac + nc2 + qq * nc;
+  const float* DSH = L.fac + 3 * nc2 + qq * nc;
+  float b = 0.f;
+  for (int k = 0; k < nc; ++k)
+    b = fmaf(DS[k], __shfl(um, k, 64), fmaf(DSH[k], __shfl(xm, k, 64), b));
+  if (p == 0 && q < nc) L.means[ax * nc + q] = b;
+}
+
+// The xi_bar step on MFMA 16x16x4 tiles, one wave per tile of 16 rows (row =
+// axis * n + robot) and every coefficient column tile: xi_bar'[row][c] =
+// c_xi + sum_q u[row][q] S[c][q] + sum_q x[row][q] SH[c][q] + bias[axis][c],
+// u = lambda - 2 rho R formed as the A operand is read (A[m][k] = u[16 rt +
+// m][4 s + k'], B[k][m] = S[16 ct + m][4 s + k']); the tile's lanes then
+// write lambda' = lambda - rho R of their own entries (no other wave reads
+// these rows), check the candidate lists and, with `last`, add ||z' - z||^2.
+template <int NT>
+__device__ __forceinline__ void xi_step3(const ProbDesc& P, const Lds3& L, int nc, float rho,
+                                         const float* xcur, float* xnext, bool last,
+                                         bool lists, float& dzsq) {
+  const int n = P.n, nc2 = nc * nc, rows = 3 * n;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, m = lane & 15, kq = lane >> 4;
+  const int nrt = (rows + 15) >> 4, nct = (nc + 15) >> 4, ks = (nc + 3) >> 2;
+  const float ska = kSkin3 * P.a, skb = kSkin3 * P.b;
+  bool moved = false;
+  for (int rt = wave; rt < nrt; rt += NT >> 6) {
+    const int rowA = min(rt * 16 + m, rows - 1);
+    floatx4 acc[2][2];
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) acc[ct][0] = acc[ct][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int s4 = 0; s4 < ks; ++s4) {
+      const int q = 4 * s4 + kq, qq = min(q, nc - 1);
+      const float u = fmaf(-2.f * rho, L.R[rowA * nc + qq], L.lam[rowA * nc + qq]);
+      const float au = q < nc ? u : 0.f;
+      const float xa = q < nc ? xcur[rowA * nc + qq] : 0.f;
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) {
+        if (ct < nct) {
+          const int cB = min(ct * 16 + m, nc - 1);
+          acc[ct][0] = mfma_16x16x4(au, L.fac[cB * nc + qq], acc[ct][0]);
+          acc[ct][1] = mfma_16x16x4(xa, L.fac[2 * nc2 + cB * nc + qq], acc[ct][1]);
+        }
+      }
+    }
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      const int c = ct * 16 + m;
+      if (ct >= nct || c >= nc) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = rt * 16 + 4 * kq + v;
+        if (row >= rows) continue;
+        const int e = row * nc + c, axis = row / n;
+        const float val =
+            L.cxi[e] + ((acc[ct][0][v] + acc[ct][1][v]) + L.means[axis * nc + c]);
+        xnext[e] = val;
+        const float r = L.R[e];
+        L.lam[e] = fmaf(-rho, r, L.lam[e]);
+        if (lists) moved |= !(fabsf(val - L.refc[e]) <= (axis < 2 ? ska : skb));
+        if (last) {
+          const float d = val - xcur[e];
+          dzsq = fmaf(rho * r, rho * r, fmaf(d, d, dzsq));
+        }
+      }
+    }
+  }
+  if (lists) note_moved3(moved, L.lslot);
+}
+
+// One application of T on the LDS state (xcur, L.lam) -> (xnext, L.lam): the
+// constraint sweep (R = W^T V), the mean-field term, the xi_bar and lambda
+// steps.  With `last`, dzsq gets this thread's share of ||z' - z||^2.
+// Entered and left block-synchronised.
 template <int NT, typename Args>
 __device__ __forceinline__ void iterate3(const Args& A, const ProbDesc& P, const Lds3& L,
                                          const float* xcur, float* xnext, bool last,
                                          float& dzsq) {
-  const int n = P.n, nc = A.nc, tid = threadIdx.x;
-  const int nn = n * nc, S = 3 * nn, nc2 = nc * nc;
-  const float rho = A.rho;
   float z0 = 0.f, z1 = 0.f;
   sweep3_any<NT, kForward>(A, P, L, xcur, z0, z1);
-  for (int t = tid; t < S; t += NT) {
-    const float r = L.R[t], lm = L.lam[t];
-    L.lam[t] = fmaf(-rho, r, lm);
-    L.R[t] = fmaf(-2.f * rho, r, lm);
-    if (last) dzsq = fmaf(rho * r, rho * r, dzsq);
-  }
+  mean_field3<NT>(P, L, A.nc, A.rho, xcur);
   __syncthreads();
-  // robot means of u and xb: means[0..3nc) and means[3nc..6nc)
-  for (int t = tid; t < 6 * nc; t += NT) {
-    const int which = t / (3 * nc), q = t - which * 3 * nc, ax = q / nc, c = q - ax * nc;
-    const float* src = (which ? xcur : L.R) + ax * nn + c;
-    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;   // four chains in flight
-    int i = 0;
-    for (; i + 4 <= n; i += 4) {
-      s0 += src[i * nc];
-      s1 += src[(i + 1) * nc];
-      s2 += src[(i + 2) * nc];
-      s3 += src[(i + 3) * nc];
-    }
-    for (; i < n; ++i) s0 += src[i * nc];
-    L.means[t] = ((s0 + s1) + (s2 + s3)) / (float)n;
-  }
-  __syncthreads();
-  // xi_bar step
-  for (int t = tid; t < S; t += NT) {
-    const int ax = t / nn, rem = t - ax * nn, i = rem / nc, c = rem - i * nc;
-    const float* Sp = L.fac + c * nc;
-    const float* DS = Sp + nc2;
-    const float* SH = Sp + 2 * nc2;
-    const float* DSH = Sp + 3 * nc2;
-    const float* u = L.R + ax * nn + i * nc;
-    const float* x = xcur + ax * nn + i * nc;
-    const float* um = L.means + ax * nc;
-    const float* xm = L.means + 3 * nc + ax * nc;
-    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;   // one chain per block
-    for (int q = 0; q < nc; ++q) {
-      a0 = fmaf(Sp[q], u[q], a0);
-      a1 = fmaf(DS[q], um[q], a1);
-      a2 = fmaf(SH[q], x[q], a2);
-      a3 = fmaf(DSH[q], xm[q], a3);
-    }
-    const float v = L.cxi[t] + ((a0 + a1) + (a2 + a3));
-    xnext[t] = v;
-    if (last) {
-      const float d = v - xcur[t];
-      dzsq = fmaf(d, d, dzsq);
-    }
-  }
+  xi_step3<NT>(P, L, A.nc, A.rho, xcur, xnext, last, A.lists3 != 0, dzsq);
   __syncthreads();
 }
 
@@ -490,6 +741,7 @@ __global__ __launch_bounds__(NT) void fwd3_kernel(FwdArgs A) {
   const size_t St = (size_t)A.S_total;
 
   setup3<NT>(A, P, L, A.obstacles);
+  if (A.lists3) reset_lists3<NT>(L.refc, L.lslot, S);   // the first sweep builds every list
   if (A.save)   // the adjoint reads the obstacles from the workspace
     for (int t = tid; t < 5 * M; t += NT)
       A.ws_obs[(size_t)P.obs_off * 5 + t] = A.obstacles[(size_t)P.obs_off * 5 + t];
@@ -613,6 +865,42 @@ __device__ __forceinline__ Lds3b carve3b(float* p, int S_max) {
   return B;
 }
 
+// VJP rows of kRob robots against partner j (its position and G at u, u +
+// plane, u + 2 plane): J^T (G_i - G_j) added to h.
+template <int kRob>
+__device__ __forceinline__ void pair_vjp3(const ProbDesc& P, const int (&ir)[kRob], int j, int u,
+                                          int plane, const float* X, const float* G,
+                                          const float (&px)[kRob], const float (&py)[kRob],
+                                          const float (&pz)[kRob], const float (&gx)[kRob],
+                                          const float (&gy)[kRob], const float (&gz)[kRob],
+                                          float (&hx)[kRob], float (&hy)[kRob],
+                                          float (&hz)[kRob]) {
+  const float qx = X[u], qy = X[plane + u], qz = X[2 * plane + u];
+  const float wx = G[u], wy = G[plane + u], wz = G[2 * plane + u];
+#pragma unroll
+  for (int r = 0; r < kRob; ++r)
+    spheroid_vjp(px[r] - qx, py[r] - qy, pz[r] - qz, P.a, P.b, gx[r] - wx, gy[r] - wy,
+                 gz[r] - wz, j != ir[r], hx[r], hy[r], hz[r]);
+}
+
+// VJP rows of kRob robots against obstacle entry o at time tau: J^T G_i.
+template <int kRob>
+__device__ __forceinline__ void obstacle_vjp3(const float* o, float tau, bool moving,
+                                              const float (&px)[kRob], const float (&py)[kRob],
+                                              const float (&pz)[kRob], const float (&gx)[kRob],
+                                              const float (&gy)[kRob], const float (&gz)[kRob],
+                                              float (&hx)[kRob], float (&hy)[kRob],
+                                              float (&hz)[kRob]) {
+  const float cx = moving ? fmaf(o[7], tau, o[2]) : o[2];
+  const float cy = moving ? fmaf(o[8], tau, o[3]) : o[3];
+  const float cz = moving ? fmaf(o[9], tau, o[4]) : o[4];
+  const float ra = o[0], rb = o[1], oa = o[5], ob = o[6];
+#pragma unroll
+  for (int r = 0; r < kRob; ++r)
+    spheroid_vjp(fmaf(px[r], ra, cx), fmaf(py[r], ra, cy), fmaf(pz[r], rb, cz), oa, ob, gx[r],
+                 gy[r], gz[r], true, hx[r], hy[r], hz[r]);
+}
+
 // VJP sweep over the horizon in chunks of Tv steps: X = W xb (scaled), G = W
 // gR, H = VJP (stored in L.V as [3][n][Tv]), R = W^T H (into L.R).
 template <int NT, int kRob>
@@ -624,8 +912,14 @@ __device__ __forceinline__ void vjp3(const BwdArgs& A, const ProbDesc& P, const 
   const float inv_Tm1 = 1.f / (float)(T - 1);
   const bool moving = A.ovel != nullptr;
   const int lane = tid & 63, wave = tid >> 6, m = lane & 15, kq = lane >> 4;
+  const bool lists = A.lists3 != 0;
+  const bool rebuild = lists && lists_moved3(L.lslot, NT >> 6);
+  if (rebuild)
+    for (int t = tid; t < 3 * n * nc; t += NT) L.refc[t] = xb[t];
+  const int pw = (n + 31) >> 5, mw = mask_words3(n, M);
   for (int k0 = 0; k0 < T; k0 += Tv) {
     const int Tce = min(Tv, T - k0);
+    const int Ts = Tce | 1;   // odd row stride of X, G and H
     if (chunked) {
       __syncthreads();
       for (int t = tid; t < Tce * nc; t += NT) L.W[t] = A.W[k0 * nc + t];
@@ -654,13 +948,17 @@ __device__ __forceinline__ void vjp3(const BwdArgs& A, const ProbDesc& P, const 
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int step = wt * 16 + 4 * kq + v;
-            if (step < Tce) dst[col * Tce + step] = acc[v] * sc;
+            if (step < Tce) dst[col * Ts + step] = acc[v] * sc;
           }
         }
       }
     }
     __syncthreads();
-    const int plane = n * Tce;
+    if (lists && rebuild) {
+      if (k0 == 0 && tid < kSlots3) L.lslot[tid] = 0;   // every thread has read the flags
+      build_lists3<NT>(P, L, k0, Tce, Ts, inv_Tm1, moving);
+    }
+    const int plane = n * Ts;
     const int ngrp = (n + kRob - 1) / kRob;
     for (int t = tid; t < ngrp * Tce; t += NT) {
       const int g = t / Tce, kk = t - g * Tce;
@@ -670,7 +968,7 @@ __device__ __forceinline__ void vjp3(const BwdArgs& A, const ProbDesc& P, const 
 #pragma unroll
       for (int r = 0; r < kRob; ++r) {
         ir[r] = g * kRob + r;
-        const int u = min(ir[r], n - 1) * Tce + kk;
+        const int u = min(ir[r], n - 1) * Ts + kk;
         px[r] = L.X[u];
         py[r] = L.X[plane + u];
         pz[r] = L.X[2 * plane + u];
@@ -679,31 +977,46 @@ __device__ __forceinline__ void vjp3(const BwdArgs& A, const ProbDesc& P, const 
         gz[r] = B.G[2 * plane + u];
         hx[r] = hy[r] = hz[r] = 0.f;
       }
-      for (int j = 0; j < n; ++j) {
-        const int u = j * Tce + kk;
-        const float qx = L.X[u], qy = L.X[plane + u], qz = L.X[2 * plane + u];
-        const float wx = B.G[u], wy = B.G[plane + u], wz = B.G[2 * plane + u];
-#pragma unroll
-        for (int r = 0; r < kRob; ++r)
-          spheroid_vjp(px[r] - qx, py[r] - qy, pz[r] - qz, P.a, P.b, gx[r] - wx, gy[r] - wy,
-                       gz[r] - wz, j != ir[r], hx[r], hy[r], hz[r]);
-      }
       const float tau = (float)(k0 + kk) * inv_Tm1;
-      for (int mo = 0; mo < M; ++mo) {
-        const float* o = L.obs + mo * kObsFloats;
-        const float cx = moving ? fmaf(o[7], tau, o[2]) : o[2];
-        const float cy = moving ? fmaf(o[8], tau, o[3]) : o[3];
-        const float cz = moving ? fmaf(o[9], tau, o[4]) : o[4];
-        const float ra = o[0], rb = o[1], oa = o[5], ob = o[6];
+      if (lists) {
+        // the union of the thread's robots' lists, in increasing index
+        const unsigned* mk = L.mask + ((size_t)((k0 + kk) >> kWinShift3) * n + g * kRob) * mw;
+        for (int q = 0; q < pw; ++q) {
+          unsigned u = 0u;
 #pragma unroll
-        for (int r = 0; r < kRob; ++r)
-          spheroid_vjp(fmaf(px[r], ra, cx), fmaf(py[r], ra, cy), fmaf(pz[r], rb, cz), oa, ob,
-                       gx[r], gy[r], gz[r], true, hx[r], hy[r], hz[r]);
+          for (int r = 0; r < kRob; ++r)
+            if (ir[r] < n) u |= mk[r * mw + q];
+          while (u) {
+            const int j = (__ffs(u) - 1) + 32 * q;
+            u &= u - 1u;
+            pair_vjp3<kRob>(P, ir, j, j * Ts + kk, plane, L.X, B.G, px, py, pz, gx, gy, gz,
+                            hx, hy, hz);
+          }
+        }
+        for (int q = 0; q < mw - pw; ++q) {
+          unsigned u = 0u;
+#pragma unroll
+          for (int r = 0; r < kRob; ++r)
+            if (ir[r] < n) u |= mk[r * mw + pw + q];
+          while (u) {
+            const int mo = (__ffs(u) - 1) + 32 * q;
+            u &= u - 1u;
+            obstacle_vjp3<kRob>(L.obs + mo * kObsFloats, tau, moving, px, py, pz, gx, gy, gz,
+                                hx, hy, hz);
+          }
+        }
+      } else {
+        for (int j = 0; j < n; ++j)
+          pair_vjp3<kRob>(P, ir, j, j * Ts + kk, plane, L.X, B.G, px, py, pz, gx, gy, gz, hx,
+                          hy, hz);
+        for (int mo = 0; mo < M; ++mo)
+          obstacle_vjp3<kRob>(L.obs + mo * kObsFloats, tau, moving, px, py, pz, gx, gy, gz, hx,
+                              hy, hz);
       }
 #pragma unroll
       for (int r = 0; r < kRob; ++r) {
         if (ir[r] >= n) continue;
-        const int u = ir[r] * Tce + kk;
+        const int u = ir[r] * Ts + kk;
         const float x = P.a * px[r], y = P.a * py[r], z = P.b * pz[r];
         float ox = hx[r], oy = hy[r], oz = hz[r];
         if (x > P.pmax[0] || x < P.pmin[0]) ox += gx[r];
@@ -721,7 +1034,7 @@ __device__ __forceinline__ void vjp3(const BwdArgs& A, const ProbDesc& P, const 
       for (int q = wave; q < nrt * nct; q += NT >> 6) {
         const int rt = q / nct, ct = q - rt * nct;
         const int rowA = min(rt * 16 + m, 3 * n - 1), cB = min(ct * 16 + m, nc - 1);
-        const float* vrow = L.V + rowA * Tce;
+        const float* vrow = L.V + rowA * Ts;
         floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
         int s4 = 0;
         for (; s4 + 2 <= nk; s4 += 2) {
@@ -763,12 +1076,16 @@ __global__ __launch_bounds__(NT) void bwd3_kernel(BwdArgs A, int Tv) {
   const int n = P.n, nc = A.nc, tid = threadIdx.x;
   const int nn = n * nc, S = 3 * nn, nc2 = nc * nc;
   const Lds3 L = carve3(lds3, nc, A.Tc, A.n_max, A.M_max, A.S_max);
-  const Lds3b B = carve3b(lds3 + lds3_floats(nc, A.Tc, A.n_max, A.M_max, A.S_max), A.S_max);
+  const Lds3b B = carve3b(
+      lds3 + lds3_floats(nc, A.T, A.Tc, A.n_max, A.M_max, A.S_max, A.lists3 != 0), A.S_max);
   const float rho = A.rho, fw = A.fp_weight;
   const size_t St = (size_t)A.S_total;
   const int rpt = robots_per_thread(n);
+  const bool lists = A.lists3 != 0;
+  const float ska = kSkin3 * P.a, skb = kSkin3 * P.b;
 
   setup3<NT>(A, P, L, A.obs);
+  if (lists) reset_lists3<NT>(L.refc, L.lslot, S);
   for (int t = tid; t < S; t += NT) {
     L.cxi[t] = A.cxi[P.coef_off + t];
     B.gA[t] = A.g_xi_out ? A.g_xi_out[P.coef_off + t] : 0.f;
@@ -808,10 +1125,13 @@ __global__ __launch_bounds__(NT) void bwd3_kernel(BwdArgs A, int Tv) {
       // recompute iterates l0+1 .. l1-1 into the segment area (slot l - l0)
       float* xc = L.xb[0];
       float* xq = L.xb[1];
+      bool moved = false;
       for (int t = tid; t < S; t += NT) {
         xc[t] = ck[t];
         L.lam[t] = ck[St + t];
+        if (lists) moved |= coef_moved3(xc, L.refc, t, nn, ska, skb);
       }
+      if (lists) note_moved3(moved, L.lslot);
       __syncthreads();
       for (int l = l0; l < l1 - 1; ++l) {
         iterate3<NT>(A, P, L, xc, xq, false, dz);
@@ -833,10 +1153,13 @@ __global__ __launch_bounds__(NT) void bwd3_kernel(BwdArgs A, int Tv) {
                                       : A.ckpt + (size_t)(seg + 1) * 2 * St + P.coef_off;
       float* xl = L.xb[0];
       // the cotangent entering the step: g + 2 fw (xi_bar^{l+1} - xi_bar^l)
+      bool moved = false;
       for (int t = tid; t < S; t += NT) {
         xl[t] = cur[t];
         if (fw != 0.f) gx[t] = fmaf(2.f * fw, nxt[t] - cur[t], gx[t]);
+        if (lists) moved |= coef_moved3(xl, L.refc, t, nn, ska, skb);
       }
+      if (lists) note_moved3(moved, L.lslot);
       __syncthreads();
       // robot means of g: means[0..3nc)
       for (int t = tid; t < 3 * nc; t += NT) {
@@ -869,7 +1192,9 @@ __global__ __launch_bounds__(NT) void bwd3_kernel(BwdArgs A, int Tv) {
         gn[t] = fmaf(-2.f * fw, dxi, a2 + a3);
       }
       __syncthreads();
-      if (rpt == 4)
+      if (lists)
+        vjp3<NT, kListRob3>(A, P, L, B, xl, Tv);
+      else if (rpt == 4)
         vjp3<NT, 4>(A, P, L, B, xl, Tv);
       else if (rpt == 2)
         vjp3<NT, 2>(A, P, L, B, xl, Tv);
@@ -891,14 +1216,16 @@ __global__ __launch_bounds__(NT) void bwd3_kernel(BwdArgs A, int Tv) {
 
 }  // namespace
 
-size_t fwd3_lds_bytes(int nc, int T, int Tc, int n_max, int M_max, int S_max) {
-  (void)T;
-  return lds3_floats(nc, Tc, n_max, M_max, S_max) * sizeof(float);
+int list_window3() { return kWin3; }
+
+size_t fwd3_lds_bytes(int nc, int T, int Tc, int n_max, int M_max, int S_max, bool lists) {
+  return lds3_floats(nc, T, Tc, n_max, M_max, S_max, lists) * sizeof(float);
 }
 
-size_t bwd3_lds_bytes(int nc, int Tc, int Tv, int n_max, int M_max, int S_max) {
-  return (lds3_floats(nc, Tc, n_max, M_max, S_max) + 5 * (size_t)r4(S_max) +
-          3 * (size_t)n_max * Tv) * sizeof(float);
+size_t bwd3_lds_bytes(int nc, int T, int Tc, int Tv, int n_max, int M_max, int S_max,
+                      bool lists) {
+  return (lds3_floats(nc, T, Tc, n_max, M_max, S_max, lists) + 5 * (size_t)r4(S_max) +
+          3 * (size_t)n_max * (Tv | 1)) * sizeof(float);
 }
 
 hipError_t prepare_kernels3(size_t lds) {

@@ -109,8 +109,9 @@ def test_3d_accel_objective_matches_oracle(gpu):
 
 
 def test_3d_threads_and_graph_give_the_same_bits(gpu):
-    """Each output entry is summed in a fixed order whatever the block size;
-    graph replays (eager work between them) repeat the eager bits."""
+    """Each output entry, and the residual norms, are summed in a fixed order
+    whatever the block size; graph replays (eager work between them) repeat
+    the eager bits."""
     import torch
     probs = make_batch3d(WORKLOADS_3D[48], batch=5)
     base = _run(probs, 30, threads=512)
@@ -118,6 +119,7 @@ def test_3d_threads_and_graph_give_the_same_bits(gpu):
         got = _run(probs, 30, threads=th)
         np.testing.assert_array_equal(got[1], base[1])
         np.testing.assert_array_equal(got[2], base[2])
+        np.testing.assert_array_equal(got[3][:, [0, 1, 3]], base[3][:, [0, 1, 3]])
     plan, t = base[4], base[5]
     outs = (torch.empty_like(t["xi"]), torch.empty_like(t["xi"]),
             torch.empty((len(probs), 4), device=t["xi"].device))
@@ -334,3 +336,84 @@ def test_3d_autograd_function(gpu):
         got_xi0 = unpack3d(xi0.grad.cpu().numpy(), probs)[b]
         assert rel_err(got_xi, ref.g_xi) <= GRAD_REL_TOL, b
         assert rel_err(got_xi0, ref.g_xi0) <= GRAD_REL_TOL, b
+
+
+# ------------------------------------------------------- 3D candidate lists
+def _bits(probs, L, lists, disp=None, grad=None, threads=0):
+    """Forward (and with grad = (ckpt, g_res, fp_weight) the adjoint) with the
+    candidate lists switched on or off; returns the outputs as numpy arrays."""
+    import torch
+    pk = pack3d(probs)
+    plan = _plan(pk, threads=threads, max_iters=L if grad else 0, ckpt=grad[0] if grad else 1)
+    assert plan.set_candidate_lists(lists) == lists
+    if disp is not None:
+        plan.set_obstacle_motion(torch.from_numpy(disp).cuda())
+    t = {k: torch.from_numpy(getattr(pk, k)).cuda() for k in ("xi", "xi0", "lam0",
+                                                               "boundary", "obstacles")}
+    xo, lo, res = plan.project(t["xi"], t["xi0"], t["lam0"], t["boundary"],
+                               t["obstacles"] if pk.obstacles.size else None, L,
+                               save=grad is not None)
+    out = [xo, lo, res]
+    if grad is not None:
+        rng = np.random.default_rng(11)
+        g_xi = torch.from_numpy(rng.standard_normal(pk.xi.size).astype(np.float32)).cuda()
+        g_lam = torch.from_numpy(rng.standard_normal(pk.xi.size).astype(np.float32)).cuda()
+        gr = torch.from_numpy(np.tile(np.array([grad[1], grad[1], 0, 0], np.float32),
+                                      (len(probs), 1))).cuda()
+        out += list(plan.backward(g_xi, g_lam, gr, grad[2]))
+    torch.cuda.synchronize()
+    return [o.cpu().numpy() for o in out]
+
+
+def _same_bits(a, b):
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+
+
+@pytest.mark.parametrize("case", ["32r", "uneven", "chunked64", "ragged98", "single"])
+def test_3d_candidate_lists_give_the_same_bits(gpu, case):
+    """The lists only skip rows that add exact zeros: forward outputs and
+    residuals with and without them are identical, on LDS-resident and
+    time-chunked horizons (chunks of a multiple of the 16-step window, a
+    ragged last window), ragged robot groups and a lone robot."""
+    cfg, batch, L = {
+        "32r": (WORKLOADS_3D[32], 2, 60),
+        "uneven": (WORKLOADS_3D[48], 6, 40),
+        "chunked64": (scaled3d(WORKLOADS_3D[32], n_robots=(64, 64), n_obs=(30, 30), side=16.0,
+                               height=8.0, n_coef=15, n_steps=120), 1, 12),
+        "ragged98": (scaled3d(WORKLOADS_3D[32], n_robots=(98, 98), n_obs=(7, 7), side=14.0,
+                              height=7.0, n_coef=13, n_steps=77), 1, 6),
+        "single": (scaled3d(WORKLOADS_3D[16], n_robots=(1, 1), n_obs=(0, 0), side=2.0,
+                            height=1.0), 2, 25),
+    }[case]
+    probs = make_batch3d(cfg, batch=batch)
+    on = _bits(probs, L, True)
+    off = _bits(probs, L, False)
+    print(f"[lists3d] {case}: residual max {on[2][:, 0].max():.3e}, "
+          f"status {on[2][:, 3].max()}", flush=True)
+    _same_bits(on, off)
+
+
+def test_3d_candidate_lists_with_moving_obstacles_give_the_same_bits(gpu):
+    probs = make_batch3d(WORKLOADS_3D[16], batch=3)
+    pk = pack3d(probs)
+    disp = np.random.default_rng(16).uniform(-2.0, 2.0, (int(pk.n_obs.sum()), 3))
+    disp = disp.astype(np.float32)
+    _same_bits(_bits(probs, 50, True, disp=disp), _bits(probs, 50, False, disp=disp))
+
+
+@pytest.mark.parametrize("case", ["uneven", "tight"])
+def test_3d_adjoint_candidate_lists_give_the_same_bits(gpu, case):
+    """The adjoint's recompute, residual-cotangent pass and VJP with and
+    without the lists: identical gradients (checkpoint segments jump back and
+    forth over iterates, so the lists are rebuilt on demand)."""
+    if case == "uneven":
+        probs = make_batch3d(WORKLOADS_3D[48], batch=4)
+        grad = (5, 0.5, 0.1)
+    else:
+        cfg = scaled3d(WORKLOADS_3D[16], n_robots=(6, 6), n_obs=(4, 4), side=2.5, height=1.4)
+        probs = make_batch3d(cfg, batch=2)
+        grad = (4, 0.9, 0.25)
+    on = _bits(probs, 24, True, grad=grad)
+    off = _bits(probs, 24, False, grad=grad)
+    _same_bits(on, off)
