@@ -39,6 +39,25 @@ __host__ __device__ inline int r4(int x) { return (x + 3) & ~3; }
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
+// threadIdx.x passed through an empty asm: the per-lane addresses of each
+// phase are then formed inside the iteration loop instead of being hoisted
+// out of it by the compiler and held in registers for the whole loop (which
+// exceeds the 128 VGPRs of a 1024-thread block and spills).
+__device__ __forceinline__ int phase_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
+// The wave's index as a scalar: job and tile indices derived from it stay in
+// scalar registers (divisions by tile counts run on the scalar unit).
+__device__ __forceinline__ int wave_id3(int tid) { return __builtin_amdgcn_readfirstlane(tid >> 6); }
+
+// Scheduling fence between a group of LDS operand reads and the MFMA chain
+// that consumes them: the reads are all issued before the first MFMA (one
+// wait for the group instead of one LDS round trip per MFMA step).
+__device__ __forceinline__ void reads_first() { __builtin_amdgcn_sched_barrier(0); }
+
 // C += A B on a 16x16x4 FP32 MFMA tile (A[m][k] and B[k][m] from lane
 // m + 16 k; C[4 k + v][m] in accumulator v of lane m + 16 k).
 __device__ __forceinline__ floatx4 mfma_16x16x4(float a, float b, floatx4 c) {
@@ -238,7 +257,7 @@ __device__ __forceinline__ bool coef_moved3(const float* x, const float* ref, in
 template <int NT>
 __device__ __forceinline__ void build_lists3(const ProbDesc& P, const Lds3& L, int k0, int Tce,
                                              int Ts, float inv_Tm1, bool moving) {
-  const int n = P.n, M = P.M, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int n = P.n, M = P.M, tid = phase_tid(), lane = tid & 63, wave = wave_id3(tid);
   const int nwc = (Tce + kWin3 - 1) >> kWinShift3;
   float* box = L.V;   // [3 n][nwc] (lo, hi)
   for (int t = tid; t < 3 * n * nwc; t += NT) {
@@ -309,6 +328,128 @@ __device__ __forceinline__ void build_lists3(const ProbDesc& P, const Lds3& L, i
 // overshoot), the gradient of w1 ||r_1||^2 / 2 + w2 ||r_2||^2 / 2.
 constexpr int kForward = 0, kFinal = 1, kResGrad = 2;
 
+// Position tiles: dst[col][step] = scale(col) sum_c W[step][c] Y[col][c]
+// (col < rows; scale s_lo for col < rows_lo, else s_hi) on MFMA 16x16x4 tiles
+// of 16 steps x 16 columns.  A lane supplies A[m][k] = W[16 wt + m][4 s + k']
+// and B[k][m] = Y[16 ct + m][4 s + k'] (m = lane % 16, k' = lane / 16) and
+// holds dst[16 ct + m][16 wt + 4 k' + v]; coefficients past nc enter as 0.
+// Every operand read of a tile is issued before its chain of KS = ceil(nc/4)
+// MFMA steps.  Tiles q0, q0 + qs, ... of nsrc sources (Y0 -> D0 scaled, Y1 ->
+// D1 unscaled) are this wave's.
+template <int KS>
+__device__ __forceinline__ void map_tiles3(const float* Wc, int nc, int rows, int Ts, int Tce,
+                                           const float* Y0, float* D0, float s_lo, float s_hi,
+                                           int rows_lo, const float* Y1, float* D1, int nsrc,
+                                           int q0, int qs) {
+  const int lane = phase_tid() & 63, m = lane & 15, kq = lane >> 4;
+  const int nwt = (Tce + 15) >> 4, nct = (rows + 15) >> 4, per = nwt * nct;
+  for (int q = q0; q < nsrc * per; q += qs) {
+    const int src = q >= per, qq = q - src * per;
+    const int wt = qq / nct, ct = qq - wt * nct;
+    const float* Y = src ? Y1 : Y0;
+    const int stepA = min(wt * 16 + m, Tce - 1), colB = min(ct * 16 + m, rows - 1);
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    if (KS > 0) {
+      constexpr int K = KS > 0 ? KS : 1;
+      float a[K], b[K];
+#pragma unroll
+      for (int s4 = 0; s4 < K; ++s4) {
+        const int c = 4 * s4 + kq, cc = min(c, nc - 1);
+        const float w = Wc[stepA * nc + cc];
+        a[s4] = c < nc ? w : 0.f;
+        b[s4] = Y[colB * nc + cc];
+      }
+      reads_first();
+#pragma unroll
+      for (int s4 = 0; s4 < K; ++s4) acc = mfma_16x16x4(a[s4], b[s4], acc);
+    } else {
+      for (int s4 = 0; s4 < ((nc + 3) >> 2); ++s4) {
+        const int c = 4 * s4 + kq, cc = min(c, nc - 1);
+        const float w = Wc[stepA * nc + cc];
+        acc = mfma_16x16x4(c < nc ? w : 0.f, Y[colB * nc + cc], acc);
+      }
+    }
+    const int col = ct * 16 + m;
+    if (col < rows) {
+      const float sc = src ? 1.f : (col < rows_lo ? s_lo : s_hi);
+      float* d = (src ? D1 : D0) + col * Ts + wt * 16 + 4 * kq;
+      const int left = Tce - (wt * 16 + 4 * kq);
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (v < left) d[v] = acc[v] * sc;
+    }
+  }
+}
+
+// map_tiles3 for nc coefficients: three or four MFMA steps with their
+// operands read first up to 16 coefficients (steps past nc add exact zeros),
+// a plain loop above.
+__device__ __forceinline__ void map_tiles3_any(const float* Wc, int nc, int rows, int Ts,
+                                               int Tce, const float* Y0, float* D0, float s_lo,
+                                               float s_hi, int rows_lo, const float* Y1,
+                                               float* D1, int nsrc, int q0, int qs) {
+  if (nc <= 12)
+    map_tiles3<3>(Wc, nc, rows, Ts, Tce, Y0, D0, s_lo, s_hi, rows_lo, Y1, D1, nsrc, q0, qs);
+  else if (nc <= 16)
+    map_tiles3<4>(Wc, nc, rows, Ts, Tce, Y0, D0, s_lo, s_hi, rows_lo, Y1, D1, nsrc, q0, qs);
+  else
+    map_tiles3<0>(Wc, nc, rows, Ts, Tce, Y0, D0, s_lo, s_hi, rows_lo, Y1, D1, nsrc, q0, qs);
+}
+
+// R (+)= W^T V over a chunk of Tce steps: MFMA 16x16x4 tiles of 16 rows x 16
+// coefficients, A[m][k] = V[16 rt + m][4 s + k'], B[k][m] = W[4 s + k'][16 ct
+// + m]; steps past Tce enter as 0.  Even and odd s go to two accumulators,
+// added at the end; the operands of eight steps are read before their MFMAs.
+template <int NT>
+__device__ __forceinline__ void wtv_tiles3(const float* V, int Ts, const float* Wc, int nc,
+                                           int Tce, int rows, float* R, bool first) {
+  const int tid = phase_tid(), lane = tid & 63, wave = wave_id3(tid), m = lane & 15, kq = lane >> 4;
+  const int nrt = (rows + 15) >> 4, nct = (nc + 15) >> 4, nk = (Tce + 3) >> 2;
+  for (int q = wave; q < nrt * nct; q += NT >> 6) {
+    const int rt = q / nct, ct = q - rt * nct;
+    const int rowA = min(rt * 16 + m, rows - 1), cB = min(ct * 16 + m, nc - 1);
+    const float* vrow = V + rowA * Ts;
+    floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    int s0 = 0;
+    for (; s0 + 8 <= nk; s0 += 8) {
+      float a[8], b[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = 4 * (s0 + u) + kq, kc = min(k, Tce - 1);
+        const float v = vrow[kc];
+        a[u] = k < Tce ? v : 0.f;
+        b[u] = Wc[kc * nc + cB];
+      }
+      reads_first();
+#pragma unroll
+      for (int u = 0; u < 8; u += 2) {
+        acc0 = mfma_16x16x4(a[u], b[u], acc0);
+        acc1 = mfma_16x16x4(a[u + 1], b[u + 1], acc1);
+      }
+    }
+    for (; s0 < nk; ++s0) {
+      const int k = 4 * s0 + kq, kc = min(k, Tce - 1);
+      const float v = vrow[kc];
+      const float a = k < Tce ? v : 0.f, b = Wc[kc * nc + cB];
+      if (s0 & 1)
+        acc1 = mfma_16x16x4(a, b, acc1);
+      else
+        acc0 = mfma_16x16x4(a, b, acc0);
+    }
+    const int c = ct * 16 + m;
+    if (c < nc) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = rt * 16 + 4 * kq + v;
+        if (row < rows) {
+          const float sum = acc0[v] + acc1[v];
+          R[row * nc + c] = first ? sum : R[row * nc + c] + sum;
+        }
+      }
+    }
+  }
+}
+
 // The rows of kRob robots (indices ir, scaled positions p) against partner
 // j at scaled position q: r_1 (kForward, and |r_1|^2 for each unordered pair
 // once in kFinal) or J^T r_1 (kResGrad) added to v.
@@ -360,7 +501,7 @@ __device__ __forceinline__ void sweep3(const Args& A, const ProbDesc& P, const L
                                        const float* xb, float& r1sq, float& r2sq,
                                        float w1 = 1.f, float w2 = 1.f) {
   constexpr bool FINAL = MODE == kFinal;
-  const int n = P.n, M = P.M, nc = A.nc, T = A.T, Tc = A.Tc, tid = threadIdx.x;
+  const int n = P.n, M = P.M, nc = A.nc, T = A.T, Tc = A.Tc, tid = phase_tid();
   const bool chunked = Tc < T;
   const float inv_a = 1.f / P.a, inv_b = 1.f / P.b;
   const float inv_Tm1 = 1.f / (float)(T - 1);
@@ -380,35 +521,10 @@ __device__ __forceinline__ void sweep3(const Args& A, const ProbDesc& P, const L
       __syncthreads();
     }
     const float* Wc = chunked ? L.W : L.W + k0 * nc;
-    // positions X[row][kk] = sum_c W[kk][c] xb[row][c] on MFMA 16x16x4 tiles
-    // of 16 steps x 16 rows (row = axis * n + robot), the wave's tiles dealt
-    // round-robin.  A lane supplies A[m][k] = W[16 wt + m][4 s + k'] and
-    // B[k][m] = xb[16 ct + m][4 s + k'] (m = lane % 16, k' = lane / 16) and
-    // holds X[16 ct + m][16 wt + 4 k' + v]; coefficients past nc enter as 0.
-    {
-      const int lane = tid & 63, wave = tid >> 6, m = lane & 15, kq = lane >> 4;
-      const int nwt = (Tce + 15) >> 4, nct = (3 * n + 15) >> 4, ks = (nc + 3) >> 2;
-      for (int q = wave; q < nwt * nct; q += NT >> 6) {
-        const int wt = q / nct, ct = q - wt * nct;
-        const int stepA = min(wt * 16 + m, Tce - 1), colB = min(ct * 16 + m, 3 * n - 1);
-        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-        for (int s4 = 0; s4 < ks; ++s4) {
-          const int c = 4 * s4 + kq, cc = min(c, nc - 1);
-          const float a = c < nc ? Wc[stepA * nc + cc] : 0.f;
-          acc = mfma_16x16x4(a, xb[colB * nc + cc], acc);
-        }
-        // stored scaled by the robot's semi-axes: x/a, y/a, z/b
-        const int col = ct * 16 + m;
-        const float sc = col < 2 * n ? inv_a : inv_b;
-        if (col < 3 * n) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int step = wt * 16 + 4 * kq + v;
-            if (step < Tce) L.X[col * Ts + step] = acc[v] * sc;
-          }
-        }
-      }
-    }
+    // positions X[row][kk] = sum_c W[kk][c] xb[row][c] (row = axis * n +
+    // robot), stored scaled by the robot's semi-axes: x/a, y/a, z/b
+    map_tiles3_any(Wc, nc, 3 * n, Ts, Tce, xb, L.X, inv_a, inv_b, 2 * n, nullptr, nullptr, 1,
+                   wave_id3(tid), NT >> 6);
     __syncthreads();
     if (lists && rebuild) {
       if (k0 == 0 && tid < kSlots3) L.lslot[tid] = 0;   // every thread has read the flags
@@ -528,44 +644,7 @@ __device__ __forceinline__ void sweep3(const Args& A, const ProbDesc& P, const L
         }
       __syncthreads();
     } else {
-      // R (+)= W^T V over this chunk's steps on MFMA 16x16x4 tiles of 16 rows
-      // x 16 coefficients: A[m][k] = V[16 rt + m][4 s + k'], B[k][m] =
-      // W[4 s + k'][16 ct + m]; steps past Tce enter as 0.  Two accumulators
-      // (even and odd s) added at the end.
-      const int lane = tid & 63, wave = tid >> 6, m = lane & 15, kq = lane >> 4;
-      const int nrt = (3 * n + 15) >> 4, nct = (nc + 15) >> 4, nk = (Tce + 3) >> 2;
-      for (int q = wave; q < nrt * nct; q += NT >> 6) {
-        const int rt = q / nct, ct = q - rt * nct;
-        const int rowA = min(rt * 16 + m, 3 * n - 1), cB = min(ct * 16 + m, nc - 1);
-        const float* vrow = L.V + rowA * Ts;
-        floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-        int s4 = 0;
-        for (; s4 + 2 <= nk; s4 += 2) {
-          const int k0s = 4 * s4 + kq, k1s = k0s + 4;
-          const float a0 = k0s < Tce ? vrow[min(k0s, Tce - 1)] : 0.f;
-          const float a1 = k1s < Tce ? vrow[min(k1s, Tce - 1)] : 0.f;
-          const float b0 = Wc[min(k0s, Tce - 1) * nc + cB];
-          const float b1 = Wc[min(k1s, Tce - 1) * nc + cB];
-          acc0 = mfma_16x16x4(a0, b0, acc0);
-          acc1 = mfma_16x16x4(a1, b1, acc1);
-        }
-        if (s4 < nk) {
-          const int k0s = 4 * s4 + kq;
-          const float a0 = k0s < Tce ? vrow[min(k0s, Tce - 1)] : 0.f;
-          acc0 = mfma_16x16x4(a0, Wc[min(k0s, Tce - 1) * nc + cB], acc0);
-        }
-        const int c = ct * 16 + m;
-        if (c < nc) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int row = rt * 16 + 4 * kq + v;
-            if (row < 3 * n) {
-              const float sum = acc0[v] + acc1[v];
-              L.R[row * nc + c] = k0 == 0 ? sum : L.R[row * nc + c] + sum;
-            }
-          }
-        }
-      }
+      wtv_tiles3<NT>(L.V, Ts, Wc, nc, Tce, 3 * n, L.R, k0 == 0);
       __syncthreads();
     }
   }
@@ -619,72 +698,101 @@ __device__ __forceinline__ void setup3(const Args& A, const ProbDesc& P, const L
   }
 }
 
-// Mean-field term of the xi_bar step: wave ax < 3 forms the robot means of
-// u = lambda - 2 rho R and of x for axis ax (lane q + QW p sums the robots
-// i = p (mod 64 / QW) of coefficient q, then a butterfly over p), and
-// bias[ax][c] = sum_q DS[c][q] um[q] + DSH[c][q] xm[q] into L.means[ax nc + c].
-// Needs at least three waves (NT >= 256).
+// Robot means per (axis, coefficient) of u = lambda - 2 rho R (into
+// L.means[ax nc + q]) and of x (into L.means[3 nc + ax nc + q]), one (axis,
+// quantity) job per wave: lane q + QW p sums the robots i = p (mod 64 / QW) in
+// two chains, then a butterfly over p.
 template <int NT>
 __device__ __forceinline__ void mean_field3(const ProbDesc& P, const Lds3& L, int nc, float rho,
                                             const float* x) {
-  const int n = P.n, nn = n * nc, nc2 = nc * nc;
-  const int lane = threadIdx.x & 63, ax = threadIdx.x >> 6;
-  if (ax >= 3) return;
+  const int n = P.n, nn = n * nc, tid = phase_tid(), lane = tid & 63;
   const int QW = nc <= 16 ? 16 : 32, Pw = 64 / QW;
   const int q = lane % QW, p = lane / QW, qq = min(q, nc - 1);
-  const float* lam = L.lam + ax * nn + qq;
-  const float* R = L.R + ax * nn + qq;
-  const float* xa = x + ax * nn + qq;
-  float su = 0.f, sx = 0.f;
-  for (int i = p; i < n; i += Pw) {
-    su += fmaf(-2.f * rho, R[i * nc], lam[i * nc]);
-    sx += xa[i * nc];
+  for (int job = wave_id3(tid); job < 6; job += NT >> 6) {
+    const int ax = job >> 1, which = job & 1;
+    const float* lam = L.lam + ax * nn + qq;
+    const float* R = L.R + ax * nn + qq;
+    const float* xa = x + ax * nn + qq;
+    float s0 = 0.f, s1 = 0.f;
+    int i = p;
+    for (; i + Pw < n; i += 2 * Pw) {
+      const int i1 = i + Pw;
+      s0 += which ? xa[i * nc] : fmaf(-2.f * rho, R[i * nc], lam[i * nc]);
+      s1 += which ? xa[i1 * nc] : fmaf(-2.f * rho, R[i1 * nc], lam[i1 * nc]);
+    }
+    if (i < n) s0 += which ? xa[i * nc] : fmaf(-2.f * rho, R[i * nc], lam[i * nc]);
+    float sm = s0 + s1;
+    for (int o = QW; o < 64; o <<= 1) sm += __shfl_xor(sm, o, 64);
+    if (p == 0 && q < nc) L.means[which * 3 * nc + ax * nc + q] = sm / (float)n;
   }
-  for (int o = QW; o < 64; o <<= 1) {
-    su += __shfl_xor(su, o, 64);
-    sx += __shfl_xor(sx, o, 64);
-  }
-  const float um = su / (float)n, xm = sx / (float)n;
-  const float* DS = L.fac + nc2 + qq * nc;
-  const float* DSH = L.fac + 3 * nc2 + qq * nc;
-  float b = 0.f;
-  for (int k = 0; k < nc; ++k)
-    b = fmaf(DS[k], __shfl(um, k, 64), fmaf(DSH[k], __shfl(xm, k, 64), b));
-  if (p == 0 && q < nc) L.means[ax * nc + q] = b;
 }
 
 // The xi_bar step on MFMA 16x16x4 tiles, one wave per tile of 16 rows (row =
-// axis * n + robot) and every coefficient column tile: xi_bar'[row][c] =
-// c_xi + sum_q u[row][q] S[c][q] + sum_q x[row][q] SH[c][q] + bias[axis][c],
-// u = lambda - 2 rho R formed as the A operand is read (A[m][k] = u[16 rt +
-// m][4 s + k'], B[k][m] = S[16 ct + m][4 s + k']); the tile's lanes then
-// write lambda' = lambda - rho R of their own entries (no other wave reads
-// these rows), check the candidate lists and, with `last`, add ||z' - z||^2.
-template <int NT>
+// axis * n + robot) and every coefficient column tile:
+//   xi_bar'[row][c] = c_xi + sum_q (u[row][q] S[c][q] + um[axis][q] DS[c][q])
+//                           + sum_q (x[row][q] SH[c][q] + xm[axis][q] DSH[c][q])
+// with u = lambda - 2 rho R formed as the A operand is read (A[m][k] =
+// u[16 rt + m][4 s + k'], B[k][m] = S[16 ct + m][4 s + k'], KS >= nc/4
+// steps in groups of four whose operand reads are issued first; steps past
+// nc add exact zeros).  The tile's lanes then write lambda'
+// = lambda - rho R of their own entries (no other wave reads these rows),
+// check the candidate lists and, with `last`, add ||z' - z||^2.
+template <int NT, int KS>
 __device__ __forceinline__ void xi_step3(const ProbDesc& P, const Lds3& L, int nc, float rho,
                                          const float* xcur, float* xnext, bool last,
                                          bool lists, float& dzsq) {
   const int n = P.n, nc2 = nc * nc, rows = 3 * n;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, m = lane & 15, kq = lane >> 4;
-  const int nrt = (rows + 15) >> 4, nct = (nc + 15) >> 4, ks = (nc + 3) >> 2;
+  const int tid = phase_tid(), lane = tid & 63, wave = wave_id3(tid), m = lane & 15, kq = lane >> 4;
+  const int nrt = (rows + 15) >> 4, nct = (nc + 15) >> 4;
   const float ska = kSkin3 * P.a, skb = kSkin3 * P.b;
   bool moved = false;
   for (int rt = wave; rt < nrt; rt += NT >> 6) {
-    const int rowA = min(rt * 16 + m, rows - 1);
+    const int rowA = min(rt * 16 + m, rows - 1), axA = rowA / n;
     floatx4 acc[2][2];
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct) acc[ct][0] = acc[ct][1] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int s4 = 0; s4 < ks; ++s4) {
-      const int q = 4 * s4 + kq, qq = min(q, nc - 1);
-      const float u = fmaf(-2.f * rho, L.R[rowA * nc + qq], L.lam[rowA * nc + qq]);
-      const float au = q < nc ? u : 0.f;
-      const float xa = q < nc ? xcur[rowA * nc + qq] : 0.f;
+    // KS > 0: groups of up to four MFMA steps, every operand of a group read
+    // first; KS = 0: one step at a time over ceil(nc / 4) steps
+    const int ksteps = KS > 0 ? KS : (nc + 3) >> 2;
+#pragma unroll
+    for (int g0 = 0; g0 < ksteps; g0 += (KS > 0 ? 4 : 1)) {
+      constexpr int KG = KS == 0 ? 1 : (KS < 4 ? KS : 4);
+      float au[KG], aum[KG], ax[KG], axm[KG];
+#pragma unroll
+      for (int e = 0; e < KG; ++e) {
+        const int q = 4 * (g0 + e) + kq, qq = min(q, nc - 1);
+        const bool ok = g0 + e < ksteps && q < nc;
+        const float u = fmaf(-2.f * rho, L.R[rowA * nc + qq], L.lam[rowA * nc + qq]);
+        const float um = L.means[axA * nc + qq], xv = xcur[rowA * nc + qq];
+        const float xm = L.means[3 * nc + axA * nc + qq];
+        au[e] = ok ? u : 0.f;
+        aum[e] = ok ? um : 0.f;
+        ax[e] = ok ? xv : 0.f;
+        axm[e] = ok ? xm : 0.f;
+      }
 #pragma unroll
       for (int ct = 0; ct < 2; ++ct) {
-        if (ct < nct) {
-          const int cB = min(ct * 16 + m, nc - 1);
-          acc[ct][0] = mfma_16x16x4(au, L.fac[cB * nc + qq], acc[ct][0]);
-          acc[ct][1] = mfma_16x16x4(xa, L.fac[2 * nc2 + cB * nc + qq], acc[ct][1]);
+        if (ct >= nct) continue;
+        const float* Sr = L.fac + min(ct * 16 + m, nc - 1) * nc;
+        float bs[KG], bds[KG], bsh[KG], bdsh[KG];
+#pragma unroll
+        for (int e = 0; e < KG; ++e) {
+          const int qq = min(4 * (g0 + e) + kq, nc - 1);
+          bs[e] = Sr[qq];
+          bds[e] = Sr[nc2 + qq];
+          bsh[e] = Sr[2 * nc2 + qq];
+          bdsh[e] = Sr[3 * nc2 + qq];
+        }
+        reads_first();
+#pragma unroll
+        for (int e = 0; e < KG; ++e) {
+          acc[ct][0] = mfma_16x16x4(au[e], bs[e], acc[ct][0]);
+          acc[ct][1] = mfma_16x16x4(ax[e], bsh[e], acc[ct][1]);
+        }
+#pragma unroll
+        for (int e = 0; e < KG; ++e) {
+          acc[ct][0] = mfma_16x16x4(aum[e], bds[e], acc[ct][0]);
+          acc[ct][1] = mfma_16x16x4(axm[e], bdsh[e], acc[ct][1]);
         }
       }
     }
@@ -696,13 +804,12 @@ __device__ __forceinline__ void xi_step3(const ProbDesc& P, const Lds3& L, int n
       for (int v = 0; v < 4; ++v) {
         const int row = rt * 16 + 4 * kq + v;
         if (row >= rows) continue;
-        const int e = row * nc + c, axis = row / n;
-        const float val =
-            L.cxi[e] + ((acc[ct][0][v] + acc[ct][1][v]) + L.means[axis * nc + c]);
+        const int e = row * nc + c;
+        const float val = L.cxi[e] + (acc[ct][0][v] + acc[ct][1][v]);
         xnext[e] = val;
         const float r = L.R[e];
         L.lam[e] = fmaf(-rho, r, L.lam[e]);
-        if (lists) moved |= !(fabsf(val - L.refc[e]) <= (axis < 2 ? ska : skb));
+        if (lists) moved |= !(fabsf(val - L.refc[e]) <= (row < 2 * n ? ska : skb));
         if (last) {
           const float d = val - xcur[e];
           dzsq = fmaf(rho * r, rho * r, fmaf(d, d, dzsq));
@@ -725,7 +832,11 @@ __device__ __forceinline__ void iterate3(const Args& A, const ProbDesc& P, const
   sweep3_any<NT, kForward>(A, P, L, xcur, z0, z1);
   mean_field3<NT>(P, L, A.nc, A.rho, xcur);
   __syncthreads();
-  xi_step3<NT>(P, L, A.nc, A.rho, xcur, xnext, last, A.lists3 != 0, dzsq);
+  const bool lists = A.lists3 != 0;
+  if (A.nc <= 16)
+    xi_step3<NT, 4>(P, L, A.nc, A.rho, xcur, xnext, last, lists, dzsq);
+  else
+    xi_step3<NT, 0>(P, L, A.nc, A.rho, xcur, xnext, last, lists, dzsq);
   __syncthreads();
 }
 
@@ -906,12 +1017,12 @@ __device__ __forceinline__ void obstacle_vjp3(const float* o, float tau, bool mo
 template <int NT, int kRob>
 __device__ __forceinline__ void vjp3(const BwdArgs& A, const ProbDesc& P, const Lds3& L,
                                      const Lds3b& B, const float* xb, int Tv) {
-  const int n = P.n, M = P.M, nc = A.nc, T = A.T, Tc = A.Tc, tid = threadIdx.x;
+  const int n = P.n, M = P.M, nc = A.nc, T = A.T, Tc = A.Tc, tid = phase_tid();
   const bool chunked = Tc < T;
   const float inv_a = 1.f / P.a, inv_b = 1.f / P.b;
   const float inv_Tm1 = 1.f / (float)(T - 1);
   const bool moving = A.ovel != nullptr;
-  const int lane = tid & 63, wave = tid >> 6, m = lane & 15, kq = lane >> 4;
+  const int wave = wave_id3(tid);
   const bool lists = A.lists3 != 0;
   const bool rebuild = lists && lists_moved3(L.lslot, NT >> 6);
   if (rebuild)
@@ -926,33 +1037,9 @@ __device__ __forceinline__ void vjp3(const BwdArgs& A, const ProbDesc& P, const 
       __syncthreads();
     }
     const float* Wc = chunked ? L.W : L.W + k0 * nc;
-    // X (scaled as in the forward) and G on MFMA 16x16x4 tiles (the forward's
-    // position tiles, two sources)
-    {
-      const int nwt = (Tce + 15) >> 4, nct = (3 * n + 15) >> 4, ks = (nc + 3) >> 2;
-      for (int q = wave; q < 2 * nwt * nct; q += NT >> 6) {
-        const int src = q >= nwt * nct, qq = q - src * nwt * nct;
-        const int wt = qq / nct, ct = qq - wt * nct;
-        const float* Y = src ? B.gR : xb;
-        const int stepA = min(wt * 16 + m, Tce - 1), colB = min(ct * 16 + m, 3 * n - 1);
-        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-        for (int s4 = 0; s4 < ks; ++s4) {
-          const int c = 4 * s4 + kq, cc = min(c, nc - 1);
-          const float a = c < nc ? Wc[stepA * nc + cc] : 0.f;
-          acc = mfma_16x16x4(a, Y[colB * nc + cc], acc);
-        }
-        const int col = ct * 16 + m;
-        const float sc = src ? 1.f : (col < 2 * n ? inv_a : inv_b);
-        float* dst = src ? B.G : L.X;
-        if (col < 3 * n) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int step = wt * 16 + 4 * kq + v;
-            if (step < Tce) dst[col * Ts + step] = acc[v] * sc;
-          }
-        }
-      }
-    }
+    // X (scaled as in the forward) and G = W g_R, the forward's position tiles
+    map_tiles3_any(Wc, nc, 3 * n, Ts, Tce, xb, L.X, inv_a, inv_b, 2 * n, B.gR, B.G, 2, wave,
+                   NT >> 6);
     __syncthreads();
     if (lists && rebuild) {
       if (k0 == 0 && tid < kSlots3) L.lslot[tid] = 0;   // every thread has read the flags
@@ -1029,41 +1116,7 @@ __device__ __forceinline__ void vjp3(const BwdArgs& A, const ProbDesc& P, const 
     }
     __syncthreads();
     // R (+)= W^T H, the forward's W^T tiles
-    {
-      const int nrt = (3 * n + 15) >> 4, nct = (nc + 15) >> 4, nk = (Tce + 3) >> 2;
-      for (int q = wave; q < nrt * nct; q += NT >> 6) {
-        const int rt = q / nct, ct = q - rt * nct;
-        const int rowA = min(rt * 16 + m, 3 * n - 1), cB = min(ct * 16 + m, nc - 1);
-        const float* vrow = L.V + rowA * Ts;
-        floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-        int s4 = 0;
-        for (; s4 + 2 <= nk; s4 += 2) {
-          const int k0s = 4 * s4 + kq, k1s = k0s + 4;
-          const float a0 = k0s < Tce ? vrow[min(k0s, Tce - 1)] : 0.f;
-          const float a1 = k1s < Tce ? vrow[min(k1s, Tce - 1)] : 0.f;
-          const float b0 = Wc[min(k0s, Tce - 1) * nc + cB];
-          const float b1 = Wc[min(k1s, Tce - 1) * nc + cB];
-          acc0 = mfma_16x16x4(a0, b0, acc0);
-          acc1 = mfma_16x16x4(a1, b1, acc1);
-        }
-        if (s4 < nk) {
-          const int k0s = 4 * s4 + kq;
-          const float a0 = k0s < Tce ? vrow[min(k0s, Tce - 1)] : 0.f;
-          acc0 = mfma_16x16x4(a0, Wc[min(k0s, Tce - 1) * nc + cB], acc0);
-        }
-        const int c = ct * 16 + m;
-        if (c < nc) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int row = rt * 16 + 4 * kq + v;
-            if (row < 3 * n) {
-              const float sum = acc0[v] + acc1[v];
-              L.R[row * nc + c] = k0 == 0 ? sum : L.R[row * nc + c] + sum;
-            }
-          }
-        }
-      }
-    }
+    wtv_tiles3<NT>(L.V, Ts, Wc, nc, Tce, 3 * n, L.R, k0 == 0);
     __syncthreads();
   }
 }
