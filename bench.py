@@ -203,6 +203,7 @@ def candidate_pipeline_timing(dev, steps=5):
     return dict(workload=f"{WORKLOADS[2].name}: 32 candidates -> top {k} -> SF {L} iterations -> "
                          "best by feasibility and smoothness",
                 ms=round(e0.elapsed_time(e1) / steps, 4),
+                threads=[int(pl.threads) for pl in plans],
                 chosen=int(out["topk"].cpu()[best]),
                 chosen_residual=float(np.hypot(res[best, 0], res[best, 1])),
                 chosen_cost=float(out["cost"].cpu()[best]))
@@ -316,9 +317,71 @@ def config_rates(cfg_id, dev, steps=3, graph=False, plain_sample=2):
     if B == 1:
         out["latency_ms"] = dict(fwd=round(fwd_ms, 4), fwd_bwd=round(f_ms + b_ms, 4),
                                  plain_fwd=round(plain_ms, 4))
+    if graph and B > 1:
+        # the costliest problem alone (same thread count, same graph path):
+        # with no more problems than compute units every block has a CU of
+        # its own, so the batch takes about as long as its largest problem
+        cost = [T * (0.5 * p.n * (p.n - 1) + p.n * p.M + p.n) + 4.0 * p.n * nc * nc
+                for p in probs]
+        big = probs[int(np.argmax(cost))]
+        bpk = pack([big])
+        bplan = SFPlan(bpk.n_robots, bpk.n_obs, bpk.robot_a, bpk.box, bpk.n_coef, bpk.n_steps,
+                       RHO, threads=plan.threads, device=dev)
+        bt = to_device(bpk, dev)
+        bargs = (bt["xi"], bt["xi0"], bt["lam0"], bt["boundary"], bt["obstacles"])
+        bouts = (torch.empty_like(bt["xi"]), torch.empty_like(bt["xi"]),
+                 torch.empty((1, 4), dtype=torch.float32, device=dev))
+        with torch.cuda.stream(stream):
+            bplan.project(*bargs, L, graph=True, out=bouts)
+            torch.cuda.synchronize()
+            e = _events(2)
+            e[0].record(stream)
+            for _ in range(steps):
+                bplan.project(*bargs, L, graph=True, out=bouts)
+            e[1].record(stream)
+            torch.cuda.synchronize()
+        big_ms = e[0].elapsed_time(e[1]) / steps
+        out["largest_alone"] = dict(robots=int(big.n), obstacles=int(big.M),
+                                    fwd_ms=round(big_ms, 4),
+                                    batch_over_largest=round(fwd_ms / big_ms, 3))
+        bplan.close()
     plan.close()
     splan.close()
     return out
+
+
+def uneven_scaling(dev, L=500, sizes=(48, 256, 1024)):
+    """Uneven batches of the c4 recipe (robots U{8..64}) at growing batch
+    size, one fused forward launch each (1024 threads, L iterations): with no
+    more problems than compute units the batch takes about as long as its
+    largest problem; beyond, the time grows with the work."""
+    import torch
+
+    from paper_2510_09204_amd import SFPlan, to_device
+    from workloads import WORKLOADS, make_batch, pack
+    rows = []
+    for B in sizes:
+        probs = make_batch(WORKLOADS[4], batch=B)
+        pk = pack(probs)
+        plan = SFPlan(pk.n_robots, pk.n_obs, pk.robot_a, pk.box, pk.n_coef, pk.n_steps, RHO,
+                      threads=1024, device=dev)
+        t = to_device(pk, dev)
+        args = (t["xi"], t["xi0"], t["lam0"], t["boundary"], t["obstacles"], L)
+        plan.project(*args)
+        torch.cuda.synchronize()
+        e = _events(2)
+        e[0].record(torch.cuda.current_stream(dev))
+        plan.project(*args)
+        e[1].record(torch.cuda.current_stream(dev))
+        torch.cuda.synchronize()
+        ms = e[0].elapsed_time(e[1])
+        rows.append(dict(batch=B, ms=round(ms, 3), problems_per_s=round(B / (ms / 1e3), 1),
+                         robots_max=int(pk.n_robots.max())))
+        plan.close()
+    for r in rows:
+        r["time_over_smallest_batch"] = round(r["ms"] / rows[0]["ms"], 3)
+    return dict(workload="c4 recipe, robots U{8..64}, obstacles U{0..30}", iters=L, threads=1024,
+                runs=rows)
 
 
 def cpu_model():
@@ -481,9 +544,12 @@ def main(argv=None):
         return 0
     if a.copy_probe:
         import torch
+        # the last kernel of the run is the calibration copy: an elementwise
+        # shader kernel that reads MIB MiB and writes MIB MiB
         src = torch.ones(a.copy_probe * (1 << 18), dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         print(json.dumps(dict(copy_probe_bytes=src.numel() * 4)))
         return 0
@@ -623,6 +689,7 @@ def main(argv=None):
         others = {f"c{c}": config_rates(c, dev, steps=2 if c == 5 else 3, graph=(c == 4),
                                         plain_sample=1 if c == 5 else 2)
                   for c in (1, 2, 4, 5) if c != a.config}
+        others["uneven_scaling"] = uneven_scaling(dev)
     cpu = None
     if not a.no_cpu:
         cpu = cpu_baseline(probs[0], L, a.cpu_budget, pool)

@@ -767,8 +767,10 @@ int sf_project(sf_plan_t* plan, void* workspace, const float* xi, const float* x
     const std::string key = tune_key(plan, false);
     int t = 0;
     if (!tune_lookup(key, t)) {
+      // trials of a few dozen iterations: the first iterations of a launch
+      // (set-up, the forced list build) are not representative
       sf::FwdArgs trial = a;
-      trial.L = std::min<int>(n_iters, 3);
+      trial.L = std::min<int>(n_iters, 24);
       trial.save = 0;
       float ms[3] = {0.f, 0.f, 0.f};
       hipError_t err = hipSuccess;
