@@ -148,8 +148,15 @@ def cpu_pool_rates(problems, L, budget_s=8.0):
     import multiprocessing as mp
     workers = max(1, min(16, len(os.sched_getaffinity(0))))
     jobs = [(problems[w % len(problems)], budget_s) for w in range(workers)]
-    with mp.get_context("fork").Pool(workers) as pool:
+    # close + join (not terminate) so that no pool thread outlives the call:
+    # a lingering handler thread competes for the interpreter lock with the
+    # host side of the later GPU timings
+    pool = mp.get_context("fork").Pool(workers)
+    try:
         times = pool.map(_pool_worker, jobs)
+    finally:
+        pool.close()
+        pool.join()
     return dict(value=sum(1.0 / (t[2] * L) for t in times), unit="problems/s",
                 cores=workers, fwd_value=sum(1.0 / (t[0] * L) for t in times),
                 sample=f"{workers} problems, one per process, each timed as the one-core "
