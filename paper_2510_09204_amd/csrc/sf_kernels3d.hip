@@ -170,7 +170,7 @@ constexpr int kSlots3 = 16;        // per-wave flags of the list check (waves of
 constexpr float kSkin3 = 0.25f;    // skin d in scaled units
 constexpr int kWinShift3 = 4;      // list window of 2^kWinShift3 steps
 constexpr int kWin3 = 1 << kWinShift3;
-constexpr int kListRob3 = 4;       // robots per thread of the list walk
+constexpr int kListRob3 = 1;       // robots per thread of the list walk
 static_assert(kWin3 >= 4, "window boxes of a chunk must fit in the V area");
 
 // 32-bit mask words per (window, robot): partner words, then obstacle words.

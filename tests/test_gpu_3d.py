@@ -187,6 +187,12 @@ def test_3d_unsupported_calls_fail_loudly(gpu):
     with pytest.raises(SFError) as e:
         plan.backward(t["xi0"], None, None)
     assert e.value.code == -4
+    # the candidate-list switch is for 3D plans; planar fused kernels always use lists
+    from sf_testlib import make_plan
+    plan2, _ = make_plan(make_batch(WORKLOADS[1], batch=1), RHO, 0, 1, 0)
+    with pytest.raises(SFError) as e:
+        plan2.set_candidate_lists(False)
+    assert e.value.code == -1
 
 
 @pytest.mark.parametrize("cfg_id,batch,L", [(16, 3, 50), (48, 5, 40)])
