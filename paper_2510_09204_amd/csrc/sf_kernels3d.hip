@@ -369,15 +369,15 @@ __device__ __forceinline__ void map_tiles3(const float* Wc, int nc, int rows, in
         acc = mfma_16x16x4(c < nc ? w : 0.f, Y[colB * nc + cc], acc);
       }
     }
-    const int col = ct * 16 + m;
-    if (col < rows) {
-      const float sc = src ? 1.f : (col < rows_lo ? s_lo : s_hi);
-      float* d = (src ? D1 : D0) + col * Ts + wt * 16 + 4 * kq;
-      const int left = Tce - (wt * 16 + 4 * kq);
+    // stores without branches: a padding step's value is that of step Tce - 1
+    // and a padding column's that of column rows - 1 (the same operands give
+    // the same bits), so their clamped stores repeat those values
+    const int col = min(ct * 16 + m, rows - 1);
+    const float sc = src ? 1.f : (col < rows_lo ? s_lo : s_hi);
+    float* d = (src ? D1 : D0) + col * Ts;
+    const int k = wt * 16 + 4 * kq;
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        if (v < left) d[v] = acc[v] * sc;
-    }
+    for (int v = 0; v < 4; ++v) d[min(k + v, Tce - 1)] = acc[v] * sc;
   }
 }
 

@@ -74,3 +74,32 @@ def test_static_area_rejects_a_recompute_area_beyond_its_size(gpu):
     g = plan.backward(cot[0], cot[1], g_res, 0.0)       # the workspace path still runs
     torch.cuda.synchronize()
     assert all(np.isfinite(x.cpu().numpy()).all() for x in g)
+
+
+def test_static_area_backward_matches_workspace_backward_3d(gpu):
+    """The same on a 3D (spheroid) plan: the 3D adjoint's segment recompute
+    goes to the static array."""
+    import torch
+    from paper_2510_09204_amd import SFPlan, to_device
+    from workloads.gen3d import WORKLOADS_3D, make_batch3d, pack3d
+    probs = make_batch3d(WORKLOADS_3D[48], batch=3)
+    pk = pack3d(probs)
+    L = 20
+    plan = SFPlan(pk.n_robots, pk.n_obs, pk.robot_ab, pk.box, pk.n_coef, pk.n_steps, RHO,
+                  n_dim=3, max_iters=L, checkpoint_every=5)
+    t = {k: torch.from_numpy(getattr(pk, k)).cuda() for k in ("xi", "xi0", "lam0",
+                                                               "boundary", "obstacles")}
+    plan.project(t["xi"], t["xi0"], t["lam0"], t["boundary"], t["obstacles"], L, save=True)
+    rng = np.random.default_rng(48)
+    cot = [torch.from_numpy(rng.standard_normal(plan.coef_size).astype(np.float32)).cuda()
+           for _ in range(2)]
+    g_res = torch.from_numpy(np.tile(np.float32([[0.5, 0.5, 0.0, 0.0]]), (plan.B, 1))).cuda()
+    outs = _outputs(plan)
+    print(f"[static] 3D B={plan.B} L={L} ckpt=5", flush=True)
+    plan.backward(cot[0], cot[1], g_res, 0.1, out=outs, static_area=True)
+    ref = plan.backward(cot[0], cot[1], g_res, 0.1)
+    torch.cuda.synchronize()
+    for name, a, b in zip(("g_xi", "g_xi0", "g_lam0"), outs, ref):
+        a, b = a.cpu().numpy(), b.cpu().numpy()
+        assert np.isfinite(b).all(), name
+        np.testing.assert_array_equal(a, b)
