@@ -37,12 +37,13 @@
  * (for a != b this is not the Euclidean argmin of eq. beta_step with d held
  * fixed), and d = max(1, s) with s the scaled length of Delta, the exact
  * minimiser over d >= 1 in scaled coordinates; together they put e on the ray
- * of Delta.  For n_dim = 3, sf_project (SF_SAVE_FOR_BACKWARD and SF_GRAPH
- * included, obstacle motion too) and sf_project_backward run; the adjoint
- * chains through the same alpha, beta and d steps, with the Jacobian of r_1 =
- * (1 - 1/s) Delta on active rows (identity at Delta = 0).  SF_PLAIN,
- * SF_UNFUSED, early exit and sf_smoothness return SF_ERR_INVALID_ARG.  Each
- * workgroup visits every robot pair.
+ * of Delta.  For n_dim = 3, sf_project (SF_SAVE_FOR_BACKWARD, SF_GRAPH,
+ * obstacle motion and early exit included) and sf_project_backward run; the
+ * adjoint chains through the same alpha, beta and d steps, with the Jacobian
+ * of r_1 = (1 - 1/s) Delta on active rows (identity at Delta = 0).  SF_PLAIN,
+ * SF_UNFUSED and sf_smoothness return SF_ERR_INVALID_ARG.  Each workgroup
+ * visits the candidate partners and obstacles of each robot
+ * (sf_set_candidate_lists).
  *
  * Ownership: the caller allocates every array and the workspace; the library
  * owns only the host-side plan.  Calls never retain caller pointers (the
@@ -242,7 +243,8 @@ int64_t sf_forward_generation(const sf_plan_t* plan);
  * primal_residual, read as sqrt(||r_1||^2 + ||r_2||^2)).  With check_every = c
  * > 0, at every iteration l that is a multiple of c the residual of the
  * current iterate xi_bar^l is formed as part of that iteration's constraint
- * pass; if it is <= tol, the problem completes iteration l and stops, so it
+ * pass (n_dim = 3: by a residual pass just before it); if it is <= tol, the
+ * problem completes iteration l and stops, so it
  * returns xi_bar^{l+1}, lambda^{l+1} (and their residual, as always).  Other
  * problems of the batch continue.  n_iters stays the upper bound.  The
  * iterations each problem ran are available from sf_project_iterations, and

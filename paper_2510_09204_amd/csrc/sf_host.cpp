@@ -732,8 +732,6 @@ int sf_project(sf_plan_t* plan, void* workspace, const float* xi, const float* x
   if (dim3 && (flags & (SF_PLAIN | SF_UNFUSED)))
     return fail(SF_ERR_INVALID_ARG, "n_dim = 3 runs the fused kernels only (no SF_PLAIN, "
                                     "SF_UNFUSED)");
-  if (dim3 && plan->exit_every > 0)
-    return fail(SF_ERR_INVALID_ARG, "n_dim = 3 has no early exit");
   hipStream_t s = static_cast<hipStream_t>(stream);
   plan->saved = false;
   ++plan->generation;
@@ -955,8 +953,6 @@ int sf_set_early_exit(sf_plan_t* plan, float tol, int32_t check_every) {
   if (!plan) return fail(SF_ERR_INVALID_ARG, "plan is NULL");
   if (check_every < 0) return fail(SF_ERR_INVALID_ARG, "check_every < 0");
   if (!std::isfinite(tol) || tol < 0.f) return fail(SF_ERR_INVALID_ARG, "tol must be finite, >= 0");
-  if (plan->cfg.n_dim == 3 && check_every > 0)
-    return fail(SF_ERR_INVALID_ARG, "n_dim = 3 has no early exit");
   plan->exit_every = check_every;
   plan->exit_tol = tol;
   return SF_OK;

@@ -901,6 +901,7 @@ __global__ __launch_bounds__(NT) void fwd3_kernel(FwdArgs A) {
   float* xcur = L.xb[0];
   float* xnext = L.xb[1];
   float dzsq = 0.f;
+  int ran = A.L;
   for (int l = 0; l < A.L; ++l) {
     if (A.save && (l % A.ckpt_every) == 0) {
       float* ck = A.ws_ckpt + (size_t)(l / A.ckpt_every) * 2 * St + P.coef_off;
@@ -909,10 +910,24 @@ __global__ __launch_bounds__(NT) void fwd3_kernel(FwdArgs A) {
         ck[St + t] = L.lam[t];
       }
     }
-    iterate3<NT>(A, P, L, xcur, xnext, l == A.L - 1, dzsq);
+    // early exit: at a check iteration, the residual of xi_bar^l decides
+    // whether this iteration is the problem's last (sums in a fixed order,
+    // the same value in every thread)
+    bool stop = false;
+    if (A.check_every > 0 && (l % A.check_every) == 0) {
+      float v[3] = {0.f, 0.f, 0.f};
+      sweep3_any<NT, kFinal>(A, P, L, xcur, v[0], v[1]);
+      block_sum3<NT>(v, L.red);
+      stop = sqrtf(v[0] + v[1]) <= A.tol;
+    }
+    iterate3<NT>(A, P, L, xcur, xnext, stop || l == A.L - 1, dzsq);
     float* tmp = xcur;
     xcur = xnext;
     xnext = tmp;
+    if (stop) {
+      ran = l + 1;
+      break;
+    }
   }
 
   // residual of the returned iterate, outputs, status
@@ -934,11 +949,11 @@ __global__ __launch_bounds__(NT) void fwd3_kernel(FwdArgs A) {
   float dz[3] = {dzsq, 0.f, 0.f};
   block_sum3<NT>(dz, L.red);
   if (tid == 0) {
-    A.ws_iters[b] = A.L;
+    A.ws_iters[b] = ran;
     float* res = A.residual + (size_t)b * 4;
     res[0] = sqrtf(v[0]);
     res[1] = sqrtf(v[1]);
-    res[2] = A.L > 0 ? sqrtf(dz[0]) : 0.f;
+    res[2] = ran > 0 ? sqrtf(dz[0]) : 0.f;
     res[3] = (v[2] > 0.f || !isfinite(v[0]) || !isfinite(v[1])) ? 1.f : 0.f;
   }
 }
@@ -1167,7 +1182,7 @@ __global__ __launch_bounds__(NT) void bwd3_kernel(BwdArgs A, int Tv) {
     __syncthreads();
   }
 
-  const int L_ = A.L, k = A.ckpt_every;
+  const int L_ = A.iters ? A.iters[b] : A.L, k = A.ckpt_every;   // each problem's own chain
   const int nseg = (L_ + k - 1) / k;
   float dz = 0.f;
   for (int seg = nseg - 1; seg >= 0; --seg) {

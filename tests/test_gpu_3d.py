@@ -182,8 +182,6 @@ def test_3d_unsupported_calls_fail_loudly(gpu):
     for kw in (dict(save=True), dict(plain=True), dict(unfused=True)):
         with pytest.raises(SFError):
             plan.project(*args, **kw)
-    with pytest.raises(SFError):
-        plan.set_early_exit(1e-3, 10)
     with pytest.raises(SFError) as e:
         plan.backward(t["xi0"], None, None)
     assert e.value.code == -4
@@ -423,3 +421,99 @@ def test_3d_adjoint_candidate_lists_give_the_same_bits(gpu, case):
     on = _bits(probs, 24, True, grad=grad)
     off = _bits(probs, 24, False, grad=grad)
     _same_bits(on, off)
+
+
+# ------------------------------------------------------------ 3D early exit
+def _oracle_early_exit3(inp, L, tol, every, rel_margin=1e-3):
+    """The 3D oracle under the rule of sf_set_early_exit: at every iteration l
+    that is a multiple of `every`, if the residual of xi_bar^l is <= tol,
+    iteration l is completed and the run stops.  Returns (iterations run,
+    xi_bar, lambda, near) with `near` set when a tested residual lies within
+    rel_margin of tol (FP32 may then decide otherwise)."""
+    orc = _oracle(inp)
+    xi = orc.flat(inp["xi"])
+    xib, lam = orc.flat(inp["xi0"]).copy(), orc.flat(inp["lam0"]).copy()
+    near = False
+    for l in range(L):
+        stop = False
+        if l % every == 0:
+            res = orc.residual_of(xib)
+            near = near or abs(res - tol) <= rel_margin * tol
+            stop = res <= tol
+        xib, lam, _, _ = orc.step(xi, xib, lam)
+        if stop:
+            return l + 1, orc.shaped(xib), orc.shaped(lam), near
+    return L, orc.shaped(xib), orc.shaped(lam), near
+
+
+def _early3(probs, L, tol, every, save=False, ckpt=1):
+    import torch
+    pk = pack3d(probs)
+    plan = _plan(pk, max_iters=L if save else 0, ckpt=ckpt)
+    plan.set_early_exit(tol, every)
+    t = {k: torch.from_numpy(getattr(pk, k)).cuda() for k in ("xi", "xi0", "lam0",
+                                                               "boundary", "obstacles")}
+    xo, lo, res = plan.project(t["xi"], t["xi0"], t["lam0"], t["boundary"], t["obstacles"], L,
+                               save=save)
+    its = plan.iterations()
+    torch.cuda.synchronize()
+    return plan, pk, xo.cpu().numpy(), lo.cpu().numpy(), res.cpu().numpy(), its.cpu().numpy()
+
+
+def test_3d_early_exit_matches_oracle_rule(gpu):
+    """Per-problem early exit on 3D plans: the iteration counts, outputs and
+    residual rows against the oracle run under the same rule."""
+    from sf_testlib import REL_TOL, lam_err
+    probs = make_batch3d(WORKLOADS_3D[16], batch=4)
+    L, tol, every = 200, 2e-2, 10
+    _, pk, xo, lo, res, its = _early3(probs, L, tol, every)
+    gx, gl = unpack3d(xo, probs), unpack3d(lo, probs)
+    stopped, checked = 0, 0
+    for b, inp in enumerate(_inputs3d(pk, probs)):
+        n_ref, xb_ref, lam_ref, near = _oracle_early_exit3(inp, L, tol, every)
+        print(f"[early3d] problem {b}: GPU {its[b]} iterations, oracle {n_ref}"
+              f"{' (near tol)' if near else ''}", flush=True)
+        if near:
+            continue
+        checked += 1
+        assert its[b] == n_ref, (b, its[b], n_ref)
+        stopped += n_ref < L
+        assert rel_err(gx[b], xb_ref) <= REL_TOL, b
+        assert lam_err(gl[b], lam_ref) <= REL_TOL, b
+        r1, r2 = _oracle(inp).residual_terms(_oracle(inp).flat(gx[b]))[:2]
+        assert abs(res[b, 0] - np.linalg.norm(r1)) <= 1e-5 + 1e-5 * np.linalg.norm(r1)
+        assert abs(res[b, 1] - np.linalg.norm(r2)) <= 1e-5 + 1e-5 * np.linalg.norm(r2)
+        assert res[b, 3] == 0.0
+    assert checked >= 2 and stopped >= 1, (checked, stopped)
+    # a tolerance every iterate meets: each problem runs exactly one iteration
+    assert (_early3(probs, 40, 1e9, 7)[5] == 1).all()
+
+
+def test_3d_adjoint_follows_each_problems_own_chain(gpu):
+    import torch
+    from oracle import SFAdjoint
+    from sf_testlib import GRAD_REL_TOL
+    cfg = scaled3d(WORKLOADS_3D[16], n_robots=(5, 5), n_obs=(3, 3), side=3.0, height=1.6)
+    probs = make_batch3d(cfg, batch=4)
+    L, tol, every = 60, 3e-2, 4
+    plan, pk, xo, lo, res, its = _early3(probs, L, tol, every, save=True, ckpt=3)
+    rng = np.random.default_rng(17)
+    g_xi = [rng.standard_normal(p.xi.shape) for p in probs]
+    g_lam = [rng.standard_normal(p.xi.shape) for p in probs]
+    dev = lambda gs: torch.from_numpy(np.concatenate([g.ravel() for g in gs])
+                                      .astype(np.float32)).cuda()
+    grads = plan.backward(dev(g_xi), dev(g_lam), None, 0.05)
+    torch.cuda.synchronize()
+    grads = [unpack3d(g.cpu().numpy(), probs) for g in grads]
+    print(f"[early3d] iterations {its.tolist()}", flush=True)
+    assert len(set(its.tolist())) >= 2, its   # problems stopped at different iterations
+    for b, inp in enumerate(_inputs3d(pk, probs)):
+        n_ref, _, _, near = _oracle_early_exit3(inp, L, tol, every)
+        assert near or its[b] == n_ref, (b, its[b], n_ref)
+        ref = SFAdjoint(_oracle(inp)).gradient(
+            inp["xi"], inp["xi0"], inp["lam0"], int(its[b]),
+            g_xi[b].astype(np.float32).astype(np.float64),
+            g_lam[b].astype(np.float32).astype(np.float64), 0.0, 0.0, 0.05)
+        for name, gv, rv in (("xi", grads[0][b], ref.g_xi), ("xi0", grads[1][b], ref.g_xi0),
+                             ("lam0", grads[2][b], ref.g_lam0)):
+            assert rel_err(gv, rv) <= GRAD_REL_TOL, (b, name)
