@@ -468,8 +468,31 @@ def spheroid_3d_timing(dev, steps=5):
                             roofline=roofline_of(
                                 "fwd3_kernel", algorithmic_flops3d(probs, pk.n_steps, pk.n_coef, L),
                                 ms))
-    # forward + adjoint at the workload's iteration count, every iterate kept
+    # the plain per-problem forward (each stage its own launch, the state in
+    # the workspace) on the first two problems, one launch group each
     L = cfg.iters
+    sub = probs[:2]
+    spk = pack3d(sub)
+    splan = SFPlan(spk.n_robots, spk.n_obs, spk.robot_ab, spk.box, spk.n_coef, spk.n_steps, RHO,
+                   n_dim=3, device=dev)
+    st = {k: torch.from_numpy(getattr(spk, k)).to(dev) for k in ("xi", "xi0", "lam0",
+                                                                  "boundary", "obstacles")}
+    sargs = (st["xi"], st["xi0"], st["lam0"], st["boundary"], st["obstacles"])
+    splan.project(*sargs, 1, plain=True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    splan.project(*sargs, L, plain=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1)
+    splan.close()
+    plain_rate = len(sub) / (plain_ms / 1e3)
+    out["plain"] = dict(sample=f"first {len(sub)} problems, {L} iterations, one launch group each",
+                        ms=round(plain_ms, 4), fwd_problems_per_s=round(plain_rate, 2),
+                        batched_over_plain_fwd=round(out[f"L{L}"]["problems_per_s"] / plain_rate,
+                                                     2))
+    # forward + adjoint at the workload's iteration count, every iterate kept
     planb = SFPlan(pk.n_robots, pk.n_obs, pk.robot_ab, pk.box, pk.n_coef, pk.n_steps, RHO,
                    n_dim=3, max_iters=L, checkpoint_every=1, device=dev)
     args = (t["xi"], t["xi0"], t["lam0"], t["boundary"], t["obstacles"], L)

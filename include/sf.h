@@ -40,9 +40,11 @@
  * of Delta.  For n_dim = 3, sf_project (SF_SAVE_FOR_BACKWARD, SF_GRAPH,
  * obstacle motion and early exit included) and sf_project_backward run; the
  * adjoint chains through the same alpha, beta and d steps, with the Jacobian
- * of r_1 = (1 - 1/s) Delta on active rows (identity at Delta = 0).  SF_PLAIN,
- * SF_UNFUSED and sf_smoothness return SF_ERR_INVALID_ARG.  Each workgroup
- * visits the candidate partners and obstacles of each robot
+ * of r_1 = (1 - 1/s) Delta on active rows (identity at Delta = 0).  SF_PLAIN
+ * and SF_UNFUSED run the forward's stages as separate launches (prep; per
+ * iteration the constraint sweep and the update; the final pass) with the
+ * same bits; sf_smoothness returns SF_ERR_INVALID_ARG.  Each workgroup visits
+ * the candidate partners and obstacles of each robot
  * (sf_set_candidate_lists).
  *
  * Ownership: the caller allocates every array and the workspace; the library
@@ -252,7 +254,8 @@ int64_t sf_forward_generation(const sf_plan_t* plan);
  *
  *   tol          >= 0, finite (metres).
  *   check_every  0 turns early exit off (the default); otherwise >= 1.
- * Not available with SF_PLAIN (sf_project then fails with SF_ERR_INVALID_ARG).
+ * Not available with SF_PLAIN or SF_UNFUSED (sf_project then fails with
+ * SF_ERR_INVALID_ARG).
  */
 int sf_set_early_exit(sf_plan_t* plan, float tol, int32_t check_every);
 

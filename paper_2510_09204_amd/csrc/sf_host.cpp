@@ -729,9 +729,6 @@ int sf_project(sf_plan_t* plan, void* workspace, const float* xi, const float* x
   if (xi_out == xi || xi_out == xi0 || lam_out == lam0 || xi_out == lam_out)
     return fail(SF_ERR_INVALID_ARG, "outputs must not alias inputs");
   const bool dim3 = plan->cfg.n_dim == 3;
-  if (dim3 && (flags & (SF_PLAIN | SF_UNFUSED)))
-    return fail(SF_ERR_INVALID_ARG, "n_dim = 3 runs the fused kernels only (no SF_PLAIN, "
-                                    "SF_UNFUSED)");
   hipStream_t s = static_cast<hipStream_t>(stream);
   plan->saved = false;
   ++plan->generation;
@@ -752,7 +749,14 @@ int sf_project(sf_plan_t* plan, void* workspace, const float* xi, const float* x
     pb.cxi = plan->at<float>(plan->off_pcxi);
     pb.red = plan->at<float>(plan->off_red);
     pb.part = plan->at<float>(plan->off_part);
-    if (unfused) {
+    if (dim3) {
+      if (unfused) {
+        SF_HIP_CHECK(sf::launch_plain3(a, pb, -1, plan->lds_fwd, s));
+      } else {
+        for (int b = 0; b < plan->B; ++b)
+          SF_HIP_CHECK(sf::launch_plain3(a, pb, b, plan->lds_fwd, s));
+      }
+    } else if (unfused) {
       SF_HIP_CHECK(sf::launch_plain_problem(a, pb, -1, s));
     } else {
       for (int b = 0; b < plan->B; ++b) SF_HIP_CHECK(sf::launch_plain_problem(a, pb, b, s));

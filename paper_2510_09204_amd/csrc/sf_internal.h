@@ -153,6 +153,10 @@ hipError_t launch_fwd3(const FwdArgs& a, int threads, size_t lds, hipStream_t s)
 size_t bwd3_lds_bytes(int nc, int T, int Tc, int Tv, int n_max, int M_max, int S_max,
                       bool lists);
 hipError_t launch_bwd3(const BwdArgs& a, int threads, size_t lds, int Tv, hipStream_t s);
+// 3D plain path: the forward's stages as separate launches (state in pb:
+// xb[2], lam, cxi, R, red), problem b alone (b >= 0) or the batch (b < 0).
+hipError_t launch_plain3(const FwdArgs& a, const PlainBufs& pb, int b, size_t lds,
+                         hipStream_t s);
 
 // Candidate selection (sf_select.hip).  Batches of at most kSelectMaxBatch
 // candidates (the ranking keys live in LDS).

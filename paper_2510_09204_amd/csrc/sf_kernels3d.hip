@@ -33,6 +33,7 @@ namespace sf {
 namespace {
 
 constexpr int kRed3 = 64;          // block-reduction scratch (3 values x 16 waves)
+constexpr int kPlainThreads3 = 256;   // threads of the plain path's stage kernels
 constexpr int kObsFloats = 12;     // obstacle table entry (10 used, see the set-up)
 
 __host__ __device__ inline int r4(int x) { return (x + 3) & ~3; }
@@ -840,13 +841,54 @@ __device__ __forceinline__ void iterate3(const Args& A, const ProbDesc& P, const
   __syncthreads();
 }
 
+// The constant term c_xi = S xi + DS mean(xi) + N b + DN mean(b) per axis
+// (mode form) into L.cxi, from the target staged in L.R and the boundary
+// [n][2][3]; L.means is scratch.  Entered and left block-synchronised.
+template <int NT>
+__device__ __forceinline__ void form_cxi3(const ProbDesc& P, const Lds3& L, int nc,
+                                          const float* bnd) {
+  const int n = P.n, tid = threadIdx.x;
+  const int nn = n * nc, S = 3 * nn, nc2 = nc * nc;
+  // robot means of the target ([3][nc]) and of the boundary ([3][2])
+  for (int t = tid; t < 3 * nc + 6; t += NT) {
+    float s = 0.f;
+    if (t < 3 * nc) {
+      const int ax = t / nc, c = t - ax * nc;
+      for (int i = 0; i < n; ++i) s += L.R[ax * nn + i * nc + c];
+    } else {
+      const int q = t - 3 * nc, ax = q >> 1, e = q & 1;
+      for (int i = 0; i < n; ++i) s += bnd[i * 6 + e * 3 + ax];
+    }
+    L.means[t] = s / (float)n;
+  }
+  __syncthreads();
+  const float* Np = L.fac + 4 * nc2;
+  const float* DN = Np + 2 * nc;
+  const float* bm = L.means + 3 * nc;
+  for (int t = tid; t < S; t += NT) {
+    const int ax = t / nn, rem = t - ax * nn, i = rem / nc, c = rem - i * nc;
+    const float* Sp = L.fac + c * nc;
+    const float* DS = L.fac + nc2 + c * nc;
+    const float* y = L.R + ax * nn + i * nc;
+    const float* ym = L.means + ax * nc;
+    float out = 0.f;
+    for (int q = 0; q < nc; ++q) out = fmaf(Sp[q], y[q], fmaf(DS[q], ym[q], out));
+    for (int e = 0; e < 2; ++e) {
+      out = fmaf(Np[c * 2 + e], bnd[i * 6 + e * 3 + ax], out);
+      out = fmaf(DN[c * 2 + e], bm[ax * 2 + e], out);
+    }
+    L.cxi[t] = out;
+  }
+  __syncthreads();
+}
+
 template <int NT>
 __global__ __launch_bounds__(NT) void fwd3_kernel(FwdArgs A) {
   extern __shared__ float lds3[];
   const int b = A.order[blockIdx.x];
   const ProbDesc P = A.probs[b];
   const int n = P.n, M = P.M, nc = A.nc, tid = threadIdx.x;
-  const int nn = n * nc, S = 3 * nn, nc2 = nc * nc;
+  const int nn = n * nc, S = 3 * nn;
   const Lds3 L = carve3(lds3, nc, A.Tc, A.n_max, A.M_max, A.S_max);
   const float* bnd = A.boundary + (size_t)P.rob_off * 6;
   const size_t St = (size_t)A.S_total;
@@ -862,40 +904,9 @@ __global__ __launch_bounds__(NT) void fwd3_kernel(FwdArgs A) {
     L.R[t] = A.xi[P.coef_off + t];      // the target, until c_xi is formed
   }
   __syncthreads();
-  // robot means of the target ([3][nc]) and of the boundary ([3][2])
-  for (int t = tid; t < 3 * nc + 6; t += NT) {
-    float s = 0.f;
-    if (t < 3 * nc) {
-      const int ax = t / nc, c = t - ax * nc;
-      for (int i = 0; i < n; ++i) s += L.R[ax * nn + i * nc + c];
-    } else {
-      const int q = t - 3 * nc, ax = q >> 1, e = q & 1;
-      for (int i = 0; i < n; ++i) s += bnd[i * 6 + e * 3 + ax];
-    }
-    L.means[t] = s / (float)n;
-  }
-  __syncthreads();
-  {
-    const float* Np = L.fac + 4 * nc2;
-    const float* DN = Np + 2 * nc;
-    const float* bm = L.means + 3 * nc;
-    for (int t = tid; t < S; t += NT) {
-      const int ax = t / nn, rem = t - ax * nn, i = rem / nc, c = rem - i * nc;
-      const float* Sp = L.fac + c * nc;
-      const float* DS = L.fac + nc2 + c * nc;
-      const float* y = L.R + ax * nn + i * nc;
-      const float* ym = L.means + ax * nc;
-      float out = 0.f;
-      for (int q = 0; q < nc; ++q) out = fmaf(Sp[q], y[q], fmaf(DS[q], ym[q], out));
-      for (int e = 0; e < 2; ++e) {
-        out = fmaf(Np[c * 2 + e], bnd[i * 6 + e * 3 + ax], out);
-        out = fmaf(DN[c * 2 + e], bm[ax * 2 + e], out);
-      }
-      L.cxi[t] = out;
-      if (A.save) A.ws_cxi[P.coef_off + t] = out;
-    }
-  }
-  __syncthreads();
+  form_cxi3<NT>(P, L, nc, bnd);
+  if (A.save)
+    for (int t = tid; t < S; t += NT) A.ws_cxi[P.coef_off + t] = L.cxi[t];
 
   // ping-pong by pointer swap (an index into L.xb would put L in scratch)
   float* xcur = L.xb[0];
@@ -955,6 +966,99 @@ __global__ __launch_bounds__(NT) void fwd3_kernel(FwdArgs A) {
     res[1] = sqrtf(v[1]);
     res[2] = ran > 0 ? sqrtf(dz[0]) : 0.f;
     res[3] = (v[2] > 0.f || !isfinite(v[0]) || !isfinite(v[1])) ? 1.f : 0.f;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Plain 3D path (SF_PLAIN, SF_UNFUSED): the forward's stages as separate
+// launches with the state in the workspace between them — prep (the state and
+// c_xi), per iteration the constraint sweep (positions, rows, W^T V into R)
+// and the update (mean field, xi_bar and lambda steps), then the final pass
+// (residual of the returned iterate, outputs).  One workgroup per problem,
+// problem b0 alone (b0 >= 0) or the batch (b0 < 0, grid = B).  Each stage
+// runs the fused kernel's own code on the same LDS layout (the full sweep,
+// without candidate lists, whose rows give the same sums), so the outputs
+// carry the fused kernel's bits.
+// ---------------------------------------------------------------------------
+constexpr int kPlainPrep = 0, kPlainSweep = 1, kPlainUpdate = 2, kPlainFinal = 3;
+
+template <int NT>
+__global__ __launch_bounds__(NT) void plain3_kernel(FwdArgs A, PlainBufs pb, int b0, int stage,
+                                                    int cur, int last) {
+  extern __shared__ float lds3[];
+  const int b = b0 >= 0 ? b0 : A.order[blockIdx.x];
+  const ProbDesc P = A.probs[b];
+  const int n = P.n, nc = A.nc, tid = threadIdx.x;
+  const int S = 3 * n * nc;
+  const Lds3 L = carve3(lds3, nc, A.Tc, A.n_max, A.M_max, A.S_max);
+  const size_t off = P.coef_off;
+  float* gcur = pb.xb[cur] + off;
+  float* gnext = pb.xb[cur ^ 1] + off;
+  float* glam = pb.lam + off;
+  setup3<NT>(A, P, L, A.obstacles);
+  if (stage == kPlainPrep) {
+    for (int t = tid; t < S; t += NT) {
+      gcur[t] = A.xi0[off + t];
+      glam[t] = A.lam0[off + t];
+      L.R[t] = A.xi[off + t];   // the target, until c_xi is formed
+    }
+    __syncthreads();
+    form_cxi3<NT>(P, L, nc, A.boundary + (size_t)P.rob_off * 6);
+    for (int t = tid; t < S; t += NT) pb.cxi[off + t] = L.cxi[t];
+    if (tid == 0) pb.red[(size_t)b * 4 + 2] = 0.f;
+  } else if (stage == kPlainSweep) {
+    for (int t = tid; t < S; t += NT) L.xb[0][t] = gcur[t];
+    __syncthreads();
+    float z0 = 0.f, z1 = 0.f;
+    sweep3_any<NT, kForward>(A, P, L, L.xb[0], z0, z1);
+    for (int t = tid; t < S; t += NT) pb.R[off + t] = L.R[t];
+  } else if (stage == kPlainUpdate) {
+    for (int t = tid; t < S; t += NT) {
+      L.xb[0][t] = gcur[t];
+      L.lam[t] = glam[t];
+      L.R[t] = pb.R[off + t];
+      L.cxi[t] = pb.cxi[off + t];
+    }
+    __syncthreads();
+    mean_field3<NT>(P, L, nc, A.rho, L.xb[0]);
+    __syncthreads();
+    float dzsq = 0.f;
+    if (nc <= 16)
+      xi_step3<NT, 4>(P, L, nc, A.rho, L.xb[0], L.xb[1], last != 0, false, dzsq);
+    else
+      xi_step3<NT, 0>(P, L, nc, A.rho, L.xb[0], L.xb[1], last != 0, false, dzsq);
+    __syncthreads();
+    for (int t = tid; t < S; t += NT) {
+      gnext[t] = L.xb[1][t];
+      glam[t] = L.lam[t];
+    }
+    if (last) {
+      float dz[3] = {dzsq, 0.f, 0.f};
+      block_sum3<NT>(dz, L.red);
+      if (tid == 0) pb.red[(size_t)b * 4 + 2] = dz[0];
+    }
+  } else {
+    for (int t = tid; t < S; t += NT) L.xb[0][t] = gcur[t];
+    __syncthreads();
+    float v[3] = {0.f, 0.f, 0.f};
+    sweep3_any<NT, kFinal>(A, P, L, L.xb[0], v[0], v[1]);
+    float bad = 0.f;
+    for (int t = tid; t < S; t += NT) {
+      const float x = gcur[t], lm = glam[t];
+      A.xi_out[off + t] = x;
+      A.lam_out[off + t] = lm;
+      if (!isfinite(x) || !isfinite(lm)) bad = 1.f;
+    }
+    v[2] = bad;
+    block_sum3<NT>(v, L.red);
+    if (tid == 0) {
+      A.ws_iters[b] = A.L;
+      float* res = A.residual + (size_t)b * 4;
+      res[0] = sqrtf(v[0]);
+      res[1] = sqrtf(v[1]);
+      res[2] = A.L > 0 ? sqrtf(pb.red[(size_t)b * 4 + 2]) : 0.f;
+      res[3] = (v[2] > 0.f || !isfinite(v[0]) || !isfinite(v[1])) ? 1.f : 0.f;
+    }
   }
 }
 
@@ -1302,7 +1406,8 @@ hipError_t prepare_kernels3(size_t lds) {
                        reinterpret_cast<const void*>(&fwd3_kernel<1024>),
                        reinterpret_cast<const void*>(&bwd3_kernel<256>),
                        reinterpret_cast<const void*>(&bwd3_kernel<512>),
-                       reinterpret_cast<const void*>(&bwd3_kernel<1024>)};
+                       reinterpret_cast<const void*>(&bwd3_kernel<1024>),
+                       reinterpret_cast<const void*>(&plain3_kernel<kPlainThreads3>)};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -1325,6 +1430,26 @@ hipError_t launch_fwd3(const FwdArgs& a, int threads, size_t lds, hipStream_t s)
     default:
       return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_plain3(const FwdArgs& a, const PlainBufs& pb, int b, size_t lds,
+                         hipStream_t s) {
+  FwdArgs ap = a;
+  ap.lists3 = 0;   // the full sweep (same sums as the lists)
+  const dim3 grid(b >= 0 ? 1 : a.B), block(kPlainThreads3);
+  hipLaunchKernelGGL(plain3_kernel<kPlainThreads3>, grid, block, lds, s, ap, pb, b, kPlainPrep,
+                     0, 0);
+  int cur = 0;
+  for (int l = 0; l < a.L; ++l) {
+    hipLaunchKernelGGL(plain3_kernel<kPlainThreads3>, grid, block, lds, s, ap, pb, b,
+                       kPlainSweep, cur, 0);
+    hipLaunchKernelGGL(plain3_kernel<kPlainThreads3>, grid, block, lds, s, ap, pb, b,
+                       kPlainUpdate, cur, (int)(l == a.L - 1));
+    cur ^= 1;
+  }
+  hipLaunchKernelGGL(plain3_kernel<kPlainThreads3>, grid, block, lds, s, ap, pb, b, kPlainFinal,
+                     cur, 0);
   return hipGetLastError();
 }
 

@@ -178,10 +178,9 @@ def test_3d_unsupported_calls_fail_loudly(gpu):
     t = {k: torch.from_numpy(getattr(pk, k)).cuda() for k in ("xi", "xi0", "lam0",
                                                                "boundary", "obstacles")}
     args = (t["xi"], t["xi0"], t["lam0"], t["boundary"], t["obstacles"], 5)
-    # the per-stage baselines are planar only; saving needs max_iters >= L
-    for kw in (dict(save=True), dict(plain=True), dict(unfused=True)):
-        with pytest.raises(SFError):
-            plan.project(*args, **kw)
+    # saving needs max_iters >= L; the plain path does not save
+    with pytest.raises(SFError):
+        plan.project(*args, save=True)
     with pytest.raises(SFError) as e:
         plan.backward(t["xi0"], None, None)
     assert e.value.code == -4
@@ -517,3 +516,40 @@ def test_3d_adjoint_follows_each_problems_own_chain(gpu):
         for name, gv, rv in (("xi", grads[0][b], ref.g_xi), ("xi0", grads[1][b], ref.g_xi0),
                              ("lam0", grads[2][b], ref.g_lam0)):
             assert rel_err(gv, rv) <= GRAD_REL_TOL, (b, name)
+
+
+# --------------------------------------------------------- 3D plain path
+@pytest.mark.parametrize("case", ["uneven", "chunked64", "moving"])
+def test_3d_plain_and_unfused_paths_match_fused_bitwise(gpu, case):
+    """SF_PLAIN (one problem per launch group) and SF_UNFUSED (each stage
+    launch over the batch) run the forward's stages as separate launches with
+    the state in the workspace: the same coefficients and multipliers bit for
+    bit, and the residual norms (the final pass sums in the same fixed order);
+    ||z' - z|| is summed over a different block size, so it matches to
+    rounding."""
+    import torch
+    if case == "chunked64":
+        cfg = scaled3d(WORKLOADS_3D[32], n_robots=(64, 64), n_obs=(30, 30), side=16.0,
+                       height=8.0, n_coef=15, n_steps=120)
+        probs, L = make_batch3d(cfg, batch=1), 10
+    else:
+        probs, L = make_batch3d(WORKLOADS_3D[48], batch=5), 25
+    pk = pack3d(probs)
+    plan = _plan(pk)
+    if case == "moving":
+        disp = np.random.default_rng(48).uniform(-2.0, 2.0, (int(pk.n_obs.sum()), 3))
+        plan.set_obstacle_motion(torch.from_numpy(disp.astype(np.float32)).cuda())
+    t = {k: torch.from_numpy(getattr(pk, k)).cuda() for k in ("xi", "xi0", "lam0",
+                                                               "boundary", "obstacles")}
+    args = (t["xi"], t["xi0"], t["lam0"], t["boundary"], t["obstacles"], L)
+    runs = {}
+    for name, kw in (("fused", {}), ("plain", dict(plain=True)), ("unfused", dict(unfused=True))):
+        xo, lo, res = plan.project(*args, **kw)
+        torch.cuda.synchronize()
+        runs[name] = (xo.cpu().numpy(), lo.cpu().numpy(), res.cpu().numpy())
+    for name in ("plain", "unfused"):
+        np.testing.assert_array_equal(runs[name][0], runs["fused"][0])
+        np.testing.assert_array_equal(runs[name][1], runs["fused"][1])
+        np.testing.assert_array_equal(runs[name][2][:, [0, 1, 3]], runs["fused"][2][:, [0, 1, 3]])
+        np.testing.assert_allclose(runs[name][2][:, 2], runs["fused"][2][:, 2], rtol=1e-5,
+                                   atol=1e-7)
