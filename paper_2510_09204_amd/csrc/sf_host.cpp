@@ -390,14 +390,13 @@ int build_plan(const sf_config_t* cfg, int B, const int32_t* n_robots, const int
       const int win = sf::list_window3();
       auto len_ok = [&](int len) { return !lists || len >= T || len % win == 0; };
       auto round_win = [&](int len) { return lists && len < T ? (len + win - 1) / win * win : len; };
-      // longest VJP chunk that fits beside forward chunks of tc (the adjoint's
-      // LDS grows by 3 n_max floats per VJP step)
-      const size_t per_tv = sizeof(float) * 3 * (size_t)p->n_max;
+      // longest VJP chunk that fits beside forward chunks of tc
       auto tv_for = [&](int tc) {
-        const size_t base =
-            sf::bwd3_lds_bytes(nc, T, tc, 0, p->n_max, p->M_max, p->S_max, lists);
-        if (base > kLdsBudget) return 0;
-        int tv = (int)std::min<size_t>((size_t)tc, (kLdsBudget - base) / per_tv);
+        int tv = tc;
+        while (tv > 0 &&
+               sf::bwd3_lds_bytes(nc, T, tc, tv, p->n_max, p->M_max, p->S_max, lists) >
+                   kLdsBudget)
+          --tv;
         if (lists && tv < T) tv = tv / win * win;
         return tv;
       };

@@ -205,8 +205,8 @@ __device__ __forceinline__ Lds3 carve3(float* p, int nc, int Tc, int n_max, int 
   L.means = p; p += 6 * kMaxCoef + 8;
   L.obs = p; p += kObsFloats * M_max;
   L.red = p; p += kRed3;
-  L.X = p; p += 3 * n_max * (Tc | 1);
-  L.V = p; p += 3 * n_max * (Tc | 1);
+  L.X = p; p += r4(3 * n_max * (Tc | 1));
+  L.V = p; p += r4(3 * n_max * (Tc | 1));
   // list area (used only when the lists are on)
   L.refc = p; p += r4(S_max);
   L.lslot = reinterpret_cast<int*>(p); p += kSlots3;
@@ -214,11 +214,37 @@ __device__ __forceinline__ Lds3 carve3(float* p, int nc, int Tc, int n_max, int 
   return L;
 }
 
+// The adjoint's arrangement of the same arrays (same total): xi_bar's
+// ping-pong partner, lambda and c_xi last, after the list area (present only
+// with the lists), so that the VJP chunk's G can lie over them during a
+// reverse step (they are reloaded before a segment is recomputed).
+__device__ __forceinline__ Lds3 carve3_adj(float* p, int nc, int T, int Tc, int n_max,
+                                           int M_max, int S_max, bool lists) {
+  Lds3 L;
+  L.W = p; p += r4(Tc * nc);
+  L.fac = p; p += r4(fac_stride(nc));
+  L.xb[0] = p; p += r4(S_max);
+  L.R = p; p += r4(S_max);
+  L.means = p; p += 6 * kMaxCoef + 8;
+  L.obs = p; p += kObsFloats * M_max;
+  L.red = p; p += kRed3;
+  L.X = p; p += r4(3 * n_max * (Tc | 1));
+  L.V = p; p += r4(3 * n_max * (Tc | 1));
+  L.refc = p;
+  L.lslot = reinterpret_cast<int*>(p + r4(S_max));
+  L.mask = reinterpret_cast<unsigned*>(p + r4(S_max) + kSlots3);
+  if (lists) p += r4(list3_floats(T, n_max, M_max, S_max));
+  L.xb[1] = p; p += r4(S_max);
+  L.lam = p; p += r4(S_max);
+  L.cxi = p;
+  return L;
+}
+
 // LDS floats of the forward's layout (carve3), with or without the lists.
 __host__ __device__ inline size_t lds3_floats(int nc, int T, int Tc, int n_max, int M_max,
                                               int S_max, bool lists) {
   return (size_t)r4(Tc * nc) + r4(fac_stride(nc)) + 5 * (size_t)r4(S_max) + 6 * kMaxCoef + 8 +
-         (size_t)kObsFloats * M_max + kRed3 + 6 * (size_t)n_max * (Tc | 1) +
+         (size_t)kObsFloats * M_max + kRed3 + 2 * (size_t)r4(3 * n_max * (Tc | 1)) +
          (lists ? r4(list3_floats(T, n_max, M_max, S_max)) : 0);
 }
 
@@ -247,21 +273,20 @@ __device__ __forceinline__ bool coef_moved3(const float* x, const float* ref, in
 }
 
 // Lists of the windows of a chunk of Tce steps starting at step k0 (a
-// multiple of kWin3), from the scaled positions
-// in L.X.  Window boxes go to L.V first (written again only after the lists).
+// multiple of kWin3), from the scaled positions in L.X: list_boxes3 writes
+// the window boxes to L.V (written again only after the lists), over threads
+// t0, t0 + nt, ...; list_masks3 then ballots the masks.
 // Margins: a pair is kept when its boxes come within 1 + 2 d (both robots may
 // move by d), an obstacle when the box of the offset in the obstacle's scaling
 // comes within 1 + d (r_a, r_b) of the origin; 1e-4 (1 + magnitudes) more on
 // each covers the float rounding of the positions and of the tests, which is
 // orders of magnitude smaller.  A ballot tests two robots against 32
 // candidates at once (lane = 32 slot + jj).
-template <int NT>
-__device__ __forceinline__ void build_lists3(const ProbDesc& P, const Lds3& L, int k0, int Tce,
-                                             int Ts, float inv_Tm1, bool moving) {
-  const int n = P.n, M = P.M, tid = phase_tid(), lane = tid & 63, wave = wave_id3(tid);
-  const int nwc = (Tce + kWin3 - 1) >> kWinShift3;
+__device__ __forceinline__ void list_boxes3(const ProbDesc& P, const Lds3& L, int Tce, int Ts,
+                                            int t0, int nt) {
+  const int n = P.n, nwc = (Tce + kWin3 - 1) >> kWinShift3;
   float* box = L.V;   // [3 n][nwc] (lo, hi)
-  for (int t = tid; t < 3 * n * nwc; t += NT) {
+  for (int t = t0; t < 3 * n * nwc; t += nt) {
     const int row = t / nwc, wl = t - row * nwc;
     const float* x = L.X + row * Ts + wl * kWin3;
     const int cnt = min(kWin3, Tce - wl * kWin3);
@@ -273,53 +298,107 @@ __device__ __forceinline__ void build_lists3(const ProbDesc& P, const Lds3& L, i
     box[2 * t] = lo;
     box[2 * t + 1] = hi;
   }
-  __syncthreads();
-  const int pw = (n + 31) >> 5, mw = mask_words3(n, M), np = (n + 1) >> 1;
+}
+
+// The masks of list_boxes3's windows, one ballot job per (window, robot pair,
+// mask word) over waves w0, w0 + nw, ...
+__device__ __forceinline__ void list_masks3(const ProbDesc& P, const Lds3& L, int k0, int Tce,
+                                            float inv_Tm1, bool moving, int w0, int nw) {
+  const int n = P.n, M = P.M, lane = phase_tid() & 63;
+  const int nwc = (Tce + kWin3 - 1) >> kWinShift3;
+  const float* box = L.V;
+  const int pw = (n + 31) >> 5, mw = mask_words3(n, M), np = (n + 1) >> 1, ow = mw - pw;
   const int slot = lane >> 5, jj = lane & 31;
-  const int per_win = np * mw;
-  for (int q = wave; q < nwc * per_win; q += NT >> 6) {
-    const int wl = q / per_win, rem = q - wl * per_win, ip = rem / mw, word = rem - ip * mw;
+  // Ballot jobs (window, robot pair ip, mask word), pair words and obstacle
+  // words in loops of their own, four jobs of a wave at a time so that their
+  // box reads are in flight together.
+  auto pair_test = [&](int wl, int ip, int word) {
     const int i = 2 * ip + slot, ic = min(i, n - 1);
-    bool c = i < n;
-    if (word < pw) {
-      const int j = 32 * word + jj, jc = min(j, n - 1);
-      c = c && j < n && j != i;
+    const int j = 32 * word + jj, jc = min(j, n - 1);
+    bool c = i < n && j < n && j != i;
 #pragma unroll
-      for (int ax = 0; ax < 3; ++ax) {
-        const float* bi = box + ((ax * n + ic) * nwc + wl) * 2;
-        const float* bj = box + ((ax * n + jc) * nwc + wl) * 2;
-        const float mag =
-            fmaxf(fmaxf(fabsf(bi[0]), fabsf(bi[1])), fmaxf(fabsf(bj[0]), fabsf(bj[1])));
-        const float thr = 1.f + 2.f * kSkin3 + 1e-4f * (1.f + mag);
-        c = c && (bi[0] - bj[1] < thr) && (bj[0] - bi[1] < thr);
-      }
-    } else {
-      const int mo = 32 * (word - pw) + jj;
-      const float* o = L.obs + min(mo, M - 1) * kObsFloats;
-      c = c && mo < M;
-      // the obstacle's centre term is monotone in the step, so its range over
-      // the window is that of the window's first and last steps
-      const float ta = (float)(k0 + wl * kWin3) * inv_Tm1;
-      const float tb = (float)(k0 + min(wl * kWin3 + kWin3 - 1, Tce - 1)) * inv_Tm1;
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) {
-        const float* bi = box + ((ax * n + ic) * nwc + wl) * 2;
-        const float ca = moving ? fmaf(o[7 + ax], ta, o[2 + ax]) : o[2 + ax];
-        const float cb = moving ? fmaf(o[7 + ax], tb, o[2 + ax]) : o[2 + ax];
-        const float r = ax < 2 ? o[0] : o[1];
-        const float elo = fmaf(bi[0], r, fminf(ca, cb)), ehi = fmaf(bi[1], r, fmaxf(ca, cb));
-        const float sl = fmaf(r, kSkin3, 1e-4f * (1.f + fabsf(elo) + fabsf(ehi) +
-                                                   r * (fabsf(bi[0]) + fabsf(bi[1]))));
-        c = c && (elo - sl < 1.f) && (ehi + sl > -1.f);
-      }
+    for (int ax = 0; ax < 3; ++ax) {
+      const float* bi = box + ((ax * n + ic) * nwc + wl) * 2;
+      const float* bj = box + ((ax * n + jc) * nwc + wl) * 2;
+      const float mag =
+          fmaxf(fmaxf(fabsf(bi[0]), fabsf(bi[1])), fmaxf(fabsf(bj[0]), fabsf(bj[1])));
+      const float thr = 1.f + 2.f * kSkin3 + 1e-4f * (1.f + mag);
+      c = c && (bi[0] - bj[1] < thr) && (bj[0] - bi[1] < thr);
     }
+    return c;
+  };
+  auto obstacle_test = [&](int wl, int ip, int w) {
+    const int i = 2 * ip + slot, ic = min(i, n - 1);
+    const int mo = 32 * w + jj;
+    const float* o = L.obs + min(mo, M - 1) * kObsFloats;
+    bool c = i < n && mo < M;
+    // the obstacle's centre term is monotone in the step, so its range over
+    // the window is that of the window's first and last steps
+    const float ta = (float)(k0 + wl * kWin3) * inv_Tm1;
+    const float tb = (float)(k0 + min(wl * kWin3 + kWin3 - 1, Tce - 1)) * inv_Tm1;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const float* bi = box + ((ax * n + ic) * nwc + wl) * 2;
+      const float ca = moving ? fmaf(o[7 + ax], ta, o[2 + ax]) : o[2 + ax];
+      const float cb = moving ? fmaf(o[7 + ax], tb, o[2 + ax]) : o[2 + ax];
+      const float r = ax < 2 ? o[0] : o[1];
+      const float elo = fmaf(bi[0], r, fminf(ca, cb)), ehi = fmaf(bi[1], r, fmaxf(ca, cb));
+      const float sl = fmaf(r, kSkin3, 1e-4f * (1.f + fabsf(elo) + fabsf(ehi) +
+                                                 r * (fabsf(bi[0]) + fabsf(bi[1]))));
+      c = c && (elo - sl < 1.f) && (ehi + sl > -1.f);
+    }
+    return c;
+  };
+  auto put = [&](bool c, bool valid, int wl, int ip, int word) {
     const unsigned long long bal = __builtin_amdgcn_ballot_w64(c);
-    if (lane == 0) {
+    if (valid && lane == 0) {
       unsigned* mk = L.mask + ((size_t)((k0 >> kWinShift3) + wl) * n + 2 * ip) * mw + word;
       mk[0] = (unsigned)bal;
       if (2 * ip + 1 < n) mk[mw] = (unsigned)(bal >> 32);
     }
+  };
+  constexpr int U = 4;
+  const int pair_jobs = nwc * np * pw, obs_jobs = nwc * np * ow;
+  for (int q0 = w0; q0 < pair_jobs; q0 += U * nw) {
+    bool c[U];
+    int wl[U], ip[U], wd[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = min(q0 + u * nw, pair_jobs - 1), per = np * pw;
+      wl[u] = q / per;
+      const int rem = q - wl[u] * per;
+      ip[u] = rem / pw;
+      wd[u] = rem - ip[u] * pw;
+      c[u] = pair_test(wl[u], ip[u], wd[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) put(c[u], q0 + u * nw < pair_jobs, wl[u], ip[u], wd[u]);
   }
+  for (int q0 = w0; q0 < obs_jobs; q0 += U * nw) {
+    bool c[U];
+    int wl[U], ip[U], wd[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = min(q0 + u * nw, obs_jobs - 1), per = np * ow;
+      wl[u] = q / per;
+      const int rem = q - wl[u] * per;
+      ip[u] = rem / ow;
+      wd[u] = rem - ip[u] * ow;
+      c[u] = obstacle_test(wl[u], ip[u], wd[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) put(c[u], q0 + u * nw < obs_jobs, wl[u], ip[u], pw + wd[u]);
+  }
+}
+
+// Both passes over the block, each ending at a barrier.
+template <int NT>
+__device__ __forceinline__ void build_lists3(const ProbDesc& P, const Lds3& L, int k0, int Tce,
+                                             int Ts, float inv_Tm1, bool moving) {
+  const int tid = phase_tid();
+  list_boxes3(P, L, Tce, Ts, tid, NT);
+  __syncthreads();
+  list_masks3(P, L, k0, Tce, inv_Tm1, moving, wave_id3(tid), NT >> 6);
   __syncthreads();
 }
 
@@ -1078,20 +1157,28 @@ __global__ __launch_bounds__(NT) void plain3_kernel(FwdArgs A, PlainBufs pb, int
 // I at Delta = 0, 0 on inactive rows), over time chunks of Tv steps.
 // ---------------------------------------------------------------------------
 
-// Extra LDS of the adjoint after the forward's layout: cotangents g (two,
-// ping-pong), g_lambda, g_xi, g_R, and G = W g_R over a VJP chunk [3][n][Tv].
+// LDS of the adjoint beyond the forward's arrays (carve3_adj): G = W g_R over
+// a VJP chunk [3][n][Tv], laid from xi_bar's ping-pong partner on (over lambda
+// and c_xi, which a reverse step does not use), then the cotangents g (two,
+// ping-pong), g_lambda, g_xi and g_R.
 struct Lds3b {
   float *gA, *gB, *glam, *gxi, *gR, *G;
 };
 
-__device__ __forceinline__ Lds3b carve3b(float* p, int S_max) {
+__host__ __device__ inline size_t g_area3(int n_max, int Tv, int S_max) {
+  const size_t g = r4(3 * n_max * (Tv | 1)), tail = 3 * (size_t)r4(S_max);
+  return g > tail ? g : tail;
+}
+
+__device__ __forceinline__ Lds3b carve3b(const Lds3& L, int n_max, int Tv, int S_max) {
   Lds3b B;
+  float* p = L.xb[1];
+  B.G = p; p += g_area3(n_max, Tv, S_max);
   B.gA = p; p += r4(S_max);
   B.gB = p; p += r4(S_max);
   B.glam = p; p += r4(S_max);
   B.gxi = p; p += r4(S_max);
-  B.gR = p; p += r4(S_max);
-  B.G = p;
+  B.gR = p;
   return B;
 }
 
@@ -1132,10 +1219,13 @@ __device__ __forceinline__ void obstacle_vjp3(const float* o, float tau, bool mo
 }
 
 // VJP sweep over the horizon in chunks of Tv steps: X = W xb (scaled), G = W
-// gR, H = VJP (stored in L.V as [3][n][Tv]), R = W^T H (into L.R).
+// gR, H = VJP (stored in L.V as [3][n][Tv]), R = W^T H (into L.R).  With
+// `premapped` (one chunk, Tv >= T) the caller has mapped X and, for a list
+// rebuild, written the window boxes already.
 template <int NT, int kRob>
 __device__ __forceinline__ void vjp3(const BwdArgs& A, const ProbDesc& P, const Lds3& L,
-                                     const Lds3b& B, const float* xb, int Tv) {
+                                     const Lds3b& B, const float* xb, int Tv, bool rebuild,
+                                     bool premapped) {
   const int n = P.n, M = P.M, nc = A.nc, T = A.T, Tc = A.Tc, tid = phase_tid();
   const bool chunked = Tc < T;
   const float inv_a = 1.f / P.a, inv_b = 1.f / P.b;
@@ -1143,7 +1233,6 @@ __device__ __forceinline__ void vjp3(const BwdArgs& A, const ProbDesc& P, const 
   const bool moving = A.ovel != nullptr;
   const int wave = wave_id3(tid);
   const bool lists = A.lists3 != 0;
-  const bool rebuild = lists && lists_moved3(L.lslot, NT >> 6);
   if (rebuild)
     for (int t = tid; t < 3 * n * nc; t += NT) L.refc[t] = xb[t];
   const int pw = (n + 31) >> 5, mw = mask_words3(n, M);
@@ -1156,13 +1245,24 @@ __device__ __forceinline__ void vjp3(const BwdArgs& A, const ProbDesc& P, const 
       __syncthreads();
     }
     const float* Wc = chunked ? L.W : L.W + k0 * nc;
-    // X (scaled as in the forward) and G = W g_R, the forward's position tiles
-    map_tiles3_any(Wc, nc, 3 * n, Ts, Tce, xb, L.X, inv_a, inv_b, 2 * n, B.gR, B.G, 2, wave,
-                   NT >> 6);
-    __syncthreads();
-    if (lists && rebuild) {
-      if (k0 == 0 && tid < kSlots3) L.lslot[tid] = 0;   // every thread has read the flags
-      build_lists3<NT>(P, L, k0, Tce, Ts, inv_Tm1, moving);
+    if (premapped) {
+      // G = W g_R, then the list masks from the boxes
+      map_tiles3_any(Wc, nc, 3 * n, Ts, Tce, B.gR, B.G, 1.f, 1.f, 0, nullptr, nullptr, 1, wave,
+                     NT >> 6);
+      if (rebuild) {
+        if (tid < kSlots3) L.lslot[tid] = 0;   // every thread has read the flags
+        list_masks3(P, L, k0, Tce, inv_Tm1, moving, wave, NT >> 6);
+      }
+      __syncthreads();
+    } else {
+      // X (scaled as in the forward) and G = W g_R, the forward's position tiles
+      map_tiles3_any(Wc, nc, 3 * n, Ts, Tce, xb, L.X, inv_a, inv_b, 2 * n, B.gR, B.G, 2, wave,
+                     NT >> 6);
+      __syncthreads();
+      if (rebuild) {
+        if (k0 == 0 && tid < kSlots3) L.lslot[tid] = 0;   // every thread has read the flags
+        build_lists3<NT>(P, L, k0, Tce, Ts, inv_Tm1, moving);
+      }
     }
     const int plane = n * Ts;
     const int ngrp = (n + kRob - 1) / kRob;
@@ -1240,26 +1340,134 @@ __device__ __forceinline__ void vjp3(const BwdArgs& A, const ProbDesc& P, const 
   }
 }
 
+// Robot means per (axis, coefficient) of the coefficient array g (into
+// L.means[ax nc + q]), one axis per wave, lanes as in mean_field3.
+// Axes w0, w0 + nw, ... of this wave.
+__device__ __forceinline__ void robot_means3(const ProbDesc& P, const Lds3& L, int nc,
+                                             const float* g, int w0, int nw) {
+  const int n = P.n, nn = n * nc, lane = phase_tid() & 63;
+  const int QW = nc <= 16 ? 16 : 32, Pw = 64 / QW;
+  const int q = lane % QW, p = lane / QW, qq = min(q, nc - 1);
+  for (int ax = w0; ax < 3; ax += nw) {
+    const float* ga = g + ax * nn + qq;
+    float s0 = 0.f, s1 = 0.f;
+    int i = p;
+    for (; i + Pw < n; i += 2 * Pw) {
+      s0 += ga[i * nc];
+      s1 += ga[(i + Pw) * nc];
+    }
+    if (i < n) s0 += ga[i * nc];
+    float sm = s0 + s1;
+    for (int o = QW; o < 64; o <<= 1) sm += __shfl_xor(sm, o, 64);
+    if (p == 0 && q < nc) L.means[ax * nc + q] = sm / (float)n;
+  }
+}
+
+// The transposed xi_bar step of the adjoint on MFMA 16x16x4 tiles, one wave
+// per tile of 16 rows (row = axis * n + robot; tiles w0, w0 + nw, ...) and
+// every coefficient column tile: for the cotangent g of xi_bar^{l+1} with robot means gm (L.means),
+//   g_u[row][q] = sum_c (g[row][c] S[c][q]  + gm[axis][c] DS[c][q])
+//   g_x[row][q] = sum_c (g[row][c] SH[c][q] + gm[axis][c] DSH[c][q])
+// (A[m][k] = g[16 rt + m][4 s + k'], B[k][m] = S[4 s + k'][16 ct + m]; steps
+// past nc add exact zeros).  The tile's lanes then form, for their own
+// entries, the cotangent of R (through u = lambda - 2 rho R and lambda' =
+// lambda - rho R), of lambda^l and of the target, and g_x into gn, with the
+// fixed-point terms of weight fw (xi_bar and lambda of steps l, l + 1 at cur
+// and nxt, lambda St floats after xi_bar).
+template <int KS>
+__device__ __forceinline__ void adj_step3(const ProbDesc& P, const Lds3& L, const Lds3b& B,
+                                          int nc, float rho, float fw, const float* g, float* gn,
+                                          const float* cur, const float* nxt, size_t St, int w0,
+                                          int nw) {
+  const int n = P.n, nc2 = nc * nc, rows = 3 * n;
+  const int lane = phase_tid() & 63, m = lane & 15, kq = lane >> 4;
+  const int nrt = (rows + 15) >> 4, nct = (nc + 15) >> 4;
+  for (int rt = w0; rt < nrt; rt += nw) {
+    const int rowA = min(rt * 16 + m, rows - 1), axA = rowA / n;
+    floatx4 acc[2][2];
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) acc[ct][0] = acc[ct][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const int ksteps = KS > 0 ? KS : (nc + 3) >> 2;
+#pragma unroll
+    for (int g0 = 0; g0 < ksteps; g0 += (KS > 0 ? 4 : 1)) {
+      constexpr int KG = KS == 0 ? 1 : (KS < 4 ? KS : 4);
+      float ag[KG], agm[KG];
+#pragma unroll
+      for (int e = 0; e < KG; ++e) {
+        const int q = 4 * (g0 + e) + kq, qq = min(q, nc - 1);
+        const bool ok = g0 + e < ksteps && q < nc;
+        const float gv = g[rowA * nc + qq], gmv = L.means[axA * nc + qq];
+        ag[e] = ok ? gv : 0.f;
+        agm[e] = ok ? gmv : 0.f;
+      }
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) {
+        if (ct >= nct) continue;
+        const int col = min(ct * 16 + m, nc - 1);
+        float bs[KG], bds[KG], bsh[KG], bdsh[KG];
+#pragma unroll
+        for (int e = 0; e < KG; ++e) {
+          const float* Sc = L.fac + min(4 * (g0 + e) + kq, nc - 1) * nc + col;
+          bs[e] = Sc[0];
+          bds[e] = Sc[nc2];
+          bsh[e] = Sc[2 * nc2];
+          bdsh[e] = Sc[3 * nc2];
+        }
+        reads_first();
+#pragma unroll
+        for (int e = 0; e < KG; ++e) {
+          acc[ct][0] = mfma_16x16x4(ag[e], bs[e], acc[ct][0]);
+          acc[ct][1] = mfma_16x16x4(ag[e], bsh[e], acc[ct][1]);
+        }
+#pragma unroll
+        for (int e = 0; e < KG; ++e) {
+          acc[ct][0] = mfma_16x16x4(agm[e], bds[e], acc[ct][0]);
+          acc[ct][1] = mfma_16x16x4(agm[e], bdsh[e], acc[ct][1]);
+        }
+      }
+    }
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      const int c = ct * 16 + m;
+      if (ct >= nct || c >= nc) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = rt * 16 + 4 * kq + v;
+        if (row >= rows) continue;
+        const int e = row * nc + c;
+        const float gu = acc[ct][0][v];
+        const float dxi = fw != 0.f ? nxt[e] - cur[e] : 0.f;
+        const float dla = fw != 0.f ? nxt[St + e] - cur[St + e] : 0.f;
+        const float gl = B.glam[e];
+        B.gR[e] = fmaf(-2.f * rho, gu, fmaf(-rho, gl, -2.f * rho * fw * dla));
+        B.glam[e] = gl + gu;
+        B.gxi[e] += gu;
+        gn[e] = fmaf(-2.f * fw, dxi, acc[ct][1][v]);
+      }
+    }
+  }
+}
+
 template <int NT>
 __global__ __launch_bounds__(NT) void bwd3_kernel(BwdArgs A, int Tv) {
   extern __shared__ float lds3[];
   const int b = A.order[blockIdx.x];
   const ProbDesc P = A.probs[b];
   const int n = P.n, nc = A.nc, tid = threadIdx.x;
-  const int nn = n * nc, S = 3 * nn, nc2 = nc * nc;
-  const Lds3 L = carve3(lds3, nc, A.Tc, A.n_max, A.M_max, A.S_max);
-  const Lds3b B = carve3b(
-      lds3 + lds3_floats(nc, A.T, A.Tc, A.n_max, A.M_max, A.S_max, A.lists3 != 0), A.S_max);
+  const int nn = n * nc, S = 3 * nn;
+  const Lds3 L = carve3_adj(lds3, nc, A.T, A.Tc, A.n_max, A.M_max, A.S_max, A.lists3 != 0);
+  const Lds3b B = carve3b(L, A.n_max, Tv, A.S_max);
   const float rho = A.rho, fw = A.fp_weight;
   const size_t St = (size_t)A.S_total;
   const int rpt = robots_per_thread(n);
   const bool lists = A.lists3 != 0;
   const float ska = kSkin3 * P.a, skb = kSkin3 * P.b;
+  const int T = A.T, NW = NT >> 6, wave = wave_id3(tid);
+  const bool whole = Tv >= T;   // one VJP chunk
 
   setup3<NT>(A, P, L, A.obs);
   if (lists) reset_lists3<NT>(L.refc, L.lslot, S);
   for (int t = tid; t < S; t += NT) {
-    L.cxi[t] = A.cxi[P.coef_off + t];
     B.gA[t] = A.g_xi_out ? A.g_xi_out[P.coef_off + t] : 0.f;
     B.glam[t] = A.g_lam_out ? A.g_lam_out[P.coef_off + t] : 0.f;
     B.gxi[t] = 0.f;
@@ -1301,6 +1509,7 @@ __global__ __launch_bounds__(NT) void bwd3_kernel(BwdArgs A, int Tv) {
       for (int t = tid; t < S; t += NT) {
         xc[t] = ck[t];
         L.lam[t] = ck[St + t];
+        L.cxi[t] = A.cxi[P.coef_off + t];
         if (lists) moved |= coef_moved3(xc, L.refc, t, nn, ska, skb);
       }
       if (lists) note_moved3(moved, L.lslot);
@@ -1333,45 +1542,44 @@ __global__ __launch_bounds__(NT) void bwd3_kernel(BwdArgs A, int Tv) {
       }
       if (lists) note_moved3(moved, L.lslot);
       __syncthreads();
-      // robot means of g: means[0..3nc)
-      for (int t = tid; t < 3 * nc; t += NT) {
-        const int ax = t / nc, c = t - ax * nc;
-        float sm = 0.f;
-        for (int i = 0; i < n; ++i) sm += gx[ax * nn + i * nc + c];
-        L.means[t] = sm / (float)n;
-      }
-      __syncthreads();
-      // g_u = S^T g, g_xi_bar (before the VJP) = SH^T g - 2 fw (dxi), g_R
-      for (int t = tid; t < S; t += NT) {
-        const int ax = t / nn, rem = t - ax * nn, i = rem / nc, q = rem - i * nc;
-        const float* g = gx + ax * nn + i * nc;
-        const float* gm = L.means + ax * nc;
-        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-        for (int c = 0; c < nc; ++c) {
-          const float* row = L.fac + c * nc + q;     // column q of row c
-          a0 = fmaf(row[0], g[c], a0);
-          a1 = fmaf(row[nc2], gm[c], a1);
-          a2 = fmaf(row[2 * nc2], g[c], a2);
-          a3 = fmaf(row[3 * nc2], gm[c], a3);
+      const bool rebuild = lists && lists_moved3(L.lslot, NW);
+      const int nrt = (3 * n + 15) >> 4;
+      if (whole) {
+        // the robot means of g (waves 0-2) beside the positions X = W xi_bar^l
+        // (the other waves), then the g step beside the window boxes of a
+        // list rebuild
+        if (wave < 3)
+          robot_means3(P, L, nc, gx, wave, 3);
+        else
+          map_tiles3_any(L.W, nc, 3 * n, T | 1, T, xl, L.X, 1.f / P.a, 1.f / P.b, 2 * n, nullptr,
+                         nullptr, 1, wave - 3, NW - 3);
+        __syncthreads();
+        const int wa = rebuild ? min(nrt, NW - 1) : NW;
+        if (wave < wa) {
+          if (nc <= 16)
+            adj_step3<4>(P, L, B, nc, rho, fw, gx, gn, cur, nxt, St, wave, wa);
+          else
+            adj_step3<0>(P, L, B, nc, rho, fw, gx, gn, cur, nxt, St, wave, wa);
+        } else {
+          list_boxes3(P, L, T, T | 1, tid - 64 * wa, NT - 64 * wa);
         }
-        const float gu = a0 + a1;
-        const float dxi = fw != 0.f ? nxt[t] - cur[t] : 0.f;
-        const float dla = fw != 0.f ? nxt[St + t] - cur[St + t] : 0.f;
-        const float gl = B.glam[t];
-        B.gR[t] = fmaf(-2.f * rho, gu, fmaf(-rho, gl, -2.f * rho * fw * dla));
-        B.glam[t] = gl + gu;
-        B.gxi[t] += gu;
-        gn[t] = fmaf(-2.f * fw, dxi, a2 + a3);
+      } else {
+        robot_means3(P, L, nc, gx, wave, NW);
+        __syncthreads();
+        if (nc <= 16)
+          adj_step3<4>(P, L, B, nc, rho, fw, gx, gn, cur, nxt, St, wave, NW);
+        else
+          adj_step3<0>(P, L, B, nc, rho, fw, gx, gn, cur, nxt, St, wave, NW);
       }
       __syncthreads();
       if (lists)
-        vjp3<NT, kListRob3>(A, P, L, B, xl, Tv);
+        vjp3<NT, kListRob3>(A, P, L, B, xl, Tv, rebuild, whole);
       else if (rpt == 4)
-        vjp3<NT, 4>(A, P, L, B, xl, Tv);
+        vjp3<NT, 4>(A, P, L, B, xl, Tv, false, whole);
       else if (rpt == 2)
-        vjp3<NT, 2>(A, P, L, B, xl, Tv);
+        vjp3<NT, 2>(A, P, L, B, xl, Tv, false, whole);
       else
-        vjp3<NT, 1>(A, P, L, B, xl, Tv);
+        vjp3<NT, 1>(A, P, L, B, xl, Tv, false, whole);
       for (int t = tid; t < S; t += NT) gn[t] += L.R[t];
       __syncthreads();
       float* tmp = gx;
@@ -1396,8 +1604,9 @@ size_t fwd3_lds_bytes(int nc, int T, int Tc, int n_max, int M_max, int S_max, bo
 
 size_t bwd3_lds_bytes(int nc, int T, int Tc, int Tv, int n_max, int M_max, int S_max,
                       bool lists) {
-  return (lds3_floats(nc, T, Tc, n_max, M_max, S_max, lists) + 5 * (size_t)r4(S_max) +
-          3 * (size_t)n_max * (Tv | 1)) * sizeof(float);
+  // the forward's layout up to its last three arrays, G over them, five more
+  return (lds3_floats(nc, T, Tc, n_max, M_max, S_max, lists) - 3 * (size_t)r4(S_max) +
+          g_area3(n_max, Tv, S_max) + 5 * (size_t)r4(S_max)) * sizeof(float);
 }
 
 hipError_t prepare_kernels3(size_t lds) {
