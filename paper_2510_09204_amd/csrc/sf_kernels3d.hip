@@ -167,8 +167,32 @@ __device__ __forceinline__ int robots_per_thread(int n) { return n >= 24 ? 4 : (
 // first iteration in which one does, rebuilds them.  The sweep then walks the
 // lists in increasing index: the rows it skips add exact zeros in the full
 // sweep, so both give the same bits.
+//
+// The skin only trades rebuilds against longer walks, so it follows the
+// iterates: d = 1/2 while the lists last few passes (early iterates move by
+// more than a quarter of a semi-axis per iteration), 1/4 once they served
+// sixteen passes or more, and back to 1/2 when the lists of a 1/4 skin serve a
+// single pass (measured on 32 robots: a fixed 1/2 is 11 % faster than 1/4 over
+// the first 100 iterations and 2 % slower over 1000; larger skins are slower).
+// Every thread keeps its own copy and updates it at the same block-uniform
+// points, so all agree; the lists always match the skin they were built with.
 constexpr int kSlots3 = 16;        // per-wave flags of the list check (waves of 1024 threads)
-constexpr float kSkin3 = 0.25f;    // skin d in scaled units
+constexpr float kSkinInit3 = 0.5f, kSkinMin3 = 0.25f, kSkinMax3 = 0.5f;
+struct Skin3 {
+  float d = kSkinInit3;   // skin in scaled units
+  int age = 2;            // passes served by the current lists
+  // one pass over the horizon, rebuilding or not
+  __device__ __forceinline__ void pass(bool rebuild) {
+    if (rebuild) {
+      if (age <= 1)
+        d = fminf(2.f * d, kSkinMax3);
+      else if (age >= 16)
+        d = fmaxf(0.5f * d, kSkinMin3);
+      age = 0;
+    }
+    ++age;
+  }
+};
 constexpr int kWinShift3 = 4;      // list window of 2^kWinShift3 steps
 constexpr int kWin3 = 1 << kWinShift3;
 constexpr int kListRob3 = 1;       // robots per thread of the list walk
@@ -303,7 +327,8 @@ __device__ __forceinline__ void list_boxes3(const ProbDesc& P, const Lds3& L, in
 // The masks of list_boxes3's windows, one ballot job per (window, robot pair,
 // mask word) over waves w0, w0 + nw, ...
 __device__ __forceinline__ void list_masks3(const ProbDesc& P, const Lds3& L, int k0, int Tce,
-                                            float inv_Tm1, bool moving, int w0, int nw) {
+                                            float inv_Tm1, bool moving, float d, int w0,
+                                            int nw) {
   const int n = P.n, M = P.M, lane = phase_tid() & 63;
   const int nwc = (Tce + kWin3 - 1) >> kWinShift3;
   const float* box = L.V;
@@ -322,7 +347,7 @@ __device__ __forceinline__ void list_masks3(const ProbDesc& P, const Lds3& L, in
       const float* bj = box + ((ax * n + jc) * nwc + wl) * 2;
       const float mag =
           fmaxf(fmaxf(fabsf(bi[0]), fabsf(bi[1])), fmaxf(fabsf(bj[0]), fabsf(bj[1])));
-      const float thr = 1.f + 2.f * kSkin3 + 1e-4f * (1.f + mag);
+      const float thr = 1.f + 2.f * d + 1e-4f * (1.f + mag);
       c = c && (bi[0] - bj[1] < thr) && (bj[0] - bi[1] < thr);
     }
     return c;
@@ -343,7 +368,7 @@ __device__ __forceinline__ void list_masks3(const ProbDesc& P, const Lds3& L, in
       const float cb = moving ? fmaf(o[7 + ax], tb, o[2 + ax]) : o[2 + ax];
       const float r = ax < 2 ? o[0] : o[1];
       const float elo = fmaf(bi[0], r, fminf(ca, cb)), ehi = fmaf(bi[1], r, fmaxf(ca, cb));
-      const float sl = fmaf(r, kSkin3, 1e-4f * (1.f + fabsf(elo) + fabsf(ehi) +
+      const float sl = fmaf(r, d, 1e-4f * (1.f + fabsf(elo) + fabsf(ehi) +
                                                  r * (fabsf(bi[0]) + fabsf(bi[1]))));
       c = c && (elo - sl < 1.f) && (ehi + sl > -1.f);
     }
@@ -394,11 +419,11 @@ __device__ __forceinline__ void list_masks3(const ProbDesc& P, const Lds3& L, in
 // Both passes over the block, each ending at a barrier.
 template <int NT>
 __device__ __forceinline__ void build_lists3(const ProbDesc& P, const Lds3& L, int k0, int Tce,
-                                             int Ts, float inv_Tm1, bool moving) {
+                                             int Ts, float inv_Tm1, bool moving, float d) {
   const int tid = phase_tid();
   list_boxes3(P, L, Tce, Ts, tid, NT);
   __syncthreads();
-  list_masks3(P, L, k0, Tce, inv_Tm1, moving, wave_id3(tid), NT >> 6);
+  list_masks3(P, L, k0, Tce, inv_Tm1, moving, d, wave_id3(tid), NT >> 6);
   __syncthreads();
 }
 
@@ -578,7 +603,7 @@ __device__ __forceinline__ void obstacle_rows3(const float* o, float tau, bool m
 
 template <int NT, int MODE, int kRob, typename Args>
 __device__ __forceinline__ void sweep3(const Args& A, const ProbDesc& P, const Lds3& L,
-                                       const float* xb, float& r1sq, float& r2sq,
+                                       const float* xb, float& r1sq, float& r2sq, Skin3& sk,
                                        float w1 = 1.f, float w2 = 1.f) {
   constexpr bool FINAL = MODE == kFinal;
   const int n = P.n, M = P.M, nc = A.nc, T = A.T, Tc = A.Tc, tid = phase_tid();
@@ -591,6 +616,7 @@ __device__ __forceinline__ void sweep3(const Args& A, const ProbDesc& P, const L
   // xb as the new reference
   const bool lists = A.lists3 != 0;
   const bool rebuild = lists && lists_moved3(L.lslot, NT >> 6);
+  if (lists) sk.pass(rebuild);
   if (rebuild)
     for (int t = tid; t < 3 * n * nc; t += NT) L.refc[t] = xb[t];
   for (int k0 = 0; k0 < T; k0 += Tc) {
@@ -608,7 +634,7 @@ __device__ __forceinline__ void sweep3(const Args& A, const ProbDesc& P, const L
     __syncthreads();
     if (lists && rebuild) {
       if (k0 == 0 && tid < kSlots3) L.lslot[tid] = 0;   // every thread has read the flags
-      build_lists3<NT>(P, L, k0, Tce, Ts, inv_Tm1, moving);
+      build_lists3<NT>(P, L, k0, Tce, Ts, inv_Tm1, moving, sk.d);
     }
     // constraint rows (robot pairs, obstacles, the box).  A thread takes kRob
     // robots at one step, so each partner position and obstacle read from LDS
@@ -733,17 +759,17 @@ __device__ __forceinline__ void sweep3(const Args& A, const ProbDesc& P, const L
 // Sweep dispatch on the problem's robots per thread.
 template <int NT, int MODE, typename Args>
 __device__ __forceinline__ void sweep3_any(const Args& A, const ProbDesc& P, const Lds3& L,
-                                           const float* xb, float& r1sq, float& r2sq,
+                                           const float* xb, float& r1sq, float& r2sq, Skin3& sk,
                                            float w1 = 1.f, float w2 = 1.f) {
   const int rpt = robots_per_thread(P.n);
   if (A.lists3)
-    sweep3<NT, MODE, kListRob3>(A, P, L, xb, r1sq, r2sq, w1, w2);
+    sweep3<NT, MODE, kListRob3>(A, P, L, xb, r1sq, r2sq, sk, w1, w2);
   else if (rpt == 4)
-    sweep3<NT, MODE, 4>(A, P, L, xb, r1sq, r2sq, w1, w2);
+    sweep3<NT, MODE, 4>(A, P, L, xb, r1sq, r2sq, sk, w1, w2);
   else if (rpt == 2)
-    sweep3<NT, MODE, 2>(A, P, L, xb, r1sq, r2sq, w1, w2);
+    sweep3<NT, MODE, 2>(A, P, L, xb, r1sq, r2sq, sk, w1, w2);
   else
-    sweep3<NT, MODE, 1>(A, P, L, xb, r1sq, r2sq, w1, w2);
+    sweep3<NT, MODE, 1>(A, P, L, xb, r1sq, r2sq, sk, w1, w2);
 }
 
 // Set-up shared by the forward and the adjoint: factor block, W (whole table
@@ -820,11 +846,11 @@ __device__ __forceinline__ void mean_field3(const ProbDesc& P, const Lds3& L, in
 template <int NT, int KS>
 __device__ __forceinline__ void xi_step3(const ProbDesc& P, const Lds3& L, int nc, float rho,
                                          const float* xcur, float* xnext, bool last,
-                                         bool lists, float& dzsq) {
+                                         bool lists, float d, float& dzsq) {
   const int n = P.n, nc2 = nc * nc, rows = 3 * n;
   const int tid = phase_tid(), lane = tid & 63, wave = wave_id3(tid), m = lane & 15, kq = lane >> 4;
   const int nrt = (rows + 15) >> 4, nct = (nc + 15) >> 4;
-  const float ska = kSkin3 * P.a, skb = kSkin3 * P.b;
+  const float ska = d * P.a, skb = d * P.b;
   bool moved = false;
   for (int rt = wave; rt < nrt; rt += NT >> 6) {
     const int rowA = min(rt * 16 + m, rows - 1), axA = rowA / n;
@@ -907,16 +933,16 @@ __device__ __forceinline__ void xi_step3(const ProbDesc& P, const Lds3& L, int n
 template <int NT, typename Args>
 __device__ __forceinline__ void iterate3(const Args& A, const ProbDesc& P, const Lds3& L,
                                          const float* xcur, float* xnext, bool last,
-                                         float& dzsq) {
+                                         float& dzsq, Skin3& sk) {
   float z0 = 0.f, z1 = 0.f;
-  sweep3_any<NT, kForward>(A, P, L, xcur, z0, z1);
+  sweep3_any<NT, kForward>(A, P, L, xcur, z0, z1, sk);
   mean_field3<NT>(P, L, A.nc, A.rho, xcur);
   __syncthreads();
   const bool lists = A.lists3 != 0;
   if (A.nc <= 16)
-    xi_step3<NT, 4>(P, L, A.nc, A.rho, xcur, xnext, last, lists, dzsq);
+    xi_step3<NT, 4>(P, L, A.nc, A.rho, xcur, xnext, last, lists, sk.d, dzsq);
   else
-    xi_step3<NT, 0>(P, L, A.nc, A.rho, xcur, xnext, last, lists, dzsq);
+    xi_step3<NT, 0>(P, L, A.nc, A.rho, xcur, xnext, last, lists, sk.d, dzsq);
   __syncthreads();
 }
 
@@ -972,6 +998,7 @@ __global__ __launch_bounds__(NT) void fwd3_kernel(FwdArgs A) {
   const float* bnd = A.boundary + (size_t)P.rob_off * 6;
   const size_t St = (size_t)A.S_total;
 
+  Skin3 sk;
   setup3<NT>(A, P, L, A.obstacles);
   if (A.lists3) reset_lists3<NT>(L.refc, L.lslot, S);   // the first sweep builds every list
   if (A.save)   // the adjoint reads the obstacles from the workspace
@@ -1006,11 +1033,11 @@ __global__ __launch_bounds__(NT) void fwd3_kernel(FwdArgs A) {
     bool stop = false;
     if (A.check_every > 0 && (l % A.check_every) == 0) {
       float v[3] = {0.f, 0.f, 0.f};
-      sweep3_any<NT, kFinal>(A, P, L, xcur, v[0], v[1]);
+      sweep3_any<NT, kFinal>(A, P, L, xcur, v[0], v[1], sk);
       block_sum3<NT>(v, L.red);
       stop = sqrtf(v[0] + v[1]) <= A.tol;
     }
-    iterate3<NT>(A, P, L, xcur, xnext, stop || l == A.L - 1, dzsq);
+    iterate3<NT>(A, P, L, xcur, xnext, stop || l == A.L - 1, dzsq, sk);
     float* tmp = xcur;
     xcur = xnext;
     xnext = tmp;
@@ -1022,7 +1049,7 @@ __global__ __launch_bounds__(NT) void fwd3_kernel(FwdArgs A) {
 
   // residual of the returned iterate, outputs, status
   float v[3] = {0.f, 0.f, 0.f};
-  sweep3_any<NT, kFinal>(A, P, L, xcur, v[0], v[1]);
+  sweep3_any<NT, kFinal>(A, P, L, xcur, v[0], v[1], sk);
   float bad = 0.f;
   for (int t = tid; t < S; t += NT) {
     const float x = xcur[t], lm = L.lam[t];
@@ -1089,7 +1116,8 @@ __global__ __launch_bounds__(NT) void plain3_kernel(FwdArgs A, PlainBufs pb, int
     for (int t = tid; t < S; t += NT) L.xb[0][t] = gcur[t];
     __syncthreads();
     float z0 = 0.f, z1 = 0.f;
-    sweep3_any<NT, kForward>(A, P, L, L.xb[0], z0, z1);
+    Skin3 sk;   // the plain path runs without lists
+    sweep3_any<NT, kForward>(A, P, L, L.xb[0], z0, z1, sk);
     for (int t = tid; t < S; t += NT) pb.R[off + t] = L.R[t];
   } else if (stage == kPlainUpdate) {
     for (int t = tid; t < S; t += NT) {
@@ -1103,9 +1131,9 @@ __global__ __launch_bounds__(NT) void plain3_kernel(FwdArgs A, PlainBufs pb, int
     __syncthreads();
     float dzsq = 0.f;
     if (nc <= 16)
-      xi_step3<NT, 4>(P, L, nc, A.rho, L.xb[0], L.xb[1], last != 0, false, dzsq);
+      xi_step3<NT, 4>(P, L, nc, A.rho, L.xb[0], L.xb[1], last != 0, false, 0.f, dzsq);
     else
-      xi_step3<NT, 0>(P, L, nc, A.rho, L.xb[0], L.xb[1], last != 0, false, dzsq);
+      xi_step3<NT, 0>(P, L, nc, A.rho, L.xb[0], L.xb[1], last != 0, false, 0.f, dzsq);
     __syncthreads();
     for (int t = tid; t < S; t += NT) {
       gnext[t] = L.xb[1][t];
@@ -1120,7 +1148,8 @@ __global__ __launch_bounds__(NT) void plain3_kernel(FwdArgs A, PlainBufs pb, int
     for (int t = tid; t < S; t += NT) L.xb[0][t] = gcur[t];
     __syncthreads();
     float v[3] = {0.f, 0.f, 0.f};
-    sweep3_any<NT, kFinal>(A, P, L, L.xb[0], v[0], v[1]);
+    Skin3 sk;
+    sweep3_any<NT, kFinal>(A, P, L, L.xb[0], v[0], v[1], sk);
     float bad = 0.f;
     for (int t = tid; t < S; t += NT) {
       const float x = gcur[t], lm = glam[t];
@@ -1225,7 +1254,7 @@ __device__ __forceinline__ void obstacle_vjp3(const float* o, float tau, bool mo
 template <int NT, int kRob>
 __device__ __forceinline__ void vjp3(const BwdArgs& A, const ProbDesc& P, const Lds3& L,
                                      const Lds3b& B, const float* xb, int Tv, bool rebuild,
-                                     bool premapped) {
+                                     bool premapped, float d) {
   const int n = P.n, M = P.M, nc = A.nc, T = A.T, Tc = A.Tc, tid = phase_tid();
   const bool chunked = Tc < T;
   const float inv_a = 1.f / P.a, inv_b = 1.f / P.b;
@@ -1251,7 +1280,7 @@ __device__ __forceinline__ void vjp3(const BwdArgs& A, const ProbDesc& P, const 
                      NT >> 6);
       if (rebuild) {
         if (tid < kSlots3) L.lslot[tid] = 0;   // every thread has read the flags
-        list_masks3(P, L, k0, Tce, inv_Tm1, moving, wave, NT >> 6);
+        list_masks3(P, L, k0, Tce, inv_Tm1, moving, d, wave, NT >> 6);
       }
       __syncthreads();
     } else {
@@ -1261,7 +1290,7 @@ __device__ __forceinline__ void vjp3(const BwdArgs& A, const ProbDesc& P, const 
       __syncthreads();
       if (rebuild) {
         if (k0 == 0 && tid < kSlots3) L.lslot[tid] = 0;   // every thread has read the flags
-        build_lists3<NT>(P, L, k0, Tce, Ts, inv_Tm1, moving);
+        build_lists3<NT>(P, L, k0, Tce, Ts, inv_Tm1, moving, d);
       }
     }
     const int plane = n * Ts;
@@ -1461,7 +1490,7 @@ __global__ __launch_bounds__(NT) void bwd3_kernel(BwdArgs A, int Tv) {
   const size_t St = (size_t)A.S_total;
   const int rpt = robots_per_thread(n);
   const bool lists = A.lists3 != 0;
-  const float ska = kSkin3 * P.a, skb = kSkin3 * P.b;
+  Skin3 sk;
   const int T = A.T, NW = NT >> 6, wave = wave_id3(tid);
   const bool whole = Tv >= T;   // one VJP chunk
 
@@ -1484,12 +1513,12 @@ __global__ __launch_bounds__(NT) void bwd3_kernel(BwdArgs A, int Tv) {
     for (int t = tid; t < S; t += NT) xf[t] = A.fin[P.coef_off + t];
     __syncthreads();
     float v[3] = {0.f, 0.f, 0.f};
-    sweep3_any<NT, kFinal>(A, P, L, xf, v[0], v[1]);
+    sweep3_any<NT, kFinal>(A, P, L, xf, v[0], v[1], sk);
     block_sum3<NT>(v, L.red);
     const float c1 = v[0] > 0.f ? gr1 / sqrtf(v[0]) : 0.f;
     const float c2 = v[1] > 0.f ? gr2 / sqrtf(v[1]) : 0.f;
     float d0 = 0.f, d1 = 0.f;
-    sweep3_any<NT, kResGrad>(A, P, L, xf, d0, d1, c1, c2);
+    sweep3_any<NT, kResGrad>(A, P, L, xf, d0, d1, sk, c1, c2);
     for (int t = tid; t < S; t += NT) gx[t] += L.R[t];
     __syncthreads();
   }
@@ -1510,12 +1539,12 @@ __global__ __launch_bounds__(NT) void bwd3_kernel(BwdArgs A, int Tv) {
         xc[t] = ck[t];
         L.lam[t] = ck[St + t];
         L.cxi[t] = A.cxi[P.coef_off + t];
-        if (lists) moved |= coef_moved3(xc, L.refc, t, nn, ska, skb);
+        if (lists) moved |= coef_moved3(xc, L.refc, t, nn, sk.d * P.a, sk.d * P.b);
       }
       if (lists) note_moved3(moved, L.lslot);
       __syncthreads();
       for (int l = l0; l < l1 - 1; ++l) {
-        iterate3<NT>(A, P, L, xc, xq, false, dz);
+        iterate3<NT>(A, P, L, xc, xq, false, dz, sk);
         float* tmp = xc;
         xc = xq;
         xq = tmp;
@@ -1538,11 +1567,12 @@ __global__ __launch_bounds__(NT) void bwd3_kernel(BwdArgs A, int Tv) {
       for (int t = tid; t < S; t += NT) {
         xl[t] = cur[t];
         if (fw != 0.f) gx[t] = fmaf(2.f * fw, nxt[t] - cur[t], gx[t]);
-        if (lists) moved |= coef_moved3(xl, L.refc, t, nn, ska, skb);
+        if (lists) moved |= coef_moved3(xl, L.refc, t, nn, sk.d * P.a, sk.d * P.b);
       }
       if (lists) note_moved3(moved, L.lslot);
       __syncthreads();
       const bool rebuild = lists && lists_moved3(L.lslot, NW);
+      if (lists) sk.pass(rebuild);
       const int nrt = (3 * n + 15) >> 4;
       if (whole) {
         // the robot means of g (waves 0-2) beside the positions X = W xi_bar^l
@@ -1573,13 +1603,13 @@ __global__ __launch_bounds__(NT) void bwd3_kernel(BwdArgs A, int Tv) {
       }
       __syncthreads();
       if (lists)
-        vjp3<NT, kListRob3>(A, P, L, B, xl, Tv, rebuild, whole);
+        vjp3<NT, kListRob3>(A, P, L, B, xl, Tv, rebuild, whole, sk.d);
       else if (rpt == 4)
-        vjp3<NT, 4>(A, P, L, B, xl, Tv, false, whole);
+        vjp3<NT, 4>(A, P, L, B, xl, Tv, false, whole, 0.f);
       else if (rpt == 2)
-        vjp3<NT, 2>(A, P, L, B, xl, Tv, false, whole);
+        vjp3<NT, 2>(A, P, L, B, xl, Tv, false, whole, 0.f);
       else
-        vjp3<NT, 1>(A, P, L, B, xl, Tv, false, whole);
+        vjp3<NT, 1>(A, P, L, B, xl, Tv, false, whole, 0.f);
       for (int t = tid; t < S; t += NT) gn[t] += L.R[t];
       __syncthreads();
       float* tmp = gx;
