@@ -324,95 +324,89 @@ __device__ __forceinline__ void list_boxes3(const ProbDesc& P, const Lds3& L, in
   }
 }
 
-// The masks of list_boxes3's windows, one ballot job per (window, robot pair,
-// mask word) over waves w0, w0 + nw, ...
+// The masks of list_boxes3's windows.  A job is (window, mask word, range of
+// robot pairs): a lane holds its candidate (partner j = 32 word + jj, or
+// obstacle 32 (word - pw) + jj) and that candidate's part of the test, and
+// each robot pair of the range takes one ballot (lane = 32 slot + jj: robots
+// 2 ip and 2 ip + 1), reading only the two robots' boxes.
 __device__ __forceinline__ void list_masks3(const ProbDesc& P, const Lds3& L, int k0, int Tce,
                                             float inv_Tm1, bool moving, float d, int w0,
                                             int nw) {
   const int n = P.n, M = P.M, lane = phase_tid() & 63;
   const int nwc = (Tce + kWin3 - 1) >> kWinShift3;
   const float* box = L.V;
-  const int pw = (n + 31) >> 5, mw = mask_words3(n, M), np = (n + 1) >> 1, ow = mw - pw;
+  const int pw = (n + 31) >> 5, mw = mask_words3(n, M), np = (n + 1) >> 1;
   const int slot = lane >> 5, jj = lane & 31;
-  // Ballot jobs (window, robot pair ip, mask word), pair words and obstacle
-  // words in loops of their own, four jobs of a wave at a time so that their
-  // box reads are in flight together.
-  auto pair_test = [&](int wl, int ip, int word) {
-    const int i = 2 * ip + slot, ic = min(i, n - 1);
-    const int j = 32 * word + jj, jc = min(j, n - 1);
-    bool c = i < n && j < n && j != i;
+  // ranges of robot pairs per (window, word): enough jobs for the waves
+  const int split = min(max((nw + nwc * mw - 1) / (nwc * mw), 1), np);
+  const int per = (np + split - 1) / split, jobs = nwc * mw * split;
+  for (int q = w0; q < jobs; q += nw) {
+    const int wl = q / (mw * split), rem = q - wl * (mw * split);
+    const int word = rem / split, ip0 = (rem - word * split) * per, ip1 = min(np, ip0 + per);
+    unsigned* mk = L.mask + (size_t)((k0 >> kWinShift3) + wl) * n * mw + word;
+    if (word < pw) {
+      const int j = 32 * word + jj, jc = min(j, n - 1);
+      float jlo[3], jhi[3], jmag[3];
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-      const float* bi = box + ((ax * n + ic) * nwc + wl) * 2;
-      const float* bj = box + ((ax * n + jc) * nwc + wl) * 2;
-      const float mag =
-          fmaxf(fmaxf(fabsf(bi[0]), fabsf(bi[1])), fmaxf(fabsf(bj[0]), fabsf(bj[1])));
-      const float thr = 1.f + 2.f * d + 1e-4f * (1.f + mag);
-      c = c && (bi[0] - bj[1] < thr) && (bj[0] - bi[1] < thr);
+      for (int ax = 0; ax < 3; ++ax) {
+        const float* bj = box + ((ax * n + jc) * nwc + wl) * 2;
+        jlo[ax] = bj[0];
+        jhi[ax] = bj[1];
+        jmag[ax] = fmaxf(fabsf(bj[0]), fabsf(bj[1]));
+      }
+#pragma unroll 2
+      for (int ip = ip0; ip < ip1; ++ip) {
+        const int i = 2 * ip + slot, ic = min(i, n - 1);
+        bool c = i < n && j < n && j != i;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          const float* bi = box + ((ax * n + ic) * nwc + wl) * 2;
+          const float mag = fmaxf(fmaxf(fabsf(bi[0]), fabsf(bi[1])), jmag[ax]);
+          const float thr = 1.f + 2.f * d + 1e-4f * (1.f + mag);
+          c = c && (bi[0] - jhi[ax] < thr) && (jlo[ax] - bi[1] < thr);
+        }
+        const unsigned long long bal = __builtin_amdgcn_ballot_w64(c);
+        if (lane == 0) {
+          mk[(size_t)2 * ip * mw] = (unsigned)bal;
+          if (2 * ip + 1 < n) mk[(size_t)(2 * ip + 1) * mw] = (unsigned)(bal >> 32);
+        }
+      }
+    } else {
+      const int mo = 32 * (word - pw) + jj;
+      const float* o = L.obs + min(mo, M - 1) * kObsFloats;
+      // the obstacle's centre term is monotone in the step, so its range over
+      // the window is that of the window's first and last steps
+      const float ta = (float)(k0 + wl * kWin3) * inv_Tm1;
+      const float tb = (float)(k0 + min(wl * kWin3 + kWin3 - 1, Tce - 1)) * inv_Tm1;
+      float clo[3], chi[3], rr[3];
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        const float ca = moving ? fmaf(o[7 + ax], ta, o[2 + ax]) : o[2 + ax];
+        const float cb = moving ? fmaf(o[7 + ax], tb, o[2 + ax]) : o[2 + ax];
+        clo[ax] = fminf(ca, cb);
+        chi[ax] = fmaxf(ca, cb);
+        rr[ax] = ax < 2 ? o[0] : o[1];
+      }
+#pragma unroll 2
+      for (int ip = ip0; ip < ip1; ++ip) {
+        const int i = 2 * ip + slot, ic = min(i, n - 1);
+        bool c = i < n && mo < M;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          const float* bi = box + ((ax * n + ic) * nwc + wl) * 2;
+          const float r = rr[ax];
+          const float elo = fmaf(bi[0], r, clo[ax]), ehi = fmaf(bi[1], r, chi[ax]);
+          const float sl = fmaf(r, d, 1e-4f * (1.f + fabsf(elo) + fabsf(ehi) +
+                                               r * (fabsf(bi[0]) + fabsf(bi[1]))));
+          c = c && (elo - sl < 1.f) && (ehi + sl > -1.f);
+        }
+        const unsigned long long bal = __builtin_amdgcn_ballot_w64(c);
+        if (lane == 0) {
+          mk[(size_t)2 * ip * mw] = (unsigned)bal;
+          if (2 * ip + 1 < n) mk[(size_t)(2 * ip + 1) * mw] = (unsigned)(bal >> 32);
+        }
+      }
     }
-    return c;
-  };
-  auto obstacle_test = [&](int wl, int ip, int w) {
-    const int i = 2 * ip + slot, ic = min(i, n - 1);
-    const int mo = 32 * w + jj;
-    const float* o = L.obs + min(mo, M - 1) * kObsFloats;
-    bool c = i < n && mo < M;
-    // the obstacle's centre term is monotone in the step, so its range over
-    // the window is that of the window's first and last steps
-    const float ta = (float)(k0 + wl * kWin3) * inv_Tm1;
-    const float tb = (float)(k0 + min(wl * kWin3 + kWin3 - 1, Tce - 1)) * inv_Tm1;
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-      const float* bi = box + ((ax * n + ic) * nwc + wl) * 2;
-      const float ca = moving ? fmaf(o[7 + ax], ta, o[2 + ax]) : o[2 + ax];
-      const float cb = moving ? fmaf(o[7 + ax], tb, o[2 + ax]) : o[2 + ax];
-      const float r = ax < 2 ? o[0] : o[1];
-      const float elo = fmaf(bi[0], r, fminf(ca, cb)), ehi = fmaf(bi[1], r, fmaxf(ca, cb));
-      const float sl = fmaf(r, d, 1e-4f * (1.f + fabsf(elo) + fabsf(ehi) +
-                                                 r * (fabsf(bi[0]) + fabsf(bi[1]))));
-      c = c && (elo - sl < 1.f) && (ehi + sl > -1.f);
-    }
-    return c;
-  };
-  auto put = [&](bool c, bool valid, int wl, int ip, int word) {
-    const unsigned long long bal = __builtin_amdgcn_ballot_w64(c);
-    if (valid && lane == 0) {
-      unsigned* mk = L.mask + ((size_t)((k0 >> kWinShift3) + wl) * n + 2 * ip) * mw + word;
-      mk[0] = (unsigned)bal;
-      if (2 * ip + 1 < n) mk[mw] = (unsigned)(bal >> 32);
-    }
-  };
-  constexpr int U = 4;
-  const int pair_jobs = nwc * np * pw, obs_jobs = nwc * np * ow;
-  for (int q0 = w0; q0 < pair_jobs; q0 += U * nw) {
-    bool c[U];
-    int wl[U], ip[U], wd[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int q = min(q0 + u * nw, pair_jobs - 1), per = np * pw;
-      wl[u] = q / per;
-      const int rem = q - wl[u] * per;
-      ip[u] = rem / pw;
-      wd[u] = rem - ip[u] * pw;
-      c[u] = pair_test(wl[u], ip[u], wd[u]);
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) put(c[u], q0 + u * nw < pair_jobs, wl[u], ip[u], wd[u]);
-  }
-  for (int q0 = w0; q0 < obs_jobs; q0 += U * nw) {
-    bool c[U];
-    int wl[U], ip[U], wd[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int q = min(q0 + u * nw, obs_jobs - 1), per = np * ow;
-      wl[u] = q / per;
-      const int rem = q - wl[u] * per;
-      ip[u] = rem / ow;
-      wd[u] = rem - ip[u] * ow;
-      c[u] = obstacle_test(wl[u], ip[u], wd[u]);
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) put(c[u], q0 + u * nw < obs_jobs, wl[u], ip[u], pw + wd[u]);
   }
 }
 
