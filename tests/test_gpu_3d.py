@@ -553,3 +553,55 @@ def test_3d_plain_and_unfused_paths_match_fused_bitwise(gpu, case):
         np.testing.assert_array_equal(runs[name][2][:, [0, 1, 3]], runs["fused"][2][:, [0, 1, 3]])
         np.testing.assert_allclose(runs[name][2][:, 2], runs["fused"][2][:, 2], rtol=1e-5,
                                    atol=1e-7)
+
+
+# ------------------------------------------- 3D at the benchmark's configuration
+def test_3d_bench_configuration_sampled(gpu):
+    """The 3D benchmark's launch as timed: all 64 problems of 32 spheroid
+    robots and 20 obstacles, 1024 threads, candidate lists, L = 100 with every
+    iterate saved, then the adjoint; two sampled problems' forward outputs and
+    gradients against the oracle."""
+    import torch
+    from oracle import SFAdjoint
+    from sf_testlib import GRAD_REL_TOL
+    probs = make_batch3d(WORKLOADS_3D[32])
+    assert len(probs) == 64
+    L, picks = 100, (0, 37)
+    pk = pack3d(probs)
+    plan = _plan(pk, max_iters=L, ckpt=1)
+    assert plan.set_candidate_lists(True)
+    t = {k: torch.from_numpy(getattr(pk, k)).cuda() for k in ("xi", "xi0", "lam0",
+                                                               "boundary", "obstacles")}
+    xo, lo, res = plan.project(t["xi"], t["xi0"], t["lam0"], t["boundary"], t["obstacles"], L,
+                               save=True)
+    rng = np.random.default_rng(32)
+    g_xi = [rng.standard_normal(p.xi.shape) for p in probs]
+    g_lam = [rng.standard_normal(p.xi.shape) for p in probs]
+    dev = lambda gs: torch.from_numpy(np.concatenate([g.ravel() for g in gs])
+                                      .astype(np.float32)).cuda()
+    g = plan.backward(dev(g_xi), dev(g_lam), None)
+    torch.cuda.synchronize()
+    print(f"[3d bench] GPU done, oracle on problems {picks}", flush=True)
+    res = res.cpu().numpy()
+    assert np.all(res[:, 3] == 0.0)
+    gx, gl = unpack3d(xo.cpu().numpy(), probs), unpack3d(lo.cpu().numpy(), probs)
+    grads = [unpack3d(x.cpu().numpy(), probs) for x in g]
+    inps = _inputs3d(pk, probs)
+    errs, misses = [], []
+    for b in picks:
+        inp = inps[b]
+        ref = _oracle(inp).solve(inp["xi"], inp["xi0"], inp["lam0"], L)
+        errs.append(check_against(ref, gx[b], gl[b], res[b]))
+        gref = SFAdjoint(_oracle(inp)).gradient(
+            inp["xi"], inp["xi0"], inp["lam0"], L,
+            g_xi[b].astype(np.float32).astype(np.float64),
+            g_lam[b].astype(np.float32).astype(np.float64), 0.0, 0.0, 0.0)
+        ge = {name: rel_err(gv, rv) for name, gv, rv in
+              (("xi", grads[0][b], gref.g_xi), ("xi0", grads[1][b], gref.g_xi0),
+               ("lam0", grads[2][b], gref.g_lam0))}
+        print(f"[3d bench] problem {b}: residual {np.hypot(res[b, 0], res[b, 1]):.3e}, "
+              + ", ".join(f"g_{k} {v:.2e}" for k, v in ge.items()), flush=True)
+        misses += [f"problem {b} g_{k} {v:.2e}" for k, v in ge.items() if v > GRAD_REL_TOL]
+    report("3d bench L=100", errs)
+    assert not misses, misses
+    finish_parity(errs)   # the residual bar on unconverged outputs: reported, expected
