@@ -1,5 +1,6 @@
-// 3D (spheroid) SF forward: one workgroup per problem, the problem's state in
-// LDS for all L iterations.
+// 3D (spheroid) SF: the forward (fwd3_kernel), its adjoint (bwd3_kernel) and
+// the per-stage plain path (plain3_kernel); one workgroup per problem, the
+// problem's state in LDS for all L iterations.
 //
 // Robots are axis-aligned spheroids (a/2, a/2, b/2) and obstacles spheroids
 // (a_o, a_o, b_o) inflated by the robot (problem formulation; Appendix eqs.
@@ -18,7 +19,8 @@
 //
 // One iteration, in time chunks of Tc steps held in LDS:
 //   positions X = W xi_bar (MFMA tiles), stored as x/a, y/a, z/b   [3][n][Tc]
-//   V = F^T r_1 + G^T r_2 per (robot, step), every pair visited    [3][n][Tc]
+//   V = F^T r_1 + G^T r_2 per (robot, step), over each robot's     [3][n][Tc]
+//       candidate partners and obstacles (or all of them)
 //   R += W^T V (MFMA tiles)
 // then lambda' = lambda - rho R, u = lambda - 2 rho R and the mode-form
 // xi_bar' = c_xi + S u + SH xi_bar (S, SH: perpendicular block per robot plus
