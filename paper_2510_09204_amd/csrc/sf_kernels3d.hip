@@ -356,7 +356,6 @@ __device__ __forceinline__ void list_masks3(const ProbDesc& P, const Lds3& L, in
         jhi[ax] = bj[1];
         jmag[ax] = fmaxf(fabsf(bj[0]), fabsf(bj[1]));
       }
-#pragma unroll 2
       for (int ip = ip0; ip < ip1; ++ip) {
         const int i = 2 * ip + slot, ic = min(i, n - 1);
         bool c = i < n && j < n && j != i;
@@ -389,7 +388,6 @@ __device__ __forceinline__ void list_masks3(const ProbDesc& P, const Lds3& L, in
         chi[ax] = fmaxf(ca, cb);
         rr[ax] = ax < 2 ? o[0] : o[1];
       }
-#pragma unroll 2
       for (int ip = ip0; ip < ip1; ++ip) {
         const int i = 2 * ip + slot, ic = min(i, n - 1);
         bool c = i < n && mo < M;
