@@ -422,6 +422,19 @@ def test_3d_adjoint_candidate_lists_give_the_same_bits(gpu, case):
     _same_bits(on, off)
 
 
+def test_3d_candidate_lists_through_skin_changes_give_the_same_bits(gpu):
+    """Long runs on the 32-robot workload, long enough for the list skin to
+    halve once lists last sixteen passes (and to double again where they stop
+    lasting): forward over 400 iterations, adjoint over 150 with every
+    iterate kept and with checkpoints every 4; outputs and gradients stay
+    those of the full sweep bit for bit."""
+    probs = make_batch3d(WORKLOADS_3D[32], batch=2)
+    _same_bits(_bits(probs, 400, True), _bits(probs, 400, False))
+    for ckpt in (1, 4):
+        grad = (ckpt, 0.3, 0.05)
+        _same_bits(_bits(probs, 150, True, grad=grad), _bits(probs, 150, False, grad=grad))
+
+
 # ------------------------------------------------------------ 3D early exit
 def _oracle_early_exit3(inp, L, tol, every, rel_margin=1e-3):
     """The 3D oracle under the rule of sf_set_early_exit: at every iteration l
